@@ -1,0 +1,69 @@
+"""Transfer-matrix reflectance/transmittance of a homogeneous slab.
+
+Closed-form reference for the homogeneous periodic slab (a periodic structure
+whose unit cell is uniform): with vacuum on both sides, a plane wave of angle
+theta sees the classical thin-film (Airy) result.  Optics convention
+exp(-i w t) with eps Im >= 0 lossy; R, T and A are convention-independent.
+
+  kz_j = k0 sqrt(eps_j - sin^2 theta)  (Im kz >= 0)
+  TE: r_ij = (kz_i - kz_j) / (kz_i + kz_j),         t_ij = 2 kz_i / (kz_i + kz_j)
+  TM: r_ij = (eps_j kz_i - eps_i kz_j) / (eps_j kz_i + eps_i kz_j),
+      t_ij = 2 sqrt(eps_i eps_j) kz_i / (eps_j kz_i + eps_i kz_j)   (field ratio H-based)
+  r = (r01 + r12 e^{2 i d kz1}) / (1 + r01 r12 e^{2 i d kz1})
+  t = t01 t12 e^{i d kz1} / (1 + r01 r12 e^{2 i d kz1})
+  R = |r|^2, T = |t|^2 (same medium on both sides), A = 1 - R - T.
+
+A second, independent formulation (characteristic 2x2 matrix of the layer)
+is provided for the pins.
+"""
+import numpy as np
+
+
+def slab_rta(eps, d, lam, theta, pol):
+    """pol: 0 = TE (s), 1 = TM (p)."""
+    k0 = 2 * np.pi / lam
+    s2 = np.sin(theta) ** 2
+    e0, e1 = 1.0 + 0j, complex(eps)
+    kz0 = k0 * np.sqrt(e0 - s2 + 0j)
+    kz1 = k0 * np.sqrt(e1 - s2 + 0j)
+    if kz1.imag < 0:
+        kz1 = -kz1
+    if pol == 0:
+        r01 = (kz0 - kz1) / (kz0 + kz1); r12 = (kz1 - kz0) / (kz1 + kz0)
+        t01 = 2 * kz0 / (kz0 + kz1); t12 = 2 * kz1 / (kz1 + kz0)
+    else:
+        r01 = (e1 * kz0 - e0 * kz1) / (e1 * kz0 + e0 * kz1)
+        r12 = (e0 * kz1 - e1 * kz0) / (e0 * kz1 + e1 * kz0)
+        t01 = 2 * np.sqrt(e0 * e1) * kz0 / (e1 * kz0 + e0 * kz1)
+        t12 = 2 * np.sqrt(e1 * e0) * kz1 / (e0 * kz1 + e1 * kz0)
+    ph = np.exp(1j * kz1 * d)
+    den = 1 + r01 * r12 * ph * ph
+    r = (r01 + r12 * ph * ph) / den
+    t = t01 * t12 * ph / den
+    R = abs(r) ** 2
+    T = abs(t) ** 2
+    return R, T, 1.0 - R - T
+
+
+def slab_rta_matrix(eps, d, lam, theta, pol):
+    """Characteristic-matrix form (Born & Wolf): M = [[cos b, -i sin b / Y],
+    [-i Y sin b, cos b]], b = kz1 d, Y = admittance (TE: kz/k0, TM: eps k0/kz)."""
+    k0 = 2 * np.pi / lam
+    s2 = np.sin(theta) ** 2
+    kz0 = k0 * np.sqrt(1 - s2 + 0j)
+    kz1 = k0 * np.sqrt(complex(eps) - s2)
+    if kz1.imag < 0:
+        kz1 = -kz1
+    if pol == 0:
+        Y0, Y1 = kz0 / k0, kz1 / k0
+    else:
+        Y0, Y1 = k0 / kz0, complex(eps) * k0 / kz1
+    bb = kz1 * d
+    m11, m12 = np.cos(bb), -1j * np.sin(bb) / Y1
+    m21, m22 = -1j * Y1 * np.sin(bb), np.cos(bb)
+    den = (m11 + m12 * Y0) * Y0 + (m21 + m22 * Y0)
+    r = ((m11 + m12 * Y0) * Y0 - (m21 + m22 * Y0)) / den
+    t = 2 * Y0 / den
+    R = abs(r) ** 2
+    T = abs(t) ** 2
+    return R, T, 1.0 - R - T
