@@ -1,0 +1,176 @@
+/*
+ * vie.h -- C-ABI of libvie: the periodic volume-integral-equation method of
+ * moments for plasmonic thin-film cells, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (He, Gu, Sha, Chen, "Efficient Volumetric Method of Moments for
+ * Modeling Plasmonic Thin-Film Solar Cells with Periodic Structures"):
+ *   - VIE in the polarisation current, SWG basis, Galerkin testing
+ *     (Sec. 2.1, Eqs. 1-2; contrast kappa = (eps_r - 1)/eps_r);
+ *   - two-dimensional periodic Green's function with the incidence Bloch
+ *     phase, evaluated with the Ewald split (Sec. 2.2, Eqs. 3-4);
+ *   - material-domain block partition and block-diagonal preconditioner
+ *     (Sec. 2.3, Eqs. 5-6), applied on the right inside GMRES (Sec. 3);
+ *   - absorbed power Im(eps)|E|^2 per domain (Sec. 3, Eq. 7).
+ *
+ * Conventions shared by every entry point:
+ *   - lengths in nm, angles in radians;
+ *   - permittivities use the optics sign (Im eps >= 0 is lossy); internally
+ *     the library works in exp(+j w t) (Sec. 2.1) with eps_int = conj(eps);
+ *   - the incident plane wave arrives from +z with unit amplitude,
+ *     k = k0 (sin th cos ph, sin th sin ph, -cos th); TE: E || (-sin ph, cos ph, 0),
+ *     TM: E || (cos th cos ph, cos th sin ph, sin th);
+ *   - every call returns VIE_OK (0) or a negative vie_status; the message of
+ *     the last failure is available from vie_last_error().
+ *
+ * Memory: host inputs are copied before a call returns.  All device memory
+ * the library uses lives in ONE caller-owned workspace bound with
+ * vie_bind_workspace (the library never allocates device memory itself).
+ * The caller keeps the workspace alive until vie_destroy or the next bind.
+ * Work is issued on the stream given to vie_create; calls that return
+ * results to host buffers synchronise that stream.
+ *
+ * Call order: create -> mesh_upload -> bind_workspace -> fill -> precond_factor
+ * -> solve (any number of times, per polarisation) -> absorption.  A new fill
+ * (new wavelength, angles or permittivities) invalidates the factor and the
+ * solution.  Any other order returns VIE_ESTATE.  A context is not thread-safe;
+ * distinct contexts may run concurrently on distinct streams.
+ */
+#ifndef VIE_H
+#define VIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vie_ctx vie_ctx;
+
+typedef struct {
+  double re, im;
+} vie_c128;
+
+typedef enum {
+  VIE_OK = 0,
+  VIE_EINVAL = -1,     /* bad argument or bad mesh */
+  VIE_ESTATE = -2,     /* call out of order */
+  VIE_ENOMEM = -3,     /* workspace too small */
+  VIE_ENOCONV = -4,    /* GMRES hit max_iter; solution and info still written */
+  VIE_EWOOD = -5,      /* a Floquet order grazes the cell plane (Rayleigh-Wood anomaly) */
+  VIE_ESINGULAR = -6,  /* zero pivot in a diagonal-block factorisation */
+  VIE_EDEVICE = -7     /* HIP runtime error */
+} vie_status;
+
+enum { VIE_TE = 0, VIE_TM = 1 };
+
+/* Arithmetic of the impedance matrix and the Krylov solve.
+ * VIE_FP64: everything in FP64.
+ * VIE_MIXED_FP32: Z stored and multiplied in complex FP32, GMRES inner solve in
+ *   FP32 with the block preconditioner factored in FP32, inside an FP64
+ *   iterative-refinement loop whose residual uses the FP64 near-field terms. */
+enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1 };
+
+typedef struct {
+  int iters;                 /* total GMRES iterations (all restarts, all refinement steps) */
+  int restarts;              /* GMRES restarts */
+  int refine_steps;          /* outer refinement steps (mixed precision), 1 for FP64 */
+  double true_rel_residual;  /* ||b - Z x|| / ||b|| recomputed in FP64 at the end */
+  double t_fill_ms;          /* device time of the last vie_fill */
+  double t_factor_ms;        /* device time of the last vie_precond_factor */
+  double t_solve_ms;         /* device time of this vie_solve */
+} vie_solve_info;
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the device's null stream).  *out receives the handle. */
+int vie_create(vie_ctx **out, int device, void *hip_stream);
+int vie_destroy(vie_ctx *ctx);
+
+/* Upload a tetrahedral mesh of ONE unit cell [0,a] x [0,b] x [zmin,zmax]
+ * (Sec. 2.2: only one unit cell is modelled, the periodic Green's function
+ * supplies the Bloch condition; Fig. 1 geometry).
+ *   verts_nm   [3*nv]  vertex coordinates (x,y,z) in nm; vertices on the
+ *                      x = a / y = b walls must have partners on x = 0 / y = 0
+ *   tets       [4*nt]  0-based vertex ids of each tetrahedron (any orientation)
+ *   tet_domain [nt]    material domain id in [0, ndom) (Sec. 2.3, Eq. 5 blocks);
+ *                      a face between two domains belongs to the lower id
+ *   a, b               periods along x and y (Sec. 2.2)
+ * Builds the SWG unknowns (one per face; wall faces paired into Bloch-periodic
+ * functions; top/bottom faces are half-SWGs), ordered domain-major.  Host-only:
+ * no device work until the workspace is bound.  Errors: VIE_EINVAL for
+ * degenerate or non-periodic meshes, or fewer than 2 cells per periodic
+ * direction (every tetrahedron must span at most a/2 in x and b/2 in y). */
+int vie_mesh_upload(vie_ctx *ctx, const double *verts_nm, int64_t nv, const int32_t *tets, int64_t nt,
+                    const int32_t *tet_domain, int32_t ndom, double a_nm, double b_nm);
+
+int64_t vie_num_unknowns(const vie_ctx *ctx);
+
+/* starts_ends [2*ndom]: unknown range [start, end) of each domain's diagonal block. */
+int vie_domain_ranges(const vie_ctx *ctx, int64_t *starts_ends);
+
+/* Bytes of device workspace needed for `precision` and GMRES `restart`. */
+size_t vie_workspace_bytes(const vie_ctx *ctx, int precision, int restart);
+
+/* Bind caller-owned device memory (>= vie_workspace_bytes, 256-byte aligned)
+ * and upload the mesh tables into it.  VIE_ENOMEM if too small. */
+int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart);
+
+/* Fill Z (dense, complex, row-major, domain-major unknowns) for wavelength
+ * lambda_nm, incidence (theta, phi) and per-tetrahedron permittivity
+ * eps_per_tet [nt] (Sec. 2.1, Eq. 2 with the periodic Green's function of
+ * Sec. 2.2, Eqs. 3-4).  precision: VIE_FP64 or VIE_MIXED_FP32 (must match the
+ * bound workspace).  VIE_EWOOD if a non-specular Floquet order has
+ * |gamma_pq| / k0 < 0.02. */
+int vie_fill(vie_ctx *ctx, double lambda_nm, double theta_rad, double phi_rad, const vie_c128 *eps_per_tet,
+             int precision);
+
+/* LU factorisation with partial pivoting of every diagonal block A_dd
+ * (Sec. 2.3, Eq. 6).  VIE_ESINGULAR on a zero pivot. */
+int vie_precond_factor(vie_ctx *ctx);
+
+/* Right-preconditioned restarted GMRES(restart) on Z M^-1 y = b, x = M^-1 y,
+ * x0 = 0, for the incident polarisation `polarisation` (VIE_TE / VIE_TM),
+ * stopping when the residual estimate falls below tol * ||b|| (Sec. 3).
+ * The true FP64 residual is recomputed at the end (info->true_rel_residual).
+ * VIE_ENOCONV after max_iter iterations (x and info still written).
+ * `info` may be NULL. */
+int vie_solve(vie_ctx *ctx, int polarisation, double tol, int max_iter, int restart, vie_solve_info *info);
+
+/* Absorptance (absorbed / incident power) per domain of the last solution
+ * (Sec. 3, Eq. 7, normalised by the incident power crossing one cell):
+ *   A_d = k0 sum_{T in d} Im(eps_T) / |eps_T|^2 int_T |D/eps0|^2 dV / (cos th a b).
+ * absorptance_per_domain [ndom]; R, T (nullable): reflectance and
+ * transmittance summed over the propagating Floquet orders. */
+int vie_absorption(vie_ctx *ctx, double *absorptance_per_domain, double *R, double *T);
+
+const char *vie_last_error(const vie_ctx *ctx);
+
+/* ---------------------------------------------------------------- diagnostics
+ * Read-back helpers used by tests; they synchronise the context's stream. */
+
+/* Face table in unknown order: face_vid [3N] (vertex ids as the face sits in
+ * T+), tplus [N], tminus [N] (-1 for a half-SWG), dom [N].  Any pointer may be NULL. */
+int vie_export_faces(const vie_ctx *ctx, int32_t *face_vid, int32_t *tplus, int32_t *tminus, int32_t *dom);
+
+/* out[i] = Z[rows[i], cols[i]] (FP64 value; in mixed precision the stored
+ * FP32 far part plus the FP64 near part). */
+int vie_read_Z(const vie_ctx *ctx, const int64_t *rows, const int64_t *cols, int64_t k, vie_c128 *out);
+
+/* Right-hand side of the last solve's polarisation, and the last solution x [N]. */
+int vie_read_rhs(const vie_ctx *ctx, vie_c128 *b);
+int vie_read_solution(const vie_ctx *ctx, vie_c128 *x);
+
+/* Evaluate g_p(r, r') (Sec. 2.2, Eqs. 3-4) on the device at n separations
+ * delta_host [3n] = r - r', with the tables of the last vie_fill.
+ * out [n].  Needs a bound workspace and a completed fill. */
+int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *out);
+
+/* Residual history (estimate / ||b||) of the last solve; returns the count
+ * written (at most cap). */
+int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VIE_H */

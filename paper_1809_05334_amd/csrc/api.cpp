@@ -1,0 +1,884 @@
+// C-ABI of libvie (include/vie.h): context state machine, workspace layout and
+// the host orchestration of the fill, block factorisation, GMRES solve and
+// absorption kernels.  All device work is issued on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vie.h"
+#include "device_math.h"
+#include "host.h"
+#include "kernels.h"
+
+using namespace vie;
+
+namespace {
+
+enum State { S_NEW = 0, S_MESH = 1, S_BOUND = 2, S_FILLED = 3, S_FACTORED = 4, S_SOLVED = 5 };
+
+constexpr int kLuNB = 64;
+constexpr int kRedBlocks = 240;   // blocks of the two-stage reductions
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf;
+  Region eps, alpha, gsrc, kappa, inveps, sigma;
+  Region Z, F, ipiv, perm, rpiv, info;
+  Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
+  size_t total = 0;
+  int64_t ld = 0;
+  std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
+  int restart = 0;
+  int64_t ldv = 0;
+};
+
+}  // namespace
+
+struct vie_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  State state = S_NEW;
+  std::string err;
+  MeshTopology topo;
+  QuadRules quad;
+  Layout L;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int precision = VIE_FP64;
+  // fill parameters
+  double lambda = 0, theta = 0, phi = 0;
+  PgfTable *tab = nullptr;          // host copy (heap, large)
+  std::vector<dz> eps_int;
+  std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
+  std::vector<int32_t> color_off;
+  int nhalf = 0, nface = 0;
+  int last_pol = 0;
+  std::vector<double> hist;
+  double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_fill = 0, t_factor = 0;
+
+  template <class T>
+  T *ptr(const Region &r) const {
+    return reinterpret_cast<T *>(ws + r.off);
+  }
+};
+
+namespace {
+
+int fail(vie_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCK(expr)                                                                            \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, VIE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCK()                                                                                        \
+  do {                                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                                    \
+    if (e_ != hipSuccess) return fail(ctx, VIE_EDEVICE, "kernel launch (line %d): %s", __LINE__, hipGetErrorString(e_)); \
+  } while (0)
+
+unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf) {
+  Layout L;
+  size_t off = 0;
+  auto put = [&](Region &r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off = align256(off + std::max<size_t>(bytes, 1));
+  };
+  const int64_t N = t.N, nt = t.nt;
+  put(L.tg, sizeof(TetGeom) * nt);
+  put(L.t2f, sizeof(TetFace) * 4 * nt);
+  put(L.area, 8 * N);
+  put(L.dom, 4 * nt);
+  put(L.fg, sizeof(FaceGeom) * std::max(1, nface));
+  put(L.half, 4 * std::max(1, nhalf));
+  put(L.ctp, 4 * std::max(1, nface));
+  put(L.ctm, 4 * std::max(1, nface));
+  put(L.utet, 8 * N);
+  put(L.uk, 8 * N);
+  put(L.colors, 4 * nt);
+  put(L.near_t, 4 * std::max<int64_t>(1, nnear));
+  put(L.near_s, 4 * std::max<int64_t>(1, nnear));
+  put(L.near_m, 4 * std::max<int64_t>(1, nnear));
+  put(L.quad, sizeof(QuadRules));
+  put(L.pgf, sizeof(PgfTable));
+  put(L.eps, 16 * nt);
+  put(L.alpha, 16 * 4 * nt);
+  put(L.gsrc, 16 * 4 * nt);
+  put(L.kappa, 16 * nt);
+  put(L.inveps, 16 * nt);
+  put(L.sigma, 16 * std::max(1, nface));
+  L.ld = (N + 7) / 8 * 8;
+  put(L.Z, 16 * (size_t)N * L.ld);
+  L.fld.resize(t.ndom);
+  L.foff.resize(t.ndom);
+  int64_t fel = 0, npiv = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    int64_t n = t.dend[d] - t.dstart[d];
+    L.fld[d] = (n + 7) / 8 * 8;
+    L.foff[d] = fel;
+    fel += n * L.fld[d];
+    npiv += n;
+  }
+  put(L.F, 16 * (size_t)std::max<int64_t>(1, fel));
+  put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
+  put(L.perm, 4 * std::max<int64_t>(1, npiv));
+  put(L.rpiv, 16);
+  put(L.info, 4 * std::max(1, t.ndom));
+  L.restart = restart;
+  L.ldv = (N + 31) / 32 * 32;
+  put(L.V, 16 * (size_t)L.ldv * (restart + 1));
+  put(L.H, 16 * (size_t)(restart + 2) * (restart + 1));
+  put(L.cs, 8 * (restart + 1));
+  put(L.sn, 16 * (restart + 1));
+  put(L.g, 16 * (restart + 2));
+  put(L.y, 16 * (restart + 1));
+  for (Region *r : {&L.vb, &L.vx, &L.vw, &L.vz, &L.vu, &L.vr, &L.vt}) put(*r, 16 * N);
+  put(L.dpart, 16 * (size_t)kRedBlocks * (restart + 1));
+  put(L.npart, 8 * kRedBlocks);
+  put(L.scal, 64);
+  put(L.apart, 8 * (size_t)nblk(nt, 256) * std::max(6 * 2 * 32, t.ndom));
+  put(L.kv, 8 * 3 * 2 * 32);
+  put(L.idx, 16 * (size_t)N);
+  L.total = off;
+  return L;
+}
+
+int check(vie_ctx *ctx, State need, const char *what) {
+  if (!ctx) return VIE_EINVAL;
+  if (ctx->state < need) return fail(ctx, VIE_ESTATE, "%s called out of order", what);
+  return VIE_OK;
+}
+
+}  // namespace
+
+// ================================================================ C-ABI
+extern "C" {
+
+int vie_create(vie_ctx **out, int device, void *hip_stream) {
+  if (!out) return VIE_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VIE_EDEVICE;
+  vie_ctx *ctx = new vie_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->tab = new PgfTable();
+  build_quadrature(ctx->quad);
+  HIPCK(hipSetDevice(device));
+  HIPCK(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
+  HIPCK(hipEventCreate(&ctx->ev0));
+  HIPCK(hipEventCreate(&ctx->ev1));
+  *out = ctx;
+  return VIE_OK;
+}
+
+int vie_destroy(vie_ctx *ctx) {
+  if (!ctx) return VIE_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx->tab;
+  delete ctx;
+  return VIE_OK;
+}
+
+const char *vie_last_error(const vie_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int vie_mesh_upload(vie_ctx *ctx, const double *verts_nm, int64_t nv, const int32_t *tets, int64_t nt,
+                    const int32_t *tet_domain, int32_t ndom, double a_nm, double b_nm) {
+  if (!ctx) return VIE_EINVAL;
+  if (!verts_nm || !tets || !tet_domain) return fail(ctx, VIE_EINVAL, "null mesh array");
+  std::string e = build_topology(ctx->topo, verts_nm, nv, tets, nt, tet_domain, ndom, a_nm, b_nm);
+  if (!e.empty()) {
+    ctx->state = S_NEW;
+    return fail(ctx, VIE_EINVAL, "mesh: %s", e.c_str());
+  }
+  ctx->state = S_MESH;
+  ctx->ws = nullptr;
+  return VIE_OK;
+}
+
+int64_t vie_num_unknowns(const vie_ctx *ctx) { return ctx && ctx->state >= S_MESH ? ctx->topo.N : -1; }
+
+int vie_domain_ranges(const vie_ctx *ctx, int64_t *se) {
+  if (!ctx || ctx->state < S_MESH || !se) return VIE_ESTATE;
+  for (int d = 0; d < ctx->topo.ndom; ++d) {
+    se[2 * d] = ctx->topo.dstart[d];
+    se[2 * d + 1] = ctx->topo.dend[d];
+  }
+  return VIE_OK;
+}
+
+static int64_t total_near(const MeshTopology &t) {
+  int64_t s = 0;
+  for (auto &v : t.near_t) s += (int64_t)v.size();
+  return s;
+}
+
+size_t vie_workspace_bytes(const vie_ctx *ctx, int precision, int restart) {
+  if (!ctx || ctx->state < S_MESH || restart < 1 || precision != VIE_FP64) return 0;
+  int nhalf = 0;
+  for (int32_t f : ctx->topo.charged)
+    if (ctx->topo.tminus[f] < 0) ++nhalf;
+  return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf).total;
+}
+
+int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart) {
+  if (int r = check(ctx, S_MESH, "vie_bind_workspace")) return r;
+  if (precision != VIE_FP64) return fail(ctx, VIE_EINVAL, "precision %d not supported by this build", precision);
+  if (restart < 1 || restart > 1000) return fail(ctx, VIE_EINVAL, "restart must be in [1, 1000]");
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(ctx, VIE_EINVAL, "workspace must be 256-byte aligned");
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  std::vector<int32_t> half;
+  for (size_t i = 0; i < t.charged.size(); ++i)
+    if (t.tminus[t.charged[i]] < 0) half.push_back((int32_t)i);
+  ctx->nhalf = (int)half.size();
+  ctx->nface = (int)t.charged.size();
+  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf);
+  if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
+  ctx->L = L;
+  ctx->ws = (char *)dev_ptr;
+  ctx->ws_bytes = bytes;
+  ctx->precision = precision;
+
+  // ---- host staging of the mesh tables
+  std::vector<TetGeom> tg(t.nt);
+  for (int64_t e = 0; e < t.nt; ++e) {
+    TetGeom &g = tg[e];
+    for (int d = 0; d < 3; ++d) g.c[d] = 0;
+    for (int k = 0; k < 4; ++k) {
+      int32_t v = t.tets[4 * e + k];
+      for (int d = 0; d < 3; ++d) {
+        g.v[k][d] = t.verts[3 * v + d];
+        g.c[d] += 0.25 * t.verts[3 * v + d];
+      }
+      g.canon[k] = t.canon[v];
+      g.off[k] = (t.offx[v] + 2) | ((t.offy[v] + 2) << 4);
+    }
+    g.vol = t.vol[e];
+  }
+  std::vector<FaceGeom> fg(std::max<size_t>(1, t.charged.size()));
+  std::vector<int32_t> ctp(fg.size(), 0), ctm(fg.size(), -1);
+  for (size_t i = 0; i < t.charged.size(); ++i) {
+    int32_t f = t.charged[i];
+    FaceGeom &g = fg[i];
+    for (int j = 0; j < 3; ++j) {
+      int32_t v = t.face_vid[3 * f + j];
+      for (int d = 0; d < 3; ++d) g.v[j][d] = t.verts[3 * v + d];
+      g.canon[j] = t.canon[v];
+      g.off[j] = (t.offx[v] + 2) | ((t.offy[v] + 2) << 4);
+    }
+    g.area = t.area[f];
+    g.unknown = f;
+    g.half = t.tminus[f] < 0;
+    ctp[i] = t.tplus[f];
+    ctm[i] = t.tminus[f];
+  }
+  std::vector<int32_t> utet(2 * t.N, -1), uk(2 * t.N, 0);
+  for (int64_t e = 0; e < t.nt; ++e)
+    for (int k = 0; k < 4; ++k) {
+      const TetFace &f = t.t2f[4 * e + k];
+      int h = f.sign > 0 ? 0 : 1;
+      utet[2 * f.unknown + h] = (int32_t)e;
+      uk[2 * f.unknown + h] = k;
+    }
+  std::vector<int32_t> colors;
+  ctx->color_off.assign(t.ncolors + 1, 0);
+  for (int c = 0; c < t.ncolors; ++c) {
+    ctx->color_off[c] = (int32_t)colors.size();
+    colors.insert(colors.end(), t.color_tets[c].begin(), t.color_tets[c].end());
+  }
+  ctx->color_off[t.ncolors] = (int32_t)colors.size();
+  std::vector<int32_t> nt_, ns_, nm_;
+  const int C = t.ncolors;
+  ctx->near_off.assign(C * C + 1, 0);
+  for (int g = 0; g < C * C; ++g) {
+    ctx->near_off[g] = (int32_t)nt_.size();
+    nt_.insert(nt_.end(), t.near_t[g].begin(), t.near_t[g].end());
+    ns_.insert(ns_.end(), t.near_s[g].begin(), t.near_s[g].end());
+    nm_.insert(nm_.end(), t.near_mask[g].begin(), t.near_mask[g].end());
+  }
+  ctx->near_off[C * C] = (int32_t)nt_.size();
+
+  auto up = [&](const Region &r, const void *src, size_t n) -> int {
+    if (n == 0) return VIE_OK;
+    HIPCK(hipMemcpyAsync(ctx->ws + r.off, src, n, hipMemcpyHostToDevice, ctx->stream));
+    return VIE_OK;
+  };
+  int rc = 0;
+  rc |= up(L.tg, tg.data(), sizeof(TetGeom) * t.nt);
+  rc |= up(L.t2f, t.t2f.data(), sizeof(TetFace) * 4 * t.nt);
+  rc |= up(L.area, t.area.data(), 8 * t.N);
+  rc |= up(L.dom, t.dom.data(), 4 * t.nt);
+  rc |= up(L.fg, fg.data(), sizeof(FaceGeom) * t.charged.size());
+  rc |= up(L.half, half.data(), 4 * half.size());
+  rc |= up(L.ctp, ctp.data(), 4 * t.charged.size());
+  rc |= up(L.ctm, ctm.data(), 4 * t.charged.size());
+  rc |= up(L.utet, utet.data(), 4 * utet.size());
+  rc |= up(L.uk, uk.data(), 4 * uk.size());
+  rc |= up(L.colors, colors.data(), 4 * colors.size());
+  rc |= up(L.near_t, nt_.data(), 4 * nt_.size());
+  rc |= up(L.near_s, ns_.data(), 4 * ns_.size());
+  rc |= up(L.near_m, nm_.data(), 4 * nm_.size());
+  rc |= up(L.quad, &ctx->quad, sizeof(QuadRules));
+  if (rc) return rc;
+  HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
+  ctx->state = S_BOUND;
+  return VIE_OK;
+}
+
+int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
+  if (int r = check(ctx, S_BOUND, "vie_fill")) return r;
+  if (precision != ctx->precision) return fail(ctx, VIE_EINVAL, "precision does not match the bound workspace");
+  if (!eps_per_tet || !(lambda_nm > 0) || !(std::fabs(theta) < 1.5533)) return fail(ctx, VIE_EINVAL, "bad fill arguments");
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  double margin = 0;
+  std::string e = build_pgf_table(*ctx->tab, t.a, t.b, t.zmax - t.zmin, lambda_nm, theta, phi, &margin);
+  if (!e.empty()) return fail(ctx, VIE_EINVAL, "%s", e.c_str());
+  if (margin < 0.02) return fail(ctx, VIE_EWOOD, "Floquet order near grazing (margin %.3g < 0.02)", margin);
+  ctx->lambda = lambda_nm;
+  ctx->theta = theta;
+  ctx->phi = phi;
+  ctx->eps_int.resize(t.nt);
+  for (int64_t i = 0; i < t.nt; ++i) ctx->eps_int[i] = dz{eps_per_tet[i].re, -eps_per_tet[i].im};
+  // the previous fill's kernels may still read the tables: wait before overwriting
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->ws + L.pgf.off, ctx->tab, sizeof(PgfTable), hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->ws + L.eps.off, ctx->eps_int.data(), 16 * t.nt, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
+
+  const PgfTable *tab = ctx->ptr<PgfTable>(L.pgf);
+  const QuadRules *qr = ctx->ptr<QuadRules>(L.quad);
+  const TetGeom *tg = ctx->ptr<TetGeom>(L.tg);
+  const TetFace *t2f = ctx->ptr<TetFace>(L.t2f);
+  dz *alpha = ctx->ptr<dz>(L.alpha), *gsrc = ctx->ptr<dz>(L.gsrc), *kappa = ctx->ptr<dz>(L.kappa),
+     *inveps = ctx->ptr<dz>(L.inveps), *sigma = ctx->ptr<dz>(L.sigma), *Z = ctx->ptr<dz>(L.Z);
+  const double k0 = 2 * M_PI / lambda_nm;
+  const double k0sq9 = k0 * k0 / 9.0;
+  const double kx = k0 * std::sin(theta) * std::cos(phi), ky = k0 * std::sin(theta) * std::sin(phi);
+
+  hipLaunchKernelGGL(k_prep, dim3(nblk(t.nt, 256)), dim3(256), 0, ctx->stream, (int64_t)t.nt, t2f, tg,
+                     ctx->ptr<double>(L.area), ctx->ptr<dz>(L.eps), kx, ky, t.a, t.b, alpha, gsrc, kappa, inveps);
+  LAUNCHCK();
+  if (ctx->nface)
+    hipLaunchKernelGGL(k_sigma, dim3(nblk(ctx->nface, 256)), dim3(256), 0, ctx->stream, ctx->nface,
+                       ctx->ptr<int32_t>(L.ctp), ctx->ptr<int32_t>(L.ctm), (const dz *)kappa, sigma);
+  hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, Z, (int64_t)t.N * L.ld);
+  LAUNCHCK();
+  const int C = t.ncolors;
+  const int32_t *colors = ctx->ptr<int32_t>(L.colors);
+  for (int ct = 0; ct < C; ++ct)
+    for (int cs = 0; cs < C; ++cs) {
+      const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
+      hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), 0, ctx->stream, tab, qr, tg, t2f,
+                         colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
+                         (const dz *)gsrc, (const dz *)kappa, k0sq9, Z, L.ld);
+      LAUNCHCK();
+      const int g = ct * C + cs;
+      const int np = ctx->near_off[g + 1] - ctx->near_off[g];
+      if (np) {
+        hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), 0, ctx->stream, tab, qr, tg, t2f,
+                           ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
+                           ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
+                           (const dz *)kappa, (const dz *)inveps, k0sq9, Z, L.ld);
+        LAUNCHCK();
+      }
+    }
+  if (ctx->nface) {
+    const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
+    for (int ct = 0; ct < C; ++ct) {
+      const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
+      hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), 0, ctx->stream, tab, qr, tg,
+                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, Z,
+                         L.ld);
+      LAUNCHCK();
+    }
+    if (ctx->nhalf) {
+      for (int cs = 0; cs < C; ++cs) {
+        const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
+        hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), 0, ctx->stream, tab, qr,
+                           fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
+                           (const dz *)gsrc, (const dz *)kappa, Z, L.ld);
+        LAUNCHCK();
+      }
+      hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), 0, ctx->stream, tab,
+                         qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, Z, L.ld);
+      LAUNCHCK();
+    }
+  }
+  HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCK(hipEventSynchronize(ctx->ev1));
+  float ms = 0;
+  HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->t_fill = ms;
+  ctx->state = S_FILLED;
+  return VIE_OK;
+}
+
+// ---------------------------------------------------------------- factor
+int vie_precond_factor(vie_ctx *ctx) {
+  if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  dz *Z = ctx->ptr<dz>(L.Z);
+  dz *F = ctx->ptr<dz>(L.F);
+  int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *perm = ctx->ptr<int32_t>(L.perm), *info = ctx->ptr<int32_t>(L.info);
+  dz *rpiv = ctx->ptr<dz>(L.rpiv);
+  HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
+  HIPCK(hipMemsetAsync(info, 0, 4 * t.ndom, ctx->stream));
+  int64_t poff = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    const int n = (int)(t.dend[d] - t.dstart[d]);
+    if (n == 0) continue;
+    const int64_t ldf = L.fld[d];
+    dz *A = F + L.foff[d];
+    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld,
+                       t.dstart[d], n, A, ldf);
+    LAUNCHCK();
+    int32_t *ip = ipiv + poff;
+    for (int k0 = 0; k0 < n; k0 += kLuNB) {
+      const int jb = std::min(kLuNB, n - k0);
+      for (int j = k0; j < k0 + jb; ++j) {
+        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, ctx->stream, A, ldf, n, j, k0, jb, ip, rpiv, info + d);
+        if (j + 1 < n)
+          hipLaunchKernelGGL(k_lu_col, dim3(nblk(n - j - 1, 256)), dim3(256), 0, ctx->stream, A, ldf, n, j, k0, jb,
+                             (const dz *)rpiv);
+      }
+      LAUNCHCK();
+      hipLaunchKernelGGL(k_lu_swap, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, A, ldf, n, k0, jb,
+                         (const int32_t *)ip);
+      const int rest = n - k0 - jb;
+      if (rest > 0) {
+        hipLaunchKernelGGL(k_lu_trsm, dim3(nblk(rest, 64)), dim3(64), 0, ctx->stream, A, ldf, n, k0, jb);
+        hipLaunchKernelGGL(k_lu_gemm, dim3(nblk(rest, 64), nblk(rest, 64)), dim3(256), 0, ctx->stream, A, ldf, n, k0,
+                           jb);
+      }
+      LAUNCHCK();
+    }
+    hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)ip, perm + poff);
+    LAUNCHCK();
+    poff += n;
+  }
+  HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->pinned, info, 4 * t.ndom, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  float ms = 0;
+  HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->t_factor = ms;
+  const int32_t *inf = reinterpret_cast<const int32_t *>(ctx->pinned);
+  for (int d = 0; d < t.ndom; ++d)
+    if (inf[d]) return fail(ctx, VIE_ESINGULAR, "zero pivot in block %d at column %d", d, inf[d] - 1);
+  ctx->state = S_FACTORED;
+  return VIE_OK;
+}
+
+// ---------------------------------------------------------------- solve
+namespace {
+
+// out = M^{-1} v  (block-diagonal LU solves); uses vt, vu as scratch when
+// out differs from them.
+int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const dz *F = ctx->ptr<dz>(L.F);
+  const int32_t *perm = ctx->ptr<int32_t>(L.perm);
+  int64_t poff = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    const int n = (int)(t.dend[d] - t.dstart[d]);
+    if (n == 0) continue;
+    const int64_t off = t.dstart[d];
+    const dz *A = F + L.foff[d];
+    const int64_t ldf = L.fld[d];
+    hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, off, perm + poff, v, s1);
+    for (int b0 = 0; b0 < n; b0 += kTrsvNB) {
+      const int nb = std::min(kTrsvNB, n - b0);
+      hipLaunchKernelGGL(k_trsv_step<true>, dim3(nblk(n - b0 - nb, kTrsvRows)), dim3(256), 0, ctx->stream, A, ldf, n,
+                         b0, nb, s1 + off, s2 + off);
+    }
+    const int last = (n - 1) / kTrsvNB * kTrsvNB;
+    for (int b0 = last; b0 >= 0; b0 -= kTrsvNB) {
+      const int nb = std::min(kTrsvNB, n - b0);
+      hipLaunchKernelGGL(k_trsv_step<false>, dim3(nblk(b0, kTrsvRows)), dim3(256), 0, ctx->stream, A, ldf, n, b0,
+                         nb, s2 + off, out + off);
+    }
+    poff += n;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "preconditioner apply: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+int norm_to(vie_ctx *ctx, const dz *w, int64_t N, double *dst) {
+  const Layout &L = ctx->L;
+  hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(256), 0, ctx->stream, w, N, ctx->ptr<double>(L.npart));
+  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(1), 0, ctx->stream, (const double *)ctx->ptr<double>(L.npart),
+                     kRedBlocks, dst);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "norm: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+int read_scalar(vie_ctx *ctx, const double *dev, double *host) {
+  hipError_t e = hipMemcpyAsync(ctx->pinned, dev, 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "read-back: %s", hipGetErrorString(e));
+  *host = ctx->pinned[0];
+  return VIE_OK;
+}
+
+// CGS2 column j: H[:, j] = V_{0..j}^H w twice, w orthogonalised in place.
+int cgs2(vie_ctx *ctx, int j, dz *w) {
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  const dz *V = ctx->ptr<dz>(L.V);
+  dz *hcol = ctx->ptr<dz>(L.H) + (int64_t)j * (L.restart + 2);
+  dz *part = ctx->ptr<dz>(L.dpart);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(256), 0, ctx->stream, V, L.ldv, j + 1, (const dz *)w, N, part);
+    hipLaunchKernelGGL(k_dots_reduce, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)part, kRedBlocks,
+                       j + 1, hcol, pass);
+    // pass 0 subtracts h; pass 1 subtracts only the correction, computed into y as scratch
+    if (pass == 0) {
+      hipLaunchKernelGGL(k_update, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, V, L.ldv, j + 1, (const dz *)hcol, w,
+                         N);
+      hipLaunchKernelGGL(k_copy, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, ctx->ptr<dz>(L.y),
+                         (const dz *)hcol, (int64_t)(j + 1));
+    } else {
+      // hcol now holds h0 + h1; the correction is hcol - y
+      hipLaunchKernelGGL(k_sub_into, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)hcol,
+                         ctx->ptr<dz>(L.y), (int64_t)(j + 1));
+      hipLaunchKernelGGL(k_update, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, V, L.ldv, j + 1,
+                         (const dz *)ctx->ptr<dz>(L.y), w, N);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "cgs2: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+}  // namespace
+
+int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
+  if (int r = check(ctx, S_FACTORED, "vie_solve")) return r;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
+  if (!(tol > 0) || max_iter < 1) return fail(ctx, VIE_EINVAL, "bad tol / max_iter");
+  if (restart < 1 || restart > ctx->L.restart)
+    return fail(ctx, VIE_EINVAL, "restart %d exceeds the bound workspace (%d)", restart, ctx->L.restart);
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const int64_t N = t.N;
+  dz *Z = ctx->ptr<dz>(L.Z), *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g),
+     *y = ctx->ptr<dz>(L.y);
+  dz *b = ctx->ptr<dz>(L.vb), *x = ctx->ptr<dz>(L.vx), *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz),
+     *u = ctx->ptr<dz>(L.vu), *r = ctx->ptr<dz>(L.vr), *tmp = ctx->ptr<dz>(L.vt);
+  double *cs = ctx->ptr<double>(L.cs), *scal = ctx->ptr<double>(L.scal);
+  dz *sn = ctx->ptr<dz>(L.sn);
+  const int ldh = L.restart + 2;
+  ctx->hist.clear();
+  ctx->last_pol = pol;
+  HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
+
+  // right-hand side <f_m, E^i>
+  const double k0 = 2 * M_PI / ctx->lambda;
+  const double st = std::sin(ctx->theta), ct = std::cos(ctx->theta), sp = std::sin(ctx->phi), cp = std::cos(ctx->phi);
+  const double kix = k0 * st * cp, kiy = k0 * st * sp, kiz = -k0 * ct;
+  double ex, ey, ez;
+  if (pol == VIE_TE) {
+    ex = -sp;
+    ey = cp;
+    ez = 0;
+  } else {
+    ex = ct * cp;
+    ey = ct * sp;
+    ez = st;
+  }
+  hipLaunchKernelGGL(k_rhs, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, N, ctx->ptr<int32_t>(L.utet),
+                     ctx->ptr<int32_t>(L.uk), ctx->ptr<TetGeom>(L.tg), ctx->ptr<QuadRules>(L.quad),
+                     (const dz *)ctx->ptr<dz>(L.alpha), kix, kiy, kiz, ex, ey, ez, b);
+  hipLaunchKernelGGL(k_zero, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N);
+  hipLaunchKernelGGL(k_copy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, r, (const dz *)b, N);
+  LAUNCHCK();
+  if (int rc = norm_to(ctx, r, N, scal + 0)) return rc;   // scal[0] = ||b||
+  double bnorm = 0;
+  if (int rc = read_scalar(ctx, scal + 0, &bnorm)) return rc;
+  if (!(bnorm > 0)) return fail(ctx, VIE_EINVAL, "zero right-hand side");
+  HIPCK(hipMemcpyAsync(scal + 1, scal + 0, 8, hipMemcpyDeviceToDevice, ctx->stream));  // scal[1] = beta
+
+  int iters = 0, restarts = 0;
+  double beta = bnorm, true_rel = 1.0;
+  bool converged = false;
+  while (true) {
+    // V0 = r / beta ; g = beta e1
+    hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)r,
+                       (const double *)(scal + 1), V, N);
+    hipLaunchKernelGGL(k_ginit, dim3(1), dim3(256), 0, ctx->stream, g, restart + 1, (const double *)(scal + 1));
+    LAUNCHCK();
+    int jdone = 0;
+    bool est_ok = false;
+    for (int j = 0; j < restart; ++j) {
+      if (int rc = apply_minv(ctx, V + (int64_t)j * L.ldv, z, tmp, u)) return rc;
+      hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld, N,
+                         (const dz *)z, (const dz *)nullptr, w);
+      LAUNCHCK();
+      if (int rc = cgs2(ctx, j, w)) return rc;
+      if (int rc = norm_to(ctx, w, N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, ctx->stream, H, ldh, j, (const double *)(scal + 2), cs, sn, g,
+                         scal + 3);
+      hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)w,
+                         (const double *)(scal + 2), V + (int64_t)(j + 1) * L.ldv, N);
+      LAUNCHCK();
+      double res = 0;
+      if (int rc = read_scalar(ctx, scal + 3, &res)) return rc;
+      ++iters;
+      jdone = j + 1;
+      ctx->hist.push_back(res / bnorm);
+      if (res / bnorm <= tol) {
+        est_ok = true;
+        break;
+      }
+      if (iters >= max_iter) break;
+    }
+    // x += M^{-1} V y
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, ctx->stream, (const dz *)H, ldh, jdone, (const dz *)g, y);
+    hipLaunchKernelGGL(k_combine, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv, jdone,
+                       (const dz *)y, w, N);
+    LAUNCHCK();
+    if (int rc = apply_minv(ctx, w, u, tmp, z)) return rc;
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, (const dz *)u, N);
+    // true residual r = b - Z x
+    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld, N,
+                       (const dz *)x, (const dz *)b, r);
+    LAUNCHCK();
+    if (int rc = norm_to(ctx, r, N, scal + 1)) return rc;
+    if (int rc = read_scalar(ctx, scal + 1, &beta)) return rc;
+    true_rel = beta / bnorm;
+    if (true_rel <= tol || (est_ok && true_rel <= 10 * tol)) {
+      converged = true;
+      break;
+    }
+    if (iters >= max_iter) break;
+    ++restarts;
+  }
+  HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
+  HIPCK(hipEventSynchronize(ctx->ev1));
+  float ms = 0;
+  HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (info) {
+    info->iters = iters;
+    info->restarts = restarts;
+    info->refine_steps = 1;
+    info->true_rel_residual = true_rel;
+    info->t_fill_ms = ctx->t_fill;
+    info->t_factor_ms = ctx->t_factor;
+    info->t_solve_ms = ms;
+  }
+  ctx->state = S_SOLVED;
+  if (!converged) return fail(ctx, VIE_ENOCONV, "GMRES: %d iterations, relative residual %.3e", iters, true_rel);
+  return VIE_OK;
+}
+
+// ---------------------------------------------------------------- outputs
+int vie_absorption(vie_ctx *ctx, double *absorptance, double *R, double *T) {
+  if (int r = check(ctx, S_SOLVED, "vie_absorption")) return r;
+  if (!absorptance) return fail(ctx, VIE_EINVAL, "null output");
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const unsigned nb = nblk(t.nt, 256);
+  double *part = ctx->ptr<double>(L.apart);
+  double *out = ctx->ptr<double>(L.idx);
+  hipLaunchKernelGGL(k_absorb, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, t.ndom, ctx->ptr<TetGeom>(L.tg),
+                     ctx->ptr<TetFace>(L.t2f), ctx->ptr<int32_t>(L.dom), ctx->ptr<QuadRules>(L.quad),
+                     (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), (const dz *)ctx->ptr<dz>(L.vx),
+                     part);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, ctx->stream, (const double *)part, (int)nb, t.ndom, out);
+  LAUNCHCK();
+  std::vector<double> h(t.ndom);
+  HIPCK(hipMemcpyAsync(h.data(), out, 8 * t.ndom, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  const double k0 = 2 * M_PI / ctx->lambda;
+  const double scale = k0 / (std::cos(ctx->theta) * t.a * t.b);
+  for (int d = 0; d < t.ndom; ++d) absorptance[d] = h[d] * scale;
+
+  if (R || T) {
+    const double kx = k0 * std::sin(ctx->theta) * std::cos(ctx->phi), ky = k0 * std::sin(ctx->theta) * std::sin(ctx->phi);
+    std::vector<double> kvh;
+    std::vector<double> beta;
+    std::vector<int> isz;
+    for (int p = -kPgfM; p <= kPgfM; ++p)
+      for (int q = -kPgfM; q <= kPgfM; ++q) {
+        double tx = kx + 2 * M_PI * p / t.a, ty = ky + 2 * M_PI * q / t.b;
+        double kt2 = tx * tx + ty * ty;
+        if (kt2 >= k0 * k0) continue;
+        double bz = std::sqrt(k0 * k0 - kt2);
+        if ((int)beta.size() >= 32) break;
+        for (int s : {+1, -1}) {
+          kvh.push_back(tx);
+          kvh.push_back(ty);
+          kvh.push_back(s * bz);
+        }
+        beta.push_back(bz);
+        isz.push_back(p == 0 && q == 0);
+      }
+    const int nk = (int)kvh.size() / 3;
+    HIPCK(hipMemcpyAsync(ctx->ptr<double>(L.kv), kvh.data(), 8 * kvh.size(), hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, ctx->ptr<TetGeom>(L.tg),
+                       ctx->ptr<TetFace>(L.t2f), ctx->ptr<QuadRules>(L.quad), (const dz *)ctx->ptr<dz>(L.gsrc),
+                       (const dz *)ctx->ptr<dz>(L.kappa), (const dz *)ctx->ptr<dz>(L.vx), nk,
+                       (const double *)ctx->ptr<double>(L.kv), part);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(6 * nk, 256)), dim3(256), 0, ctx->stream, (const double *)part, (int)nb,
+                       6 * nk, out);
+    LAUNCHCK();
+    std::vector<double> v(6 * nk);
+    HIPCK(hipMemcpyAsync(v.data(), out, 8 * v.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    const double st = std::sin(ctx->theta), ct = std::cos(ctx->theta), sp = std::sin(ctx->phi), cp = std::cos(ctx->phi);
+    double e_inc[3];
+    if (ctx->last_pol == VIE_TE) {
+      e_inc[0] = -sp;
+      e_inc[1] = cp;
+      e_inc[2] = 0;
+    } else {
+      e_inc[0] = ct * cp;
+      e_inc[1] = ct * sp;
+      e_inc[2] = st;
+    }
+    const double beta00 = k0 * ct;
+    double Rs = 0, Ts = 0;
+    for (int i = 0; i < nk; ++i) {
+      const int mode = i / 2;
+      const bool up = (i % 2) == 0;
+      zd vv[3];
+      for (int d = 0; d < 3; ++d) vv[d] = zd(v[6 * i + 2 * d], v[6 * i + 2 * d + 1]);
+      const double *k = &kvh[3 * i];
+      zd kdotv = k[0] * vv[0] + k[1] * vv[1] + k[2] * vv[2];
+      zd gam(0, beta[mode]);
+      zd e[3];
+      for (int d = 0; d < 3; ++d) e[d] = (k0 * k0 * vv[d] - k[d] * kdotv) / (2 * t.a * t.b * gam);
+      if (!up && isz[mode])
+        for (int d = 0; d < 3; ++d) e[d] += e_inc[d];
+      double p2 = std::norm(e[0]) + std::norm(e[1]) + std::norm(e[2]);
+      if (up) Rs += p2 * beta[mode] / beta00;
+      else Ts += p2 * beta[mode] / beta00;
+    }
+    if (R) *R = Rs;
+    if (T) *T = Ts;
+  }
+  return VIE_OK;
+}
+
+// ---------------------------------------------------------------- diagnostics
+int vie_export_faces(const vie_ctx *c, int32_t *face_vid, int32_t *tplus, int32_t *tminus, int32_t *dom) {
+  if (!c || c->state < S_MESH) return VIE_ESTATE;
+  const MeshTopology &t = c->topo;
+  if (face_vid) std::memcpy(face_vid, t.face_vid.data(), 4 * 3 * t.N);
+  if (tplus) std::memcpy(tplus, t.tplus.data(), 4 * t.N);
+  if (tminus) std::memcpy(tminus, t.tminus.data(), 4 * t.N);
+  if (dom) std::memcpy(dom, t.fdom.data(), 4 * t.N);
+  return VIE_OK;
+}
+
+int vie_read_Z(const vie_ctx *cctx, const int64_t *rows, const int64_t *cols, int64_t k, vie_c128 *out) {
+  vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
+  if (int r = check(ctx, S_FILLED, "vie_read_Z")) return r;
+  if (!rows || !cols || !out || k < 0) return fail(ctx, VIE_EINVAL, "bad arguments");
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  HIPCK(hipSetDevice(ctx->device));
+  // rows, cols and values staged through the Krylov-basis region (clobbers it)
+  const int64_t cap = (int64_t)((L.V.bytes - 512) / 32);
+  if (cap < 1) return fail(ctx, VIE_ENOMEM, "no staging space");
+  int64_t *ri = ctx->ptr<int64_t>(L.V);
+  for (int64_t s = 0; s < k; s += cap) {
+    const int64_t n = std::min(cap, k - s);
+    for (int64_t i = 0; i < n; ++i)
+      if (rows[s + i] < 0 || rows[s + i] >= N || cols[s + i] < 0 || cols[s + i] >= N)
+        return fail(ctx, VIE_EINVAL, "index out of range");
+    dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(16 * (size_t)n));
+    HIPCK(hipMemcpyAsync(ri, rows + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(ri + n, cols + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z), L.ld,
+                       (const int64_t *)ri, (const int64_t *)(ri + n), n, o);
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(out + s, o, 16 * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+  }
+  return VIE_OK;
+}
+
+static int read_vec(const vie_ctx *cctx, const Region &r, vie_c128 *dst) {
+  vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
+  if (int rc = check(ctx, S_SOLVED, "read-back")) return rc;
+  if (!dst) return fail(ctx, VIE_EINVAL, "null output");
+  HIPCK(hipSetDevice(ctx->device));
+  HIPCK(hipMemcpyAsync(dst, ctx->ws + r.off, 16 * ctx->topo.N, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+int vie_read_rhs(const vie_ctx *ctx, vie_c128 *b) { return ctx ? read_vec(ctx, ctx->L.vb, b) : VIE_EINVAL; }
+int vie_read_solution(const vie_ctx *ctx, vie_c128 *x) { return ctx ? read_vec(ctx, ctx->L.vx, x) : VIE_EINVAL; }
+
+int vie_pgf_eval(vie_ctx *ctx, const double *delta, int64_t n, vie_c128 *out) {
+  if (int r = check(ctx, S_FILLED, "vie_pgf_eval")) return r;
+  const Layout &L = ctx->L;
+  if (!delta || !out || n < 0) return fail(ctx, VIE_EINVAL, "bad arguments");
+  // points and values staged in the Krylov-basis region (clobbers it), in chunks
+  const int64_t cap = (int64_t)((L.V.bytes - 512) / 40);
+  if (cap < 1) return fail(ctx, VIE_ENOMEM, "no staging space");
+  HIPCK(hipSetDevice(ctx->device));
+  double *d = ctx->ptr<double>(L.V);
+  for (int64_t s = 0; s < n; s += cap) {
+    const int64_t m = std::min(cap, n - s);
+    dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(24 * (size_t)m));
+    HIPCK(hipMemcpyAsync(d, delta + 3 * s, 24 * m, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_pgf_probe, dim3(nblk(m, 256)), dim3(256), 0, ctx->stream, ctx->ptr<PgfTable>(L.pgf),
+                       (const double *)d, m, o);
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(out + s, o, 16 * m, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+  }
+  return VIE_OK;
+}
+
+int vie_residual_history(const vie_ctx *ctx, double *hist, int cap) {
+  if (!ctx || !hist || cap < 0) return VIE_EINVAL;
+  int n = std::min<int>(cap, (int)ctx->hist.size());
+  for (int i = 0; i < n; ++i) hist[i] = ctx->hist[i];
+  return n;
+}
+
+}  // extern "C"

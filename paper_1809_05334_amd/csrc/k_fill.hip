@@ -1,0 +1,477 @@
+// Impedance-matrix fill of the periodic SWG VIE (Sec. 2.1, Eq. 2 with the
+// periodic Green's function of Sec. 2.2, Eqs. 3-4), right-hand side, and a
+// diagnostic evaluation of g_p.
+//
+// Galerkin terms for test tet T (local face k -> unknown m) and source tet S
+// (local face l -> unknown n), u = r - c_T, u' = r' - c_S, p~ = v_k - c_T,
+// q~ = v'_l - c_S:
+//   Z_mn += alpha_Tk * beta_Sl * [ II g_p - (k0^2/9) II (u - p~).(u' - q~) g_p ]
+//   alpha_Tk = chi s a_m / V_T,   beta_Sl = psi s a_n kappa_S / V_S,
+// with the Bloch test/source phases chi = e^{+j kt.rho}, psi = e^{-j kt.rho} of
+// a wall-shifted half.  Surface charges (sigma_n on interface/boundary faces)
+// and the boundary term of half-SWG test faces add scalar-potential pairs of
+// tetrahedra and faces.  The mass term <f_m, f_n/eps> is added with the
+// self pair.
+//
+// Scatter: every launch covers a pair of tetrahedron colour classes (no two
+// tetrahedra of a class share a face), so no two lanes of one launch touch
+// the same Z entry; the read-modify-write needs no atomics and the result is
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace vie {
+
+static constexpr double kInv4Pi = 0.079577471545947667884;
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void zadd(dz *__restrict__ Z, int64_t idx, dz v) {
+  dz z = Z[idx];
+  Z[idx] = z + v;
+}
+
+// ------------------------------------------------------------ per-fill coefficients
+__global__ void k_prep(int64_t nt, const TetFace *__restrict__ t2f, const TetGeom *__restrict__ tg,
+                       const double *__restrict__ area, const dz *__restrict__ eps_int, double kx, double ky,
+                       double a, double b, dz *__restrict__ alpha, dz *__restrict__ gsrc, dz *__restrict__ kappa,
+                       dz *__restrict__ inv_eps) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const dz e = eps_int[t];
+  const double den = e.re * e.re + e.im * e.im;
+  const dz ie = mk(e.re / den, -e.im / den);
+  inv_eps[t] = ie;
+  kappa[t] = mk(1.0 - ie.re, -ie.im);
+  const double V = tg[t].vol;
+  for (int k = 0; k < 4; ++k) {
+    const TetFace f = t2f[4 * t + k];
+    double s, c;
+    sincos(kx * f.sx * a + ky * f.sy * b, &s, &c);
+    const double w = f.sign * area[f.unknown] / V;
+    alpha[4 * t + k] = mk(w * c, w * s);   // e^{+j kt.rho} s a / V
+    gsrc[4 * t + k] = mk(w * c, -w * s);   // e^{-j kt.rho} s a / V
+  }
+}
+
+// sigma_n = kappa(T+) - kappa(T-) for each surface-charge face slot
+__global__ void k_sigma(int nc, const int32_t *__restrict__ ctp, const int32_t *__restrict__ ctm,
+                        const dz *__restrict__ kappa, dz *__restrict__ sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  dz s = kappa[ctp[i]];
+  if (ctm[i] >= 0) s = s - kappa[ctm[i]];
+  sigma[i] = s;
+}
+
+__global__ void k_zero(dz *__restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = mk(0.0, 0.0);
+}
+
+// ------------------------------------------------------------ tet-pair moments
+struct Moments {
+  dz m0, mu[3], mv[3], muv;
+};
+
+__device__ __forceinline__ void moments_zero(Moments &M) {
+  M.m0 = mk(0, 0);
+  M.muv = mk(0, 0);
+  for (int d = 0; d < 3; ++d) M.mu[d] = M.mv[d] = mk(0, 0);
+}
+
+// Scatter the 16 face-pair contributions of tet pair (T, S) into Z.
+__device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, const TetGeom &gs,
+                                           const TetFace *__restrict__ t2f, int T, int S,
+                                           const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                           const dz *__restrict__ kappa, double k0sq9, dz *__restrict__ Z,
+                                           int64_t ld) {
+  const dz ks = kappa[S];
+  double qv[4][3];
+  dz bl[4];
+  int64_t col[4];
+  for (int l = 0; l < 4; ++l) {
+    for (int d = 0; d < 3; ++d) qv[l][d] = gs.v[l][d] - gs.c[d];
+    bl[l] = gsrc[4 * S + l] * ks;
+    col[l] = t2f[4 * S + l].unknown;
+  }
+  for (int k = 0; k < 4; ++k) {
+    double pk[3];
+    for (int d = 0; d < 3; ++d) pk[d] = gt.v[k][d] - gt.c[d];
+    // muv - p~.mv
+    dz base = M.muv;
+    for (int d = 0; d < 3; ++d) base = base - pk[d] * M.mv[d];
+    const dz ak = alpha[4 * T + k];
+    const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
+    for (int l = 0; l < 4; ++l) {
+      dz I = base;
+      for (int d = 0; d < 3; ++d) I = I - qv[l][d] * M.mu[d];
+      I = I + dot3(pk, qv[l]) * M.m0;
+      const dz v = M.m0 - k0sq9 * I;
+      zadd(Z, row + col[l], (ak * bl[l]) * v);
+    }
+  }
+}
+
+// Far tet pairs: 4 x 4 product rule.  One wave = one test tet x 64 source tets.
+__global__ __launch_bounds__(256) void k_tt_far(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+                                                const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                const int32_t *__restrict__ test_list, int ntest,
+                                                const int32_t *__restrict__ src_list, int nsrc,
+                                                const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                                const dz *__restrict__ kappa, double k0sq9, dz *__restrict__ Z,
+                                                int64_t ld) {
+  const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int si = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (ti >= ntest || si >= nsrc) return;
+  const int T = uniform(test_list[ti]);
+  const int S = src_list[si];
+  const TetGeom &gt = tg[T];
+  const TetGeom gs = tg[S];
+  if (touch_mask(gt.canon, gt.off, 4, gs.canon, gs.off, 4)) return;  // touching pairs: k_tt_near
+
+  double up[4][3], wq = 0.25 * gs.vol, wt = 0.25 * gt.vol;
+  for (int j = 0; j < 4; ++j)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
+      up[j][d] = s - gs.c[d];
+    }
+  Moments M;
+  moments_zero(M);
+  const double dc[3] = {gt.c[0] - gs.c[0], gt.c[1] - gs.c[1], gt.c[2] - gs.c[2]};
+  for (int i = 0; i < 4; ++i) {
+    double u[3];
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
+      u[d] = s - gt.c[d];
+    }
+    for (int j = 0; j < 4; ++j) {
+      const dz g = pgf_eval<false>(tab, dc[0] + u[0] - up[j][0], dc[1] + u[1] - up[j][1],
+                                   dc[2] + u[2] - up[j][2], 0);
+      const dz gw = (wt * wq) * g;
+      M.m0 = M.m0 + gw;
+      for (int d = 0; d < 3; ++d) {
+        axpy(M.mu[d], u[d], gw);
+        axpy(M.mv[d], up[j][d], gw);
+      }
+      axpy(M.muv, dot3(u, up[j]), gw);
+    }
+  }
+  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, Z, ld);
+}
+
+// Touching tet pairs: 14-point outer rule on T; per touching image the closed
+// form int_S 1/R and int_S (r'-r)/R; 4-point inner rule for the remainder.
+// The self pair also adds the mass term <f_m, f_n / eps_r>.
+__global__ __launch_bounds__(128) void k_tt_near(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+                                                 const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                 const int32_t *__restrict__ lt, const int32_t *__restrict__ ls,
+                                                 const int32_t *__restrict__ lmask, int npairs,
+                                                 const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                                 const dz *__restrict__ kappa, const dz *__restrict__ inv_eps,
+                                                 double k0sq9, dz *__restrict__ Z, int64_t ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  const int T = lt[i], S = ls[i], mask = lmask[i];
+  const TetGeom gt = tg[T];
+  const TetGeom gs = tg[S];
+  double up[4][3];
+  const double wq = 0.25 * gs.vol;
+  for (int j = 0; j < 4; ++j)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
+      up[j][d] = s - gs.c[d];
+    }
+  Moments M;
+  moments_zero(M);
+  for (int q = 0; q < 14; ++q) {
+    double r[3], u[3];
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet14[q][k], gt.v[k][d], s);
+      r[d] = s;
+      u[d] = s - gt.c[d];
+    }
+    const double w = qr->w14[q] * gt.vol;
+    dz s0 = mk(0, 0), s1[3] = {mk(0, 0), mk(0, 0), mk(0, 0)};
+    for (int b = 0; b < 9; ++b) {
+      if (!((mask >> b) & 1)) continue;
+      const int m = b / 3 - 1, n = b % 3 - 1;
+      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      double P, V1[3];
+      tet_potentials(gs.v, o, P, V1);
+      const dz ph = kInv4Pi * mk(tab->ph0re[b], -tab->ph0im[b]);  // e^{+j kt.rho}/(4 pi)
+      s0 = s0 + P * ph;
+      for (int d = 0; d < 3; ++d) s1[d] = s1[d] + (V1[d] + (o[d] - gs.c[d]) * P) * ph;
+    }
+    for (int j = 0; j < 4; ++j) {
+      const dz g = pgf_eval<true>(tab, r[0] - gs.c[0] - up[j][0], r[1] - gs.c[1] - up[j][1],
+                                  r[2] - gs.c[2] - up[j][2], mask);
+      axpy(s0, wq, g);
+      for (int d = 0; d < 3; ++d) axpy(s1[d], wq * up[j][d], g);
+    }
+    axpy(M.m0, w, s0);
+    for (int d = 0; d < 3; ++d) {
+      axpy(M.mu[d], w * u[d], s0);
+      axpy(M.mv[d], w, s1[d]);
+    }
+    dz us = mk(0, 0);
+    for (int d = 0; d < 3; ++d) axpy(us, u[d], s1[d]);
+    axpy(M.muv, w, us);
+  }
+  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, Z, ld);
+  if (T == S) {
+    // mass <f_m, f_n / eps_r>: alpha_k gsrc_l / (9 eps) int_T (r - v_k).(r - v_l), 4-point rule (exact)
+    const dz ie = inv_eps[T];
+    for (int k = 0; k < 4; ++k) {
+      const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
+      for (int l = 0; l < 4; ++l) {
+        double s = 0;
+        for (int q = 0; q < 4; ++q) {
+          double a2 = 0;
+          for (int d = 0; d < 3; ++d) {
+            double r = 0;
+            for (int kk = 0; kk < 4; ++kk) r = fma(qr->tet4[q][kk], gt.v[kk][d], r);
+            a2 = fma(r - gt.v[k][d], r - gt.v[l][d], a2);
+          }
+          s = fma(0.25 * gt.vol, a2, s);
+        }
+        zadd(Z, row + t2f[4 * T + l].unknown, (s / 9.0) * ((alpha[4 * T + k] * gsrc[4 * T + l]) * ie));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ pairs with faces
+// M0 = II g_p over (test tet T, face F).  Far: 4 x 3 rule.  Touching: outer
+// 14-point rule on T, closed-form int_F 1/R per touching image, 3-point
+// inner rule for the remainder.
+__device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const TetGeom &gt,
+                            const FaceGeom &f) {
+  const int mask = touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3);
+  double fp[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int d = 0; d < 3; ++d) fp[j][d] = qr->tri3[j][0] * f.v[0][d] + qr->tri3[j][1] * f.v[1][d] + qr->tri3[j][2] * f.v[2][d];
+  const double wf = f.area / 3.0;
+  dz acc = mk(0, 0);
+  if (!mask) {
+    for (int i = 0; i < 4; ++i) {
+      double r[3];
+      for (int d = 0; d < 3; ++d) {
+        double s = 0;
+        for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
+        r[d] = s;
+      }
+      for (int j = 0; j < 3; ++j)
+        acc = acc + pgf_eval<false>(tab, r[0] - fp[j][0], r[1] - fp[j][1], r[2] - fp[j][2], 0);
+    }
+    return (0.25 * gt.vol * wf) * acc;
+  }
+  for (int q = 0; q < 14; ++q) {
+    double r[3];
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet14[q][k], gt.v[k][d], s);
+      r[d] = s;
+    }
+    dz s0 = mk(0, 0);
+    for (int b = 0; b < 9; ++b) {
+      if (!((mask >> b) & 1)) continue;
+      const int m = b / 3 - 1, n = b % 3 - 1;
+      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      double iinv, ione;
+      tri_potentials(f.v[0], f.v[1], f.v[2], o, iinv, ione);
+      s0 = s0 + (kInv4Pi * iinv) * mk(tab->ph0re[b], -tab->ph0im[b]);
+    }
+    for (int j = 0; j < 3; ++j)
+      axpy(s0, wf, pgf_eval<true>(tab, r[0] - fp[j][0], r[1] - fp[j][1], r[2] - fp[j][2], mask));
+    axpy(acc, qr->w14[q] * gt.vol, s0);
+  }
+  return acc;
+}
+
+// M0 = II g_p over (test face F, source tet S).  Touching: outer 7-point rule
+// on F, closed-form int_S 1/R, 4-point inner rule for the remainder.
+__device__ dz pair_face_tet(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const FaceGeom &f,
+                            const TetGeom &gs) {
+  const int mask = touch_mask(f.canon, f.off, 3, gs.canon, gs.off, 4);
+  double sp[4][3];
+  for (int j = 0; j < 4; ++j)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
+      sp[j][d] = s;
+    }
+  const double ws = 0.25 * gs.vol;
+  dz acc = mk(0, 0);
+  if (!mask) {
+    for (int i = 0; i < 3; ++i) {
+      double r[3];
+      for (int d = 0; d < 3; ++d) r[d] = qr->tri3[i][0] * f.v[0][d] + qr->tri3[i][1] * f.v[1][d] + qr->tri3[i][2] * f.v[2][d];
+      for (int j = 0; j < 4; ++j)
+        acc = acc + pgf_eval<false>(tab, r[0] - sp[j][0], r[1] - sp[j][1], r[2] - sp[j][2], 0);
+    }
+    return (f.area / 3.0 * ws) * acc;
+  }
+  for (int q = 0; q < 7; ++q) {
+    double r[3];
+    for (int d = 0; d < 3; ++d) r[d] = qr->tri7[q][0] * f.v[0][d] + qr->tri7[q][1] * f.v[1][d] + qr->tri7[q][2] * f.v[2][d];
+    dz s0 = mk(0, 0);
+    for (int b = 0; b < 9; ++b) {
+      if (!((mask >> b) & 1)) continue;
+      const int m = b / 3 - 1, n = b % 3 - 1;
+      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      double P, V1[3];
+      tet_potentials(gs.v, o, P, V1);
+      s0 = s0 + (kInv4Pi * P) * mk(tab->ph0re[b], -tab->ph0im[b]);
+    }
+    for (int j = 0; j < 4; ++j)
+      axpy(s0, ws, pgf_eval<true>(tab, r[0] - sp[j][0], r[1] - sp[j][1], r[2] - sp[j][2], mask));
+    axpy(acc, qr->w7[q] * f.area, s0);
+  }
+  return acc;
+}
+
+// M0 = II g_p over (test face F, source face G).
+__device__ dz pair_face_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const FaceGeom &f,
+                             const FaceGeom &g) {
+  const int mask = touch_mask(f.canon, f.off, 3, g.canon, g.off, 3);
+  double gp[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int d = 0; d < 3; ++d) gp[j][d] = qr->tri3[j][0] * g.v[0][d] + qr->tri3[j][1] * g.v[1][d] + qr->tri3[j][2] * g.v[2][d];
+  const double wg = g.area / 3.0;
+  dz acc = mk(0, 0);
+  if (!mask) {
+    for (int i = 0; i < 3; ++i) {
+      double r[3];
+      for (int d = 0; d < 3; ++d) r[d] = qr->tri3[i][0] * f.v[0][d] + qr->tri3[i][1] * f.v[1][d] + qr->tri3[i][2] * f.v[2][d];
+      for (int j = 0; j < 3; ++j)
+        acc = acc + pgf_eval<false>(tab, r[0] - gp[j][0], r[1] - gp[j][1], r[2] - gp[j][2], 0);
+    }
+    return (f.area / 3.0 * wg) * acc;
+  }
+  for (int q = 0; q < 7; ++q) {
+    double r[3];
+    for (int d = 0; d < 3; ++d) r[d] = qr->tri7[q][0] * f.v[0][d] + qr->tri7[q][1] * f.v[1][d] + qr->tri7[q][2] * f.v[2][d];
+    dz s0 = mk(0, 0);
+    for (int b = 0; b < 9; ++b) {
+      if (!((mask >> b) & 1)) continue;
+      const int m = b / 3 - 1, n = b % 3 - 1;
+      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      double iinv, ione;
+      tri_potentials(g.v[0], g.v[1], g.v[2], o, iinv, ione);
+      s0 = s0 + (kInv4Pi * iinv) * mk(tab->ph0re[b], -tab->ph0im[b]);
+    }
+    for (int j = 0; j < 3; ++j)
+      axpy(s0, wg, pgf_eval<true>(tab, r[0] - gp[j][0], r[1] - gp[j][1], r[2] - gp[j][2], mask));
+    axpy(acc, qr->w7[q] * f.area, s0);
+  }
+  return acc;
+}
+
+// test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0
+__global__ __launch_bounds__(256) void k_tet_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+                                                  const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                  const int32_t *__restrict__ test_list, int ntest,
+                                                  const FaceGeom *__restrict__ fg, int nface,
+                                                  const dz *__restrict__ alpha, const dz *__restrict__ sigma,
+                                                  dz *__restrict__ Z, int64_t ld) {
+  const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int fi = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (ti >= ntest || fi >= nface) return;
+  const int T = uniform(test_list[ti]);
+  const TetGeom &gt = tg[T];
+  const FaceGeom f = fg[fi];
+  const dz m0 = pair_tet_face(tab, qr, gt, f);
+  const dz sm = sigma[fi] * m0;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
+    zadd(Z, row + f.unknown, mk(0, 0) - alpha[4 * T + k] * sm);
+  }
+}
+
+// half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0
+__global__ __launch_bounds__(256) void k_face_tet(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+                                                  const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
+                                                  int nhalf, const TetGeom *__restrict__ tg,
+                                                  const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
+                                                  int nsrc, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                  dz *__restrict__ Z, int64_t ld) {
+  const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int si = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (hi >= nhalf || si >= nsrc) return;
+  const FaceGeom &f = fg[uniform(half_list[hi])];
+  const int S = src_list[si];
+  const TetGeom gs = tg[S];
+  const dz m0 = pair_face_tet(tab, qr, f, gs) * kappa[S];
+  const int64_t row = (int64_t)f.unknown * ld;
+  for (int l = 0; l < 4; ++l) zadd(Z, row + t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0);
+}
+
+// half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
+__global__ __launch_bounds__(256) void k_face_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+                                                   const FaceGeom *__restrict__ fg,
+                                                   const int32_t *__restrict__ half_list, int nhalf, int nface,
+                                                   const dz *__restrict__ sigma, dz *__restrict__ Z, int64_t ld) {
+  const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (hi >= nhalf || gi >= nface) return;
+  const FaceGeom &f = fg[uniform(half_list[hi])];
+  const FaceGeom g = fg[gi];
+  const dz m0 = pair_face_face(tab, qr, f, g);
+  zadd(Z, (int64_t)f.unknown * ld + g.unknown, sigma[gi] * m0);
+}
+
+// ------------------------------------------------------------ right-hand side
+// b_m = sum_{T in m} chi s a_m/(3 V_T) int_T (r - p).E^i dV, 14-point rule;
+// one thread per unknown (gathers its two halves, no write conflicts).
+__global__ void k_rhs(int64_t N, const int32_t *__restrict__ utet, const int32_t *__restrict__ uk,
+                      const TetGeom *__restrict__ tg, const QuadRules *__restrict__ qr, const dz *__restrict__ alpha,
+                      double kix, double kiy, double kiz, double ex, double ey, double ez, dz *__restrict__ b) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  dz acc = mk(0, 0);
+  for (int h = 0; h < 2; ++h) {
+    const int T = utet[2 * m + h];
+    if (T < 0) continue;
+    const int k = uk[2 * m + h];
+    const TetGeom &g = tg[T];
+    dz s = mk(0, 0);
+    for (int q = 0; q < 14; ++q) {
+      double r[3];
+      for (int d = 0; d < 3; ++d) {
+        double t = 0;
+        for (int kk = 0; kk < 4; ++kk) t = fma(qr->tet14[q][kk], g.v[kk][d], t);
+        r[d] = t;
+      }
+      const double proj = (r[0] - g.v[k][0]) * ex + (r[1] - g.v[k][1]) * ey + (r[2] - g.v[k][2]) * ez;
+      double sn, cs;
+      sincos(-(kix * r[0] + kiy * r[1] + kiz * r[2]), &sn, &cs);
+      axpy(s, qr->w14[q] * g.vol * proj, mk(cs, sn));
+    }
+    acc = acc + alpha[4 * T + k] * ((1.0 / 3.0) * s);
+  }
+  b[m] = acc;
+}
+
+// ------------------------------------------------------------ diagnostics
+__global__ void k_pgf_probe(const PgfTable *__restrict__ tab, const double *__restrict__ d, int64_t n,
+                            dz *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = pgf_eval<false>(tab, d[3 * i], d[3 * i + 1], d[3 * i + 2], 0);
+}
+
+// gather Z entries
+__global__ void k_gather(const dz *__restrict__ Z, int64_t ld, const int64_t *__restrict__ rows,
+                         const int64_t *__restrict__ cols, int64_t k, dz *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  out[i] = Z[rows[i] * ld + cols[i]];
+}
+
+}  // namespace vie

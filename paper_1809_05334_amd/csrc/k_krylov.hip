@@ -1,0 +1,223 @@
+// GMRES building blocks (Sec. 3): dense complex matrix-vector product,
+// classical Gram-Schmidt (applied twice) against the Krylov basis, norms,
+// Givens rotations on the Hessenberg matrix, and the final small solve.
+// All in FP64.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace vie {
+
+__device__ __forceinline__ dz wsum(dz v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_xor(v.re, o);
+    v.im += __shfl_xor(v.im, o);
+  }
+  return v;
+}
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// y = Z x  (or y = b - Z x when b != nullptr).  Z row-major, N x ld.
+// A block of 4 waves owns 4*RPW consecutive rows; x is staged through LDS in
+// chunks shared by the block, Z is streamed once with non-temporal loads.
+constexpr int kMvChunk = 1024;
+
+__global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_t ld, int64_t N,
+                                                const dz *__restrict__ x, const dz *__restrict__ b,
+                                                dz *__restrict__ y) {
+  __shared__ dz xs[kMvChunk];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * kMvRPW;
+  double are[kMvRPW], aim[kMvRPW];
+  for (int r = 0; r < kMvRPW; ++r) are[r] = aim[r] = 0.0;
+  const double *Zd = reinterpret_cast<const double *>(Z);
+  for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
+    const int len = (int)min<int64_t>(kMvChunk, N - c0);
+    __syncthreads();
+    for (int i = tid; i < len; i += 256) xs[i] = x[c0 + i];
+    __syncthreads();
+    for (int cc = lane; cc < len; cc += 64) {
+      const dz xv = xs[cc];
+#pragma unroll
+      for (int r = 0; r < kMvRPW; ++r) {
+        const int64_t row = row0 + r;
+        if (row < N) {
+          const int64_t o = 2 * (row * ld + c0 + cc);
+          const double zr = __builtin_nontemporal_load(Zd + o);
+          const double zi = __builtin_nontemporal_load(Zd + o + 1);
+          are[r] = fma(zr, xv.re, fma(-zi, xv.im, are[r]));
+          aim[r] = fma(zr, xv.im, fma(zi, xv.re, aim[r]));
+        }
+      }
+    }
+  }
+  for (int r = 0; r < kMvRPW; ++r) {
+    const double sr = wsum(are[r]), si = wsum(aim[r]);
+    const int64_t row = row0 + r;
+    if (lane == 0 && row < N) {
+      if (b) y[row] = mk(b[row].re - sr, b[row].im - si);
+      else y[row] = mk(sr, si);
+    }
+  }
+}
+
+// Partial inner products h_i = sum_k conj(V_i[k]) w[k], i < nv, per block:
+// part[blockIdx.x * nv + i].  V column-major: V_i = V + i * ldv.
+__global__ __launch_bounds__(256) void k_dots(const dz *__restrict__ V, int64_t ldv, int nv,
+                                              const dz *__restrict__ w, int64_t N, dz *__restrict__ part) {
+  __shared__ dz red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
+  for (int i = 0; i < nv; ++i) {
+    const dz *Vi = V + (int64_t)i * ldv;
+    dz s = mk(0, 0);
+    for (int64_t k = lo + tid; k < hi; k += 256) {
+      const dz v = Vi[k], ww = w[k];
+      s.re = fma(v.re, ww.re, fma(v.im, ww.im, s.re));
+      s.im = fma(v.re, ww.im, fma(-v.im, ww.re, s.im));
+    }
+    s = wsum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) part[(int64_t)blockIdx.x * nv + i] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// h[i] (+)= sum_b part[b * nv + i]; one thread per i (nblk small).
+__global__ void k_dots_reduce(const dz *__restrict__ part, int nblk, int nv, dz *__restrict__ h, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  dz s = mk(0, 0);
+  for (int b = 0; b < nblk; ++b) s = s + part[(int64_t)b * nv + i];
+  h[i] = accumulate ? h[i] + s : s;
+}
+
+// w[k] -= sum_{i<nv} V_i[k] c[i]
+__global__ __launch_bounds__(256) void k_update(const dz *__restrict__ V, int64_t ldv, int nv,
+                                                const dz *__restrict__ c, dz *__restrict__ w, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  dz s = w[k];
+  for (int i = 0; i < nv; ++i) s = s - V[(int64_t)i * ldv + k] * c[i];
+  w[k] = s;
+}
+
+// y[k] = sum_{i<nv} V_i[k] c[i]
+__global__ __launch_bounds__(256) void k_combine(const dz *__restrict__ V, int64_t ldv, int nv,
+                                                 const dz *__restrict__ c, dz *__restrict__ y, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  dz s = mk(0, 0);
+  for (int i = 0; i < nv; ++i) s = s + V[(int64_t)i * ldv + k] * c[i];
+  y[k] = s;
+}
+
+// partial squared norms per block
+__global__ __launch_bounds__(256) void k_norm2(const dz *__restrict__ w, int64_t N, double *__restrict__ part) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
+  double s = 0;
+  for (int64_t k = lo + tid; k < hi; k += 256) s = fma(w[k].re, w[k].re, fma(w[k].im, w[k].im, s));
+  s = wsum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// out = sqrt(sum part)
+__global__ void k_norm_reduce(const double *__restrict__ part, int nblk, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  *out = sqrt(s);
+}
+
+// v = w / *nrm  (or v = w * scale when nrm == nullptr)
+__global__ void k_scale(const dz *__restrict__ w, const double *__restrict__ nrm, dz *__restrict__ v, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double s = 1.0 / *nrm;
+  v[k] = s * w[k];
+}
+
+__global__ void k_axpy(dz *__restrict__ x, const dz *__restrict__ u, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) x[k] = x[k] + u[k];
+}
+
+// y = a - y
+__global__ void k_sub_into(const dz *__restrict__ a, dz *__restrict__ y, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] = a[k] - y[k];
+}
+
+__global__ void k_copy(dz *__restrict__ d, const dz *__restrict__ s, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) d[k] = s[k];
+}
+
+// GMRES state on the device: H (ldh x m, column j holds h_{0..j+1, j}),
+// Givens cosines (real) and sines (complex), g (m+1).
+// Arnoldi column j: h[0..j] from CGS2, hn = ||w||.  Apply the previous
+// rotations to column j, form the new one, update g, write |g[j+1]|.
+__global__ void k_givens(dz *__restrict__ H, int ldh, int j, const double *__restrict__ hn,
+                         double *__restrict__ cs, dz *__restrict__ sn, dz *__restrict__ g, double *__restrict__ res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  dz *h = H + (int64_t)j * ldh;
+  h[j + 1] = mk(*hn, 0.0);
+  for (int i = 0; i < j; ++i) {
+    // [c  s; -conj(s) c] acting on (h_i, h_{i+1})
+    const dz a = h[i], b = h[i + 1];
+    h[i] = cs[i] * a + sn[i] * b;
+    h[i + 1] = cs[i] * b - conjz(sn[i]) * a;
+  }
+  const dz a = h[j], b = h[j + 1];
+  const double na = sqrt(a.re * a.re + a.im * a.im), nb = sqrt(b.re * b.re + b.im * b.im);
+  double c;
+  dz s;
+  if (na == 0.0) {
+    c = 0.0;
+    s = mk(1.0, 0.0);
+    h[j] = b;
+  } else {
+    const double t = sqrt(na * na + nb * nb);
+    c = na / t;
+    const dz al = mk(a.re / na, a.im / na);       // a / |a|
+    s = (1.0 / t) * (al * conjz(b));              // alpha conj(b) / t
+    h[j] = al * mk(t, 0.0);
+  }
+  h[j + 1] = mk(0.0, 0.0);
+  cs[j] = c;
+  sn[j] = s;
+  const dz gj = g[j];
+  g[j] = c * gj;
+  g[j + 1] = mk(0, 0) - conjz(s) * gj;
+  *res = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im);
+}
+
+// y = R^{-1} g for the leading k x k upper triangle of H (single thread).
+__global__ void k_backsolve(const dz *__restrict__ H, int ldh, int k, const dz *__restrict__ g, dz *__restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    dz s = g[i];
+    for (int l = i + 1; l < k; ++l) s = s - H[(int64_t)l * ldh + i] * y[l];
+    const dz d = H[(int64_t)i * ldh + i];
+    const double den = d.re * d.re + d.im * d.im;
+    y[i] = mk((s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den);
+  }
+}
+
+// g = (beta, 0, ..., 0)
+__global__ void k_ginit(dz *__restrict__ g, int m1, const double *__restrict__ beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m1) g[i] = i == 0 ? mk(*beta, 0.0) : mk(0.0, 0.0);
+}
+
+}  // namespace vie

@@ -1,0 +1,304 @@
+// Diagonal-block preconditioner of Sec. 2.3 (Eq. 6): LU factorisation with
+// partial pivoting of each material-domain block A_dd, and the forward/back
+// substitutions that apply A_dd^{-1} inside GMRES.
+//
+// Right-looking blocked LU on a row-major complex FP64 block (leading
+// dimension ld): per panel of nb columns, a column-by-column panel
+// factorisation (pivot search, row swap inside the panel, scale, rank-1
+// update), the panel's row swaps applied to the other columns, a triangular
+// solve for the U12 block row, and the trailing update A22 -= L21 U12 on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64, four real products per complex
+// product).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace vie {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double cabs1(dz a) { return fabs(a.re) + fabs(a.im); }
+
+// copy the diagonal block Z[start:start+n, start:start+n] into A (ld lda)
+__global__ void k_copy_block(const dz *__restrict__ Z, int64_t ldz, int64_t start, int n, dz *__restrict__ A,
+                             int64_t lda) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c < n) A[(int64_t)r * lda + c] = Z[(start + r) * ldz + start + c];
+}
+
+// ------------------------------------------------------------ panel
+// Pivot search in column j (rows j..n-1), swap rows j and p inside the panel
+// columns [k0, k0+jb), store ipiv[j] = p and the reciprocal pivot.
+__global__ __launch_bounds__(1024) void k_lu_pivot(dz *__restrict__ A, int64_t ld, int n, int j, int k0, int jb,
+                                                   int32_t *__restrict__ ipiv, dz *__restrict__ rpiv,
+                                                   int32_t *__restrict__ info) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = j + tid; i < n; i += 1024) {
+    const double v = cabs1(A[(int64_t)i * ld + j]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = sv[tid + s];
+      const int oi = si[tid + s];
+      if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) {
+        sv[tid] = o;
+        si[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = si[0];
+  const double pv = sv[0];
+  if (tid == 0) ipiv[j] = p;
+  if (p != j)
+    for (int c = k0 + tid; c < k0 + jb; c += 1024) {
+      const dz t = A[(int64_t)j * ld + c];
+      A[(int64_t)j * ld + c] = A[(int64_t)p * ld + c];
+      A[(int64_t)p * ld + c] = t;
+    }
+  __syncthreads();
+  if (tid == 0) {
+    if (!(pv > 0.0)) {
+      if (*info == 0) *info = j + 1;
+      *rpiv = mk(0.0, 0.0);
+    } else {
+      const dz d = A[(int64_t)j * ld + j];
+      const double den = d.re * d.re + d.im * d.im;
+      *rpiv = mk(d.re / den, -d.im / den);
+    }
+  }
+}
+
+// Scale column j below the diagonal and apply the rank-1 update to the rest
+// of the panel (columns j+1 .. k0+jb-1).
+__global__ __launch_bounds__(256) void k_lu_col(dz *__restrict__ A, int64_t ld, int n, int j, int k0, int jb,
+                                                const dz *__restrict__ rpiv) {
+  const int i = j + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dz *row = A + (int64_t)i * ld;
+  const dz *prow = A + (int64_t)j * ld;
+  const dz l = row[j] * (*rpiv);
+  row[j] = l;
+  for (int c = j + 1; c < k0 + jb; ++c) row[c] = row[c] - l * prow[c];
+}
+
+// Apply the panel's row swaps to the columns outside the panel.
+__global__ __launch_bounds__(256) void k_lu_swap(dz *__restrict__ A, int64_t ld, int n, int k0, int jb,
+                                                 const int32_t *__restrict__ ipiv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (c >= k0 && c < k0 + jb)) return;
+  for (int j = k0; j < k0 + jb; ++j) {
+    const int p = ipiv[j];
+    if (p != j) {
+      const dz t = A[(int64_t)j * ld + c];
+      A[(int64_t)j * ld + c] = A[(int64_t)p * ld + c];
+      A[(int64_t)p * ld + c] = t;
+    }
+  }
+}
+
+// U12 = L11^{-1} A12 (L11 unit lower, jb <= 64): one wave per 64 columns, the
+// column block lives in LDS.
+__global__ __launch_bounds__(64) void k_lu_trsm(dz *__restrict__ A, int64_t ld, int n, int k0, int jb) {
+  __shared__ dz tile[64][65];
+  const int lane = threadIdx.x;
+  const int c = k0 + jb + blockIdx.x * 64 + lane;
+  const bool ok = c < n;
+  for (int i = 0; i < jb; ++i) tile[i][lane] = ok ? A[(int64_t)(k0 + i) * ld + c] : mk(0, 0);
+  for (int i = 1; i < jb; ++i) {
+    const dz *Lr = A + (int64_t)(k0 + i) * ld + k0;
+    dz s = tile[i][lane];
+    for (int l = 0; l < i; ++l) s = s - Lr[l] * tile[l][lane];
+    tile[i][lane] = s;
+  }
+  if (ok)
+    for (int i = 1; i < jb; ++i) A[(int64_t)(k0 + i) * ld + c] = tile[i][lane];
+}
+
+// A22 -= L21 U12 on the matrix cores.  Tile 64 x 64 per block of 4 waves
+// (2 x 2 waves of 32 x 32, each 2 x 2 MFMA tiles of 16 x 16); K = jb <= 64
+// staged through LDS in chunks of 16.
+//   v_mfma_f64_16x16x4f64 operand layout (lane l): A[i = l%16][k = l/16],
+//   B[k = l/16][j = l%16]; result register r holds D[i = 4*r + l/16][j = l%16].
+constexpr int kGemmKC = 16;
+
+__global__ __launch_bounds__(256) void k_lu_gemm(dz *__restrict__ A, int64_t ld, int n, int k0, int jb) {
+  __shared__ double Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
+  __shared__ double Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
+  const int r0 = k0 + jb + blockIdx.y * 64;   // rows of A22
+  const int c0 = k0 + jb + blockIdx.x * 64;   // cols of A22
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v4d cre[2][2], cim[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = v4d{0, 0, 0, 0};
+      cim[a][b] = v4d{0, 0, 0, 0};
+    }
+  for (int kc = 0; kc < jb; kc += kGemmKC) {
+    __syncthreads();
+    // stage L21[r0.., k0+kc..] (64 x KC) and U12[k0+kc.., c0..] (KC x 64)
+    for (int e = tid; e < 64 * kGemmKC; e += 256) {
+      const int i = e / kGemmKC, k = e % kGemmKC;
+      const int gr = r0 + i, gk = kc + k;
+      dz v = mk(0, 0);
+      if (gr < n && gk < jb) v = A[(int64_t)gr * ld + k0 + gk];
+      Ar[i][k] = v.re;
+      Ai[i][k] = v.im;
+    }
+    for (int e = tid; e < kGemmKC * 64; e += 256) {
+      const int k = e / 64, j = e % 64;
+      const int gk = kc + k, gc = c0 + j;
+      dz v = mk(0, 0);
+      if (gk < jb && gc < n) v = A[(int64_t)(k0 + gk) * ld + gc];
+      Br[k][j] = v.re;
+      Bi[k][j] = v.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmKC; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      double are[2], aim[2], bre[2], bim[2];
+      for (int a = 0; a < 2; ++a) {
+        const int i = wr * 32 + a * 16 + (lane & 15);
+        are[a] = Ar[i][ka];
+        aim[a] = Ai[i][ka];
+      }
+      for (int b = 0; b < 2; ++b) {
+        const int j = wc * 32 + b * 16 + (lane & 15);
+        bre[b] = Br[ka][j];
+        bim[b] = Bi[ka][j];
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[a], bre[b], cre[a][b], 0, 0, 0);
+          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[a], bim[b], cre[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[a], bim[b], cim[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[a], bre[b], cim[a][b], 0, 0, 0);
+        }
+    }
+  }
+  // A22 -= C
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int gi = r0 + wr * 32 + a * 16 + 4 * r + (lane >> 4);
+        const int gj = c0 + wc * 32 + b * 16 + (lane & 15);
+        if (gi < n && gj < n) {
+          dz *p = A + (int64_t)gi * ld + gj;
+          const dz v = *p;
+          *p = mk(v.re - cre[a][b][r], v.im - cim[a][b][r]);
+        }
+      }
+}
+
+// ------------------------------------------------------------ apply
+// perm[i] = original row now at position i, from the sequential swaps ipiv.
+__global__ void k_lu_perm(int n, const int32_t *__restrict__ ipiv, int32_t *__restrict__ perm) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int j = 0; j < n; ++j) {
+    const int p = ipiv[j];
+    const int t = perm[j];
+    perm[j] = perm[p];
+    perm[p] = t;
+  }
+}
+
+// z[i] = v[perm[i]] for one block (offset `off` in the global vectors)
+__global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, const dz *__restrict__ v,
+                          dz *__restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[off + i] = v[off + perm[i]];
+}
+
+// One block-column step of a blocked triangular solve.  `rhs` holds the
+// right-hand side being updated; rows [b0, b0+nb) are final when the step
+// starts.  Every thread block solves the diagonal block (wave 0, values kept
+// in registers, one dot product per row reduced across the wave), block 0
+// stores the solved rows into `sol`, and all blocks update their share of the
+// remaining rows of `rhs`: below the block for L (unit diagonal), above it
+// for U.  The diagonal rows of `rhs` are only read in this step, so the
+// stores to `sol` do not race with other blocks' loads.
+
+__device__ __forceinline__ dz wave_sum(dz v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_xor(v.re, o);
+    v.im += __shfl_xor(v.im, o);
+  }
+  return v;
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int nb,
+                                                   dz *__restrict__ rhs, dz *__restrict__ sol) {
+  __shared__ dz zb[kTrsvNB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (wave == 0) {
+    // lane holds entries lane and lane + 64 of the block
+    dz x0 = lane < nb ? rhs[b0 + lane] : mk(0, 0);
+    dz x1 = lane + 64 < nb ? rhs[b0 + lane + 64] : mk(0, 0);
+    if (LOWER) {
+      for (int i = 1; i < nb; ++i) {
+        const dz *Li = F + (int64_t)(b0 + i) * ld + b0;
+        dz s = mk(0, 0);
+        if (lane < i) s = Li[lane] * x0;
+        if (lane + 64 < i) s = s + Li[lane + 64] * x1;
+        s = wave_sum(s);
+        if (lane == (i & 63)) {
+          if (i < 64) x0 = x0 - s;
+          else x1 = x1 - s;
+        }
+      }
+    } else {
+      for (int i = nb - 1; i >= 0; --i) {
+        const dz *Ui = F + (int64_t)(b0 + i) * ld + b0;
+        dz s = mk(0, 0);
+        if (lane > i && lane < nb) s = Ui[lane] * x0;
+        if (lane + 64 > i && lane + 64 < nb) s = s + Ui[lane + 64] * x1;
+        s = wave_sum(s);
+        if (lane == (i & 63)) {
+          const dz d = Ui[i];
+          const double den = d.re * d.re + d.im * d.im;
+          const dz t = (i < 64 ? x0 : x1) - s;
+          const dz q = mk((t.re * d.re + t.im * d.im) / den, (t.im * d.re - t.re * d.im) / den);
+          if (i < 64) x0 = q;
+          else x1 = q;
+        }
+      }
+    }
+    if (lane < nb) zb[lane] = x0;
+    if (lane + 64 < nb) zb[lane + 64] = x1;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = tid; i < nb; i += 256) sol[b0 + i] = zb[i];
+  const int rbase = LOWER ? b0 + nb : 0;
+  const int rend = LOWER ? n : b0;
+  for (int rr = 0; rr < 16; ++rr) {
+    const int i = rbase + blockIdx.x * kTrsvRows + wave * 16 + rr;
+    if (i >= rend) break;
+    const dz *Fi = F + (int64_t)i * ld + b0;
+    dz s = mk(0, 0);
+    for (int l = lane; l < nb; l += 64) s = s + Fi[l] * zb[l];
+    s = wave_sum(s);
+    if (lane == 0) rhs[i] = rhs[i] - s;
+  }
+}
+
+template __global__ void k_trsv_step<true>(const dz *, int64_t, int, int, int, dz *, dz *);
+template __global__ void k_trsv_step<false>(const dz *, int64_t, int, int, int, dz *, dz *);
+
+}  // namespace vie

@@ -1,0 +1,73 @@
+// Declarations of the libvie kernels launched from the host orchestration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+
+namespace vie {
+
+// fill (k_fill.hip)
+__global__ void k_prep(int64_t nt, const TetFace *t2f, const TetGeom *tg, const double *area, const dz *eps_int,
+                       double kx, double ky, double a, double b, dz *alpha, dz *gsrc, dz *kappa, dz *inv_eps);
+__global__ void k_sigma(int nc, const int32_t *ctp, const int32_t *ctm, const dz *kappa, dz *sigma);
+__global__ void k_zero(dz *p, int64_t n);
+__global__ void k_tt_far(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+                         const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc, const dz *alpha,
+                         const dz *gsrc, const dz *kappa, double k0sq9, dz *Z, int64_t ld);
+__global__ void k_tt_near(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+                          const int32_t *lt, const int32_t *ls, const int32_t *lmask, int npairs, const dz *alpha,
+                          const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, dz *Z, int64_t ld);
+__global__ void k_tet_face(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+                           const int32_t *test_list, int ntest, const FaceGeom *fg, int nface, const dz *alpha,
+                           const dz *sigma, dz *Z, int64_t ld);
+__global__ void k_face_tet(const PgfTable *tab, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
+                           int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
+                           const dz *gsrc, const dz *kappa, dz *Z, int64_t ld);
+__global__ void k_face_face(const PgfTable *tab, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
+                            int nhalf, int nface, const dz *sigma, dz *Z, int64_t ld);
+__global__ void k_rhs(int64_t N, const int32_t *utet, const int32_t *uk, const TetGeom *tg, const QuadRules *qr,
+                      const dz *alpha, double kix, double kiy, double kiz, double ex, double ey, double ez, dz *b);
+__global__ void k_pgf_probe(const PgfTable *tab, const double *d, int64_t n, dz *out);
+__global__ void k_gather(const dz *Z, int64_t ld, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
+
+// block LU and its application (k_lu.hip)
+constexpr int kTrsvNB = 128;
+constexpr int kTrsvRows = 64;
+__global__ void k_copy_block(const dz *Z, int64_t ldz, int64_t start, int n, dz *A, int64_t lda);
+__global__ void k_lu_pivot(dz *A, int64_t ld, int n, int j, int k0, int jb, int32_t *ipiv, dz *rpiv, int32_t *info);
+__global__ void k_lu_col(dz *A, int64_t ld, int n, int j, int k0, int jb, const dz *rpiv);
+__global__ void k_lu_swap(dz *A, int64_t ld, int n, int k0, int jb, const int32_t *ipiv);
+__global__ void k_lu_trsm(dz *A, int64_t ld, int n, int k0, int jb);
+__global__ void k_lu_gemm(dz *A, int64_t ld, int n, int k0, int jb);
+__global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
+__global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
+template <bool LOWER>
+__global__ void k_trsv_step(const dz *F, int64_t ld, int n, int b0, int nb, dz *rhs, dz *sol);
+extern template __global__ void k_trsv_step<true>(const dz *, int64_t, int, int, int, dz *, dz *);
+extern template __global__ void k_trsv_step<false>(const dz *, int64_t, int, int, int, dz *, dz *);
+
+// Krylov (k_krylov.hip)
+constexpr int kMvRPW = 4;
+__global__ void k_matvec(const dz *Z, int64_t ld, int64_t N, const dz *x, const dz *b, dz *y);
+__global__ void k_dots(const dz *V, int64_t ldv, int nv, const dz *w, int64_t N, dz *part);
+__global__ void k_dots_reduce(const dz *part, int nblk, int nv, dz *h, int accumulate);
+__global__ void k_update(const dz *V, int64_t ldv, int nv, const dz *c, dz *w, int64_t N);
+__global__ void k_combine(const dz *V, int64_t ldv, int nv, const dz *c, dz *y, int64_t N);
+__global__ void k_norm2(const dz *w, int64_t N, double *part);
+__global__ void k_norm_reduce(const double *part, int nblk, double *out);
+__global__ void k_scale(const dz *w, const double *nrm, dz *v, int64_t N);
+__global__ void k_axpy(dz *x, const dz *u, int64_t N);
+__global__ void k_copy(dz *d, const dz *s, int64_t N);
+__global__ void k_sub_into(const dz *a, dz *y, int64_t n);
+__global__ void k_givens(dz *H, int ldh, int j, const double *hn, double *cs, dz *sn, dz *g, double *res);
+__global__ void k_backsolve(const dz *H, int ldh, int k, const dz *g, dz *y);
+__global__ void k_ginit(dz *g, int m1, const double *beta);
+
+// outputs (k_absorb.hip)
+__global__ void k_absorb(int64_t nt, int ndom, const TetGeom *tg, const TetFace *t2f, const int32_t *dom,
+                         const QuadRules *qr, const dz *gsrc, const dz *inv_eps, const dz *x, double *part);
+__global__ void k_project(int64_t nt, const TetGeom *tg, const TetFace *t2f, const QuadRules *qr, const dz *gsrc,
+                          const dz *kappa, const dz *x, int nk, const double *kv, double *part);
+__global__ void k_reduce_cols(const double *part, int nblk, int width, double *out);
+
+}  // namespace vie

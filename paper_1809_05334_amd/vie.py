@@ -1,0 +1,221 @@
+"""Python binding of libvie (include/vie.h): argument marshalling only.
+
+Device memory for the library's workspace comes from PyTorch (one uint8
+tensor on the GPU) and work runs on PyTorch's current HIP stream; every step
+of the method runs in the library's HIP kernels.  The binding refuses to run
+without the built library (no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvie.so")
+
+VIE_OK, VIE_EINVAL, VIE_ESTATE, VIE_ENOMEM, VIE_ENOCONV, VIE_EWOOD, VIE_ESINGULAR, VIE_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+VIE_TE, VIE_TM = 0, 1
+VIE_FP64, VIE_MIXED_FP32 = 0, 1
+
+_STATUS = {0: "VIE_OK", -1: "VIE_EINVAL", -2: "VIE_ESTATE", -3: "VIE_ENOMEM", -4: "VIE_ENOCONV",
+           -5: "VIE_EWOOD", -6: "VIE_ESINGULAR", -7: "VIE_EDEVICE"}
+
+
+class VieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class c128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("refine_steps", C.c_int),
+                ("true_rel_residual", C.c_double), ("t_fill_ms", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+_SIGS = {
+    "vie_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "vie_destroy": (C.c_int, [C.c_void_p]),
+    "vie_mesh_upload": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_int32, C.c_double, C.c_double]),
+    "vie_num_unknowns": (C.c_int64, [C.c_void_p]),
+    "vie_domain_ranges": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vie_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_int]),
+    "vie_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int]),
+    "vie_fill": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_int]),
+    "vie_precond_factor": (C.c_int, [C.c_void_p]),
+    "vie_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(SolveInfo)]),
+    "vie_absorption": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_last_error": (C.c_char_p, [C.c_void_p]),
+    "vie_export_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_read_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "vie_read_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vie_read_solution": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vie_pgf_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "vie_residual_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+}
+
+
+def load():
+    """Load libvie.so (built in-tree by __graft_entry__.build / build.py)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libvie.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Solver:
+    """One context = one unit cell on one device stream (not thread-safe)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = self.lib.vie_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != VIE_OK:
+            raise VieError(rc, "vie_create failed (no HIP device?)")
+        self.h = h
+        self.ws = None
+        self.ndom = 0
+        self.nt = 0
+
+    def _ck(self, rc, allow=()):
+        if rc != VIE_OK and rc not in allow:
+            raise VieError(rc, self.lib.vie_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vie_destroy(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- setup
+    def upload(self, verts, tets, tet_domain, ndom, a, b):
+        v = np.ascontiguousarray(verts, np.float64)
+        t = np.ascontiguousarray(tets, np.int32)
+        d = np.ascontiguousarray(tet_domain, np.int32)
+        self._ck(self.lib.vie_mesh_upload(self.h, _p(v), len(v), _p(t), len(t), _p(d), int(ndom), float(a), float(b)))
+        self.ndom = int(ndom)
+        self.nt = len(t)
+        return self.num_unknowns()
+
+    def upload_mesh(self, mesh):
+        return self.upload(mesh.verts, mesh.tets, mesh.tet_domain, mesh.ndom, mesh.a, mesh.b)
+
+    def num_unknowns(self):
+        return int(self.lib.vie_num_unknowns(self.h))
+
+    def domain_ranges(self):
+        out = np.zeros(2 * self.ndom, np.int64)
+        self._ck(self.lib.vie_domain_ranges(self.h, _p(out)))
+        return out.reshape(-1, 2)
+
+    def workspace_bytes(self, precision=VIE_FP64, restart=100):
+        return int(self.lib.vie_workspace_bytes(self.h, precision, restart))
+
+    def bind(self, precision=VIE_FP64, restart=100, workspace=None):
+        nbytes = self.workspace_bytes(precision, restart)
+        if nbytes == 0:
+            raise VieError(VIE_EINVAL, "workspace size unavailable (precision/restart)")
+        if workspace is None:
+            workspace = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        ptr = workspace.data_ptr()
+        off = (-ptr) % 256
+        self._ck(self.lib.vie_bind_workspace(self.h, C.c_void_p(ptr + off), workspace.numel() - off, precision, restart))
+        self.ws = workspace
+        self.precision = precision
+        self.restart = restart
+        return nbytes
+
+    # -------------------------------------------------------------- method
+    def fill(self, lam, theta, phi, eps, precision=None):
+        e = np.ascontiguousarray(np.asarray(eps, np.complex128))
+        if len(e) != self.nt:
+            raise ValueError("eps must have one value per tetrahedron")
+        p = self.precision if precision is None else precision
+        self._ck(self.lib.vie_fill(self.h, float(lam), float(theta), float(phi), _p(e), p))
+
+    def factor(self):
+        self._ck(self.lib.vie_precond_factor(self.h))
+
+    def solve(self, pol, tol=1e-12, max_iter=2000, restart=None, allow_noconv=False):
+        info = SolveInfo()
+        rc = self.lib.vie_solve(self.h, int(pol), float(tol), int(max_iter), int(restart or self.restart),
+                                C.byref(info))
+        self._ck(rc, allow=(VIE_ENOCONV,) if allow_noconv else ())
+        d = info.as_dict()
+        d["converged"] = rc == VIE_OK
+        return d
+
+    def absorption(self, want_rt=True):
+        A = np.zeros(self.ndom)
+        R = C.c_double(); T = C.c_double()
+        self._ck(self.lib.vie_absorption(self.h, _p(A), C.byref(R) if want_rt else None,
+                                         C.byref(T) if want_rt else None))
+        return (A, R.value, T.value) if want_rt else A
+
+    # -------------------------------------------------------------- diagnostics
+    def read_Z(self, rows, cols):
+        r = np.ascontiguousarray(rows, np.int64); c = np.ascontiguousarray(cols, np.int64)
+        out = np.zeros(len(r), np.complex128)
+        self._ck(self.lib.vie_read_Z(self.h, _p(r), _p(c), len(r), _p(out)))
+        return out
+
+    def read_rhs(self):
+        out = np.zeros(self.num_unknowns(), np.complex128)
+        self._ck(self.lib.vie_read_rhs(self.h, _p(out)))
+        return out
+
+    def read_solution(self):
+        out = np.zeros(self.num_unknowns(), np.complex128)
+        self._ck(self.lib.vie_read_solution(self.h, _p(out)))
+        return out
+
+    def pgf(self, delta):
+        d = np.ascontiguousarray(delta, np.float64).reshape(-1, 3)
+        out = np.zeros(len(d), np.complex128)
+        self._ck(self.lib.vie_pgf_eval(self.h, _p(d), len(d), _p(out)))
+        return out
+
+    def export_faces(self):
+        N = self.num_unknowns()
+        fv = np.zeros(3 * N, np.int32); tp = np.zeros(N, np.int32); tm = np.zeros(N, np.int32); dm = np.zeros(N, np.int32)
+        self._ck(self.lib.vie_export_faces(self.h, _p(fv), _p(tp), _p(tm), _p(dm)))
+        return fv.reshape(-1, 3), tp, tm, dm
+
+    def residual_history(self, cap=100000):
+        h = np.zeros(cap)
+        n = self.lib.vie_residual_history(self.h, _p(h), cap)
+        return h[:max(0, n)]

@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle on the same
+seeded inputs: topology, the periodic Green's function, every entry of Z,
+the right-hand side, the solution, absorptance and R/T, GMRES iteration
+counts, and the error paths of the boundary.
+
+Tolerances: Z entries |dZ| <= 1e-10 max(|Z_ij|, 1e-6 max|Z|); absorptance,
+R and T <= 1e-8 absolute; g_p <= 1e-12 relative."""
+import numpy as np
+import pytest
+
+from oracle import pgf as OP
+from oracle import topology as OT
+from oracle import vie as OV
+from paper_1809_05334_amd import workloads as W
+
+from gpu_cases import eps_for, osc_rect, osc_small, slab_cfg1, slab_small
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vie():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1809_05334_amd import vie as V
+    return V
+
+
+def oracle_topo(m):
+    return OT.build(m.verts, m.tets, m.tet_domain, m.ndom, m.a, m.b)
+
+
+def make_solver(vie, m, restart=60):
+    s = vie.Solver()
+    s.upload_mesh(m)
+    s.bind(vie.VIE_FP64, restart)
+    return s
+
+
+CASES = {"slab_small": slab_small, "slab_cfg1": slab_cfg1, "osc_small": osc_small, "osc_rect": osc_rect}
+ILLUM = {"slab_small": (600.0, 0.0, 0.0), "slab_cfg1": (600.0, 0.5, 0.3),
+         "osc_small": (520.0, 0.35, 0.6), "osc_rect": (450.0, 0.6, 1.1)}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_topology_matches_oracle(vie, name):
+    m = CASES[name]()
+    t = oracle_topo(m)
+    s = vie.Solver()
+    N = s.upload_mesh(m)
+    assert N == t.N
+    fv, tp, tm, dm = s.export_faces()
+    assert np.array_equal(fv, t.face_vid)
+    assert np.array_equal(tp, t.tplus) and np.array_equal(tm, t.tminus) and np.array_equal(dm, t.fdom)
+    se = s.domain_ranges()
+    assert [tuple(r) for r in se] == [tuple(r) for r in t.domain_ranges]
+
+
+@pytest.mark.parametrize("lam,th,ph,a,b,zs", [
+    (600.0, 0.0, 0.0, 100.0, 100.0, 50.0),
+    (450.0, 0.7, 0.4, 60.0, 45.0, 30.0),
+    (400.0, 0.9, 0.2, 300.0, 300.0, 160.0),   # propagating diffraction orders
+    (700.0, 0.2, 1.3, 200.0, 120.0, 120.0),
+])
+def test_pgf_matches_oracle(vie, lam, th, ph, a, b, zs):
+    # a mesh only fixes the cell; g_p depends on (a, b, z-extent, lambda, angles)
+    xs = np.linspace(0, a, 3); ys = np.linspace(0, b, 3); zz = np.linspace(0, zs, 2)
+    verts, tets = W.brick_grid_mesh(xs, ys, zz)
+    m = W.Mesh(verts, tets, np.zeros(len(tets), np.int32), 1, a, b)
+    s = make_solver(vie, m, restart=8)
+    s.fill(lam, th, ph, np.full(m.nt, 2.0 + 0.1j))
+    rng = np.random.default_rng(7)
+    d = np.stack([rng.uniform(-a, a, 300), rng.uniform(-b, b, 300), rng.uniform(-zs, zs, 300)], 1)
+    d = d[np.linalg.norm(d, axis=1) > 0.05 * min(a, b)]
+    g_gpu = s.pgf(d)
+    k0 = 2 * np.pi / lam
+    g_or = OP.pgf_ewald(d, k0, k0 * np.sin(th) * np.cos(ph), k0 * np.sin(th) * np.sin(ph), a, b)
+    err = np.abs(g_gpu - g_or) / np.abs(g_or)
+    assert err.max() < 1e-12, err.max()
+
+
+def z_tolerance_ok(Zg, Zo):
+    scale = np.abs(Zo).max()
+    tol = 1e-10 * np.maximum(np.abs(Zo), 1e-6 * scale)
+    bad = np.abs(Zg - Zo) > tol
+    return (not bad.any()), np.max(np.abs(Zg - Zo) / np.maximum(np.abs(Zo), 1e-6 * scale))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_Z_rhs_solution_outputs(vie, name):
+    m = CASES[name]()
+    lam, th, ph = ILLUM[name]
+    t = oracle_topo(m)
+    eps = eps_for(m, lam)
+    s = make_solver(vie, m)
+    s.fill(lam, th, ph, eps)
+    N = t.N
+    r, c = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    Zg = s.read_Z(r.ravel(), c.ravel()).reshape(N, N)
+    wave = OV.make_wave(lam, th, ph)
+    Zo = OV.assemble(t, wave, eps)
+    ok, worst = z_tolerance_ok(Zg, Zo)
+    assert ok, f"worst relative Z error {worst:.3e}"
+    s.factor()
+    for pol in (0, 1):
+        info = s.solve(pol, tol=1e-12, max_iter=500, restart=60)
+        assert info["converged"] and info["true_rel_residual"] < 1e-11
+        bo = OV.rhs(t, wave, pol)
+        bg = s.read_rhs()
+        assert np.max(np.abs(bg - bo)) < 1e-12 * np.abs(bo).max()
+        xo = OV.solve_lu(Zo, bo)
+        xg = s.read_solution()
+        assert np.linalg.norm(xg - xo) < 1e-9 * np.linalg.norm(xo)
+        A, R, T = s.absorption()
+        Ao = OV.absorptance(t, wave, eps, xo)
+        Ro, To = OV.reflect_transmit(t, wave, eps, xo, pol)
+        assert np.max(np.abs(A - Ao)) < 1e-8 and abs(R - Ro) < 1e-8 and abs(T - To) < 1e-8, (A, Ao, R, Ro, T, To)
+
+
+def test_gmres_iterations_match_oracle(vie):
+    m = osc_small()
+    t = oracle_topo(m)
+    lam = 480.0
+    eps = eps_for(m, lam)
+    s = make_solver(vie, m, restart=30)
+    s.fill(lam, 0.2, 0.1, eps)
+    s.factor()
+    info = s.solve(1, tol=1e-10, max_iter=500, restart=30)
+    wave = OV.make_wave(lam, 0.2, 0.1)
+    Zo = OV.assemble(t, wave, eps)
+    xo, it, hist, ok = OV.gmres_right_block(Zo, OV.rhs(t, wave, 1), t.domain_ranges, tol=1e-10, restart=30)
+    assert ok and info["converged"]
+    assert abs(info["iters"] - it) <= 1, (info["iters"], it)
+    hg = s.residual_history()
+    assert len(hg) == info["iters"]
+    k = min(len(hg), len(hist))
+    assert np.allclose(hg[:k], hist[:k], rtol=1e-4, atol=1e-13)
+
+
+def test_single_domain_converges_in_one_iteration(vie):
+    m = slab_small()
+    s = make_solver(vie, m)
+    s.fill(600.0, 0.3, 0.0, W.slab_eps(m))
+    s.factor()
+    info = s.solve(0, tol=1e-12, max_iter=50)
+    assert info["iters"] == 1 and info["converged"]
+
+
+def test_error_paths(vie):
+    m = slab_small()
+    s = vie.Solver()
+    with pytest.raises(vie.VieError) as e:
+        s.factor()
+    assert e.value.code == vie.VIE_ESTATE
+    s.upload_mesh(m)
+    with pytest.raises(vie.VieError) as e:
+        s.factor()
+    assert e.value.code == vie.VIE_ESTATE
+    import torch
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(vie.VieError) as e:
+        s.bind(vie.VIE_FP64, 20, workspace=small)
+    assert e.value.code == vie.VIE_ENOMEM
+    s.bind(vie.VIE_FP64, 20)
+    # Rayleigh-Wood anomaly: an order grazing the cell plane (lambda = a (1 + sin th))
+    th = 0.4
+    with pytest.raises(vie.VieError) as e:
+        s.fill(50.0 * (1 + np.sin(th)), th, 0.0, W.slab_eps(m))
+    assert e.value.code == vie.VIE_EWOOD
+    s.fill(600.0, 0.0, 0.0, W.slab_eps(m))
+    s.factor()
+    # two-domain split of the slab so that GMRES needs more than one iteration
+    m2 = W.slab_mesh(a=50.0, b=50.0, thickness=50.0, nx=2, ny=2, nz=2)
+    c = W.centroids(m2.verts, m2.tets)
+    m2.tet_domain = (c[:, 2] > 25).astype(np.int32); m2.ndom = 2
+    s2 = make_solver(vie, m2)
+    s2.fill(600.0, 0.0, 0.0, W.slab_eps(m2))
+    s2.factor()
+    with pytest.raises(vie.VieError) as e:
+        s2.solve(0, tol=1e-14, max_iter=1)
+    assert e.value.code == vie.VIE_ENOCONV
+    info = s2.solve(0, tol=1e-14, max_iter=1, allow_noconv=True)
+    assert info["iters"] == 1 and not info["converged"] and info["true_rel_residual"] > 0
+    bad = m.verts.copy(); bad[np.argmax(bad[:, 0] + 1e-3 * bad[:, 1])] += [0, 0, 1.0]
+    s3 = vie.Solver()
+    with pytest.raises(vie.VieError) as e:
+        s3.upload(bad, m.tets, m.tet_domain, 1, m.a, m.b)
+    assert e.value.code == vie.VIE_EINVAL
