@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the periodic VIE-MoM hot path on one MI355X.
+
+Workload (plasmonic organic-solar-cell unit cell, the 400-800 nm sweep at
+normal incidence): period 200 x 200 nm, active layer 80 nm (eps 3.6+0.6i),
+spacer 40 nm (eps 2.3+0.05i), Drude-silver sphere r = 20 nm in the spacer;
+graded Kuhn brick mesh (5 nm over the sphere span and the spacer, 20 nm
+elsewhere): 18,432 tetrahedra, N = 37,376 unknowns, three material domains.
+
+One step = one wavelength of the 41-point sweep (visited with stride 7,
+starting at 450 nm): fill Z (FP64), factor the
+three diagonal blocks, right-preconditioned GMRES for TE and TM, absorptance
+per domain and R/T for each -> 2 solves.  Inputs are resident on the device
+when the timed region starts (the mesh tables are uploaded at bind time; the
+41 permittivity vectors are host arrays of 18,432 complex values, part of
+each fill call).
+
+Prints ONE JSON line.  `value` = solves/s of the whole job.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(mesh, lam, n_rows=8, n_lu=3000, seed=0):
+    """The CPU oracle on a bounded sample of the same workload, extrapolated:
+    fill = (time of n_rows full rows of Z) * N / n_rows; dense LU of Z = time
+    of an n_lu x n_lu complex LU * (N / n_lu)^3; two LU solves scaled by
+    (N / n_lu)^2.  solves/s = 2 / (fill + LU + 2 solves)."""
+    import scipy.linalg as sla
+
+    from oracle import topology as OT
+    from oracle import vie as OV
+    from paper_1809_05334_amd import workloads as W
+
+    t = OT.build(mesh.verts, mesh.tets, mesh.tet_domain, mesh.ndom, mesh.a, mesh.b)
+    N = t.N
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(N, n_rows, replace=False))
+    wave = OV.make_wave(lam, 0.0, 0.0)
+    eps = W.osc_eps(mesh, lam)
+    t0 = time.perf_counter()
+    OV.assemble(t, wave, eps, rows=rows)
+    t_rows = time.perf_counter() - t0
+    A = rng.standard_normal((n_lu, n_lu)) + 1j * rng.standard_normal((n_lu, n_lu))
+    t0 = time.perf_counter()
+    f = sla.lu_factor(A)
+    t_lu = time.perf_counter() - t0
+    bvec = rng.standard_normal(n_lu) + 0j
+    t0 = time.perf_counter()
+    sla.lu_solve(f, bvec)
+    t_sv = time.perf_counter() - t0
+    fill = t_rows * N / n_rows
+    lu = t_lu * (N / n_lu) ** 3
+    sv = t_sv * (N / n_lu) ** 2
+    total = fill + lu + 2 * sv
+    cores = len(os.sched_getaffinity(0))
+    return {"value": 2.0 / total, "unit": "solves/s", "cores": min(16, cores), "kind": "oracle",
+            "sample": (f"{n_rows} rows of Z (x {N} columns) timed and scaled by N/{n_rows}; "
+                       f"dense {n_lu}x{n_lu} complex LU and solve timed and scaled by (N/{n_lu})^3, ^2; "
+                       f"extrapolated: fill {fill:.0f} s, LU {lu:.0f} s, solve {sv:.1f} s per solve"),
+            "seconds_sampled": t_rows + t_lu + t_sv}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--max-iter", type=int, default=1500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the method's units of parallel work "
+              "(sweep points, cells) shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1809_05334_amd import vie
+    from paper_1809_05334_amd import workloads as W
+
+    mesh = W.config2_mesh()
+    lams = np.linspace(400.0, 800.0, 41)
+    eps_all = [W.osc_eps(mesh, l) for l in lams]
+    s = vie.Solver(0)
+    N = s.upload_mesh(mesh)
+    ws_bytes = s.bind(vie.VIE_FP64, args.restart)
+    stream = s.stream
+
+    lat = []
+    stages = []
+    absorb = None
+
+    def step(i):
+        # sweep order: stride 7 through the 41 wavelengths (starts at 450 nm)
+        nonlocal absorb
+        k = (5 + 7 * i) % len(lams)
+        t0 = time.perf_counter()
+        s.fill(lams[k], 0.0, 0.0, eps_all[k])
+        s.factor()
+        out = {}
+        for pol in (vie.VIE_TE, vie.VIE_TM):
+            info = s.solve(pol, tol=args.tol, max_iter=args.max_iter, restart=args.restart, allow_noconv=True)
+            A, R, T = s.absorption()
+            out[pol] = (info, A, R, T)
+            lat.append((time.perf_counter() - t0) * 1e3)
+        absorb = {"lambda_nm": float(lams[k]), "A_TE": out[0][1].tolist(), "R_TE": out[0][2], "T_TE": out[0][3]}
+        stages.append({"fill_ms": out[0][0]["t_fill_ms"], "factor_ms": out[0][0]["t_factor_ms"],
+                       "solve_ms": [out[p][0]["t_solve_ms"] for p in (0, 1)],
+                       "iters": [out[p][0]["iters"] for p in (0, 1)],
+                       "converged": [out[p][0]["converged"] for p in (0, 1)]})
+        print(f"step {i}: lambda {lams[k]:.0f} nm  {json.dumps(stages[-1])}", file=sys.stderr, flush=True)
+
+    print(f"bench: N={N}, workspace {ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    lat.clear(); stages.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nsolves = 2 * args.steps
+
+    fs = s.fill_stats()
+    far_tflops = fs["far_flops"] / (fs["t_far_ms"] * 1e-3) / 1e12
+    mv_ms = s.bench_matvec(10)
+    mv_bytes = 16.0 * N * N + 32.0 * N
+    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    # the bench's dominant kernel family: the far tet-pair fill kernel
+    roofline = {"bound": "alu", "kernel": "k_tt_far", "achieved": far_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": far_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "launches": fs["far_launches"], "flops_per_launch": fs["far_flops"] / fs["far_launches"],
+                "avg_launch_ms": fs["t_far_ms"] / fs["far_launches"]}
+    res = {
+        "metric": "solves/s (FP64 path); p50/p99 latency; fill GFLOP/s; matvec GB/s",
+        "value": nsolves / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plasmonic OSC cell 200x200 nm, Ag sphere r=20 nm, N=%d, 400-800 nm sweep, "
+                               "normal incidence, TE+TM per step" % N,
+                   "unknowns": N, "tets": int(mesh.nt), "restart": args.restart, "tol": args.tol,
+                   "workspace_gb": ws_bytes / 1e9},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "fill_gflops": fs["far_flops"] / (fs["t_far_ms"] * 1e-3) / 1e9,
+        "matvec_gbs": mv_gbs,
+        "matvec_frac_hbm": mv_gbs / HBM_PEAK_GBS,
+        "stages": stages,
+        "fill_stats": fs,
+        "result": absorb,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(mesh, float(lams[0]))
+    s.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -169,6 +169,24 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *ou
  * written (at most cap). */
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);
 
+/* Timing and work counts of the last vie_fill.  Device times come from HIP
+ * events on the context's stream around each kernel family.  far_flops is
+ * the algorithmic work of the far tetrahedron-pair kernel under the cost model
+ * stated in the library source (FMA = 2 FLOPs, per-term operation counts of
+ * the lattice-sum evaluation with the fitted degrees of this fill). */
+typedef struct {
+  double t_fill_ms, t_far_ms, t_near_ms, t_face_ms;
+  int64_t far_pairs, near_pairs, face_pairs, far_launches;
+  double point_pair_flops, far_flops;
+  int nimg, nmode;
+} vie_fill_stats;
+int vie_get_fill_stats(const vie_ctx *ctx, vie_fill_stats *out);
+
+/* Time `reps` back-to-back products y = Z x on the context's stream (HIP
+ * events); *ms_per_matvec = average.  Needs a completed fill; uses the
+ * solver's work vectors. */
+int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec);
+
 #ifdef __cplusplus
 }
 #endif

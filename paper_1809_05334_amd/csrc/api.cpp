@@ -34,11 +34,12 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, F, ipiv, perm, rpiv, info;
+  Region Z, F, ipiv, perm, rpiv, info, dinv;
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
+  std::vector<int64_t> doff;       // per-domain offset of the diagonal-block inverses (elements)
   int restart = 0;
   int64_t ldv = 0;
 };
@@ -66,7 +67,8 @@ struct vie_ctx {
   int last_pol = 0;
   std::vector<double> hist;
   double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  vie_fill_stats fstats{};
   double t_fill = 0, t_factor = 0;
 
   template <class T>
@@ -145,6 +147,14 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     npiv += n;
   }
   put(L.F, 16 * (size_t)std::max<int64_t>(1, fel));
+  L.doff.resize(t.ndom);
+  int64_t del = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    int64_t n = t.dend[d] - t.dstart[d];
+    L.doff[d] = del;
+    del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
+  }
+  put(L.dinv, 16 * (size_t)std::max<int64_t>(1, del));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
   put(L.rpiv, 16);
@@ -193,6 +203,8 @@ int vie_create(vie_ctx **out, int device, void *hip_stream) {
   HIPCK(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
+  HIPCK(hipEventCreate(&ctx->ev2));
+  HIPCK(hipEventCreate(&ctx->ev3));
   *out = ctx;
   return VIE_OK;
 }
@@ -205,6 +217,8 @@ int vie_destroy(vie_ctx *ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+  if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
   delete ctx->tab;
   delete ctx;
   return VIE_OK;
@@ -398,6 +412,9 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   LAUNCHCK();
   const int C = t.ncolors;
   const int32_t *colors = ctx->ptr<int32_t>(L.colors);
+  // far tet pairs (all colour pairs), then touching pairs, then face pairs;
+  // events between the groups time each kernel family
+  HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
   for (int ct = 0; ct < C; ++ct)
     for (int cs = 0; cs < C; ++cs) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
@@ -405,16 +422,20 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
                          colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
                          (const dz *)gsrc, (const dz *)kappa, k0sq9, Z, L.ld);
       LAUNCHCK();
-      const int g = ct * C + cs;
-      const int np = ctx->near_off[g + 1] - ctx->near_off[g];
-      if (np) {
-        hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), 0, ctx->stream, tab, qr, tg, t2f,
-                           ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
-                           ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
-                           (const dz *)kappa, (const dz *)inveps, k0sq9, Z, L.ld);
-        LAUNCHCK();
-      }
     }
+  HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
+  for (int g = 0; g < C * C; ++g) {
+    const int np = ctx->near_off[g + 1] - ctx->near_off[g];
+    if (!np) continue;
+    hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), 0, ctx->stream, tab, qr, tg, t2f,
+                       ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
+                       ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
+                       (const dz *)kappa, (const dz *)inveps, k0sq9, Z, L.ld);
+    LAUNCHCK();
+  }
+  hipEvent_t evn = nullptr;
+  HIPCK(hipEventCreate(&evn));
+  HIPCK(hipEventRecord(evn, ctx->stream));
   if (ctx->nface) {
     const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
     for (int ct = 0; ct < C; ++ct) {
@@ -439,9 +460,43 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipEventSynchronize(ctx->ev1));
-  float ms = 0;
+  float ms = 0, mfar = 0, mnear = 0, mface = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  HIPCK(hipEventElapsedTime(&mfar, ctx->ev2, ctx->ev3));
+  HIPCK(hipEventElapsedTime(&mnear, ctx->ev3, evn));
+  HIPCK(hipEventElapsedTime(&mface, evn, ctx->ev1));
+  (void)hipEventDestroy(evn);
   ctx->t_fill = ms;
+  // algorithmic work of the far tet-pair kernel (cost model, FMA = 2 FLOPs):
+  // per point pair: separation and wrap 12; per image 29 + 3 deg (X, Y, R^2,
+  // rsqrt counted as 8, x, t, Clenshaw, scale, accumulate); spectral set-up
+  // 212 (four sincos counted as 40 each, phase powers); per mode 13 + 3 deg
+  // (twice the Clenshaw for a complex order); final phase 6.  Per tet pair:
+  // 16 point pairs + 1200 for moments and the 16-entry scatter.
+  double pp = 12 + 212 + 6;
+  const PgfTable &tb = *ctx->tab;
+  for (int i = 0; i < tb.nimg; ++i) pp += 29 + 3 * tb.img[i].deg;
+  int nmodes = 0;
+  for (int i = 0; i < kPgfTerms; ++i)
+    if (tb.mode[i].deg >= 0) {
+      ++nmodes;
+      pp += 13 + 3 * tb.mode[i].deg * (tb.mode[i].cplx ? 2 : 1) + (tb.mode[i].cplx ? 4 : 0);
+    }
+  int64_t nnear = 0;
+  for (auto &v : t.near_t) nnear += (int64_t)v.size();
+  vie_fill_stats &st = ctx->fstats;
+  st.t_fill_ms = ms;
+  st.t_far_ms = mfar;
+  st.t_near_ms = mnear;
+  st.t_face_ms = mface;
+  st.far_pairs = t.nt * t.nt - nnear;
+  st.near_pairs = nnear;
+  st.face_pairs = (int64_t)t.nt * ctx->nface + (int64_t)ctx->nhalf * t.nt + (int64_t)ctx->nhalf * ctx->nface;
+  st.far_launches = C * C;
+  st.point_pair_flops = pp;
+  st.far_flops = (double)st.far_pairs * (16.0 * pp + 1200.0);
+  st.nimg = tb.nimg;
+  st.nmode = nmodes;
   ctx->state = S_FILLED;
   return VIE_OK;
 }
@@ -488,6 +543,11 @@ int vie_precond_factor(vie_ctx *ctx) {
       LAUNCHCK();
     }
     hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)ip, perm + poff);
+    const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
+    dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
+    dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
+    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)A, ldf, n, kTrsvNB, 1, DL);
+    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)A, ldf, n, kTrsvNB, 0, DU);
     LAUNCHCK();
     poff += n;
   }
@@ -522,16 +582,20 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
     const dz *A = F + L.foff[d];
     const int64_t ldf = L.fld[d];
     hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, off, perm + poff, v, s1);
-    for (int b0 = 0; b0 < n; b0 += kTrsvNB) {
-      const int nb = std::min(kTrsvNB, n - b0);
-      hipLaunchKernelGGL(k_trsv_step<true>, dim3(nblk(n - b0 - nb, kTrsvRows)), dim3(256), 0, ctx->stream, A, ldf, n,
-                         b0, nb, s1 + off, s2 + off);
+    const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
+    const dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
+    const dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
+    // L y = P v: rhs s1 (updated in place), solution s2; then U x = y: rhs s2, solution out
+    for (int bk = 0; bk < nbk; ++bk) {
+      const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
+      const int rest = n - b0 - m;
+      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(rest, kTrsvBlockRowsH)), dim3(256), 0, ctx->stream, A, ldf, n, b0, m,
+                         1, DL + (int64_t)bk * kTrsvNB * kTrsvNB, s1 + off, s2 + off);
     }
-    const int last = (n - 1) / kTrsvNB * kTrsvNB;
-    for (int b0 = last; b0 >= 0; b0 -= kTrsvNB) {
-      const int nb = std::min(kTrsvNB, n - b0);
-      hipLaunchKernelGGL(k_trsv_step<false>, dim3(nblk(b0, kTrsvRows)), dim3(256), 0, ctx->stream, A, ldf, n, b0,
-                         nb, s2 + off, out + off);
+    for (int bk = nbk - 1; bk >= 0; --bk) {
+      const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
+      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(b0, kTrsvBlockRowsH)), dim3(256), 0, ctx->stream, A, ldf, n, b0, m, 0,
+                         DU + (int64_t)bk * kTrsvNB * kTrsvNB, s2 + off, out + off);
     }
     poff += n;
   }
@@ -871,6 +935,35 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta, int64_t n, vie_c128 *out) {
     HIPCK(hipMemcpyAsync(out + s, o, 16 * m, hipMemcpyDeviceToHost, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
   }
+  return VIE_OK;
+}
+
+int vie_get_fill_stats(const vie_ctx *ctx, vie_fill_stats *out) {
+  if (!ctx || !out) return VIE_EINVAL;
+  if (ctx->state < S_FILLED) return VIE_ESTATE;
+  *out = ctx->fstats;
+  return VIE_OK;
+}
+
+int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec) {
+  if (int r = check(ctx, S_FILLED, "vie_bench_matvec")) return r;
+  if (reps < 1 || !ms_per_matvec) return fail(ctx, VIE_EINVAL, "bad arguments");
+  HIPCK(hipSetDevice(ctx->device));
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  dz *x = ctx->ptr<dz>(L.vz), *y = ctx->ptr<dz>(L.vw);
+  hipLaunchKernelGGL(k_fill_const, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N, 1.0, 0.5);
+  LAUNCHCK();
+  HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
+  for (int r = 0; r < reps; ++r)
+    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z),
+                       L.ld, N, (const dz *)x, (const dz *)nullptr, y);
+  LAUNCHCK();
+  HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
+  HIPCK(hipEventSynchronize(ctx->ev3));
+  float ms = 0;
+  HIPCK(hipEventElapsedTime(&ms, ctx->ev2, ctx->ev3));
+  *ms_per_matvec = ms / reps;
   return VIE_OK;
 }
 

@@ -158,6 +158,11 @@ __global__ void k_sub_into(const dz *__restrict__ a, dz *__restrict__ y, int64_t
   if (k < n) y[k] = a[k] - y[k];
 }
 
+__global__ void k_fill_const(dz *__restrict__ x, int64_t N, double re, double im) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) x[k] = mk(re, im);
+}
+
 __global__ void k_copy(dz *__restrict__ d, const dz *__restrict__ s, int64_t N) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) d[k] = s[k];

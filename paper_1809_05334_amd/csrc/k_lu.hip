@@ -224,14 +224,42 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
   if (i < n) z[off + i] = v[off + perm[i]];
 }
 
-// One block-column step of a blocked triangular solve.  `rhs` holds the
-// right-hand side being updated; rows [b0, b0+nb) are final when the step
-// starts.  Every thread block solves the diagonal block (wave 0, values kept
-// in registers, one dot product per row reduced across the wave), block 0
-// stores the solved rows into `sol`, and all blocks update their share of the
-// remaining rows of `rhs`: below the block for L (unit diagonal), above it
-// for U.  The diagonal rows of `rhs` are only read in this step, so the
-// stores to `sol` do not race with other blocks' loads.
+// Inverses of the nb x nb diagonal blocks of L (unit lower) and U (upper),
+// computed once per factorisation and stored TRANSPOSED: block b of DT holds
+// inv(T_bb)^T row-major (nb x nb), T_bb the diagonal block at row b*nb.  One
+// thread block per diagonal block; thread j forms column j of the inverse
+// (row j of DT, contiguous) by substitution.
+__global__ __launch_bounds__(128) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb, int lower,
+                                                  dz *__restrict__ DT) {
+  const int b = blockIdx.x;
+  const int b0 = b * nb;
+  const int m = min(nb, n - b0);
+  const int j = threadIdx.x;
+  if (j >= nb) return;
+  dz *X = DT + ((int64_t)b * nb + j) * nb;   // X[i] = inv(T)[i][j]
+  for (int i = 0; i < nb; ++i) X[i] = mk(0, 0);
+  if (j >= m) return;
+  const dz *T = F + (int64_t)b0 * ld + b0;
+  if (lower) {
+    X[j] = mk(1, 0);
+    for (int i = j + 1; i < m; ++i) {
+      dz s = mk(0, 0);
+      for (int l = j; l < i; ++l) s = s + T[(int64_t)i * ld + l] * X[l];
+      X[i] = mk(0, 0) - s;
+    }
+  } else {
+    auto inv = [](dz d) {
+      const double den = d.re * d.re + d.im * d.im;
+      return mk(d.re / den, -d.im / den);
+    };
+    X[j] = inv(T[(int64_t)j * ld + j]);
+    for (int i = j - 1; i >= 0; --i) {
+      dz s = mk(0, 0);
+      for (int l = i + 1; l <= j; ++l) s = s + T[(int64_t)i * ld + l] * X[l];
+      X[i] = mk(0, 0) - s * inv(T[(int64_t)i * ld + i]);
+    }
+  }
+}
 
 __device__ __forceinline__ dz wave_sum(dz v) {
   for (int o = 32; o > 0; o >>= 1) {
@@ -241,64 +269,79 @@ __device__ __forceinline__ dz wave_sum(dz v) {
   return v;
 }
 
-template <bool LOWER>
-__global__ __launch_bounds__(256) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int nb,
-                                                   dz *__restrict__ rhs, dz *__restrict__ sol) {
+// One block-column step of a blocked triangular solve.  On entry rows
+// [b0, b0+m) of rhs are final.  Every thread block forms
+// z_b = inv(T_bb) rhs_b (128 x 128 product with the transposed inverse,
+// coalesced, two threads per row, loads unrolled so they overlap), thread
+// block 0 stores z_b into sol, and each block then subtracts
+// T[i, b0:b0+m] z_b from its 64 rows still to be solved (below the block for
+// L, above it for U), eight rows per wave at once.
+constexpr int kTrsvBlockRows = 64;
+
+__global__ __launch_bounds__(256) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int m,
+                                                   int lower, const dz *__restrict__ DT, dz *__restrict__ rhs,
+                                                   dz *__restrict__ sol) {
+  __shared__ dz xb[kTrsvNB];
+  __shared__ dz part[2][kTrsvNB];
   __shared__ dz zb[kTrsvNB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (wave == 0) {
-    // lane holds entries lane and lane + 64 of the block
-    dz x0 = lane < nb ? rhs[b0 + lane] : mk(0, 0);
-    dz x1 = lane + 64 < nb ? rhs[b0 + lane + 64] : mk(0, 0);
-    if (LOWER) {
-      for (int i = 1; i < nb; ++i) {
-        const dz *Li = F + (int64_t)(b0 + i) * ld + b0;
-        dz s = mk(0, 0);
-        if (lane < i) s = Li[lane] * x0;
-        if (lane + 64 < i) s = s + Li[lane + 64] * x1;
-        s = wave_sum(s);
-        if (lane == (i & 63)) {
-          if (i < 64) x0 = x0 - s;
-          else x1 = x1 - s;
-        }
-      }
-    } else {
-      for (int i = nb - 1; i >= 0; --i) {
-        const dz *Ui = F + (int64_t)(b0 + i) * ld + b0;
-        dz s = mk(0, 0);
-        if (lane > i && lane < nb) s = Ui[lane] * x0;
-        if (lane + 64 > i && lane + 64 < nb) s = s + Ui[lane + 64] * x1;
-        s = wave_sum(s);
-        if (lane == (i & 63)) {
-          const dz d = Ui[i];
-          const double den = d.re * d.re + d.im * d.im;
-          const dz t = (i < 64 ? x0 : x1) - s;
-          const dz q = mk((t.re * d.re + t.im * d.im) / den, (t.im * d.re - t.re * d.im) / den);
-          if (i < 64) x0 = q;
-          else x1 = q;
-        }
-      }
+  if (tid < kTrsvNB) xb[tid] = tid < m ? rhs[b0 + tid] : mk(0, 0);
+  __syncthreads();
+  {
+    const int r = tid & (kTrsvNB - 1), h = tid >> 7;
+    const dz *col = DT + (int64_t)(h * 64) * kTrsvNB + r;
+    dz s0 = mk(0, 0), s1 = mk(0, 0), s2 = mk(0, 0), s3 = mk(0, 0);
+#pragma unroll 4
+    for (int l = 0; l < 64; l += 4) {
+      const dz d0 = col[(int64_t)(l + 0) * kTrsvNB], d1 = col[(int64_t)(l + 1) * kTrsvNB];
+      const dz d2 = col[(int64_t)(l + 2) * kTrsvNB], d3 = col[(int64_t)(l + 3) * kTrsvNB];
+      s0 = s0 + d0 * xb[h * 64 + l];
+      s1 = s1 + d1 * xb[h * 64 + l + 1];
+      s2 = s2 + d2 * xb[h * 64 + l + 2];
+      s3 = s3 + d3 * xb[h * 64 + l + 3];
     }
-    if (lane < nb) zb[lane] = x0;
-    if (lane + 64 < nb) zb[lane + 64] = x1;
+    part[h][r] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
-  if (blockIdx.x == 0)
-    for (int i = tid; i < nb; i += 256) sol[b0 + i] = zb[i];
-  const int rbase = LOWER ? b0 + nb : 0;
-  const int rend = LOWER ? n : b0;
-  for (int rr = 0; rr < 16; ++rr) {
-    const int i = rbase + blockIdx.x * kTrsvRows + wave * 16 + rr;
-    if (i >= rend) break;
-    const dz *Fi = F + (int64_t)i * ld + b0;
-    dz s = mk(0, 0);
-    for (int l = lane; l < nb; l += 64) s = s + Fi[l] * zb[l];
-    s = wave_sum(s);
-    if (lane == 0) rhs[i] = rhs[i] - s;
+  if (tid < kTrsvNB) {
+    const dz z = part[0][tid] + part[1][tid];
+    zb[tid] = tid < m ? z : mk(0, 0);
+    if (blockIdx.x == 0 && tid < m) sol[b0 + tid] = z;
+  }
+  __syncthreads();
+  int rlo, rhi;
+  if (lower) {
+    rlo = b0 + m + blockIdx.x * kTrsvBlockRows;
+    rhi = min(n, rlo + kTrsvBlockRows);
+  } else {
+    rlo = blockIdx.x * kTrsvBlockRows;
+    rhi = min(b0, rlo + kTrsvBlockRows);
+  }
+  const dz z0 = zb[lane], z1 = zb[lane + 64];
+  // wave w owns rows rlo + 16 w .. rlo + 16 w + 15, in two groups of eight
+  for (int g = 0; g < 2; ++g) {
+    const int i0 = rlo + 16 * wave + 8 * g;
+    dz s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q;
+      s[q] = mk(0, 0);
+      if (i < rhi) {
+        const dz *Fi = F + (int64_t)i * ld + b0;
+        if (lane < m) s[q] = Fi[lane] * z0;
+        if (lane + 64 < m) s[q] = s[q] + Fi[lane + 64] * z1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = wave_sum(s[q]);
+    if (lane < 8 && i0 + lane < rhi) {
+      dz v = s[0];
+#pragma unroll
+      for (int q = 1; q < 8; ++q)
+        if (lane == q) v = s[q];
+      rhs[i0 + lane] = rhs[i0 + lane] - v;
+    }
   }
 }
-
-template __global__ void k_trsv_step<true>(const dz *, int64_t, int, int, int, dz *, dz *);
-template __global__ void k_trsv_step<false>(const dz *, int64_t, int, int, int, dz *, dz *);
 
 }  // namespace vie

@@ -41,10 +41,9 @@ __global__ void k_lu_trsm(dz *A, int64_t ld, int n, int k0, int jb);
 __global__ void k_lu_gemm(dz *A, int64_t ld, int n, int k0, int jb);
 __global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
-template <bool LOWER>
-__global__ void k_trsv_step(const dz *F, int64_t ld, int n, int b0, int nb, dz *rhs, dz *sol);
-extern template __global__ void k_trsv_step<true>(const dz *, int64_t, int, int, int, dz *, dz *);
-extern template __global__ void k_trsv_step<false>(const dz *, int64_t, int, int, int, dz *, dz *);
+__global__ void k_diag_inv(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
+constexpr int kTrsvBlockRowsH = 64;   // rows updated per thread block in k_trsv_step
+__global__ void k_trsv_step(const dz *F, int64_t ld, int n, int b0, int m, int lower, const dz *DT, dz *rhs, dz *sol);
 
 // Krylov (k_krylov.hip)
 constexpr int kMvRPW = 4;
@@ -58,6 +57,7 @@ __global__ void k_norm_reduce(const double *part, int nblk, double *out);
 __global__ void k_scale(const dz *w, const double *nrm, dz *v, int64_t N);
 __global__ void k_axpy(dz *x, const dz *u, int64_t N);
 __global__ void k_copy(dz *d, const dz *s, int64_t N);
+__global__ void k_fill_const(dz *x, int64_t N, double re, double im);
 __global__ void k_sub_into(const dz *a, dz *y, int64_t n);
 __global__ void k_givens(dz *H, int ldh, int j, const double *hn, double *cs, dz *sn, dz *g, double *res);
 __global__ void k_backsolve(const dz *H, int ldh, int k, const dz *g, dz *y);

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "host.h"
@@ -292,6 +294,20 @@ static int cheb_fit(F f, double lo, double hi, double abs_tol, double rel_tol, d
   return -1;
 }
 
+// Run body(i) for i in [0, n) on up to 16 host threads.
+template <class Fn>
+static void parallel_for(int n, Fn body) {
+  const int nth = std::max(1, std::min<int>({16, n, (int)std::thread::hardware_concurrency()}));
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (int i = next++; i < n; i = next++) body(i);
+  };
+  std::vector<std::thread> th;
+  for (int k = 1; k < nth; ++k) th.emplace_back(work);
+  work();
+  for (auto &t : th) t.join();
+}
+
 // ---------------------------------------------------------------- Ewald tables
 std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, double lambda, double theta,
                             double phi, double *wood_margin) {
@@ -360,8 +376,13 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
   };
   auto Ffull = [&](double x) -> ld { return x >= 0.5 ? Fx(x) : 1.0L + (ld)x * Hx(x); };
 
-  // ---- spatial images
-  int ni = 0;
+  // ---- spatial images: significance cut first, then the fits in parallel
+  struct ImgJob {
+    int m, n;
+    double xlo, xhi;
+    bool touching;
+  };
+  std::vector<ImgJob> jobs;
   for (int m = -kPgfM; m <= kPgfM; ++m)
     for (int n = -kPgfM; n <= kPgfM; ++n) {
       double dxlo = std::max(0.0, (std::abs(m) - 0.5) * a), dylo = std::max(0.0, (std::abs(n) - 0.5) * b);
@@ -371,30 +392,32 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
       double xlo = Rlo * E, xhi = Rhi * E;
       bool touching_class = std::abs(m) <= 1 && std::abs(n) <= 1;
       if (!touching_class && Rlo > 0 && std::exp(y * y - xlo * xlo) / (4 * kPi * Rlo) < sig) continue;
-      PgfImage &im = tab.img[ni];
-      im.m = m;
-      im.n = n;
-      im.xa = xlo;
-      im.xs = 2.0 / (xhi - xlo);
-      double ph = kx * m * a + ky * n * b;
-      im.cre = std::cos(ph) / (4 * kPi);
-      im.cim = std::sin(ph) / (4 * kPi);
-      im.deg = cheb_fit(Ffull, xlo, xhi, 1e-16, 1e-15, im.f, kPgfMaxDeg);
-      if (im.deg < 0) return "lattice-sum table: spatial fit did not converge";
-      im.hdeg = -1;
-      if (touching_class) {
-        im.hdeg = cheb_fit(Hx, xlo, xhi, 0.0, 1e-15, im.h, kPgfMaxDeg);
-        if (im.hdeg < 0) return "lattice-sum table: singular-remainder fit did not converge";
-      }
-      ++ni;
+      jobs.push_back({m, n, xlo, xhi, touching_class});
     }
-  tab.nimg = ni;
+  tab.nimg = (int)jobs.size();
+  std::atomic<int> bad(0);
+  parallel_for((int)jobs.size(), [&](int i) {
+    const ImgJob &jb = jobs[i];
+    PgfImage &im = tab.img[i];
+    im.m = jb.m;
+    im.n = jb.n;
+    im.xa = jb.xlo;
+    im.xs = 2.0 / (jb.xhi - jb.xlo);
+    double ph = kx * jb.m * a + ky * jb.n * b;
+    im.cre = std::cos(ph) / (4 * kPi);
+    im.cim = std::sin(ph) / (4 * kPi);
+    im.deg = cheb_fit(Ffull, jb.xlo, jb.xhi, 1e-16, 1e-15, im.f, kPgfMaxDeg);
+    im.hdeg = -1;
+    if (jb.touching) im.hdeg = cheb_fit(Hx, jb.xlo, jb.xhi, 0.0, 1e-15, im.h, kPgfMaxDeg);
+    if (im.deg < 0 || (jb.touching && im.hdeg < 0)) bad = 1;
+  });
+  if (bad) return "lattice-sum table: spatial fit did not converge";
 
   // ---- spectral modes, K_pq as a function of w = (z E)^2 on [0, (zspan E)^2]
   const double wmax = std::max(1e-30, zspan * E * zspan * E) * (1 + 1e-9);
   tab.ws = 2.0 / wmax;
-  for (int p = -kPgfM; p <= kPgfM; ++p)
-    for (int q = -kPgfM; q <= kPgfM; ++q) {
+  parallel_for(kPgfTerms, [&](int idx) {
+      const int p = idx / kPgfSide - kPgfM, q = idx % kPgfSide - kPgfM;
       double tx = kx + 2 * kPi * p / a, ty = ky + 2 * kPi * q / b;
       double kt2 = tx * tx + ty * ty;
       PgfMode &md = tab.mode[(p + kPgfM) * kPgfSide + (q + kPgfM)];
@@ -413,10 +436,10 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
         };
         double kmax = 0;
         for (int j = 0; j <= 16; ++j) kmax = std::max(kmax, (double)std::fabs(K(wmax * j / 16.0)));
-        if (kmax < sig) continue;  // deg stays -1
+        if (kmax < sig) return;  // deg stays -1
         md.cplx = 0;
         md.deg = cheb_fit(K, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg);
-        if (md.deg < 0) return "lattice-sum table: spectral fit did not converge";
+        if (md.deg < 0) bad = 1;
       } else {
         // propagating order: gamma = +j beta
         double beta = std::sqrt(k0 * k0 - kt2);
@@ -430,10 +453,11 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
         md.cplx = 1;
         int d1 = cheb_fit([&](double w) { return Kc(w).real(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg);
         int d2 = cheb_fit([&](double w) { return Kc(w).imag(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kim, kPgfMaxDeg);
-        if (d1 < 0 || d2 < 0) return "lattice-sum table: spectral fit did not converge";
+        if (d1 < 0 || d2 < 0) bad = 1;
         md.deg = std::max(d1, d2);
       }
-    }
+    });
+  if (bad) return "lattice-sum table: spectral fit did not converge";
   return "";
 }
 

@@ -42,6 +42,16 @@ class SolveInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FillStats(C.Structure):
+    _fields_ = [("t_fill_ms", C.c_double), ("t_far_ms", C.c_double), ("t_near_ms", C.c_double),
+                ("t_face_ms", C.c_double), ("far_pairs", C.c_int64), ("near_pairs", C.c_int64),
+                ("face_pairs", C.c_int64), ("far_launches", C.c_int64), ("point_pair_flops", C.c_double),
+                ("far_flops", C.c_double), ("nimg", C.c_int), ("nmode", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _LIB = None
 
 _SIGS = {
@@ -64,6 +74,8 @@ _SIGS = {
     "vie_read_solution": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vie_pgf_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "vie_residual_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
+    "vie_bench_matvec": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
 }
 
 
@@ -219,3 +231,13 @@ class Solver:
         h = np.zeros(cap)
         n = self.lib.vie_residual_history(self.h, _p(h), cap)
         return h[:max(0, n)]
+
+    def fill_stats(self):
+        st = FillStats()
+        self._ck(self.lib.vie_get_fill_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def bench_matvec(self, reps=10):
+        ms = C.c_double()
+        self._ck(self.lib.vie_bench_matvec(self.h, int(reps), C.byref(ms)))
+        return ms.value
