@@ -23,6 +23,7 @@ namespace {
 enum State { S_NEW = 0, S_MESH = 1, S_BOUND = 2, S_FILLED = 3, S_FACTORED = 4, S_SOLVED = 5 };
 
 constexpr int kLuNB = 64;
+constexpr int kMaxPack = 8192;     // doubles of the packed lattice-sum table (64 KB of LDS)
 constexpr int kRedBlocks = 240;   // blocks of the two-stage reductions
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -32,7 +33,7 @@ struct Region {
 };
 
 struct Layout {
-  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf;
+  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
   Region Z, F, ipiv, perm, rpiv, info, dinv;
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
@@ -61,6 +62,8 @@ struct vie_ctx {
   double lambda = 0, theta = 0, phi = 0;
   PgfTable *tab = nullptr;          // host copy (heap, large)
   std::vector<dz> eps_int;
+  std::vector<double> pack;         // packed lattice-sum table of the last fill
+  int packlen = 0;
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
   std::vector<int32_t> color_off;
   int nhalf = 0, nface = 0;
@@ -128,6 +131,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.near_m, 4 * std::max<int64_t>(1, nnear));
   put(L.quad, sizeof(QuadRules));
   put(L.pgf, sizeof(PgfTable));
+  put(L.pack, 8 * (size_t)kMaxPack);
   put(L.eps, 16 * nt);
   put(L.alpha, 16 * 4 * nt);
   put(L.gsrc, 16 * 4 * nt);
@@ -389,10 +393,18 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   // the previous fill's kernels may still read the tables: wait before overwriting
   HIPCK(hipStreamSynchronize(ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->ws + L.pgf.off, ctx->tab, sizeof(PgfTable), hipMemcpyHostToDevice, ctx->stream));
+  pack_pgf_table(*ctx->tab, ctx->pack);
+  if ((int)ctx->pack.size() > kMaxPack)
+    return fail(ctx, VIE_EINVAL, "lattice-sum table needs %zu doubles (> %d)", ctx->pack.size(), kMaxPack);
+  ctx->packlen = (int)ctx->pack.size();
+  HIPCK(hipMemcpyAsync(ctx->ws + L.pack.off, ctx->pack.data(), 8 * ctx->pack.size(), hipMemcpyHostToDevice,
+                       ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->ws + L.eps.off, ctx->eps_int.data(), 16 * t.nt, hipMemcpyHostToDevice, ctx->stream));
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
 
-  const PgfTable *tab = ctx->ptr<PgfTable>(L.pgf);
+  const double *pk_ = ctx->ptr<double>(L.pack);
+  const int pkl = ctx->packlen;
+  const size_t lds = 8 * (size_t)pkl;
   const QuadRules *qr = ctx->ptr<QuadRules>(L.quad);
   const TetGeom *tg = ctx->ptr<TetGeom>(L.tg);
   const TetFace *t2f = ctx->ptr<TetFace>(L.t2f);
@@ -418,7 +430,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   for (int ct = 0; ct < C; ++ct)
     for (int cs = 0; cs < C; ++cs) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-      hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), 0, ctx->stream, tab, qr, tg, t2f,
+      hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                          colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
                          (const dz *)gsrc, (const dz *)kappa, k0sq9, Z, L.ld);
       LAUNCHCK();
@@ -427,7 +439,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   for (int g = 0; g < C * C; ++g) {
     const int np = ctx->near_off[g + 1] - ctx->near_off[g];
     if (!np) continue;
-    hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), 0, ctx->stream, tab, qr, tg, t2f,
+    hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                        ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
                        ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
                        (const dz *)kappa, (const dz *)inveps, k0sq9, Z, L.ld);
@@ -440,7 +452,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
-      hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), 0, ctx->stream, tab, qr, tg,
+      hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
                          t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, Z,
                          L.ld);
       LAUNCHCK();
@@ -448,13 +460,13 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     if (ctx->nhalf) {
       for (int cs = 0; cs < C; ++cs) {
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-        hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), 0, ctx->stream, tab, qr,
+        hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr,
                            fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
                            (const dz *)gsrc, (const dz *)kappa, Z, L.ld);
         LAUNCHCK();
       }
-      hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), 0, ctx->stream, tab,
-                         qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, Z, L.ld);
+      hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_,
+                         pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, Z, L.ld);
       LAUNCHCK();
     }
   }
@@ -589,12 +601,12 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
     for (int bk = 0; bk < nbk; ++bk) {
       const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
       const int rest = n - b0 - m;
-      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(rest, kTrsvBlockRowsH)), dim3(256), 0, ctx->stream, A, ldf, n, b0, m,
+      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(rest, kTrsvBlockRowsH)), dim3(1024), 0, ctx->stream, A, ldf, n, b0, m,
                          1, DL + (int64_t)bk * kTrsvNB * kTrsvNB, s1 + off, s2 + off);
     }
     for (int bk = nbk - 1; bk >= 0; --bk) {
       const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
-      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(b0, kTrsvBlockRowsH)), dim3(256), 0, ctx->stream, A, ldf, n, b0, m, 0,
+      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(b0, kTrsvBlockRowsH)), dim3(1024), 0, ctx->stream, A, ldf, n, b0, m, 0,
                          DU + (int64_t)bk * kTrsvNB * kTrsvNB, s2 + off, out + off);
     }
     poff += n;
@@ -929,8 +941,8 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta, int64_t n, vie_c128 *out) {
     const int64_t m = std::min(cap, n - s);
     dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(24 * (size_t)m));
     HIPCK(hipMemcpyAsync(d, delta + 3 * s, 24 * m, hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_pgf_probe, dim3(nblk(m, 256)), dim3(256), 0, ctx->stream, ctx->ptr<PgfTable>(L.pgf),
-                       (const double *)d, m, o);
+    hipLaunchKernelGGL(k_pgf_probe, dim3(nblk(m, 256)), dim3(256), 8 * (size_t)ctx->packlen, ctx->stream,
+                       (const double *)ctx->ptr<double>(L.pack), ctx->packlen, (const double *)d, m, o);
     LAUNCHCK();
     HIPCK(hipMemcpyAsync(out + s, o, 16 * m, hipMemcpyDeviceToHost, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));

@@ -28,89 +28,202 @@ __device__ __forceinline__ void axpy(dz &acc, double s, dz a) {
 }
 
 // f(t) = sum_{k=0}^{deg} c_k T_k(t), c_0 already halved (Clenshaw recurrence).
-__device__ __forceinline__ double clenshaw(const double *__restrict__ c, int deg, double t) {
+// f(t) = sum_{k=0}^{K} c_k T_k(t) by the Clenshaw recurrence for a
+// zero-padded coefficient run, K a multiple of 4: four steps per iteration
+// with the next four coefficients fetched before the current ones are used.
+__device__ __forceinline__ double clenshaw4(const double *__restrict__ c, int K, double t) {
   double b1 = 0.0, b2 = 0.0;
   const double t2 = t + t;
-  for (int k = deg; k >= 1; --k) {
-    double b0 = fma(t2, b1, c[k] - b2);
-    b2 = b1;
-    b1 = b0;
+  if (K >= 4) {
+    double c3 = c[K], c2 = c[K - 1], c1 = c[K - 2], c0 = c[K - 3];
+#pragma unroll 1
+    for (int k = K;; k -= 4) {
+      const bool more = k >= 8;
+      double d3 = 0.0, d2 = 0.0, d1 = 0.0, d0 = 0.0;
+      if (more) {
+        d3 = c[k - 4];
+        d2 = c[k - 5];
+        d1 = c[k - 6];
+        d0 = c[k - 7];
+      }
+      double b0 = fma(t2, b1, c3 - b2);
+      b2 = b1;
+      b1 = b0;
+      b0 = fma(t2, b1, c2 - b2);
+      b2 = b1;
+      b1 = b0;
+      b0 = fma(t2, b1, c1 - b2);
+      b2 = b1;
+      b1 = b0;
+      b0 = fma(t2, b1, c0 - b2);
+      b2 = b1;
+      b1 = b0;
+      if (!more) break;
+      c3 = d3;
+      c2 = d2;
+      c1 = d1;
+      c0 = d0;
+    }
   }
   return fma(t, b1, c[0] - b2);
 }
 
-// g_p at separation (dx, dy, dz) = r - r'.  When TOUCH is true, `mask` lists the
-// lattice images (bit (m+1)*3 + (n+1)) whose 1/(4 pi R) part is integrated in
-// closed form elsewhere; for those images the remainder H(x) E/(4 pi) is used,
-// so the value returned is g_p - sum_touching e^{j kt.rho}/(4 pi R).
-template <bool TOUCH>
-__device__ __forceinline__ dz pgf_eval(const PgfTable *__restrict__ T, double dx, double dy, double dzv, int mask) {
-  const double a = T->a, b = T->b, E = T->E;
-  const double m0 = rint(dx * T->inv_a), n0 = rint(dy * T->inv_b);
-  dx = fma(-m0, a, dx);
-  dy = fma(-n0, b, dy);
-  const int im0 = (int)m0, in0 = (int)n0;
-  const double dz2 = dzv * dzv;
+// Packed lattice-sum table (layout written by the host: header, per-mode
+// offsets, image records, mode records; see host.h).
+namespace pk {
+constexpr int E = 0, A = 1, B = 2, IA = 3, IB = 4, KX = 5, KY = 6, TPA = 7, TPB = 8, WS = 9, PHRE = 10, PHIM = 19,
+              NIMG = 28, MODES = 32, IMAGES = 116;
+}
 
+// Stage the packed table into LDS (all threads of the block participate).
+__device__ __forceinline__ void stage_table(const double *__restrict__ pack, int len, double *lds) {
+  for (int i = threadIdx.x; i < len; i += blockDim.x) lds[i] = pack[i];
+  __syncthreads();
+}
+
+__device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// g_p at W separations d[w] = r - r'_w at once (one test point, W source
+// points), from the packed table P.  The table entries are read once for
+// all W separations and the W Clenshaw recurrences run interleaved.  When
+// TOUCH is true, `mask` lists the lattice images (bit (m+1)*3 + (n+1)) whose
+// 1/(4 pi R) part is integrated in closed form elsewhere; for those images
+// the remainder H(x) E/(4 pi) is used, so the value returned is
+// g_p - sum_touching e^{j kt.rho}/(4 pi R).
+template <bool TOUCH, int W>
+__device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const double (&d)[W][3], int mask,
+                                           dz (&out)[W]) {
+  const double a = P[pk::A], b = P[pk::B], E = P[pk::E];
+  double dx[W], dy[W], dz2[W], sre[W], sim[W];
+  int im0[W], in0[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const double m0 = rint(d[w][0] * P[pk::IA]), n0 = rint(d[w][1] * P[pk::IB]);
+    dx[w] = fma(-m0, a, d[w][0]);
+    dy[w] = fma(-n0, b, d[w][1]);
+    dz2[w] = d[w][2] * d[w][2];
+    im0[w] = (int)m0;
+    in0[w] = (int)n0;
+    sre[w] = 0.0;
+    sim[w] = 0.0;
+  }
   // spatial series
-  double sre = 0.0, sim = 0.0;
-  const int nimg = T->nimg;
+  const int nimg = ufirst((int)P[pk::NIMG]);
+  int off = pk::IMAGES;
+#pragma unroll 1
   for (int i = 0; i < nimg; ++i) {
-    const PgfImage &I = T->img[i];
-    const double X = fma((double)I.m, a, dx), Y = fma((double)I.n, b, dy);
-    const double R2 = fma(X, X, fma(Y, Y, dz2));
-    bool touch = false;
-    if (TOUCH) {
-      const int um = I.m - im0, un = I.n - in0;
-      touch = um >= -1 && um <= 1 && un >= -1 && un <= 1 && ((mask >> ((um + 1) * 3 + (un + 1))) & 1);
-    }
-    double f;
-    if (!touch) {
+    const double *R = P + off;
+    const double xa = R[0], xs = R[1], cre = R[2], cim = R[3];
+    const int im = ufirst((int)R[4]), in = ufirst((int)R[5]), K = ufirst((int)R[6]);
+    off += ufirst((int)R[7]);
+    double t[W], sc[W];
+    bool touch[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const double X = fma((double)im, a, dx[w]), Y = fma((double)in, b, dy[w]);
+      const double R2 = fma(X, X, fma(Y, Y, dz2[w]));
+      touch[w] = false;
+      if (TOUCH) {
+        const int um = im - im0[w], un = in - in0[w];
+        touch[w] = um >= -1 && um <= 1 && un >= -1 && un <= 1 && ((mask >> ((um + 1) * 3 + (un + 1))) & 1);
+      }
       const double rinv = rsqrt(R2);
-      const double x = R2 * rinv * E;
-      f = clenshaw(I.f, I.deg, fma(x - I.xa, I.xs, -1.0)) * rinv;
-    } else {
-      const double x = sqrt(R2) * E;
-      f = clenshaw(I.h, I.hdeg, fma(x - I.xa, I.xs, -1.0)) * E;
+      const double x = R2 > 0.0 ? R2 * rinv * E : 0.0;
+      t[w] = fma(x - xa, xs, -1.0);
+      sc[w] = touch[w] ? E : rinv;
     }
-    sre = fma(I.cre, f, sre);
-    sim = fma(I.cim, f, sim);
+    // W interleaved Clenshaw recurrences on the F coefficients
+    double b1[W], b2[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) b1[w] = b2[w] = 0.0;
+    const double *c = R + 8;
+#pragma unroll 1
+    for (int k = K; k >= 2; k -= 2) {
+      const double ck = c[k], ck1 = c[k - 1];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const double t2 = t[w] + t[w];
+        const double bk = fma(t2, b1[w], ck - b2[w]);
+        const double bk1 = fma(t2, bk, ck1 - b1[w]);
+        b2[w] = bk;
+        b1[w] = bk1;
+      }
+    }
+    double f[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) f[w] = fma(t[w], b1[w], c[0] - b2[w]);
+    if (TOUCH) {
+      bool any = false;
+#pragma unroll
+      for (int w = 0; w < W; ++w) any = any || touch[w];
+      if (any) {
+        // touching images use the H fit (extracted 1/(4 pi R))
+        const double *Hb = R + 8 + K + 4;
+        const int HK = ufirst((int)Hb[0]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (touch[w]) f[w] = clenshaw4(Hb + 4, HK, t[w]);
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const double g = f[w] * sc[w];
+      sre[w] = fma(cre, g, sre[w]);
+      sim[w] = fma(cim, g, sim[w]);
+    }
   }
 
-  // spectral series, Floquet phases by recurrence in p and q
-  const double tw = fma(dz2 * E * E, T->ws, -1.0);
-  double s0, c0, s1, c1;
-  sincos(-T->kx * dx, &s0, &c0);
-  sincos(-T->two_pi_a * dx, &s1, &c1);
-  const dz bx = mk(c1, s1);
-  dz ex = mk(c0, s0) * conjz(bx * bx * bx * bx);  // p = -4
-  sincos(-T->ky * dy, &s0, &c0);
-  sincos(-T->two_pi_b * dy, &s1, &c1);
-  const dz by = mk(c1, s1);
-  const dz ey0 = mk(c0, s0) * conjz(by * by * by * by);  // q = -4
-  double kre = 0.0, kim = 0.0;
-  for (int p = 0; p < kPgfSide; ++p) {
-    dz e = ex * ey0;
-    for (int q = 0; q < kPgfSide; ++q) {
-      const PgfMode &M = T->mode[p * kPgfSide + q];
-      if (M.deg >= 0) {
-        const double kr = clenshaw(M.kre, M.deg, tw);
-        if (M.cplx) {
-          const double ki = clenshaw(M.kim, M.deg, tw);
-          kre += e.re * kr - e.im * ki;
-          kim += e.re * ki + e.im * kr;
-        } else {
-          kre = fma(e.re, kr, kre);
-          kim = fma(e.im, kr, kim);
+  // spectral series one separation at a time (keeps the Floquet phase
+  // recurrences of a single point live), phases by recurrence in p and q
+#pragma unroll 1
+  for (int w = 0; w < W; ++w) {
+    const double tw = fma(dz2[w] * E * E, P[pk::WS], -1.0);
+    double s0, c0, s1, c1;
+    sincos(-P[pk::KX] * dx[w], &s0, &c0);
+    sincos(-P[pk::TPA] * dx[w], &s1, &c1);
+    const dz bx = mk(c1, s1);
+    dz ex = mk(c0, s0) * conjz(bx * bx * bx * bx);  // p = -4
+    sincos(-P[pk::KY] * dy[w], &s0, &c0);
+    sincos(-P[pk::TPB] * dy[w], &s1, &c1);
+    const dz by = mk(c1, s1);
+    const dz ey0 = mk(c0, s0) * conjz(by * by * by * by);  // q = -4
+    double kre = 0.0, kim = 0.0;
+#pragma unroll 1
+    for (int p = 0; p < kPgfSide; ++p) {
+      dz e = ex * ey0;
+#pragma unroll 1
+      for (int q = 0; q < kPgfSide; ++q) {
+        const int moff = ufirst((int)P[pk::MODES + p * kPgfSide + q]);
+        if (moff > 0) {
+          const double *M = P + moff;
+          const int K = ufirst((int)M[0]);
+          const double kr = clenshaw4(M + 4, K, tw);
+          if (M[1] != 0.0) {
+            const double ki = clenshaw4(M + 4 + K + 4, K, tw);
+            kre += e.re * kr - e.im * ki;
+            kim += e.re * ki + e.im * kr;
+          } else {
+            kre = fma(e.re, kr, kre);
+            kim = fma(e.im, kr, kim);
+          }
         }
+        e = e * by;
       }
-      e = e * by;
+      ex = ex * bx;
     }
-    ex = ex * bx;
+    const int pi = (im0[w] + 1) * 3 + (in0[w] + 1);
+    const dz ph = mk(P[pk::PHRE + pi], P[pk::PHIM + pi]);
+    out[w] = ph * mk(sre[w] + kre, sim[w] + kim);
   }
-  const int pi = (im0 + 1) * 3 + (in0 + 1);
-  const dz ph = mk(T->ph0re[pi], T->ph0im[pi]);
-  return ph * mk(sre + kre, sim + kim);
+}
+
+// single separation
+template <bool TOUCH>
+__device__ __forceinline__ dz pgf_eval(const double *__restrict__ P, double dx, double dy, double dzv, int mask) {
+  const double d[1][3] = {{dx, dy, dzv}};
+  dz o[1];
+  pgf_eval_w<TOUCH, 1>(P, d, mask, o);
+  return o[0];
 }
 
 // ---------------------------------------------------------------- potentials
@@ -192,7 +305,7 @@ __device__ inline void tet_potentials(const double (*v)[3], const double *r, dou
   for (int d = 0; d < 3; ++d) c[d] = 0.25 * (v[0][d] + v[1][d] + v[2][d] + v[3][d]);
   P = 0.0;
   V1[0] = V1[1] = V1[2] = 0.0;
-#pragma unroll
+#pragma unroll 1
   for (int f = 0; f < 4; ++f) {
     const double *A = v[F[f][0]], *B = v[F[f][1]], *C = v[F[f][2]];
     double e1[3], e2[3], n[3], ac[3];

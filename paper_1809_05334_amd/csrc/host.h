@@ -73,4 +73,17 @@ double erfi_r(double y);
 std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, double lambda, double theta,
                             double phi, double *wood_margin);
 
+// Compact copy of the table for the kernels (staged into LDS): only the
+// fitted coefficients of the significant terms, in doubles.  Layout:
+//   [0..10)  E, a, b, 1/a, 1/b, kx, ky, 2pi/a, 2pi/b, ws
+//   [10..19) Re phase0[9], [19..28) Im phase0[9], [28] nimg
+//   [32..113) per mode (p,q) grid index: offset of its record or 0
+//   image records from kPackImages on, each
+//     [xa, xs, cre, cim, m, n, K, len] f[0..K] (pad to 4) [HK, 0, 0, 0] h[0..HK] (pad to 4)
+//     (the H block only for touching classes; len = record length)
+//   mode records [K, cplx, 0, 0] kre[0..K] (pad) kim[0..K] (pad, complex orders only)
+// K, HK are the degrees rounded up to a multiple of 4 (zero coefficients).
+constexpr int kPackImages = 116;
+void pack_pgf_table(const PgfTable &tab, std::vector<double> &out);
+
 }  // namespace vie

@@ -115,13 +115,17 @@ __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, 
 }
 
 // Far tet pairs: 4 x 4 product rule.  One wave = one test tet x 64 source tets.
-__global__ __launch_bounds__(256) void k_tt_far(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                 const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                 const int32_t *__restrict__ test_list, int ntest,
                                                 const int32_t *__restrict__ src_list, int nsrc,
                                                 const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
                                                 const dz *__restrict__ kappa, double k0sq9, dz *__restrict__ Z,
                                                 int64_t ld) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const double *__restrict__ P = s_tab;
+
   const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int si = blockIdx.x * 64 + (threadIdx.x & 63);
   if (ti >= ntest || si >= nsrc) return;
@@ -131,16 +135,22 @@ __global__ __launch_bounds__(256) void k_tt_far(const PgfTable *__restrict__ tab
   const TetGeom gs = tg[S];
   if (touch_mask(gt.canon, gt.off, 4, gs.canon, gs.off, 4)) return;  // touching pairs: k_tt_near
 
-  double up[4][3], wq = 0.25 * gs.vol, wt = 0.25 * gt.vol;
+  const double wq = 0.25 * gs.vol, wt = 0.25 * gt.vol;
+  Moments M;
+  moments_zero(M);
+  const double dc[3] = {gt.c[0] - gs.c[0], gt.c[1] - gs.c[1], gt.c[2] - gs.c[2]};
+  // source points relative to the source centroid
+  double up[4][3];
+#pragma unroll
   for (int j = 0; j < 4; ++j)
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       double s = 0;
       for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
       up[j][d] = s - gs.c[d];
     }
-  Moments M;
-  moments_zero(M);
-  const double dc[3] = {gt.c[0] - gs.c[0], gt.c[1] - gs.c[1], gt.c[2] - gs.c[2]};
+  // one test point against the four source points per lattice-sum call
+#pragma unroll 1
   for (int i = 0; i < 4; ++i) {
     double u[3];
     for (int d = 0; d < 3; ++d) {
@@ -148,10 +158,16 @@ __global__ __launch_bounds__(256) void k_tt_far(const PgfTable *__restrict__ tab
       for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
       u[d] = s - gt.c[d];
     }
+    double sep[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sep[j][d] = dc[d] + u[d] - up[j][d];
+    dz g[4];
+    pgf_eval_w<false, 4>(P, sep, 0, g);
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const dz g = pgf_eval<false>(tab, dc[0] + u[0] - up[j][0], dc[1] + u[1] - up[j][1],
-                                   dc[2] + u[2] - up[j][2], 0);
-      const dz gw = (wt * wq) * g;
+      const dz gw = (wt * wq) * g[j];
       M.m0 = M.m0 + gw;
       for (int d = 0; d < 3; ++d) {
         axpy(M.mu[d], u[d], gw);
@@ -166,28 +182,26 @@ __global__ __launch_bounds__(256) void k_tt_far(const PgfTable *__restrict__ tab
 // Touching tet pairs: 14-point outer rule on T; per touching image the closed
 // form int_S 1/R and int_S (r'-r)/R; 4-point inner rule for the remainder.
 // The self pair also adds the mass term <f_m, f_n / eps_r>.
-__global__ __launch_bounds__(128) void k_tt_near(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                  const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                  const int32_t *__restrict__ lt, const int32_t *__restrict__ ls,
                                                  const int32_t *__restrict__ lmask, int npairs,
                                                  const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
                                                  const dz *__restrict__ kappa, const dz *__restrict__ inv_eps,
                                                  double k0sq9, dz *__restrict__ Z, int64_t ld) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const double *__restrict__ P = s_tab;
+
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npairs) return;
   const int T = lt[i], S = ls[i], mask = lmask[i];
   const TetGeom gt = tg[T];
   const TetGeom gs = tg[S];
-  double up[4][3];
   const double wq = 0.25 * gs.vol;
-  for (int j = 0; j < 4; ++j)
-    for (int d = 0; d < 3; ++d) {
-      double s = 0;
-      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
-      up[j][d] = s - gs.c[d];
-    }
   Moments M;
   moments_zero(M);
+#pragma unroll 1
   for (int q = 0; q < 14; ++q) {
     double r[3], u[3];
     for (int d = 0; d < 3; ++d) {
@@ -198,21 +212,33 @@ __global__ __launch_bounds__(128) void k_tt_near(const PgfTable *__restrict__ ta
     }
     const double w = qr->w14[q] * gt.vol;
     dz s0 = mk(0, 0), s1[3] = {mk(0, 0), mk(0, 0), mk(0, 0)};
+#pragma unroll 1
     for (int b = 0; b < 9; ++b) {
       if (!((mask >> b) & 1)) continue;
       const int m = b / 3 - 1, n = b % 3 - 1;
-      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
-      double P, V1[3];
-      tet_potentials(gs.v, o, P, V1);
-      const dz ph = kInv4Pi * mk(tab->ph0re[b], -tab->ph0im[b]);  // e^{+j kt.rho}/(4 pi)
-      s0 = s0 + P * ph;
-      for (int d = 0; d < 3; ++d) s1[d] = s1[d] + (V1[d] + (o[d] - gs.c[d]) * P) * ph;
+      const double o[3] = {r[0] + m * P[pk::A], r[1] + n * P[pk::B], r[2]};
+      double pot, V1[3];
+      tet_potentials(gs.v, o, pot, V1);
+      const dz ph = kInv4Pi * mk(P[pk::PHRE + b], -P[pk::PHIM + b]);  // e^{+j kt.rho}/(4 pi)
+      s0 = s0 + pot * ph;
+      for (int d = 0; d < 3; ++d) s1[d] = s1[d] + (V1[d] + (o[d] - gs.c[d]) * pot) * ph;
     }
+    double sep[4][3], upj[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double t = 0;
+        for (int k = 0; k < 4; ++k) t = fma(qr->tet4[j][k], gs.v[k][d], t);
+        upj[j][d] = t - gs.c[d];
+        sep[j][d] = r[d] - t;
+      }
+    dz g[4];
+    pgf_eval_w<true, 4>(P, sep, mask, g);
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const dz g = pgf_eval<true>(tab, r[0] - gs.c[0] - up[j][0], r[1] - gs.c[1] - up[j][1],
-                                  r[2] - gs.c[2] - up[j][2], mask);
-      axpy(s0, wq, g);
-      for (int d = 0; d < 3; ++d) axpy(s1[d], wq * up[j][d], g);
+      axpy(s0, wq, g[j]);
+      for (int d = 0; d < 3; ++d) axpy(s1[d], wq * upj[j][d], g[j]);
     }
     axpy(M.m0, w, s0);
     for (int d = 0; d < 3; ++d) {
@@ -250,7 +276,7 @@ __global__ __launch_bounds__(128) void k_tt_near(const PgfTable *__restrict__ ta
 // M0 = II g_p over (test tet T, face F).  Far: 4 x 3 rule.  Touching: outer
 // 14-point rule on T, closed-form int_F 1/R per touching image, 3-point
 // inner rule for the remainder.
-__device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const TetGeom &gt,
+__device__ dz pair_tet_face(const double *__restrict__ P, const QuadRules *__restrict__ qr, const TetGeom &gt,
                             const FaceGeom &f) {
   const int mask = touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3);
   double fp[3][3];
@@ -259,6 +285,7 @@ __device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *_
   const double wf = f.area / 3.0;
   dz acc = mk(0, 0);
   if (!mask) {
+#pragma unroll 1
     for (int i = 0; i < 4; ++i) {
       double r[3];
       for (int d = 0; d < 3; ++d) {
@@ -266,11 +293,18 @@ __device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *_
         for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
         r[d] = s;
       }
+      double sep[3][3];
+#pragma unroll
       for (int j = 0; j < 3; ++j)
-        acc = acc + pgf_eval<false>(tab, r[0] - fp[j][0], r[1] - fp[j][1], r[2] - fp[j][2], 0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - fp[j][d];
+      dz g[3];
+      pgf_eval_w<false, 3>(P, sep, 0, g);
+      acc = acc + (g[0] + g[1]) + g[2];
     }
     return (0.25 * gt.vol * wf) * acc;
   }
+#pragma unroll 1
   for (int q = 0; q < 14; ++q) {
     double r[3];
     for (int d = 0; d < 3; ++d) {
@@ -279,16 +313,25 @@ __device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *_
       r[d] = s;
     }
     dz s0 = mk(0, 0);
+#pragma unroll 1
     for (int b = 0; b < 9; ++b) {
       if (!((mask >> b) & 1)) continue;
       const int m = b / 3 - 1, n = b % 3 - 1;
-      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      const double o[3] = {r[0] + m * P[pk::A], r[1] + n * P[pk::B], r[2]};
       double iinv, ione;
       tri_potentials(f.v[0], f.v[1], f.v[2], o, iinv, ione);
-      s0 = s0 + (kInv4Pi * iinv) * mk(tab->ph0re[b], -tab->ph0im[b]);
+      s0 = s0 + (kInv4Pi * iinv) * mk(P[pk::PHRE + b], -P[pk::PHIM + b]);
     }
-    for (int j = 0; j < 3; ++j)
-      axpy(s0, wf, pgf_eval<true>(tab, r[0] - fp[j][0], r[1] - fp[j][1], r[2] - fp[j][2], mask));
+    {
+      double sep[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - fp[j][d];
+      dz g[3];
+      pgf_eval_w<true, 3>(P, sep, mask, g);
+      axpy(s0, wf, (g[0] + g[1]) + g[2]);
+    }
     axpy(acc, qr->w14[q] * gt.vol, s0);
   }
   return acc;
@@ -296,7 +339,7 @@ __device__ dz pair_tet_face(const PgfTable *__restrict__ tab, const QuadRules *_
 
 // M0 = II g_p over (test face F, source tet S).  Touching: outer 7-point rule
 // on F, closed-form int_S 1/R, 4-point inner rule for the remainder.
-__device__ dz pair_face_tet(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const FaceGeom &f,
+__device__ dz pair_face_tet(const double *__restrict__ P, const QuadRules *__restrict__ qr, const FaceGeom &f,
                             const TetGeom &gs) {
   const int mask = touch_mask(f.canon, f.off, 3, gs.canon, gs.off, 4);
   double sp[4][3];
@@ -309,35 +352,52 @@ __device__ dz pair_face_tet(const PgfTable *__restrict__ tab, const QuadRules *_
   const double ws = 0.25 * gs.vol;
   dz acc = mk(0, 0);
   if (!mask) {
+#pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       double r[3];
       for (int d = 0; d < 3; ++d) r[d] = qr->tri3[i][0] * f.v[0][d] + qr->tri3[i][1] * f.v[1][d] + qr->tri3[i][2] * f.v[2][d];
+      double sep[4][3];
+#pragma unroll
       for (int j = 0; j < 4; ++j)
-        acc = acc + pgf_eval<false>(tab, r[0] - sp[j][0], r[1] - sp[j][1], r[2] - sp[j][2], 0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - sp[j][d];
+      dz g[4];
+      pgf_eval_w<false, 4>(P, sep, 0, g);
+      acc = acc + ((g[0] + g[1]) + (g[2] + g[3]));
     }
     return (f.area / 3.0 * ws) * acc;
   }
+#pragma unroll 1
   for (int q = 0; q < 7; ++q) {
     double r[3];
     for (int d = 0; d < 3; ++d) r[d] = qr->tri7[q][0] * f.v[0][d] + qr->tri7[q][1] * f.v[1][d] + qr->tri7[q][2] * f.v[2][d];
     dz s0 = mk(0, 0);
+#pragma unroll 1
     for (int b = 0; b < 9; ++b) {
       if (!((mask >> b) & 1)) continue;
       const int m = b / 3 - 1, n = b % 3 - 1;
-      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
-      double P, V1[3];
-      tet_potentials(gs.v, o, P, V1);
-      s0 = s0 + (kInv4Pi * P) * mk(tab->ph0re[b], -tab->ph0im[b]);
+      const double o[3] = {r[0] + m * P[pk::A], r[1] + n * P[pk::B], r[2]};
+      double pot, V1[3];
+      tet_potentials(gs.v, o, pot, V1);
+      s0 = s0 + (kInv4Pi * pot) * mk(P[pk::PHRE + b], -P[pk::PHIM + b]);
     }
-    for (int j = 0; j < 4; ++j)
-      axpy(s0, ws, pgf_eval<true>(tab, r[0] - sp[j][0], r[1] - sp[j][1], r[2] - sp[j][2], mask));
+    {
+      double sep[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - sp[j][d];
+      dz g[4];
+      pgf_eval_w<true, 4>(P, sep, mask, g);
+      axpy(s0, ws, (g[0] + g[1]) + (g[2] + g[3]));
+    }
     axpy(acc, qr->w7[q] * f.area, s0);
   }
   return acc;
 }
 
 // M0 = II g_p over (test face F, source face G).
-__device__ dz pair_face_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr, const FaceGeom &f,
+__device__ dz pair_face_face(const double *__restrict__ P, const QuadRules *__restrict__ qr, const FaceGeom &f,
                              const FaceGeom &g) {
   const int mask = touch_mask(f.canon, f.off, 3, g.canon, g.off, 3);
   double gp[3][3];
@@ -346,47 +406,68 @@ __device__ dz pair_face_face(const PgfTable *__restrict__ tab, const QuadRules *
   const double wg = g.area / 3.0;
   dz acc = mk(0, 0);
   if (!mask) {
+#pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       double r[3];
       for (int d = 0; d < 3; ++d) r[d] = qr->tri3[i][0] * f.v[0][d] + qr->tri3[i][1] * f.v[1][d] + qr->tri3[i][2] * f.v[2][d];
+      double sep[3][3];
+#pragma unroll
       for (int j = 0; j < 3; ++j)
-        acc = acc + pgf_eval<false>(tab, r[0] - gp[j][0], r[1] - gp[j][1], r[2] - gp[j][2], 0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - gp[j][d];
+      dz g[3];
+      pgf_eval_w<false, 3>(P, sep, 0, g);
+      acc = acc + (g[0] + g[1]) + g[2];
     }
     return (f.area / 3.0 * wg) * acc;
   }
+#pragma unroll 1
   for (int q = 0; q < 7; ++q) {
     double r[3];
     for (int d = 0; d < 3; ++d) r[d] = qr->tri7[q][0] * f.v[0][d] + qr->tri7[q][1] * f.v[1][d] + qr->tri7[q][2] * f.v[2][d];
     dz s0 = mk(0, 0);
+#pragma unroll 1
     for (int b = 0; b < 9; ++b) {
       if (!((mask >> b) & 1)) continue;
       const int m = b / 3 - 1, n = b % 3 - 1;
-      const double o[3] = {r[0] + m * tab->a, r[1] + n * tab->b, r[2]};
+      const double o[3] = {r[0] + m * P[pk::A], r[1] + n * P[pk::B], r[2]};
       double iinv, ione;
       tri_potentials(g.v[0], g.v[1], g.v[2], o, iinv, ione);
-      s0 = s0 + (kInv4Pi * iinv) * mk(tab->ph0re[b], -tab->ph0im[b]);
+      s0 = s0 + (kInv4Pi * iinv) * mk(P[pk::PHRE + b], -P[pk::PHIM + b]);
     }
-    for (int j = 0; j < 3; ++j)
-      axpy(s0, wg, pgf_eval<true>(tab, r[0] - gp[j][0], r[1] - gp[j][1], r[2] - gp[j][2], mask));
+    {
+      double sep[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - gp[j][d];
+      dz g[3];
+      pgf_eval_w<true, 3>(P, sep, mask, g);
+      axpy(s0, wg, (g[0] + g[1]) + g[2]);
+    }
     axpy(acc, qr->w7[q] * f.area, s0);
   }
   return acc;
 }
 
 // test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0
-__global__ __launch_bounds__(256) void k_tet_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
                                                   const FaceGeom *__restrict__ fg, int nface,
                                                   const dz *__restrict__ alpha, const dz *__restrict__ sigma,
                                                   dz *__restrict__ Z, int64_t ld) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const double *__restrict__ P = s_tab;
+
   const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int fi = blockIdx.x * 64 + (threadIdx.x & 63);
   if (ti >= ntest || fi >= nface) return;
   const int T = uniform(test_list[ti]);
   const TetGeom &gt = tg[T];
   const FaceGeom f = fg[fi];
-  const dz m0 = pair_tet_face(tab, qr, gt, f);
+  const dz m0 = pair_tet_face(s_tab, qr, gt, f);
   const dz sm = sigma[fi] * m0;
   for (int k = 0; k < 4; ++k) {
     const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
@@ -395,34 +476,42 @@ __global__ __launch_bounds__(256) void k_tet_face(const PgfTable *__restrict__ t
 }
 
 // half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0
-__global__ __launch_bounds__(256) void k_face_tet(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
                                                   int nhalf, const TetGeom *__restrict__ tg,
                                                   const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
                                                   int nsrc, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
                                                   dz *__restrict__ Z, int64_t ld) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const double *__restrict__ P = s_tab;
+
   const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int si = blockIdx.x * 64 + (threadIdx.x & 63);
   if (hi >= nhalf || si >= nsrc) return;
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const int S = src_list[si];
   const TetGeom gs = tg[S];
-  const dz m0 = pair_face_tet(tab, qr, f, gs) * kappa[S];
+  const dz m0 = pair_face_tet(s_tab, qr, f, gs) * kappa[S];
   const int64_t row = (int64_t)f.unknown * ld;
   for (int l = 0; l < 4; ++l) zadd(Z, row + t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0);
 }
 
 // half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
-__global__ __launch_bounds__(256) void k_face_face(const PgfTable *__restrict__ tab, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                    const FaceGeom *__restrict__ fg,
                                                    const int32_t *__restrict__ half_list, int nhalf, int nface,
                                                    const dz *__restrict__ sigma, dz *__restrict__ Z, int64_t ld) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const double *__restrict__ P = s_tab;
+
   const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
   if (hi >= nhalf || gi >= nface) return;
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const FaceGeom g = fg[gi];
-  const dz m0 = pair_face_face(tab, qr, f, g);
+  const dz m0 = pair_face_face(s_tab, qr, f, g);
   zadd(Z, (int64_t)f.unknown * ld + g.unknown, sigma[gi] * m0);
 }
 
@@ -459,11 +548,13 @@ __global__ void k_rhs(int64_t N, const int32_t *__restrict__ utet, const int32_t
 }
 
 // ------------------------------------------------------------ diagnostics
-__global__ void k_pgf_probe(const PgfTable *__restrict__ tab, const double *__restrict__ d, int64_t n,
+__global__ void k_pgf_probe(const double *__restrict__ pack, int packlen, const double *__restrict__ d, int64_t n,
                             dz *__restrict__ out) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = pgf_eval<false>(tab, d[3 * i], d[3 * i + 1], d[3 * i + 2], 0);
+  out[i] = pgf_eval<false>(s_tab, d[3 * i], d[3 * i + 1], d[3 * i + 2], 0);
 }
 
 // gather Z entries

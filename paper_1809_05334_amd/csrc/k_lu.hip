@@ -270,41 +270,42 @@ __device__ __forceinline__ dz wave_sum(dz v) {
 }
 
 // One block-column step of a blocked triangular solve.  On entry rows
-// [b0, b0+m) of rhs are final.  Every thread block forms
-// z_b = inv(T_bb) rhs_b (128 x 128 product with the transposed inverse,
-// coalesced, two threads per row, loads unrolled so they overlap), thread
-// block 0 stores z_b into sol, and each block then subtracts
+// [b0, b0+m) of rhs are final.  Every thread block (16 waves) forms
+// z_b = inv(T_bb) rhs_b: the 128 x 128 product with the transposed inverse
+// is split eight ways per row (16 independent, coalesced loads per thread),
+// thread block 0 stores z_b into sol, and each block then subtracts
 // T[i, b0:b0+m] z_b from its 64 rows still to be solved (below the block for
-// L, above it for U), eight rows per wave at once.
+// L, above it for U), four rows per wave with all loads issued together.
 constexpr int kTrsvBlockRows = 64;
 
-__global__ __launch_bounds__(256) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int m,
-                                                   int lower, const dz *__restrict__ DT, dz *__restrict__ rhs,
-                                                   dz *__restrict__ sol) {
+__global__ __launch_bounds__(1024) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int m,
+                                                    int lower, const dz *__restrict__ DT, dz *__restrict__ rhs,
+                                                    dz *__restrict__ sol) {
   __shared__ dz xb[kTrsvNB];
-  __shared__ dz part[2][kTrsvNB];
+  __shared__ dz part[8][kTrsvNB];
   __shared__ dz zb[kTrsvNB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < kTrsvNB) xb[tid] = tid < m ? rhs[b0 + tid] : mk(0, 0);
   __syncthreads();
   {
-    const int r = tid & (kTrsvNB - 1), h = tid >> 7;
-    const dz *col = DT + (int64_t)(h * 64) * kTrsvNB + r;
-    dz s0 = mk(0, 0), s1 = mk(0, 0), s2 = mk(0, 0), s3 = mk(0, 0);
-#pragma unroll 4
-    for (int l = 0; l < 64; l += 4) {
-      const dz d0 = col[(int64_t)(l + 0) * kTrsvNB], d1 = col[(int64_t)(l + 1) * kTrsvNB];
-      const dz d2 = col[(int64_t)(l + 2) * kTrsvNB], d3 = col[(int64_t)(l + 3) * kTrsvNB];
-      s0 = s0 + d0 * xb[h * 64 + l];
-      s1 = s1 + d1 * xb[h * 64 + l + 1];
-      s2 = s2 + d2 * xb[h * 64 + l + 2];
-      s3 = s3 + d3 * xb[h * 64 + l + 3];
+    const int r = tid & (kTrsvNB - 1), h = tid >> 7;   // h = 0..7: columns 16 h .. 16 h + 15
+    const dz *col = DT + (int64_t)(h * 16) * kTrsvNB + r;
+    dz d[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) d[l] = col[(int64_t)l * kTrsvNB];
+    dz s0 = mk(0, 0), s1 = mk(0, 0);
+#pragma unroll
+    for (int l = 0; l < 16; l += 2) {
+      s0 = s0 + d[l] * xb[h * 16 + l];
+      s1 = s1 + d[l + 1] * xb[h * 16 + l + 1];
     }
-    part[h][r] = (s0 + s1) + (s2 + s3);
+    part[h][r] = s0 + s1;
   }
   __syncthreads();
   if (tid < kTrsvNB) {
-    const dz z = part[0][tid] + part[1][tid];
+    dz z = part[0][tid];
+#pragma unroll
+    for (int h = 1; h < 8; ++h) z = z + part[h][tid];
     zb[tid] = tid < m ? z : mk(0, 0);
     if (blockIdx.x == 0 && tid < m) sol[b0 + tid] = z;
   }
@@ -318,29 +319,23 @@ __global__ __launch_bounds__(256) void k_trsv_step(const dz *__restrict__ F, int
     rhi = min(b0, rlo + kTrsvBlockRows);
   }
   const dz z0 = zb[lane], z1 = zb[lane + 64];
-  // wave w owns rows rlo + 16 w .. rlo + 16 w + 15, in two groups of eight
-  for (int g = 0; g < 2; ++g) {
-    const int i0 = rlo + 16 * wave + 8 * g;
-    dz s[8];
+  const int i0 = rlo + 4 * wave;
+  dz s[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int i = i0 + q;
-      s[q] = mk(0, 0);
-      if (i < rhi) {
-        const dz *Fi = F + (int64_t)i * ld + b0;
-        if (lane < m) s[q] = Fi[lane] * z0;
-        if (lane + 64 < m) s[q] = s[q] + Fi[lane + 64] * z1;
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + q;
+    s[q] = mk(0, 0);
+    if (i < rhi) {
+      const dz *Fi = F + (int64_t)i * ld + b0;
+      if (lane < m) s[q] = Fi[lane] * z0;
+      if (lane + 64 < m) s[q] = s[q] + Fi[lane + 64] * z1;
     }
+  }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s[q] = wave_sum(s[q]);
-    if (lane < 8 && i0 + lane < rhi) {
-      dz v = s[0];
-#pragma unroll
-      for (int q = 1; q < 8; ++q)
-        if (lane == q) v = s[q];
-      rhs[i0 + lane] = rhs[i0 + lane] - v;
-    }
+  for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
+  if (lane < 4 && i0 + lane < rhi) {
+    const dz v = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
+    rhs[i0 + lane] = rhs[i0 + lane] - v;
   }
 }
 

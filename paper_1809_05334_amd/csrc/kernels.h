@@ -11,23 +11,23 @@ __global__ void k_prep(int64_t nt, const TetFace *t2f, const TetGeom *tg, const 
                        double kx, double ky, double a, double b, dz *alpha, dz *gsrc, dz *kappa, dz *inv_eps);
 __global__ void k_sigma(int nc, const int32_t *ctp, const int32_t *ctm, const dz *kappa, dz *sigma);
 __global__ void k_zero(dz *p, int64_t n);
-__global__ void k_tt_far(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+__global__ void k_tt_far(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                          const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc, const dz *alpha,
                          const dz *gsrc, const dz *kappa, double k0sq9, dz *Z, int64_t ld);
-__global__ void k_tt_near(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+__global__ void k_tt_near(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                           const int32_t *lt, const int32_t *ls, const int32_t *lmask, int npairs, const dz *alpha,
                           const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, dz *Z, int64_t ld);
-__global__ void k_tet_face(const PgfTable *tab, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
+__global__ void k_tet_face(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                            const int32_t *test_list, int ntest, const FaceGeom *fg, int nface, const dz *alpha,
                            const dz *sigma, dz *Z, int64_t ld);
-__global__ void k_face_tet(const PgfTable *tab, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
+__global__ void k_face_tet(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                            int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
                            const dz *gsrc, const dz *kappa, dz *Z, int64_t ld);
-__global__ void k_face_face(const PgfTable *tab, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
+__global__ void k_face_face(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                             int nhalf, int nface, const dz *sigma, dz *Z, int64_t ld);
 __global__ void k_rhs(int64_t N, const int32_t *utet, const int32_t *uk, const TetGeom *tg, const QuadRules *qr,
                       const dz *alpha, double kix, double kiy, double kiz, double ex, double ey, double ez, dz *b);
-__global__ void k_pgf_probe(const PgfTable *tab, const double *d, int64_t n, dz *out);
+__global__ void k_pgf_probe(const double *pack, int packlen, const double *d, int64_t n, dz *out);
 __global__ void k_gather(const dz *Z, int64_t ld, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
 // block LU and its application (k_lu.hip)

@@ -406,9 +406,9 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
     double ph = kx * jb.m * a + ky * jb.n * b;
     im.cre = std::cos(ph) / (4 * kPi);
     im.cim = std::sin(ph) / (4 * kPi);
-    im.deg = cheb_fit(Ffull, jb.xlo, jb.xhi, 1e-16, 1e-15, im.f, kPgfMaxDeg);
+    im.deg = cheb_fit(Ffull, jb.xlo, jb.xhi, 1e-16, 1e-15, im.f, kPgfMaxDeg - 1);
     im.hdeg = -1;
-    if (jb.touching) im.hdeg = cheb_fit(Hx, jb.xlo, jb.xhi, 0.0, 1e-15, im.h, kPgfMaxDeg);
+    if (jb.touching) im.hdeg = cheb_fit(Hx, jb.xlo, jb.xhi, 0.0, 1e-15, im.h, kPgfMaxDeg - 1);
     if (im.deg < 0 || (jb.touching && im.hdeg < 0)) bad = 1;
   });
   if (bad) return "lattice-sum table: spatial fit did not converge";
@@ -438,7 +438,7 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
         for (int j = 0; j <= 16; ++j) kmax = std::max(kmax, (double)std::fabs(K(wmax * j / 16.0)));
         if (kmax < sig) return;  // deg stays -1
         md.cplx = 0;
-        md.deg = cheb_fit(K, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg);
+        md.deg = cheb_fit(K, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg - 1);
         if (md.deg < 0) bad = 1;
       } else {
         // propagating order: gamma = +j beta
@@ -451,14 +451,49 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
           return pref * (e1 * erfc_l(zl(v, bl)) + e2 * erfc_l(zl(-v, bl)));
         };
         md.cplx = 1;
-        int d1 = cheb_fit([&](double w) { return Kc(w).real(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg);
-        int d2 = cheb_fit([&](double w) { return Kc(w).imag(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kim, kPgfMaxDeg);
+        int d1 = cheb_fit([&](double w) { return Kc(w).real(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg - 1);
+        int d2 = cheb_fit([&](double w) { return Kc(w).imag(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kim, kPgfMaxDeg - 1);
         if (d1 < 0 || d2 < 0) bad = 1;
         md.deg = std::max(d1, d2);
       }
     });
   if (bad) return "lattice-sum table: spectral fit did not converge";
   return "";
+}
+
+// ---------------------------------------------------------------- packing
+void pack_pgf_table(const PgfTable &tab, std::vector<double> &out) {
+  auto pad4 = [](int n) { return (n + 3) & ~3; };
+  out.assign(kPackImages, 0.0);
+  const double hdr[10] = {tab.E, tab.a, tab.b, tab.inv_a, tab.inv_b, tab.kx, tab.ky, tab.two_pi_a, tab.two_pi_b, tab.ws};
+  for (int i = 0; i < 10; ++i) out[i] = hdr[i];
+  for (int i = 0; i < 9; ++i) {
+    out[10 + i] = tab.ph0re[i];
+    out[19 + i] = tab.ph0im[i];
+  }
+  out[28] = tab.nimg;
+  for (int i = 0; i < tab.nimg; ++i) {
+    const PgfImage &im = tab.img[i];
+    const int K = pad4(im.deg), HK = im.hdeg >= 0 ? pad4(im.hdeg) : -1;
+    const size_t start = out.size();
+    out.insert(out.end(), {im.xa, im.xs, im.cre, im.cim, (double)im.m, (double)im.n, (double)K, 0.0});
+    for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= im.deg ? im.f[k] : 0.0);
+    if (HK >= 0) {
+      out.insert(out.end(), {(double)HK, 0.0, 0.0, 0.0});
+      for (int k = 0; k < pad4(HK + 1); ++k) out.push_back(k <= im.hdeg ? im.h[k] : 0.0);
+    }
+    out[start + 7] = (double)(out.size() - start);
+  }
+  for (int idx = 0; idx < kPgfTerms; ++idx) {
+    const PgfMode &md = tab.mode[idx];
+    if (md.deg < 0) continue;
+    const int K = pad4(md.deg);
+    out[32 + idx] = (double)out.size();
+    out.insert(out.end(), {(double)K, (double)md.cplx, 0.0, 0.0});
+    for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kre[k] : 0.0);
+    if (md.cplx)
+      for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kim[k] : 0.0);
+  }
 }
 
 }  // namespace vie
