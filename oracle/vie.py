@@ -27,7 +27,7 @@ cos th sin ph, sin th), |E0| = 1.
 
 Quadrature (readings): elements that share no vertex under any lattice image
 use degree-2 product rules (tet 4 points, triangle 3 points); touching
-elements use a degree-5 outer rule on the test element (tet 27 points,
+elements use a degree-5 outer rule on the test element (tet 14 points,
 triangle 7 points), the closed-form 1/R and (r'-r)/R integrals for every
 touching image, and the degree-2 inner rule for the remainder
 g_p - sum_near e^{j kt.rho}/(4 pi R).
@@ -79,15 +79,15 @@ class Elements:
         self.charged = topo.charged
         self.slot_of_face = {int(n): i for i, n in enumerate(topo.charged)}
         lam4, w4 = Q.tet_deg2()
-        lam27, w27 = Q.tet_deg5()
+        lam5, w5 = Q.tet_deg5()
         lam3, w3 = Q.tri_deg2()
         lam7, w7 = Q.tri_deg5()
         tv = topo.verts[topo.tets]                       # [nt,4,3]
         self.tet_verts = tv
         self.tet_far_pts = np.einsum("qk,tkd->tqd", lam4, tv)
         self.tet_far_w = w4[None, :] * topo.vol[:, None]
-        self.tet_near_pts = np.einsum("qk,tkd->tqd", lam27, tv)
-        self.tet_near_w = w27[None, :] * topo.vol[:, None]
+        self.tet_near_pts = np.einsum("qk,tkd->tqd", lam5, tv)
+        self.tet_near_w = w5[None, :] * topo.vol[:, None]
         fv = topo.verts[topo.face_vid[topo.charged]] if len(topo.charged) else np.zeros((0, 3, 3))
         self.face_verts = fv
         area = topo.area[topo.charged]
@@ -393,7 +393,7 @@ def assemble(topo, wave, eps_in, rows=None, cols=None, M=4, E=None, verbose=Fals
 def rhs(topo, wave, pol, rows=None):
     """b_m = <f_m, E^i> with the degree-5 tetrahedron rule."""
     N = topo.N
-    lam27, w27 = Q.tet_deg5()
+    lam5, w5 = Q.tet_deg5()
     e = wave.pol_vector(pol)
     L = np.array([topo.a, topo.b])
     kt = np.array([wave.kx, wave.ky])
@@ -401,11 +401,11 @@ def rhs(topo, wave, pol, rows=None):
     b = np.zeros(N, complex)
     for t in range(len(topo.tets)):
         v4 = topo.verts[topo.tets[t]]
-        X = lam27 @ v4
+        X = lam5 @ v4
         Ei = np.exp(-1j * (X @ wave.kinc))[:, None] * e[None, :]
         for k in range(4):
             m = topo.t2f[t, k]
-            val = np.sum(w27 * topo.vol[t] * np.einsum("qd,qd->q", X - v4[k], Ei))
+            val = np.sum(w5 * topo.vol[t] * np.einsum("qd,qd->q", X - v4[k], Ei))
             b[m] += chi[t, k] * topo.t2s[t, k] * topo.area[m] / (3.0 * topo.vol[t]) * val
     return b if rows is None else b[rows]
 
@@ -510,12 +510,12 @@ def reflect_transmit(topo, wave, eps_in, x, pol, P=4):
     eps = internal_eps(eps_in)
     kappa = 1.0 - 1.0 / eps
     c = tet_field_coeffs(topo, wave, x)
-    lam27, w27 = Q.tet_deg5()
+    lam5, w5 = Q.tet_deg5()
     k0, a, b = wave.k0, topo.a, topo.b
     e_inc = wave.pol_vector(pol)
     beta00 = k0 * np.cos(wave.theta)
-    pts = np.einsum("qk,tkd->tqd", lam27, topo.verts[topo.tets])          # [nt,27,3]
-    wts = w27[None, :] * topo.vol[:, None]
+    pts = np.einsum("qk,tkd->tqd", lam5, topo.verts[topo.tets])          # [nt,14,3]
+    wts = w5[None, :] * topo.vol[:, None]
     # D~ at the points: sum_k c_k (X - v_k)
     D = np.einsum("tk,tqkd->tqd", c, pts[:, :, None, :] - topo.verts[topo.tets][:, None, :, :])
     Pt = kappa[:, None, None] * D
