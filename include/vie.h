@@ -165,6 +165,12 @@ int vie_read_solution(const vie_ctx *ctx, vie_c128 *x);
  * out [n].  Needs a bound workspace and a completed fill. */
 int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *out);
 
+/* z = M^{-1} v for the block-diagonal preconditioner of the last
+ * vie_precond_factor (Sec. 2.3, Eq. 6: M = blockdiag(A_dd)); v, z [N] host
+ * vectors in unknown order.  Clobbers the solver's work vectors but not the
+ * last solution or right-hand side.  VIE_ESTATE before a factorisation. */
+int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z);
+
 /* Residual history (estimate / ||b||) of the last solve; returns the count
  * written (at most cap). */
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);

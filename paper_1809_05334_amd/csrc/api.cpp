@@ -35,7 +35,7 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, F, ipiv, perm, rpiv, info, dinv;
+  Region Z, F, ipiv, perm, rpiv, info, dinv, tpart, tcount;
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
@@ -159,6 +159,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
   }
   put(L.dinv, 16 * (size_t)std::max<int64_t>(1, del));
+  put(L.tpart, 16 * (size_t)kTrsvGroupsH * kTrsvNB * std::max(1, t.ndom));
+  put(L.tcount, 4 * (size_t)std::max(1, t.ndom));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
   put(L.rpiv, 16);
@@ -369,6 +371,8 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   rc |= up(L.near_m, nm_.data(), 4 * nm_.size());
   rc |= up(L.quad, &ctx->quad, sizeof(QuadRules));
   if (rc) return rc;
+  // the triangular-solve step counter starts (and always ends) at zero
+  HIPCK(hipMemsetAsync(ctx->ws + L.tcount.off, 0, L.tcount.bytes, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
   ctx->state = S_BOUND;
   return VIE_OK;
@@ -581,35 +585,79 @@ namespace {
 
 // out = M^{-1} v  (block-diagonal LU solves); uses vt, vu as scratch when
 // out differs from them.
+// z = M^{-1} v for the block-diagonal preconditioner: per domain, permute by
+// the pivots, then L y = P v and U z = y by blocked triangular solves.  Each
+// k_trsv_step launch advances every domain (up to kTrsvMaxDom per launch) by
+// one diagonal block, so the launch count follows the largest domain.
 int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   const dz *F = ctx->ptr<dz>(L.F);
   const int32_t *perm = ctx->ptr<int32_t>(L.perm);
   int64_t poff = 0;
+  int maxnbk = 0;
   for (int d = 0; d < t.ndom; ++d) {
     const int n = (int)(t.dend[d] - t.dstart[d]);
-    if (n == 0) continue;
-    const int64_t off = t.dstart[d];
-    const dz *A = F + L.foff[d];
-    const int64_t ldf = L.fld[d];
-    hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, off, perm + poff, v, s1);
-    const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
-    const dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
-    const dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
-    // L y = P v: rhs s1 (updated in place), solution s2; then U x = y: rhs s2, solution out
-    for (int bk = 0; bk < nbk; ++bk) {
-      const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
-      const int rest = n - b0 - m;
-      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(rest, kTrsvBlockRowsH)), dim3(1024), 0, ctx->stream, A, ldf, n, b0, m,
-                         1, DL + (int64_t)bk * kTrsvNB * kTrsvNB, s1 + off, s2 + off);
-    }
-    for (int bk = nbk - 1; bk >= 0; --bk) {
-      const int b0 = bk * kTrsvNB, m = std::min(kTrsvNB, n - b0);
-      hipLaunchKernelGGL(k_trsv_step, dim3(nblk(b0, kTrsvBlockRowsH)), dim3(1024), 0, ctx->stream, A, ldf, n, b0, m, 0,
-                         DU + (int64_t)bk * kTrsvNB * kTrsvNB, s2 + off, out + off);
-    }
+    if (n > 0)
+      hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, (int64_t)t.dstart[d],
+                         perm + poff, v, s1);
     poff += n;
+    maxnbk = std::max(maxnbk, (n + kTrsvNB - 1) / kTrsvNB);
+  }
+  dz *part = ctx->ptr<dz>(L.tpart);
+  int *cnt = ctx->ptr<int>(L.tcount);
+  // L sweep: rhs s1 (updated in place), solution s2; U sweep: rhs s2, solution out.
+  for (int lower = 1; lower >= 0; --lower) {
+    for (int k = 0; k < maxnbk; ++k) {
+      TrsvStep st{};
+      st.lower = lower;
+      int blocks = 0;
+      auto flush = [&]() {
+        if (st.ndom == 0) return;
+        hipLaunchKernelGGL(k_trsv_step, dim3(blocks), dim3(1024), 0, ctx->stream, st);
+        st.ndom = 0;
+        blocks = 0;
+      };
+      for (int d = 0; d < t.ndom; ++d) {
+        const int n = (int)(t.dend[d] - t.dstart[d]);
+        const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
+        if (k >= nbk) continue;
+        const int64_t off = t.dstart[d];
+        const dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
+        TrsvDom &D = st.d[st.ndom];
+        D.F = F + L.foff[d];
+        D.ld = L.fld[d];
+        D.n = n;
+        D.part = part + (int64_t)d * kTrsvGroupsH * kTrsvNB;
+        D.counter = cnt + d;
+        D.first_block = blocks;
+        int rest;
+        if (lower) {
+          const int bk = k;
+          D.nb0 = bk * kTrsvNB;
+          D.nm = std::min(kTrsvNB, n - D.nb0);
+          D.cb0 = bk > 0 ? D.nb0 - kTrsvNB : 0;
+          D.cm = bk > 0 ? kTrsvNB : 0;
+          D.DT = DL + (int64_t)bk * kTrsvNB * kTrsvNB;
+          D.rhs = s1 + off;
+          D.sol = s2 + off;
+          rest = D.cm > 0 ? n - D.nb0 - D.nm : 0;
+        } else {
+          const int bk = nbk - 1 - k;
+          D.nb0 = bk * kTrsvNB;
+          D.nm = std::min(kTrsvNB, n - D.nb0);
+          D.cb0 = k > 0 ? D.nb0 + kTrsvNB : 0;
+          D.cm = k > 0 ? std::min(kTrsvNB, n - D.cb0) : 0;
+          D.DT = DL + (int64_t)(nbk + bk) * kTrsvNB * kTrsvNB;
+          D.rhs = s2 + off;
+          D.sol = out + off;
+          rest = D.cm > 0 ? D.nb0 : 0;
+        }
+        blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, kTrsvBlockRowsH) : 0);
+        if (++st.ndom == kTrsvMaxDom) flush();
+      }
+      flush();
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "preconditioner apply: %s", hipGetErrorString(e));
@@ -976,6 +1024,20 @@ int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec) {
   float ms = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev2, ctx->ev3));
   *ms_per_matvec = ms / reps;
+  return VIE_OK;
+}
+
+int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z) {
+  if (int r = check(ctx, S_FACTORED, "vie_precond_apply")) return r;
+  if (!v || !z) return fail(ctx, VIE_EINVAL, "null vector");
+  HIPCK(hipSetDevice(ctx->device));
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  dz *in = ctx->ptr<dz>(L.vw), *out = ctx->ptr<dz>(L.vz);
+  HIPCK(hipMemcpyAsync(in, v, 16 * N, hipMemcpyHostToDevice, ctx->stream));
+  if (int rc = apply_minv(ctx, in, out, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vr))) return rc;
+  HIPCK(hipMemcpyAsync(z, out, 16 * N, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
 }
 

@@ -229,7 +229,7 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
 // inv(T_bb)^T row-major (nb x nb), T_bb the diagonal block at row b*nb.  One
 // thread block per diagonal block; thread j forms column j of the inverse
 // (row j of DT, contiguous) by substitution.
-__global__ __launch_bounds__(128) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb, int lower,
+__global__ __launch_bounds__(kTrsvNB) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb, int lower,
                                                   dz *__restrict__ DT) {
   const int b = blockIdx.x;
   const int b0 = b * nb;
@@ -269,73 +269,138 @@ __device__ __forceinline__ dz wave_sum(dz v) {
   return v;
 }
 
-// One block-column step of a blocked triangular solve.  On entry rows
-// [b0, b0+m) of rhs are final.  Every thread block (16 waves) forms
-// z_b = inv(T_bb) rhs_b: the 128 x 128 product with the transposed inverse
-// is split eight ways per row (16 independent, coalesced loads per thread),
-// thread block 0 stores z_b into sol, and each block then subtracts
-// T[i, b0:b0+m] z_b from its 64 rows still to be solved (below the block for
-// L, above it for U), four rows per wave with all loads issued together.
-constexpr int kTrsvBlockRows = 64;
+// One step of the blocked triangular solves (L forward or U backward) of
+// every material domain at once, with nb = kTrsvNB diagonal blocks whose
+// transposed inverses DT are precomputed.  Domain d's part of the launch:
+//
+// On entry the solution of its column block [cb0, cb0+cm) is final in sol
+// (cm = 0 on the first step) and the rows of its next diagonal block
+// [nb0, nb0+nm) have received every update except the one from that column
+// block.  The launch
+//   (a) subtracts T[i, cb0:cb0+cm] z_c from every row i still to be solved
+//       (below the column block for L, above it for U), and
+//   (b) solves the next diagonal block: z_n = inv(T_nn) rhs_n.
+// The first kTrsvGroupsH thread blocks of the domain own 16 rows each of the
+// next diagonal block: after updating them they form the partial product
+// inv(T_nn)[:, 16g:16g+16] r_g into part[g][:], and the last of them to
+// finish (agent-scope acq_rel counter; nothing waits on it) sums the partials
+// into sol and puts the counter back to zero.  The domain's further thread
+// blocks update the remaining rows, 64 per block, four rows per wave.
+constexpr int kTrsvGroups = kTrsvGroupsH;
+constexpr int kTrsvBlockRows = kTrsvBlockRowsH;
+constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
 
-__global__ __launch_bounds__(1024) void k_trsv_step(const dz *__restrict__ F, int64_t ld, int n, int b0, int m,
-                                                    int lower, const dz *__restrict__ DT, dz *__restrict__ rhs,
-                                                    dz *__restrict__ sol) {
-  __shared__ dz xb[kTrsvNB];
-  __shared__ dz part[8][kTrsvNB];
-  __shared__ dz zb[kTrsvNB];
+__device__ __forceinline__ dz row_dot(const dz *__restrict__ Fi, int cm, const dz *zc, int lane) {
+  dz f[kTrsvCol];
+#pragma unroll
+  for (int c = 0; c < kTrsvCol; ++c) f[c] = lane + 64 * c < cm ? Fi[lane + 64 * c] : mk(0, 0);
+  dz s = mk(0, 0);
+#pragma unroll
+  for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[lane + 64 * c];
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_trsv_step(TrsvStep st) {
+  __shared__ dz zc[kTrsvNB];
+  __shared__ dz rg[16];
+  __shared__ dz red[4][kTrsvNB];
+  __shared__ int last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < kTrsvNB) xb[tid] = tid < m ? rhs[b0 + tid] : mk(0, 0);
-  __syncthreads();
-  {
-    const int r = tid & (kTrsvNB - 1), h = tid >> 7;   // h = 0..7: columns 16 h .. 16 h + 15
-    const dz *col = DT + (int64_t)(h * 16) * kTrsvNB + r;
-    dz d[16];
+  int d = 0;
+  while (d + 1 < st.ndom && (int)blockIdx.x >= st.d[d + 1].first_block) ++d;
+  const TrsvDom &D = st.d[d];
+  const int blk = blockIdx.x - D.first_block;
+  const int cb0 = D.cb0, cm = D.cm, nb0 = D.nb0, nm = D.nm;
+  const int64_t ld = D.ld;
+  if (tid < kTrsvNB) zc[tid] = tid < cm ? D.sol[cb0 + tid] : mk(0, 0);
+  if (blk < kTrsvGroups) {
+    const int g = blk;
+    // independent loads first: the row of group g this wave updates, its rhs,
+    // and this thread's four entries of the DT slice
+    const int r = 16 * g + wave;
+    const int i = nb0 + r;
+    dz f[kTrsvCol];
+    dz rv = mk(0, 0);
+    if (r < nm) {
+      rv = D.rhs[i];
 #pragma unroll
-    for (int l = 0; l < 16; ++l) d[l] = col[(int64_t)l * kTrsvNB];
-    dz s0 = mk(0, 0), s1 = mk(0, 0);
-#pragma unroll
-    for (int l = 0; l < 16; l += 2) {
-      s0 = s0 + d[l] * xb[h * 16 + l];
-      s1 = s1 + d[l + 1] * xb[h * 16 + l + 1];
+      for (int c = 0; c < kTrsvCol; ++c)
+        f[c] = lane + 64 * c < cm ? D.F[(int64_t)i * ld + cb0 + lane + 64 * c] : mk(0, 0);
     }
-    part[h][r] = s0 + s1;
-  }
-  __syncthreads();
-  if (tid < kTrsvNB) {
-    dz z = part[0][tid];
+    const int oi = tid & (kTrsvNB - 1), h = tid >> 8;   // h = 0..3 takes columns 16 g + 4 h .. + 3
+    const dz *col = D.DT + (int64_t)(16 * g + 4 * h) * kTrsvNB + oi;
+    dz dt[4];
 #pragma unroll
-    for (int h = 1; h < 8; ++h) z = z + part[h][tid];
-    zb[tid] = tid < m ? z : mk(0, 0);
-    if (blockIdx.x == 0 && tid < m) sol[b0 + tid] = z;
+    for (int l = 0; l < 4; ++l) dt[l] = col[(int64_t)l * kTrsvNB];
+    __syncthreads();
+    // (a) for the 16 rows of group g, one row per wave
+    {
+      dz s = mk(0, 0);
+#pragma unroll
+      for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[lane + 64 * c];
+      s = wave_sum(s);
+      if (lane == 0) rg[wave] = r < nm ? rv - s : mk(0, 0);
+    }
+    __syncthreads();
+    // (b) partial product with columns 16 g .. 16 g + 15 of inv(T_nn)
+    red[h][oi] = dt[0] * rg[4 * h] + dt[1] * rg[4 * h + 1] + dt[2] * rg[4 * h + 2] + dt[3] * rg[4 * h + 3];
+    __syncthreads();
+    if (tid < kTrsvNB) {
+      const dz z = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      D.part[g * kTrsvNB + tid] = z;
+      __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const int old = __hip_atomic_fetch_add(D.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      last = old == kTrsvGroups - 1;
+    }
+    __syncthreads();
+    if (last) {
+      __threadfence();
+      if (tid < nm) {
+        dz p[kTrsvGroups];
+#pragma unroll
+        for (int q = 0; q < kTrsvGroups; ++q) p[q] = D.part[q * kTrsvNB + tid];
+        dz z = mk(0, 0);
+#pragma unroll
+        for (int q = 0; q < kTrsvGroups; ++q) z = z + p[q];
+        D.sol[nb0 + tid] = z;
+      }
+      if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
   }
-  __syncthreads();
+  // (a) for the rows outside the next diagonal block
   int rlo, rhi;
-  if (lower) {
-    rlo = b0 + m + blockIdx.x * kTrsvBlockRows;
-    rhi = min(n, rlo + kTrsvBlockRows);
+  if (st.lower) {
+    rlo = nb0 + nm + (blk - kTrsvGroups) * kTrsvBlockRows;
+    rhi = min(D.n, rlo + kTrsvBlockRows);
   } else {
-    rlo = blockIdx.x * kTrsvBlockRows;
-    rhi = min(b0, rlo + kTrsvBlockRows);
+    rlo = (blk - kTrsvGroups) * kTrsvBlockRows;
+    rhi = min(nb0, rlo + kTrsvBlockRows);
   }
-  const dz z0 = zb[lane], z1 = zb[lane + 64];
   const int i0 = rlo + 4 * wave;
+  dz f[4][kTrsvCol];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < kTrsvCol; ++c)
+      f[q][c] = (i0 + q < rhi && lane + 64 * c < cm) ? D.F[(int64_t)(i0 + q) * ld + cb0 + lane + 64 * c] : mk(0, 0);
+  __syncthreads();
   dz s[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int i = i0 + q;
     s[q] = mk(0, 0);
-    if (i < rhi) {
-      const dz *Fi = F + (int64_t)i * ld + b0;
-      if (lane < m) s[q] = Fi[lane] * z0;
-      if (lane + 64 < m) s[q] = s[q] + Fi[lane + 64] * z1;
-    }
+#pragma unroll
+    for (int c = 0; c < kTrsvCol; ++c) s[q] = s[q] + f[q][c] * zc[lane + 64 * c];
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
   if (lane < 4 && i0 + lane < rhi) {
     const dz v = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
-    rhs[i0 + lane] = rhs[i0 + lane] - v;
+    D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
   }
 }
 

@@ -31,8 +31,7 @@ __global__ void k_pgf_probe(const double *pack, int packlen, const double *d, in
 __global__ void k_gather(const dz *Z, int64_t ld, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
 // block LU and its application (k_lu.hip)
-constexpr int kTrsvNB = 128;
-constexpr int kTrsvRows = 64;
+constexpr int kTrsvNB = 256;
 __global__ void k_copy_block(const dz *Z, int64_t ldz, int64_t start, int n, dz *A, int64_t lda);
 __global__ void k_lu_pivot(dz *A, int64_t ld, int n, int j, int k0, int jb, int32_t *ipiv, dz *rpiv, int32_t *info);
 __global__ void k_lu_col(dz *A, int64_t ld, int n, int j, int k0, int jb, const dz *rpiv);
@@ -42,8 +41,25 @@ __global__ void k_lu_gemm(dz *A, int64_t ld, int n, int k0, int jb);
 __global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
-constexpr int kTrsvBlockRowsH = 64;   // rows updated per thread block in k_trsv_step
-__global__ void k_trsv_step(const dz *F, int64_t ld, int n, int b0, int m, int lower, const dz *DT, dz *rhs, dz *sol);
+// One launch advances the blocked triangular solves of up to kTrsvMaxDom
+// domains by one diagonal block each (k_lu.hip).
+constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
+constexpr int kTrsvBlockRowsH = 64;          // rows updated per further thread block
+constexpr int kTrsvMaxDom = 8;
+struct TrsvDom {
+  const dz *F;        // the domain's LU factors (row-major, leading dimension ld)
+  const dz *DT;       // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB)
+  dz *rhs, *sol;      // right-hand side (updated in place) and solution, domain-local
+  dz *part;           // kTrsvGroupsH x kTrsvNB partial products
+  int *counter;       // zero between launches
+  int64_t ld;
+  int n, cb0, cm, nb0, nm, first_block;
+};
+struct TrsvStep {
+  TrsvDom d[kTrsvMaxDom];
+  int ndom, lower;
+};
+__global__ void k_trsv_step(TrsvStep st);
 
 // Krylov (k_krylov.hip)
 constexpr int kMvRPW = 4;

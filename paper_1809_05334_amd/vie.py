@@ -76,6 +76,7 @@ _SIGS = {
     "vie_residual_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
     "vie_bench_matvec": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
+    "vie_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -236,6 +237,13 @@ class Solver:
         st = FillStats()
         self._ck(self.lib.vie_get_fill_stats(self.h, C.byref(st)))
         return st.as_dict()
+
+    def precond_apply(self, v):
+        """z = M^{-1} v with the block-diagonal preconditioner of the last factor()."""
+        vin = np.ascontiguousarray(v, np.complex128)
+        out = np.zeros(self.num_unknowns(), np.complex128)
+        self._ck(self.lib.vie_precond_apply(self.h, _p(vin), _p(out)))
+        return out
 
     def bench_matvec(self, reps=10):
         ms = C.c_double()
