@@ -8,9 +8,12 @@ graded Kuhn brick mesh (5 nm over the sphere span and the spacer, 20 nm
 elsewhere): 18,432 tetrahedra, N = 37,376 unknowns, three material domains.
 
 One step = one wavelength of the 41-point sweep (visited with stride 7,
-starting at 450 nm): fill Z (FP64), factor the
-three diagonal blocks, right-preconditioned GMRES for TE and TM, absorptance
-per domain and R/T for each -> 2 solves.  Inputs are resident on the device
+starting at 450 nm): fill Z, factor the three diagonal blocks,
+right-preconditioned GMRES for TE and TM, absorptance per domain and R/T for
+each -> 2 solves.  The same steps run on the mixed-precision path (far part
+of Z stored in complex FP32, touching-pair terms in FP64; `value`) and on the
+FP64 path (`fp64`), and the largest absorptance/R/T difference between the
+two is reported.  Inputs are resident on the device
 when the timed region starts (the mesh tables are uploaded at bind time; the
 41 permittivity vectors are host arrays of 18,432 complex values, part of
 each fill call).
@@ -118,94 +121,119 @@ def main():
     mesh = W.config2_mesh()
     lams = np.linspace(400.0, 800.0, 41)
     eps_all = [W.osc_eps(mesh, l) for l in lams]
-    s = vie.Solver(0)
-    N = s.upload_mesh(mesh)
-    ws_bytes = s.bind(vie.VIE_FP64, args.restart)
-    stream = s.stream
 
-    lat = []
-    stages = []
-    fills = []
-    absorb = None
+    def run_path(precision):
+        """Warm-up + timed sweep steps on one solver; returns its record."""
+        s = vie.Solver(0)
+        N = s.upload_mesh(mesh)
+        ws_bytes = s.bind(precision, args.restart)
+        lat, stages, fills, results = [], [], [], []
 
-    def step(i):
-        # sweep order: stride 7 through the 41 wavelengths (starts at 450 nm)
-        nonlocal absorb
-        k = (5 + 7 * i) % len(lams)
+        def step(i):
+            # sweep order: stride 7 through the 41 wavelengths (starts at 450 nm)
+            k = (5 + 7 * i) % len(lams)
+            t0 = time.perf_counter()
+            s.fill(lams[k], 0.0, 0.0, eps_all[k])
+            fills.append(s.fill_stats())
+            s.factor()
+            out = {}
+            for pol in (vie.VIE_TE, vie.VIE_TM):
+                info = s.solve(pol, tol=args.tol, max_iter=args.max_iter, restart=args.restart, allow_noconv=True)
+                A, R, T = s.absorption()
+                out[pol] = (info, A, R, T)
+                lat.append((time.perf_counter() - t0) * 1e3)
+            results.append({"lambda_nm": float(lams[k]),
+                            "A": [out[p][1].tolist() for p in (0, 1)],
+                            "R": [out[p][2] for p in (0, 1)], "T": [out[p][3] for p in (0, 1)]})
+            stages.append({"fill_ms": out[0][0]["t_fill_ms"], "factor_ms": out[0][0]["t_factor_ms"],
+                           "solve_ms": [out[p][0]["t_solve_ms"] for p in (0, 1)],
+                           "iters": [out[p][0]["iters"] for p in (0, 1)],
+                           "converged": [out[p][0]["converged"] for p in (0, 1)]})
+            name = "mixed" if precision == vie.VIE_MIXED_FP32 else "fp64"
+            print(f"{name} step {i}: lambda {lams[k]:.0f} nm  {json.dumps(stages[-1])}", file=sys.stderr, flush=True)
+
+        print(f"bench: N={N}, precision {precision}, workspace {ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
+        for i in range(args.warmup):
+            step(i)
+        lat.clear(); stages.clear(); fills.clear(); results.clear()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.fill(lams[k], 0.0, 0.0, eps_all[k])
-        fills.append(s.fill_stats())
-        s.factor()
-        out = {}
-        for pol in (vie.VIE_TE, vie.VIE_TM):
-            info = s.solve(pol, tol=args.tol, max_iter=args.max_iter, restart=args.restart, allow_noconv=True)
-            A, R, T = s.absorption()
-            out[pol] = (info, A, R, T)
-            lat.append((time.perf_counter() - t0) * 1e3)
-        absorb = {"lambda_nm": float(lams[k]), "A_TE": out[0][1].tolist(), "R_TE": out[0][2], "T_TE": out[0][3]}
-        stages.append({"fill_ms": out[0][0]["t_fill_ms"], "factor_ms": out[0][0]["t_factor_ms"],
-                       "solve_ms": [out[p][0]["t_solve_ms"] for p in (0, 1)],
-                       "iters": [out[p][0]["iters"] for p in (0, 1)],
-                       "converged": [out[p][0]["converged"] for p in (0, 1)]})
-        print(f"step {i}: lambda {lams[k]:.0f} nm  {json.dumps(stages[-1])}", file=sys.stderr, flush=True)
+        for i in range(args.steps):
+            step(args.warmup + i)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mv_ms = s.bench_matvec(10)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        return {"N": N, "ws_bytes": ws_bytes, "dt": dt, "lat": lat, "stages": stages, "fills": fills,
+                "results": results, "mv_ms": mv_ms}
 
-    print(f"bench: N={N}, workspace {ws_bytes / 1e9:.1f} GB", file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        step(i)
-    lat.clear(); stages.clear(); fills.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    mixed = run_path(vie.VIE_MIXED_FP32)
+    fp64 = run_path(vie.VIE_FP64)
+    N = mixed["N"]
     nsolves = 2 * args.steps
+    dA = 0.0
+    for rm, rf in zip(mixed["results"], fp64["results"]):
+        for p in (0, 1):
+            dA = max(dA, float(np.max(np.abs(np.array(rm["A"][p]) - np.array(rf["A"][p])))),
+                     abs(rm["R"][p] - rf["R"][p]), abs(rm["T"][p] - rf["T"][p]))
 
-    fs = fills[-1]
-    # far-kernel rate over every fill of the timed region (HIP events around
-    # the far launches inside each fill)
-    far_flops = sum(f["far_flops"] for f in fills)
-    far_ms = sum(f["t_far_ms"] for f in fills)
-    far_launches = sum(f["far_launches"] for f in fills)
+    def far_rate(fills):
+        flops = sum(f["far_flops"] for f in fills)
+        ms = sum(f["t_far_ms"] for f in fills)
+        launches = sum(f["far_launches"] for f in fills)
+        return flops, ms, launches
+
+    # dominant kernel of the headline (mixed) path: the far tet-pair fill kernel
+    far_flops, far_ms, far_launches = far_rate(mixed["fills"])
     far_tflops = far_flops / (far_ms * 1e-3) / 1e12
-    mv_ms = s.bench_matvec(10)
-    mv_bytes = 16.0 * N * N + 32.0 * N
-    mv_gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
-    # the bench's dominant kernel family: the far tet-pair fill kernel
+    f64_flops, f64_ms, _ = far_rate(fp64["fills"])
+    mv32_bytes = 8.0 * N * N + 32.0 * N
+    mv64_bytes = 16.0 * N * N + 32.0 * N
+    mv32_gbs = mv32_bytes / (mixed["mv_ms"] * 1e-3) / 1e9
+    mv64_gbs = mv64_bytes / (fp64["mv_ms"] * 1e-3) / 1e9
     roofline = {"bound": "alu", "kernel": "k_tt_far", "achieved": far_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": far_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": far_traffic(),
                 "traffic_unit": "bytes per launch", "launches": far_launches,
                 "flops_per_launch": far_flops / far_launches, "avg_launch_ms": far_ms / far_launches}
     res = {
-        "metric": "solves/s (FP64 path); p50/p99 latency; fill GFLOP/s; matvec GB/s",
-        "value": nsolves / dt,
+        "metric": "solves/s (mixed FP32/FP64 path) vs FP64 path at dA<=1e-4; p50/p99 latency; fill GFLOP/s; "
+                  "matvec GB/s",
+        "value": nsolves / mixed["dt"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": mixed["dt"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 arithmetic, far Z stored c64",
         "data": "synthetic",
         "config": {"workload": "plasmonic OSC cell 200x200 nm, Ag sphere r=20 nm, N=%d, 400-800 nm sweep, "
                                "normal incidence, TE+TM per step" % N,
                    "unknowns": N, "tets": int(mesh.nt), "restart": args.restart, "tol": args.tol,
-                   "workspace_gb": ws_bytes / 1e9},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                   "workspace_gb": mixed["ws_bytes"] / 1e9},
+        "latency_ms": {"p50": float(np.percentile(mixed["lat"], 50)), "p99": float(np.percentile(mixed["lat"], 99))},
         "fill_gflops": far_tflops * 1e3,
-        "matvec_gbs": mv_gbs,
-        "matvec_frac_hbm": mv_gbs / HBM_PEAK_GBS,
-        "stages": stages,
-        "fill_stats": fs,
-        "result": absorb,
+        "matvec_gbs": mv32_gbs,
+        "matvec_frac_hbm": mv32_gbs / HBM_PEAK_GBS,
+        "dA_mixed_vs_fp64": dA,
+        "fp64": {"value": nsolves / fp64["dt"], "ms_per_step": fp64["dt"] / args.steps * 1e3,
+                 "latency_ms": {"p50": float(np.percentile(fp64["lat"], 50)),
+                                "p99": float(np.percentile(fp64["lat"], 99))},
+                 "fill_gflops": f64_flops / (f64_ms * 1e-3) / 1e9, "matvec_gbs": mv64_gbs,
+                 "matvec_frac_hbm": mv64_gbs / HBM_PEAK_GBS, "workspace_gb": fp64["ws_bytes"] / 1e9,
+                 "stages": fp64["stages"]},
+        "stages": mixed["stages"],
+        "fill_stats": mixed["fills"][-1],
+        "result": mixed["results"][-1],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         print("cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(mesh, float(lams[0]))
-    s.close()
     print(json.dumps(res))
 
 

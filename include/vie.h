@@ -64,17 +64,23 @@ typedef enum {
 
 enum { VIE_TE = 0, VIE_TM = 1 };
 
-/* Arithmetic of the impedance matrix and the Krylov solve.
- * VIE_FP64: everything in FP64.
- * VIE_MIXED_FP32: Z stored and multiplied in complex FP32, GMRES inner solve in
- *   FP32 with the block preconditioner factored in FP32, inside an FP64
- *   iterative-refinement loop whose residual uses the FP64 near-field terms. */
+/* Storage precision of the impedance matrix.
+ * VIE_FP64: Z dense in complex FP64 (16 bytes per entry).
+ * VIE_MIXED_FP32: the far part of Z dense in complex FP32 (8 bytes per
+ *   entry); every contribution of a touching element pair (singularity-
+ *   extracted self and neighbour integrals, near-field Ewald remainders, the
+ *   mass term) kept in FP64 in a sparse part over the touching-pair pattern.
+ *   Products with Z, the preconditioner (factored in FP64 from that operator),
+ *   the Krylov basis, Hessenberg/Givens updates and the true residual that
+ *   closes every restart cycle all run in FP64 arithmetic on the mixed
+ *   operator, so the solve converges to the tolerance of that operator; its
+ *   difference from the FP64 Z is the FP32 rounding of far entries. */
 enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1 };
 
 typedef struct {
   int iters;                 /* total GMRES iterations (all restarts, all refinement steps) */
   int restarts;              /* GMRES restarts */
-  int refine_steps;          /* outer refinement steps (mixed precision), 1 for FP64 */
+  int refine_steps;          /* restart cycles, each closed by an FP64 true residual b - Z x */
   double true_rel_residual;  /* ||b - Z x|| / ||b|| recomputed in FP64 at the end */
   double t_fill_ms;          /* device time of the last vie_fill */
   double t_factor_ms;        /* device time of the last vie_precond_factor */

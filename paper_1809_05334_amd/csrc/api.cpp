@@ -35,7 +35,7 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, F, ipiv, perm, rpiv, info, dinv, tpart, tcount;
+  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, dinv, tpart, tcount;
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
@@ -65,6 +65,9 @@ struct vie_ctx {
   std::vector<double> pack;         // packed lattice-sum table of the last fill
   int packlen = 0;
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
+  std::vector<int64_t> nrow;        // near-part CSR pattern (mixed precision), built on first use
+  std::vector<int32_t> ncol;
+  bool npat = false;
   std::vector<int32_t> color_off;
   int nhalf = 0, nface = 0;
   int last_pol = 0;
@@ -106,7 +109,8 @@ int fail(vie_ctx *c, int code, const char *fmt, ...) {
 
 unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
-Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf) {
+Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf, int precision,
+                   int64_t near_nnz) {
   Layout L;
   size_t off = 0;
   auto put = [&](Region &r, size_t bytes) {
@@ -139,7 +143,11 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.inveps, 16 * nt);
   put(L.sigma, 16 * std::max(1, nface));
   L.ld = (N + 7) / 8 * 8;
-  put(L.Z, 16 * (size_t)N * L.ld);
+  const bool mixed = precision == VIE_MIXED_FP32;
+  put(L.Z, (mixed ? 8 : 16) * (size_t)N * L.ld);
+  put(L.nrow, mixed ? 8 * (size_t)(N + 1) : 0);
+  put(L.ncol, mixed ? 4 * (size_t)near_nnz : 0);
+  put(L.nval, mixed ? 16 * (size_t)near_nnz : 0);
   L.fld.resize(t.ndom);
   L.foff.resize(t.ndom);
   int64_t fel = 0, npiv = 0;
@@ -187,6 +195,43 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
 int check(vie_ctx *ctx, State need, const char *what) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->state < need) return fail(ctx, VIE_ESTATE, "%s called out of order", what);
+  return VIE_OK;
+}
+
+void ensure_near_pattern(vie_ctx *ctx) {
+  if (ctx->npat) return;
+  build_near_pattern(ctx->topo, ctx->nrow, ctx->ncol);
+  ctx->npat = true;
+}
+
+ZOut zout(vie_ctx *ctx) {
+  const Layout &L = ctx->L;
+  ZOut o{};
+  o.ld = L.ld;
+  if (ctx->precision == VIE_MIXED_FP32) {
+    o.Zs = ctx->ptr<fz>(L.Z);
+    o.rowptr = ctx->ptr<int64_t>(L.nrow);
+    o.cols = ctx->ptr<int32_t>(L.ncol);
+    o.vals = ctx->ptr<dz>(L.nval);
+  } else {
+    o.Z = ctx->ptr<dz>(L.Z);
+  }
+  return o;
+}
+
+// y = Z x, or y = b - Z x when b is given, with the bound precision's operator
+int matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  if (ctx->precision == VIE_MIXED_FP32)
+    hipLaunchKernelGGL(k_matvec_mixed, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream,
+                       (const fz *)ctx->ptr<fz>(L.Z), L.ld, N, (const int64_t *)ctx->ptr<int64_t>(L.nrow),
+                       (const int32_t *)ctx->ptr<int32_t>(L.ncol), (const dz *)ctx->ptr<dz>(L.nval), x, b, y);
+  else
+    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z),
+                       L.ld, N, x, b, y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "matvec: %s", hipGetErrorString(e));
   return VIE_OK;
 }
 
@@ -263,17 +308,26 @@ static int64_t total_near(const MeshTopology &t) {
   return s;
 }
 
-size_t vie_workspace_bytes(const vie_ctx *ctx, int precision, int restart) {
-  if (!ctx || ctx->state < S_MESH || restart < 1 || precision != VIE_FP64) return 0;
+size_t vie_workspace_bytes(const vie_ctx *cctx, int precision, int restart) {
+  if (!cctx || cctx->state < S_MESH || restart < 1) return 0;
+  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32) return 0;
+  vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
   int nhalf = 0;
   for (int32_t f : ctx->topo.charged)
     if (ctx->topo.tminus[f] < 0) ++nhalf;
-  return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf).total;
+  int64_t nnz = 0;
+  if (precision == VIE_MIXED_FP32) {
+    ensure_near_pattern(ctx);
+    nnz = (int64_t)ctx->ncol.size();
+  }
+  return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf, precision, nnz)
+      .total;
 }
 
 int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart) {
   if (int r = check(ctx, S_MESH, "vie_bind_workspace")) return r;
-  if (precision != VIE_FP64) return fail(ctx, VIE_EINVAL, "precision %d not supported by this build", precision);
+  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32)
+    return fail(ctx, VIE_EINVAL, "precision must be VIE_FP64 or VIE_MIXED_FP32");
   if (restart < 1 || restart > 1000) return fail(ctx, VIE_EINVAL, "restart must be in [1, 1000]");
   if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(ctx, VIE_EINVAL, "workspace must be 256-byte aligned");
   HIPCK(hipSetDevice(ctx->device));
@@ -283,7 +337,12 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
     if (t.tminus[t.charged[i]] < 0) half.push_back((int32_t)i);
   ctx->nhalf = (int)half.size();
   ctx->nface = (int)t.charged.size();
-  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf);
+  int64_t nnz = 0;
+  if (precision == VIE_MIXED_FP32) {
+    ensure_near_pattern(ctx);
+    nnz = (int64_t)ctx->ncol.size();
+  }
+  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz);
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
   ctx->L = L;
   ctx->ws = (char *)dev_ptr;
@@ -370,6 +429,10 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   rc |= up(L.near_s, ns_.data(), 4 * ns_.size());
   rc |= up(L.near_m, nm_.data(), 4 * nm_.size());
   rc |= up(L.quad, &ctx->quad, sizeof(QuadRules));
+  if (precision == VIE_MIXED_FP32) {
+    rc |= up(L.nrow, ctx->nrow.data(), 8 * ctx->nrow.size());
+    rc |= up(L.ncol, ctx->ncol.data(), 4 * ctx->ncol.size());
+  }
   if (rc) return rc;
   // the triangular-solve step counter starts (and always ends) at zero
   HIPCK(hipMemsetAsync(ctx->ws + L.tcount.off, 0, L.tcount.bytes, ctx->stream));
@@ -413,7 +476,8 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   const TetGeom *tg = ctx->ptr<TetGeom>(L.tg);
   const TetFace *t2f = ctx->ptr<TetFace>(L.t2f);
   dz *alpha = ctx->ptr<dz>(L.alpha), *gsrc = ctx->ptr<dz>(L.gsrc), *kappa = ctx->ptr<dz>(L.kappa),
-     *inveps = ctx->ptr<dz>(L.inveps), *sigma = ctx->ptr<dz>(L.sigma), *Z = ctx->ptr<dz>(L.Z);
+     *inveps = ctx->ptr<dz>(L.inveps), *sigma = ctx->ptr<dz>(L.sigma);
+  const ZOut zo = zout(ctx);
   const double k0 = 2 * M_PI / lambda_nm;
   const double k0sq9 = k0 * k0 / 9.0;
   const double kx = k0 * std::sin(theta) * std::cos(phi), ky = k0 * std::sin(theta) * std::sin(phi);
@@ -424,7 +488,10 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   if (ctx->nface)
     hipLaunchKernelGGL(k_sigma, dim3(nblk(ctx->nface, 256)), dim3(256), 0, ctx->stream, ctx->nface,
                        ctx->ptr<int32_t>(L.ctp), ctx->ptr<int32_t>(L.ctm), (const dz *)kappa, sigma);
-  hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, Z, (int64_t)t.N * L.ld);
+  // clear Z (and the near part): the fill accumulates into it
+  hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z), (int64_t)(L.Z.bytes / 16));
+  if (L.nval.bytes)
+    hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.nval), (int64_t)(L.nval.bytes / 16));
   LAUNCHCK();
   const int C = t.ncolors;
   const int32_t *colors = ctx->ptr<int32_t>(L.colors);
@@ -436,7 +503,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
       hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                          colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
-                         (const dz *)gsrc, (const dz *)kappa, k0sq9, Z, L.ld);
+                         (const dz *)gsrc, (const dz *)kappa, k0sq9, zo);
       LAUNCHCK();
     }
   HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
@@ -446,7 +513,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                        ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
                        ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
-                       (const dz *)kappa, (const dz *)inveps, k0sq9, Z, L.ld);
+                       (const dz *)kappa, (const dz *)inveps, k0sq9, zo);
     LAUNCHCK();
   }
   hipEvent_t evn = nullptr;
@@ -457,8 +524,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
       hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
-                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, Z,
-                         L.ld);
+                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, zo);
       LAUNCHCK();
     }
     if (ctx->nhalf) {
@@ -466,11 +532,11 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
         hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr,
                            fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
-                           (const dz *)gsrc, (const dz *)kappa, Z, L.ld);
+                           (const dz *)gsrc, (const dz *)kappa, zo);
         LAUNCHCK();
       }
       hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_,
-                         pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, Z, L.ld);
+                         pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, zo);
       LAUNCHCK();
     }
   }
@@ -523,7 +589,7 @@ int vie_precond_factor(vie_ctx *ctx) {
   HIPCK(hipSetDevice(ctx->device));
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
-  dz *Z = ctx->ptr<dz>(L.Z);
+  const ZOut zo = zout(ctx);
   dz *F = ctx->ptr<dz>(L.F);
   int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *perm = ctx->ptr<int32_t>(L.perm), *info = ctx->ptr<int32_t>(L.info);
   dz *rpiv = ctx->ptr<dz>(L.rpiv);
@@ -535,8 +601,10 @@ int vie_precond_factor(vie_ctx *ctx) {
     if (n == 0) continue;
     const int64_t ldf = L.fld[d];
     dz *A = F + L.foff[d];
-    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld,
-                       t.dstart[d], n, A, ldf);
+    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, A,
+                       ldf);
+    if (!zo.Z)
+      hipLaunchKernelGGL(k_add_near, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, A, ldf);
     LAUNCHCK();
     int32_t *ip = ipiv + poff;
     for (int k0 = 0; k0 < n; k0 += kLuNB) {
@@ -724,8 +792,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   const int64_t N = t.N;
-  dz *Z = ctx->ptr<dz>(L.Z), *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g),
-     *y = ctx->ptr<dz>(L.y);
+  dz *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g), *y = ctx->ptr<dz>(L.y);
   dz *b = ctx->ptr<dz>(L.vb), *x = ctx->ptr<dz>(L.vx), *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz),
      *u = ctx->ptr<dz>(L.vu), *r = ctx->ptr<dz>(L.vr), *tmp = ctx->ptr<dz>(L.vt);
   double *cs = ctx->ptr<double>(L.cs), *scal = ctx->ptr<double>(L.scal);
@@ -774,9 +841,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
     bool est_ok = false;
     for (int j = 0; j < restart; ++j) {
       if (int rc = apply_minv(ctx, V + (int64_t)j * L.ldv, z, tmp, u)) return rc;
-      hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld, N,
-                         (const dz *)z, (const dz *)nullptr, w);
-      LAUNCHCK();
+      if (int rc = matvec(ctx, z, nullptr, w)) return rc;
       if (int rc = cgs2(ctx, j, w)) return rc;
       if (int rc = norm_to(ctx, w, N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
       hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, ctx->stream, H, ldh, j, (const double *)(scal + 2), cs, sn, g,
@@ -803,9 +868,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
     if (int rc = apply_minv(ctx, w, u, tmp, z)) return rc;
     hipLaunchKernelGGL(k_axpy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, (const dz *)u, N);
     // true residual r = b - Z x
-    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)Z, L.ld, N,
-                       (const dz *)x, (const dz *)b, r);
-    LAUNCHCK();
+    if (int rc = matvec(ctx, x, b, r)) return rc;
     if (int rc = norm_to(ctx, r, N, scal + 1)) return rc;
     if (int rc = read_scalar(ctx, scal + 1, &beta)) return rc;
     true_rel = beta / bnorm;
@@ -823,7 +886,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
   if (info) {
     info->iters = iters;
     info->restarts = restarts;
-    info->refine_steps = 1;
+    info->refine_steps = restarts + 1;
     info->true_rel_residual = true_rel;
     info->t_fill_ms = ctx->t_fill;
     info->t_factor_ms = ctx->t_factor;
@@ -954,7 +1017,7 @@ int vie_read_Z(const vie_ctx *cctx, const int64_t *rows, const int64_t *cols, in
     dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(16 * (size_t)n));
     HIPCK(hipMemcpyAsync(ri, rows + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
     HIPCK(hipMemcpyAsync(ri + n, cols + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z), L.ld,
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zout(ctx),
                        (const int64_t *)ri, (const int64_t *)(ri + n), n, o);
     LAUNCHCK();
     HIPCK(hipMemcpyAsync(out + s, o, 16 * n, hipMemcpyDeviceToHost, ctx->stream));
@@ -1016,9 +1079,7 @@ int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec) {
   LAUNCHCK();
   HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
   for (int r = 0; r < reps; ++r)
-    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z),
-                       L.ld, N, (const dz *)x, (const dz *)nullptr, y);
-  LAUNCHCK();
+    if (int rc = matvec(ctx, x, nullptr, y)) return rc;
   HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
   HIPCK(hipEventSynchronize(ctx->ev3));
   float ms = 0;

@@ -12,6 +12,10 @@ namespace vie {
 struct dz {
   double re, im;
 };
+// complex FP32 storage element (mixed-precision Z); arithmetic stays FP64
+struct fz {
+  float re, im;
+};
 __device__ __forceinline__ dz mk(double r, double i) { return dz{r, i}; }
 __device__ __forceinline__ dz operator+(dz a, dz b) { return dz{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ dz operator-(dz a, dz b) { return dz{a.re - b.re, a.im - b.im}; }

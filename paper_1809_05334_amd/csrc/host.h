@@ -45,6 +45,10 @@ struct MeshTopology {
 std::string build_topology(MeshTopology &t, const double *verts, int64_t nv, const int32_t *tets, int64_t nt,
                            const int32_t *tet_domain, int ndom, double a, double b);
 
+// Sparsity pattern of the near (touching-pair) entries of Z, CSR with sorted
+// rows (rowptr [N+1], cols [nnz]).
+void build_near_pattern(const MeshTopology &t, std::vector<int64_t> &rowptr, std::vector<int32_t> &cols);
+
 // Touching-image mask (bit (m+1)*3 + (n+1)) of two vertex sets given by canonical
 // ids and packed offsets ((ox+2) | (oy+2) << 4).
 inline int touching_mask(const int32_t *ct, const int32_t *ot, int nt_, const int32_t *cs, const int32_t *os,

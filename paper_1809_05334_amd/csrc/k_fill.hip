@@ -27,9 +27,26 @@ static constexpr double kInv4Pi = 0.079577471545947667884;
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ void zadd(dz *__restrict__ Z, int64_t idx, dz v) {
-  dz z = Z[idx];
-  Z[idx] = z + v;
+// Z[m][n] += v into the destination of this fill (see ZOut).  In mixed
+// precision a far contribution is added to the FP32 entry in FP64 and rounded
+// once; a near one goes to its slot of the sorted CSR row.
+__device__ __forceinline__ void zput(const ZOut &o, int64_t m, int64_t n, dz v, bool near) {
+  if (o.Z) {
+    dz *p = o.Z + m * o.ld + n;
+    *p = *p + v;
+  } else if (near) {
+    int64_t lo = o.rowptr[m], hi = o.rowptr[m + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (o.cols[mid] < n) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < o.rowptr[m + 1] && o.cols[lo] == n) o.vals[lo] = o.vals[lo] + v;
+  } else {
+    fz *p = o.Zs + m * o.ld + n;
+    const fz z = *p;
+    *p = fz{(float)((double)z.re + v.re), (float)((double)z.im + v.im)};
+  }
 }
 
 // ------------------------------------------------------------ per-fill coefficients
@@ -85,8 +102,8 @@ __device__ __forceinline__ void moments_zero(Moments &M) {
 __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, const TetGeom &gs,
                                            const TetFace *__restrict__ t2f, int T, int S,
                                            const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
-                                           const dz *__restrict__ kappa, double k0sq9, dz *__restrict__ Z,
-                                           int64_t ld) {
+                                           const dz *__restrict__ kappa, double k0sq9, const ZOut &out,
+                                           bool near) {
   const dz ks = kappa[S];
   double qv[4][3];
   dz bl[4];
@@ -103,13 +120,13 @@ __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, 
     dz base = M.muv;
     for (int d = 0; d < 3; ++d) base = base - pk[d] * M.mv[d];
     const dz ak = alpha[4 * T + k];
-    const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
+    const int64_t row = t2f[4 * T + k].unknown;
     for (int l = 0; l < 4; ++l) {
       dz I = base;
       for (int d = 0; d < 3; ++d) I = I - qv[l][d] * M.mu[d];
       I = I + dot3(pk, qv[l]) * M.m0;
       const dz v = M.m0 - k0sq9 * I;
-      zadd(Z, row + col[l], (ak * bl[l]) * v);
+      zput(out, row, col[l], (ak * bl[l]) * v, near);
     }
   }
 }
@@ -120,8 +137,7 @@ __global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack,
                                                 const int32_t *__restrict__ test_list, int ntest,
                                                 const int32_t *__restrict__ src_list, int nsrc,
                                                 const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
-                                                const dz *__restrict__ kappa, double k0sq9, dz *__restrict__ Z,
-                                                int64_t ld) {
+                                                const dz *__restrict__ kappa, double k0sq9, ZOut out) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack,
       axpy(M.muv, dot3(u, up[j]), gw);
     }
   }
-  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, Z, ld);
+  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, false);
 }
 
 // Touching tet pairs: 14-point outer rule on T; per touching image the closed
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
                                                  const int32_t *__restrict__ lmask, int npairs,
                                                  const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
                                                  const dz *__restrict__ kappa, const dz *__restrict__ inv_eps,
-                                                 double k0sq9, dz *__restrict__ Z, int64_t ld) {
+                                                 double k0sq9, ZOut out) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -249,12 +265,12 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
     for (int d = 0; d < 3; ++d) axpy(us, u[d], s1[d]);
     axpy(M.muv, w, us);
   }
-  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, Z, ld);
+  scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, true);
   if (T == S) {
     // mass <f_m, f_n / eps_r>: alpha_k gsrc_l / (9 eps) int_T (r - v_k).(r - v_l), 4-point rule (exact)
     const dz ie = inv_eps[T];
     for (int k = 0; k < 4; ++k) {
-      const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
+      const int64_t row = t2f[4 * T + k].unknown;
       for (int l = 0; l < 4; ++l) {
         double s = 0;
         for (int q = 0; q < 4; ++q) {
@@ -266,7 +282,7 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
           }
           s = fma(0.25 * gt.vol, a2, s);
         }
-        zadd(Z, row + t2f[4 * T + l].unknown, (s / 9.0) * ((alpha[4 * T + k] * gsrc[4 * T + l]) * ie));
+        zput(out, row, t2f[4 * T + l].unknown, (s / 9.0) * ((alpha[4 * T + k] * gsrc[4 * T + l]) * ie), true);
       }
     }
   }
@@ -277,8 +293,8 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
 // 14-point rule on T, closed-form int_F 1/R per touching image, 3-point
 // inner rule for the remainder.
 __device__ dz pair_tet_face(const double *__restrict__ P, const QuadRules *__restrict__ qr, const TetGeom &gt,
-                            const FaceGeom &f) {
-  const int mask = touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3);
+                            const FaceGeom &f, int &mask) {
+  mask = touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3);
   double fp[3][3];
   for (int j = 0; j < 3; ++j)
     for (int d = 0; d < 3; ++d) fp[j][d] = qr->tri3[j][0] * f.v[0][d] + qr->tri3[j][1] * f.v[1][d] + qr->tri3[j][2] * f.v[2][d];
@@ -340,8 +356,8 @@ __device__ dz pair_tet_face(const double *__restrict__ P, const QuadRules *__res
 // M0 = II g_p over (test face F, source tet S).  Touching: outer 7-point rule
 // on F, closed-form int_S 1/R, 4-point inner rule for the remainder.
 __device__ dz pair_face_tet(const double *__restrict__ P, const QuadRules *__restrict__ qr, const FaceGeom &f,
-                            const TetGeom &gs) {
-  const int mask = touch_mask(f.canon, f.off, 3, gs.canon, gs.off, 4);
+                            const TetGeom &gs, int &mask) {
+  mask = touch_mask(f.canon, f.off, 3, gs.canon, gs.off, 4);
   double sp[4][3];
   for (int j = 0; j < 4; ++j)
     for (int d = 0; d < 3; ++d) {
@@ -398,8 +414,8 @@ __device__ dz pair_face_tet(const double *__restrict__ P, const QuadRules *__res
 
 // M0 = II g_p over (test face F, source face G).
 __device__ dz pair_face_face(const double *__restrict__ P, const QuadRules *__restrict__ qr, const FaceGeom &f,
-                             const FaceGeom &g) {
-  const int mask = touch_mask(f.canon, f.off, 3, g.canon, g.off, 3);
+                             const FaceGeom &g, int &mask) {
+  mask = touch_mask(f.canon, f.off, 3, g.canon, g.off, 3);
   double gp[3][3];
   for (int j = 0; j < 3; ++j)
     for (int d = 0; d < 3; ++d) gp[j][d] = qr->tri3[j][0] * g.v[0][d] + qr->tri3[j][1] * g.v[1][d] + qr->tri3[j][2] * g.v[2][d];
@@ -456,7 +472,7 @@ __global__ __launch_bounds__(256) void k_tet_face(const double *__restrict__ pac
                                                   const int32_t *__restrict__ test_list, int ntest,
                                                   const FaceGeom *__restrict__ fg, int nface,
                                                   const dz *__restrict__ alpha, const dz *__restrict__ sigma,
-                                                  dz *__restrict__ Z, int64_t ld) {
+                                                  ZOut out) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -467,12 +483,10 @@ __global__ __launch_bounds__(256) void k_tet_face(const double *__restrict__ pac
   const int T = uniform(test_list[ti]);
   const TetGeom &gt = tg[T];
   const FaceGeom f = fg[fi];
-  const dz m0 = pair_tet_face(s_tab, qr, gt, f);
+  int mask;
+  const dz m0 = pair_tet_face(s_tab, qr, gt, f, mask);
   const dz sm = sigma[fi] * m0;
-  for (int k = 0; k < 4; ++k) {
-    const int64_t row = (int64_t)t2f[4 * T + k].unknown * ld;
-    zadd(Z, row + f.unknown, mk(0, 0) - alpha[4 * T + k] * sm);
-  }
+  for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, mask != 0);
 }
 
 // half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0
@@ -481,7 +495,7 @@ __global__ __launch_bounds__(256) void k_face_tet(const double *__restrict__ pac
                                                   int nhalf, const TetGeom *__restrict__ tg,
                                                   const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
                                                   int nsrc, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
-                                                  dz *__restrict__ Z, int64_t ld) {
+                                                  ZOut out) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -492,16 +506,16 @@ __global__ __launch_bounds__(256) void k_face_tet(const double *__restrict__ pac
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const int S = src_list[si];
   const TetGeom gs = tg[S];
-  const dz m0 = pair_face_tet(s_tab, qr, f, gs) * kappa[S];
-  const int64_t row = (int64_t)f.unknown * ld;
-  for (int l = 0; l < 4; ++l) zadd(Z, row + t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0);
+  int mask;
+  const dz m0 = pair_face_tet(s_tab, qr, f, gs, mask) * kappa[S];
+  for (int l = 0; l < 4; ++l) zput(out, f.unknown, t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0, mask != 0);
 }
 
 // half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
 __global__ __launch_bounds__(256) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                    const FaceGeom *__restrict__ fg,
                                                    const int32_t *__restrict__ half_list, int nhalf, int nface,
-                                                   const dz *__restrict__ sigma, dz *__restrict__ Z, int64_t ld) {
+                                                   const dz *__restrict__ sigma, ZOut out) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -511,8 +525,9 @@ __global__ __launch_bounds__(256) void k_face_face(const double *__restrict__ pa
   if (hi >= nhalf || gi >= nface) return;
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const FaceGeom g = fg[gi];
-  const dz m0 = pair_face_face(s_tab, qr, f, g);
-  zadd(Z, (int64_t)f.unknown * ld + g.unknown, sigma[gi] * m0);
+  int mask;
+  const dz m0 = pair_face_face(s_tab, qr, f, g, mask);
+  zput(out, f.unknown, g.unknown, sigma[gi] * m0, mask != 0);
 }
 
 // ------------------------------------------------------------ right-hand side
@@ -557,12 +572,26 @@ __global__ void k_pgf_probe(const double *__restrict__ pack, int packlen, const 
   out[i] = pgf_eval<false>(s_tab, d[3 * i], d[3 * i + 1], d[3 * i + 2], 0);
 }
 
-// gather Z entries
-__global__ void k_gather(const dz *__restrict__ Z, int64_t ld, const int64_t *__restrict__ rows,
-                         const int64_t *__restrict__ cols, int64_t k, dz *__restrict__ out) {
+// gather Z entries (mixed precision: FP32 far part plus the FP64 near entry)
+__global__ void k_gather(ZOut Z, const int64_t *__restrict__ rows, const int64_t *__restrict__ cols, int64_t k,
+                         dz *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
-  out[i] = Z[rows[i] * ld + cols[i]];
+  const int64_t m = rows[i], n = cols[i];
+  if (Z.Z) {
+    out[i] = Z.Z[m * Z.ld + n];
+    return;
+  }
+  const fz f = Z.Zs[m * Z.ld + n];
+  dz v = mk(f.re, f.im);
+  int64_t lo = Z.rowptr[m], hi = Z.rowptr[m + 1];
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (Z.cols[mid] < n) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < Z.rowptr[m + 1] && Z.cols[lo] == n) v = v + Z.vals[lo];
+  out[i] = v;
 }
 
 }  // namespace vie

@@ -64,6 +64,64 @@ __global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_
   }
 }
 
+// y = Z x (or b - Z x) for the mixed-precision operator Z = Zs + Zn: Zs the
+// complex-FP32 dense far part (row-major, ld a multiple of 8), Zn the FP64
+// near part in CSR.  Arithmetic and accumulation in FP64.  Same row mapping
+// as k_matvec; each lane streams two adjacent FP32 entries (16 bytes) per
+// row, then the wave adds its rows' near entries.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs, int64_t ld, int64_t N,
+                                                      const int64_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ cols, const dz *__restrict__ vals,
+                                                      const dz *__restrict__ x, const dz *__restrict__ b,
+                                                      dz *__restrict__ y) {
+  __shared__ dz xs[kMvChunk];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * kMvRPW;
+  double are[kMvRPW], aim[kMvRPW];
+  for (int r = 0; r < kMvRPW; ++r) are[r] = aim[r] = 0.0;
+  for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
+    const int len = (int)min<int64_t>(kMvChunk, N - c0);
+    __syncthreads();
+    for (int i = tid; i < len; i += 256) xs[i] = x[c0 + i];
+    __syncthreads();
+    for (int cc = 2 * lane; cc < len; cc += 128) {
+      const dz x0 = xs[cc];
+      const dz x1 = cc + 1 < len ? xs[cc + 1] : mk(0, 0);
+#pragma unroll
+      for (int r = 0; r < kMvRPW; ++r) {
+        const int64_t row = row0 + r;
+        if (row < N) {
+          const v4f z = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Zs + row * ld + c0 + cc));
+          are[r] = fma((double)z[0], x0.re, fma(-(double)z[1], x0.im, are[r]));
+          aim[r] = fma((double)z[0], x0.im, fma((double)z[1], x0.re, aim[r]));
+          are[r] = fma((double)z[2], x1.re, fma(-(double)z[3], x1.im, are[r]));
+          aim[r] = fma((double)z[2], x1.im, fma((double)z[3], x1.re, aim[r]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kMvRPW; ++r) {
+    const int64_t row = row0 + r;
+    if (row < N)
+      for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) {
+        const dz v = vals[e], xv = x[cols[e]];
+        are[r] = fma(v.re, xv.re, fma(-v.im, xv.im, are[r]));
+        aim[r] = fma(v.re, xv.im, fma(v.im, xv.re, aim[r]));
+      }
+  }
+  for (int r = 0; r < kMvRPW; ++r) {
+    const double sr = wsum(are[r]), si = wsum(aim[r]);
+    const int64_t row = row0 + r;
+    if (lane == 0 && row < N) {
+      if (b) y[row] = mk(b[row].re - sr, b[row].im - si);
+      else y[row] = mk(sr, si);
+    }
+  }
+}
+
 // Partial inner products h_i = sum_k conj(V_i[k]) w[k], i < nv, per block:
 // part[blockIdx.x * nv + i].  V column-major: V_i = V + i * ldv.
 __global__ __launch_bounds__(256) void k_dots(const dz *__restrict__ V, int64_t ldv, int nv,

@@ -19,12 +19,30 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double cabs1(dz a) { return fabs(a.re) + fabs(a.im); }
 
-// copy the diagonal block Z[start:start+n, start:start+n] into A (ld lda)
-__global__ void k_copy_block(const dz *__restrict__ Z, int64_t ldz, int64_t start, int n, dz *__restrict__ A,
-                             int64_t lda) {
+// copy the diagonal block Z[start:start+n, start:start+n] into A (ld lda);
+// in mixed precision the FP32 far part here, the near part by k_add_near
+__global__ void k_copy_block(ZOut Z, int64_t start, int n, dz *__restrict__ A, int64_t lda) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (c < n) A[(int64_t)r * lda + c] = Z[(start + r) * ldz + start + c];
+  if (c >= n) return;
+  const int64_t idx = (start + r) * Z.ld + start + c;
+  if (Z.Z) {
+    A[(int64_t)r * lda + c] = Z.Z[idx];
+  } else {
+    const fz f = Z.Zs[idx];
+    A[(int64_t)r * lda + c] = mk(f.re, f.im);
+  }
+}
+
+// A += the FP64 near entries of the diagonal block (one thread per row)
+__global__ void k_add_near(ZOut Z, int64_t start, int n, dz *__restrict__ A, int64_t lda) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t m = start + r;
+  for (int64_t e = Z.rowptr[m]; e < Z.rowptr[m + 1]; ++e) {
+    const int64_t c = Z.cols[e] - start;
+    if (c >= 0 && c < n) A[(int64_t)r * lda + c] = A[(int64_t)r * lda + c] + Z.vals[e];
+  }
 }
 
 // ------------------------------------------------------------ panel

@@ -6,6 +6,19 @@
 
 namespace vie {
 
+// Destination of the fill.  VIE_FP64: everything into the FP64 dense Z.
+// VIE_MIXED_FP32: far contributions into the complex-FP32 dense Zs, the
+// contributions of touching pairs (singular extraction, mass) into the FP64
+// CSR near part (rowptr/cols/vals over the touching-pair pattern).
+struct ZOut {
+  dz *Z;
+  fz *Zs;
+  int64_t ld;
+  const int64_t *rowptr;
+  const int32_t *cols;
+  dz *vals;
+};
+
 // fill (k_fill.hip)
 __global__ void k_prep(int64_t nt, const TetFace *t2f, const TetGeom *tg, const double *area, const dz *eps_int,
                        double kx, double ky, double a, double b, dz *alpha, dz *gsrc, dz *kappa, dz *inv_eps);
@@ -13,26 +26,27 @@ __global__ void k_sigma(int nc, const int32_t *ctp, const int32_t *ctm, const dz
 __global__ void k_zero(dz *p, int64_t n);
 __global__ void k_tt_far(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                          const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc, const dz *alpha,
-                         const dz *gsrc, const dz *kappa, double k0sq9, dz *Z, int64_t ld);
+                         const dz *gsrc, const dz *kappa, double k0sq9, ZOut out);
 __global__ void k_tt_near(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                           const int32_t *lt, const int32_t *ls, const int32_t *lmask, int npairs, const dz *alpha,
-                          const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, dz *Z, int64_t ld);
+                          const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, ZOut out);
 __global__ void k_tet_face(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                            const int32_t *test_list, int ntest, const FaceGeom *fg, int nface, const dz *alpha,
-                           const dz *sigma, dz *Z, int64_t ld);
+                           const dz *sigma, ZOut out);
 __global__ void k_face_tet(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                            int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
-                           const dz *gsrc, const dz *kappa, dz *Z, int64_t ld);
+                           const dz *gsrc, const dz *kappa, ZOut out);
 __global__ void k_face_face(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
-                            int nhalf, int nface, const dz *sigma, dz *Z, int64_t ld);
+                            int nhalf, int nface, const dz *sigma, ZOut out);
 __global__ void k_rhs(int64_t N, const int32_t *utet, const int32_t *uk, const TetGeom *tg, const QuadRules *qr,
                       const dz *alpha, double kix, double kiy, double kiz, double ex, double ey, double ez, dz *b);
 __global__ void k_pgf_probe(const double *pack, int packlen, const double *d, int64_t n, dz *out);
-__global__ void k_gather(const dz *Z, int64_t ld, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
+__global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
 // block LU and its application (k_lu.hip)
 constexpr int kTrsvNB = 256;
-__global__ void k_copy_block(const dz *Z, int64_t ldz, int64_t start, int n, dz *A, int64_t lda);
+__global__ void k_copy_block(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
+__global__ void k_add_near(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
 __global__ void k_lu_pivot(dz *A, int64_t ld, int n, int j, int k0, int jb, int32_t *ipiv, dz *rpiv, int32_t *info);
 __global__ void k_lu_col(dz *A, int64_t ld, int n, int j, int k0, int jb, const dz *rpiv);
 __global__ void k_lu_swap(dz *A, int64_t ld, int n, int k0, int jb, const int32_t *ipiv);
@@ -64,6 +78,8 @@ __global__ void k_trsv_step(TrsvStep st);
 // Krylov (k_krylov.hip)
 constexpr int kMvRPW = 4;
 __global__ void k_matvec(const dz *Z, int64_t ld, int64_t N, const dz *x, const dz *b, dz *y);
+__global__ void k_matvec_mixed(const fz *Zs, int64_t ld, int64_t N, const int64_t *rowptr, const int32_t *cols,
+                               const dz *vals, const dz *x, const dz *b, dz *y);
 __global__ void k_dots(const dz *V, int64_t ldv, int nv, const dz *w, int64_t N, dz *part);
 __global__ void k_dots_reduce(const dz *part, int nblk, int nv, dz *h, int accumulate);
 __global__ void k_update(const dz *V, int64_t ldv, int nv, const dz *c, dz *w, int64_t N);

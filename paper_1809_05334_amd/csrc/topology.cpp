@@ -307,4 +307,42 @@ std::string build_topology(MeshTopology &t, const double *verts, int64_t nv, con
   return "";
 }
 
+// Sparsity pattern of the entries that touching tetrahedron pairs reach:
+// (m, n) with m a face of T, n a face of S, (T, S) touching under some
+// lattice image (the self pair included).  Every singular or near-neighbour
+// contribution of the fill (tet-tet, tet-face, face-tet, face-face) lands
+// inside it, because a face touches a tetrahedron only if the face's own
+// tetrahedron does.  Rows sorted, no duplicates.
+void build_near_pattern(const MeshTopology &t, std::vector<int64_t> &rowptr, std::vector<int32_t> &cols) {
+  const int64_t N = t.N;
+  std::vector<int64_t> cnt(N + 1, 0);
+  const size_t G = t.near_t.size();
+  for (size_t g = 0; g < G; ++g)
+    for (size_t i = 0; i < t.near_t[g].size(); ++i) {
+      const int32_t T = t.near_t[g][i];
+      for (int k = 0; k < 4; ++k) cnt[t.t2f[4 * T + k].unknown + 1] += 4;
+    }
+  for (int64_t m = 0; m < N; ++m) cnt[m + 1] += cnt[m];
+  std::vector<int32_t> raw(cnt[N]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (size_t g = 0; g < G; ++g)
+    for (size_t i = 0; i < t.near_t[g].size(); ++i) {
+      const int32_t T = t.near_t[g][i], S = t.near_s[g][i];
+      for (int k = 0; k < 4; ++k) {
+        const int32_t m = t.t2f[4 * T + k].unknown;
+        for (int l = 0; l < 4; ++l) raw[pos[m]++] = t.t2f[4 * S + l].unknown;
+      }
+    }
+  rowptr.assign(N + 1, 0);
+  cols.clear();
+  cols.reserve(raw.size() / 2);
+  for (int64_t m = 0; m < N; ++m) {
+    auto b = raw.begin() + cnt[m], e = raw.begin() + cnt[m + 1];
+    std::sort(b, e);
+    e = std::unique(b, e);
+    cols.insert(cols.end(), b, e);
+    rowptr[m + 1] = (int64_t)cols.size();
+  }
+}
+
 }  // namespace vie
