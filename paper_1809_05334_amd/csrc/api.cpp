@@ -22,7 +22,6 @@ namespace {
 
 enum State { S_NEW = 0, S_MESH = 1, S_BOUND = 2, S_FILLED = 3, S_FACTORED = 4, S_SOLVED = 5 };
 
-constexpr int kLuNB = 64;
 constexpr int kMaxPack = 8192;     // doubles of the packed lattice-sum table (64 KB of LDS)
 constexpr int kRedBlocks = 240;   // blocks of the two-stage reductions
 
@@ -35,7 +34,7 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, dinv, tpart, tcount;
+  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, dinv, tpart, tcount;
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
@@ -171,8 +170,13 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.tcount, 4 * (size_t)std::max(1, t.ndom));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
-  put(L.rpiv, 16);
+  int64_t npart = 0;
+  for (int d = 0; d < t.ndom; ++d) npart += nblk(t.dend[d] - t.dstart[d], 256);
+  put(L.rpiv, 16 * (size_t)std::max(1, t.ndom));
   put(L.info, 4 * std::max(1, t.ndom));
+  put(L.lupv, 8 * (size_t)std::max<int64_t>(1, npart));
+  put(L.lupi, 4 * (size_t)std::max<int64_t>(1, npart));
+  put(L.lucnt, 4 * (size_t)std::max(1, t.ndom));
   L.restart = restart;
   L.ldv = (N + 31) / 32 * 32;
   put(L.V, 16 * (size_t)L.ldv * (restart + 1));
@@ -434,8 +438,9 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
     rc |= up(L.ncol, ctx->ncol.data(), 4 * ctx->ncol.size());
   }
   if (rc) return rc;
-  // the triangular-solve step counter starts (and always ends) at zero
+  // the triangular-solve and panel counters start (and always end) at zero
   HIPCK(hipMemsetAsync(ctx->ws + L.tcount.off, 0, L.tcount.bytes, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->ws + L.lucnt.off, 0, L.lucnt.bytes, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
   ctx->state = S_BOUND;
   return VIE_OK;
@@ -584,6 +589,47 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
 }
 
 // ---------------------------------------------------------------- factor
+}  // extern "C"
+
+namespace {
+
+enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM };
+
+// One launch of an LU kernel over every domain with blocks_of(d) > 0 thread
+// blocks (kLuMaxDom domains per launch; more domains take more launches).
+template <typename BlocksOf>
+void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of) {
+  LuStep st{};
+  st.j = j;
+  st.k0 = k0;
+  int total = 0;
+  auto flush = [&]() {
+    if (st.ndom == 0) return;
+    switch (k) {
+      case LU_PIVOT: hipLaunchKernelGGL(k_lu_pivot, dim3(total), dim3(1024), 0, ctx->stream, st); break;
+      case LU_COL: hipLaunchKernelGGL(k_lu_col, dim3(total), dim3(256), 0, ctx->stream, st); break;
+      case LU_SWAP: hipLaunchKernelGGL(k_lu_swap, dim3(total), dim3(256), 0, ctx->stream, st); break;
+      case LU_TRSM: hipLaunchKernelGGL(k_lu_trsm, dim3(total), dim3(64), 0, ctx->stream, st); break;
+      case LU_GEMM: hipLaunchKernelGGL(k_lu_gemm, dim3(total), dim3(256), 0, ctx->stream, st); break;
+    }
+    st.ndom = 0;
+    total = 0;
+  };
+  for (size_t d = 0; d < doms.size(); ++d) {
+    const int nb = blocks_of((int)d);
+    if (nb <= 0) continue;
+    st.d[st.ndom] = doms[d];
+    st.d[st.ndom].first_block = total;
+    total += nb;
+    if (++st.ndom == kLuMaxDom) flush();
+  }
+  flush();
+}
+
+}  // namespace
+
+extern "C" {
+
 int vie_precond_factor(vie_ctx *ctx) {
   if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
   HIPCK(hipSetDevice(ctx->device));
@@ -595,45 +641,67 @@ int vie_precond_factor(vie_ctx *ctx) {
   dz *rpiv = ctx->ptr<dz>(L.rpiv);
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(hipMemsetAsync(info, 0, 4 * t.ndom, ctx->stream));
-  int64_t poff = 0;
+  std::vector<LuDom> doms(t.ndom);
+  int64_t poff = 0, pvoff = 0;
+  int maxn = 0;
   for (int d = 0; d < t.ndom; ++d) {
     const int n = (int)(t.dend[d] - t.dstart[d]);
+    LuDom &D = doms[d];
+    D = LuDom{};
+    D.A = F + L.foff[d];
+    D.ld = L.fld[d];
+    D.n = n;
+    D.ipiv = ipiv + poff;
+    D.info = info + d;
+    D.rpiv = rpiv + d;
+    D.pval = ctx->ptr<double>(L.lupv) + pvoff;
+    D.pidx = ctx->ptr<int32_t>(L.lupi) + pvoff;
+    D.counter = ctx->ptr<int>(L.lucnt) + d;
+    poff += n;
+    pvoff += nblk(n, 256);
+    maxn = std::max(maxn, n);
     if (n == 0) continue;
-    const int64_t ldf = L.fld[d];
-    dz *A = F + L.foff[d];
-    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, A,
-                       ldf);
+    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n,
+                       D.A, D.ld);
     if (!zo.Z)
-      hipLaunchKernelGGL(k_add_near, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, A, ldf);
+      hipLaunchKernelGGL(k_add_near, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, D.A,
+                         D.ld);
     LAUNCHCK();
-    int32_t *ip = ipiv + poff;
-    for (int k0 = 0; k0 < n; k0 += kLuNB) {
-      const int jb = std::min(kLuNB, n - k0);
-      for (int j = k0; j < k0 + jb; ++j) {
-        hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1024), 0, ctx->stream, A, ldf, n, j, k0, jb, ip, rpiv, info + d);
-        if (j + 1 < n)
-          hipLaunchKernelGGL(k_lu_col, dim3(nblk(n - j - 1, 256)), dim3(256), 0, ctx->stream, A, ldf, n, j, k0, jb,
-                             (const dz *)rpiv);
-      }
-      LAUNCHCK();
-      hipLaunchKernelGGL(k_lu_swap, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, A, ldf, n, k0, jb,
-                         (const int32_t *)ip);
-      const int rest = n - k0 - jb;
-      if (rest > 0) {
-        hipLaunchKernelGGL(k_lu_trsm, dim3(nblk(rest, 64)), dim3(64), 0, ctx->stream, A, ldf, n, k0, jb);
-        hipLaunchKernelGGL(k_lu_gemm, dim3(nblk(rest, 64), nblk(rest, 64)), dim3(256), 0, ctx->stream, A, ldf, n, k0,
-                           jb);
-      }
-      LAUNCHCK();
-    }
-    hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)ip, perm + poff);
+  }
+  // right-looking blocked LU of every domain, advanced together column by column
+  for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
+    auto jb_of = [&](int d) { return std::min(kLuNB, doms[d].n - k0); };
+    lu_launch(ctx, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
+    for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
+      lu_launch(ctx, LU_COL, doms, j, k0, [&](int d) {
+        const int n = doms[d].n;
+        return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, 256) : 0;
+      });
+    lu_launch(ctx, LU_SWAP, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; });
+    lu_launch(ctx, LU_TRSM, doms, k0, k0, [&](int d) {
+      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
+      return rest > 0 ? (int)nblk(rest, 64) : 0;
+    });
+    lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) {
+      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
+      const int nt = (int)nblk(rest, 64);
+      return rest > 0 ? nt * nt : 0;
+    });
+    LAUNCHCK();
+  }
+  for (int d = 0; d < t.ndom; ++d) {
+    const int n = doms[d].n;
+    if (n == 0) continue;
+    hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)doms[d].ipiv,
+                       perm + (doms[d].ipiv - ipiv));
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
     dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
     dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
-    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)A, ldf, n, kTrsvNB, 1, DL);
-    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)A, ldf, n, kTrsvNB, 0, DU);
+    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n,
+                       kTrsvNB, 1, DL);
+    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n,
+                       kTrsvNB, 0, DU);
     LAUNCHCK();
-    poff += n;
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->pinned, info, 4 * t.ndom, hipMemcpyDeviceToHost, ctx->stream));
@@ -651,8 +719,6 @@ int vie_precond_factor(vie_ctx *ctx) {
 // ---------------------------------------------------------------- solve
 namespace {
 
-// out = M^{-1} v  (block-diagonal LU solves); uses vt, vu as scratch when
-// out differs from them.
 // z = M^{-1} v for the block-diagonal preconditioner: per domain, permute by
 // the pivots, then L y = P v and U z = y by blocked triangular solves.  Each
 // k_trsv_step launch advances every domain (up to kTrsvMaxDom per launch) by

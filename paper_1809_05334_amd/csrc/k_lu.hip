@@ -46,19 +46,57 @@ __global__ void k_add_near(ZOut Z, int64_t start, int n, dz *__restrict__ A, int
 }
 
 // ------------------------------------------------------------ panel
-// Pivot search in column j (rows j..n-1), swap rows j and p inside the panel
-// columns [k0, k0+jb), store ipiv[j] = p and the reciprocal pivot.
-__global__ __launch_bounds__(1024) void k_lu_pivot(dz *__restrict__ A, int64_t ld, int n, int j, int k0, int jb,
-                                                   int32_t *__restrict__ ipiv, dz *__restrict__ rpiv,
-                                                   int32_t *__restrict__ info) {
+// Every launch below advances the factorisations of up to kLuMaxDom domains
+// at the same global column (domain d's thread blocks start at
+// st.d[d].first_block); a domain takes part while the column lies inside it.
+
+__device__ __forceinline__ int lu_domain(const LuStep &st) {
+  int d = 0;
+  while (d + 1 < st.ndom && (int)blockIdx.x >= st.d[d + 1].first_block) ++d;
+  return d;
+}
+
+// better pivot candidate: larger |re| + |im|, ties to the smaller row
+__device__ __forceinline__ bool piv_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// Swap rows j and p inside the panel columns [k0, k0 + jb) and store the
+// reciprocal pivot (or flag a zero pivot); `tid`/`nthr` stride the columns.
+__device__ __forceinline__ void pivot_finish(const LuDom &D, int j, int k0, int jb, int p, double pv, int tid,
+                                             int nthr) {
+  if (p != j)
+    for (int c = k0 + tid; c < k0 + jb; c += nthr) {
+      const dz t = D.A[(int64_t)j * D.ld + c];
+      D.A[(int64_t)j * D.ld + c] = D.A[(int64_t)p * D.ld + c];
+      D.A[(int64_t)p * D.ld + c] = t;
+    }
+  __syncthreads();
+  if (tid == 0) {
+    D.ipiv[j] = p;
+    if (!(pv > 0.0)) {
+      if (*D.info == 0) *D.info = j + 1;
+      *D.rpiv = mk(0.0, 0.0);
+    } else {
+      const dz d = D.A[(int64_t)j * D.ld + j];
+      const double den = d.re * d.re + d.im * d.im;
+      *D.rpiv = mk(d.re / den, -d.im / den);
+    }
+  }
+}
+
+// Pivot of the first column j = k0 of a panel: one thread block per domain.
+__global__ __launch_bounds__(1024) void k_lu_pivot(LuStep st) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
+  const LuDom &D = st.d[blockIdx.x];
+  const int j = st.j, k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int tid = threadIdx.x;
   double best = -1.0;
   int bi = n;
   for (int i = j + tid; i < n; i += 1024) {
-    const double v = cabs1(A[(int64_t)i * ld + j]);
-    if (v > best) {
+    const double v = cabs1(D.A[(int64_t)i * D.ld + j]);
+    if (piv_better(v, i, best, bi)) {
       best = v;
       bi = i;
     }
@@ -67,72 +105,116 @@ __global__ __launch_bounds__(1024) void k_lu_pivot(dz *__restrict__ A, int64_t l
   si[tid] = bi;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double o = sv[tid + s];
-      const int oi = si[tid + s];
-      if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) {
-        sv[tid] = o;
-        si[tid] = oi;
-      }
+    if (tid < s && piv_better(sv[tid + s], si[tid + s], sv[tid], si[tid])) {
+      sv[tid] = sv[tid + s];
+      si[tid] = si[tid + s];
     }
     __syncthreads();
   }
-  const int p = si[0];
-  const double pv = sv[0];
-  if (tid == 0) ipiv[j] = p;
-  if (p != j)
-    for (int c = k0 + tid; c < k0 + jb; c += 1024) {
-      const dz t = A[(int64_t)j * ld + c];
-      A[(int64_t)j * ld + c] = A[(int64_t)p * ld + c];
-      A[(int64_t)p * ld + c] = t;
-    }
-  __syncthreads();
-  if (tid == 0) {
-    if (!(pv > 0.0)) {
-      if (*info == 0) *info = j + 1;
-      *rpiv = mk(0.0, 0.0);
-    } else {
-      const dz d = A[(int64_t)j * ld + j];
-      const double den = d.re * d.re + d.im * d.im;
-      *rpiv = mk(d.re / den, -d.im / den);
-    }
-  }
+  pivot_finish(D, j, k0, jb, si[0], sv[0], tid, 1024);
 }
 
-// Scale column j below the diagonal and apply the rank-1 update to the rest
-// of the panel (columns j+1 .. k0+jb-1).
-__global__ __launch_bounds__(256) void k_lu_col(dz *__restrict__ A, int64_t ld, int n, int j, int k0, int jb,
-                                                const dz *__restrict__ rpiv) {
-  const int i = j + 1 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  dz *row = A + (int64_t)i * ld;
-  const dz *prow = A + (int64_t)j * ld;
-  const dz l = row[j] * (*rpiv);
-  row[j] = l;
-  for (int c = j + 1; c < k0 + jb; ++c) row[c] = row[c] - l * prow[c];
+// Column j of the panel: scale it below the diagonal, apply the rank-1 update
+// to the rest of the panel (columns j+1 .. k0+jb-1), one thread per row.
+// When column j+1 is inside the panel, each thread block also reduces its
+// rows' pivot candidates in column j+1 into part; the last block of the
+// domain to finish (agent-scope acq_rel counter; nothing waits on it) picks
+// the pivot of column j+1, swaps it into place inside the panel, stores the
+// reciprocal pivot and puts the counter back to zero.
+__global__ __launch_bounds__(256) void k_lu_col(LuStep st) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  __shared__ int last;
+  const int d = lu_domain(st);
+  const LuDom &D = st.d[d];
+  const int j = st.j, k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int blk = blockIdx.x - D.first_block;
+  const int tid = threadIdx.x;
+  const int i = j + 1 + blk * 256 + tid;
+  const bool next = j + 1 < k0 + jb;
+  double v = -1.0;
+  if (i < n) {
+    dz *row = D.A + (int64_t)i * D.ld;
+    const dz *prow = D.A + (int64_t)j * D.ld;
+    const dz l = row[j] * (*D.rpiv);
+    row[j] = l;
+    for (int c = j + 1; c < k0 + jb; ++c) row[c] = row[c] - l * prow[c];
+    if (next) v = cabs1(row[j + 1]);
+  }
+  if (!next) return;
+  sv[tid] = v;
+  si[tid] = i < n ? i : n;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s && piv_better(sv[tid + s], si[tid + s], sv[tid], si[tid])) {
+      sv[tid] = sv[tid + s];
+      si[tid] = si[tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    D.pval[blk] = sv[0];
+    D.pidx[blk] = si[0];
+    __threadfence();
+    const int nb = (n - j - 1 + 255) / 256;
+    const int old = __hip_atomic_fetch_add(D.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = old == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = (n - j - 1 + 255) / 256;
+  double best = -1.0;
+  int bi = n;
+  for (int q = tid; q < nb; q += 256) {
+    const double pv = D.pval[q];
+    const int pi = D.pidx[q];
+    if (piv_better(pv, pi, best, bi)) {
+      best = pv;
+      bi = pi;
+    }
+  }
+  __syncthreads();
+  sv[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s && piv_better(sv[tid + s], si[tid + s], sv[tid], si[tid])) {
+      sv[tid] = sv[tid + s];
+      si[tid] = si[tid + s];
+    }
+    __syncthreads();
+  }
+  pivot_finish(D, j + 1, k0, jb, si[0], sv[0], tid, 256);
+  if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Apply the panel's row swaps to the columns outside the panel.
-__global__ __launch_bounds__(256) void k_lu_swap(dz *__restrict__ A, int64_t ld, int n, int k0, int jb,
-                                                 const int32_t *__restrict__ ipiv) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_lu_swap(LuStep st) {
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int c = (blockIdx.x - D.first_block) * 256 + threadIdx.x;
   if (c >= n || (c >= k0 && c < k0 + jb)) return;
   for (int j = k0; j < k0 + jb; ++j) {
-    const int p = ipiv[j];
+    const int p = D.ipiv[j];
     if (p != j) {
-      const dz t = A[(int64_t)j * ld + c];
-      A[(int64_t)j * ld + c] = A[(int64_t)p * ld + c];
-      A[(int64_t)p * ld + c] = t;
+      const dz t = D.A[(int64_t)j * D.ld + c];
+      D.A[(int64_t)j * D.ld + c] = D.A[(int64_t)p * D.ld + c];
+      D.A[(int64_t)p * D.ld + c] = t;
     }
   }
 }
 
 // U12 = L11^{-1} A12 (L11 unit lower, jb <= 64): one wave per 64 columns, the
 // column block lives in LDS.
-__global__ __launch_bounds__(64) void k_lu_trsm(dz *__restrict__ A, int64_t ld, int n, int k0, int jb) {
+__global__ __launch_bounds__(64) void k_lu_trsm(LuStep st) {
   __shared__ dz tile[64][65];
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int64_t ld = D.ld;
+  dz *A = D.A;
   const int lane = threadIdx.x;
-  const int c = k0 + jb + blockIdx.x * 64 + lane;
+  const int c = k0 + jb + (blockIdx.x - D.first_block) * 64 + lane;
   const bool ok = c < n;
   for (int i = 0; i < jb; ++i) tile[i][lane] = ok ? A[(int64_t)(k0 + i) * ld + c] : mk(0, 0);
   for (int i = 1; i < jb; ++i) {
@@ -152,11 +234,17 @@ __global__ __launch_bounds__(64) void k_lu_trsm(dz *__restrict__ A, int64_t ld, 
 //   B[k = l/16][j = l%16]; result register r holds D[i = 4*r + l/16][j = l%16].
 constexpr int kGemmKC = 16;
 
-__global__ __launch_bounds__(256) void k_lu_gemm(dz *__restrict__ A, int64_t ld, int n, int k0, int jb) {
+__global__ __launch_bounds__(256) void k_lu_gemm(LuStep st) {
   __shared__ double Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
   __shared__ double Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
-  const int r0 = k0 + jb + blockIdx.y * 64;   // rows of A22
-  const int c0 = k0 + jb + blockIdx.x * 64;   // cols of A22
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int64_t ld = D.ld;
+  dz *__restrict__ A = D.A;
+  const int nt = (n - k0 - jb + 63) / 64;     // tiles per side of A22
+  const int tile = blockIdx.x - D.first_block;
+  const int r0 = k0 + jb + (tile / nt) * 64;  // rows of A22
+  const int c0 = k0 + jb + (tile % nt) * 64;  // cols of A22
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   v4d cre[2][2], cim[2][2];

@@ -47,11 +47,31 @@ __global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64
 constexpr int kTrsvNB = 256;
 __global__ void k_copy_block(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
 __global__ void k_add_near(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
-__global__ void k_lu_pivot(dz *A, int64_t ld, int n, int j, int k0, int jb, int32_t *ipiv, dz *rpiv, int32_t *info);
-__global__ void k_lu_col(dz *A, int64_t ld, int n, int j, int k0, int jb, const dz *rpiv);
-__global__ void k_lu_swap(dz *A, int64_t ld, int n, int k0, int jb, const int32_t *ipiv);
-__global__ void k_lu_trsm(dz *A, int64_t ld, int n, int k0, int jb);
-__global__ void k_lu_gemm(dz *A, int64_t ld, int n, int k0, int jb);
+// The panel, swap, triangular-solve and trailing-update launches of the
+// block LU advance up to kLuMaxDom domains at the same global column.
+constexpr int kLuNB = 64;
+constexpr int kLuMaxDom = 8;
+struct LuDom {
+  dz *A;              // the domain's block, row-major, leading dimension ld, factored in place
+  int64_t ld;
+  int n;
+  int first_block;    // first thread block of this domain in the launch
+  int32_t *ipiv;      // row swaps (LAPACK order)
+  int32_t *info;      // first zero pivot (1-based), 0 if none
+  dz *rpiv;           // reciprocal of the current pivot
+  double *pval;       // per-thread-block pivot candidates (k_lu_col)
+  int32_t *pidx;
+  int *counter;       // zero between launches
+};
+struct LuStep {
+  LuDom d[kLuMaxDom];
+  int ndom, j, k0;    // current column and panel start
+};
+__global__ void k_lu_pivot(LuStep st);
+__global__ void k_lu_col(LuStep st);
+__global__ void k_lu_swap(LuStep st);
+__global__ void k_lu_trsm(LuStep st);
+__global__ void k_lu_gemm(LuStep st);
 __global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
