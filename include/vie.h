@@ -92,6 +92,13 @@ typedef struct {
 int vie_create(vie_ctx **out, int device, void *hip_stream);
 int vie_destroy(vie_ctx *ctx);
 
+/* Move the context to another stream of the same device (hipStream_t; NULL =
+ * the null stream).  Once a workspace is bound it first waits for the work
+ * already issued on the old stream; before that the context has issued no
+ * device work, so a scheduler can prepare a context (mesh upload, workspace
+ * query) and pick the stream the request will run on later. */
+int vie_set_stream(vie_ctx *ctx, void *hip_stream);
+
 /* Upload a tetrahedral mesh of ONE unit cell [0,a] x [0,b] x [zmin,zmax]
  * (Sec. 2.2: only one unit cell is modelled, the periodic Green's function
  * supplies the Bloch condition; Fig. 1 geometry).

@@ -264,6 +264,15 @@ int vie_create(vie_ctx **out, int device, void *hip_stream) {
   return VIE_OK;
 }
 
+int vie_set_stream(vie_ctx *ctx, void *hip_stream) {
+  if (!ctx) return VIE_EINVAL;
+  HIPCK(hipSetDevice(ctx->device));
+  // before the workspace is bound the context has issued no device work
+  if (ctx->state >= S_BOUND) HIPCK(hipStreamSynchronize(ctx->stream));
+  ctx->stream = (hipStream_t)hip_stream;
+  return VIE_OK;
+}
+
 int vie_destroy(vie_ctx *ctx) {
   if (!ctx) return VIE_OK;
   (void)hipSetDevice(ctx->device);

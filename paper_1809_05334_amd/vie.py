@@ -57,6 +57,7 @@ _LIB = None
 _SIGS = {
     "vie_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
     "vie_destroy": (C.c_int, [C.c_void_p]),
+    "vie_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vie_mesh_upload": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_int32, C.c_double, C.c_double]),
     "vie_num_unknowns": (C.c_int64, [C.c_void_p]),
@@ -122,6 +123,11 @@ class Solver:
             raise VieError(rc, self.lib.vie_last_error(self.h).decode())
         return rc
 
+    def set_stream(self, stream):
+        """Run this context's work on `stream` (a torch.cuda.Stream) from now on."""
+        self._ck(self.lib.vie_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.vie_destroy(self.h)
@@ -163,7 +169,10 @@ class Solver:
         if nbytes == 0:
             raise VieError(VIE_EINVAL, "workspace size unavailable (precision/restart)")
         if workspace is None:
-            workspace = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=f"cuda:{self.device}")
+            # allocated on the context's stream, so torch's caching allocator
+            # does not hand the block to another stream while it is in use
+            with self.torch.cuda.stream(self.stream):
+                workspace = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=f"cuda:{self.device}")
         ptr = workspace.data_ptr()
         off = (-ptr) % 256
         self._ck(self.lib.vie_bind_workspace(self.h, C.c_void_p(ptr + off), workspace.numel() - off, precision, restart))

@@ -208,6 +208,8 @@ def config4_cells(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
         theta = np.deg2rad(rng.uniform(0.0, 60.0))
         phi = np.deg2rad(rng.uniform(0.0, 90.0))
         pol = int(rng.integers(0, 2))
+        while wood_margin(a, a, lam, theta, phi) < 0.03:   # keep clear of Rayleigh-Wood anomalies
+            lam = rng.uniform(400.0, 800.0)
         h_c = min(40.0, a / 3.0)
         h_f = h_f0
         while True:
@@ -223,6 +225,55 @@ def config4_cells(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
                       "h_fine": h_f, "h_coarse": h_c, "n_est": n,
                       "lambda": lam, "theta": theta, "phi": phi, "pol": pol})
     return cells
+
+
+def cell_mesh(cell):
+    """Mesh of a cell drawn by config4_cells / serve_trace."""
+    return osc_cell_mesh(cell["a"], cell["t_active"], cell["t_spacer"], cell["radius"], cell["h_fine"],
+                         cell["h_coarse"])
+
+
+def large_cell(rng, n_lo=15000, n_hi=60000):
+    """Config-2 geometry (200 nm period, 80 + 40 nm layers, r = 20 nm sphere)
+    with the fine spacing coarsened from 3.33 nm until N <= N_target."""
+    n_target = int(rng.uniform(n_lo, n_hi))
+    a, t_act, t_sp, radius, h_c = 200.0, 80.0, 40.0, 20.0, 20.0
+    h_f = 40.0 / 12.0
+    while True:
+        xs = graded_axis(a, a / 2 - radius, a / 2 + radius, h_f, h_c)
+        zs = np.concatenate([graded_axis(t_act, 0, 0, h_f, h_c), t_act + graded_axis(t_sp, 0, t_sp, h_f, h_c)[1:]])
+        n = count_unknowns_paired(xs, xs, zs)
+        if n <= n_target or h_f >= h_c / 2:
+            break
+        h_f *= 1.05
+    return {"a": a, "t_active": t_act, "t_spacer": t_sp, "radius": radius, "h_fine": h_f, "h_coarse": h_c,
+            "n_est": n}
+
+
+def serve_trace(rate, n_requests, seed=1, large_frac=0.1, n_lo=2000, n_hi=15000, large_lo=15000,
+                large_hi=60000):
+    """Poisson request stream (requests / s) of (cell, lambda, theta, phi, pol):
+    1 - large_frac of the cells from the config-4 generator, large_frac large
+    cells of the config-2 geometry family.  Returns dicts with the cell, the
+    illumination and the arrival time (s from the start)."""
+    rng = np.random.default_rng(seed)
+    small = config4_cells(n_requests, seed=seed + 1000, n_lo=n_lo, n_hi=n_hi)
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        if rng.uniform() < large_frac:
+            cell = large_cell(rng, large_lo, large_hi)
+        else:
+            cell = {k: small[i][k] for k in ("a", "t_active", "t_spacer", "radius", "h_fine", "h_coarse", "n_est")}
+        lam = rng.uniform(400.0, 800.0)
+        theta = np.deg2rad(rng.uniform(0.0, 60.0))
+        phi = np.deg2rad(rng.uniform(0.0, 90.0))
+        while wood_margin(cell["a"], cell["a"], lam, theta, phi) < 0.03:
+            lam = rng.uniform(400.0, 800.0)
+        out.append({"rid": i, "arrival": t, "cell": cell, "lambda": lam, "theta": theta, "phi": phi,
+                    "pol": int(rng.integers(0, 2))})
+    return out
 
 
 def wood_margin(a, b, lambda_nm, theta, phi, M=4):
