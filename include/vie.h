@@ -184,6 +184,31 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *ou
  * last solution or right-hand side.  VIE_ESTATE before a factorisation. */
 int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z);
 
+/* ---------------------------------------------------------------- tuning
+ * Launch shapes and graph capture.  None of them changes a result: every
+ * variant computes the same sums in the same order. */
+enum {
+  VIE_OPT_GRAPH_STEPS = 1,  /* Arnoldi steps per captured HIP graph, 0 = plain launches (default);
+                             * residual estimates are read back once per graph launch, so a solve
+                             * may run up to this many steps past convergence (unused) */
+  VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
+  VIE_OPT_TRSV_ROWS = 3     /* triangular-solve update rows per wave: 1, 2 or 4 (default) */
+};
+int vie_set_option(vie_ctx *ctx, int option, int value);
+int vie_get_option(const vie_ctx *ctx, int option, int *value);
+
+typedef struct {
+  double matvec_ms[3];   /* per product, rows per wave 2, 4, 8 */
+  double apply_ms[3];    /* per preconditioner apply, rows per wave 1, 2, 4 */
+  int matvec_rows, trsv_rows;   /* the picks, now set on the context */
+} vie_tuning;
+
+/* Autotuner: time each matvec and triangular-solve variant on this context's
+ * operator and factors (reps timed runs after one warm-up, HIP events) and
+ * keep the fastest.  Needs a completed factorisation; clobbers the solver's
+ * work vectors but not the last solution.  `out` may be NULL. */
+int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out);
+
 /* Residual history (estimate / ||b||) of the last solve; returns the count
  * written (at most cap). */
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);

@@ -35,7 +35,7 @@ struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
   Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, dinv, tpart, tcount;
-  Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, dpart, npart, scal, apart, kv, idx;
+  Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, apart, kv, idx, jd, rhist;
   size_t total = 0;
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
@@ -64,6 +64,12 @@ struct vie_ctx {
   std::vector<double> pack;         // packed lattice-sum table of the last fill
   int packlen = 0;
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
+  int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
+  int trsv_rw = 4;                  // triangular-solve update rows per wave (1, 2, 4)
+  int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
+  hipGraphExec_t gexec_g = nullptr; // graph_steps steps
+  hipGraphExec_t gexec_1 = nullptr; // one step (tail of a restart cycle)
+  int gexec_g_steps = 0;
   std::vector<int64_t> nrow;        // near-part CSR pattern (mixed precision), built on first use
   std::vector<int32_t> ncol;
   bool npat = false;
@@ -185,7 +191,9 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.sn, 16 * (restart + 1));
   put(L.g, 16 * (restart + 2));
   put(L.y, 16 * (restart + 1));
-  for (Region *r : {&L.vb, &L.vx, &L.vw, &L.vz, &L.vu, &L.vr, &L.vt}) put(*r, 16 * N);
+  for (Region *r : {&L.vb, &L.vx, &L.vw, &L.vz, &L.vu, &L.vr, &L.vt, &L.vin}) put(*r, 16 * N);
+  put(L.jd, 256);
+  put(L.rhist, 8 * (size_t)(restart + 1));
   put(L.dpart, 16 * (size_t)kRedBlocks * (restart + 1));
   put(L.npart, 8 * kRedBlocks);
   put(L.scal, 64);
@@ -200,6 +208,13 @@ int check(vie_ctx *ctx, State need, const char *what) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->state < need) return fail(ctx, VIE_ESTATE, "%s called out of order", what);
   return VIE_OK;
+}
+
+void drop_graphs(vie_ctx *ctx) {
+  if (ctx->gexec_g) (void)hipGraphExecDestroy(ctx->gexec_g);
+  if (ctx->gexec_1) (void)hipGraphExecDestroy(ctx->gexec_1);
+  ctx->gexec_g = ctx->gexec_1 = nullptr;
+  ctx->gexec_g_steps = 0;
 }
 
 void ensure_near_pattern(vie_ctx *ctx) {
@@ -227,13 +242,22 @@ ZOut zout(vie_ctx *ctx) {
 int matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  if (ctx->precision == VIE_MIXED_FP32)
-    hipLaunchKernelGGL(k_matvec_mixed, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream,
-                       (const fz *)ctx->ptr<fz>(L.Z), L.ld, N, (const int64_t *)ctx->ptr<int64_t>(L.nrow),
-                       (const int32_t *)ctx->ptr<int32_t>(L.ncol), (const dz *)ctx->ptr<dz>(L.nval), x, b, y);
-  else
-    hipLaunchKernelGGL(k_matvec, dim3(nblk(N, 4 * kMvRPW)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(L.Z),
-                       L.ld, N, x, b, y);
+  const int R = ctx->mv_rpw;
+  const dim3 grid(nblk(N, 4 * R)), blk(256);
+  if (ctx->precision == VIE_MIXED_FP32) {
+    const fz *Zs = ctx->ptr<fz>(L.Z);
+    const int64_t *rp = ctx->ptr<int64_t>(L.nrow);
+    const int32_t *cl = ctx->ptr<int32_t>(L.ncol);
+    const dz *vl = ctx->ptr<dz>(L.nval);
+    if (R == 2) hipLaunchKernelGGL(k_matvec_mixed_r2, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, x, b, y);
+    else if (R == 8) hipLaunchKernelGGL(k_matvec_mixed_r8, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, x, b, y);
+    else hipLaunchKernelGGL(k_matvec_mixed_r4, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, x, b, y);
+  } else {
+    const dz *Z = ctx->ptr<dz>(L.Z);
+    if (R == 2) hipLaunchKernelGGL(k_matvec_r2, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
+    else if (R == 8) hipLaunchKernelGGL(k_matvec_r8, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
+    else hipLaunchKernelGGL(k_matvec_r4, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "matvec: %s", hipGetErrorString(e));
   return VIE_OK;
@@ -278,6 +302,7 @@ int vie_destroy(vie_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  drop_graphs(ctx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -357,6 +382,7 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   }
   Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz);
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
+  drop_graphs(ctx);   // captured graphs hold pointers into the old workspace
   ctx->L = L;
   ctx->ws = (char *)dev_ptr;
   ctx->ws_bytes = bytes;
@@ -757,7 +783,9 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
       int blocks = 0;
       auto flush = [&]() {
         if (st.ndom == 0) return;
-        hipLaunchKernelGGL(k_trsv_step, dim3(blocks), dim3(1024), 0, ctx->stream, st);
+        if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_r1, dim3(blocks), dim3(1024), 0, ctx->stream, st);
+        else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_r2, dim3(blocks), dim3(1024), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_trsv_step_r4, dim3(blocks), dim3(1024), 0, ctx->stream, st);
         st.ndom = 0;
         blocks = 0;
       };
@@ -796,7 +824,7 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
           D.sol = out + off;
           rest = D.cm > 0 ? D.nb0 : 0;
         }
-        blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, kTrsvBlockRowsH) : 0);
+        blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
         if (++st.ndom == kTrsvMaxDom) flush();
       }
       flush();
@@ -825,33 +853,78 @@ int read_scalar(vie_ctx *ctx, const double *dev, double *host) {
   return VIE_OK;
 }
 
-// CGS2 column j: H[:, j] = V_{0..j}^H w twice, w orthogonalised in place.
-int cgs2(vie_ctx *ctx, int j, dz *w) {
+// One Arnoldi step of right-preconditioned GMRES for the column j held in
+// device memory (L.jd): z = M^-1 V_j, w = Z z, CGS2 against V_0..V_j into
+// H[:, j], h_{j+1,j} = ||w||, Givens update of H and g (|g_{j+1}| into
+// rhist[j]), V_{j+1} = w / h_{j+1,j}, j += 1.  The launches do not depend on
+// j, so the step can be captured in a graph and replayed.
+int arnoldi_step(vie_ctx *ctx) {
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  const dz *V = ctx->ptr<dz>(L.V);
-  dz *hcol = ctx->ptr<dz>(L.H) + (int64_t)j * (L.restart + 2);
-  dz *part = ctx->ptr<dz>(L.dpart);
+  dz *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g), *y = ctx->ptr<dz>(L.y);
+  dz *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz), *u = ctx->ptr<dz>(L.vu), *tmp = ctx->ptr<dz>(L.vt),
+     *vin = ctx->ptr<dz>(L.vin);
+  double *cs = ctx->ptr<double>(L.cs), *scal = ctx->ptr<double>(L.scal);
+  dz *sn = ctx->ptr<dz>(L.sn), *part = ctx->ptr<dz>(L.dpart);
+  int *jd = ctx->ptr<int>(L.jd);
+  const int ldh = L.restart + 2;
+  hipLaunchKernelGGL(k_arn_begin, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
+                     (const int *)jd, vin, N);
+  if (int rc = apply_minv(ctx, vin, z, tmp, u)) return rc;
+  if (int rc = matvec(ctx, z, nullptr, w)) return rc;
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_dots, dim3(kRedBlocks), dim3(256), 0, ctx->stream, V, L.ldv, j + 1, (const dz *)w, N, part);
-    hipLaunchKernelGGL(k_dots_reduce, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)part, kRedBlocks,
-                       j + 1, hcol, pass);
-    // pass 0 subtracts h; pass 1 subtracts only the correction, computed into y as scratch
-    if (pass == 0) {
-      hipLaunchKernelGGL(k_update, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, V, L.ldv, j + 1, (const dz *)hcol, w,
-                         N);
-      hipLaunchKernelGGL(k_copy, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, ctx->ptr<dz>(L.y),
-                         (const dz *)hcol, (int64_t)(j + 1));
-    } else {
-      // hcol now holds h0 + h1; the correction is hcol - y
-      hipLaunchKernelGGL(k_sub_into, dim3(nblk(j + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)hcol,
-                         ctx->ptr<dz>(L.y), (int64_t)(j + 1));
-      hipLaunchKernelGGL(k_update, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, V, L.ldv, j + 1,
-                         (const dz *)ctx->ptr<dz>(L.y), w, N);
-    }
+    hipLaunchKernelGGL(k_dots_j, dim3(kRedBlocks), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv, (const int *)jd,
+                       (const dz *)w, N, part);
+    hipLaunchKernelGGL(k_dots_reduce_j, dim3(nblk(L.restart + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)part,
+                       kRedBlocks, (const int *)jd, H, ldh, y, pass);
+    hipLaunchKernelGGL(k_update_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
+                       (const int *)jd, (const dz *)y, w, N);
   }
+  if (int rc = norm_to(ctx, w, N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
+  hipLaunchKernelGGL(k_givens_j, dim3(1), dim3(1), 0, ctx->stream, H, ldh, (const int *)jd,
+                     (const double *)(scal + 2), cs, sn, g, ctx->ptr<double>(L.rhist));
+  hipLaunchKernelGGL(k_scale_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)w,
+                     (const double *)(scal + 2), V, L.ldv, (const int *)jd, N);
+  hipLaunchKernelGGL(k_jinc, dim3(1), dim3(1), 0, ctx->stream, jd);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "cgs2: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "Arnoldi step: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+// Capture `steps` Arnoldi steps on the context's stream into an executable graph.
+int capture_steps(vie_ctx *ctx, int steps, hipGraphExec_t *out) {
+  hipGraph_t graph = nullptr;
+  HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  int rc = VIE_OK;
+  for (int q = 0; q < steps && rc == VIE_OK; ++q) rc = arnoldi_step(ctx);
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+// Issue `steps` Arnoldi steps: replay a captured graph when graph mode is on.
+int issue_steps(vie_ctx *ctx, int steps) {
+  if (ctx->graph_steps <= 0 || ctx->stream == nullptr) {
+    for (int q = 0; q < steps; ++q)
+      if (int rc = arnoldi_step(ctx)) return rc;
+    return VIE_OK;
+  }
+  hipGraphExec_t *ge = steps == 1 ? &ctx->gexec_1 : &ctx->gexec_g;
+  if (steps != 1 && ctx->gexec_g_steps != steps) {
+    if (ctx->gexec_g) (void)hipGraphExecDestroy(ctx->gexec_g);
+    ctx->gexec_g = nullptr;
+    ctx->gexec_g_steps = steps;
+  }
+  if (!*ge)
+    if (int rc = capture_steps(ctx, steps, ge)) return rc;
+  HIPCK(hipGraphLaunch(*ge, ctx->stream));
   return VIE_OK;
 }
 
@@ -870,8 +943,8 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
   dz *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g), *y = ctx->ptr<dz>(L.y);
   dz *b = ctx->ptr<dz>(L.vb), *x = ctx->ptr<dz>(L.vx), *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz),
      *u = ctx->ptr<dz>(L.vu), *r = ctx->ptr<dz>(L.vr), *tmp = ctx->ptr<dz>(L.vt);
-  double *cs = ctx->ptr<double>(L.cs), *scal = ctx->ptr<double>(L.scal);
-  dz *sn = ctx->ptr<dz>(L.sn);
+  double *scal = ctx->ptr<double>(L.scal), *rhist = ctx->ptr<double>(L.rhist);
+  int *jd = ctx->ptr<int>(L.jd);
   const int ldh = L.restart + 2;
   ctx->hist.clear();
   ctx->last_pol = pol;
@@ -906,34 +979,40 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
   int iters = 0, restarts = 0;
   double beta = bnorm, true_rel = 1.0;
   bool converged = false;
+  const int G = std::max(1, ctx->graph_steps);
   while (true) {
-    // V0 = r / beta ; g = beta e1
+    // V0 = r / beta ; g = beta e1 ; j = 0
     hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)r,
                        (const double *)(scal + 1), V, N);
     hipLaunchKernelGGL(k_ginit, dim3(1), dim3(256), 0, ctx->stream, g, restart + 1, (const double *)(scal + 1));
+    hipLaunchKernelGGL(k_jset, dim3(1), dim3(1), 0, ctx->stream, jd, 0);
     LAUNCHCK();
     int jdone = 0;
-    bool est_ok = false;
-    for (int j = 0; j < restart; ++j) {
-      if (int rc = apply_minv(ctx, V + (int64_t)j * L.ldv, z, tmp, u)) return rc;
-      if (int rc = matvec(ctx, z, nullptr, w)) return rc;
-      if (int rc = cgs2(ctx, j, w)) return rc;
-      if (int rc = norm_to(ctx, w, N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, ctx->stream, H, ldh, j, (const double *)(scal + 2), cs, sn, g,
-                         scal + 3);
-      hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)w,
-                         (const double *)(scal + 2), V + (int64_t)(j + 1) * L.ldv, N);
-      LAUNCHCK();
-      double res = 0;
-      if (int rc = read_scalar(ctx, scal + 3, &res)) return rc;
-      ++iters;
-      jdone = j + 1;
-      ctx->hist.push_back(res / bnorm);
-      if (res / bnorm <= tol) {
-        est_ok = true;
-        break;
+    bool est_ok = false, stop = false;
+    // Arnoldi steps in launches of up to G steps; the residual estimates of a
+    // launch are read back together.  Steps past the converged one are
+    // harmless: the update below uses only the first jdone columns.
+    for (int j = 0; j < restart && !stop;) {
+      const int steps = (ctx->graph_steps > 0 && j + G <= restart) ? G : 1;
+      if (int rc = issue_steps(ctx, steps)) return rc;
+      HIPCK(hipMemcpyAsync(ctx->pinned, rhist + j, 8 * steps, hipMemcpyDeviceToHost, ctx->stream));
+      HIPCK(hipStreamSynchronize(ctx->stream));
+      for (int q = 0; q < steps; ++q) {
+        const double res = ctx->pinned[q];
+        ++iters;
+        jdone = j + q + 1;
+        ctx->hist.push_back(res / bnorm);
+        if (res / bnorm <= tol) {
+          est_ok = true;
+          stop = true;
+          break;
+        }
+        if (iters >= max_iter) {
+          stop = true;
+          break;
+        }
       }
-      if (iters >= max_iter) break;
+      j += steps;
     }
     // x += M^{-1} V y
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, ctx->stream, (const dz *)H, ldh, jdone, (const dz *)g, y);
@@ -1174,6 +1253,93 @@ int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z) {
   if (int rc = apply_minv(ctx, in, out, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vr))) return rc;
   HIPCK(hipMemcpyAsync(z, out, 16 * N, hipMemcpyDeviceToHost, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
+  return VIE_OK;
+}
+
+int vie_set_option(vie_ctx *ctx, int option, int value) {
+  if (!ctx) return VIE_EINVAL;
+  switch (option) {
+    case VIE_OPT_GRAPH_STEPS:
+      if (value < 0 || value > 64) return fail(ctx, VIE_EINVAL, "graph steps must be in [0, 64]");
+      if (value != ctx->graph_steps) drop_graphs(ctx);
+      ctx->graph_steps = value;
+      return VIE_OK;
+    case VIE_OPT_MATVEC_ROWS:
+      if (value != 2 && value != 4 && value != 8) return fail(ctx, VIE_EINVAL, "matvec rows per wave: 2, 4 or 8");
+      if (value != ctx->mv_rpw) drop_graphs(ctx);
+      ctx->mv_rpw = value;
+      return VIE_OK;
+    case VIE_OPT_TRSV_ROWS:
+      if (value != 1 && value != 2 && value != 4) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2 or 4");
+      if (value != ctx->trsv_rw) drop_graphs(ctx);
+      ctx->trsv_rw = value;
+      return VIE_OK;
+  }
+  return fail(ctx, VIE_EINVAL, "unknown option %d", option);
+}
+
+int vie_get_option(const vie_ctx *ctx, int option, int *value) {
+  if (!ctx || !value) return VIE_EINVAL;
+  switch (option) {
+    case VIE_OPT_GRAPH_STEPS: *value = ctx->graph_steps; return VIE_OK;
+    case VIE_OPT_MATVEC_ROWS: *value = ctx->mv_rpw; return VIE_OK;
+    case VIE_OPT_TRSV_ROWS: *value = ctx->trsv_rw; return VIE_OK;
+  }
+  return VIE_EINVAL;
+}
+
+int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
+  if (int r = check(ctx, S_FACTORED, "vie_autotune")) return r;
+  if (reps < 1) return fail(ctx, VIE_EINVAL, "reps must be >= 1");
+  HIPCK(hipSetDevice(ctx->device));
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  dz *x = ctx->ptr<dz>(L.vz), *y = ctx->ptr<dz>(L.vw);
+  hipLaunchKernelGGL(k_fill_const, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N, 1.0, 0.5);
+  LAUNCHCK();
+  vie_tuning t{};
+  auto time_it = [&](auto &&issue, double *ms_out) -> int {
+    if (int rc = issue()) return rc;   // warm-up
+    HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
+    for (int r = 0; r < reps; ++r)
+      if (int rc = issue()) return rc;
+    HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
+    HIPCK(hipEventSynchronize(ctx->ev3));
+    float ms = 0;
+    HIPCK(hipEventElapsedTime(&ms, ctx->ev2, ctx->ev3));
+    *ms_out = ms / reps;
+    return VIE_OK;
+  };
+  const int mv_opts[3] = {2, 4, 8}, tr_opts[3] = {1, 2, 4};
+  double best = 1e300;
+  int pick = ctx->mv_rpw;
+  for (int i = 0; i < 3; ++i) {
+    ctx->mv_rpw = mv_opts[i];
+    if (int rc = time_it([&]() { return matvec(ctx, x, nullptr, y); }, &t.matvec_ms[i])) return rc;
+    if (t.matvec_ms[i] < best) {
+      best = t.matvec_ms[i];
+      pick = mv_opts[i];
+    }
+  }
+  ctx->mv_rpw = pick;
+  best = 1e300;
+  pick = ctx->trsv_rw;
+  for (int i = 0; i < 3; ++i) {
+    ctx->trsv_rw = tr_opts[i];
+    if (int rc = time_it([&]() { return apply_minv(ctx, x, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vt),
+                                                   ctx->ptr<dz>(L.vr)); },
+                         &t.apply_ms[i]))
+      return rc;
+    if (t.apply_ms[i] < best) {
+      best = t.apply_ms[i];
+      pick = tr_opts[i];
+    }
+  }
+  ctx->trsv_rw = pick;
+  drop_graphs(ctx);
+  t.matvec_rows = ctx->mv_rpw;
+  t.trsv_rows = ctx->trsv_rw;
+  if (out) *out = t;
   return VIE_OK;
 }
 

@@ -25,14 +25,14 @@ __device__ __forceinline__ double wsum(double v) {
 // chunks shared by the block, Z is streamed once with non-temporal loads.
 constexpr int kMvChunk = 1024;
 
-__global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_t ld, int64_t N,
-                                                const dz *__restrict__ x, const dz *__restrict__ b,
-                                                dz *__restrict__ y) {
-  __shared__ dz xs[kMvChunk];
+template <int RPW>
+__device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld, int64_t N,
+                                            const dz *__restrict__ x, const dz *__restrict__ b, dz *__restrict__ y,
+                                            dz *xs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * kMvRPW;
-  double are[kMvRPW], aim[kMvRPW];
-  for (int r = 0; r < kMvRPW; ++r) are[r] = aim[r] = 0.0;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
+  double are[RPW], aim[RPW];
+  for (int r = 0; r < RPW; ++r) are[r] = aim[r] = 0.0;
   const double *Zd = reinterpret_cast<const double *>(Z);
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_
     for (int cc = lane; cc < len; cc += 64) {
       const dz xv = xs[cc];
 #pragma unroll
-      for (int r = 0; r < kMvRPW; ++r) {
+      for (int r = 0; r < RPW; ++r) {
         const int64_t row = row0 + r;
         if (row < N) {
           const int64_t o = 2 * (row * ld + c0 + cc);
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_
       }
     }
   }
-  for (int r = 0; r < kMvRPW; ++r) {
+  for (int r = 0; r < RPW; ++r) {
     const double sr = wsum(are[r]), si = wsum(aim[r]);
     const int64_t row = row0 + r;
     if (lane == 0 && row < N) {
@@ -64,6 +64,17 @@ __global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_
   }
 }
 
+#define VIE_MATVEC(R)                                                                                           \
+  __global__ __launch_bounds__(256) void k_matvec_r##R(const dz *__restrict__ Z, int64_t ld, int64_t N,         \
+                                                       const dz *__restrict__ x, const dz *__restrict__ b,      \
+                                                       dz *__restrict__ y) {                                    \
+    __shared__ dz xs[kMvChunk];                                                                                 \
+    matvec_body<R>(Z, ld, N, x, b, y, xs);                                                                      \
+  }
+VIE_MATVEC(2)
+VIE_MATVEC(4)
+VIE_MATVEC(8)
+
 // y = Z x (or b - Z x) for the mixed-precision operator Z = Zs + Zn: Zs the
 // complex-FP32 dense far part (row-major, ld a multiple of 8), Zn the FP64
 // near part in CSR.  Arithmetic and accumulation in FP64.  Same row mapping
@@ -71,16 +82,16 @@ __global__ __launch_bounds__(256) void k_matvec(const dz *__restrict__ Z, int64_
 // row, then the wave adds its rows' near entries.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs, int64_t ld, int64_t N,
-                                                      const int64_t *__restrict__ rowptr,
-                                                      const int32_t *__restrict__ cols, const dz *__restrict__ vals,
-                                                      const dz *__restrict__ x, const dz *__restrict__ b,
-                                                      dz *__restrict__ y) {
-  __shared__ dz xs[kMvChunk];
+template <int RPW>
+__device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int64_t ld, int64_t N,
+                                                  const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ cols, const dz *__restrict__ vals,
+                                                  const dz *__restrict__ x, const dz *__restrict__ b,
+                                                  dz *__restrict__ y, dz *xs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * kMvRPW;
-  double are[kMvRPW], aim[kMvRPW];
-  for (int r = 0; r < kMvRPW; ++r) are[r] = aim[r] = 0.0;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
+  double are[RPW], aim[RPW];
+  for (int r = 0; r < RPW; ++r) are[r] = aim[r] = 0.0;
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
     __syncthreads();
@@ -90,7 +101,7 @@ __global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs,
       const dz x0 = xs[cc];
       const dz x1 = cc + 1 < len ? xs[cc + 1] : mk(0, 0);
 #pragma unroll
-      for (int r = 0; r < kMvRPW; ++r) {
+      for (int r = 0; r < RPW; ++r) {
         const int64_t row = row0 + r;
         if (row < N) {
           const v4f z = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Zs + row * ld + c0 + cc));
@@ -103,7 +114,7 @@ __global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs,
     }
   }
 #pragma unroll
-  for (int r = 0; r < kMvRPW; ++r) {
+  for (int r = 0; r < RPW; ++r) {
     const int64_t row = row0 + r;
     if (row < N)
       for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) {
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs,
         aim[r] = fma(v.re, xv.im, fma(v.im, xv.re, aim[r]));
       }
   }
-  for (int r = 0; r < kMvRPW; ++r) {
+  for (int r = 0; r < RPW; ++r) {
     const double sr = wsum(are[r]), si = wsum(aim[r]);
     const int64_t row = row0 + r;
     if (lane == 0 && row < N) {
@@ -122,48 +133,17 @@ __global__ __launch_bounds__(256) void k_matvec_mixed(const fz *__restrict__ Zs,
   }
 }
 
-// Partial inner products h_i = sum_k conj(V_i[k]) w[k], i < nv, per block:
-// part[blockIdx.x * nv + i].  V column-major: V_i = V + i * ldv.
-__global__ __launch_bounds__(256) void k_dots(const dz *__restrict__ V, int64_t ldv, int nv,
-                                              const dz *__restrict__ w, int64_t N, dz *__restrict__ part) {
-  __shared__ dz red[4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
-  for (int i = 0; i < nv; ++i) {
-    const dz *Vi = V + (int64_t)i * ldv;
-    dz s = mk(0, 0);
-    for (int64_t k = lo + tid; k < hi; k += 256) {
-      const dz v = Vi[k], ww = w[k];
-      s.re = fma(v.re, ww.re, fma(v.im, ww.im, s.re));
-      s.im = fma(v.re, ww.im, fma(-v.im, ww.re, s.im));
-    }
-    s = wsum(s);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    if (tid == 0) part[(int64_t)blockIdx.x * nv + i] = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
+#define VIE_MATVEC_MIXED(R)                                                                                     \
+  __global__ __launch_bounds__(256) void k_matvec_mixed_r##R(                                                   \
+      const fz *__restrict__ Zs, int64_t ld, int64_t N, const int64_t *__restrict__ rowptr,                     \
+      const int32_t *__restrict__ cols, const dz *__restrict__ vals, const dz *__restrict__ x,                  \
+      const dz *__restrict__ b, dz *__restrict__ y) {                                                           \
+    __shared__ dz xs[kMvChunk];                                                                                 \
+    matvec_mixed_body<R>(Zs, ld, N, rowptr, cols, vals, x, b, y, xs);                                           \
   }
-}
-
-// h[i] (+)= sum_b part[b * nv + i]; one thread per i (nblk small).
-__global__ void k_dots_reduce(const dz *__restrict__ part, int nblk, int nv, dz *__restrict__ h, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
-  dz s = mk(0, 0);
-  for (int b = 0; b < nblk; ++b) s = s + part[(int64_t)b * nv + i];
-  h[i] = accumulate ? h[i] + s : s;
-}
-
-// w[k] -= sum_{i<nv} V_i[k] c[i]
-__global__ __launch_bounds__(256) void k_update(const dz *__restrict__ V, int64_t ldv, int nv,
-                                                const dz *__restrict__ c, dz *__restrict__ w, int64_t N) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  dz s = w[k];
-  for (int i = 0; i < nv; ++i) s = s - V[(int64_t)i * ldv + k] * c[i];
-  w[k] = s;
-}
+VIE_MATVEC_MIXED(2)
+VIE_MATVEC_MIXED(4)
+VIE_MATVEC_MIXED(8)
 
 // y[k] = sum_{i<nv} V_i[k] c[i]
 __global__ __launch_bounds__(256) void k_combine(const dz *__restrict__ V, int64_t ldv, int nv,
@@ -210,12 +190,6 @@ __global__ void k_axpy(dz *__restrict__ x, const dz *__restrict__ u, int64_t N) 
   if (k < N) x[k] = x[k] + u[k];
 }
 
-// y = a - y
-__global__ void k_sub_into(const dz *__restrict__ a, dz *__restrict__ y, int64_t n) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) y[k] = a[k] - y[k];
-}
-
 __global__ void k_fill_const(dz *__restrict__ x, int64_t N, double re, double im) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) x[k] = mk(re, im);
@@ -226,15 +200,92 @@ __global__ void k_copy(dz *__restrict__ d, const dz *__restrict__ s, int64_t N) 
   if (k < N) d[k] = s[k];
 }
 
+// ------------------------------------------------------------ Arnoldi step
+// The kernels of one Arnoldi step read the column index j from device memory
+// (*jd), so the step issues the same launches for every j and can be
+// captured once in a HIP graph and replayed.  k_jinc advances *jd at the end
+// of the step.
+
+// vin = V_j
+__global__ void k_arn_begin(const dz *__restrict__ V, int64_t ldv, const int *__restrict__ jd, dz *__restrict__ vin,
+                            int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) vin[k] = V[(int64_t)(*jd) * ldv + k];
+}
+
+// partial inner products with V_0 .. V_j (k_dots with nv = j + 1)
+__global__ __launch_bounds__(256) void k_dots_j(const dz *__restrict__ V, int64_t ldv, const int *__restrict__ jd,
+                                                const dz *__restrict__ w, int64_t N, dz *__restrict__ part) {
+  __shared__ dz red[4];
+  const int nv = *jd + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
+  for (int i = 0; i < nv; ++i) {
+    const dz *Vi = V + (int64_t)i * ldv;
+    dz s = mk(0, 0);
+    for (int64_t k = lo + tid; k < hi; k += 256) {
+      const dz v = Vi[k], ww = w[k];
+      s.re = fma(v.re, ww.re, fma(v.im, ww.im, s.re));
+      s.im = fma(v.re, ww.im, fma(-v.im, ww.re, s.im));
+    }
+    s = wsum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (tid == 0) part[(int64_t)blockIdx.x * nv + i] = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+  }
+}
+
+// s_i = sum_b part[b][i]; y_i = s_i; H[i][j] = s_i (pass 0) or += s_i (pass 1)
+__global__ void k_dots_reduce_j(const dz *__restrict__ part, int nblk, const int *__restrict__ jd,
+                                dz *__restrict__ H, int ldh, dz *__restrict__ y, int pass) {
+  const int j = *jd, nv = j + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  dz s = mk(0, 0);
+  for (int b = 0; b < nblk; ++b) s = s + part[(int64_t)b * nv + i];
+  dz *h = H + (int64_t)j * ldh;
+  h[i] = pass ? h[i] + s : s;
+  y[i] = s;
+}
+
+// w[k] -= sum_{i<=j} V_i[k] c[i]
+__global__ __launch_bounds__(256) void k_update_j(const dz *__restrict__ V, int64_t ldv, const int *__restrict__ jd,
+                                                  const dz *__restrict__ c, dz *__restrict__ w, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int nv = *jd + 1;
+  dz s = w[k];
+  for (int i = 0; i < nv; ++i) s = s - V[(int64_t)i * ldv + k] * c[i];
+  w[k] = s;
+}
+
+// V_{j+1} = w / *nrm
+__global__ void k_scale_j(const dz *__restrict__ w, const double *__restrict__ nrm, dz *__restrict__ V, int64_t ldv,
+                          const int *__restrict__ jd, int64_t N) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double s = 1.0 / *nrm;
+  V[(int64_t)(*jd + 1) * ldv + k] = s * w[k];
+}
+
+__global__ void k_jset(int *__restrict__ jd, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *jd = v;
+}
+
+__global__ void k_jinc(int *__restrict__ jd) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *jd = *jd + 1;
+}
+
 // GMRES state on the device: H (ldh x m, column j holds h_{0..j+1, j}),
 // Givens cosines (real) and sines (complex), g (m+1).
 // Arnoldi column j: h[0..j] from CGS2, hn = ||w||.  Apply the previous
 // rotations to column j, form the new one, update g, write |g[j+1]|.
-__global__ void k_givens(dz *__restrict__ H, int ldh, int j, const double *__restrict__ hn,
-                         double *__restrict__ cs, dz *__restrict__ sn, dz *__restrict__ g, double *__restrict__ res) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void givens_step(dz *__restrict__ H, int ldh, int j, double hnv, double *__restrict__ cs,
+                            dz *__restrict__ sn, dz *__restrict__ g, double *__restrict__ res) {
   dz *h = H + (int64_t)j * ldh;
-  h[j + 1] = mk(*hn, 0.0);
+  h[j + 1] = mk(hnv, 0.0);
   for (int i = 0; i < j; ++i) {
     // [c  s; -conj(s) c] acting on (h_i, h_{i+1})
     const dz a = h[i], b = h[i + 1];
@@ -263,6 +314,15 @@ __global__ void k_givens(dz *__restrict__ H, int ldh, int j, const double *__res
   g[j] = c * gj;
   g[j + 1] = mk(0, 0) - conjz(s) * gj;
   *res = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im);
+}
+
+// k_givens for the j in *jd; also records |g[j+1]| in hist[j]
+__global__ void k_givens_j(dz *__restrict__ H, int ldh, const int *__restrict__ jd, const double *__restrict__ hn,
+                           double *__restrict__ cs, dz *__restrict__ sn, dz *__restrict__ g,
+                           double *__restrict__ hist) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int j = *jd;
+  givens_step(H, ldh, j, *hn, cs, sn, g, hist + j);
 }
 
 // y = R^{-1} g for the leading k x k upper triangle of H (single thread).

@@ -393,7 +393,6 @@ __device__ __forceinline__ dz wave_sum(dz v) {
 // into sol and puts the counter back to zero.  The domain's further thread
 // blocks update the remaining rows, 64 per block, four rows per wave.
 constexpr int kTrsvGroups = kTrsvGroupsH;
-constexpr int kTrsvBlockRows = kTrsvBlockRowsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
 
 __device__ __forceinline__ dz row_dot(const dz *__restrict__ Fi, int cm, const dz *zc, int lane) {
@@ -406,11 +405,15 @@ __device__ __forceinline__ dz row_dot(const dz *__restrict__ Fi, int cm, const d
   return s;
 }
 
-__global__ __launch_bounds__(1024) void k_trsv_step(TrsvStep st) {
+// RW rows per wave in the update blocks (16 RW rows per thread block); the
+// autotuner picks RW per context.
+template <int RW>
+__device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   __shared__ dz zc[kTrsvNB];
   __shared__ dz rg[16];
   __shared__ dz red[4][kTrsvNB];
   __shared__ int last;
+  constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int d = 0;
   while (d + 1 < st.ndom && (int)blockIdx.x >= st.d[d + 1].first_block) ++d;
@@ -487,27 +490,32 @@ __global__ __launch_bounds__(1024) void k_trsv_step(TrsvStep st) {
     rlo = (blk - kTrsvGroups) * kTrsvBlockRows;
     rhi = min(nb0, rlo + kTrsvBlockRows);
   }
-  const int i0 = rlo + 4 * wave;
-  dz f[4][kTrsvCol];
+  const int i0 = rlo + RW * wave;
+  dz f[RW][kTrsvCol];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c)
       f[q][c] = (i0 + q < rhi && lane + 64 * c < cm) ? D.F[(int64_t)(i0 + q) * ld + cb0 + lane + 64 * c] : mk(0, 0);
   __syncthreads();
-  dz s[4];
+  dz s[RW];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < RW; ++q) {
     s[q] = mk(0, 0);
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c) s[q] = s[q] + f[q][c] * zc[lane + 64 * c];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
-  if (lane < 4 && i0 + lane < rhi) {
-    const dz v = lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3];
-    D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
-  }
+  for (int q = 0; q < RW; ++q) s[q] = wave_sum(s[q]);
+  dz v = s[0];
+#pragma unroll
+  for (int q = 1; q < RW; ++q)
+    if (lane == q) v = s[q];
+  if (lane < RW && i0 + lane < rhi) D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
 }
+
+__global__ __launch_bounds__(1024) void k_trsv_step_r1(TrsvStep st) { trsv_step_body<1>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_r2(TrsvStep st) { trsv_step_body<2>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_r4(TrsvStep st) { trsv_step_body<4>(st); }
 
 }  // namespace vie

@@ -78,7 +78,6 @@ __global__ void k_diag_inv(const dz *F, int64_t ld, int n, int nb, int lower, dz
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
 // domains by one diagonal block each (k_lu.hip).
 constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
-constexpr int kTrsvBlockRowsH = 64;          // rows updated per further thread block
 constexpr int kTrsvMaxDom = 8;
 struct TrsvDom {
   const dz *F;        // the domain's LU factors (row-major, leading dimension ld)
@@ -93,16 +92,21 @@ struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
   int ndom, lower;
 };
-__global__ void k_trsv_step(TrsvStep st);
+// variants by rows per wave of the update blocks (1, 2, 4 -> 16, 32, 64 rows per block)
+__global__ void k_trsv_step_r1(TrsvStep st);
+__global__ void k_trsv_step_r2(TrsvStep st);
+__global__ void k_trsv_step_r4(TrsvStep st);
 
-// Krylov (k_krylov.hip)
-constexpr int kMvRPW = 4;
-__global__ void k_matvec(const dz *Z, int64_t ld, int64_t N, const dz *x, const dz *b, dz *y);
-__global__ void k_matvec_mixed(const fz *Zs, int64_t ld, int64_t N, const int64_t *rowptr, const int32_t *cols,
-                               const dz *vals, const dz *x, const dz *b, dz *y);
-__global__ void k_dots(const dz *V, int64_t ldv, int nv, const dz *w, int64_t N, dz *part);
-__global__ void k_dots_reduce(const dz *part, int nblk, int nv, dz *h, int accumulate);
-__global__ void k_update(const dz *V, int64_t ldv, int nv, const dz *c, dz *w, int64_t N);
+// Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block
+// of 4 waves owns 4 * RPW rows; the autotuner picks one per context.
+#define VIE_DECL_MATVEC(R)                                                                                      \
+  __global__ void k_matvec_r##R(const dz *Z, int64_t ld, int64_t N, const dz *x, const dz *b, dz *y);           \
+  __global__ void k_matvec_mixed_r##R(const fz *Zs, int64_t ld, int64_t N, const int64_t *rowptr,               \
+                                      const int32_t *cols, const dz *vals, const dz *x, const dz *b, dz *y);
+VIE_DECL_MATVEC(2)
+VIE_DECL_MATVEC(4)
+VIE_DECL_MATVEC(8)
+#undef VIE_DECL_MATVEC
 __global__ void k_combine(const dz *V, int64_t ldv, int nv, const dz *c, dz *y, int64_t N);
 __global__ void k_norm2(const dz *w, int64_t N, double *part);
 __global__ void k_norm_reduce(const double *part, int nblk, double *out);
@@ -110,10 +114,17 @@ __global__ void k_scale(const dz *w, const double *nrm, dz *v, int64_t N);
 __global__ void k_axpy(dz *x, const dz *u, int64_t N);
 __global__ void k_copy(dz *d, const dz *s, int64_t N);
 __global__ void k_fill_const(dz *x, int64_t N, double re, double im);
-__global__ void k_sub_into(const dz *a, dz *y, int64_t n);
-__global__ void k_givens(dz *H, int ldh, int j, const double *hn, double *cs, dz *sn, dz *g, double *res);
 __global__ void k_backsolve(const dz *H, int ldh, int k, const dz *g, dz *y);
 __global__ void k_ginit(dz *g, int m1, const double *beta);
+// one Arnoldi step with the column index j read from device memory
+__global__ void k_arn_begin(const dz *V, int64_t ldv, const int *jd, dz *vin, int64_t N);
+__global__ void k_dots_j(const dz *V, int64_t ldv, const int *jd, const dz *w, int64_t N, dz *part);
+__global__ void k_dots_reduce_j(const dz *part, int nblk, const int *jd, dz *H, int ldh, dz *y, int pass);
+__global__ void k_update_j(const dz *V, int64_t ldv, const int *jd, const dz *c, dz *w, int64_t N);
+__global__ void k_scale_j(const dz *w, const double *nrm, dz *V, int64_t ldv, const int *jd, int64_t N);
+__global__ void k_givens_j(dz *H, int ldh, const int *jd, const double *hn, double *cs, dz *sn, dz *g, double *hist);
+__global__ void k_jset(int *jd, int v);
+__global__ void k_jinc(int *jd);
 
 // outputs (k_absorb.hip)
 __global__ void k_absorb(int64_t nt, int ndom, const TetGeom *tg, const TetFace *t2f, const int32_t *dom,

@@ -54,6 +54,18 @@ class FillStats(C.Structure):
 
 _LIB = None
 
+VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS = 1, 2, 3
+
+
+class Tuning(C.Structure):
+    _fields_ = [("matvec_ms", C.c_double * 3), ("apply_ms", C.c_double * 3),
+                ("matvec_rows", C.c_int), ("trsv_rows", C.c_int)]
+
+    def as_dict(self):
+        return {"matvec_ms": list(self.matvec_ms), "apply_ms": list(self.apply_ms),
+                "matvec_rows": self.matvec_rows, "trsv_rows": self.trsv_rows}
+
+
 _SIGS = {
     "vie_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
     "vie_destroy": (C.c_int, [C.c_void_p]),
@@ -78,6 +90,9 @@ _SIGS = {
     "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
     "vie_bench_matvec": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
     "vie_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_set_option": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "vie_get_option": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "vie_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
 }
 
 
@@ -253,6 +268,20 @@ class Solver:
         out = np.zeros(self.num_unknowns(), np.complex128)
         self._ck(self.lib.vie_precond_apply(self.h, _p(vin), _p(out)))
         return out
+
+    def set_option(self, option, value):
+        self._ck(self.lib.vie_set_option(self.h, int(option), int(value)))
+
+    def get_option(self, option):
+        v = C.c_int()
+        self._ck(self.lib.vie_get_option(self.h, int(option), C.byref(v)))
+        return v.value
+
+    def autotune(self, reps=5):
+        """Time the matvec and triangular-solve variants, keep the fastest (needs factor())."""
+        t = Tuning()
+        self._ck(self.lib.vie_autotune(self.h, int(reps), C.byref(t)))
+        return t.as_dict()
 
     def bench_matvec(self, reps=10):
         ms = C.c_double()
