@@ -550,7 +550,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   for (int g = 0; g < C * C; ++g) {
     const int np = ctx->near_off[g + 1] - ctx->near_off[g];
     if (!np) continue;
-    hipLaunchKernelGGL(k_tt_near, dim3(nblk(np, 128)), dim3(128), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
+    hipLaunchKernelGGL(k_tt_near, dim3(nblk(16 * (int64_t)np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                        ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
                        ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
                        (const dz *)kappa, (const dz *)inveps, k0sq9, zo);
@@ -732,10 +732,9 @@ int vie_precond_factor(vie_ctx *ctx) {
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
     dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
     dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
-    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n,
-                       kTrsvNB, 1, DL);
-    hipLaunchKernelGGL(k_diag_inv, dim3(nbk), dim3(kTrsvNB), 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n,
-                       kTrsvNB, 0, DU);
+    const dim3 ig(nbk, kTrsvNB / 32), ib(128);   // 32 columns of one inverse per thread block
+    hipLaunchKernelGGL(k_diag_inv, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, DL);
+    hipLaunchKernelGGL(k_diag_inv, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, DU);
     LAUNCHCK();
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));

@@ -197,8 +197,12 @@ __global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack,
 
 // Touching tet pairs: 14-point outer rule on T; per touching image the closed
 // form int_S 1/R and int_S (r'-r)/R; 4-point inner rule for the remainder.
-// The self pair also adds the mass term <f_m, f_n / eps_r>.
-__global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+// The self pair also adds the mass term <f_m, f_n / eps_r>.  Sixteen lanes
+// share a pair: lane q < 14 takes outer point q, the moments are summed
+// across the 16 lanes by shuffles, and the pair's first lane scatters.
+__device__ __forceinline__ dz shfl_xor_dz(dz v, int o) { return mk(__shfl_xor(v.re, o), __shfl_xor(v.im, o)); }
+
+__global__ __launch_bounds__(256) void k_tt_near(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                  const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                  const int32_t *__restrict__ lt, const int32_t *__restrict__ ls,
                                                  const int32_t *__restrict__ lmask, int npairs,
@@ -209,16 +213,18 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npairs) return;
-  const int T = lt[i], S = ls[i], mask = lmask[i];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid >> 4, q = gid & 15;
+  const bool act = i < npairs;
+  // lanes past the last pair stay in the shuffles below with zero moments
+  const int ii = act ? i : npairs - 1;
+  const int T = lt[ii], S = ls[ii], mask = lmask[ii];
   const TetGeom gt = tg[T];
   const TetGeom gs = tg[S];
   const double wq = 0.25 * gs.vol;
   Moments M;
   moments_zero(M);
-#pragma unroll 1
-  for (int q = 0; q < 14; ++q) {
+  if (act && q < 14) {
     double r[3], u[3];
     for (int d = 0; d < 3; ++d) {
       double s = 0;
@@ -265,6 +271,17 @@ __global__ __launch_bounds__(128) void k_tt_near(const double *__restrict__ pack
     for (int d = 0; d < 3; ++d) axpy(us, u[d], s1[d]);
     axpy(M.muv, w, us);
   }
+  // sum the 16 lanes of the pair (fixed order: deterministic)
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    M.m0 = M.m0 + shfl_xor_dz(M.m0, o);
+    M.muv = M.muv + shfl_xor_dz(M.muv, o);
+    for (int d = 0; d < 3; ++d) {
+      M.mu[d] = M.mu[d] + shfl_xor_dz(M.mu[d], o);
+      M.mv[d] = M.mv[d] + shfl_xor_dz(M.mv[d], o);
+    }
+  }
+  if (!act || q != 0) return;
   scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, true);
   if (T == S) {
     // mass <f_m, f_n / eps_r>: alpha_k gsrc_l / (9 eps) int_T (r - v_k).(r - v_l), 4-point rule (exact)

@@ -330,40 +330,69 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
   if (i < n) z[off + i] = v[off + perm[i]];
 }
 
-// Inverses of the nb x nb diagonal blocks of L (unit lower) and U (upper),
-// computed once per factorisation and stored TRANSPOSED: block b of DT holds
-// inv(T_bb)^T row-major (nb x nb), T_bb the diagonal block at row b*nb.  One
-// thread block per diagonal block; thread j forms column j of the inverse
-// (row j of DT, contiguous) by substitution.
-__global__ __launch_bounds__(kTrsvNB) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb, int lower,
-                                                  dz *__restrict__ DT) {
+// Inverses of the kTrsvNB x kTrsvNB diagonal blocks of L (unit lower) and U
+// (upper), computed once per factorisation and stored TRANSPOSED: block b of
+// DT holds inv(T_bb)^T row-major, T_bb the diagonal block at row b*nb.  A
+// thread block forms 32 columns of one inverse by substitution; the columns
+// live in LDS, and each column's dot products are split over 4 lanes
+// (residues of the summation index mod 4, combined by shuffles).  A lane only
+// reads back the entries it wrote itself, so no barrier is needed inside the
+// substitution.
+constexpr int kInvCols = 32;
+
+__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb,
+                                                          int lower, dz *__restrict__ DT) {
+  __shared__ dz X[kInvCols][kTrsvNB];
   const int b = blockIdx.x;
   const int b0 = b * nb;
   const int m = min(nb, n - b0);
-  const int j = threadIdx.x;
-  if (j >= nb) return;
-  dz *X = DT + ((int64_t)b * nb + j) * nb;   // X[i] = inv(T)[i][j]
-  for (int i = 0; i < nb; ++i) X[i] = mk(0, 0);
-  if (j >= m) return;
+  const int cl = threadIdx.x >> 2, t = threadIdx.x & 3;
+  const int j = blockIdx.y * kInvCols + cl;      // column of the inverse
+  for (int i = t; i < nb; i += 4) X[cl][i] = mk(0, 0);
   const dz *T = F + (int64_t)b0 * ld + b0;
-  if (lower) {
-    X[j] = mk(1, 0);
-    for (int i = j + 1; i < m; ++i) {
-      dz s = mk(0, 0);
-      for (int l = j; l < i; ++l) s = s + T[(int64_t)i * ld + l] * X[l];
-      X[i] = mk(0, 0) - s;
+  auto inv = [](dz d) {
+    const double den = d.re * d.re + d.im * d.im;
+    return mk(d.re / den, -d.im / den);
+  };
+  if (j < m) {
+    if (lower) {
+      if ((j & 3) == t) X[cl][j] = mk(1, 0);
+      for (int i = j + 1; i < m; ++i) {
+        const dz *Ti = T + (int64_t)i * ld;
+        dz s0 = mk(0, 0), s1 = mk(0, 0);
+        int l = j + ((t - j) & 3);                 // first l >= j with l = t (mod 4)
+        for (; l + 4 < i; l += 8) {
+          s0 = s0 + Ti[l] * X[cl][l];
+          s1 = s1 + Ti[l + 4] * X[cl][l + 4];
+        }
+        if (l < i) s0 = s0 + Ti[l] * X[cl][l];
+        dz s = s0 + s1;
+        s = s + mk(__shfl_xor(s.re, 1), __shfl_xor(s.im, 1));
+        s = s + mk(__shfl_xor(s.re, 2), __shfl_xor(s.im, 2));
+        if ((i & 3) == t) X[cl][i] = mk(0, 0) - s;
+      }
+    } else {
+      if ((j & 3) == t) X[cl][j] = inv(T[(int64_t)j * ld + j]);
+      for (int i = j - 1; i >= 0; --i) {
+        const dz *Ti = T + (int64_t)i * ld;
+        dz s0 = mk(0, 0), s1 = mk(0, 0);
+        int l = (i + 1) + ((t - (i + 1)) & 3);     // first l > i with l = t (mod 4)
+        for (; l + 4 <= j; l += 8) {
+          s0 = s0 + Ti[l] * X[cl][l];
+          s1 = s1 + Ti[l + 4] * X[cl][l + 4];
+        }
+        if (l <= j) s0 = s0 + Ti[l] * X[cl][l];
+        dz s = s0 + s1;
+        s = s + mk(__shfl_xor(s.re, 1), __shfl_xor(s.im, 1));
+        s = s + mk(__shfl_xor(s.re, 2), __shfl_xor(s.im, 2));
+        if ((i & 3) == t) X[cl][i] = mk(0, 0) - s * inv(Ti[i]);
+      }
     }
-  } else {
-    auto inv = [](dz d) {
-      const double den = d.re * d.re + d.im * d.im;
-      return mk(d.re / den, -d.im / den);
-    };
-    X[j] = inv(T[(int64_t)j * ld + j]);
-    for (int i = j - 1; i >= 0; --i) {
-      dz s = mk(0, 0);
-      for (int l = i + 1; l <= j; ++l) s = s + T[(int64_t)i * ld + l] * X[l];
-      X[i] = mk(0, 0) - s * inv(T[(int64_t)i * ld + i]);
-    }
+  }
+  __syncthreads();
+  if (j < nb) {
+    dz *row = DT + ((int64_t)b * nb + j) * nb;   // row j of DT = column j of the inverse
+    for (int i = t; i < nb; i += 4) row[i] = X[cl][i];
   }
 }
 
