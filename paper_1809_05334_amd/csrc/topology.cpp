@@ -15,6 +15,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <thread>
 #include <unordered_map>
 
 #include "host.h"
@@ -333,16 +334,23 @@ void build_near_pattern(const MeshTopology &t, std::vector<int64_t> &rowptr, std
         for (int l = 0; l < 4; ++l) raw[pos[m]++] = t.t2f[4 * S + l].unknown;
       }
     }
+  // sort and de-duplicate every row (rows split over host threads), then compact
+  std::vector<int64_t> uniq(N, 0);
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nth; ++w)
+    pool.emplace_back([&, w]() {
+      for (int64_t m = w; m < N; m += nth) {
+        auto b = raw.begin() + cnt[m], e = raw.begin() + cnt[m + 1];
+        std::sort(b, e);
+        uniq[m] = std::unique(b, e) - b;
+      }
+    });
+  for (auto &th : pool) th.join();
   rowptr.assign(N + 1, 0);
-  cols.clear();
-  cols.reserve(raw.size() / 2);
-  for (int64_t m = 0; m < N; ++m) {
-    auto b = raw.begin() + cnt[m], e = raw.begin() + cnt[m + 1];
-    std::sort(b, e);
-    e = std::unique(b, e);
-    cols.insert(cols.end(), b, e);
-    rowptr[m + 1] = (int64_t)cols.size();
-  }
+  for (int64_t m = 0; m < N; ++m) rowptr[m + 1] = rowptr[m] + uniq[m];
+  cols.resize(rowptr[N]);
+  for (int64_t m = 0; m < N; ++m) std::copy(raw.begin() + cnt[m], raw.begin() + cnt[m] + uniq[m], cols.begin() + rowptr[m]);
 }
 
 }  // namespace vie
