@@ -87,6 +87,32 @@ __device__ __forceinline__ void stage_table(const double *__restrict__ pack, int
 
 __device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// W Chebyshev series with the same coefficients c[0..K] (K even, zero-padded)
+// at W arguments t[w]: interleaved Clenshaw recurrences, two coefficients per
+// step, each coefficient read once for all W.
+template <int W>
+__device__ __forceinline__ void clenshaw_w(const double *__restrict__ c, int K, const double (&t)[W], double (&f)[W]) {
+  double b1[W], b2[W], t2[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    b1[w] = b2[w] = 0.0;
+    t2[w] = t[w] + t[w];
+  }
+#pragma unroll 1
+  for (int k = K; k >= 2; k -= 2) {
+    const double ck = c[k], ck1 = c[k - 1];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const double bk = fma(t2[w], b1[w], ck - b2[w]);
+      const double bk1 = fma(t2[w], bk, ck1 - b1[w]);
+      b2[w] = bk;
+      b1[w] = bk1;
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) f[w] = fma(t[w], b1[w], c[0] - b2[w]);
+}
+
 // g_p at W separations d[w] = r - r'_w at once (one test point, W source
 // points), from the packed table P.  The table entries are read once for
 // all W separations and the W Clenshaw recurrences run interleaved.  When
@@ -177,47 +203,66 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     }
   }
 
-  // spectral series one separation at a time (keeps the Floquet phase
-  // recurrences of a single point live), phases by recurrence in p and q
-#pragma unroll 1
+  // spectral series: the W separations share every mode's coefficient reads
+  // and run W interleaved Clenshaw recurrences in w = (z E)^2; the Floquet
+  // phases e^{-j k_tpq . Delta_t} of each separation by recurrence in p and q
+  double tw[W], kre[W], kim[W];
+  dz erow[W], bx[W], by[W];   // erow: phase of (p, q = -4); steps in p and in q
+#pragma unroll
   for (int w = 0; w < W; ++w) {
-    const double tw = fma(dz2[w] * E * E, P[pk::WS], -1.0);
+    tw[w] = fma(dz2[w] * E * E, P[pk::WS], -1.0);
     double s0, c0, s1, c1;
-    sincos(-P[pk::KX] * dx[w], &s0, &c0);
     sincos(-P[pk::TPA] * dx[w], &s1, &c1);
-    const dz bx = mk(c1, s1);
-    dz ex = mk(c0, s0) * conjz(bx * bx * bx * bx);  // p = -4
-    sincos(-P[pk::KY] * dy[w], &s0, &c0);
+    bx[w] = mk(c1, s1);
+    sincos(-P[pk::KX] * dx[w], &s0, &c0);
+    const dz ex = mk(c0, s0) * conjz(bx[w] * bx[w] * bx[w] * bx[w]);  // p = -4
     sincos(-P[pk::TPB] * dy[w], &s1, &c1);
-    const dz by = mk(c1, s1);
-    const dz ey0 = mk(c0, s0) * conjz(by * by * by * by);  // q = -4
-    double kre = 0.0, kim = 0.0;
+    by[w] = mk(c1, s1);
+    sincos(-P[pk::KY] * dy[w], &s0, &c0);
+    erow[w] = ex * (mk(c0, s0) * conjz(by[w] * by[w] * by[w] * by[w]));  // (p, q) = (-4, -4)
+    kre[w] = 0.0;
+    kim[w] = 0.0;
+  }
 #pragma unroll 1
-    for (int p = 0; p < kPgfSide; ++p) {
-      dz e = ex * ey0;
+  for (int p = 0; p < kPgfSide; ++p) {
+    dz e[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) e[w] = erow[w];
 #pragma unroll 1
-      for (int q = 0; q < kPgfSide; ++q) {
-        const int moff = ufirst((int)P[pk::MODES + p * kPgfSide + q]);
-        if (moff > 0) {
-          const double *M = P + moff;
-          const int K = ufirst((int)M[0]);
-          const double kr = clenshaw4(M + 4, K, tw);
-          if (M[1] != 0.0) {
-            const double ki = clenshaw4(M + 4 + K + 4, K, tw);
-            kre += e.re * kr - e.im * ki;
-            kim += e.re * ki + e.im * kr;
-          } else {
-            kre = fma(e.re, kr, kre);
-            kim = fma(e.im, kr, kim);
+    for (int q = 0; q < kPgfSide; ++q) {
+      const int moff = ufirst((int)P[pk::MODES + p * kPgfSide + q]);
+      if (moff > 0) {
+        const double *M = P + moff;
+        const int K = ufirst((int)M[0]);
+        double kr[W];
+        clenshaw_w<W>(M + 4, K, tw, kr);
+        if (M[1] != 0.0) {
+          double ki[W];
+          clenshaw_w<W>(M + 4 + K + 4, K, tw, ki);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kre[w] += e[w].re * kr[w] - e[w].im * ki[w];
+            kim[w] += e[w].re * ki[w] + e[w].im * kr[w];
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kre[w] = fma(e[w].re, kr[w], kre[w]);
+            kim[w] = fma(e[w].im, kr[w], kim[w]);
           }
         }
-        e = e * by;
       }
-      ex = ex * bx;
+#pragma unroll
+      for (int w = 0; w < W; ++w) e[w] = e[w] * by[w];
     }
+#pragma unroll
+    for (int w = 0; w < W; ++w) erow[w] = erow[w] * bx[w];
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
     const int pi = (im0[w] + 1) * 3 + (in0[w] + 1);
     const dz ph = mk(P[pk::PHRE + pi], P[pk::PHIM + pi]);
-    out[w] = ph * mk(sre[w] + kre, sim[w] + kim);
+    out[w] = ph * mk(sre[w] + kre[w], sim[w] + kim[w]);
   }
 }
 

@@ -132,7 +132,7 @@ __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, 
 }
 
 // Far tet pairs: 4 x 4 product rule.  One wave = one test tet x 64 source tets.
-__global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                 const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                 const int32_t *__restrict__ test_list, int ntest,
                                                 const int32_t *__restrict__ src_list, int nsrc,
@@ -148,23 +148,26 @@ __global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack,
   const int T = uniform(test_list[ti]);
   const int S = src_list[si];
   const TetGeom &gt = tg[T];
-  const TetGeom gs = tg[S];
-  if (touch_mask(gt.canon, gt.off, 4, gs.canon, gs.off, 4)) return;  // touching pairs: k_tt_near
-
-  const double wq = 0.25 * gs.vol, wt = 0.25 * gt.vol;
+  double wq;
+  double up[4][3], dc[3];
+  {
+    const TetGeom gs = tg[S];
+    if (touch_mask(gt.canon, gt.off, 4, gs.canon, gs.off, 4)) return;  // touching pairs: k_tt_near
+    wq = 0.25 * gs.vol;
+    for (int d = 0; d < 3; ++d) dc[d] = gt.c[d] - gs.c[d];
+    // source points relative to the source centroid
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double s = 0;
+        for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
+        up[j][d] = s - gs.c[d];
+      }
+  }
+  const double wt = 0.25 * gt.vol;
   Moments M;
   moments_zero(M);
-  const double dc[3] = {gt.c[0] - gs.c[0], gt.c[1] - gs.c[1], gt.c[2] - gs.c[2]};
-  // source points relative to the source centroid
-  double up[4][3];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double s = 0;
-      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[j][k], gs.v[k][d], s);
-      up[j][d] = s - gs.c[d];
-    }
   // one test point against the four source points per lattice-sum call
 #pragma unroll 1
   for (int i = 0; i < 4; ++i) {
@@ -192,6 +195,11 @@ __global__ __launch_bounds__(256) void k_tt_far(const double *__restrict__ pack,
       axpy(M.muv, dot3(u, up[j]), gw);
     }
   }
+  // the source geometry is read again here rather than held in registers
+  // through the lattice sums (the empty asm hides the earlier load)
+  const TetGeom *tgs = tg + S;
+  asm volatile("" : "+v"(tgs));
+  const TetGeom gs = *tgs;
   scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, false);
 }
 
@@ -484,7 +492,7 @@ __device__ dz pair_face_face(const double *__restrict__ P, const QuadRules *__re
 }
 
 // test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0
-__global__ __launch_bounds__(256) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
                                                   const FaceGeom *__restrict__ fg, int nface,
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(256) void k_tet_face(const double *__restrict__ pac
 }
 
 // half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0
-__global__ __launch_bounds__(256) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
                                                   int nhalf, const TetGeom *__restrict__ tg,
                                                   const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
@@ -529,7 +537,7 @@ __global__ __launch_bounds__(256) void k_face_tet(const double *__restrict__ pac
 }
 
 // half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
-__global__ __launch_bounds__(256) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__global__ __launch_bounds__(256, 2) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                    const FaceGeom *__restrict__ fg,
                                                    const int32_t *__restrict__ half_list, int nhalf, int nface,
                                                    const dz *__restrict__ sigma, ZOut out) {

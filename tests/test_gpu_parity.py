@@ -3,7 +3,7 @@ seeded inputs: topology, the periodic Green's function, every entry of Z,
 the right-hand side, the solution, absorptance and R/T, GMRES iteration
 counts, and the error paths of the boundary.
 
-Tolerances: Z entries |dZ| <= 1e-10 max(|Z_ij|, 1e-6 max|Z|); absorptance,
+Tolerances: Z entries |dZ| <= 1e-10 max(|Z_ij|, 1e-5 max|Z|); absorptance,
 R and T <= 1e-8 absolute; g_p <= 1e-12 relative."""
 import numpy as np
 import pytest
@@ -80,11 +80,19 @@ def test_pgf_matches_oracle(vie, lam, th, ph, a, b, zs):
     assert err.max() < 1e-12, err.max()
 
 
+# Entries are compared to 1e-10 relative, down to a floor of 1e-5 max|Z|:
+# an entry is a sum of contributions up to max|Z| in size, so FP64 rounding
+# leaves either implementation about 2e-16 max|Z| (absolute) off; below the
+# floor that rounding alone exceeds 1e-10 relative (measured: 1e-13 absolute
+# on entries of 1.4e-6 max|Z| in both the oracle and the library).
+Z_FLOOR = 1e-5
+
+
 def z_tolerance_ok(Zg, Zo):
     scale = np.abs(Zo).max()
-    tol = 1e-10 * np.maximum(np.abs(Zo), 1e-6 * scale)
+    tol = 1e-10 * np.maximum(np.abs(Zo), Z_FLOOR * scale)
     bad = np.abs(Zg - Zo) > tol
-    return (not bad.any()), np.max(np.abs(Zg - Zo) / np.maximum(np.abs(Zo), 1e-6 * scale))
+    return (not bad.any()), np.max(np.abs(Zg - Zo) / np.maximum(np.abs(Zo), Z_FLOOR * scale))
 
 
 @pytest.mark.parametrize("name", list(CASES))
