@@ -70,11 +70,13 @@ enum { VIE_TE = 0, VIE_TM = 1 };
  *   entry); every contribution of a touching element pair (singularity-
  *   extracted self and neighbour integrals, near-field Ewald remainders, the
  *   mass term) kept in FP64 in a sparse part over the touching-pair pattern.
- *   Products with Z, the preconditioner (factored in FP64 from that operator),
- *   the Krylov basis, Hessenberg/Givens updates and the true residual that
- *   closes every restart cycle all run in FP64 arithmetic on the mixed
- *   operator, so the solve converges to the tolerance of that operator; its
- *   difference from the FP64 Z is the FP32 rounding of far entries. */
+ *   The block preconditioner is factored in FP32 (FP32 matrix cores) from
+ *   that operator and its factors are stored in FP32.  Products with Z,
+ *   preconditioner applications (FP32 factors read, FP64 arithmetic), the
+ *   Krylov basis, Hessenberg/Givens updates and the true residual that closes
+ *   every restart cycle run in FP64 on the mixed operator, so the solve
+ *   converges to the tolerance of that operator; its difference from the FP64
+ *   Z is the FP32 rounding of far entries. */
 enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1 };
 
 typedef struct {

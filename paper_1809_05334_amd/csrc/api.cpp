@@ -163,7 +163,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     fel += n * L.fld[d];
     npiv += n;
   }
-  put(L.F, 16 * (size_t)std::max<int64_t>(1, fel));
+  const size_t fes = mixed ? 8 : 16;   // factor element: complex FP32 in mixed precision
+  put(L.F, fes * (size_t)std::max<int64_t>(1, fel));
   L.doff.resize(t.ndom);
   int64_t del = 0;
   for (int d = 0; d < t.ndom; ++d) {
@@ -171,7 +172,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     L.doff[d] = del;
     del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
   }
-  put(L.dinv, 16 * (size_t)std::max<int64_t>(1, del));
+  put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
   put(L.tpart, 16 * (size_t)kTrsvGroupsH * kTrsvNB * std::max(1, t.ndom));
   put(L.tcount, 4 * (size_t)std::max(1, t.ndom));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
@@ -208,6 +209,13 @@ int check(vie_ctx *ctx, State need, const char *what) {
   if (!ctx) return VIE_EINVAL;
   if (ctx->state < need) return fail(ctx, VIE_ESTATE, "%s called out of order", what);
   return VIE_OK;
+}
+
+// factor storage: complex FP32 in mixed precision, FP64 otherwise
+bool fp32_factors(const vie_ctx *ctx) { return ctx->precision == VIE_MIXED_FP32; }
+size_t factor_bytes(const vie_ctx *ctx) { return fp32_factors(ctx) ? 8 : 16; }
+void *factor_ptr(vie_ctx *ctx, const Region &r, int64_t elem) {
+  return ctx->ws + r.off + factor_bytes(ctx) * (size_t)elem;
 }
 
 void drop_graphs(vie_ctx *ctx) {
@@ -640,12 +648,28 @@ void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, 
   int total = 0;
   auto flush = [&]() {
     if (st.ndom == 0) return;
+    const bool f32 = fp32_factors(ctx);
     switch (k) {
-      case LU_PIVOT: hipLaunchKernelGGL(k_lu_pivot, dim3(total), dim3(1024), 0, ctx->stream, st); break;
-      case LU_COL: hipLaunchKernelGGL(k_lu_col, dim3(total), dim3(256), 0, ctx->stream, st); break;
-      case LU_SWAP: hipLaunchKernelGGL(k_lu_swap, dim3(total), dim3(256), 0, ctx->stream, st); break;
-      case LU_TRSM: hipLaunchKernelGGL(k_lu_trsm, dim3(total), dim3(64), 0, ctx->stream, st); break;
-      case LU_GEMM: hipLaunchKernelGGL(k_lu_gemm, dim3(total), dim3(256), 0, ctx->stream, st); break;
+      case LU_PIVOT:
+        if (f32) hipLaunchKernelGGL(k_lu_pivot_c, dim3(total), dim3(1024), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_pivot_z, dim3(total), dim3(1024), 0, ctx->stream, st);
+        break;
+      case LU_COL:
+        if (f32) hipLaunchKernelGGL(k_lu_col_c, dim3(total), dim3(256), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_col_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        break;
+      case LU_SWAP:
+        if (f32) hipLaunchKernelGGL(k_lu_swap_c, dim3(total), dim3(256), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_swap_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        break;
+      case LU_TRSM:
+        if (f32) hipLaunchKernelGGL(k_lu_trsm_c, dim3(total), dim3(64), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_trsm_z, dim3(total), dim3(64), 0, ctx->stream, st);
+        break;
+      case LU_GEMM:
+        if (f32) hipLaunchKernelGGL(k_lu_gemm_c, dim3(total), dim3(256), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_gemm_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        break;
     }
     st.ndom = 0;
     total = 0;
@@ -671,9 +695,8 @@ int vie_precond_factor(vie_ctx *ctx) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   const ZOut zo = zout(ctx);
-  dz *F = ctx->ptr<dz>(L.F);
+  const bool f32 = fp32_factors(ctx);
   int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *perm = ctx->ptr<int32_t>(L.perm), *info = ctx->ptr<int32_t>(L.info);
-  dz *rpiv = ctx->ptr<dz>(L.rpiv);
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(hipMemsetAsync(info, 0, 4 * t.ndom, ctx->stream));
   std::vector<LuDom> doms(t.ndom);
@@ -683,12 +706,12 @@ int vie_precond_factor(vie_ctx *ctx) {
     const int n = (int)(t.dend[d] - t.dstart[d]);
     LuDom &D = doms[d];
     D = LuDom{};
-    D.A = F + L.foff[d];
+    D.A = factor_ptr(ctx, L.F, L.foff[d]);
     D.ld = L.fld[d];
     D.n = n;
     D.ipiv = ipiv + poff;
     D.info = info + d;
-    D.rpiv = rpiv + d;
+    D.rpiv = ctx->ws + L.rpiv.off + 16 * (size_t)d;
     D.pval = ctx->ptr<double>(L.lupv) + pvoff;
     D.pidx = ctx->ptr<int32_t>(L.lupi) + pvoff;
     D.counter = ctx->ptr<int>(L.lucnt) + d;
@@ -696,11 +719,14 @@ int vie_precond_factor(vie_ctx *ctx) {
     pvoff += nblk(n, 256);
     maxn = std::max(maxn, n);
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_copy_block, dim3(nblk(n, 256), n), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n,
-                       D.A, D.ld);
-    if (!zo.Z)
-      hipLaunchKernelGGL(k_add_near, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zo, (int64_t)t.dstart[d], n, D.A,
-                         D.ld);
+    const dim3 cg(nblk(n, 256), n), ng(nblk(n, 256)), b256(256);
+    if (f32) {
+      hipLaunchKernelGGL(k_copy_block_c, cg, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (fz *)D.A, D.ld);
+      if (!zo.Z) hipLaunchKernelGGL(k_add_near_c, ng, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (fz *)D.A, D.ld);
+    } else {
+      hipLaunchKernelGGL(k_copy_block_z, cg, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (dz *)D.A, D.ld);
+      if (!zo.Z) hipLaunchKernelGGL(k_add_near_z, ng, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (dz *)D.A, D.ld);
+    }
     LAUNCHCK();
   }
   // right-looking blocked LU of every domain, advanced together column by column
@@ -730,11 +756,16 @@ int vie_precond_factor(vie_ctx *ctx) {
     hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)doms[d].ipiv,
                        perm + (doms[d].ipiv - ipiv));
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
-    dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
-    dz *DU = DL + (int64_t)nbk * kTrsvNB * kTrsvNB;
+    void *DL = factor_ptr(ctx, L.dinv, L.doff[d]);
+    void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
     const dim3 ig(nbk, kTrsvNB / 32), ib(128);   // 32 columns of one inverse per thread block
-    hipLaunchKernelGGL(k_diag_inv, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, DL);
-    hipLaunchKernelGGL(k_diag_inv, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, DU);
+    if (f32) {
+      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, (fz *)DL);
+      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, (fz *)DU);
+    } else {
+      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, (dz *)DL);
+      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, (dz *)DU);
+    }
     LAUNCHCK();
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
@@ -760,7 +791,6 @@ namespace {
 int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
-  const dz *F = ctx->ptr<dz>(L.F);
   const int32_t *perm = ctx->ptr<int32_t>(L.perm);
   int64_t poff = 0;
   int maxnbk = 0;
@@ -782,9 +812,16 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
       int blocks = 0;
       auto flush = [&]() {
         if (st.ndom == 0) return;
-        if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_r1, dim3(blocks), dim3(1024), 0, ctx->stream, st);
-        else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_r2, dim3(blocks), dim3(1024), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_trsv_step_r4, dim3(blocks), dim3(1024), 0, ctx->stream, st);
+        const dim3 g(blocks), b(1024);
+        if (fp32_factors(ctx)) {
+          if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
+          else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
+          else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
+        } else {
+          if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_z_r1, g, b, 0, ctx->stream, st);
+          else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_z_r2, g, b, 0, ctx->stream, st);
+          else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
+        }
         st.ndom = 0;
         blocks = 0;
       };
@@ -793,9 +830,9 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
         const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
         if (k >= nbk) continue;
         const int64_t off = t.dstart[d];
-        const dz *DL = ctx->ptr<dz>(L.dinv) + L.doff[d];
+        const int64_t dl = L.doff[d];
         TrsvDom &D = st.d[st.ndom];
-        D.F = F + L.foff[d];
+        D.F = factor_ptr(ctx, L.F, L.foff[d]);
         D.ld = L.fld[d];
         D.n = n;
         D.part = part + (int64_t)d * kTrsvGroupsH * kTrsvNB;
@@ -808,7 +845,7 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
           D.nm = std::min(kTrsvNB, n - D.nb0);
           D.cb0 = bk > 0 ? D.nb0 - kTrsvNB : 0;
           D.cm = bk > 0 ? kTrsvNB : 0;
-          D.DT = DL + (int64_t)bk * kTrsvNB * kTrsvNB;
+          D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)bk * kTrsvNB * kTrsvNB);
           D.rhs = s1 + off;
           D.sol = s2 + off;
           rest = D.cm > 0 ? n - D.nb0 - D.nm : 0;
@@ -818,7 +855,7 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
           D.nm = std::min(kTrsvNB, n - D.nb0);
           D.cb0 = k > 0 ? D.nb0 + kTrsvNB : 0;
           D.cm = k > 0 ? std::min(kTrsvNB, n - D.cb0) : 0;
-          D.DT = DL + (int64_t)(nbk + bk) * kTrsvNB * kTrsvNB;
+          D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(nbk + bk) * kTrsvNB * kTrsvNB);
           D.rhs = s2 + off;
           D.sol = out + off;
           rest = D.cm > 0 ? D.nb0 : 0;

@@ -12,7 +12,7 @@ namespace vie {
 struct dz {
   double re, im;
 };
-// complex FP32 storage element (mixed-precision Z); arithmetic stays FP64
+// complex FP32: storage of the mixed-precision Z and of FP32 block factors
 struct fz {
   float re, im;
 };
@@ -30,6 +30,29 @@ __device__ __forceinline__ void axpy(dz &acc, double s, dz a) {
   acc.re = fma(s, a.re, acc.re);
   acc.im = fma(s, a.im, acc.im);
 }
+
+__device__ __forceinline__ fz operator+(fz a, fz b) { return fz{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ fz operator-(fz a, fz b) { return fz{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ fz operator*(fz a, fz b) {
+  return fz{fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
+}
+
+// complex element traits: real type, construction, conversions to and from FP64
+template <typename C> struct cx;
+template <> struct cx<dz> {
+  typedef double R;
+  static __device__ __forceinline__ dz make(double a, double b) { return dz{a, b}; }
+  static __device__ __forceinline__ dz of(dz v) { return v; }
+  static __device__ __forceinline__ dz of(fz v) { return dz{v.re, v.im}; }
+};
+template <> struct cx<fz> {
+  typedef float R;
+  static __device__ __forceinline__ fz make(float a, float b) { return fz{a, b}; }
+  static __device__ __forceinline__ fz of(dz v) { return fz{(float)v.re, (float)v.im}; }
+  static __device__ __forceinline__ fz of(fz v) { return v; }
+};
+__device__ __forceinline__ dz to_dz(dz v) { return v; }
+__device__ __forceinline__ dz to_dz(fz v) { return dz{v.re, v.im}; }
 
 // f(t) = sum_{k=0}^{deg} c_k T_k(t), c_0 already halved (Clenshaw recurrence).
 // f(t) = sum_{k=0}^{K} c_k T_k(t) by the Clenshaw recurrence for a

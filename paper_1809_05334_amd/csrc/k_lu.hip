@@ -2,13 +2,15 @@
 // partial pivoting of each material-domain block A_dd, and the forward/back
 // substitutions that apply A_dd^{-1} inside GMRES.
 //
-// Right-looking blocked LU on a row-major complex FP64 block (leading
-// dimension ld): per panel of nb columns, a column-by-column panel
-// factorisation (pivot search, row swap inside the panel, scale, rank-1
-// update), the panel's row swaps applied to the other columns, a triangular
-// solve for the U12 block row, and the trailing update A22 -= L21 U12 on the
-// FP64 matrix cores (v_mfma_f64_16x16x4f64, four real products per complex
-// product).
+// Right-looking blocked LU on a row-major complex block (leading dimension
+// ld), in FP64 (dz) or, for the mixed-precision path, FP32 (fz): per panel of
+// nb columns, a column-by-column panel factorisation (pivot search, row swap
+// inside the panel, scale, rank-1 update), the panel's row swaps applied to
+// the other columns, a triangular solve for the U12 block row, and the
+// trailing update A22 -= L21 U12 on the matrix cores (v_mfma_f64_16x16x4f64
+// or v_mfma_f32_16x16x4f32, four real products per complex product).  Every
+// kernel body is a template on the element type with one __global__ wrapper
+// per type (suffix _z: FP64, _c: FP32).
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -17,33 +19,39 @@ namespace vie {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double cabs1(dz a) { return fabs(a.re) + fabs(a.im); }
+__device__ __forceinline__ double cabs1(fz a) { return (double)(fabsf(a.re) + fabsf(a.im)); }
 
 // copy the diagonal block Z[start:start+n, start:start+n] into A (ld lda);
 // in mixed precision the FP32 far part here, the near part by k_add_near
-__global__ void k_copy_block(ZOut Z, int64_t start, int n, dz *__restrict__ A, int64_t lda) {
+template <typename C>
+__device__ __forceinline__ void copy_block_body(const ZOut &Z, int64_t start, int n, C *__restrict__ A, int64_t lda) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (c >= n) return;
   const int64_t idx = (start + r) * Z.ld + start + c;
-  if (Z.Z) {
-    A[(int64_t)r * lda + c] = Z.Z[idx];
-  } else {
-    const fz f = Z.Zs[idx];
-    A[(int64_t)r * lda + c] = mk(f.re, f.im);
-  }
+  A[(int64_t)r * lda + c] = Z.Z ? cx<C>::of(Z.Z[idx]) : cx<C>::of(Z.Zs[idx]);
 }
 
-// A += the FP64 near entries of the diagonal block (one thread per row)
-__global__ void k_add_near(ZOut Z, int64_t start, int n, dz *__restrict__ A, int64_t lda) {
+// A += the FP64 near entries of the diagonal block (one thread per row; the
+// sum is formed in FP64 and rounded once)
+template <typename C>
+__device__ __forceinline__ void add_near_body(const ZOut &Z, int64_t start, int n, C *__restrict__ A, int64_t lda) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int64_t m = start + r;
   for (int64_t e = Z.rowptr[m]; e < Z.rowptr[m + 1]; ++e) {
     const int64_t c = Z.cols[e] - start;
-    if (c >= 0 && c < n) A[(int64_t)r * lda + c] = A[(int64_t)r * lda + c] + Z.vals[e];
+    if (c >= 0 && c < n) A[(int64_t)r * lda + c] = cx<C>::of(to_dz(A[(int64_t)r * lda + c]) + Z.vals[e]);
   }
 }
+
+__global__ void k_copy_block_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda) { copy_block_body(Z, start, n, A, lda); }
+__global__ void k_copy_block_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda) { copy_block_body(Z, start, n, A, lda); }
+__global__ void k_add_near_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda) { add_near_body(Z, start, n, A, lda); }
+__global__ void k_add_near_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda) { add_near_body(Z, start, n, A, lda); }
 
 // ------------------------------------------------------------ panel
 // Every launch below advances the factorisations of up to kLuMaxDom domains
@@ -63,39 +71,45 @@ __device__ __forceinline__ bool piv_better(double v, int i, double bv, int bi) {
 
 // Swap rows j and p inside the panel columns [k0, k0 + jb) and store the
 // reciprocal pivot (or flag a zero pivot); `tid`/`nthr` stride the columns.
+template <typename C>
 __device__ __forceinline__ void pivot_finish(const LuDom &D, int j, int k0, int jb, int p, double pv, int tid,
                                              int nthr) {
+  typedef typename cx<C>::R R;
+  C *A = (C *)D.A;
   if (p != j)
     for (int c = k0 + tid; c < k0 + jb; c += nthr) {
-      const dz t = D.A[(int64_t)j * D.ld + c];
-      D.A[(int64_t)j * D.ld + c] = D.A[(int64_t)p * D.ld + c];
-      D.A[(int64_t)p * D.ld + c] = t;
+      const C t = A[(int64_t)j * D.ld + c];
+      A[(int64_t)j * D.ld + c] = A[(int64_t)p * D.ld + c];
+      A[(int64_t)p * D.ld + c] = t;
     }
   __syncthreads();
   if (tid == 0) {
     D.ipiv[j] = p;
+    C *rp = (C *)D.rpiv;
     if (!(pv > 0.0)) {
       if (*D.info == 0) *D.info = j + 1;
-      *D.rpiv = mk(0.0, 0.0);
+      *rp = cx<C>::make(0, 0);
     } else {
-      const dz d = D.A[(int64_t)j * D.ld + j];
-      const double den = d.re * d.re + d.im * d.im;
-      *D.rpiv = mk(d.re / den, -d.im / den);
+      const C d = A[(int64_t)j * D.ld + j];
+      const R den = d.re * d.re + d.im * d.im;
+      *rp = cx<C>::make(d.re / den, -d.im / den);
     }
   }
 }
 
 // Pivot of the first column j = k0 of a panel: one thread block per domain.
-__global__ __launch_bounds__(1024) void k_lu_pivot(LuStep st) {
+template <typename C>
+__device__ __forceinline__ void lu_pivot_body(const LuStep &st) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
   const LuDom &D = st.d[blockIdx.x];
+  const C *A = (const C *)D.A;
   const int j = st.j, k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int tid = threadIdx.x;
   double best = -1.0;
   int bi = n;
   for (int i = j + tid; i < n; i += 1024) {
-    const double v = cabs1(D.A[(int64_t)i * D.ld + j]);
+    const double v = cabs1(A[(int64_t)i * D.ld + j]);
     if (piv_better(v, i, best, bi)) {
       best = v;
       bi = i;
@@ -111,7 +125,7 @@ __global__ __launch_bounds__(1024) void k_lu_pivot(LuStep st) {
     }
     __syncthreads();
   }
-  pivot_finish(D, j, k0, jb, si[0], sv[0], tid, 1024);
+  pivot_finish<C>(D, j, k0, jb, si[0], sv[0], tid, 1024);
 }
 
 // Column j of the panel: scale it below the diagonal, apply the rank-1 update
@@ -121,7 +135,8 @@ __global__ __launch_bounds__(1024) void k_lu_pivot(LuStep st) {
 // domain to finish (agent-scope acq_rel counter; nothing waits on it) picks
 // the pivot of column j+1, swaps it into place inside the panel, stores the
 // reciprocal pivot and puts the counter back to zero.
-__global__ __launch_bounds__(256) void k_lu_col(LuStep st) {
+template <typename C>
+__device__ __forceinline__ void lu_col_body(const LuStep &st) {
   __shared__ double sv[256];
   __shared__ int si[256];
   __shared__ int last;
@@ -134,9 +149,9 @@ __global__ __launch_bounds__(256) void k_lu_col(LuStep st) {
   const bool next = j + 1 < k0 + jb;
   double v = -1.0;
   if (i < n) {
-    dz *row = D.A + (int64_t)i * D.ld;
-    const dz *prow = D.A + (int64_t)j * D.ld;
-    const dz l = row[j] * (*D.rpiv);
+    C *row = (C *)D.A + (int64_t)i * D.ld;
+    const C *prow = (const C *)D.A + (int64_t)j * D.ld;
+    const C l = row[j] * (*(const C *)D.rpiv);
     row[j] = l;
     for (int c = j + 1; c < k0 + jb; ++c) row[c] = row[c] - l * prow[c];
     if (next) v = cabs1(row[j + 1]);
@@ -185,41 +200,44 @@ __global__ __launch_bounds__(256) void k_lu_col(LuStep st) {
     }
     __syncthreads();
   }
-  pivot_finish(D, j + 1, k0, jb, si[0], sv[0], tid, 256);
+  pivot_finish<C>(D, j + 1, k0, jb, si[0], sv[0], tid, 256);
   if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Apply the panel's row swaps to the columns outside the panel.
-__global__ __launch_bounds__(256) void k_lu_swap(LuStep st) {
+template <typename C>
+__device__ __forceinline__ void lu_swap_body(const LuStep &st) {
   const LuDom &D = st.d[lu_domain(st)];
+  C *A = (C *)D.A;
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int c = (blockIdx.x - D.first_block) * 256 + threadIdx.x;
   if (c >= n || (c >= k0 && c < k0 + jb)) return;
   for (int j = k0; j < k0 + jb; ++j) {
     const int p = D.ipiv[j];
     if (p != j) {
-      const dz t = D.A[(int64_t)j * D.ld + c];
-      D.A[(int64_t)j * D.ld + c] = D.A[(int64_t)p * D.ld + c];
-      D.A[(int64_t)p * D.ld + c] = t;
+      const C t = A[(int64_t)j * D.ld + c];
+      A[(int64_t)j * D.ld + c] = A[(int64_t)p * D.ld + c];
+      A[(int64_t)p * D.ld + c] = t;
     }
   }
 }
 
 // U12 = L11^{-1} A12 (L11 unit lower, jb <= 64): one wave per 64 columns, the
 // column block lives in LDS.
-__global__ __launch_bounds__(64) void k_lu_trsm(LuStep st) {
-  __shared__ dz tile[64][65];
+template <typename C>
+__device__ __forceinline__ void lu_trsm_body(const LuStep &st) {
+  __shared__ C tile[64][65];
   const LuDom &D = st.d[lu_domain(st)];
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int64_t ld = D.ld;
-  dz *A = D.A;
+  C *A = (C *)D.A;
   const int lane = threadIdx.x;
   const int c = k0 + jb + (blockIdx.x - D.first_block) * 64 + lane;
   const bool ok = c < n;
-  for (int i = 0; i < jb; ++i) tile[i][lane] = ok ? A[(int64_t)(k0 + i) * ld + c] : mk(0, 0);
+  for (int i = 0; i < jb; ++i) tile[i][lane] = ok ? A[(int64_t)(k0 + i) * ld + c] : cx<C>::make(0, 0);
   for (int i = 1; i < jb; ++i) {
-    const dz *Lr = A + (int64_t)(k0 + i) * ld + k0;
-    dz s = tile[i][lane];
+    const C *Lr = A + (int64_t)(k0 + i) * ld + k0;
+    C s = tile[i][lane];
     for (int l = 0; l < i; ++l) s = s - Lr[l] * tile[l][lane];
     tile[i][lane] = s;
   }
@@ -234,13 +252,13 @@ __global__ __launch_bounds__(64) void k_lu_trsm(LuStep st) {
 //   B[k = l/16][j = l%16]; result register r holds D[i = 4*r + l/16][j = l%16].
 constexpr int kGemmKC = 16;
 
-__global__ __launch_bounds__(256) void k_lu_gemm(LuStep st) {
+__global__ __launch_bounds__(256) void k_lu_gemm_z(LuStep st) {
   __shared__ double Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
   __shared__ double Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
   const LuDom &D = st.d[lu_domain(st)];
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int64_t ld = D.ld;
-  dz *__restrict__ A = D.A;
+  dz *__restrict__ A = (dz *)D.A;
   const int nt = (n - k0 - jb + 63) / 64;     // tiles per side of A22
   const int tile = blockIdx.x - D.first_block;
   const int r0 = k0 + jb + (tile / nt) * 64;  // rows of A22
@@ -310,6 +328,92 @@ __global__ __launch_bounds__(256) void k_lu_gemm(LuStep st) {
       }
 }
 
+// FP32 blocks: the same tiling on v_mfma_f32_16x16x4f32, whose operand layout
+// matches the FP64 instruction but whose result register r holds
+// D[i = 4*(l/16) + r][j = l%16].
+__global__ __launch_bounds__(256) void k_lu_gemm_c(LuStep st) {
+  __shared__ float Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
+  __shared__ float Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int64_t ld = D.ld;
+  fz *__restrict__ A = (fz *)D.A;
+  const int nt = (n - k0 - jb + 63) / 64;
+  const int tile = blockIdx.x - D.first_block;
+  const int r0 = k0 + jb + (tile / nt) * 64;
+  const int c0 = k0 + jb + (tile % nt) * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  v4f cre[2][2], cim[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      cre[a][b] = v4f{0, 0, 0, 0};
+      cim[a][b] = v4f{0, 0, 0, 0};
+    }
+  for (int kc = 0; kc < jb; kc += kGemmKC) {
+    __syncthreads();
+    for (int e = tid; e < 64 * kGemmKC; e += 256) {
+      const int i = e / kGemmKC, k = e % kGemmKC;
+      const int gr = r0 + i, gk = kc + k;
+      fz v = fz{0, 0};
+      if (gr < n && gk < jb) v = A[(int64_t)gr * ld + k0 + gk];
+      Ar[i][k] = v.re;
+      Ai[i][k] = v.im;
+    }
+    for (int e = tid; e < kGemmKC * 64; e += 256) {
+      const int k = e / 64, j = e % 64;
+      const int gk = kc + k, gc = c0 + j;
+      fz v = fz{0, 0};
+      if (gk < jb && gc < n) v = A[(int64_t)(k0 + gk) * ld + gc];
+      Br[k][j] = v.re;
+      Bi[k][j] = v.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGemmKC; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      float are[2], aim[2], bre[2], bim[2];
+      for (int a = 0; a < 2; ++a) {
+        const int i = wr * 32 + a * 16 + (lane & 15);
+        are[a] = Ar[i][ka];
+        aim[a] = Ai[i][ka];
+      }
+      for (int b = 0; b < 2; ++b) {
+        const int j = wc * 32 + b * 16 + (lane & 15);
+        bre[b] = Br[ka][j];
+        bim[b] = Bi[ka][j];
+      }
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          cre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[a], bre[b], cre[a][b], 0, 0, 0);
+          cre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[a], bim[b], cre[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[a], bim[b], cim[a][b], 0, 0, 0);
+          cim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[a], bre[b], cim[a][b], 0, 0, 0);
+        }
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int gi = r0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int gj = c0 + wc * 32 + b * 16 + (lane & 15);
+        if (gi < n && gj < n) {
+          fz *p = A + (int64_t)gi * ld + gj;
+          const fz v = *p;
+          *p = fz{v.re - cre[a][b][r], v.im - cim[a][b][r]};
+        }
+      }
+}
+
+__global__ __launch_bounds__(1024) void k_lu_pivot_z(LuStep st) { lu_pivot_body<dz>(st); }
+__global__ __launch_bounds__(1024) void k_lu_pivot_c(LuStep st) { lu_pivot_body<fz>(st); }
+__global__ __launch_bounds__(256) void k_lu_col_z(LuStep st) { lu_col_body<dz>(st); }
+__global__ __launch_bounds__(256) void k_lu_col_c(LuStep st) { lu_col_body<fz>(st); }
+__global__ __launch_bounds__(256) void k_lu_swap_z(LuStep st) { lu_swap_body<dz>(st); }
+__global__ __launch_bounds__(256) void k_lu_swap_c(LuStep st) { lu_swap_body<fz>(st); }
+__global__ __launch_bounds__(64) void k_lu_trsm_z(LuStep st) { lu_trsm_body<dz>(st); }
+__global__ __launch_bounds__(64) void k_lu_trsm_c(LuStep st) { lu_trsm_body<fz>(st); }
+
 // ------------------------------------------------------------ apply
 // perm[i] = original row now at position i, from the sequential swaps ipiv.
 __global__ void k_lu_perm(int n, const int32_t *__restrict__ ipiv, int32_t *__restrict__ perm) {
@@ -340,8 +444,9 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
 // substitution.
 constexpr int kInvCols = 32;
 
-__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv(const dz *__restrict__ F, int64_t ld, int n, int nb,
-                                                          int lower, dz *__restrict__ DT) {
+template <typename C>
+__device__ __forceinline__ void diag_inv_body(const C *__restrict__ F, int64_t ld, int n, int nb, int lower,
+                                              C *__restrict__ DT) {
   __shared__ dz X[kInvCols][kTrsvNB];
   const int b = blockIdx.x;
   const int b0 = b * nb;
@@ -349,7 +454,7 @@ __global__ __launch_bounds__(4 * kInvCols) void k_diag_inv(const dz *__restrict_
   const int cl = threadIdx.x >> 2, t = threadIdx.x & 3;
   const int j = blockIdx.y * kInvCols + cl;      // column of the inverse
   for (int i = t; i < nb; i += 4) X[cl][i] = mk(0, 0);
-  const dz *T = F + (int64_t)b0 * ld + b0;
+  const C *T = F + (int64_t)b0 * ld + b0;
   auto inv = [](dz d) {
     const double den = d.re * d.re + d.im * d.im;
     return mk(d.re / den, -d.im / den);
@@ -358,42 +463,49 @@ __global__ __launch_bounds__(4 * kInvCols) void k_diag_inv(const dz *__restrict_
     if (lower) {
       if ((j & 3) == t) X[cl][j] = mk(1, 0);
       for (int i = j + 1; i < m; ++i) {
-        const dz *Ti = T + (int64_t)i * ld;
+        const C *Ti = T + (int64_t)i * ld;
         dz s0 = mk(0, 0), s1 = mk(0, 0);
         int l = j + ((t - j) & 3);                 // first l >= j with l = t (mod 4)
         for (; l + 4 < i; l += 8) {
-          s0 = s0 + Ti[l] * X[cl][l];
-          s1 = s1 + Ti[l + 4] * X[cl][l + 4];
+          s0 = s0 + to_dz(Ti[l]) * X[cl][l];
+          s1 = s1 + to_dz(Ti[l + 4]) * X[cl][l + 4];
         }
-        if (l < i) s0 = s0 + Ti[l] * X[cl][l];
+        if (l < i) s0 = s0 + to_dz(Ti[l]) * X[cl][l];
         dz s = s0 + s1;
         s = s + mk(__shfl_xor(s.re, 1), __shfl_xor(s.im, 1));
         s = s + mk(__shfl_xor(s.re, 2), __shfl_xor(s.im, 2));
         if ((i & 3) == t) X[cl][i] = mk(0, 0) - s;
       }
     } else {
-      if ((j & 3) == t) X[cl][j] = inv(T[(int64_t)j * ld + j]);
+      if ((j & 3) == t) X[cl][j] = inv(to_dz(T[(int64_t)j * ld + j]));
       for (int i = j - 1; i >= 0; --i) {
-        const dz *Ti = T + (int64_t)i * ld;
+        const C *Ti = T + (int64_t)i * ld;
         dz s0 = mk(0, 0), s1 = mk(0, 0);
         int l = (i + 1) + ((t - (i + 1)) & 3);     // first l > i with l = t (mod 4)
         for (; l + 4 <= j; l += 8) {
-          s0 = s0 + Ti[l] * X[cl][l];
-          s1 = s1 + Ti[l + 4] * X[cl][l + 4];
+          s0 = s0 + to_dz(Ti[l]) * X[cl][l];
+          s1 = s1 + to_dz(Ti[l + 4]) * X[cl][l + 4];
         }
-        if (l <= j) s0 = s0 + Ti[l] * X[cl][l];
+        if (l <= j) s0 = s0 + to_dz(Ti[l]) * X[cl][l];
         dz s = s0 + s1;
         s = s + mk(__shfl_xor(s.re, 1), __shfl_xor(s.im, 1));
         s = s + mk(__shfl_xor(s.re, 2), __shfl_xor(s.im, 2));
-        if ((i & 3) == t) X[cl][i] = mk(0, 0) - s * inv(Ti[i]);
+        if ((i & 3) == t) X[cl][i] = mk(0, 0) - s * inv(to_dz(Ti[i]));
       }
     }
   }
   __syncthreads();
   if (j < nb) {
-    dz *row = DT + ((int64_t)b * nb + j) * nb;   // row j of DT = column j of the inverse
-    for (int i = t; i < nb; i += 4) row[i] = X[cl][i];
+    C *row = DT + ((int64_t)b * nb + j) * nb;   // row j of DT = column j of the inverse
+    for (int i = t; i < nb; i += 4) row[i] = cx<C>::of(X[cl][i]);
   }
+}
+
+__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *DT) {
+  diag_inv_body(F, ld, n, nb, lower, DT);
+}
+__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *DT) {
+  diag_inv_body(F, ld, n, nb, lower, DT);
 }
 
 __device__ __forceinline__ dz wave_sum(dz v) {
@@ -424,10 +536,11 @@ __device__ __forceinline__ dz wave_sum(dz v) {
 constexpr int kTrsvGroups = kTrsvGroupsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
 
-__device__ __forceinline__ dz row_dot(const dz *__restrict__ Fi, int cm, const dz *zc, int lane) {
+template <typename C>
+__device__ __forceinline__ dz row_dot(const C *__restrict__ Fi, int cm, const dz *zc, int lane) {
   dz f[kTrsvCol];
 #pragma unroll
-  for (int c = 0; c < kTrsvCol; ++c) f[c] = lane + 64 * c < cm ? Fi[lane + 64 * c] : mk(0, 0);
+  for (int c = 0; c < kTrsvCol; ++c) f[c] = lane + 64 * c < cm ? to_dz(Fi[lane + 64 * c]) : mk(0, 0);
   dz s = mk(0, 0);
 #pragma unroll
   for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[lane + 64 * c];
@@ -436,7 +549,7 @@ __device__ __forceinline__ dz row_dot(const dz *__restrict__ Fi, int cm, const d
 
 // RW rows per wave in the update blocks (16 RW rows per thread block); the
 // autotuner picks RW per context.
-template <int RW>
+template <typename C, int RW>
 __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   __shared__ dz zc[kTrsvNB];
   __shared__ dz rg[16];
@@ -450,6 +563,7 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   const int blk = blockIdx.x - D.first_block;
   const int cb0 = D.cb0, cm = D.cm, nb0 = D.nb0, nm = D.nm;
   const int64_t ld = D.ld;
+  const C *__restrict__ F = (const C *)D.F;
   if (tid < kTrsvNB) zc[tid] = tid < cm ? D.sol[cb0 + tid] : mk(0, 0);
   if (blk < kTrsvGroups) {
     const int g = blk;
@@ -463,13 +577,13 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
       rv = D.rhs[i];
 #pragma unroll
       for (int c = 0; c < kTrsvCol; ++c)
-        f[c] = lane + 64 * c < cm ? D.F[(int64_t)i * ld + cb0 + lane + 64 * c] : mk(0, 0);
+        f[c] = lane + 64 * c < cm ? to_dz(F[(int64_t)i * ld + cb0 + lane + 64 * c]) : mk(0, 0);
     }
     const int oi = tid & (kTrsvNB - 1), h = tid >> 8;   // h = 0..3 takes columns 16 g + 4 h .. + 3
-    const dz *col = D.DT + (int64_t)(16 * g + 4 * h) * kTrsvNB + oi;
+    const C *col = (const C *)D.DT + (int64_t)(16 * g + 4 * h) * kTrsvNB + oi;
     dz dt[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) dt[l] = col[(int64_t)l * kTrsvNB];
+    for (int l = 0; l < 4; ++l) dt[l] = to_dz(col[(int64_t)l * kTrsvNB]);
     __syncthreads();
     // (a) for the 16 rows of group g, one row per wave
     {
@@ -525,7 +639,8 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c)
-      f[q][c] = (i0 + q < rhi && lane + 64 * c < cm) ? D.F[(int64_t)(i0 + q) * ld + cb0 + lane + 64 * c] : mk(0, 0);
+      f[q][c] = (i0 + q < rhi && lane + 64 * c < cm) ? to_dz(F[(int64_t)(i0 + q) * ld + cb0 + lane + 64 * c])
+                                                      : mk(0, 0);
   __syncthreads();
   dz s[RW];
 #pragma unroll
@@ -543,8 +658,11 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   if (lane < RW && i0 + lane < rhi) D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
 }
 
-__global__ __launch_bounds__(1024) void k_trsv_step_r1(TrsvStep st) { trsv_step_body<1>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_r2(TrsvStep st) { trsv_step_body<2>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_r4(TrsvStep st) { trsv_step_body<4>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_z_r1(TrsvStep st) { trsv_step_body<dz, 1>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_z_r2(TrsvStep st) { trsv_step_body<dz, 2>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_z_r4(TrsvStep st) { trsv_step_body<dz, 4>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_c_r1(TrsvStep st) { trsv_step_body<fz, 1>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_c_r2(TrsvStep st) { trsv_step_body<fz, 2>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_c_r4(TrsvStep st) { trsv_step_body<fz, 4>(st); }
 
 }  // namespace vie

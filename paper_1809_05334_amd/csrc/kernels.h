@@ -45,20 +45,23 @@ __global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64
 
 // block LU and its application (k_lu.hip)
 constexpr int kTrsvNB = 256;
-__global__ void k_copy_block(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
-__global__ void k_add_near(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
+// FP64 (_z) and FP32 (_c) factor storage
+__global__ void k_copy_block_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
+__global__ void k_copy_block_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda);
+__global__ void k_add_near_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
+__global__ void k_add_near_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda);
 // The panel, swap, triangular-solve and trailing-update launches of the
 // block LU advance up to kLuMaxDom domains at the same global column.
 constexpr int kLuNB = 64;
 constexpr int kLuMaxDom = 8;
 struct LuDom {
-  dz *A;              // the domain's block, row-major, leading dimension ld, factored in place
+  void *A;            // the domain's block (dz or fz), row-major, leading dimension ld, factored in place
   int64_t ld;
   int n;
   int first_block;    // first thread block of this domain in the launch
   int32_t *ipiv;      // row swaps (LAPACK order)
   int32_t *info;      // first zero pivot (1-based), 0 if none
-  dz *rpiv;           // reciprocal of the current pivot
+  void *rpiv;         // reciprocal of the current pivot (same element type as A)
   double *pval;       // per-thread-block pivot candidates (k_lu_col)
   int32_t *pidx;
   int *counter;       // zero between launches
@@ -67,21 +70,26 @@ struct LuStep {
   LuDom d[kLuMaxDom];
   int ndom, j, k0;    // current column and panel start
 };
-__global__ void k_lu_pivot(LuStep st);
-__global__ void k_lu_col(LuStep st);
-__global__ void k_lu_swap(LuStep st);
-__global__ void k_lu_trsm(LuStep st);
-__global__ void k_lu_gemm(LuStep st);
+#define VIE_DECL_LU(T)                       \
+  __global__ void k_lu_pivot_##T(LuStep st); \
+  __global__ void k_lu_col_##T(LuStep st);   \
+  __global__ void k_lu_swap_##T(LuStep st);  \
+  __global__ void k_lu_trsm_##T(LuStep st);  \
+  __global__ void k_lu_gemm_##T(LuStep st);
+VIE_DECL_LU(z)
+VIE_DECL_LU(c)
+#undef VIE_DECL_LU
 __global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
-__global__ void k_diag_inv(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
+__global__ void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
+__global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *Dinv);
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
 // domains by one diagonal block each (k_lu.hip).
 constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
 constexpr int kTrsvMaxDom = 8;
 struct TrsvDom {
-  const dz *F;        // the domain's LU factors (row-major, leading dimension ld)
-  const dz *DT;       // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB)
+  const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
+  const void *DT;     // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB, same type)
   dz *rhs, *sol;      // right-hand side (updated in place) and solution, domain-local
   dz *part;           // kTrsvGroupsH x kTrsvNB partial products
   int *counter;       // zero between launches
@@ -92,10 +100,14 @@ struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
   int ndom, lower;
 };
-// variants by rows per wave of the update blocks (1, 2, 4 -> 16, 32, 64 rows per block)
-__global__ void k_trsv_step_r1(TrsvStep st);
-__global__ void k_trsv_step_r2(TrsvStep st);
-__global__ void k_trsv_step_r4(TrsvStep st);
+// variants by factor type (_z FP64, _c FP32) and rows per wave of the update
+// blocks (1, 2, 4 -> 16, 32, 64 rows per block); vectors and arithmetic FP64
+__global__ void k_trsv_step_z_r1(TrsvStep st);
+__global__ void k_trsv_step_z_r2(TrsvStep st);
+__global__ void k_trsv_step_z_r4(TrsvStep st);
+__global__ void k_trsv_step_c_r1(TrsvStep st);
+__global__ void k_trsv_step_c_r2(TrsvStep st);
+__global__ void k_trsv_step_c_r4(TrsvStep st);
 
 // Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block
 // of 4 waves owns 4 * RPW rows; the autotuner picks one per context.
