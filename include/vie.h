@@ -194,14 +194,14 @@ enum {
                              * residual estimates are read back once per graph launch, so a solve
                              * may run up to this many steps past convergence (unused) */
   VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
-  VIE_OPT_TRSV_ROWS = 3     /* triangular-solve update rows per wave: 1, 2 or 4 (default) */
+  VIE_OPT_TRSV_ROWS = 3     /* triangular-solve update rows per wave: 1, 2, 4 (default) or 8 */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);
 
 typedef struct {
   double matvec_ms[3];   /* per product, rows per wave 2, 4, 8 */
-  double apply_ms[3];    /* per preconditioner apply, rows per wave 1, 2, 4 */
+  double apply_ms[4];    /* per preconditioner apply, rows per wave 1, 2, 4, 8 */
   int matvec_rows, trsv_rows;   /* the picks, now set on the context */
 } vie_tuning;
 

@@ -758,7 +758,7 @@ int vie_precond_factor(vie_ctx *ctx) {
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
     void *DL = factor_ptr(ctx, L.dinv, L.doff[d]);
     void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
-    const dim3 ig(nbk, kTrsvNB / 32), ib(128);   // 32 columns of one inverse per thread block
+    const dim3 ig(nbk, kTrsvNB / kInvColsH), ib(4 * kInvColsH);   // kInvColsH columns of one inverse per block
     if (f32) {
       hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, (fz *)DL);
       hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, (fz *)DU);
@@ -816,10 +816,12 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
         if (fp32_factors(ctx)) {
           if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
           else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
+          else if (ctx->trsv_rw == 8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
           else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
         } else {
           if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_z_r1, g, b, 0, ctx->stream, st);
           else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_z_r2, g, b, 0, ctx->stream, st);
+          else if (ctx->trsv_rw == 8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
           else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
         }
         st.ndom = 0;
@@ -1306,7 +1308,8 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       ctx->mv_rpw = value;
       return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
-      if (value != 1 && value != 2 && value != 4) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2 or 4");
+      if (value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2, 4 or 8");
       if (value != ctx->trsv_rw) drop_graphs(ctx);
       ctx->trsv_rw = value;
       return VIE_OK;
@@ -1346,7 +1349,7 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
     *ms_out = ms / reps;
     return VIE_OK;
   };
-  const int mv_opts[3] = {2, 4, 8}, tr_opts[3] = {1, 2, 4};
+  const int mv_opts[3] = {2, 4, 8}, tr_opts[4] = {1, 2, 4, 8};
   double best = 1e300;
   int pick = ctx->mv_rpw;
   for (int i = 0; i < 3; ++i) {
@@ -1360,7 +1363,7 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   ctx->mv_rpw = pick;
   best = 1e300;
   pick = ctx->trsv_rw;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     ctx->trsv_rw = tr_opts[i];
     if (int rc = time_it([&]() { return apply_minv(ctx, x, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vt),
                                                    ctx->ptr<dz>(L.vr)); },

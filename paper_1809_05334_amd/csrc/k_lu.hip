@@ -442,7 +442,7 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
 // (residues of the summation index mod 4, combined by shuffles).  A lane only
 // reads back the entries it wrote itself, so no barrier is needed inside the
 // substitution.
-constexpr int kInvCols = 32;
+constexpr int kInvCols = kInvColsH;
 
 template <typename C>
 __device__ __forceinline__ void diag_inv_body(const C *__restrict__ F, int64_t ld, int n, int nb, int lower,
@@ -535,6 +535,8 @@ __device__ __forceinline__ dz wave_sum(dz v) {
 // blocks update the remaining rows, 64 per block, four rows per wave.
 constexpr int kTrsvGroups = kTrsvGroupsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
+constexpr int kTrsvHS = 1024 / kTrsvNB;  // thread groups sharing a group's 16 columns of inv(T_nn)
+constexpr int kTrsvCPH = 16 / kTrsvHS;   // columns per thread group
 
 template <typename C>
 __device__ __forceinline__ dz row_dot(const C *__restrict__ Fi, int cm, const dz *zc, int lane) {
@@ -553,7 +555,7 @@ template <typename C, int RW>
 __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   __shared__ dz zc[kTrsvNB];
   __shared__ dz rg[16];
-  __shared__ dz red[4][kTrsvNB];
+  __shared__ dz red[kTrsvHS][kTrsvNB];
   __shared__ int last;
   constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -579,11 +581,11 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
       for (int c = 0; c < kTrsvCol; ++c)
         f[c] = lane + 64 * c < cm ? to_dz(F[(int64_t)i * ld + cb0 + lane + 64 * c]) : mk(0, 0);
     }
-    const int oi = tid & (kTrsvNB - 1), h = tid >> 8;   // h = 0..3 takes columns 16 g + 4 h .. + 3
-    const C *col = (const C *)D.DT + (int64_t)(16 * g + 4 * h) * kTrsvNB + oi;
-    dz dt[4];
+    const int oi = tid & (kTrsvNB - 1), h = tid / kTrsvNB;   // group h takes columns 16 g + kTrsvCPH h ..
+    const C *col = (const C *)D.DT + (int64_t)(16 * g + kTrsvCPH * h) * kTrsvNB + oi;
+    dz dt[kTrsvCPH];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) dt[l] = to_dz(col[(int64_t)l * kTrsvNB]);
+    for (int l = 0; l < kTrsvCPH; ++l) dt[l] = to_dz(col[(int64_t)l * kTrsvNB]);
     __syncthreads();
     // (a) for the 16 rows of group g, one row per wave
     {
@@ -595,10 +597,17 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
     }
     __syncthreads();
     // (b) partial product with columns 16 g .. 16 g + 15 of inv(T_nn)
-    red[h][oi] = dt[0] * rg[4 * h] + dt[1] * rg[4 * h + 1] + dt[2] * rg[4 * h + 2] + dt[3] * rg[4 * h + 3];
+    {
+      dz acc = dt[0] * rg[kTrsvCPH * h];
+#pragma unroll
+      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + dt[l] * rg[kTrsvCPH * h + l];
+      red[h][oi] = acc;
+    }
     __syncthreads();
     if (tid < kTrsvNB) {
-      const dz z = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      dz z = red[0][tid];
+#pragma unroll
+      for (int q = 1; q < kTrsvHS; ++q) z = z + red[q][tid];
       D.part[g * kTrsvNB + tid] = z;
       __threadfence();
     }
@@ -661,8 +670,10 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
 __global__ __launch_bounds__(1024) void k_trsv_step_z_r1(TrsvStep st) { trsv_step_body<dz, 1>(st); }
 __global__ __launch_bounds__(1024) void k_trsv_step_z_r2(TrsvStep st) { trsv_step_body<dz, 2>(st); }
 __global__ __launch_bounds__(1024) void k_trsv_step_z_r4(TrsvStep st) { trsv_step_body<dz, 4>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_z_r8(TrsvStep st) { trsv_step_body<dz, 8>(st); }
 __global__ __launch_bounds__(1024) void k_trsv_step_c_r1(TrsvStep st) { trsv_step_body<fz, 1>(st); }
 __global__ __launch_bounds__(1024) void k_trsv_step_c_r2(TrsvStep st) { trsv_step_body<fz, 2>(st); }
 __global__ __launch_bounds__(1024) void k_trsv_step_c_r4(TrsvStep st) { trsv_step_body<fz, 4>(st); }
+__global__ __launch_bounds__(1024) void k_trsv_step_c_r8(TrsvStep st) { trsv_step_body<fz, 8>(st); }
 
 }  // namespace vie

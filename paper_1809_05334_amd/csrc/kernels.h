@@ -44,7 +44,8 @@ __global__ void k_pgf_probe(const double *pack, int packlen, const double *d, in
 __global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
 // block LU and its application (k_lu.hip)
-constexpr int kTrsvNB = 256;
+constexpr int kTrsvNB = 256;                   // diagonal-block size of the triangular solves
+constexpr int kInvColsH = 8192 / kTrsvNB;      // columns of one inverse per k_diag_inv block (128 KB of LDS)
 // FP64 (_z) and FP32 (_c) factor storage
 __global__ void k_copy_block_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
 __global__ void k_copy_block_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda);
@@ -101,13 +102,15 @@ struct TrsvStep {
   int ndom, lower;
 };
 // variants by factor type (_z FP64, _c FP32) and rows per wave of the update
-// blocks (1, 2, 4 -> 16, 32, 64 rows per block); vectors and arithmetic FP64
+// blocks (1, 2, 4, 8 -> 16 .. 128 rows per block); vectors and arithmetic FP64
 __global__ void k_trsv_step_z_r1(TrsvStep st);
 __global__ void k_trsv_step_z_r2(TrsvStep st);
 __global__ void k_trsv_step_z_r4(TrsvStep st);
+__global__ void k_trsv_step_z_r8(TrsvStep st);
 __global__ void k_trsv_step_c_r1(TrsvStep st);
 __global__ void k_trsv_step_c_r2(TrsvStep st);
 __global__ void k_trsv_step_c_r4(TrsvStep st);
+__global__ void k_trsv_step_c_r8(TrsvStep st);
 
 // Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block
 // of 4 waves owns 4 * RPW rows; the autotuner picks one per context.

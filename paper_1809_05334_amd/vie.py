@@ -58,7 +58,7 @@ VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS = 1, 2, 3
 
 
 class Tuning(C.Structure):
-    _fields_ = [("matvec_ms", C.c_double * 3), ("apply_ms", C.c_double * 3),
+    _fields_ = [("matvec_ms", C.c_double * 3), ("apply_ms", C.c_double * 4),
                 ("matvec_rows", C.c_int), ("trsv_rows", C.c_int)]
 
     def as_dict(self):
