@@ -192,9 +192,15 @@ int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z);
 enum {
   VIE_OPT_GRAPH_STEPS = 1,  /* Arnoldi steps per captured HIP graph, 0 = plain launches (default);
                              * residual estimates are read back once per graph launch, so a solve
-                             * may run up to this many steps past convergence (unused) */
+                             * may run up to this many steps past convergence (unused).  Needs a
+                             * non-null stream: vie_solve returns VIE_EINVAL on the null stream */
   VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
-  VIE_OPT_TRSV_ROWS = 3     /* triangular-solve update rows per wave: 1, 2, 4 (default) or 8 */
+  VIE_OPT_TRSV_ROWS = 3,    /* triangular-solve update rows per wave: 1, 2, 4 (default) or 8 */
+  VIE_OPT_TRSV_COOP = 4     /* 1: each preconditioner apply runs its triangular-solve steps in one
+                             * cooperative launch with grid barriers between steps (not inside
+                             * captured graphs); 0 (default): one
+                             * launch per step.  Use 1 only where no other context's work needs
+                             * the device at the same time (a cooperative grid holds every CU). */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);

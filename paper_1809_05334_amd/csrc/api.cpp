@@ -24,6 +24,7 @@ enum State { S_NEW = 0, S_MESH = 1, S_BOUND = 2, S_FILLED = 3, S_FACTORED = 4, S
 
 constexpr int kMaxPack = 8192;     // doubles of the packed lattice-sum table (64 KB of LDS)
 constexpr int kRedBlocks = 240;   // blocks of the two-stage reductions
+constexpr int kMaxPlans = 4;      // cached cooperative triangular-solve plans per context
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -34,7 +35,8 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, dinv, tpart, tcount;
+  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, dinv, tpart, tcount, plans;
+  int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, apart, kv, idx, jd, rhist;
   size_t total = 0;
   int64_t ld = 0;
@@ -67,6 +69,15 @@ struct vie_ctx {
   int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
   int trsv_rw = 4;                  // triangular-solve update rows per wave (1, 2, 4)
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
+  int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
+  bool capturing = false;           // a graph capture is in progress on the stream
+  int coop_grid = 0;                // co-resident thread blocks of the cooperative kernel
+  struct CoopPlan {
+    const void *v, *out, *s1, *s2;
+    int rw, nsteps;
+    size_t off;                     // byte offset of the plan in the workspace
+  };
+  std::vector<CoopPlan> plans;
   hipGraphExec_t gexec_g = nullptr; // graph_steps steps
   hipGraphExec_t gexec_1 = nullptr; // one step (tail of a restart cycle)
   int gexec_g_steps = 0;
@@ -174,6 +185,13 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
   put(L.tpart, 16 * (size_t)kTrsvGroupsH * kTrsvNB * std::max(1, t.ndom));
+  {
+    int maxnbk = 1;
+    for (int d = 0; d < t.ndom; ++d) maxnbk = std::max<int>(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
+    const int chunks = (t.ndom + kTrsvMaxDom - 1) / kTrsvMaxDom;
+    L.plan_steps = 2 * maxnbk * std::max(1, chunks);
+    put(L.plans, kMaxPlans * sizeof(TrsvStep) * (size_t)L.plan_steps);
+  }
   put(L.tcount, 4 * (size_t)std::max(1, t.ndom));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
@@ -219,6 +237,7 @@ void *factor_ptr(vie_ctx *ctx, const Region &r, int64_t elem) {
 }
 
 void drop_graphs(vie_ctx *ctx) {
+  ctx->plans.clear();
   if (ctx->gexec_g) (void)hipGraphExecDestroy(ctx->gexec_g);
   if (ctx->gexec_1) (void)hipGraphExecDestroy(ctx->gexec_1);
   ctx->gexec_g = ctx->gexec_1 = nullptr;
@@ -788,44 +807,27 @@ namespace {
 // the pivots, then L y = P v and U z = y by blocked triangular solves.  Each
 // k_trsv_step launch advances every domain (up to kTrsvMaxDom per launch) by
 // one diagonal block, so the launch count follows the largest domain.
-int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
+// The step list of the blocked triangular solves (L sweep, then U sweep) for
+// the given vectors; step k advances every domain (kTrsvMaxDom per entry) by
+// one diagonal block.
+std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
-  const int32_t *perm = ctx->ptr<int32_t>(L.perm);
-  int64_t poff = 0;
   int maxnbk = 0;
-  for (int d = 0; d < t.ndom; ++d) {
-    const int n = (int)(t.dend[d] - t.dstart[d]);
-    if (n > 0)
-      hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, (int64_t)t.dstart[d],
-                         perm + poff, v, s1);
-    poff += n;
-    maxnbk = std::max(maxnbk, (n + kTrsvNB - 1) / kTrsvNB);
-  }
+  for (int d = 0; d < t.ndom; ++d) maxnbk = std::max(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
   dz *part = ctx->ptr<dz>(L.tpart);
   int *cnt = ctx->ptr<int>(L.tcount);
+  std::vector<TrsvStep> plan;
   // L sweep: rhs s1 (updated in place), solution s2; U sweep: rhs s2, solution out.
   for (int lower = 1; lower >= 0; --lower) {
     for (int k = 0; k < maxnbk; ++k) {
       TrsvStep st{};
       st.lower = lower;
-      int blocks = 0;
       auto flush = [&]() {
         if (st.ndom == 0) return;
-        const dim3 g(blocks), b(1024);
-        if (fp32_factors(ctx)) {
-          if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
-          else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
-          else if (ctx->trsv_rw == 8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
-          else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
-        } else {
-          if (ctx->trsv_rw == 1) hipLaunchKernelGGL(k_trsv_step_z_r1, g, b, 0, ctx->stream, st);
-          else if (ctx->trsv_rw == 2) hipLaunchKernelGGL(k_trsv_step_z_r2, g, b, 0, ctx->stream, st);
-          else if (ctx->trsv_rw == 8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
-          else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
-        }
-        st.ndom = 0;
-        blocks = 0;
+        plan.push_back(st);
+        st = TrsvStep{};
+        st.lower = lower;
       };
       for (int d = 0; d < t.ndom; ++d) {
         const int n = (int)(t.dend[d] - t.dstart[d]);
@@ -839,7 +841,7 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
         D.n = n;
         D.part = part + (int64_t)d * kTrsvGroupsH * kTrsvNB;
         D.counter = cnt + d;
-        D.first_block = blocks;
+        D.first_block = st.total_blocks;
         int rest;
         if (lower) {
           const int bk = k;
@@ -862,11 +864,101 @@ int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
           D.sol = out + off;
           rest = D.cm > 0 ? D.nb0 : 0;
         }
-        blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
+        st.total_blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
         if (++st.ndom == kTrsvMaxDom) flush();
       }
       flush();
     }
+  }
+  return plan;
+}
+
+void launch_trsv_step(vie_ctx *ctx, const TrsvStep &st) {
+  const dim3 g(st.total_blocks), b(1024);
+  const int rw = ctx->trsv_rw;
+  if (fp32_factors(ctx)) {
+    if (rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
+    else if (rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
+    else if (rw == 8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
+    else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
+  } else {
+    if (rw == 1) hipLaunchKernelGGL(k_trsv_step_z_r1, g, b, 0, ctx->stream, st);
+    else if (rw == 2) hipLaunchKernelGGL(k_trsv_step_z_r2, g, b, 0, ctx->stream, st);
+    else if (rw == 8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
+    else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
+  }
+}
+
+const void *coop_kernel(const vie_ctx *ctx) {
+  const int rw = ctx->trsv_rw;
+  if (fp32_factors(ctx)) {
+    if (rw == 1) return (const void *)k_trsv_coop_c_r1;
+    if (rw == 2) return (const void *)k_trsv_coop_c_r2;
+    if (rw == 8) return (const void *)k_trsv_coop_c_r8;
+    return (const void *)k_trsv_coop_c_r4;
+  }
+  if (rw == 1) return (const void *)k_trsv_coop_z_r1;
+  if (rw == 2) return (const void *)k_trsv_coop_z_r2;
+  if (rw == 8) return (const void *)k_trsv_coop_z_r8;
+  return (const void *)k_trsv_coop_z_r4;
+}
+
+// Run the plan as one cooperative launch: the plan is uploaded once per
+// (vectors, variant) and cached in the workspace; the grid is the number of
+// thread blocks that are co-resident on the device (the runtime refuses a
+// larger cooperative grid).
+int launch_trsv_coop(vie_ctx *ctx, const std::vector<TrsvStep> &plan, const dz *v, const dz *out, const dz *s1,
+                     const dz *s2) {
+  const Layout &L = ctx->L;
+  const void *kern = coop_kernel(ctx);
+  if (ctx->coop_grid <= 0) {
+    int per_cu = 0, cus = 0;
+    HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 1024, 0));
+    HIPCK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    ctx->coop_grid = std::max(1, per_cu) * std::max(1, cus);
+  }
+  if ((int)plan.size() > L.plan_steps) return fail(ctx, VIE_EINVAL, "triangular-solve plan too long");
+  const vie_ctx::CoopPlan *cp = nullptr;
+  for (const auto &p : ctx->plans)
+    if (p.v == v && p.out == out && p.s1 == s1 && p.s2 == s2 && p.rw == ctx->trsv_rw) cp = &p;
+  if (!cp) {
+    if ((int)ctx->plans.size() == kMaxPlans) ctx->plans.clear();
+    vie_ctx::CoopPlan p{v, out, s1, s2, ctx->trsv_rw, (int)plan.size(),
+                        L.plans.off + ctx->plans.size() * sizeof(TrsvStep) * (size_t)L.plan_steps};
+    HIPCK(hipMemcpyAsync(ctx->ws + p.off, plan.data(), sizeof(TrsvStep) * plan.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));   // the host plan goes out of scope
+    ctx->plans.push_back(p);
+    cp = &ctx->plans.back();
+  }
+  const TrsvStep *dplan = reinterpret_cast<const TrsvStep *>(ctx->ws + cp->off);
+  int nsteps = cp->nsteps;
+  void *args[] = {(void *)&dplan, (void *)&nsteps};
+  HIPCK(hipLaunchCooperativeKernel(kern, dim3(ctx->coop_grid), dim3(1024), args, 0, ctx->stream));
+  return VIE_OK;
+}
+
+// z = M^{-1} v for the block-diagonal preconditioner: per domain, permute by
+// the pivots, then L y = P v and U z = y by blocked triangular solves, either
+// one launch per step (the launch count follows the largest domain) or all
+// steps in one cooperative launch (VIE_OPT_TRSV_COOP, not under graph capture).
+int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const int32_t *perm = ctx->ptr<int32_t>(L.perm);
+  int64_t poff = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    const int n = (int)(t.dend[d] - t.dstart[d]);
+    if (n > 0)
+      hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, (int64_t)t.dstart[d],
+                         perm + poff, v, s1);
+    poff += n;
+  }
+  const std::vector<TrsvStep> plan = trsv_plan(ctx, out, s1, s2);
+  if (ctx->trsv_coop && !ctx->capturing) {
+    if (int rc = launch_trsv_coop(ctx, plan, v, out, s1, s2)) return rc;
+  } else {
+    for (const TrsvStep &st : plan) launch_trsv_step(ctx, st);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "preconditioner apply: %s", hipGetErrorString(e));
@@ -933,8 +1025,10 @@ int arnoldi_step(vie_ctx *ctx) {
 int capture_steps(vie_ctx *ctx, int steps, hipGraphExec_t *out) {
   hipGraph_t graph = nullptr;
   HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;   // no cooperative launches inside a captured graph
   int rc = VIE_OK;
   for (int q = 0; q < steps && rc == VIE_OK; ++q) rc = arnoldi_step(ctx);
+  ctx->capturing = false;
   hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -949,7 +1043,9 @@ int capture_steps(vie_ctx *ctx, int steps, hipGraphExec_t *out) {
 
 // Issue `steps` Arnoldi steps: replay a captured graph when graph mode is on.
 int issue_steps(vie_ctx *ctx, int steps) {
-  if (ctx->graph_steps <= 0 || ctx->stream == nullptr) {
+  if (ctx->graph_steps > 0 && ctx->stream == nullptr)
+    return fail(ctx, VIE_EINVAL, "graph capture needs a non-null stream (VIE_OPT_GRAPH_STEPS)");
+  if (ctx->graph_steps <= 0) {
     for (int q = 0; q < steps; ++q)
       if (int rc = arnoldi_step(ctx)) return rc;
     return VIE_OK;
@@ -1307,6 +1403,10 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       if (value != ctx->mv_rpw) drop_graphs(ctx);
       ctx->mv_rpw = value;
       return VIE_OK;
+    case VIE_OPT_TRSV_COOP:
+      if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "cooperative triangular solves: 0 or 1");
+      ctx->trsv_coop = value;
+      return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
       if (value != 1 && value != 2 && value != 4 && value != 8)
         return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2, 4 or 8");
@@ -1323,6 +1423,7 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value) {
     case VIE_OPT_GRAPH_STEPS: *value = ctx->graph_steps; return VIE_OK;
     case VIE_OPT_MATVEC_ROWS: *value = ctx->mv_rpw; return VIE_OK;
     case VIE_OPT_TRSV_ROWS: *value = ctx->trsv_rw; return VIE_OK;
+    case VIE_OPT_TRSV_COOP: *value = ctx->trsv_coop; return VIE_OK;
   }
   return VIE_EINVAL;
 }

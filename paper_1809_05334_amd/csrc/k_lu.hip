@@ -11,6 +11,7 @@
 // or v_mfma_f32_16x16x4f32, four real products per complex product).  Every
 // kernel body is a template on the element type with one __global__ wrapper
 // per type (suffix _z: FP64, _c: FP32).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -552,7 +553,7 @@ __device__ __forceinline__ dz row_dot(const C *__restrict__ Fi, int cm, const dz
 // RW rows per wave in the update blocks (16 RW rows per thread block); the
 // autotuner picks RW per context.
 template <typename C, int RW>
-__device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
+__device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
   __shared__ dz zc[kTrsvNB];
   __shared__ dz rg[16];
   __shared__ dz red[kTrsvHS][kTrsvNB];
@@ -560,9 +561,9 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int d = 0;
-  while (d + 1 < st.ndom && (int)blockIdx.x >= st.d[d + 1].first_block) ++d;
+  while (d + 1 < st.ndom && vb >= st.d[d + 1].first_block) ++d;
   const TrsvDom &D = st.d[d];
-  const int blk = blockIdx.x - D.first_block;
+  const int blk = vb - D.first_block;
   const int cb0 = D.cb0, cm = D.cm, nb0 = D.nb0, nm = D.nm;
   const int64_t ld = D.ld;
   const C *__restrict__ F = (const C *)D.F;
@@ -667,13 +668,49 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st) {
   if (lane < RW && i0 + lane < rhi) D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
 }
 
-__global__ __launch_bounds__(1024) void k_trsv_step_z_r1(TrsvStep st) { trsv_step_body<dz, 1>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_z_r2(TrsvStep st) { trsv_step_body<dz, 2>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_z_r4(TrsvStep st) { trsv_step_body<dz, 4>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_z_r8(TrsvStep st) { trsv_step_body<dz, 8>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_c_r1(TrsvStep st) { trsv_step_body<fz, 1>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_c_r2(TrsvStep st) { trsv_step_body<fz, 2>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_c_r4(TrsvStep st) { trsv_step_body<fz, 4>(st); }
-__global__ __launch_bounds__(1024) void k_trsv_step_c_r8(TrsvStep st) { trsv_step_body<fz, 8>(st); }
+#define VIE_TRSV_STEP(T, C, R)                                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_r##R(TrsvStep st) {               \
+    trsv_step_body<C, R>(st, blockIdx.x);                                                     \
+  }
+VIE_TRSV_STEP(z, dz, 1)
+VIE_TRSV_STEP(z, dz, 2)
+VIE_TRSV_STEP(z, dz, 4)
+VIE_TRSV_STEP(z, dz, 8)
+VIE_TRSV_STEP(c, fz, 1)
+VIE_TRSV_STEP(c, fz, 2)
+VIE_TRSV_STEP(c, fz, 4)
+VIE_TRSV_STEP(c, fz, 8)
+
+// Every step of the triangular solves in one cooperative launch: the thread
+// blocks share each step's work items (the same items the per-step launches
+// give to their thread blocks) and meet at a grid barrier between steps.
+// All blocks run the same loops and reach every barrier; the items' own
+// cross-block reduction is the counter of the per-step kernel.
+template <typename C, int RW>
+__device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan, int nsteps) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int s = 0; s < nsteps; ++s) {
+    const TrsvStep &st = plan[s];
+    const int total = st.total_blocks;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+      __syncthreads();   // the previous item's shared memory is free
+      trsv_step_body<C, RW>(st, vb);
+    }
+    grid.sync();
+  }
+}
+
+#define VIE_TRSV_COOP(T, C, R)                                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps) { \
+    trsv_coop_body<C, R>(plan, nsteps);                                                       \
+  }
+VIE_TRSV_COOP(z, dz, 1)
+VIE_TRSV_COOP(z, dz, 2)
+VIE_TRSV_COOP(z, dz, 4)
+VIE_TRSV_COOP(z, dz, 8)
+VIE_TRSV_COOP(c, fz, 1)
+VIE_TRSV_COOP(c, fz, 2)
+VIE_TRSV_COOP(c, fz, 4)
+VIE_TRSV_COOP(c, fz, 8)
 
 }  // namespace vie

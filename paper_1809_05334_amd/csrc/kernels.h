@@ -100,17 +100,23 @@ struct TrsvDom {
 struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
   int ndom, lower;
+  int total_blocks;   // thread blocks (work items) of the step over all its domains
 };
 // variants by factor type (_z FP64, _c FP32) and rows per wave of the update
-// blocks (1, 2, 4, 8 -> 16 .. 128 rows per block); vectors and arithmetic FP64
-__global__ void k_trsv_step_z_r1(TrsvStep st);
-__global__ void k_trsv_step_z_r2(TrsvStep st);
-__global__ void k_trsv_step_z_r4(TrsvStep st);
-__global__ void k_trsv_step_z_r8(TrsvStep st);
-__global__ void k_trsv_step_c_r1(TrsvStep st);
-__global__ void k_trsv_step_c_r2(TrsvStep st);
-__global__ void k_trsv_step_c_r4(TrsvStep st);
-__global__ void k_trsv_step_c_r8(TrsvStep st);
+// blocks (1, 2, 4, 8 -> 16 .. 128 rows per block); vectors and arithmetic FP64.
+// k_trsv_coop_*: every step of a plan in one cooperative launch.
+#define VIE_DECL_TRSV(T, R)                                  \
+  __global__ void k_trsv_step_##T##_r##R(TrsvStep st);       \
+  __global__ void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps);
+VIE_DECL_TRSV(z, 1)
+VIE_DECL_TRSV(z, 2)
+VIE_DECL_TRSV(z, 4)
+VIE_DECL_TRSV(z, 8)
+VIE_DECL_TRSV(c, 1)
+VIE_DECL_TRSV(c, 2)
+VIE_DECL_TRSV(c, 4)
+VIE_DECL_TRSV(c, 8)
+#undef VIE_DECL_TRSV
 
 // Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block
 // of 4 waves owns 4 * RPW rows; the autotuner picks one per context.

@@ -54,7 +54,7 @@ class FillStats(C.Structure):
 
 _LIB = None
 
-VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS = 1, 2, 3
+VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS, VIE_OPT_TRSV_COOP = 1, 2, 3, 4
 
 
 class Tuning(C.Structure):
@@ -116,14 +116,16 @@ def _p(a):
 
 
 class Solver:
-    """One context = one unit cell on one device stream (not thread-safe)."""
+    """One context = one unit cell on one device stream (not thread-safe).
+    Without `stream`, the context gets a new stream of its own."""
 
     def __init__(self, device=0, stream=None):
         import torch
         self.torch = torch
         self.lib = load()
         self.device = device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        # a stream of its own by default (the null stream cannot be captured in a graph)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = C.c_void_p()
         rc = self.lib.vie_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
         if rc != VIE_OK:

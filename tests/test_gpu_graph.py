@@ -66,6 +66,20 @@ def test_graph_replays_match_plain_launches(vie, precision, steps, restart):
         s.bench_matvec(2)
 
 
+def test_graph_mode_needs_a_stream_of_its_own(vie):
+    import torch
+    m = three_domain_slab()
+    s = vie.Solver(stream=torch.cuda.default_stream())
+    s.upload_mesh(m)
+    s.bind(vie.VIE_FP64, 20)
+    s.fill(560.0, 0.0, 0.0, W.slab_eps(m))
+    s.factor()
+    s.set_option(vie.VIE_OPT_GRAPH_STEPS, 4)
+    with pytest.raises(vie.VieError) as e:
+        s.solve(0, tol=1e-8, max_iter=50, restart=20)
+    assert e.value.code == vie.VIE_EINVAL
+
+
 def test_graph_mode_iterations_match_oracle(vie):
     from oracle import topology as OT
     from oracle import vie as OV
