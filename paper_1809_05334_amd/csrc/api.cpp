@@ -196,7 +196,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
   int64_t npart = 0;
-  for (int d = 0; d < t.ndom; ++d) npart += nblk(t.dend[d] - t.dstart[d], 256);
+  for (int d = 0; d < t.ndom; ++d) npart += nblk(t.dend[d] - t.dstart[d], kColRows);
   put(L.rpiv, 16 * (size_t)std::max(1, t.ndom));
   put(L.info, 4 * std::max(1, t.ndom));
   put(L.lupv, 8 * (size_t)std::max<int64_t>(1, npart));
@@ -735,7 +735,7 @@ int vie_precond_factor(vie_ctx *ctx) {
     D.pidx = ctx->ptr<int32_t>(L.lupi) + pvoff;
     D.counter = ctx->ptr<int>(L.lucnt) + d;
     poff += n;
-    pvoff += nblk(n, 256);
+    pvoff += nblk(n, kColRows);
     maxn = std::max(maxn, n);
     if (n == 0) continue;
     const dim3 cg(nblk(n, 256), n), ng(nblk(n, 256)), b256(256);
@@ -755,7 +755,7 @@ int vie_precond_factor(vie_ctx *ctx) {
     for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
       lu_launch(ctx, LU_COL, doms, j, k0, [&](int d) {
         const int n = doms[d].n;
-        return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, 256) : 0;
+        return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
       });
     lu_launch(ctx, LU_SWAP, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; });
     lu_launch(ctx, LU_TRSM, doms, k0, k0, [&](int d) {

@@ -130,12 +130,13 @@ __device__ __forceinline__ void lu_pivot_body(const LuStep &st) {
 }
 
 // Column j of the panel: scale it below the diagonal, apply the rank-1 update
-// to the rest of the panel (columns j+1 .. k0+jb-1), one thread per row.
-// When column j+1 is inside the panel, each thread block also reduces its
-// rows' pivot candidates in column j+1 into part; the last block of the
-// domain to finish (agent-scope acq_rel counter; nothing waits on it) picks
-// the pivot of column j+1, swaps it into place inside the panel, stores the
-// reciprocal pivot and puts the counter back to zero.
+// to the rest of the panel (columns j+1 .. k0+jb-1).  kColT adjacent lanes
+// share a row (lane t takes columns j+1+t, j+1+t+kColT, ...), kColRows rows
+// per thread block.  When column j+1 is inside the panel, each thread block
+// also reduces its rows' pivot candidates in column j+1 into part; the last
+// block of the domain to finish (agent-scope acq_rel counter; nothing waits
+// on it) picks the pivot of column j+1, swaps it into place inside the panel,
+// stores the reciprocal pivot and puts the counter back to zero.
 template <typename C>
 __device__ __forceinline__ void lu_col_body(const LuStep &st) {
   __shared__ double sv[256];
@@ -146,20 +147,24 @@ __device__ __forceinline__ void lu_col_body(const LuStep &st) {
   const int j = st.j, k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int blk = blockIdx.x - D.first_block;
   const int tid = threadIdx.x;
-  const int i = j + 1 + blk * 256 + tid;
+  const int t = tid % kColT;
+  const int i = j + 1 + blk * kColRows + tid / kColT;
   const bool next = j + 1 < k0 + jb;
   double v = -1.0;
   if (i < n) {
     C *row = (C *)D.A + (int64_t)i * D.ld;
     const C *prow = (const C *)D.A + (int64_t)j * D.ld;
+    // the kColT lanes of a row are adjacent lanes of one wave: all read row[j]
+    // before lane t == 0 stores the multiplier
     const C l = row[j] * (*(const C *)D.rpiv);
-    row[j] = l;
-    for (int c = j + 1; c < k0 + jb; ++c) row[c] = row[c] - l * prow[c];
-    if (next) v = cabs1(row[j + 1]);
+    if (t == 0) row[j] = l;
+    for (int c = j + 1 + t; c < k0 + jb; c += kColT) row[c] = row[c] - l * prow[c];
+    if (next && t == 0) v = cabs1(row[j + 1]);
   }
   if (!next) return;
+  const int nb = (n - j - 1 + kColRows - 1) / kColRows;
   sv[tid] = v;
-  si[tid] = i < n ? i : n;
+  si[tid] = (i < n && t == 0) ? i : n;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s && piv_better(sv[tid + s], si[tid + s], sv[tid], si[tid])) {
@@ -172,14 +177,12 @@ __device__ __forceinline__ void lu_col_body(const LuStep &st) {
     D.pval[blk] = sv[0];
     D.pidx[blk] = si[0];
     __threadfence();
-    const int nb = (n - j - 1 + 255) / 256;
     const int old = __hip_atomic_fetch_add(D.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     last = old == nb - 1;
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
-  const int nb = (n - j - 1 + 255) / 256;
   double best = -1.0;
   int bi = n;
   for (int q = tid; q < nb; q += 256) {

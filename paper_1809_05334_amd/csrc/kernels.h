@@ -54,6 +54,8 @@ __global__ void k_add_near_c(ZOut Z, int64_t start, int n, fz *A, int64_t lda);
 // The panel, swap, triangular-solve and trailing-update launches of the
 // block LU advance up to kLuMaxDom domains at the same global column.
 constexpr int kLuNB = 64;
+constexpr int kColT = 4;        // lanes per row in the panel column kernel
+constexpr int kColRows = 64;    // rows per thread block of the panel column kernel (256 / kColT)
 constexpr int kLuMaxDom = 8;
 struct LuDom {
   void *A;            // the domain's block (dz or fz), row-major, leading dimension ld, factored in place
