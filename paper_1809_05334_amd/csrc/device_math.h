@@ -110,6 +110,17 @@ __device__ __forceinline__ void stage_table(const double *__restrict__ pack, int
 
 __device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// integer field of the packed table (value in the low 32 bits of the slot)
+__device__ __forceinline__ int pint(double slot) { return ufirst(__double2loint(slot)); }
+
+// 1/sqrt(x) for x > 0 (finite): hardware estimate refined by one third-order
+// Householder step, r <- r (1 + e/2 + 3 e^2/8) with e = 1 - x r^2.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * r, r, 1.0);
+  return fma(r * e, fma(e, 0.375, 0.5), r);
+}
+
 // W Chebyshev series with the same coefficients c[0..K] (K even, zero-padded)
 // at W arguments t[w]: interleaved Clenshaw recurrences, two coefficients per
 // step, each coefficient read once for all W.
@@ -161,14 +172,14 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     sim[w] = 0.0;
   }
   // spatial series
-  const int nimg = ufirst((int)P[pk::NIMG]);
+  const int nimg = pint(P[pk::NIMG]);
   int off = pk::IMAGES;
 #pragma unroll 1
   for (int i = 0; i < nimg; ++i) {
     const double *R = P + off;
     const double xa = R[0], xs = R[1], cre = R[2], cim = R[3];
-    const int im = ufirst((int)R[4]), in = ufirst((int)R[5]), K = ufirst((int)R[6]);
-    off += ufirst((int)R[7]);
+    const int im = pint(R[4]), in = pint(R[5]), K = pint(R[6]);
+    off += pint(R[7]);
     double t[W], sc[W];
     bool touch[W];
 #pragma unroll
@@ -180,8 +191,14 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
         const int um = im - im0[w], un = in - in0[w];
         touch[w] = um >= -1 && um <= 1 && un >= -1 && un <= 1 && ((mask >> ((um + 1) * 3 + (un + 1))) & 1);
       }
-      const double rinv = rsqrt(R2);
-      const double x = R2 > 0.0 ? R2 * rinv * E : 0.0;
+      double rinv, x;
+      if (TOUCH) {   // a touching image can sit at R = 0 (its H fit is evaluated at x = 0)
+        rinv = rsqrt(R2);
+        x = R2 > 0.0 ? R2 * rinv * E : 0.0;
+      } else {       // separations of non-touching elements never vanish
+        rinv = rsqrt_pos(R2);
+        x = R2 * rinv * E;
+      }
       t[w] = fma(x - xa, xs, -1.0);
       sc[w] = touch[w] ? E : rinv;
     }
@@ -212,7 +229,7 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
       if (any) {
         // touching images use the H fit (extracted 1/(4 pi R))
         const double *Hb = R + 8 + K + 4;
-        const int HK = ufirst((int)Hb[0]);
+        const int HK = pint(Hb[0]);
 #pragma unroll
         for (int w = 0; w < W; ++w)
           if (touch[w]) f[w] = clenshaw4(Hb + 4, HK, t[w]);
@@ -253,13 +270,13 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     for (int w = 0; w < W; ++w) e[w] = erow[w];
 #pragma unroll 1
     for (int q = 0; q < kPgfSide; ++q) {
-      const int moff = ufirst((int)P[pk::MODES + p * kPgfSide + q]);
+      const int moff = pint(P[pk::MODES + p * kPgfSide + q]);
       if (moff > 0) {
         const double *M = P + moff;
-        const int K = ufirst((int)M[0]);
+        const int K = pint(M[0]);
         double kr[W];
         clenshaw_w<W>(M + 4, K, tw, kr);
-        if (M[1] != 0.0) {
+        if (pint(M[1]) != 0) {
           double ki[W];
           clenshaw_w<W>(M + 4 + K + 4, K, tw, ki);
 #pragma unroll

@@ -86,6 +86,8 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
 //     [xa, xs, cre, cim, m, n, K, len] f[0..K] (pad to 4) [HK, 0, 0, 0] h[0..HK] (pad to 4)
 //     (the H block only for touching classes; len = record length)
 //   mode records [K, cplx, 0, 0] kre[0..K] (pad) kim[0..K] (pad, complex orders only)
+// Integer fields (nimg, mode offsets, m, n, K, len, HK, cplx) hold the value in
+// the low 32 bits of the double slot.
 // K, HK are the degrees rounded up to a multiple of 4 (zero coefficients).
 constexpr int kPackImages = 116;
 void pack_pgf_table(const PgfTable &tab, std::vector<double> &out);

@@ -462,6 +462,15 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
 }
 
 // ---------------------------------------------------------------- packing
+// An integer field of the packed table: its value in the low 32 bits of the
+// double slot (the device reads the register half, no conversion).
+static double ibits(int v) {
+  const uint64_t u = (uint32_t)v;
+  double d;
+  std::memcpy(&d, &u, sizeof d);
+  return d;
+}
+
 void pack_pgf_table(const PgfTable &tab, std::vector<double> &out) {
   auto pad4 = [](int n) { return (n + 3) & ~3; };
   out.assign(kPackImages, 0.0);
@@ -471,25 +480,25 @@ void pack_pgf_table(const PgfTable &tab, std::vector<double> &out) {
     out[10 + i] = tab.ph0re[i];
     out[19 + i] = tab.ph0im[i];
   }
-  out[28] = tab.nimg;
+  out[28] = ibits(tab.nimg);
   for (int i = 0; i < tab.nimg; ++i) {
     const PgfImage &im = tab.img[i];
     const int K = pad4(im.deg), HK = im.hdeg >= 0 ? pad4(im.hdeg) : -1;
     const size_t start = out.size();
-    out.insert(out.end(), {im.xa, im.xs, im.cre, im.cim, (double)im.m, (double)im.n, (double)K, 0.0});
+    out.insert(out.end(), {im.xa, im.xs, im.cre, im.cim, ibits(im.m), ibits(im.n), ibits(K), 0.0});
     for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= im.deg ? im.f[k] : 0.0);
     if (HK >= 0) {
-      out.insert(out.end(), {(double)HK, 0.0, 0.0, 0.0});
+      out.insert(out.end(), {ibits(HK), 0.0, 0.0, 0.0});
       for (int k = 0; k < pad4(HK + 1); ++k) out.push_back(k <= im.hdeg ? im.h[k] : 0.0);
     }
-    out[start + 7] = (double)(out.size() - start);
+    out[start + 7] = ibits((int)(out.size() - start));
   }
   for (int idx = 0; idx < kPgfTerms; ++idx) {
     const PgfMode &md = tab.mode[idx];
     if (md.deg < 0) continue;
     const int K = pad4(md.deg);
-    out[32 + idx] = (double)out.size();
-    out.insert(out.end(), {(double)K, (double)md.cplx, 0.0, 0.0});
+    out[32 + idx] = ibits((int)out.size());
+    out.insert(out.end(), {ibits(K), ibits(md.cplx), 0.0, 0.0});
     for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kre[k] : 0.0);
     if (md.cplx)
       for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kim[k] : 0.0);
