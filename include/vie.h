@@ -139,8 +139,10 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
 int vie_fill(vie_ctx *ctx, double lambda_nm, double theta_rad, double phi_rad, const vie_c128 *eps_per_tet,
              int precision);
 
-/* LU factorisation with partial pivoting of every diagonal block A_dd
- * (Sec. 2.3, Eq. 6).  VIE_ESINGULAR on a zero pivot. */
+/* LU factorisation P A_dd = L U of every diagonal block A_dd (Sec. 2.3,
+ * Eq. 6), with tournament pivoting per 64-column panel by default or partial
+ * pivoting column by column (VIE_OPT_LU_PIVOT).  VIE_ESINGULAR on a zero
+ * pivot. */
 int vie_precond_factor(vie_ctx *ctx);
 
 /* Right-preconditioned restarted GMRES(restart) on Z M^-1 y = b, x = M^-1 y,
@@ -187,8 +189,9 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *ou
 int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z);
 
 /* ---------------------------------------------------------------- tuning
- * Launch shapes and graph capture.  None of them changes a result: every
- * variant computes the same sums in the same order. */
+ * Launch shapes, graph capture and the pivoting of the block LU.  Apart from
+ * VIE_OPT_LU_PIVOT none of them changes a result: every variant computes the
+ * same sums in the same order. */
 enum {
   VIE_OPT_GRAPH_STEPS = 1,  /* Arnoldi steps per captured HIP graph, 0 = plain launches (default);
                              * residual estimates are read back once per graph launch, so a solve
@@ -196,11 +199,16 @@ enum {
                              * non-null stream: vie_solve returns VIE_EINVAL on the null stream */
   VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
   VIE_OPT_TRSV_ROWS = 3,    /* triangular-solve update rows per wave: 1, 2, 4 (default) or 8 */
-  VIE_OPT_TRSV_COOP = 4     /* 1: each preconditioner apply runs its triangular-solve steps in one
+  VIE_OPT_TRSV_COOP = 4,    /* 1: each preconditioner apply runs its triangular-solve steps in one
                              * cooperative launch with grid barriers between steps (not inside
                              * captured graphs); 0 (default): one
                              * launch per step.  Use 1 only where no other context's work needs
                              * the device at the same time (a cooperative grid holds every CU). */
+  VIE_OPT_LU_PIVOT = 5      /* row pivoting of the next vie_precond_factor: 0 (default) tournament
+                             * pivoting, the pivot rows of each 64-column panel chosen by a
+                             * reduction tree of partial-pivoting eliminations on 128-row slices;
+                             * 1: partial pivoting column by column.  Both give P A = L U; the
+                             * factors, and so the rounding of M^{-1} v, differ between them */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);

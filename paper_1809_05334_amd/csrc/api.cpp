@@ -35,13 +35,15 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, dinv, tpart, tcount, plans;
+  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart, tcount,
+      plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, apart, kv, idx, jd, rhist;
   size_t total = 0;
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
   std::vector<int64_t> doff;       // per-domain offset of the diagonal-block inverses (elements)
+  std::vector<int64_t> toff;       // per-domain offset of the tournament tree nodes (nodes)
   int restart = 0;
   int64_t ldv = 0;
 };
@@ -70,6 +72,7 @@ struct vie_ctx {
   int trsv_rw = 4;                  // triangular-solve update rows per wave (1, 2, 4)
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
   int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
+  int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
   bool capturing = false;           // a graph capture is in progress on the stream
   int coop_grid = 0;                // co-resident thread blocks of the cooperative kernel
   struct CoopPlan {
@@ -89,6 +92,8 @@ struct vie_ctx {
   int last_pol = 0;
   std::vector<double> hist;
   double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
+  int32_t *pin_piv = nullptr;       // pinned: the pivots read back [N], the row permutation [N]
+  int64_t pin_piv_n = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
   vie_fill_stats fstats{};
   double t_fill = 0, t_factor = 0;
@@ -202,6 +207,21 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.lupv, 8 * (size_t)std::max<int64_t>(1, npart));
   put(L.lupi, 4 * (size_t)std::max<int64_t>(1, npart));
   put(L.lucnt, 4 * (size_t)std::max(1, t.ndom));
+  // tournament pivoting: nodes of the tree of the first (tallest) panel, the
+  // largest tree of the factorisation: leaves, then ceil(count / fan-in) per level
+  int64_t nodes = 0;
+  L.toff.assign(t.ndom, 0);
+  for (int d = 0; d < t.ndom; ++d) {
+    L.toff[d] = nodes;
+    for (int64_t c = nblk(t.dend[d] - t.dstart[d], mixed ? kTsRowsC : kTsRowsZ);;
+         c = (c + (mixed ? kTsFanC : kTsFanZ) - 1) / (mixed ? kTsFanC : kTsFanZ)) {
+      nodes += c;
+      if (c == 1) break;
+    }
+  }
+  put(L.tcand, 4 * (size_t)kLuNB * std::max<int64_t>(1, nodes));
+  put(L.ttcnt, 4 * (size_t)std::max<int64_t>(1, nodes));
+  put(L.tblk, fes * (size_t)kLuNB * kLuNB * std::max(1, t.ndom));
   L.restart = restart;
   L.ldv = (N + 31) / 32 * 32;
   put(L.V, 16 * (size_t)L.ldv * (restart + 1));
@@ -331,6 +351,7 @@ int vie_destroy(vie_ctx *ctx) {
   else (void)hipDeviceSynchronize();
   drop_graphs(ctx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pin_piv) (void)hipHostFree(ctx->pin_piv);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
@@ -409,6 +430,14 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   }
   Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz);
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
+  if (ctx->pin_piv_n < t.N) {
+    HIPCK(hipStreamSynchronize(ctx->stream));   // no upload of the permutation in flight
+    if (ctx->pin_piv) HIPCK(hipHostFree(ctx->pin_piv));
+    ctx->pin_piv = nullptr;
+    ctx->pin_piv_n = 0;
+    HIPCK(hipHostMalloc((void **)&ctx->pin_piv, 8 * (size_t)std::max<int64_t>(1, t.N), hipHostMallocDefault));
+    ctx->pin_piv_n = t.N;
+  }
   drop_graphs(ctx);   // captured graphs hold pointers into the old workspace
   ctx->L = L;
   ctx->ws = (char *)dev_ptr;
@@ -503,6 +532,7 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   // the triangular-solve and panel counters start (and always end) at zero
   HIPCK(hipMemsetAsync(ctx->ws + L.tcount.off, 0, L.tcount.bytes, ctx->stream));
   HIPCK(hipMemsetAsync(ctx->ws + L.lucnt.off, 0, L.lucnt.bytes, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->ws + L.ttcnt.off, 0, L.ttcnt.bytes, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
   ctx->state = S_BOUND;
   return VIE_OK;
@@ -655,15 +685,17 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
 
 namespace {
 
-enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM };
+enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_TSEL, LU_TFIN };
 
 // One launch of an LU kernel over every domain with blocks_of(d) > 0 thread
 // blocks (kLuMaxDom domains per launch; more domains take more launches).
 template <typename BlocksOf>
-void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of) {
+void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of,
+               int all_cols = 0) {
   LuStep st{};
   st.j = j;
   st.k0 = k0;
+  st.all_cols = all_cols;
   int total = 0;
   auto flush = [&]() {
     if (st.ndom == 0) return;
@@ -682,12 +714,20 @@ void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, 
         else hipLaunchKernelGGL(k_lu_swap_z, dim3(total), dim3(256), 0, ctx->stream, st);
         break;
       case LU_TRSM:
-        if (f32) hipLaunchKernelGGL(k_lu_trsm_c, dim3(total), dim3(64), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_trsm_z, dim3(total), dim3(64), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_trsm_c, dim3(total), dim3(256), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_trsm_z, dim3(total), dim3(256), 0, ctx->stream, st);
         break;
       case LU_GEMM:
         if (f32) hipLaunchKernelGGL(k_lu_gemm_c, dim3(total), dim3(256), 0, ctx->stream, st);
         else hipLaunchKernelGGL(k_lu_gemm_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        break;
+      case LU_TSEL:
+        if (f32) hipLaunchKernelGGL(k_lu_tsel_c, dim3(total), dim3(kTsRowsC * kTsLprC), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_tsel_z, dim3(total), dim3(kTsRowsZ * kTsLprZ), 0, ctx->stream, st);
+        break;
+      case LU_TFIN:
+        if (f32) hipLaunchKernelGGL(k_lu_tfin_c, dim3(total), dim3(256), 0, ctx->stream, st);
+        else hipLaunchKernelGGL(k_lu_tfin_z, dim3(total), dim3(256), 0, ctx->stream, st);
         break;
     }
     st.ndom = 0;
@@ -734,11 +774,14 @@ int vie_precond_factor(vie_ctx *ctx) {
     D.pval = ctx->ptr<double>(L.lupv) + pvoff;
     D.pidx = ctx->ptr<int32_t>(L.lupi) + pvoff;
     D.counter = ctx->ptr<int>(L.lucnt) + d;
+    D.cand = ctx->ptr<int32_t>(L.tcand) + L.toff[d] * kLuNB;
+    D.tcnt = ctx->ptr<int>(L.ttcnt) + L.toff[d];
+    D.tblk = factor_ptr(ctx, L.tblk, (int64_t)d * kLuNB * kLuNB);
     poff += n;
     pvoff += nblk(n, kColRows);
     maxn = std::max(maxn, n);
     if (n == 0) continue;
-    const dim3 cg(nblk(n, 256), n), ng(nblk(n, 256)), b256(256);
+    const dim3 cg(nblk(n, 256), std::min(n, 32768)), ng(nblk(n, 256)), b256(256);
     if (f32) {
       hipLaunchKernelGGL(k_copy_block_c, cg, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (fz *)D.A, D.ld);
       if (!zo.Z) hipLaunchKernelGGL(k_add_near_c, ng, b256, 0, ctx->stream, zo, (int64_t)t.dstart[d], n, (fz *)D.A, D.ld);
@@ -748,19 +791,33 @@ int vie_precond_factor(vie_ctx *ctx) {
     }
     LAUNCHCK();
   }
-  // right-looking blocked LU of every domain, advanced together column by column
+  // right-looking blocked LU of every domain, advanced together panel by panel
   for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
     auto jb_of = [&](int d) { return std::min(kLuNB, doms[d].n - k0); };
-    lu_launch(ctx, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
-    for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
-      lu_launch(ctx, LU_COL, doms, j, k0, [&](int d) {
-        const int n = doms[d].n;
-        return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
+    auto swap_blocks = [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
+    if (ctx->lu_pivot == 0) {
+      // tournament pivoting: pivot rows by a reduction tree, swap whole rows,
+      // then L21 = A21 U11^-1 below the factored top block
+      const int ts_rows = f32 ? kTsRowsC : kTsRowsZ;
+      lu_launch(ctx, LU_TSEL, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n - k0, ts_rows) : 0; });
+      lu_launch(ctx, LU_SWAP, doms, k0, k0, swap_blocks, 1);
+      lu_launch(ctx, LU_TFIN, doms, k0, k0, [&](int d) {
+        if (doms[d].n <= k0) return 0;
+        const int rest = doms[d].n - k0 - jb_of(d);
+        return rest > 0 ? (int)nblk(rest, kColRows) : 1;
       });
-    lu_launch(ctx, LU_SWAP, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; });
+    } else {
+      lu_launch(ctx, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
+      for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
+        lu_launch(ctx, LU_COL, doms, j, k0, [&](int d) {
+          const int n = doms[d].n;
+          return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
+        });
+      lu_launch(ctx, LU_SWAP, doms, k0, k0, swap_blocks);
+    }
     lu_launch(ctx, LU_TRSM, doms, k0, k0, [&](int d) {
       const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
-      return rest > 0 ? (int)nblk(rest, 64) : 0;
+      return rest > 0 ? (int)nblk(rest, kColRows) : 0;
     });
     lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) {
       const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
@@ -772,8 +829,6 @@ int vie_precond_factor(vie_ctx *ctx) {
   for (int d = 0; d < t.ndom; ++d) {
     const int n = doms[d].n;
     if (n == 0) continue;
-    hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, ctx->stream, n, (const int32_t *)doms[d].ipiv,
-                       perm + (doms[d].ipiv - ipiv));
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
     void *DL = factor_ptr(ctx, L.dinv, L.doff[d]);
     void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
@@ -789,13 +844,31 @@ int vie_precond_factor(vie_ctx *ctx) {
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->pinned, info, 4 * t.ndom, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->pin_piv, ipiv, 4 * (size_t)t.N, hipMemcpyDeviceToHost, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   float ms = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->t_factor = ms;
   const int32_t *inf = reinterpret_cast<const int32_t *>(ctx->pinned);
   for (int d = 0; d < t.ndom; ++d)
-    if (inf[d]) return fail(ctx, VIE_ESINGULAR, "zero pivot in block %d at column %d", d, inf[d] - 1);
+    if (inf[d] < 0) return fail(ctx, VIE_EDEVICE, "tournament pivoting of block %d chose a row outside the panel", d);
+    else if (inf[d]) return fail(ctx, VIE_ESINGULAR, "zero pivot in block %d at column %d", d, inf[d] - 1);
+  // row permutation of each block from its swaps (sequential by nature: done
+  // on the host from the pivots read back, then uploaded for the applies)
+  int32_t *hp = ctx->pin_piv + t.N;
+  for (int d = 0; d < t.ndom; ++d) {
+    const int64_t o = t.dstart[d], n = t.dend[d] - t.dstart[d];
+    const int32_t *ip = ctx->pin_piv + o;
+    int32_t *pm = hp + o;
+    for (int64_t i = 0; i < n; ++i) pm[i] = (int32_t)i;
+    for (int64_t j = 0; j < n; ++j) {
+      const int32_t p = ip[j];
+      if (p < j || p >= n) return fail(ctx, VIE_EDEVICE, "pivot %d of column %lld in block %d out of range", p,
+                                      (long long)j, d);
+      std::swap(pm[j], pm[p]);
+    }
+  }
+  HIPCK(hipMemcpyAsync(perm, hp, 4 * (size_t)t.N, hipMemcpyHostToDevice, ctx->stream));
   ctx->state = S_FACTORED;
   return VIE_OK;
 }
@@ -1407,6 +1480,10 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "cooperative triangular solves: 0 or 1");
       ctx->trsv_coop = value;
       return VIE_OK;
+    case VIE_OPT_LU_PIVOT:
+      if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "LU pivoting: 0 (tournament) or 1 (partial)");
+      ctx->lu_pivot = value;
+      return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
       if (value != 1 && value != 2 && value != 4 && value != 8)
         return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2, 4 or 8");
@@ -1424,6 +1501,7 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value) {
     case VIE_OPT_MATVEC_ROWS: *value = ctx->mv_rpw; return VIE_OK;
     case VIE_OPT_TRSV_ROWS: *value = ctx->trsv_rw; return VIE_OK;
     case VIE_OPT_TRSV_COOP: *value = ctx->trsv_coop; return VIE_OK;
+    case VIE_OPT_LU_PIVOT: *value = ctx->lu_pivot; return VIE_OK;
   }
   return VIE_EINVAL;
 }

@@ -30,10 +30,11 @@ __device__ __forceinline__ double cabs1(fz a) { return (double)(fabsf(a.re) + fa
 template <typename C>
 __device__ __forceinline__ void copy_block_body(const ZOut &Z, int64_t start, int n, C *__restrict__ A, int64_t lda) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
   if (c >= n) return;
-  const int64_t idx = (start + r) * Z.ld + start + c;
-  A[(int64_t)r * lda + c] = Z.Z ? cx<C>::of(Z.Z[idx]) : cx<C>::of(Z.Zs[idx]);
+  for (int r = blockIdx.y; r < n; r += gridDim.y) {   // rows grid-strided: gridDim.y is capped by the host
+    const int64_t idx = (start + r) * Z.ld + start + c;
+    A[(int64_t)r * lda + c] = Z.Z ? cx<C>::of(Z.Z[idx]) : cx<C>::of(Z.Zs[idx]);
+  }
 }
 
 // A += the FP64 near entries of the diagonal block (one thread per row; the
@@ -208,14 +209,15 @@ __device__ __forceinline__ void lu_col_body(const LuStep &st) {
   if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Apply the panel's row swaps to the columns outside the panel.
+// Apply the panel's row swaps to the columns outside the panel (to every
+// column with st.all_cols, after tournament pivoting).
 template <typename C>
 __device__ __forceinline__ void lu_swap_body(const LuStep &st) {
   const LuDom &D = st.d[lu_domain(st)];
   C *A = (C *)D.A;
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int c = (blockIdx.x - D.first_block) * 256 + threadIdx.x;
-  if (c >= n || (c >= k0 && c < k0 + jb)) return;
+  if (c >= n || (!st.all_cols && c >= k0 && c < k0 + jb)) return;
   for (int j = k0; j < k0 + jb; ++j) {
     const int p = D.ipiv[j];
     if (p != j) {
@@ -226,27 +228,456 @@ __device__ __forceinline__ void lu_swap_body(const LuStep &st) {
   }
 }
 
-// U12 = L11^{-1} A12 (L11 unit lower, jb <= 64): one wave per 64 columns, the
-// column block lives in LDS.
+// U12 = L11^{-1} A12 (L11 unit lower, jb <= 64), kColRows columns per
+// thread block: L11 staged in LDS, kColT lanes per column (lane t owns the
+// rows i = t (mod kColT) of its column), the dot products of the forward
+// substitution split over the lanes and combined by shuffles.
 template <typename C>
 __device__ __forceinline__ void lu_trsm_body(const LuStep &st) {
-  __shared__ C tile[64][65];
+  __shared__ C Lt[kLuNB][kLuNB + 1];
   const LuDom &D = st.d[lu_domain(st)];
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int64_t ld = D.ld;
   C *A = (C *)D.A;
-  const int lane = threadIdx.x;
-  const int c = k0 + jb + (blockIdx.x - D.first_block) * 64 + lane;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e / jb, c = e - r * jb;
+    Lt[r][c] = A[(int64_t)(k0 + r) * ld + k0 + c];
+  }
+  __syncthreads();
+  constexpr int kPer = kLuNB / kColT;
+  const int t = tid % kColT;
+  const int c = k0 + jb + (blockIdx.x - D.first_block) * kColRows + tid / kColT;
   const bool ok = c < n;
-  for (int i = 0; i < jb; ++i) tile[i][lane] = ok ? A[(int64_t)(k0 + i) * ld + c] : cx<C>::make(0, 0);
-  for (int i = 1; i < jb; ++i) {
-    const C *Lr = A + (int64_t)(k0 + i) * ld + k0;
-    C s = tile[i][lane];
-    for (int l = 0; l < i; ++l) s = s - Lr[l] * tile[l][lane];
-    tile[i][lane] = s;
+  C x[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    x[u] = (ok && kColT * u + t < jb) ? A[(int64_t)(k0 + kColT * u + t) * ld + c] : cx<C>::make(0, 0);
+#pragma clang loop unroll(full)
+  for (int i = 1; i < kLuNB; ++i) {
+    if (i < jb) {
+      C s = cx<C>::make(0, 0);
+#pragma clang loop unroll(full)
+      for (int u = 0; u < kPer; ++u)
+        if (kColT * u < i && kColT * u + t < i) s = s + Lt[i][kColT * u + t] * x[u];
+      s.re += __shfl_xor(s.re, 1);
+      s.im += __shfl_xor(s.im, 1);
+      s.re += __shfl_xor(s.re, 2);
+      s.im += __shfl_xor(s.im, 2);
+      if (t == i % kColT) x[i / kColT] = x[i / kColT] - s;
+    }
   }
   if (ok)
-    for (int i = 1; i < jb; ++i) A[(int64_t)(k0 + i) * ld + c] = tile[i][lane];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (kColT * u + t < jb) A[(int64_t)(k0 + kColT * u + t) * ld + c] = x[u];
+}
+
+// ------------------------------------------------------------ tournament panel
+// The pivot rows of a panel are chosen by a reduction tree (tournament
+// pivoting) instead of one global search per column:
+//   * a leaf thread block runs Gaussian elimination with partial pivoting on
+//     a slice of the panel's rows and keeps the kLuNB rows it chose;
+//   * up to TsCfg::fan sibling candidate sets are merged by the same elimination
+//     on their original rows; the last sibling to finish (agent-scope acq_rel
+//     counter of the parent node, put back to zero by that sibling; nothing
+//     waits on it) does the merge and climbs on;
+//   * the block that reaches the root holds the winners in pivot order and
+//     the LU factors of the panel restricted to them: it writes the row swaps
+//     (LAPACK order, as the column-by-column panel) and that factored
+//     kLuNB x kLuNB top block.
+// After the swaps (k_lu_swap over every column), k_lu_tfin stores the top
+// block and forms L21 = A21 U11^-1 for the rows below.  The result is an LU
+// factorisation P A = L U like partial pivoting's, with pivots chosen per
+// panel by the tournament; elimination inside a node is sequential, so the
+// tree depth (the panel height over the leaf slice, in powers of the fan-in)
+// sets the panel's latency.
+//
+// Inside a node the rows stay in registers: TsCfg::lpr lanes per row, lane t
+// owning the contiguous columns [t W, (t+1) W), W = kLuNB / lpr.  Rows are not
+// moved: a pivot row is marked used and its step recorded.  Each step takes
+// one barrier: every wave publishes its best candidate (a 64-bit key of the
+// magnitude and the row) and that row's remaining columns in LDS,
+// double-buffered by the step's parity, and every thread then picks the
+// winner of the waves.
+template <typename C> struct TsCfg;
+template <> struct TsCfg<dz> {
+  static constexpr int lpr = kTsLprZ, fan = kTsFanZ, rows = kTsRowsZ;
+};
+template <> struct TsCfg<fz> {
+  static constexpr int lpr = kTsLprC, fan = kTsFanC, rows = kTsRowsC;
+};
+template <typename C>
+struct TsShared {
+  static constexpr int kFan = TsCfg<C>::fan, kRows = TsCfg<C>::rows, kLpr = TsCfg<C>::lpr,
+                       kThreads = kRows * kLpr, kWaves = kThreads / 64, kW = kLuNB / kLpr;
+  C crow[2][kWaves][kLuNB];           // each wave's best candidate row, by step parity
+  unsigned long long key[2][kWaves];
+  int rid[kRows];                     // the node's rows (rows of the domain)
+  int order[kLuNB];                   // node rows in pivot order
+  int zero;                           // first zero pivot of the last elimination (1-based), 0 if none
+  int flag;
+  int nv[kFan];                       // valid candidates of each child
+};
+
+template <typename C>
+__device__ __forceinline__ C cinv(C d) {
+  typedef typename cx<C>::R R;
+  const R den = d.re * d.re + d.im * d.im;
+  if (!(den > R(0))) return cx<C>::make(0, 0);
+  const R s = R(1) / den;
+  return cx<C>::make(d.re * s, -d.im * s);
+}
+
+// x - l p as four fused multiply-adds
+template <typename C>
+__device__ __forceinline__ C fms(C x, C l, C p) {
+  return cx<C>::make(fma(-l.im, -p.im, fma(-l.re, p.re, x.re)), fma(-l.im, p.re, fma(-l.re, p.im, x.im)));
+}
+
+// Pivot key: the magnitude rounded to FP32 (its bits order like the value)
+// above the complement of the row, so a larger key is a larger magnitude, ties
+// to the smaller row; 0 = no candidate.
+__device__ __forceinline__ unsigned long long ts_key(double v, int r) {
+  return ((unsigned long long)__float_as_uint((float)v) << 32) | (unsigned)(0x7fffffff - r);
+}
+__device__ __forceinline__ int ts_key_row(unsigned long long k) { return 0x7fffffff - (int)(k & 0xffffffffu); }
+
+// Maximum of a 64-bit key over the wave, returned to every lane: DPP lane
+// permutations inside each row of 16 lanes (quad swaps, half-row and row
+// mirrors), then the four row maxima read out of lanes 0, 16, 32, 48.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)v, (int)(unsigned)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(v >> 32), (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  unsigned long long o;
+  o = dpp64<0xb1>(k);    // quad_perm [1,0,3,2]
+  k = o > k ? o : k;
+  o = dpp64<0x4e>(k);    // quad_perm [2,3,0,1]
+  k = o > k ? o : k;
+  o = dpp64<0x141>(k);   // row_half_mirror
+  k = o > k ? o : k;
+  o = dpp64<0x140>(k);   // row_mirror
+  k = o > k ? o : k;
+  unsigned long long m = readlane64(k, 0);
+  o = readlane64(k, 16);
+  m = o > m ? o : m;
+  o = readlane64(k, 32);
+  m = o > m ? o : m;
+  o = readlane64(k, 48);
+  return o > m ? o : m;
+}
+
+// This lane's columns of its row (row tid / lpr of S.rid, m valid rows; a
+// row outside the domain is read as zeros).
+template <typename C>
+__device__ __forceinline__ void ts_load(const TsShared<C> &S, const C *__restrict__ A, int64_t ld, int n, int k0,
+                                        int m, int jb, C (&x)[TsShared<C>::kW]) {
+  constexpr int L = TsShared<C>::kLpr, W = TsShared<C>::kW;
+  const int r = threadIdx.x / L, t = threadIdx.x % L;
+  const int g = r < m ? S.rid[r] : -1;
+  const bool ok = g >= 0 && g < n;
+  const C *row = A + (int64_t)(ok ? g : 0) * ld + k0 + t * W;
+#pragma unroll
+  for (int i = 0; i < W; ++i) x[i] = (ok && t * W + i < jb) ? row[i] : cx<C>::make(0, 0);
+}
+
+// Partial-pivoting elimination of the m x jb matrix held in x (m <= kRows
+// rows, S.rid): on return S.order[0 .. min(m, jb)) lists the pivot rows in
+// order, *step is this row's pivot step (-1 if none) and x holds L\U of the
+// panel restricted to the pivot rows.  Step j works on column j in block
+// b = (j mod W) / 8 of its owner lane o = j / W; the owner keeps column j in
+// the first register of that block by rotating the block one register per
+// step, so every register index is static with only the loop over blocks
+// unrolled (the loop over the 8 steps of a block is not: small code).
+template <typename C>
+__device__ __forceinline__ void ts_gepp(TsShared<C> &S, C (&x)[TsShared<C>::kW], int m, int jb, int *step) {
+  constexpr int L = TsShared<C>::kLpr, W = TsShared<C>::kW, NB = W / 8;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = tid / L, t = tid % L;
+  const bool valid = r < m;
+  const int steps = min(m, jb);
+  bool used = false;
+  int zero = 0;
+  *step = -1;
+#pragma unroll
+  for (int o = 0; o < L; ++o) {
+    const bool owner = t == o;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j0 = o * W + 8 * b;
+      if (j0 >= steps) break;
+#pragma clang loop unroll(disable)
+      for (int jt = 0; jt < 8; ++jt) {
+        const int j = j0 + jt;
+        if (j < steps) {
+          const int buf = j & 1;
+          // the non-owner lanes of a row carry no candidate (key 0)
+          const unsigned long long k =
+              wave_max_u64((owner && valid && !used) ? ts_key(cabs1(x[8 * b]), r) : 0ull);
+          if (k != 0ull && r == ts_key_row(k)) {   // the wave's best row: columns j .. kLuNB-1
+            C *dst = S.crow[buf][wave];
+            if (owner) {
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk)
+                if (kk + jt < 8) dst[j0 + kk + jt] = x[8 * b + kk];
+#pragma unroll
+              for (int bb = b + 1; bb < NB; ++bb)
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) dst[o * W + 8 * bb + kk] = x[8 * bb + kk];
+            } else if (t > o) {
+#pragma unroll
+              for (int i = 0; i < W; ++i) dst[t * W + i] = x[i];
+            }
+          }
+          if (lane == 0) S.key[buf][wave] = k;
+          __syncthreads();
+          unsigned long long best = S.key[buf][0];
+          int wb = 0;
+#pragma unroll
+          for (int w = 1; w < TsShared<C>::kWaves; ++w) {
+            const unsigned long long kw = S.key[buf][w];
+            if (kw > best) {
+              best = kw;
+              wb = w;
+            }
+          }
+          const int p = ts_key_row(best);
+          const bool nonzero = (best >> 32) != 0ull;
+          if (!nonzero && zero == 0) zero = j + 1;
+          if (r == p) {   // the pivot row: not updated any more
+            used = true;
+            *step = j;
+          }
+          if (tid == 0) S.order[j] = best != 0ull ? p : -1;
+          const C *prow = S.crow[buf][wb];
+          const C lraw = x[8 * b] * cinv(prow[j]);
+          C l = lraw;
+          if (L > 1) l = cx<C>::make(__shfl(lraw.re, (lane & ~(L - 1)) | o), __shfl(lraw.im, (lane & ~(L - 1)) | o));
+          if (valid && !used && nonzero) {
+            if (owner) {
+              C pv[8];
+#pragma unroll
+              for (int kk = 1; kk < 8; ++kk) pv[kk] = prow[j0 + min(kk + jt, 7)];
+#pragma unroll
+              for (int kk = 1; kk < 8; ++kk)
+                if (kk + jt < 8) x[8 * b + kk] = fms(x[8 * b + kk], l, pv[kk]);
+#pragma unroll
+              for (int bb = b + 1; bb < NB; ++bb) {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) pv[kk] = prow[o * W + 8 * bb + kk];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) x[8 * bb + kk] = fms(x[8 * bb + kk], l, pv[kk]);
+              }
+              x[8 * b] = l;
+            } else if (t > o) {
+#pragma unroll
+              for (int bb = 0; bb < NB; ++bb) {
+                C pv[8];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) pv[kk] = prow[t * W + 8 * bb + kk];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) x[8 * bb + kk] = fms(x[8 * bb + kk], l, pv[kk]);
+              }
+            }
+          }
+        }
+        // the owner rotates its block: column j + 1 to the front (after 8
+        // steps the block is back in column order)
+        if (owner) {
+          const C f = x[8 * b];
+#pragma unroll
+          for (int kk = 0; kk < 7; ++kk) x[8 * b + kk] = x[8 * b + kk + 1];
+          x[8 * b + 7] = f;
+        }
+      }
+    }
+  }
+  __syncthreads();   // S.order complete; the LDS rows may be reused
+  if (tid == 0) S.zero = zero;
+}
+
+// The row of the domain chosen at step j of the last elimination, -1 if the
+// record is out of range (a defect the root reports through info).
+template <typename C>
+__device__ __forceinline__ int ts_winner(const TsShared<C> &S, int j, int m) {
+  const int o = S.order[j];
+  return (o >= 0 && o < m) ? S.rid[o] : -1;
+}
+
+template <typename C>
+__device__ __forceinline__ void lu_tsel_body(const LuStep &st) {
+  __shared__ TsShared<C> S;
+  constexpr int kRows = TsShared<C>::kRows, kFan = TsShared<C>::kFan;
+  const int d = lu_domain(st);
+  const LuDom &D = st.d[d];
+  const C *A = (const C *)D.A;
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int q = blockIdx.x - D.first_block;
+  C x[TsShared<C>::kW];
+  int step;
+  // leaf: rows k0 + q kRows ...
+  const int r0 = k0 + q * kRows;
+  int m = min(kRows, n - r0);
+  if (tid < m) S.rid[tid] = r0 + tid;
+  __syncthreads();
+  int cnt = (n - k0 + kRows - 1) / kRows;   // nodes on this level
+  int base = 0;                             // first node id of this level
+  // one elimination per node this block takes: its leaf, then each merge
+  for (;;) {
+    ts_load(S, A, D.ld, n, k0, m, jb, x);
+    ts_gepp(S, x, m, jb, &step);
+    bool merged = false;
+    while (cnt > 1 && !merged) {
+      const int nc = min(m, jb);
+      const int first = q & ~(kFan - 1), nchild = min(kFan, cnt - first);
+      const int pbase = base + cnt, parent = pbase + q / kFan;
+      if (nchild > 1) {
+        // candidate lists pass between thread blocks through agent-scope
+        // atomic stores and loads; the last of the siblings to finish merges
+        if (tid < kLuNB)
+          __hip_atomic_store(D.cand + (int64_t)(base + q) * kLuNB + tid, tid < nc ? ts_winner(S, tid, m) : -1,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) {
+          const int old = __hip_atomic_fetch_add(D.tcnt + parent, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+          S.flag = old == nchild - 1;
+          if (S.flag) __hip_atomic_store(D.tcnt + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!S.flag) return;   // a sibling merges
+        __threadfence();
+        // the children are consecutive nodes; wave w < nchild loads child w,
+        // compacted in child order with empty entries dropped
+        int *c0 = D.cand + (int64_t)(base + first) * kLuNB;
+        const int rr = wave < nchild ? __hip_atomic_load(c0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+        const unsigned long long vm = __ballot(rr >= 0);
+        if (lane == 0 && wave < kFan) S.nv[wave] = wave < nchild ? __popcll(vm) : 0;
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wave && w < kFan; ++w) off += S.nv[w];
+        if (rr >= 0) S.rid[off + __popcll(vm & ((1ull << lane) - 1ull))] = rr;
+        m = 0;
+        for (int w = 0; w < kFan; ++w) m += S.nv[w];
+        __syncthreads();
+        merged = true;
+      }   // else alone in its group: its candidates go up unchanged
+      base = pbase;
+      cnt = (cnt + kFan - 1) / kFan;
+      q /= kFan;
+    }
+    if (!merged) break;   // cnt == 1: this block holds the root
+  }
+  // root: the pivot rows in S.order, their LU in the registers of their lanes
+  {
+    constexpr int L = TsShared<C>::kLpr, W = TsShared<C>::kW;
+    C *T = (C *)D.tblk;
+    const int t = tid % L;
+    if (step >= 0)
+#pragma unroll
+      for (int i = 0; i < W; ++i)
+        if (t * W + i < jb) T[step * kLuNB + t * W + i] = x[i];
+  }
+  // LAPACK-order swaps, by wave 0 alone: step j swaps position k0+j with the
+  // current position of winner j.  Lane e holds entry e of the list of rows
+  // that left their positions (dr) and where they are now (dp); lane j keeps
+  // the swap of step j.
+  if (wave == 0) {
+    int dr = -1, dp = -1, nd = 0, ipv = 0;
+    bool bad = false;
+    for (int j = 0; j < jb; ++j) {
+      const int w = ts_winner(S, j, m), tgt = k0 + j;
+      bad = bad || w < k0 || w >= n;
+      const unsigned long long fw = __ballot(dr == w), fy = __ballot(dp == tgt);
+      const int iw = fw ? __ffsll((long long)fw) - 1 : -1, iy = fy ? __ffsll((long long)fy) - 1 : -1;
+      const int p = iw >= 0 ? __builtin_amdgcn_readlane(dp, iw) : w;
+      if (lane == j) ipv = p;
+      if (p != tgt) {
+        const int y = iy >= 0 ? __builtin_amdgcn_readlane(dr, iy) : tgt;   // the row now at tgt moves to p
+        if (lane == iw) dp = tgt;
+        if (iy >= 0) {
+          if (lane == iy) dp = p;
+        } else {
+          if (lane == nd) {
+            dr = y;
+            dp = p;
+          }
+          ++nd;
+        }
+      }
+    }
+    if (bad) {   // never expected: keep the factorisation in bounds and report it
+      if (lane < jb) D.ipiv[k0 + lane] = k0 + lane;
+      if (lane == 0) *D.info = -1;
+    } else {
+      if (lane < jb) D.ipiv[k0 + lane] = ipv;
+      if (lane == 0 && S.zero && *D.info == 0) *D.info = k0 + S.zero;
+    }
+  }
+}
+
+// Store the factored top block (thread block 0 of the domain) and solve
+// x U11 = a for every row below it, kColT lanes per row: lane t owns the
+// columns j = t (mod kColT), the dot products are split over the lanes and
+// combined by shuffles.
+template <typename C>
+__device__ __forceinline__ void lu_tfin_body(const LuStep &st) {
+  __shared__ C U[kLuNB][kLuNB + 1];
+  __shared__ C rinv[kLuNB];
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
+  const int blk = blockIdx.x - D.first_block;
+  const int tid = threadIdx.x;
+  const C *T = (const C *)D.tblk;
+  C *A = (C *)D.A;
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e / jb, c = e - r * jb;
+    U[r][c] = T[r * kLuNB + c];
+  }
+  __syncthreads();
+  if (tid < jb) rinv[tid] = cinv(U[tid][tid]);
+  if (blk == 0)
+    for (int e = tid; e < jb * jb; e += 256) {
+      const int r = e / jb, c = e - r * jb;
+      A[(int64_t)(k0 + r) * D.ld + k0 + c] = U[r][c];
+    }
+  __syncthreads();
+  constexpr int kPer = kLuNB / kColT;
+  const int t = tid % kColT;
+  const int i = k0 + jb + blk * kColRows + tid / kColT;
+  const bool ok = i < n;
+  C *row = A + (int64_t)(ok ? i : 0) * D.ld + k0;
+  C x[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) x[u] = (ok && kColT * u + t < jb) ? row[kColT * u + t] : cx<C>::make(0, 0);
+#pragma clang loop unroll(full)
+  for (int j = 0; j < kLuNB; ++j) {
+    if (j < jb) {
+      C s = cx<C>::make(0, 0);
+#pragma clang loop unroll(full)
+      for (int u = 0; u < kPer; ++u)
+        if (kColT * u < j && kColT * u + t < j) s = s + x[u] * U[kColT * u + t][j];
+      s.re += __shfl_xor(s.re, 1);
+      s.im += __shfl_xor(s.im, 1);
+      s.re += __shfl_xor(s.re, 2);
+      s.im += __shfl_xor(s.im, 2);
+      if (t == j % kColT) x[j / kColT] = (x[j / kColT] - s) * rinv[j];
+    }
+  }
+  if (ok)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (kColT * u + t < jb) row[kColT * u + t] = x[u];
 }
 
 // A22 -= L21 U12 on the matrix cores.  Tile 64 x 64 per block of 4 waves
@@ -415,22 +846,14 @@ __global__ __launch_bounds__(256) void k_lu_col_z(LuStep st) { lu_col_body<dz>(s
 __global__ __launch_bounds__(256) void k_lu_col_c(LuStep st) { lu_col_body<fz>(st); }
 __global__ __launch_bounds__(256) void k_lu_swap_z(LuStep st) { lu_swap_body<dz>(st); }
 __global__ __launch_bounds__(256) void k_lu_swap_c(LuStep st) { lu_swap_body<fz>(st); }
-__global__ __launch_bounds__(64) void k_lu_trsm_z(LuStep st) { lu_trsm_body<dz>(st); }
-__global__ __launch_bounds__(64) void k_lu_trsm_c(LuStep st) { lu_trsm_body<fz>(st); }
+__global__ __launch_bounds__(256) void k_lu_trsm_z(LuStep st) { lu_trsm_body<dz>(st); }
+__global__ __launch_bounds__(256) void k_lu_trsm_c(LuStep st) { lu_trsm_body<fz>(st); }
+__global__ __launch_bounds__(TsShared<dz>::kThreads) void k_lu_tsel_z(LuStep st) { lu_tsel_body<dz>(st); }
+__global__ __launch_bounds__(TsShared<fz>::kThreads) void k_lu_tsel_c(LuStep st) { lu_tsel_body<fz>(st); }
+__global__ __launch_bounds__(256) void k_lu_tfin_z(LuStep st) { lu_tfin_body<dz>(st); }
+__global__ __launch_bounds__(256) void k_lu_tfin_c(LuStep st) { lu_tfin_body<fz>(st); }
 
 // ------------------------------------------------------------ apply
-// perm[i] = original row now at position i, from the sequential swaps ipiv.
-__global__ void k_lu_perm(int n, const int32_t *__restrict__ ipiv, int32_t *__restrict__ perm) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int i = 0; i < n; ++i) perm[i] = i;
-  for (int j = 0; j < n; ++j) {
-    const int p = ipiv[j];
-    const int t = perm[j];
-    perm[j] = perm[p];
-    perm[p] = t;
-  }
-}
-
 // z[i] = v[perm[i]] for one block (offset `off` in the global vectors)
 __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, const dz *__restrict__ v,
                           dz *__restrict__ z) {

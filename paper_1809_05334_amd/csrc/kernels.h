@@ -57,32 +57,43 @@ constexpr int kLuNB = 64;
 constexpr int kColT = 4;        // lanes per row in the panel column kernel
 constexpr int kColRows = 64;    // rows per thread block of the panel column kernel (256 / kColT)
 constexpr int kLuMaxDom = 8;
+// Tournament nodes: 256 rows and four children per node; a row takes two
+// lanes for FP64 factors (512 threads), one lane for FP32 (256 threads).
+constexpr int kTsFanZ = 4, kTsFanC = 4;
+constexpr int kTsRowsZ = kTsFanZ * kLuNB, kTsRowsC = kTsFanC * kLuNB;
+constexpr int kTsLprZ = 2, kTsLprC = 1;
 struct LuDom {
   void *A;            // the domain's block (dz or fz), row-major, leading dimension ld, factored in place
   int64_t ld;
   int n;
   int first_block;    // first thread block of this domain in the launch
   int32_t *ipiv;      // row swaps (LAPACK order)
-  int32_t *info;      // first zero pivot (1-based), 0 if none
+  int32_t *info;      // first zero pivot (1-based), 0 if none, -1 if tournament pivoting went out of range
   void *rpiv;         // reciprocal of the current pivot (same element type as A)
   double *pval;       // per-thread-block pivot candidates (k_lu_col)
   int32_t *pidx;
   int *counter;       // zero between launches
+  // tournament pivoting (k_lu_tsel / k_lu_tfin)
+  int32_t *cand;      // candidate rows of each tree node, kLuNB per node (-1 = none)
+  int *tcnt;          // per tree node: children that finished, zero between launches
+  void *tblk;         // the panel's factored top block, kLuNB x kLuNB row-major (type of A)
 };
 struct LuStep {
   LuDom d[kLuMaxDom];
   int ndom, j, k0;    // current column and panel start
+  int all_cols;       // k_lu_swap: swap inside the panel columns too
 };
 #define VIE_DECL_LU(T)                       \
   __global__ void k_lu_pivot_##T(LuStep st); \
   __global__ void k_lu_col_##T(LuStep st);   \
   __global__ void k_lu_swap_##T(LuStep st);  \
   __global__ void k_lu_trsm_##T(LuStep st);  \
-  __global__ void k_lu_gemm_##T(LuStep st);
+  __global__ void k_lu_gemm_##T(LuStep st);  \
+  __global__ void k_lu_tsel_##T(LuStep st);  \
+  __global__ void k_lu_tfin_##T(LuStep st);
 VIE_DECL_LU(z)
 VIE_DECL_LU(c)
 #undef VIE_DECL_LU
-__global__ void k_lu_perm(int n, const int32_t *ipiv, int32_t *perm);
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
 __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *Dinv);

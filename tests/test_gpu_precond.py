@@ -8,6 +8,8 @@ through the C-ABI:
     LAPACK solve of Z_dd), including more domains than one launch carries;
   * with one domain M = Z, so right-preconditioned GMRES stops after one
     iteration;
+  * tournament pivoting (the default) and partial pivoting column by column
+    both factor every block: their M^{-1} v agree, on both precision paths;
   * the GMRES solution satisfies Z x = b.
 """
 import numpy as np
@@ -104,3 +106,39 @@ def test_multidomain_solution_satisfies_Zx_eq_b(vie):
         Zr = s.read_Z(rr.ravel(), cc.ravel()).reshape(len(rows), N)
         r[rows] -= Zr @ x
     assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tournament_and_partial_pivoting_agree(vie, prec):
+    """One domain of 3,200 unknowns: 50 panels, a tournament tree of up to 25
+    leaves with odd node counts on several levels."""
+    m = slab_3200(1)
+    p = vie.VIE_FP64 if prec == "fp64" else vie.VIE_MIXED_FP32
+    s = vie.Solver()
+    s.upload_mesh(m)
+    s.bind(p, 30)
+    s.fill(600.0, 0.3, 0.2, W.slab_eps(m))
+    N = s.num_unknowns()
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    assert s.get_option(vie.VIE_OPT_LU_PIVOT) == 0
+    s.factor()
+    z_t = s.precond_apply(v)
+    s.set_option(vie.VIE_OPT_LU_PIVOT, 1)
+    assert s.get_option(vie.VIE_OPT_LU_PIVOT) == 1
+    s.factor()
+    z_p = s.precond_apply(v)
+    with pytest.raises(vie.VieError):
+        s.set_option(vie.VIE_OPT_LU_PIVOT, 2)
+    A = read_block(s, 0, N)
+    if prec == "fp64":
+        assert np.linalg.norm(z_t - z_p) < 1e-10 * np.linalg.norm(z_p)
+        for z in (z_t, z_p):
+            assert np.linalg.norm(A @ z - v) < 1e-12 * np.linalg.norm(v)
+    else:
+        # FP32 factors: the tournament's error is that of partial pivoting's
+        # up to a small factor (both are backward-stable FP32 eliminations)
+        zs = np.linalg.solve(A, v)
+        e_t = np.linalg.norm(z_t - zs) / np.linalg.norm(zs)
+        e_p = np.linalg.norm(z_p - zs) / np.linalg.norm(zs)
+        assert e_p < 1e-3 and e_t < 3 * e_p + 1e-6, (e_t, e_p)
