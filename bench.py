@@ -119,7 +119,7 @@ def main():
     from paper_1809_05334_amd import vie
     from paper_1809_05334_amd import workloads as W
 
-    mesh = W.config2_mesh()
+    mesh = W.plasmonic_cell_mesh()
     lams = np.linspace(400.0, 800.0, 41)
     eps_all = [W.osc_eps(mesh, l) for l in lams]
 

@@ -19,7 +19,7 @@ from .serve import Server, VieBackend, summarize
 
 def cell_requests(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
     from . import workloads as W
-    cells = W.config4_cells(n_cells, seed=seed, n_lo=n_lo, n_hi=n_hi)
+    cells = W.batch_cells(n_cells, seed=seed, n_lo=n_lo, n_hi=n_hi)
     return [{"rid": i, "arrival": 0.0, "cell": c, "lambda": c["lambda"], "theta": c["theta"], "phi": c["phi"],
              "pol": c["pol"]} for i, c in enumerate(cells)]
 

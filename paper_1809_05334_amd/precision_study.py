@@ -34,7 +34,7 @@ def main():
     from . import vie
     from . import workloads as W
 
-    mesh = W.config3_mesh()
+    mesh = W.plasmonic_cell_fine_mesh()
     thetas = [float(v) for v in args.thetas.split(",")]
     phis = [float(v) for v in args.phis.split(",")]
     lams = [float(v) for v in args.lambdas.split(",")]

@@ -107,7 +107,7 @@ def drude_eps(lambda_nm, eps_inf=3.7, wp_ev=9.0, gamma_ev=0.02):
     return eps_inf - wp_ev ** 2 / (w * w + 1j * gamma_ev * w)
 
 
-# ---------------------------------------------------------------- config 1
+# ---------------------------------------------------------------- homogeneous slab
 EPS_SLAB = 3.6 + 0.6j
 EPS_ACTIVE = 3.6 + 0.6j
 EPS_SPACER = 2.3 + 0.05j
@@ -127,12 +127,12 @@ def slab_eps(mesh, eps=EPS_SLAB):
     return np.full(mesh.nt, eps, dtype=np.complex128)
 
 
-# ---------------------------------------------------------------- configs 2-5
+# ---------------------------------------------------------------- plasmonic cells
 DOM_METAL, DOM_SPACER, DOM_ACTIVE = 0, 1, 2
 
 
 def osc_cell_mesh(a, t_active, t_spacer, radius, h_fine, h_coarse, b=None):
-    """Plasmonic organic-solar-cell unit cell (Fig. 1 shape, configs' reading):
+    """Plasmonic organic-solar-cell unit cell (Fig. 1 shape):
     active layer z in [0, t_active], spacer layer z in [t_active, t_active+t_spacer],
     a metal sphere of `radius` centred in the spacer layer at (a/2, b/2).
     Fine spacing over the sphere's x/y span and the whole spacer layer,
@@ -162,14 +162,14 @@ def osc_eps(mesh, lambda_nm, eps_active=EPS_ACTIVE, eps_spacer=EPS_SPACER, drude
     return eps_dom[mesh.tet_domain]
 
 
-def config2_mesh():
-    """Config 2: period 200 nm, active 80 nm + spacer 40 nm, Ag sphere r=20 nm;
+def plasmonic_cell_mesh():
+    """Plasmonic cell: period 200 nm, active 80 nm + spacer 40 nm, Ag sphere r=20 nm;
     5 nm over the sphere span and the spacer layer, 20 nm elsewhere."""
     return osc_cell_mesh(200.0, 80.0, 40.0, 20.0, 5.0, 20.0)
 
 
-def config3_mesh():
-    """Config 3: config 2's geometry at ~3.33 nm fine / 20 nm coarse."""
+def plasmonic_cell_fine_mesh():
+    """The plasmonic cell's geometry at ~3.33 nm fine / 20 nm coarse (N = 77,600)."""
     return osc_cell_mesh(200.0, 80.0, 40.0, 20.0, 40.0 / 12.0, 20.0)
 
 
@@ -188,8 +188,8 @@ def count_unknowns_paired(xs, ys, zs):
     return interior + facets_x + facets_y + facets_z
 
 
-def config4_cells(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
-    """Config 4 generator: independent cells of uneven size (seeded).
+def batch_cells(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
+    """Independent cells of uneven size (seeded), for batching and serving.
 
     Returns a list of dicts with the mesh parameters and one illumination
     (lambda, theta, phi, pol) per cell.  Fine spacing is coarsened from
@@ -228,13 +228,13 @@ def config4_cells(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
 
 
 def cell_mesh(cell):
-    """Mesh of a cell drawn by config4_cells / serve_trace."""
+    """Mesh of a cell drawn by batch_cells / serve_trace."""
     return osc_cell_mesh(cell["a"], cell["t_active"], cell["t_spacer"], cell["radius"], cell["h_fine"],
                          cell["h_coarse"])
 
 
 def large_cell(rng, n_lo=15000, n_hi=60000):
-    """Config-2 geometry (200 nm period, 80 + 40 nm layers, r = 20 nm sphere)
+    """The plasmonic cell's geometry (200 nm period, 80 + 40 nm layers, r = 20 nm sphere)
     with the fine spacing coarsened from 3.33 nm until N <= N_target."""
     n_target = int(rng.uniform(n_lo, n_hi))
     a, t_act, t_sp, radius, h_c = 200.0, 80.0, 40.0, 20.0, 20.0
@@ -253,11 +253,11 @@ def large_cell(rng, n_lo=15000, n_hi=60000):
 def serve_trace(rate, n_requests, seed=1, large_frac=0.1, n_lo=2000, n_hi=15000, large_lo=15000,
                 large_hi=60000):
     """Poisson request stream (requests / s) of (cell, lambda, theta, phi, pol):
-    1 - large_frac of the cells from the config-4 generator, large_frac large
-    cells of the config-2 geometry family.  Returns dicts with the cell, the
+    1 - large_frac of the cells from batch_cells, large_frac large cells of
+    the plasmonic cell's geometry.  Returns dicts with the cell, the
     illumination and the arrival time (s from the start)."""
     rng = np.random.default_rng(seed)
-    small = config4_cells(n_requests, seed=seed + 1000, n_lo=n_lo, n_hi=n_hi)
+    small = batch_cells(n_requests, seed=seed + 1000, n_lo=n_lo, n_hi=n_hi)
     t = 0.0
     out = []
     for i in range(n_requests):

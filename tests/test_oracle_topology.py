@@ -12,7 +12,7 @@ def build(mesh):
     return T.build(mesh.verts, mesh.tets, mesh.tet_domain, mesh.ndom, mesh.a, mesh.b)
 
 
-def test_config1_counts():
+def test_slab_100nm_counts():
     m = W.slab_mesh()
     t = build(m)
     assert len(m.tets) == 192
