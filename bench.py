@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_tt_far_traffic_osc_cell_N37376.md")
-FAR_SOURCES = ["k_fill.hip", "device_math.h", "common.h"]
+FAR_SOURCES = ["k_fill.hip", "device_math.h", "common.h", "tables.cpp"]   # kernel code and the tables that set its work
 
 
 def far_traffic():

@@ -345,9 +345,14 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
   *wood_margin = margin;
   if (margin < 0.02) return "";  // the caller reports the anomaly; no tables near gamma = 0
 
-  // significance scale: g_p at the largest in-cell separation
+  // Accuracy of the tables: a term is dropped when it stays below 1e-16 of
+  // g_p's size at the largest in-cell separation, and the fits resolve every
+  // term to 1e-15 (absolute) / 1e-14 (relative).  The lattice sum then stays
+  // within a few 1e-13 of its converged value (relative), three orders of
+  // magnitude inside what the fill is held to (1e-10 of each Z entry).
   const double G = 1.0 / (4 * kPi * std::sqrt(a * a + b * b + zspan * zspan));
-  const double sig = 1e-17 * G;
+  const double sig = 1e-16 * G;
+  const double fit_abs = 1e-15, fit_rel = 1e-14;
 
   const ld yl = y;
   const ld erfi_y = erfi_l(yl);
@@ -406,9 +411,9 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
     double ph = kx * jb.m * a + ky * jb.n * b;
     im.cre = std::cos(ph) / (4 * kPi);
     im.cim = std::sin(ph) / (4 * kPi);
-    im.deg = cheb_fit(Ffull, jb.xlo, jb.xhi, 1e-16, 1e-15, im.f, kPgfMaxDeg - 1);
+    im.deg = cheb_fit(Ffull, jb.xlo, jb.xhi, fit_abs, fit_rel, im.f, kPgfMaxDeg - 1);
     im.hdeg = -1;
-    if (jb.touching) im.hdeg = cheb_fit(Hx, jb.xlo, jb.xhi, 0.0, 1e-15, im.h, kPgfMaxDeg - 1);
+    if (jb.touching) im.hdeg = cheb_fit(Hx, jb.xlo, jb.xhi, 0.0, fit_rel, im.h, kPgfMaxDeg - 1);
     if (im.deg < 0 || (jb.touching && im.hdeg < 0)) bad = 1;
   });
   if (bad) return "lattice-sum table: spatial fit did not converge";
@@ -438,7 +443,7 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
         for (int j = 0; j <= 16; ++j) kmax = std::max(kmax, (double)std::fabs(K(wmax * j / 16.0)));
         if (kmax < sig) return;  // deg stays -1
         md.cplx = 0;
-        md.deg = cheb_fit(K, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg - 1);
+        md.deg = cheb_fit(K, 0.0, wmax, sig, fit_rel, md.kre, kPgfMaxDeg - 1);
         if (md.deg < 0) bad = 1;
       } else {
         // propagating order: gamma = +j beta
@@ -451,8 +456,8 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
           return pref * (e1 * erfc_l(zl(v, bl)) + e2 * erfc_l(zl(-v, bl)));
         };
         md.cplx = 1;
-        int d1 = cheb_fit([&](double w) { return Kc(w).real(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kre, kPgfMaxDeg - 1);
-        int d2 = cheb_fit([&](double w) { return Kc(w).imag(); }, 0.0, wmax, 1e-17 * G, 1e-15, md.kim, kPgfMaxDeg - 1);
+        int d1 = cheb_fit([&](double w) { return Kc(w).real(); }, 0.0, wmax, sig, fit_rel, md.kre, kPgfMaxDeg - 1);
+        int d2 = cheb_fit([&](double w) { return Kc(w).imag(); }, 0.0, wmax, sig, fit_rel, md.kim, kPgfMaxDeg - 1);
         if (d1 < 0 || d2 < 0) bad = 1;
         md.deg = std::max(d1, d2);
       }
