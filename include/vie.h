@@ -86,7 +86,8 @@ typedef struct {
   double true_rel_residual;  /* ||b - Z x|| / ||b|| recomputed in FP64 at the end */
   double t_fill_ms;          /* device time of the last vie_fill */
   double t_factor_ms;        /* device time of the last vie_precond_factor */
-  double t_solve_ms;         /* device time of this vie_solve */
+  double t_solve_ms;         /* device time of this vie_solve (of the pair for vie_solve_pair) */
+  int converged;             /* 1 if the stopping test was met, 0 at max_iter */
 } vie_solve_info;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -153,12 +154,28 @@ int vie_precond_factor(vie_ctx *ctx);
  * `info` may be NULL. */
 int vie_solve(vie_ctx *ctx, int polarisation, double tol, int max_iter, int restart, vie_solve_info *info);
 
+/* Both polarisations of the incident wave at once (Sec. 3 solves TE and TM
+ * for every incidence): two GMRES processes, TE and TM, run in lockstep and
+ * share each pass over Z (matvec) and over the LU factors (preconditioner
+ * apply), two vectors per pass.  Each process computes the same bits as
+ * vie_solve for its polarisation; one that converges first drops out and the
+ * other goes on alone.  info [2] (TE, TM; nullable): the shared wall time in
+ * t_solve_ms of both.  Afterwards vie_absorption / vie_read_solution /
+ * vie_residual_history refer to TM; vie_absorption_pol and
+ * vie_read_solution_pol reach either.  VIE_ENOCONV if either stops at
+ * max_iter (both solutions and info still written). */
+int vie_solve_pair(vie_ctx *ctx, double tol, int max_iter, int restart, vie_solve_info *info);
+
 /* Absorptance (absorbed / incident power) per domain of the last solution
  * (Sec. 3, Eq. 7, normalised by the incident power crossing one cell):
  *   A_d = k0 sum_{T in d} Im(eps_T) / |eps_T|^2 int_T |D/eps0|^2 dV / (cos th a b).
  * absorptance_per_domain [ndom]; R, T (nullable): reflectance and
  * transmittance summed over the propagating Floquet orders. */
 int vie_absorption(vie_ctx *ctx, double *absorptance_per_domain, double *R, double *T);
+
+/* The same for the solution of polarisation `polarisation` of the last
+ * vie_solve or vie_solve_pair; VIE_ESTATE if that solve did not cover it. */
+int vie_absorption_pol(vie_ctx *ctx, int polarisation, double *absorptance_per_domain, double *R, double *T);
 
 const char *vie_last_error(const vie_ctx *ctx);
 
@@ -176,6 +193,8 @@ int vie_read_Z(const vie_ctx *ctx, const int64_t *rows, const int64_t *cols, int
 /* Right-hand side of the last solve's polarisation, and the last solution x [N]. */
 int vie_read_rhs(const vie_ctx *ctx, vie_c128 *b);
 int vie_read_solution(const vie_ctx *ctx, vie_c128 *x);
+/* The last solution of polarisation `polarisation` (VIE_ESTATE if none). */
+int vie_read_solution_pol(const vie_ctx *ctx, int polarisation, vie_c128 *x);
 
 /* Evaluate g_p(r, r') (Sec. 2.2, Eqs. 3-4) on the device at n separations
  * delta_host [3n] = r - r', with the tables of the last vie_fill.

@@ -38,7 +38,11 @@ struct Layout {
   Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart, tcount,
       plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
-  Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, apart, kv, idx, jd, rhist;
+  // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
+  struct Kry {
+    Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, jd, rhist;
+  } K[2];
+  Region apart, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
@@ -81,16 +85,18 @@ struct vie_ctx {
     size_t off;                     // byte offset of the plan in the workspace
   };
   std::vector<CoopPlan> plans;
-  hipGraphExec_t gexec_g = nullptr; // graph_steps steps
-  hipGraphExec_t gexec_1 = nullptr; // one step (tail of a restart cycle)
-  int gexec_g_steps = 0;
+  // captured Arnoldi steps per Krylov process set (K[0], K[1], both):
+  // [0] graph_steps steps, [1] one step (tail of a restart cycle)
+  hipGraphExec_t gexec[3][2] = {};
+  int gexec_steps[3] = {};
   std::vector<int64_t> nrow;        // near-part CSR pattern (mixed precision), built on first use
   std::vector<int32_t> ncol;
   bool npat = false;
   std::vector<int32_t> color_off;
   int nhalf = 0, nface = 0;
-  int last_pol = 0;
-  std::vector<double> hist;
+  int last_pol = 0;                 // polarisation of the last solve (the TM one of a pair)
+  int sol_k[2] = {-1, -1};          // Krylov process holding the last TE / TM solution, -1: none
+  std::vector<double> hist[2];      // residual estimates of each Krylov process's last solve
   double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
   int32_t *pin_piv = nullptr;       // pinned: the pivots read back [N], the row permutation [N]
   int64_t pin_piv_n = 0;
@@ -189,7 +195,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
-  put(L.tpart, 16 * (size_t)kTrsvGroupsH * kTrsvNB * std::max(1, t.ndom));
+  put(L.tpart, 16 * 2 * (size_t)kTrsvPart * std::max(1, t.ndom));   // two right-hand sides per domain
   {
     int maxnbk = 1;
     for (int d = 0; d < t.ndom; ++d) maxnbk = std::max<int>(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
@@ -224,18 +230,20 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.tblk, fes * (size_t)kLuNB * kLuNB * std::max(1, t.ndom));
   L.restart = restart;
   L.ldv = (N + 31) / 32 * 32;
-  put(L.V, 16 * (size_t)L.ldv * (restart + 1));
-  put(L.H, 16 * (size_t)(restart + 2) * (restart + 1));
-  put(L.cs, 8 * (restart + 1));
-  put(L.sn, 16 * (restart + 1));
-  put(L.g, 16 * (restart + 2));
-  put(L.y, 16 * (restart + 1));
-  for (Region *r : {&L.vb, &L.vx, &L.vw, &L.vz, &L.vu, &L.vr, &L.vt, &L.vin}) put(*r, 16 * N);
-  put(L.jd, 256);
-  put(L.rhist, 8 * (size_t)(restart + 1));
-  put(L.dpart, 16 * (size_t)kRedBlocks * (restart + 1));
-  put(L.npart, 8 * kRedBlocks);
-  put(L.scal, 64);
+  for (Layout::Kry &k : L.K) {
+    put(k.V, 16 * (size_t)L.ldv * (restart + 1));
+    put(k.H, 16 * (size_t)(restart + 2) * (restart + 1));
+    put(k.cs, 8 * (restart + 1));
+    put(k.sn, 16 * (restart + 1));
+    put(k.g, 16 * (restart + 2));
+    put(k.y, 16 * (restart + 1));
+    for (Region *r : {&k.vb, &k.vx, &k.vw, &k.vz, &k.vu, &k.vr, &k.vt, &k.vin}) put(*r, 16 * N);
+    put(k.jd, 256);
+    put(k.rhist, 8 * (size_t)(restart + 1));
+    put(k.dpart, 16 * (size_t)kRedBlocks * (restart + 1));
+    put(k.npart, 8 * kRedBlocks);
+    put(k.scal, 64);
+  }
   put(L.apart, 8 * (size_t)nblk(nt, 256) * std::max(6 * 2 * 32, t.ndom));
   put(L.kv, 8 * 3 * 2 * 32);
   put(L.idx, 16 * (size_t)N);
@@ -258,10 +266,13 @@ void *factor_ptr(vie_ctx *ctx, const Region &r, int64_t elem) {
 
 void drop_graphs(vie_ctx *ctx) {
   ctx->plans.clear();
-  if (ctx->gexec_g) (void)hipGraphExecDestroy(ctx->gexec_g);
-  if (ctx->gexec_1) (void)hipGraphExecDestroy(ctx->gexec_1);
-  ctx->gexec_g = ctx->gexec_1 = nullptr;
-  ctx->gexec_g_steps = 0;
+  for (int m = 0; m < 3; ++m) {
+    for (hipGraphExec_t &g : ctx->gexec[m]) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+    ctx->gexec_steps[m] = 0;
+  }
 }
 
 void ensure_near_pattern(vie_ctx *ctx) {
@@ -304,6 +315,32 @@ int matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
     if (R == 2) hipLaunchKernelGGL(k_matvec_r2, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
     else if (R == 8) hipLaunchKernelGGL(k_matvec_r8, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
     else hipLaunchKernelGGL(k_matvec_r4, grid, blk, 0, ctx->stream, Z, L.ld, N, x, b, y);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "matvec: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+// y_q = Z x_q (or b_q - Z x_q) for two vectors in one pass over Z; each y_q
+// is bitwise the single-vector result.
+int matvec2(vie_ctx *ctx, const MvVecs &v) {
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  const int R = ctx->mv_rpw;
+  const dim3 grid(nblk(N, 4 * R)), blk(256);
+  if (ctx->precision == VIE_MIXED_FP32) {
+    const fz *Zs = ctx->ptr<fz>(L.Z);
+    const int64_t *rp = ctx->ptr<int64_t>(L.nrow);
+    const int32_t *cl = ctx->ptr<int32_t>(L.ncol);
+    const dz *vl = ctx->ptr<dz>(L.nval);
+    if (R == 2) hipLaunchKernelGGL(k_matvec2_mixed_r2, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, v);
+    else if (R == 8) hipLaunchKernelGGL(k_matvec2_mixed_r8, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, v);
+    else hipLaunchKernelGGL(k_matvec2_mixed_r4, grid, blk, 0, ctx->stream, Zs, L.ld, N, rp, cl, vl, v);
+  } else {
+    const dz *Z = ctx->ptr<dz>(L.Z);
+    if (R == 2) hipLaunchKernelGGL(k_matvec2_r2, grid, blk, 0, ctx->stream, Z, L.ld, N, v);
+    else if (R == 8) hipLaunchKernelGGL(k_matvec2_r8, grid, blk, 0, ctx->stream, Z, L.ld, N, v);
+    else hipLaunchKernelGGL(k_matvec2_r4, grid, blk, 0, ctx->stream, Z, L.ld, N, v);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "matvec: %s", hipGetErrorString(e));
@@ -876,14 +913,10 @@ int vie_precond_factor(vie_ctx *ctx) {
 // ---------------------------------------------------------------- solve
 namespace {
 
-// z = M^{-1} v for the block-diagonal preconditioner: per domain, permute by
-// the pivots, then L y = P v and U z = y by blocked triangular solves.  Each
-// k_trsv_step launch advances every domain (up to kTrsvMaxDom per launch) by
-// one diagonal block, so the launch count follows the largest domain.
 // The step list of the blocked triangular solves (L sweep, then U sweep) for
-// the given vectors; step k advances every domain (kTrsvMaxDom per entry) by
-// one diagonal block.
-std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
+// nv (1 or 2) right-hand sides; step k advances every domain (kTrsvMaxDom per
+// entry) by one diagonal block, so the step count follows the largest domain.
+std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const *s1, dz *const *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   int maxnbk = 0;
@@ -912,7 +945,7 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
         D.F = factor_ptr(ctx, L.F, L.foff[d]);
         D.ld = L.fld[d];
         D.n = n;
-        D.part = part + (int64_t)d * kTrsvGroupsH * kTrsvNB;
+        D.part = part + (int64_t)d * 2 * kTrsvPart;
         D.counter = cnt + d;
         D.first_block = st.total_blocks;
         int rest;
@@ -923,8 +956,10 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
           D.cb0 = bk > 0 ? D.nb0 - kTrsvNB : 0;
           D.cm = bk > 0 ? kTrsvNB : 0;
           D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)bk * kTrsvNB * kTrsvNB);
-          D.rhs = s1 + off;
-          D.sol = s2 + off;
+          for (int q = 0; q < nv; ++q) {
+            D.rhs[q] = s1[q] + off;
+            D.sol[q] = s2[q] + off;
+          }
           rest = D.cm > 0 ? n - D.nb0 - D.nm : 0;
         } else {
           const int bk = nbk - 1 - k;
@@ -933,8 +968,10 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
           D.cb0 = k > 0 ? D.nb0 + kTrsvNB : 0;
           D.cm = k > 0 ? std::min(kTrsvNB, n - D.cb0) : 0;
           D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(nbk + bk) * kTrsvNB * kTrsvNB);
-          D.rhs = s2 + off;
-          D.sol = out + off;
+          for (int q = 0; q < nv; ++q) {
+            D.rhs[q] = s2[q] + off;
+            D.sol[q] = out[q] + off;
+          }
           rest = D.cm > 0 ? D.nb0 : 0;
         }
         st.total_blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
@@ -946,9 +983,23 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, dz *out, dz *s1, dz *s2) {
   return plan;
 }
 
-void launch_trsv_step(vie_ctx *ctx, const TrsvStep &st) {
+void launch_trsv_step(vie_ctx *ctx, const TrsvStep &st, int nv) {
   const dim3 g(st.total_blocks), b(1024);
   const int rw = ctx->trsv_rw;
+  if (nv == 2) {
+    if (fp32_factors(ctx)) {
+      if (rw == 1) hipLaunchKernelGGL(k_trsv_step2_c_r1, g, b, 0, ctx->stream, st);
+      else if (rw == 2) hipLaunchKernelGGL(k_trsv_step2_c_r2, g, b, 0, ctx->stream, st);
+      else if (rw == 8) hipLaunchKernelGGL(k_trsv_step2_c_r8, g, b, 0, ctx->stream, st);
+      else hipLaunchKernelGGL(k_trsv_step2_c_r4, g, b, 0, ctx->stream, st);
+    } else {
+      if (rw == 1) hipLaunchKernelGGL(k_trsv_step2_z_r1, g, b, 0, ctx->stream, st);
+      else if (rw == 2) hipLaunchKernelGGL(k_trsv_step2_z_r2, g, b, 0, ctx->stream, st);
+      else if (rw == 8) hipLaunchKernelGGL(k_trsv_step2_z_r8, g, b, 0, ctx->stream, st);
+      else hipLaunchKernelGGL(k_trsv_step2_z_r4, g, b, 0, ctx->stream, st);
+    }
+    return;
+  }
   if (fp32_factors(ctx)) {
     if (rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
     else if (rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
@@ -1011,37 +1062,47 @@ int launch_trsv_coop(vie_ctx *ctx, const std::vector<TrsvStep> &plan, const dz *
   return VIE_OK;
 }
 
-// z = M^{-1} v for the block-diagonal preconditioner: per domain, permute by
-// the pivots, then L y = P v and U z = y by blocked triangular solves, either
-// one launch per step (the launch count follows the largest domain) or all
-// steps in one cooperative launch (VIE_OPT_TRSV_COOP, not under graph capture).
-int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) {
+// z_q = M^{-1} v_q (q < nv, nv = 1 or 2) for the block-diagonal
+// preconditioner: per domain, permute by the pivots, then L y = P v and
+// U z = y by blocked triangular solves, either one launch per step (the launch
+// count follows the largest domain; with nv = 2 each launch serves both
+// vectors from one pass over the factors) or, for one vector, all steps in one
+// cooperative launch (VIE_OPT_TRSV_COOP, not under graph capture).
+int apply_minv_n(vie_ctx *ctx, int nv, const dz *const *v, dz *const *out, dz *const *s1, dz *const *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   const int32_t *perm = ctx->ptr<int32_t>(L.perm);
-  int64_t poff = 0;
-  for (int d = 0; d < t.ndom; ++d) {
-    const int n = (int)(t.dend[d] - t.dstart[d]);
-    if (n > 0)
-      hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, (int64_t)t.dstart[d],
-                         perm + poff, v, s1);
-    poff += n;
+  for (int q = 0; q < nv; ++q) {
+    int64_t poff = 0;
+    for (int d = 0; d < t.ndom; ++d) {
+      const int n = (int)(t.dend[d] - t.dstart[d]);
+      if (n > 0)
+        hipLaunchKernelGGL(k_permute, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, n, (int64_t)t.dstart[d],
+                           perm + poff, v[q], s1[q]);
+      poff += n;
+    }
   }
-  const std::vector<TrsvStep> plan = trsv_plan(ctx, out, s1, s2);
   if (ctx->trsv_coop && !ctx->capturing) {
-    if (int rc = launch_trsv_coop(ctx, plan, v, out, s1, s2)) return rc;
+    for (int q = 0; q < nv; ++q) {
+      const std::vector<TrsvStep> plan = trsv_plan(ctx, 1, out + q, s1 + q, s2 + q);
+      if (int rc = launch_trsv_coop(ctx, plan, v[q], out[q], s1[q], s2[q])) return rc;
+    }
   } else {
-    for (const TrsvStep &st : plan) launch_trsv_step(ctx, st);
+    const std::vector<TrsvStep> plan = trsv_plan(ctx, nv, out, s1, s2);
+    for (const TrsvStep &st : plan) launch_trsv_step(ctx, st, nv);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "preconditioner apply: %s", hipGetErrorString(e));
   return VIE_OK;
 }
 
-int norm_to(vie_ctx *ctx, const dz *w, int64_t N, double *dst) {
+int apply_minv(vie_ctx *ctx, const dz *v, dz *out, dz *s1, dz *s2) { return apply_minv_n(ctx, 1, &v, &out, &s1, &s2); }
+
+// dst = ||w|| with the partial sums in the scratch of Krylov process k
+int norm_to(vie_ctx *ctx, int k, const dz *w, int64_t N, double *dst) {
   const Layout &L = ctx->L;
-  hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(256), 0, ctx->stream, w, N, ctx->ptr<double>(L.npart));
-  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(1), 0, ctx->stream, (const double *)ctx->ptr<double>(L.npart),
+  hipLaunchKernelGGL(k_norm2, dim3(kRedBlocks), dim3(256), 0, ctx->stream, w, N, ctx->ptr<double>(L.K[k].npart));
+  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(1), 0, ctx->stream, (const double *)ctx->ptr<double>(L.K[k].npart),
                      kRedBlocks, dst);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "norm: %s", hipGetErrorString(e));
@@ -1056,108 +1117,11 @@ int read_scalar(vie_ctx *ctx, const double *dev, double *host) {
   return VIE_OK;
 }
 
-// One Arnoldi step of right-preconditioned GMRES for the column j held in
-// device memory (L.jd): z = M^-1 V_j, w = Z z, CGS2 against V_0..V_j into
-// H[:, j], h_{j+1,j} = ||w||, Givens update of H and g (|g_{j+1}| into
-// rhist[j]), V_{j+1} = w / h_{j+1,j}, j += 1.  The launches do not depend on
-// j, so the step can be captured in a graph and replayed.
-int arnoldi_step(vie_ctx *ctx) {
+// Right-hand side <f_m, E^i> (Sec. 2.1) of the unit plane wave of the last
+// fill's incidence in polarisation pol, into b.
+void launch_rhs(vie_ctx *ctx, int pol, dz *b) {
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  dz *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g), *y = ctx->ptr<dz>(L.y);
-  dz *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz), *u = ctx->ptr<dz>(L.vu), *tmp = ctx->ptr<dz>(L.vt),
-     *vin = ctx->ptr<dz>(L.vin);
-  double *cs = ctx->ptr<double>(L.cs), *scal = ctx->ptr<double>(L.scal);
-  dz *sn = ctx->ptr<dz>(L.sn), *part = ctx->ptr<dz>(L.dpart);
-  int *jd = ctx->ptr<int>(L.jd);
-  const int ldh = L.restart + 2;
-  hipLaunchKernelGGL(k_arn_begin, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
-                     (const int *)jd, vin, N);
-  if (int rc = apply_minv(ctx, vin, z, tmp, u)) return rc;
-  if (int rc = matvec(ctx, z, nullptr, w)) return rc;
-  for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_dots_j, dim3(kRedBlocks), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv, (const int *)jd,
-                       (const dz *)w, N, part);
-    hipLaunchKernelGGL(k_dots_reduce_j, dim3(nblk(L.restart + 1, 128)), dim3(128), 0, ctx->stream, (const dz *)part,
-                       kRedBlocks, (const int *)jd, H, ldh, y, pass);
-    hipLaunchKernelGGL(k_update_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
-                       (const int *)jd, (const dz *)y, w, N);
-  }
-  if (int rc = norm_to(ctx, w, N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
-  hipLaunchKernelGGL(k_givens_j, dim3(1), dim3(1), 0, ctx->stream, H, ldh, (const int *)jd,
-                     (const double *)(scal + 2), cs, sn, g, ctx->ptr<double>(L.rhist));
-  hipLaunchKernelGGL(k_scale_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)w,
-                     (const double *)(scal + 2), V, L.ldv, (const int *)jd, N);
-  hipLaunchKernelGGL(k_jinc, dim3(1), dim3(1), 0, ctx->stream, jd);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "Arnoldi step: %s", hipGetErrorString(e));
-  return VIE_OK;
-}
-
-// Capture `steps` Arnoldi steps on the context's stream into an executable graph.
-int capture_steps(vie_ctx *ctx, int steps, hipGraphExec_t *out) {
-  hipGraph_t graph = nullptr;
-  HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-  ctx->capturing = true;   // no cooperative launches inside a captured graph
-  int rc = VIE_OK;
-  for (int q = 0; q < steps && rc == VIE_OK; ++q) rc = arnoldi_step(ctx);
-  ctx->capturing = false;
-  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
-  if (rc) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
-  }
-  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
-  return VIE_OK;
-}
-
-// Issue `steps` Arnoldi steps: replay a captured graph when graph mode is on.
-int issue_steps(vie_ctx *ctx, int steps) {
-  if (ctx->graph_steps > 0 && ctx->stream == nullptr)
-    return fail(ctx, VIE_EINVAL, "graph capture needs a non-null stream (VIE_OPT_GRAPH_STEPS)");
-  if (ctx->graph_steps <= 0) {
-    for (int q = 0; q < steps; ++q)
-      if (int rc = arnoldi_step(ctx)) return rc;
-    return VIE_OK;
-  }
-  hipGraphExec_t *ge = steps == 1 ? &ctx->gexec_1 : &ctx->gexec_g;
-  if (steps != 1 && ctx->gexec_g_steps != steps) {
-    if (ctx->gexec_g) (void)hipGraphExecDestroy(ctx->gexec_g);
-    ctx->gexec_g = nullptr;
-    ctx->gexec_g_steps = steps;
-  }
-  if (!*ge)
-    if (int rc = capture_steps(ctx, steps, ge)) return rc;
-  HIPCK(hipGraphLaunch(*ge, ctx->stream));
-  return VIE_OK;
-}
-
-}  // namespace
-
-int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
-  if (int r = check(ctx, S_FACTORED, "vie_solve")) return r;
-  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
-  if (!(tol > 0) || max_iter < 1) return fail(ctx, VIE_EINVAL, "bad tol / max_iter");
-  if (restart < 1 || restart > ctx->L.restart)
-    return fail(ctx, VIE_EINVAL, "restart %d exceeds the bound workspace (%d)", restart, ctx->L.restart);
-  HIPCK(hipSetDevice(ctx->device));
-  const MeshTopology &t = ctx->topo;
-  const Layout &L = ctx->L;
-  const int64_t N = t.N;
-  dz *V = ctx->ptr<dz>(L.V), *H = ctx->ptr<dz>(L.H), *g = ctx->ptr<dz>(L.g), *y = ctx->ptr<dz>(L.y);
-  dz *b = ctx->ptr<dz>(L.vb), *x = ctx->ptr<dz>(L.vx), *w = ctx->ptr<dz>(L.vw), *z = ctx->ptr<dz>(L.vz),
-     *u = ctx->ptr<dz>(L.vu), *r = ctx->ptr<dz>(L.vr), *tmp = ctx->ptr<dz>(L.vt);
-  double *scal = ctx->ptr<double>(L.scal), *rhist = ctx->ptr<double>(L.rhist);
-  int *jd = ctx->ptr<int>(L.jd);
-  const int ldh = L.restart + 2;
-  ctx->hist.clear();
-  ctx->last_pol = pol;
-  HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
-
-  // right-hand side <f_m, E^i>
   const double k0 = 2 * M_PI / ctx->lambda;
   const double st = std::sin(ctx->theta), ct = std::cos(ctx->theta), sp = std::sin(ctx->phi), cp = std::cos(ctx->phi);
   const double kix = k0 * st * cp, kiy = k0 * st * sp, kiz = -k0 * ct;
@@ -1174,103 +1138,341 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
   hipLaunchKernelGGL(k_rhs, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, N, ctx->ptr<int32_t>(L.utet),
                      ctx->ptr<int32_t>(L.uk), ctx->ptr<TetGeom>(L.tg), ctx->ptr<QuadRules>(L.quad),
                      (const dz *)ctx->ptr<dz>(L.alpha), kix, kiy, kiz, ex, ey, ez, b);
-  hipLaunchKernelGGL(k_zero, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N);
-  hipLaunchKernelGGL(k_copy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, r, (const dz *)b, N);
-  LAUNCHCK();
-  if (int rc = norm_to(ctx, r, N, scal + 0)) return rc;   // scal[0] = ||b||
-  double bnorm = 0;
-  if (int rc = read_scalar(ctx, scal + 0, &bnorm)) return rc;
-  if (!(bnorm > 0)) return fail(ctx, VIE_EINVAL, "zero right-hand side");
-  HIPCK(hipMemcpyAsync(scal + 1, scal + 0, 8, hipMemcpyDeviceToDevice, ctx->stream));  // scal[1] = beta
+}
 
+// One Arnoldi step of right-preconditioned GMRES for each Krylov process in
+// `mask` (bit k: process k), on the column j held in device memory (K[k].jd):
+// z = M^-1 V_j, w = Z z, CGS2 against V_0..V_j into H[:, j], h_{j+1,j} =
+// ||w||, Givens update of H and g (|g_{j+1}| into rhist[j]), V_{j+1} =
+// w / h_{j+1,j}, j += 1.  With both processes the preconditioner apply and the
+// matvec serve the two in one pass each; every other launch is per process,
+// so a process computes the same bits as alone.  The launches do not depend on
+// j, so steps can be captured in a graph and replayed.
+int arnoldi_step(vie_ctx *ctx, int mask) {
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  const int ldh = L.restart + 2;
+  int ks[2], np = 0;
+  for (int k = 0; k < 2; ++k)
+    if (mask >> k & 1) ks[np++] = k;
+  const dz *vin[2];
+  dz *z[2], *w[2], *tmp[2], *u[2];
+  for (int i = 0; i < np; ++i) {
+    const Layout::Kry &K = L.K[ks[i]];
+    dz *vi = ctx->ptr<dz>(K.vin);
+    vin[i] = vi;
+    z[i] = ctx->ptr<dz>(K.vz);
+    w[i] = ctx->ptr<dz>(K.vw);
+    tmp[i] = ctx->ptr<dz>(K.vt);
+    u[i] = ctx->ptr<dz>(K.vu);
+    hipLaunchKernelGGL(k_arn_begin, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(K.V),
+                       L.ldv, (const int *)ctx->ptr<int>(K.jd), vi, N);
+  }
+  if (int rc = apply_minv_n(ctx, np, vin, z, tmp, u)) return rc;
+  if (np == 2) {
+    const MvVecs v{{z[0], z[1]}, {nullptr, nullptr}, {w[0], w[1]}};
+    if (int rc = matvec2(ctx, v)) return rc;
+  } else if (int rc = matvec(ctx, z[0], nullptr, w[0])) {
+    return rc;
+  }
+  for (int i = 0; i < np; ++i) {
+    const Layout::Kry &K = L.K[ks[i]];
+    dz *V = ctx->ptr<dz>(K.V), *H = ctx->ptr<dz>(K.H), *g = ctx->ptr<dz>(K.g), *y = ctx->ptr<dz>(K.y);
+    double *cs = ctx->ptr<double>(K.cs), *scal = ctx->ptr<double>(K.scal);
+    dz *sn = ctx->ptr<dz>(K.sn), *part = ctx->ptr<dz>(K.dpart);
+    int *jd = ctx->ptr<int>(K.jd);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_dots_j, dim3(kRedBlocks), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
+                         (const int *)jd, (const dz *)w[i], N, part);
+      hipLaunchKernelGGL(k_dots_reduce_j, dim3(nblk(L.restart + 1, 128)), dim3(128), 0, ctx->stream,
+                         (const dz *)part, kRedBlocks, (const int *)jd, H, ldh, y, pass);
+      hipLaunchKernelGGL(k_update_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv,
+                         (const int *)jd, (const dz *)y, w[i], N);
+    }
+    if (int rc = norm_to(ctx, ks[i], w[i], N, scal + 2)) return rc;   // scal[2] = h_{j+1,j}
+    hipLaunchKernelGGL(k_givens_j, dim3(1), dim3(1), 0, ctx->stream, H, ldh, (const int *)jd,
+                       (const double *)(scal + 2), cs, sn, g, ctx->ptr<double>(K.rhist));
+    hipLaunchKernelGGL(k_scale_j, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)w[i],
+                       (const double *)(scal + 2), V, L.ldv, (const int *)jd, N);
+    hipLaunchKernelGGL(k_jinc, dim3(1), dim3(1), 0, ctx->stream, jd);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "Arnoldi step: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+// Capture `steps` Arnoldi steps of the processes in `mask` on the context's
+// stream into an executable graph.
+int capture_steps(vie_ctx *ctx, int mask, int steps, hipGraphExec_t *out) {
+  hipGraph_t graph = nullptr;
+  HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;   // no cooperative launches inside a captured graph
+  int rc = VIE_OK;
+  for (int q = 0; q < steps && rc == VIE_OK; ++q) rc = arnoldi_step(ctx, mask);
+  ctx->capturing = false;
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
+// Issue `steps` Arnoldi steps of the processes in `mask`: replay a captured
+// graph (one per process set and step count) when graph mode is on.
+int issue_steps(vie_ctx *ctx, int mask, int steps) {
+  if (ctx->graph_steps > 0 && ctx->stream == nullptr)
+    return fail(ctx, VIE_EINVAL, "graph capture needs a non-null stream (VIE_OPT_GRAPH_STEPS)");
+  if (ctx->graph_steps <= 0) {
+    for (int q = 0; q < steps; ++q)
+      if (int rc = arnoldi_step(ctx, mask)) return rc;
+    return VIE_OK;
+  }
+  const int m = mask - 1;
+  hipGraphExec_t *ge = steps == 1 ? &ctx->gexec[m][1] : &ctx->gexec[m][0];
+  if (steps != 1 && ctx->gexec_steps[m] != steps) {
+    if (ctx->gexec[m][0]) (void)hipGraphExecDestroy(ctx->gexec[m][0]);
+    ctx->gexec[m][0] = nullptr;
+    ctx->gexec_steps[m] = steps;
+  }
+  if (!*ge)
+    if (int rc = capture_steps(ctx, mask, steps, ge)) return rc;
+  HIPCK(hipGraphLaunch(*ge, ctx->stream));
+  return VIE_OK;
+}
+
+// One restarted GMRES process: Krylov workspace K[k], polarisation pol.
+struct Gmres {
+  int k = 0, pol = 0;
+  double bnorm = 0, beta = 0, true_rel = 1;
   int iters = 0, restarts = 0;
-  double beta = bnorm, true_rel = 1.0;
-  bool converged = false;
+  bool converged = false, done = false;
+  int jdone = 0;             // Arnoldi columns of the current cycle
+  bool est_ok = false, stop = false;
+};
+
+// Restarted right-preconditioned GMRES (Sec. 3) for np (1 or 2) processes in
+// lockstep, x0 = 0.  A restart cycle runs Arnoldi steps for every process that
+// has not stopped; a process stops at its own converged estimate or at the
+// cycle's end, and the others go on without it.  Each process takes the same
+// decisions, on the same values, as it would alone.
+int gmres(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int restart) {
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  const int ldh = L.restart + 2;
+  for (int i = 0; i < np; ++i) {
+    const Layout::Kry &K = L.K[P[i].k];
+    dz *b = ctx->ptr<dz>(K.vb), *x = ctx->ptr<dz>(K.vx), *r = ctx->ptr<dz>(K.vr);
+    ctx->hist[P[i].k].clear();
+    launch_rhs(ctx, P[i].pol, b);
+    hipLaunchKernelGGL(k_zero, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N);
+    hipLaunchKernelGGL(k_copy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, r, (const dz *)b, N);
+    LAUNCHCK();
+    if (int rc = norm_to(ctx, P[i].k, r, N, ctx->ptr<double>(K.scal) + 0)) return rc;   // scal[0] = ||b||
+  }
+  for (int i = 0; i < np; ++i) {
+    double *scal = ctx->ptr<double>(L.K[P[i].k].scal);
+    if (int rc = read_scalar(ctx, scal + 0, &P[i].bnorm)) return rc;
+    if (!(P[i].bnorm > 0)) return fail(ctx, VIE_EINVAL, "zero right-hand side");
+    HIPCK(hipMemcpyAsync(scal + 1, scal + 0, 8, hipMemcpyDeviceToDevice, ctx->stream));   // scal[1] = beta
+    P[i].beta = P[i].bnorm;
+  }
   const int G = std::max(1, ctx->graph_steps);
   while (true) {
-    // V0 = r / beta ; g = beta e1 ; j = 0
-    hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)r,
-                       (const double *)(scal + 1), V, N);
-    hipLaunchKernelGGL(k_ginit, dim3(1), dim3(256), 0, ctx->stream, g, restart + 1, (const double *)(scal + 1));
-    hipLaunchKernelGGL(k_jset, dim3(1), dim3(1), 0, ctx->stream, jd, 0);
-    LAUNCHCK();
-    int jdone = 0;
-    bool est_ok = false, stop = false;
+    int cyc = 0;   // processes in this restart cycle
+    for (int i = 0; i < np; ++i) {
+      Gmres &p = P[i];
+      if (p.done) continue;
+      cyc |= 1 << i;
+      const Layout::Kry &K = L.K[p.k];
+      // V0 = r / beta ; g = beta e1 ; j = 0
+      hipLaunchKernelGGL(k_scale, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(K.vr),
+                         (const double *)(ctx->ptr<double>(K.scal) + 1), ctx->ptr<dz>(K.V), N);
+      hipLaunchKernelGGL(k_ginit, dim3(1), dim3(256), 0, ctx->stream, ctx->ptr<dz>(K.g), restart + 1,
+                         (const double *)(ctx->ptr<double>(K.scal) + 1));
+      hipLaunchKernelGGL(k_jset, dim3(1), dim3(1), 0, ctx->stream, ctx->ptr<int>(K.jd), 0);
+      LAUNCHCK();
+      p.jdone = 0;
+      p.est_ok = p.stop = false;
+    }
+    if (!cyc) break;
     // Arnoldi steps in launches of up to G steps; the residual estimates of a
     // launch are read back together.  Steps past the converged one are
     // harmless: the update below uses only the first jdone columns.
-    for (int j = 0; j < restart && !stop;) {
-      const int steps = (ctx->graph_steps > 0 && j + G <= restart) ? G : 1;
-      if (int rc = issue_steps(ctx, steps)) return rc;
-      HIPCK(hipMemcpyAsync(ctx->pinned, rhist + j, 8 * steps, hipMemcpyDeviceToHost, ctx->stream));
-      HIPCK(hipStreamSynchronize(ctx->stream));
-      for (int q = 0; q < steps; ++q) {
-        const double res = ctx->pinned[q];
-        ++iters;
-        jdone = j + q + 1;
-        ctx->hist.push_back(res / bnorm);
-        if (res / bnorm <= tol) {
-          est_ok = true;
-          stop = true;
-          break;
+    for (int j = 0; j < restart;) {
+      int run = 0, mask = 0;
+      for (int i = 0; i < np; ++i)
+        if ((cyc >> i & 1) && !P[i].stop) {
+          run |= 1 << i;
+          mask |= 1 << P[i].k;
         }
-        if (iters >= max_iter) {
-          stop = true;
-          break;
+      if (!run) break;
+      const int steps = (ctx->graph_steps > 0 && j + G <= restart) ? G : 1;
+      if (int rc = issue_steps(ctx, mask, steps)) return rc;
+      for (int i = 0; i < np; ++i)
+        if (run >> i & 1)
+          HIPCK(hipMemcpyAsync(ctx->pinned + 64 * i, ctx->ptr<double>(L.K[P[i].k].rhist) + j, 8 * steps,
+                               hipMemcpyDeviceToHost, ctx->stream));
+      HIPCK(hipStreamSynchronize(ctx->stream));
+      for (int i = 0; i < np; ++i) {
+        if (!(run >> i & 1)) continue;
+        Gmres &p = P[i];
+        for (int q = 0; q < steps; ++q) {
+          const double res = ctx->pinned[64 * i + q];
+          ++p.iters;
+          p.jdone = j + q + 1;
+          ctx->hist[p.k].push_back(res / p.bnorm);
+          if (res / p.bnorm <= tol) {
+            p.est_ok = p.stop = true;
+            break;
+          }
+          if (p.iters >= max_iter) {
+            p.stop = true;
+            break;
+          }
         }
       }
       j += steps;
     }
-    // x += M^{-1} V y
-    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, ctx->stream, (const dz *)H, ldh, jdone, (const dz *)g, y);
-    hipLaunchKernelGGL(k_combine, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)V, L.ldv, jdone,
-                       (const dz *)y, w, N);
-    LAUNCHCK();
-    if (int rc = apply_minv(ctx, w, u, tmp, z)) return rc;
-    hipLaunchKernelGGL(k_axpy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, (const dz *)u, N);
-    // true residual r = b - Z x
-    if (int rc = matvec(ctx, x, b, r)) return rc;
-    if (int rc = norm_to(ctx, r, N, scal + 1)) return rc;
-    if (int rc = read_scalar(ctx, scal + 1, &beta)) return rc;
-    true_rel = beta / bnorm;
-    if (true_rel <= tol || (est_ok && true_rel <= 10 * tol)) {
-      converged = true;
-      break;
+    // x += M^{-1} V y, then the true residual r = b - Z x
+    int nc = 0;
+    const dz *wv[2];
+    dz *uv[2], *tv[2], *zv[2];
+    MvVecs rv{};
+    for (int i = 0; i < np; ++i) {
+      if (!(cyc >> i & 1)) continue;
+      const Layout::Kry &K = L.K[P[i].k];
+      dz *w = ctx->ptr<dz>(K.vw);
+      hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, ctx->stream, (const dz *)ctx->ptr<dz>(K.H), ldh,
+                         P[i].jdone, (const dz *)ctx->ptr<dz>(K.g), ctx->ptr<dz>(K.y));
+      hipLaunchKernelGGL(k_combine, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(K.V),
+                         L.ldv, P[i].jdone, (const dz *)ctx->ptr<dz>(K.y), w, N);
+      LAUNCHCK();
+      wv[nc] = w;
+      uv[nc] = ctx->ptr<dz>(K.vu);
+      tv[nc] = ctx->ptr<dz>(K.vt);
+      zv[nc] = ctx->ptr<dz>(K.vz);
+      rv.x[nc] = ctx->ptr<dz>(K.vx);
+      rv.b[nc] = ctx->ptr<dz>(K.vb);
+      rv.y[nc] = ctx->ptr<dz>(K.vr);
+      ++nc;
     }
-    if (iters >= max_iter) break;
-    ++restarts;
+    if (int rc = apply_minv_n(ctx, nc, wv, uv, tv, zv)) return rc;
+    for (int q = 0; q < nc; ++q)
+      hipLaunchKernelGGL(k_axpy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, const_cast<dz *>(rv.x[q]),
+                         (const dz *)uv[q], N);
+    if (nc == 2) {
+      if (int rc = matvec2(ctx, rv)) return rc;
+    } else if (int rc = matvec(ctx, rv.x[0], rv.b[0], rv.y[0])) {
+      return rc;
+    }
+    for (int i = 0; i < np; ++i) {
+      if (!(cyc >> i & 1)) continue;
+      Gmres &p = P[i];
+      double *scal = ctx->ptr<double>(L.K[p.k].scal);
+      if (int rc = norm_to(ctx, p.k, ctx->ptr<dz>(L.K[p.k].vr), N, scal + 1)) return rc;
+      if (int rc = read_scalar(ctx, scal + 1, &p.beta)) return rc;
+      p.true_rel = p.beta / p.bnorm;
+      if (p.true_rel <= tol || (p.est_ok && p.true_rel <= 10 * tol)) {
+        p.converged = p.done = true;
+      } else if (p.iters >= max_iter) {
+        p.done = true;
+      } else {
+        ++p.restarts;
+      }
+    }
   }
+  return VIE_OK;
+}
+
+int solve_args(vie_ctx *ctx, double tol, int max_iter, int restart) {
+  if (!(tol > 0) || max_iter < 1) return fail(ctx, VIE_EINVAL, "bad tol / max_iter");
+  if (restart < 1 || restart > ctx->L.restart)
+    return fail(ctx, VIE_EINVAL, "restart %d exceeds the bound workspace (%d)", restart, ctx->L.restart);
+  return VIE_OK;
+}
+
+// Run np GMRES processes and fill info[np]; t_solve_ms is the wall time of
+// the whole run (shared by a pair).
+int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int restart, vie_solve_info *info) {
+  HIPCK(hipSetDevice(ctx->device));
+  ctx->sol_k[0] = ctx->sol_k[1] = -1;
+  HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
+  if (int rc = gmres(ctx, np, P, tol, max_iter, restart)) return rc;
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipEventSynchronize(ctx->ev1));
   float ms = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  if (info) {
-    info->iters = iters;
-    info->restarts = restarts;
-    info->refine_steps = restarts + 1;
-    info->true_rel_residual = true_rel;
-    info->t_fill_ms = ctx->t_fill;
-    info->t_factor_ms = ctx->t_factor;
-    info->t_solve_ms = ms;
+  for (int i = 0; i < np; ++i) {
+    ctx->sol_k[P[i].pol] = P[i].k;
+    if (info) {
+      info[i].iters = P[i].iters;
+      info[i].restarts = P[i].restarts;
+      info[i].refine_steps = P[i].restarts + 1;
+      info[i].true_rel_residual = P[i].true_rel;
+      info[i].t_fill_ms = ctx->t_fill;
+      info[i].t_factor_ms = ctx->t_factor;
+      info[i].t_solve_ms = ms;
+      info[i].converged = P[i].converged ? 1 : 0;
+    }
   }
+  ctx->last_pol = P[np - 1].pol;
   ctx->state = S_SOLVED;
-  if (!converged) return fail(ctx, VIE_ENOCONV, "GMRES: %d iterations, relative residual %.3e", iters, true_rel);
+  for (int i = 0; i < np; ++i)
+    if (!P[i].converged)
+      return fail(ctx, VIE_ENOCONV, "GMRES (%s): %d iterations, relative residual %.3e",
+                  P[i].pol == VIE_TE ? "TE" : "TM", P[i].iters, P[i].true_rel);
   return VIE_OK;
+}
+
+}  // namespace
+
+int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
+  if (int r = check(ctx, S_FACTORED, "vie_solve")) return r;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
+  if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
+  Gmres P[1];
+  P[0].k = 0;
+  P[0].pol = pol;
+  return run_solve(ctx, 1, P, tol, max_iter, restart, info);
+}
+
+int vie_solve_pair(vie_ctx *ctx, double tol, int max_iter, int restart, vie_solve_info *info) {
+  if (int r = check(ctx, S_FACTORED, "vie_solve_pair")) return r;
+  if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
+  Gmres P[2];
+  P[0].k = 0;
+  P[0].pol = VIE_TE;
+  P[1].k = 1;
+  P[1].pol = VIE_TM;
+  return run_solve(ctx, 2, P, tol, max_iter, restart, info);
 }
 
 // ---------------------------------------------------------------- outputs
 int vie_absorption(vie_ctx *ctx, double *absorptance, double *R, double *T) {
   if (int r = check(ctx, S_SOLVED, "vie_absorption")) return r;
+  return vie_absorption_pol(ctx, ctx->last_pol, absorptance, R, T);
+}
+
+int vie_absorption_pol(vie_ctx *ctx, int pol, double *absorptance, double *R, double *T) {
+  if (int r = check(ctx, S_SOLVED, "vie_absorption_pol")) return r;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
+  if (ctx->sol_k[pol] < 0) return fail(ctx, VIE_ESTATE, "the last solve did not cover this polarisation");
   if (!absorptance) return fail(ctx, VIE_EINVAL, "null output");
   HIPCK(hipSetDevice(ctx->device));
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
+  const dz *xsol = ctx->ptr<dz>(L.K[ctx->sol_k[pol]].vx);
   const unsigned nb = nblk(t.nt, 256);
   double *part = ctx->ptr<double>(L.apart);
   double *out = ctx->ptr<double>(L.idx);
   hipLaunchKernelGGL(k_absorb, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, t.ndom, ctx->ptr<TetGeom>(L.tg),
                      ctx->ptr<TetFace>(L.t2f), ctx->ptr<int32_t>(L.dom), ctx->ptr<QuadRules>(L.quad),
-                     (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), (const dz *)ctx->ptr<dz>(L.vx),
+                     (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), xsol,
                      part);
   hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, ctx->stream, (const double *)part, (int)nb, t.ndom, out);
   LAUNCHCK();
@@ -1305,7 +1507,7 @@ int vie_absorption(vie_ctx *ctx, double *absorptance, double *R, double *T) {
     HIPCK(hipMemcpyAsync(ctx->ptr<double>(L.kv), kvh.data(), 8 * kvh.size(), hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, ctx->ptr<TetGeom>(L.tg),
                        ctx->ptr<TetFace>(L.t2f), ctx->ptr<QuadRules>(L.quad), (const dz *)ctx->ptr<dz>(L.gsrc),
-                       (const dz *)ctx->ptr<dz>(L.kappa), (const dz *)ctx->ptr<dz>(L.vx), nk,
+                       (const dz *)ctx->ptr<dz>(L.kappa), xsol, nk,
                        (const double *)ctx->ptr<double>(L.kv), part);
     hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(6 * nk, 256)), dim3(256), 0, ctx->stream, (const double *)part, (int)nb,
                        6 * nk, out);
@@ -1315,7 +1517,7 @@ int vie_absorption(vie_ctx *ctx, double *absorptance, double *R, double *T) {
     HIPCK(hipStreamSynchronize(ctx->stream));
     const double st = std::sin(ctx->theta), ct = std::cos(ctx->theta), sp = std::sin(ctx->phi), cp = std::cos(ctx->phi);
     double e_inc[3];
-    if (ctx->last_pol == VIE_TE) {
+    if (pol == VIE_TE) {
       e_inc[0] = -sp;
       e_inc[1] = cp;
       e_inc[2] = 0;
@@ -1367,15 +1569,15 @@ int vie_read_Z(const vie_ctx *cctx, const int64_t *rows, const int64_t *cols, in
   const int64_t N = ctx->topo.N;
   HIPCK(hipSetDevice(ctx->device));
   // rows, cols and values staged through the Krylov-basis region (clobbers it)
-  const int64_t cap = (int64_t)((L.V.bytes - 512) / 32);
+  const int64_t cap = (int64_t)((L.K[0].V.bytes - 512) / 32);
   if (cap < 1) return fail(ctx, VIE_ENOMEM, "no staging space");
-  int64_t *ri = ctx->ptr<int64_t>(L.V);
+  int64_t *ri = ctx->ptr<int64_t>(L.K[0].V);
   for (int64_t s = 0; s < k; s += cap) {
     const int64_t n = std::min(cap, k - s);
     for (int64_t i = 0; i < n; ++i)
       if (rows[s + i] < 0 || rows[s + i] >= N || cols[s + i] < 0 || cols[s + i] >= N)
         return fail(ctx, VIE_EINVAL, "index out of range");
-    dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(16 * (size_t)n));
+    dz *o = reinterpret_cast<dz *>(ctx->ws + L.K[0].V.off + align256(16 * (size_t)n));
     HIPCK(hipMemcpyAsync(ri, rows + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
     HIPCK(hipMemcpyAsync(ri + n, cols + s, 8 * n, hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, ctx->stream, zout(ctx),
@@ -1397,21 +1599,33 @@ static int read_vec(const vie_ctx *cctx, const Region &r, vie_c128 *dst) {
   return VIE_OK;
 }
 
-int vie_read_rhs(const vie_ctx *ctx, vie_c128 *b) { return ctx ? read_vec(ctx, ctx->L.vb, b) : VIE_EINVAL; }
-int vie_read_solution(const vie_ctx *ctx, vie_c128 *x) { return ctx ? read_vec(ctx, ctx->L.vx, x) : VIE_EINVAL; }
+static int read_pol(const vie_ctx *cctx, int pol, bool rhs, vie_c128 *dst) {
+  vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
+  if (!ctx) return VIE_EINVAL;
+  if (int rc = check(ctx, S_SOLVED, "read-back")) return rc;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
+  const int k = ctx->sol_k[pol];
+  if (k < 0) return fail(ctx, VIE_ESTATE, "the last solve did not cover this polarisation");
+  return read_vec(ctx, rhs ? ctx->L.K[k].vb : ctx->L.K[k].vx, dst);
+}
+int vie_read_rhs(const vie_ctx *ctx, vie_c128 *b) { return ctx ? read_pol(ctx, ctx->last_pol, true, b) : VIE_EINVAL; }
+int vie_read_solution(const vie_ctx *ctx, vie_c128 *x) {
+  return ctx ? read_pol(ctx, ctx->last_pol, false, x) : VIE_EINVAL;
+}
+int vie_read_solution_pol(const vie_ctx *ctx, int pol, vie_c128 *x) { return read_pol(ctx, pol, false, x); }
 
 int vie_pgf_eval(vie_ctx *ctx, const double *delta, int64_t n, vie_c128 *out) {
   if (int r = check(ctx, S_FILLED, "vie_pgf_eval")) return r;
   const Layout &L = ctx->L;
   if (!delta || !out || n < 0) return fail(ctx, VIE_EINVAL, "bad arguments");
   // points and values staged in the Krylov-basis region (clobbers it), in chunks
-  const int64_t cap = (int64_t)((L.V.bytes - 512) / 40);
+  const int64_t cap = (int64_t)((L.K[0].V.bytes - 512) / 40);
   if (cap < 1) return fail(ctx, VIE_ENOMEM, "no staging space");
   HIPCK(hipSetDevice(ctx->device));
-  double *d = ctx->ptr<double>(L.V);
+  double *d = ctx->ptr<double>(L.K[0].V);
   for (int64_t s = 0; s < n; s += cap) {
     const int64_t m = std::min(cap, n - s);
-    dz *o = reinterpret_cast<dz *>(ctx->ws + L.V.off + align256(24 * (size_t)m));
+    dz *o = reinterpret_cast<dz *>(ctx->ws + L.K[0].V.off + align256(24 * (size_t)m));
     HIPCK(hipMemcpyAsync(d, delta + 3 * s, 24 * m, hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(k_pgf_probe, dim3(nblk(m, 256)), dim3(256), 8 * (size_t)ctx->packlen, ctx->stream,
                        (const double *)ctx->ptr<double>(L.pack), ctx->packlen, (const double *)d, m, o);
@@ -1435,7 +1649,7 @@ int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec) {
   HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  dz *x = ctx->ptr<dz>(L.vz), *y = ctx->ptr<dz>(L.vw);
+  dz *x = ctx->ptr<dz>(L.K[0].vz), *y = ctx->ptr<dz>(L.K[0].vw);
   hipLaunchKernelGGL(k_fill_const, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N, 1.0, 0.5);
   LAUNCHCK();
   HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
@@ -1455,9 +1669,9 @@ int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z) {
   HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  dz *in = ctx->ptr<dz>(L.vw), *out = ctx->ptr<dz>(L.vz);
+  dz *in = ctx->ptr<dz>(L.K[0].vw), *out = ctx->ptr<dz>(L.K[0].vz);
   HIPCK(hipMemcpyAsync(in, v, 16 * N, hipMemcpyHostToDevice, ctx->stream));
-  if (int rc = apply_minv(ctx, in, out, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vr))) return rc;
+  if (int rc = apply_minv(ctx, in, out, ctx->ptr<dz>(L.K[0].vu), ctx->ptr<dz>(L.K[0].vr))) return rc;
   HIPCK(hipMemcpyAsync(z, out, 16 * N, hipMemcpyDeviceToHost, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
@@ -1512,7 +1726,7 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
-  dz *x = ctx->ptr<dz>(L.vz), *y = ctx->ptr<dz>(L.vw);
+  dz *x = ctx->ptr<dz>(L.K[0].vz), *y = ctx->ptr<dz>(L.K[0].vw);
   hipLaunchKernelGGL(k_fill_const, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, x, N, 1.0, 0.5);
   LAUNCHCK();
   vie_tuning t{};
@@ -1544,8 +1758,8 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   pick = ctx->trsv_rw;
   for (int i = 0; i < 4; ++i) {
     ctx->trsv_rw = tr_opts[i];
-    if (int rc = time_it([&]() { return apply_minv(ctx, x, ctx->ptr<dz>(L.vu), ctx->ptr<dz>(L.vt),
-                                                   ctx->ptr<dz>(L.vr)); },
+    if (int rc = time_it([&]() { return apply_minv(ctx, x, ctx->ptr<dz>(L.K[0].vu), ctx->ptr<dz>(L.K[0].vt),
+                                                   ctx->ptr<dz>(L.K[0].vr)); },
                          &t.apply_ms[i]))
       return rc;
     if (t.apply_ms[i] < best) {
@@ -1563,8 +1777,11 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
 
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap) {
   if (!ctx || !hist || cap < 0) return VIE_EINVAL;
-  int n = std::min<int>(cap, (int)ctx->hist.size());
-  for (int i = 0; i < n; ++i) hist[i] = ctx->hist[i];
+  const int k = ctx->sol_k[ctx->last_pol];
+  if (k < 0) return 0;
+  const std::vector<double> &h = ctx->hist[k];
+  int n = std::min<int>(cap, (int)h.size());
+  for (int i = 0; i < n; ++i) hist[i] = h[i];
   return n;
 }
 

@@ -23,24 +23,32 @@ __device__ __forceinline__ double wsum(double v) {
 // y = Z x  (or y = b - Z x when b != nullptr).  Z row-major, N x ld.
 // A block of 4 waves owns 4*RPW consecutive rows; x is staged through LDS in
 // chunks shared by the block, Z is streamed once with non-temporal loads.
+// With NV = 2 one pass over Z serves two vectors (the two polarisations of a
+// paired solve); each vector's sums run in the same order as with NV = 1.
 constexpr int kMvChunk = 1024;
 
-template <int RPW>
-__device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld, int64_t N,
-                                            const dz *__restrict__ x, const dz *__restrict__ b, dz *__restrict__ y,
+template <int RPW, int NV>
+__device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld, int64_t N, const MvVecs &v,
                                             dz *xs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
-  double are[RPW], aim[RPW];
-  for (int r = 0; r < RPW; ++r) are[r] = aim[r] = 0.0;
+  double are[NV][RPW], aim[NV][RPW];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) are[q][r] = aim[q][r] = 0.0;
   const double *Zd = reinterpret_cast<const double *>(Z);
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
     __syncthreads();
-    for (int i = tid; i < len; i += 256) xs[i] = x[c0 + i];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      for (int i = tid; i < len; i += 256) xs[q * kMvChunk + i] = v.x[q][c0 + i];
     __syncthreads();
     for (int cc = lane; cc < len; cc += 64) {
-      const dz xv = xs[cc];
+      dz xv[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) xv[q] = xs[q * kMvChunk + cc];
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
         const int64_t row = row0 + r;
@@ -48,20 +56,26 @@ __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld
           const int64_t o = 2 * (row * ld + c0 + cc);
           const double zr = __builtin_nontemporal_load(Zd + o);
           const double zi = __builtin_nontemporal_load(Zd + o + 1);
-          are[r] = fma(zr, xv.re, fma(-zi, xv.im, are[r]));
-          aim[r] = fma(zr, xv.im, fma(zi, xv.re, aim[r]));
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            are[q][r] = fma(zr, xv[q].re, fma(-zi, xv[q].im, are[q][r]));
+            aim[q][r] = fma(zr, xv[q].im, fma(zi, xv[q].re, aim[q][r]));
+          }
         }
       }
     }
   }
-  for (int r = 0; r < RPW; ++r) {
-    const double sr = wsum(are[r]), si = wsum(aim[r]);
-    const int64_t row = row0 + r;
-    if (lane == 0 && row < N) {
-      if (b) y[row] = mk(b[row].re - sr, b[row].im - si);
-      else y[row] = mk(sr, si);
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int r = 0; r < RPW; ++r) {
+      const double sr = wsum(are[q][r]), si = wsum(aim[q][r]);
+      const int64_t row = row0 + r;
+      if (lane == 0 && row < N) {
+        const dz *b = v.b[q];
+        if (b) v.y[q][row] = mk(b[row].re - sr, b[row].im - si);
+        else v.y[q][row] = mk(sr, si);
+      }
     }
-  }
 }
 
 #define VIE_MATVEC(R)                                                                                           \
@@ -69,7 +83,13 @@ __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld
                                                        const dz *__restrict__ x, const dz *__restrict__ b,      \
                                                        dz *__restrict__ y) {                                    \
     __shared__ dz xs[kMvChunk];                                                                                 \
-    matvec_body<R>(Z, ld, N, x, b, y, xs);                                                                      \
+    const MvVecs v{{x, nullptr}, {b, nullptr}, {y, nullptr}};                                                   \
+    matvec_body<R, 1>(Z, ld, N, v, xs);                                                                         \
+  }                                                                                                             \
+  __global__ __launch_bounds__(256) void k_matvec2_r##R(const dz *__restrict__ Z, int64_t ld, int64_t N,        \
+                                                        MvVecs v) {                                             \
+    __shared__ dz xs[2 * kMvChunk];                                                                             \
+    matvec_body<R, 2>(Z, ld, N, v, xs);                                                                         \
   }
 VIE_MATVEC(2)
 VIE_MATVEC(4)
@@ -82,33 +102,44 @@ VIE_MATVEC(8)
 // row, then the wave adds its rows' near entries.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <int RPW>
+template <int RPW, int NV>
 __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int64_t ld, int64_t N,
                                                   const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ cols, const dz *__restrict__ vals,
-                                                  const dz *__restrict__ x, const dz *__restrict__ b,
-                                                  dz *__restrict__ y, dz *xs) {
+                                                  const MvVecs &v, dz *xs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
-  double are[RPW], aim[RPW];
-  for (int r = 0; r < RPW; ++r) are[r] = aim[r] = 0.0;
+  double are[NV][RPW], aim[NV][RPW];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) are[q][r] = aim[q][r] = 0.0;
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
     __syncthreads();
-    for (int i = tid; i < len; i += 256) xs[i] = x[c0 + i];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      for (int i = tid; i < len; i += 256) xs[q * kMvChunk + i] = v.x[q][c0 + i];
     __syncthreads();
     for (int cc = 2 * lane; cc < len; cc += 128) {
-      const dz x0 = xs[cc];
-      const dz x1 = cc + 1 < len ? xs[cc + 1] : mk(0, 0);
+      dz x0[NV], x1[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        x0[q] = xs[q * kMvChunk + cc];
+        x1[q] = cc + 1 < len ? xs[q * kMvChunk + cc + 1] : mk(0, 0);
+      }
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
         const int64_t row = row0 + r;
         if (row < N) {
           const v4f z = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Zs + row * ld + c0 + cc));
-          are[r] = fma((double)z[0], x0.re, fma(-(double)z[1], x0.im, are[r]));
-          aim[r] = fma((double)z[0], x0.im, fma((double)z[1], x0.re, aim[r]));
-          are[r] = fma((double)z[2], x1.re, fma(-(double)z[3], x1.im, are[r]));
-          aim[r] = fma((double)z[2], x1.im, fma((double)z[3], x1.re, aim[r]));
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            are[q][r] = fma((double)z[0], x0[q].re, fma(-(double)z[1], x0[q].im, are[q][r]));
+            aim[q][r] = fma((double)z[0], x0[q].im, fma((double)z[1], x0[q].re, aim[q][r]));
+            are[q][r] = fma((double)z[2], x1[q].re, fma(-(double)z[3], x1[q].im, are[q][r]));
+            aim[q][r] = fma((double)z[2], x1[q].im, fma((double)z[3], x1[q].re, aim[q][r]));
+          }
         }
       }
     }
@@ -118,19 +149,27 @@ __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int
     const int64_t row = row0 + r;
     if (row < N)
       for (int64_t e = rowptr[row] + lane; e < rowptr[row + 1]; e += 64) {
-        const dz v = vals[e], xv = x[cols[e]];
-        are[r] = fma(v.re, xv.re, fma(-v.im, xv.im, are[r]));
-        aim[r] = fma(v.re, xv.im, fma(v.im, xv.re, aim[r]));
+        const dz nv = vals[e];
+        const int c = cols[e];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const dz xv = v.x[q][c];
+          are[q][r] = fma(nv.re, xv.re, fma(-nv.im, xv.im, are[q][r]));
+          aim[q][r] = fma(nv.re, xv.im, fma(nv.im, xv.re, aim[q][r]));
+        }
       }
   }
-  for (int r = 0; r < RPW; ++r) {
-    const double sr = wsum(are[r]), si = wsum(aim[r]);
-    const int64_t row = row0 + r;
-    if (lane == 0 && row < N) {
-      if (b) y[row] = mk(b[row].re - sr, b[row].im - si);
-      else y[row] = mk(sr, si);
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    for (int r = 0; r < RPW; ++r) {
+      const double sr = wsum(are[q][r]), si = wsum(aim[q][r]);
+      const int64_t row = row0 + r;
+      if (lane == 0 && row < N) {
+        const dz *b = v.b[q];
+        if (b) v.y[q][row] = mk(b[row].re - sr, b[row].im - si);
+        else v.y[q][row] = mk(sr, si);
+      }
     }
-  }
 }
 
 #define VIE_MATVEC_MIXED(R)                                                                                     \
@@ -139,7 +178,14 @@ __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int
       const int32_t *__restrict__ cols, const dz *__restrict__ vals, const dz *__restrict__ x,                  \
       const dz *__restrict__ b, dz *__restrict__ y) {                                                           \
     __shared__ dz xs[kMvChunk];                                                                                 \
-    matvec_mixed_body<R>(Zs, ld, N, rowptr, cols, vals, x, b, y, xs);                                           \
+    const MvVecs v{{x, nullptr}, {b, nullptr}, {y, nullptr}};                                                   \
+    matvec_mixed_body<R, 1>(Zs, ld, N, rowptr, cols, vals, v, xs);                                              \
+  }                                                                                                             \
+  __global__ __launch_bounds__(256) void k_matvec2_mixed_r##R(                                                  \
+      const fz *__restrict__ Zs, int64_t ld, int64_t N, const int64_t *__restrict__ rowptr,                     \
+      const int32_t *__restrict__ cols, const dz *__restrict__ vals, MvVecs v) {                                \
+    __shared__ dz xs[2 * kMvChunk];                                                                             \
+    matvec_mixed_body<R, 2>(Zs, ld, N, rowptr, cols, vals, v, xs);                                              \
   }
 VIE_MATVEC_MIXED(2)
 VIE_MATVEC_MIXED(4)

@@ -977,12 +977,13 @@ __device__ __forceinline__ dz row_dot(const C *__restrict__ Fi, int cm, const dz
 }
 
 // RW rows per wave in the update blocks (16 RW rows per thread block); the
-// autotuner picks RW per context.
-template <typename C, int RW>
+// autotuner picks RW per context.  NV right-hand sides (1 or 2) share each
+// read of the factors; vector q's sums run in the same order for any NV.
+template <typename C, int RW, int NV>
 __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
-  __shared__ dz zc[kTrsvNB];
-  __shared__ dz rg[16];
-  __shared__ dz red[kTrsvHS][kTrsvNB];
+  __shared__ dz zc[NV][kTrsvNB];
+  __shared__ dz rg[NV][16];
+  __shared__ dz red[NV][kTrsvHS][kTrsvNB];
   __shared__ int last;
   constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -993,7 +994,9 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
   const int cb0 = D.cb0, cm = D.cm, nb0 = D.nb0, nm = D.nm;
   const int64_t ld = D.ld;
   const C *__restrict__ F = (const C *)D.F;
-  if (tid < kTrsvNB) zc[tid] = tid < cm ? D.sol[cb0 + tid] : mk(0, 0);
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+    if (tid < kTrsvNB) zc[q][tid] = tid < cm ? D.sol[q][cb0 + tid] : mk(0, 0);
   if (blk < kTrsvGroups) {
     const int g = blk;
     // independent loads first: the row of group g this wave updates, its rhs,
@@ -1001,9 +1004,12 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     const int r = 16 * g + wave;
     const int i = nb0 + r;
     dz f[kTrsvCol];
-    dz rv = mk(0, 0);
+    dz rv[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) rv[q] = mk(0, 0);
     if (r < nm) {
-      rv = D.rhs[i];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) rv[q] = D.rhs[q][i];
 #pragma unroll
       for (int c = 0; c < kTrsvCol; ++c)
         f[c] = lane + 64 * c < cm ? to_dz(F[(int64_t)i * ld + cb0 + lane + 64 * c]) : mk(0, 0);
@@ -1015,27 +1021,32 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     for (int l = 0; l < kTrsvCPH; ++l) dt[l] = to_dz(col[(int64_t)l * kTrsvNB]);
     __syncthreads();
     // (a) for the 16 rows of group g, one row per wave
-    {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
       dz s = mk(0, 0);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[lane + 64 * c];
+      for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[q][lane + 64 * c];
       s = wave_sum(s);
-      if (lane == 0) rg[wave] = r < nm ? rv - s : mk(0, 0);
+      if (lane == 0) rg[q][wave] = r < nm ? rv[q] - s : mk(0, 0);
     }
     __syncthreads();
     // (b) partial product with columns 16 g .. 16 g + 15 of inv(T_nn)
-    {
-      dz acc = dt[0] * rg[kTrsvCPH * h];
 #pragma unroll
-      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + dt[l] * rg[kTrsvCPH * h + l];
-      red[h][oi] = acc;
+    for (int q = 0; q < NV; ++q) {
+      dz acc = dt[0] * rg[q][kTrsvCPH * h];
+#pragma unroll
+      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + dt[l] * rg[q][kTrsvCPH * h + l];
+      red[q][h][oi] = acc;
     }
     __syncthreads();
     if (tid < kTrsvNB) {
-      dz z = red[0][tid];
 #pragma unroll
-      for (int q = 1; q < kTrsvHS; ++q) z = z + red[q][tid];
-      D.part[g * kTrsvNB + tid] = z;
+      for (int q = 0; q < NV; ++q) {
+        dz z = red[q][0][tid];
+#pragma unroll
+        for (int p = 1; p < kTrsvHS; ++p) z = z + red[q][p][tid];
+        D.part[q * kTrsvPart + g * kTrsvNB + tid] = z;
+      }
       __threadfence();
     }
     __syncthreads();
@@ -1048,13 +1059,16 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     if (last) {
       __threadfence();
       if (tid < nm) {
-        dz p[kTrsvGroups];
 #pragma unroll
-        for (int q = 0; q < kTrsvGroups; ++q) p[q] = D.part[q * kTrsvNB + tid];
-        dz z = mk(0, 0);
+        for (int q = 0; q < NV; ++q) {
+          dz p[kTrsvGroups];
 #pragma unroll
-        for (int q = 0; q < kTrsvGroups; ++q) z = z + p[q];
-        D.sol[nb0 + tid] = z;
+          for (int k = 0; k < kTrsvGroups; ++k) p[k] = D.part[q * kTrsvPart + k * kTrsvNB + tid];
+          dz z = mk(0, 0);
+#pragma unroll
+          for (int k = 0; k < kTrsvGroups; ++k) z = z + p[k];
+          D.sol[q][nb0 + tid] = z;
+        }
       }
       if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1072,31 +1086,37 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
   const int i0 = rlo + RW * wave;
   dz f[RW][kTrsvCol];
 #pragma unroll
-  for (int q = 0; q < RW; ++q)
+  for (int p = 0; p < RW; ++p)
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c)
-      f[q][c] = (i0 + q < rhi && lane + 64 * c < cm) ? to_dz(F[(int64_t)(i0 + q) * ld + cb0 + lane + 64 * c])
+      f[p][c] = (i0 + p < rhi && lane + 64 * c < cm) ? to_dz(F[(int64_t)(i0 + p) * ld + cb0 + lane + 64 * c])
                                                       : mk(0, 0);
   __syncthreads();
-  dz s[RW];
 #pragma unroll
-  for (int q = 0; q < RW; ++q) {
-    s[q] = mk(0, 0);
+  for (int q = 0; q < NV; ++q) {
+    dz s[RW];
 #pragma unroll
-    for (int c = 0; c < kTrsvCol; ++c) s[q] = s[q] + f[q][c] * zc[lane + 64 * c];
+    for (int p = 0; p < RW; ++p) {
+      s[p] = mk(0, 0);
+#pragma unroll
+      for (int c = 0; c < kTrsvCol; ++c) s[p] = s[p] + f[p][c] * zc[q][lane + 64 * c];
+    }
+#pragma unroll
+    for (int p = 0; p < RW; ++p) s[p] = wave_sum(s[p]);
+    dz v = s[0];
+#pragma unroll
+    for (int p = 1; p < RW; ++p)
+      if (lane == p) v = s[p];
+    if (lane < RW && i0 + lane < rhi) D.rhs[q][i0 + lane] = D.rhs[q][i0 + lane] - v;
   }
-#pragma unroll
-  for (int q = 0; q < RW; ++q) s[q] = wave_sum(s[q]);
-  dz v = s[0];
-#pragma unroll
-  for (int q = 1; q < RW; ++q)
-    if (lane == q) v = s[q];
-  if (lane < RW && i0 + lane < rhi) D.rhs[i0 + lane] = D.rhs[i0 + lane] - v;
 }
 
 #define VIE_TRSV_STEP(T, C, R)                                                                  \
   __global__ __launch_bounds__(1024) void k_trsv_step_##T##_r##R(TrsvStep st) {               \
-    trsv_step_body<C, R>(st, blockIdx.x);                                                     \
+    trsv_step_body<C, R, 1>(st, blockIdx.x);                                                  \
+  }                                                                                           \
+  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_r##R(TrsvStep st) {              \
+    trsv_step_body<C, R, 2>(st, blockIdx.x);                                                  \
   }
 VIE_TRSV_STEP(z, dz, 1)
 VIE_TRSV_STEP(z, dz, 2)
@@ -1120,7 +1140,7 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
     const int total = st.total_blocks;
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
       __syncthreads();   // the previous item's shared memory is free
-      trsv_step_body<C, RW>(st, vb);
+      trsv_step_body<C, RW, 1>(st, vb);
     }
     grid.sync();
   }

@@ -100,12 +100,13 @@ __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, 
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
 // domains by one diagonal block each (k_lu.hip).
 constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
+constexpr int kTrsvPart = kTrsvGroupsH * kTrsvNB;   // partial products of one vector
 constexpr int kTrsvMaxDom = 8;
 struct TrsvDom {
   const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
   const void *DT;     // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB, same type)
-  dz *rhs, *sol;      // right-hand side (updated in place) and solution, domain-local
-  dz *part;           // kTrsvGroupsH x kTrsvNB partial products
+  dz *rhs[2], *sol[2];  // right-hand sides (updated in place) and solutions, domain-local, per vector
+  dz *part;           // kTrsvGroupsH x kTrsvNB partial products per vector (vector q at q * kTrsvPart)
   int *counter;       // zero between launches
   int64_t ld;
   int n, cb0, cm, nb0, nm, first_block;
@@ -117,9 +118,12 @@ struct TrsvStep {
 };
 // variants by factor type (_z FP64, _c FP32) and rows per wave of the update
 // blocks (1, 2, 4, 8 -> 16 .. 128 rows per block); vectors and arithmetic FP64.
+// k_trsv_step2_*: two right-hand sides per pass over the factors (each
+// vector's sums in the order of the one-vector kernel).
 // k_trsv_coop_*: every step of a plan in one cooperative launch.
 #define VIE_DECL_TRSV(T, R)                                  \
   __global__ void k_trsv_step_##T##_r##R(TrsvStep st);       \
+  __global__ void k_trsv_step2_##T##_r##R(TrsvStep st);      \
   __global__ void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps);
 VIE_DECL_TRSV(z, 1)
 VIE_DECL_TRSV(z, 2)
@@ -132,11 +136,22 @@ VIE_DECL_TRSV(c, 8)
 #undef VIE_DECL_TRSV
 
 // Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block
-// of 4 waves owns 4 * RPW rows; the autotuner picks one per context.
+// of 4 waves owns 4 * RPW rows; the autotuner picks one per context.  The
+// k_matvec2_* variants take two vectors through one pass over Z: y_q = Z x_q
+// (or b_q - Z x_q when b_q is given), each sum in the order of the one-vector
+// kernel.
+struct MvVecs {
+  const dz *x[2];
+  const dz *b[2];
+  dz *y[2];
+};
 #define VIE_DECL_MATVEC(R)                                                                                      \
   __global__ void k_matvec_r##R(const dz *Z, int64_t ld, int64_t N, const dz *x, const dz *b, dz *y);           \
   __global__ void k_matvec_mixed_r##R(const fz *Zs, int64_t ld, int64_t N, const int64_t *rowptr,               \
-                                      const int32_t *cols, const dz *vals, const dz *x, const dz *b, dz *y);
+                                      const int32_t *cols, const dz *vals, const dz *x, const dz *b, dz *y);    \
+  __global__ void k_matvec2_r##R(const dz *Z, int64_t ld, int64_t N, MvVecs v);                                \
+  __global__ void k_matvec2_mixed_r##R(const fz *Zs, int64_t ld, int64_t N, const int64_t *rowptr,              \
+                                       const int32_t *cols, const dz *vals, MvVecs v);
 VIE_DECL_MATVEC(2)
 VIE_DECL_MATVEC(4)
 VIE_DECL_MATVEC(8)

@@ -36,7 +36,7 @@ class c128(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("refine_steps", C.c_int),
                 ("true_rel_residual", C.c_double), ("t_fill_ms", C.c_double),
-                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double)]
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("converged", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,12 +79,15 @@ _SIGS = {
     "vie_fill": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_int]),
     "vie_precond_factor": (C.c_int, [C.c_void_p]),
     "vie_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(SolveInfo)]),
+    "vie_solve_pair": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(SolveInfo)]),
     "vie_absorption": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_absorption_pol": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_last_error": (C.c_char_p, [C.c_void_p]),
     "vie_export_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_read_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "vie_read_rhs": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vie_read_solution": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "vie_read_solution_pol": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "vie_pgf_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "vie_residual_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
@@ -215,14 +218,28 @@ class Solver:
                                 C.byref(info))
         self._ck(rc, allow=(VIE_ENOCONV,) if allow_noconv else ())
         d = info.as_dict()
-        d["converged"] = rc == VIE_OK
+        d["converged"] = bool(d["converged"])
         return d
 
-    def absorption(self, want_rt=True):
+    def solve_pair(self, tol=1e-12, max_iter=2000, restart=None, allow_noconv=False):
+        """TE and TM in lockstep (shared passes over Z and the factors); returns [TE info, TM info]."""
+        info = (SolveInfo * 2)()
+        rc = self.lib.vie_solve_pair(self.h, float(tol), int(max_iter), int(restart or self.restart), info)
+        self._ck(rc, allow=(VIE_ENOCONV,) if allow_noconv else ())
+        out = [info[0].as_dict(), info[1].as_dict()]
+        for d in out:
+            d["converged"] = bool(d["converged"])
+        return out
+
+    def absorption(self, want_rt=True, pol=None):
+        """Absorptance per domain (and R, T) of the last solution, or of polarisation `pol`."""
         A = np.zeros(self.ndom)
         R = C.c_double(); T = C.c_double()
-        self._ck(self.lib.vie_absorption(self.h, _p(A), C.byref(R) if want_rt else None,
-                                         C.byref(T) if want_rt else None))
+        rp, tp = (C.byref(R), C.byref(T)) if want_rt else (None, None)
+        if pol is None:
+            self._ck(self.lib.vie_absorption(self.h, _p(A), rp, tp))
+        else:
+            self._ck(self.lib.vie_absorption_pol(self.h, int(pol), _p(A), rp, tp))
         return (A, R.value, T.value) if want_rt else A
 
     # -------------------------------------------------------------- diagnostics
@@ -237,9 +254,12 @@ class Solver:
         self._ck(self.lib.vie_read_rhs(self.h, _p(out)))
         return out
 
-    def read_solution(self):
+    def read_solution(self, pol=None):
         out = np.zeros(self.num_unknowns(), np.complex128)
-        self._ck(self.lib.vie_read_solution(self.h, _p(out)))
+        if pol is None:
+            self._ck(self.lib.vie_read_solution(self.h, _p(out)))
+        else:
+            self._ck(self.lib.vie_read_solution_pol(self.h, int(pol), _p(out)))
         return out
 
     def pgf(self, delta):
