@@ -35,7 +35,7 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart, tcount,
+  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
       plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
@@ -195,15 +195,14 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
-  put(L.tpart, 16 * 2 * (size_t)kTrsvPart * std::max(1, t.ndom));   // two right-hand sides per domain
+  put(L.tpart, 16 * 4 * (size_t)kTrsvPart * std::max(1, t.ndom));   // two buffers of two right-hand sides per domain
   {
     int maxnbk = 1;
     for (int d = 0; d < t.ndom; ++d) maxnbk = std::max<int>(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
     const int chunks = (t.ndom + kTrsvMaxDom - 1) / kTrsvMaxDom;
-    L.plan_steps = 2 * maxnbk * std::max(1, chunks);
+    L.plan_steps = 2 * (maxnbk + 1) * std::max(1, chunks);   // two sweeps of maxnbk steps and a closing step
     put(L.plans, kMaxPlans * sizeof(TrsvStep) * (size_t)L.plan_steps);
   }
-  put(L.tcount, 4 * (size_t)std::max(1, t.ndom));
   put(L.ipiv, 4 * std::max<int64_t>(1, npiv));
   put(L.perm, 4 * std::max<int64_t>(1, npiv));
   int64_t npart = 0;
@@ -566,8 +565,7 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
     rc |= up(L.ncol, ctx->ncol.data(), 4 * ctx->ncol.size());
   }
   if (rc) return rc;
-  // the triangular-solve and panel counters start (and always end) at zero
-  HIPCK(hipMemsetAsync(ctx->ws + L.tcount.off, 0, L.tcount.bytes, ctx->stream));
+  // the panel and tournament counters start (and always end) at zero
   HIPCK(hipMemsetAsync(ctx->ws + L.lucnt.off, 0, L.lucnt.bytes, ctx->stream));
   HIPCK(hipMemsetAsync(ctx->ws + L.ttcnt.off, 0, L.ttcnt.bytes, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
@@ -921,15 +919,18 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
   const Layout &L = ctx->L;
   int maxnbk = 0;
   for (int d = 0; d < t.ndom; ++d) maxnbk = std::max(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
+  // partial products: per domain two buffers (steps alternate) of two vectors
   dz *part = ctx->ptr<dz>(L.tpart);
-  int *cnt = ctx->ptr<int>(L.tcount);
+  auto buf = [&](int d, int k) { return part + ((int64_t)d * 4 + 2 * (k & 1)) * kTrsvPart; };
   std::vector<TrsvStep> plan;
   // L sweep: rhs s1 (updated in place), solution s2; U sweep: rhs s2, solution out.
   for (int lower = 1; lower >= 0; --lower) {
-    for (int k = 0; k < maxnbk; ++k) {
+    // steps 0 .. maxnbk-1 advance the solves; step maxnbk stores each
+    // domain's last diagonal block
+    for (int k = 0; k <= maxnbk; ++k) {
       TrsvStep st{};
       st.lower = lower;
-      auto flush = [&]() {
+      auto push = [&]() {
         if (st.ndom == 0) return;
         plan.push_back(st);
         st = TrsvStep{};
@@ -938,46 +939,49 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
       for (int d = 0; d < t.ndom; ++d) {
         const int n = (int)(t.dend[d] - t.dstart[d]);
         const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
-        if (k >= nbk) continue;
+        if (nbk == 0 || (k >= nbk && k < maxnbk)) continue;
         const int64_t off = t.dstart[d];
         const int64_t dl = L.doff[d];
         TrsvDom &D = st.d[st.ndom];
         D.F = factor_ptr(ctx, L.F, L.foff[d]);
         D.ld = L.fld[d];
         D.n = n;
-        D.part = part + (int64_t)d * 2 * kTrsvPart;
-        D.counter = cnt + d;
         D.first_block = st.total_blocks;
-        int rest;
-        if (lower) {
-          const int bk = k;
-          D.nb0 = bk * kTrsvNB;
-          D.nm = std::min(kTrsvNB, n - D.nb0);
-          D.cb0 = bk > 0 ? D.nb0 - kTrsvNB : 0;
-          D.cm = bk > 0 ? kTrsvNB : 0;
-          D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)bk * kTrsvNB * kTrsvNB);
-          for (int q = 0; q < nv; ++q) {
-            D.rhs[q] = s1[q] + off;
-            D.sol[q] = s2[q] + off;
-          }
-          rest = D.cm > 0 ? n - D.nb0 - D.nm : 0;
-        } else {
-          const int bk = nbk - 1 - k;
-          D.nb0 = bk * kTrsvNB;
-          D.nm = std::min(kTrsvNB, n - D.nb0);
-          D.cb0 = k > 0 ? D.nb0 + kTrsvNB : 0;
-          D.cm = k > 0 ? std::min(kTrsvNB, n - D.cb0) : 0;
-          D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(nbk + bk) * kTrsvNB * kTrsvNB);
-          for (int q = 0; q < nv; ++q) {
-            D.rhs[q] = s2[q] + off;
-            D.sol[q] = out[q] + off;
-          }
-          rest = D.cm > 0 ? D.nb0 : 0;
+        for (int q = 0; q < nv; ++q) {
+          D.rhs[q] = (lower ? s1[q] : s2[q]) + off;
+          D.sol[q] = (lower ? s2[q] : out[q]) + off;
         }
+        if (k == maxnbk) {
+          // the partials of the domain's last step: one thread block stores them
+          const int bk = lower ? nbk - 1 : 0;
+          D.pb0 = bk * kTrsvNB;
+          D.pm = std::min(kTrsvNB, n - D.pb0);
+          D.cb0 = D.cm = D.nb0 = D.nm = 0;
+          D.part_in = buf(d, nbk - 1);
+          D.part_out = nullptr;
+          D.DT = nullptr;
+          st.total_blocks += 1;
+          if (++st.ndom == kTrsvMaxDom) push();
+          continue;
+        }
+        // step k solves block bk; blocks bk -+ 1 and bk -+ 2 (in the sweep's order) come before it
+        D.part_in = buf(d, k - 1);
+        D.part_out = buf(d, k);
+        const int bk = lower ? k : nbk - 1 - k;
+        const int dir = lower ? -1 : 1;
+        D.nb0 = bk * kTrsvNB;
+        D.nm = std::min(kTrsvNB, n - D.nb0);
+        D.pb0 = k >= 1 ? (bk + dir) * kTrsvNB : 0;
+        D.pm = k >= 1 ? std::min(kTrsvNB, n - D.pb0) : 0;
+        D.cb0 = k >= 2 ? (bk + 2 * dir) * kTrsvNB : 0;
+        D.cm = k >= 2 ? std::min(kTrsvNB, n - D.cb0) : 0;
+        D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(lower ? bk : nbk + bk) * kTrsvNB * kTrsvNB);
+        // rows past block bk take the update of block bk -+ 2
+        const int rest = D.cm > 0 ? (lower ? n - D.nb0 - D.nm : D.nb0) : 0;
         st.total_blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
-        if (++st.ndom == kTrsvMaxDom) flush();
+        if (++st.ndom == kTrsvMaxDom) push();
       }
-      flush();
+      push();
     }
   }
   return plan;

@@ -945,97 +945,176 @@ __device__ __forceinline__ dz wave_sum(dz v) {
 
 // One step of the blocked triangular solves (L forward or U backward) of
 // every material domain at once, with nb = kTrsvNB diagonal blocks whose
-// transposed inverses DT are precomputed.  Domain d's part of the launch:
-//
-// On entry the solution of its column block [cb0, cb0+cm) is final in sol
-// (cm = 0 on the first step) and the rows of its next diagonal block
-// [nb0, nb0+nm) have received every update except the one from that column
-// block.  The launch
-//   (a) subtracts T[i, cb0:cb0+cm] z_c from every row i still to be solved
-//       (below the column block for L, above it for U), and
-//   (b) solves the next diagonal block: z_n = inv(T_nn) rhs_n.
-// The first kTrsvGroupsH thread blocks of the domain own 16 rows each of the
-// next diagonal block: after updating them they form the partial product
-// inv(T_nn)[:, 16g:16g+16] r_g into part[g][:], and the last of them to
-// finish (agent-scope acq_rel counter; nothing waits on it) sums the partials
-// into sol and puts the counter back to zero.  The domain's further thread
-// blocks update the remaining rows, 64 per block, four rows per wave.
+// transposed inverses DT are precomputed.  Blocks are numbered in the order
+// of the sweep; step j of domain d solves its diagonal block j, [nb0, nb0+nm).
+// On entry
+//   - the solution of block j-2, [cb0, cb0+cm), is in sol (cm = 0 if j < 2);
+//   - the solution of block j-1, [pb0, pb0+pm), is known only as
+//     kTrsvGroupsH partial products in part_in (pm = 0 if j < 1);
+//   - every row still to be solved has received the updates of blocks < j-2.
+// The launch
+//   (a) subtracts T[i, block j-2] z_{j-2} from every row i past block j
+//       (below it for L, above it for U);
+//   (b) sums z_{j-1} from its partials (thread block 0 also stores it in sol),
+//       and solves block j: r = rhs_j - T[j, j-2] z_{j-2} - T[j, j-1] z_{j-1},
+//       z_j = inv(T_jj) r, left as partial products: the first kTrsvGroupsH
+//       thread blocks own 16 rows each; after updating them they form
+//       inv(T_jj)[:, 16g:16g+16] r_g into part_out[g][:].
+// The next launch (the same-stream kernel boundary orders the two) sums them.
+// Each row receives its updates one block at a time in the sweep's order, as
+// in a plain blocked substitution.  An entry with nm = 0 only stores z_{j-1}
+// (one thread block; the end of a sweep).  No thread block waits on another.
+// The domain's further thread blocks do (a), 16 RW rows per block.
 constexpr int kTrsvGroups = kTrsvGroupsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
 constexpr int kTrsvHS = 1024 / kTrsvNB;  // thread groups sharing a group's 16 columns of inv(T_nn)
 constexpr int kTrsvCPH = 16 / kTrsvHS;   // columns per thread group
 
-template <typename C>
-__device__ __forceinline__ dz row_dot(const C *__restrict__ Fi, int cm, const dz *zc, int lane) {
-  dz f[kTrsvCol];
+// Loads in these kernels are unconditional, from addresses clamped into the
+// domain's arrays, with out-of-range values zeroed afterwards: a load under a
+// branch is waited for inside the branch, which would serialise the loads.
+__device__ __forceinline__ int clampi(int v, int hi) { return max(0, min(v, hi)); }
+
+// z_{j-2} of vector q at t = tid mod kTrsvNB, from sol (zero past cm).  All
+// threads load (the same addresses four times over), so that no branch waits
+// for the load before the factor loads that follow are issued.
+template <int NV>
+struct TrsvOld {
+  dz v[NV];
+  __device__ __forceinline__ void fetch(const TrsvDom &D) {
+    const int t = threadIdx.x & (kTrsvNB - 1);
+    const int c = D.cb0 + clampi(t, D.cm - 1);
 #pragma unroll
-  for (int c = 0; c < kTrsvCol; ++c) f[c] = lane + 64 * c < cm ? to_dz(Fi[lane + 64 * c]) : mk(0, 0);
-  dz s = mk(0, 0);
+    for (int q = 0; q < NV; ++q) v[q] = D.sol[q][c];
+  }
+  __device__ __forceinline__ void store(const TrsvDom &D, dz (*zo)[kTrsvNB]) const {
+    const int t = threadIdx.x;
+    if (t >= kTrsvNB) return;
 #pragma unroll
-  for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[lane + 64 * c];
-  return s;
-}
+    for (int q = 0; q < NV; ++q) zo[q][t] = t < D.cm ? v[q] : mk(0, 0);
+  }
+};
+
+// z_{j-1} of vector q at t = tid mod kTrsvNB from its kTrsvGroups partials:
+// thread group h = tid / kTrsvNB sums partials kTrsvHS h .. kTrsvHS h + 3 in
+// order, the four group sums are added in group order through shared memory
+// (zero past pm), and thread block 0 of the domain stores z_{j-1} in sol.
+static_assert(kTrsvGroups == 4 * kTrsvHS, "four thread groups of kTrsvHS partials each");
+template <int NV>
+struct TrsvNew {
+  dz p[NV][kTrsvHS];
+  __device__ __forceinline__ void fetch(const TrsvDom &D) {
+    const int t = threadIdx.x & (kTrsvNB - 1), h = threadIdx.x / kTrsvNB;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int k = 0; k < kTrsvHS; ++k) p[q][k] = D.part_in[q * kTrsvPart + (kTrsvHS * h + k) * kTrsvNB + t];
+  }
+  // red: kTrsvHS x kTrsvNB scratch per vector; a barrier follows before zn is read
+  __device__ __forceinline__ void store(const TrsvDom &D, int blk, dz (*zn)[kTrsvNB],
+                                        dz (*red)[kTrsvHS][kTrsvNB]) const {
+    const int t = threadIdx.x & (kTrsvNB - 1), h = threadIdx.x / kTrsvNB;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      dz z = p[q][0];
+#pragma unroll
+      for (int k = 1; k < kTrsvHS; ++k) z = z + p[q][k];
+      red[q][h][t] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x >= kTrsvNB) return;
+    const bool ok = t < D.pm;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      dz z = red[q][0][t];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) z = z + red[q][k][t];
+      if (!ok) z = mk(0, 0);
+      if (ok && blk == 0) D.sol[q][D.pb0 + t] = z;
+      zn[q][t] = z;
+    }
+  }
+};
 
 // RW rows per wave in the update blocks (16 RW rows per thread block); the
 // autotuner picks RW per context.  NV right-hand sides (1 or 2) share each
 // read of the factors; vector q's sums run in the same order for any NV.
 template <typename C, int RW, int NV>
 __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
-  __shared__ dz zc[NV][kTrsvNB];
+  __shared__ dz zo[NV][kTrsvNB];
+  __shared__ dz zn[NV][kTrsvNB];
   __shared__ dz rg[NV][16];
   __shared__ dz red[NV][kTrsvHS][kTrsvNB];
-  __shared__ int last;
   constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int d = 0;
   while (d + 1 < st.ndom && vb >= st.d[d + 1].first_block) ++d;
   const TrsvDom &D = st.d[d];
   const int blk = vb - D.first_block;
-  const int cb0 = D.cb0, cm = D.cm, nb0 = D.nb0, nm = D.nm;
+  const int cb0 = D.cb0, cm = D.cm, pb0 = D.pb0, pm = D.pm, nb0 = D.nb0, nm = D.nm;
   const int64_t ld = D.ld;
   const C *__restrict__ F = (const C *)D.F;
-#pragma unroll
-  for (int q = 0; q < NV; ++q)
-    if (tid < kTrsvNB) zc[q][tid] = tid < cm ? D.sol[q][cb0 + tid] : mk(0, 0);
+  if (nm == 0) {   // end of a sweep: only the last block's solution
+    TrsvNew<NV> pn;
+    pn.fetch(D);
+    pn.store(D, blk, zn, red);
+    return;
+  }
   if (blk < kTrsvGroups) {
     const int g = blk;
-    // independent loads first: the row of group g this wave updates, its rhs,
-    // and this thread's four entries of the DT slice
+    // every load is issued before the first wait: z_{j-2}, the partials of
+    // z_{j-1} (into shared memory once they arrive), the row of group g this
+    // wave updates (its entries in blocks j-2 and j-1), its rhs, and this
+    // thread's four entries of the DT slice
+    TrsvOld<NV> po;
+    TrsvNew<NV> pn;
+    po.fetch(D);
+    pn.fetch(D);
     const int r = 16 * g + wave;
-    const int i = nb0 + r;
-    dz f[kTrsvCol];
+    // (kept in the factor type until used: registers bound the occupancy)
+    const int ic = nb0 + clampi(r, nm - 1);
+    C fo[kTrsvCol], fn[kTrsvCol];
     dz rv[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) rv[q] = mk(0, 0);
-    if (r < nm) {
+    for (int q = 0; q < NV; ++q) rv[q] = D.rhs[q][ic];
 #pragma unroll
-      for (int q = 0; q < NV; ++q) rv[q] = D.rhs[q][i];
+    for (int c = 0; c < kTrsvCol; ++c) {
+      fo[c] = F[(int64_t)ic * ld + cb0 + clampi(lane + 64 * c, cm - 1)];
+      fn[c] = F[(int64_t)ic * ld + pb0 + clampi(lane + 64 * c, pm - 1)];
+    }
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c)
-        f[c] = lane + 64 * c < cm ? to_dz(F[(int64_t)i * ld + cb0 + lane + 64 * c]) : mk(0, 0);
+    for (int c = 0; c < kTrsvCol; ++c) {
+      if (!(lane + 64 * c < cm)) fo[c] = cx<C>::make(0, 0);
+      if (!(lane + 64 * c < pm)) fn[c] = cx<C>::make(0, 0);
     }
     const int oi = tid & (kTrsvNB - 1), h = tid / kTrsvNB;   // group h takes columns 16 g + kTrsvCPH h ..
     const C *col = (const C *)D.DT + (int64_t)(16 * g + kTrsvCPH * h) * kTrsvNB + oi;
-    dz dt[kTrsvCPH];
+    C dt[kTrsvCPH];
 #pragma unroll
-    for (int l = 0; l < kTrsvCPH; ++l) dt[l] = to_dz(col[(int64_t)l * kTrsvNB]);
+    for (int l = 0; l < kTrsvCPH; ++l) dt[l] = col[(int64_t)l * kTrsvNB];
+    po.store(D, zo);
+    pn.store(D, blk, zn, red);
     __syncthreads();
-    // (a) for the 16 rows of group g, one row per wave
+    // (b) for the 16 rows of group g, one row per wave: the updates of
+    // blocks j-2 and j-1, in that order
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      dz s = mk(0, 0);
+      dz so = mk(0, 0), sn = mk(0, 0);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) s = s + f[c] * zc[q][lane + 64 * c];
-      s = wave_sum(s);
-      if (lane == 0) rg[q][wave] = r < nm ? rv[q] - s : mk(0, 0);
+      for (int c = 0; c < kTrsvCol; ++c) so = so + to_dz(fo[c]) * zo[q][lane + 64 * c];
+#pragma unroll
+      for (int c = 0; c < kTrsvCol; ++c) sn = sn + to_dz(fn[c]) * zn[q][lane + 64 * c];
+      so = wave_sum(so);
+      sn = wave_sum(sn);
+      if (lane == 0) rg[q][wave] = r < nm ? (cm > 0 ? rv[q] - so : rv[q]) - sn : mk(0, 0);
     }
     __syncthreads();
-    // (b) partial product with columns 16 g .. 16 g + 15 of inv(T_nn)
+    // partial product with columns 16 g .. 16 g + 15 of inv(T_jj)
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      dz acc = dt[0] * rg[q][kTrsvCPH * h];
+      dz acc = to_dz(dt[0]) * rg[q][kTrsvCPH * h];
 #pragma unroll
-      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + dt[l] * rg[q][kTrsvCPH * h + l];
+      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + to_dz(dt[l]) * rg[q][kTrsvCPH * h + l];
       red[q][h][oi] = acc;
     }
     __syncthreads();
@@ -1045,36 +1124,12 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
         dz z = red[q][0][tid];
 #pragma unroll
         for (int p = 1; p < kTrsvHS; ++p) z = z + red[q][p][tid];
-        D.part[q * kTrsvPart + g * kTrsvNB + tid] = z;
+        D.part_out[q * kTrsvPart + g * kTrsvNB + tid] = z;
       }
-      __threadfence();
-    }
-    __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const int old = __hip_atomic_fetch_add(D.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      last = old == kTrsvGroups - 1;
-    }
-    __syncthreads();
-    if (last) {
-      __threadfence();
-      if (tid < nm) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          dz p[kTrsvGroups];
-#pragma unroll
-          for (int k = 0; k < kTrsvGroups; ++k) p[k] = D.part[q * kTrsvPart + k * kTrsvNB + tid];
-          dz z = mk(0, 0);
-#pragma unroll
-          for (int k = 0; k < kTrsvGroups; ++k) z = z + p[k];
-          D.sol[q][nb0 + tid] = z;
-        }
-      }
-      if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
-  // (a) for the rows outside the next diagonal block
+  // (a) for the rows past block j
   int rlo, rhi;
   if (st.lower) {
     rlo = nb0 + nm + (blk - kTrsvGroups) * kTrsvBlockRows;
@@ -1083,14 +1138,21 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     rlo = (blk - kTrsvGroups) * kTrsvBlockRows;
     rhi = min(nb0, rlo + kTrsvBlockRows);
   }
+  TrsvOld<NV> po;
+  po.fetch(D);
   const int i0 = rlo + RW * wave;
-  dz f[RW][kTrsvCol];
+  C f[RW][kTrsvCol];
 #pragma unroll
   for (int p = 0; p < RW; ++p)
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c)
-      f[p][c] = (i0 + p < rhi && lane + 64 * c < cm) ? to_dz(F[(int64_t)(i0 + p) * ld + cb0 + lane + 64 * c])
-                                                      : mk(0, 0);
+      f[p][c] = F[(int64_t)clampi(i0 + p, D.n - 1) * ld + cb0 + clampi(lane + 64 * c, cm - 1)];
+#pragma unroll
+  for (int p = 0; p < RW; ++p)
+#pragma unroll
+    for (int c = 0; c < kTrsvCol; ++c)
+      if (!(i0 + p < rhi && lane + 64 * c < cm)) f[p][c] = cx<C>::make(0, 0);
+  po.store(D, zo);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -1099,7 +1161,7 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     for (int p = 0; p < RW; ++p) {
       s[p] = mk(0, 0);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) s[p] = s[p] + f[p][c] * zc[q][lane + 64 * c];
+      for (int c = 0; c < kTrsvCol; ++c) s[p] = s[p] + to_dz(f[p][c]) * zo[q][lane + 64 * c];
     }
 #pragma unroll
     for (int p = 0; p < RW; ++p) s[p] = wave_sum(s[p]);
@@ -1112,10 +1174,10 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
 }
 
 #define VIE_TRSV_STEP(T, C, R)                                                                  \
-  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_r##R(TrsvStep st) {               \
+  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_r##R(TrsvStep st) { \
     trsv_step_body<C, R, 1>(st, blockIdx.x);                                                  \
   }                                                                                           \
-  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_r##R(TrsvStep st) {              \
+  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_r##R(TrsvStep st) { \
     trsv_step_body<C, R, 2>(st, blockIdx.x);                                                  \
   }
 VIE_TRSV_STEP(z, dz, 1)
@@ -1129,9 +1191,9 @@ VIE_TRSV_STEP(c, fz, 8)
 
 // Every step of the triangular solves in one cooperative launch: the thread
 // blocks share each step's work items (the same items the per-step launches
-// give to their thread blocks) and meet at a grid barrier between steps.
-// All blocks run the same loops and reach every barrier; the items' own
-// cross-block reduction is the counter of the per-step kernel.
+// give to their thread blocks) and meet at a grid barrier between steps,
+// which orders one step's partial products before the next step's sums.
+// All blocks run the same loops and reach every barrier.
 template <typename C, int RW>
 __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan, int nsteps) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();

@@ -106,10 +106,13 @@ struct TrsvDom {
   const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
   const void *DT;     // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB, same type)
   dz *rhs[2], *sol[2];  // right-hand sides (updated in place) and solutions, domain-local, per vector
-  dz *part;           // kTrsvGroupsH x kTrsvNB partial products per vector (vector q at q * kTrsvPart)
-  int *counter;       // zero between launches
+  const dz *part_in;  // partial products of the previous block's solution (kTrsvGroupsH x kTrsvNB
+                      // per vector, vector q at q * kTrsvPart), written by the previous step
+  dz *part_out;       // the same for this step's diagonal block, read by the next step
   int64_t ld;
-  int n, cb0, cm, nb0, nm, first_block;
+  // blocks of the step: [cb0, cb0+cm) two back (solution in sol), [pb0, pb0+pm) the previous one
+  // (solution in part_in), [nb0, nb0+nm) the one solved; nm = 0: only store the previous block's solution
+  int n, cb0, cm, pb0, pm, nb0, nm, first_block;
 };
 struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
