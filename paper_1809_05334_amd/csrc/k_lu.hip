@@ -682,54 +682,91 @@ __device__ __forceinline__ void lu_tfin_body(const LuStep &st) {
 
 // A22 -= L21 U12 on the matrix cores.  Tile 64 x 64 per block of 4 waves
 // (2 x 2 waves of 32 x 32, each 2 x 2 MFMA tiles of 16 x 16); K = jb <= 64
-// staged through LDS in chunks of 16.
+// staged through LDS in chunks of 16, the next chunk's loads in flight while
+// the current one is multiplied.  Every global load is unconditional, from
+// an address clamped into the block, with out-of-range values zeroed: a load
+// under a branch is waited for inside the branch.
 //   v_mfma_f64_16x16x4f64 operand layout (lane l): A[i = l%16][k = l/16],
 //   B[k = l/16][j = l%16]; result register r holds D[i = 4*r + l/16][j = l%16].
+//   v_mfma_f32_16x16x4f32: the same operands; result register r holds
+//   D[i = 4*(l/16) + r][j = l%16].
 constexpr int kGemmKC = 16;
 
-__global__ __launch_bounds__(256) void k_lu_gemm_z(LuStep st) {
-  __shared__ double Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
-  __shared__ double Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
+template <typename C> struct Mfma;
+template <> struct Mfma<dz> {
+  typedef double R;
+  typedef v4d Acc;
+  static __device__ __forceinline__ Acc mma(R a, R b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<fz> {
+  typedef float R;
+  typedef v4f Acc;
+  static __device__ __forceinline__ Acc mma(R a, R b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename C>
+__device__ __forceinline__ void lu_gemm_body(const LuStep &st) {
+  typedef typename Mfma<C>::R R;
+  typedef typename Mfma<C>::Acc Acc;
+  constexpr int kPerA = 64 * kGemmKC / 256, kPerB = kGemmKC * 64 / 256;
+  __shared__ R Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
+  __shared__ R Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
   const LuDom &D = st.d[lu_domain(st)];
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
   const int64_t ld = D.ld;
-  dz *__restrict__ A = (dz *)D.A;
+  C *__restrict__ A = (C *)D.A;
   const int nt = (n - k0 - jb + 63) / 64;     // tiles per side of A22
   const int tile = blockIdx.x - D.first_block;
   const int r0 = k0 + jb + (tile / nt) * 64;  // rows of A22
   const int c0 = k0 + jb + (tile % nt) * 64;  // cols of A22
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  v4d cre[2][2], cim[2][2];
+  Acc cre[2][2], cim[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
-      cre[a][b] = v4d{0, 0, 0, 0};
-      cim[a][b] = v4d{0, 0, 0, 0};
+      cre[a][b] = Acc{0, 0, 0, 0};
+      cim[a][b] = Acc{0, 0, 0, 0};
     }
+  // L21[r0.., k0+kc..] (64 x KC) and U12[k0+kc.., c0..] (KC x 64) of chunk kc
+  C va[kPerA], vb[kPerB];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kPerA; ++u) {
+      const int e = tid + 256 * u, i = e / kGemmKC, k = e % kGemmKC;
+      va[u] = A[(int64_t)min(r0 + i, n - 1) * ld + k0 + min(kc + k, jb - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) {
+      const int e = tid + 256 * u, k = e / 64, j = e % 64;
+      vb[u] = A[(int64_t)(k0 + min(kc + k, jb - 1)) * ld + min(c0 + j, n - 1)];
+    }
+  };
+  fetch(0);
   for (int kc = 0; kc < jb; kc += kGemmKC) {
-    __syncthreads();
-    // stage L21[r0.., k0+kc..] (64 x KC) and U12[k0+kc.., c0..] (KC x 64)
-    for (int e = tid; e < 64 * kGemmKC; e += 256) {
-      const int i = e / kGemmKC, k = e % kGemmKC;
-      const int gr = r0 + i, gk = kc + k;
-      dz v = mk(0, 0);
-      if (gr < n && gk < jb) v = A[(int64_t)gr * ld + k0 + gk];
-      Ar[i][k] = v.re;
-      Ai[i][k] = v.im;
+    __syncthreads();   // the previous chunk's shared reads are done
+#pragma unroll
+    for (int u = 0; u < kPerA; ++u) {
+      const int e = tid + 256 * u, i = e / kGemmKC, k = e % kGemmKC;
+      const bool ok = r0 + i < n && kc + k < jb;
+      Ar[i][k] = ok ? va[u].re : R(0);
+      Ai[i][k] = ok ? va[u].im : R(0);
     }
-    for (int e = tid; e < kGemmKC * 64; e += 256) {
-      const int k = e / 64, j = e % 64;
-      const int gk = kc + k, gc = c0 + j;
-      dz v = mk(0, 0);
-      if (gk < jb && gc < n) v = A[(int64_t)(k0 + gk) * ld + gc];
-      Br[k][j] = v.re;
-      Bi[k][j] = v.im;
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) {
+      const int e = tid + 256 * u, k = e / 64, j = e % 64;
+      const bool ok = kc + k < jb && c0 + j < n;
+      Br[k][j] = ok ? vb[u].re : R(0);
+      Bi[k][j] = ok ? vb[u].im : R(0);
     }
     __syncthreads();
+    fetch(min(kc + kGemmKC, jb - 1));   // the next chunk (clamped; unused past the end)
+    __builtin_amdgcn_sched_barrier(0);  // keep its loads ahead of the products
 #pragma unroll
     for (int kk = 0; kk < kGemmKC; kk += 4) {
       const int ka = kk + (lane >> 4);
-      double are[2], aim[2], bre[2], bim[2];
+      R are[2], aim[2], bre[2], bim[2];
       for (int a = 0; a < 2; ++a) {
         const int i = wr * 32 + a * 16 + (lane & 15);
         are[a] = Ar[i][ka];
@@ -742,103 +779,41 @@ __global__ __launch_bounds__(256) void k_lu_gemm_z(LuStep st) {
       }
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[a], bre[b], cre[a][b], 0, 0, 0);
-          cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim[a], bim[b], cre[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[a], bim[b], cim[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[a], bre[b], cim[a][b], 0, 0, 0);
+          cre[a][b] = Mfma<C>::mma(are[a], bre[b], cre[a][b]);
+          cre[a][b] = Mfma<C>::mma(-aim[a], bim[b], cre[a][b]);
+          cim[a][b] = Mfma<C>::mma(are[a], bim[b], cim[a][b]);
+          cim[a][b] = Mfma<C>::mma(aim[a], bre[b], cim[a][b]);
         }
     }
   }
-  // A22 -= C
-  for (int a = 0; a < 2; ++a)
+  // A22 -= C, half a wave tile at a time: its eight loads first, then the
+  // stores of the in-range entries
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    C old[2][4];
+#pragma unroll
     for (int b = 0; b < 2; ++b)
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = r0 + wr * 32 + a * 16 + 4 * r + (lane >> 4);
+        const int gi = r0 + wr * 32 + a * 16 + Mfma<C>::row(r, lane);
         const int gj = c0 + wc * 32 + b * 16 + (lane & 15);
-        if (gi < n && gj < n) {
-          dz *p = A + (int64_t)gi * ld + gj;
-          const dz v = *p;
-          *p = mk(v.re - cre[a][b][r], v.im - cim[a][b][r]);
-        }
+        old[b][r] = A[(int64_t)min(gi, n - 1) * ld + min(gj, n - 1)];
       }
+    __builtin_amdgcn_sched_barrier(0);  // the loads stay together, ahead of the stores
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = r0 + wr * 32 + a * 16 + Mfma<C>::row(r, lane);
+        const int gj = c0 + wc * 32 + b * 16 + (lane & 15);
+        if (gi < n && gj < n)
+          A[(int64_t)gi * ld + gj] = cx<C>::make(old[b][r].re - cre[a][b][r], old[b][r].im - cim[a][b][r]);
+      }
+  }
 }
 
-// FP32 blocks: the same tiling on v_mfma_f32_16x16x4f32, whose operand layout
-// matches the FP64 instruction but whose result register r holds
-// D[i = 4*(l/16) + r][j = l%16].
-__global__ __launch_bounds__(256) void k_lu_gemm_c(LuStep st) {
-  __shared__ float Ar[64][kGemmKC + 1], Ai[64][kGemmKC + 1];
-  __shared__ float Br[kGemmKC][64 + 1], Bi[kGemmKC][64 + 1];
-  const LuDom &D = st.d[lu_domain(st)];
-  const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
-  const int64_t ld = D.ld;
-  fz *__restrict__ A = (fz *)D.A;
-  const int nt = (n - k0 - jb + 63) / 64;
-  const int tile = blockIdx.x - D.first_block;
-  const int r0 = k0 + jb + (tile / nt) * 64;
-  const int c0 = k0 + jb + (tile % nt) * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  v4f cre[2][2], cim[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      cre[a][b] = v4f{0, 0, 0, 0};
-      cim[a][b] = v4f{0, 0, 0, 0};
-    }
-  for (int kc = 0; kc < jb; kc += kGemmKC) {
-    __syncthreads();
-    for (int e = tid; e < 64 * kGemmKC; e += 256) {
-      const int i = e / kGemmKC, k = e % kGemmKC;
-      const int gr = r0 + i, gk = kc + k;
-      fz v = fz{0, 0};
-      if (gr < n && gk < jb) v = A[(int64_t)gr * ld + k0 + gk];
-      Ar[i][k] = v.re;
-      Ai[i][k] = v.im;
-    }
-    for (int e = tid; e < kGemmKC * 64; e += 256) {
-      const int k = e / 64, j = e % 64;
-      const int gk = kc + k, gc = c0 + j;
-      fz v = fz{0, 0};
-      if (gk < jb && gc < n) v = A[(int64_t)(k0 + gk) * ld + gc];
-      Br[k][j] = v.re;
-      Bi[k][j] = v.im;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < kGemmKC; kk += 4) {
-      const int ka = kk + (lane >> 4);
-      float are[2], aim[2], bre[2], bim[2];
-      for (int a = 0; a < 2; ++a) {
-        const int i = wr * 32 + a * 16 + (lane & 15);
-        are[a] = Ar[i][ka];
-        aim[a] = Ai[i][ka];
-      }
-      for (int b = 0; b < 2; ++b) {
-        const int j = wc * 32 + b * 16 + (lane & 15);
-        bre[b] = Br[ka][j];
-        bim[b] = Bi[ka][j];
-      }
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-          cre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[a], bre[b], cre[a][b], 0, 0, 0);
-          cre[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[a], bim[b], cre[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[a], bim[b], cim[a][b], 0, 0, 0);
-          cim[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[a], bre[b], cim[a][b], 0, 0, 0);
-        }
-    }
-  }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int r = 0; r < 4; ++r) {
-        const int gi = r0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
-        const int gj = c0 + wc * 32 + b * 16 + (lane & 15);
-        if (gi < n && gj < n) {
-          fz *p = A + (int64_t)gi * ld + gj;
-          const fz v = *p;
-          *p = fz{v.re - cre[a][b][r], v.im - cim[a][b][r]};
-        }
-      }
-}
+__global__ __launch_bounds__(256) void k_lu_gemm_z(LuStep st) { lu_gemm_body<dz>(st); }
+__global__ __launch_bounds__(256) void k_lu_gemm_c(LuStep st) { lu_gemm_body<fz>(st); }
 
 __global__ __launch_bounds__(1024) void k_lu_pivot_z(LuStep st) { lu_pivot_body<dz>(st); }
 __global__ __launch_bounds__(1024) void k_lu_pivot_c(LuStep st) { lu_pivot_body<fz>(st); }
