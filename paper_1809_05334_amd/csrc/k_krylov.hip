@@ -25,7 +25,46 @@ __device__ __forceinline__ double wsum(double v) {
 // chunks shared by the block, Z is streamed once with non-temporal loads.
 // With NV = 2 one pass over Z serves two vectors (the two polarisations of a
 // paired solve); each vector's sums run in the same order as with NV = 1.
+// Loads are unconditional (rows past N read row N-1 and are never stored,
+// staging reads past the chunk are clamped into it): a load under a branch is
+// waited for inside the branch, which would serialise a wave's loads.
 constexpr int kMvChunk = 1024;
+
+// x chunk [c0, c0+len) of each vector into xs (vector q at q*kMvChunk):
+// every load first, as two-double vectors held in registers (copies of the
+// complex struct were kept in scratch memory), then the shared stores
+typedef double v2d __attribute__((ext_vector_type(2)));
+static_assert(kMvChunk == 4 * 256, "four staging loads per thread and vector");
+template <int NV>
+__device__ __forceinline__ void stage_x(const MvVecs &v, int64_t c0, int len, dz *xs) {
+  static_assert(NV == 1 || NV == 2, "one or two vectors");
+  const int tid = threadIdx.x;
+  const int i0 = min(tid, len - 1), i1 = min(tid + 256, len - 1), i2 = min(tid + 512, len - 1),
+            i3 = min(tid + 768, len - 1);
+  const v2d *x = reinterpret_cast<const v2d *>(v.x[0] + c0);
+  const v2d a0 = x[i0], a1 = x[i1], a2 = x[i2], a3 = x[i3];
+  v2d b0 = a0, b1 = a1, b2 = a2, b3 = a3;
+  if constexpr (NV == 2) {
+    const v2d *y = reinterpret_cast<const v2d *>(v.x[1] + c0);
+    b0 = y[i0];
+    b1 = y[i1];
+    b2 = y[i2];
+    b3 = y[i3];
+  }
+  __syncthreads();   // the previous chunk's shared reads are done
+  v2d *o = reinterpret_cast<v2d *>(xs);
+  if (tid < len) o[tid] = a0;
+  if (tid + 256 < len) o[tid + 256] = a1;
+  if (tid + 512 < len) o[tid + 512] = a2;
+  if (tid + 768 < len) o[tid + 768] = a3;
+  if constexpr (NV == 2) {
+    if (tid < len) o[kMvChunk + tid] = b0;
+    if (tid + 256 < len) o[kMvChunk + tid + 256] = b1;
+    if (tid + 512 < len) o[kMvChunk + tid + 512] = b2;
+    if (tid + 768 < len) o[kMvChunk + tid + 768] = b3;
+  }
+  __syncthreads();
+}
 
 template <int RPW, int NV>
 __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld, int64_t N, const MvVecs &v,
@@ -40,29 +79,25 @@ __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld
   const double *Zd = reinterpret_cast<const double *>(Z);
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-      for (int i = tid; i < len; i += 256) xs[q * kMvChunk + i] = v.x[q][c0 + i];
-    __syncthreads();
+    stage_x<NV>(v, c0, len, xs);
     for (int cc = lane; cc < len; cc += 64) {
+      double zr[RPW], zi[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int64_t o = 2 * (min(row0 + r, N - 1) * ld + c0 + cc);
+        zr[r] = __builtin_nontemporal_load(Zd + o);
+        zi[r] = __builtin_nontemporal_load(Zd + o + 1);
+      }
       dz xv[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) xv[q] = xs[q * kMvChunk + cc];
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t row = row0 + r;
-        if (row < N) {
-          const int64_t o = 2 * (row * ld + c0 + cc);
-          const double zr = __builtin_nontemporal_load(Zd + o);
-          const double zi = __builtin_nontemporal_load(Zd + o + 1);
+      for (int r = 0; r < RPW; ++r)
 #pragma unroll
-          for (int q = 0; q < NV; ++q) {
-            are[q][r] = fma(zr, xv[q].re, fma(-zi, xv[q].im, are[q][r]));
-            aim[q][r] = fma(zr, xv[q].im, fma(zi, xv[q].re, aim[q][r]));
-          }
+        for (int q = 0; q < NV; ++q) {
+          are[q][r] = fma(zr[r], xv[q].re, fma(-zi[r], xv[q].im, are[q][r]));
+          aim[q][r] = fma(zr[r], xv[q].im, fma(zi[r], xv[q].re, aim[q][r]));
         }
-      }
     }
   }
 #pragma unroll
@@ -116,12 +151,12 @@ __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int
     for (int r = 0; r < RPW; ++r) are[q][r] = aim[q][r] = 0.0;
   for (int64_t c0 = 0; c0 < N; c0 += kMvChunk) {
     const int len = (int)min<int64_t>(kMvChunk, N - c0);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-      for (int i = tid; i < len; i += 256) xs[q * kMvChunk + i] = v.x[q][c0 + i];
-    __syncthreads();
+    stage_x<NV>(v, c0, len, xs);
     for (int cc = 2 * lane; cc < len; cc += 128) {
+      v4f z[RPW];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        z[r] = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Zs + min(row0 + r, N - 1) * ld + c0 + cc));
       dz x0[NV], x1[NV];
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -129,19 +164,14 @@ __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int
         x1[q] = cc + 1 < len ? xs[q * kMvChunk + cc + 1] : mk(0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        const int64_t row = row0 + r;
-        if (row < N) {
-          const v4f z = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Zs + row * ld + c0 + cc));
+      for (int r = 0; r < RPW; ++r)
 #pragma unroll
-          for (int q = 0; q < NV; ++q) {
-            are[q][r] = fma((double)z[0], x0[q].re, fma(-(double)z[1], x0[q].im, are[q][r]));
-            aim[q][r] = fma((double)z[0], x0[q].im, fma((double)z[1], x0[q].re, aim[q][r]));
-            are[q][r] = fma((double)z[2], x1[q].re, fma(-(double)z[3], x1[q].im, are[q][r]));
-            aim[q][r] = fma((double)z[2], x1[q].im, fma((double)z[3], x1[q].re, aim[q][r]));
-          }
+        for (int q = 0; q < NV; ++q) {
+          are[q][r] = fma((double)z[r][0], x0[q].re, fma(-(double)z[r][1], x0[q].im, are[q][r]));
+          aim[q][r] = fma((double)z[r][0], x0[q].im, fma((double)z[r][1], x0[q].re, aim[q][r]));
+          are[q][r] = fma((double)z[r][2], x1[q].re, fma(-(double)z[r][3], x1[q].im, are[q][r]));
+          aim[q][r] = fma((double)z[r][2], x1[q].im, fma((double)z[r][3], x1[q].re, aim[q][r]));
         }
-      }
     }
   }
 #pragma unroll
