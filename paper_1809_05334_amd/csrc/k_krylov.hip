@@ -227,7 +227,19 @@ __global__ __launch_bounds__(256) void k_combine(const dz *__restrict__ V, int64
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   dz s = mk(0, 0);
-  for (int i = 0; i < nv; ++i) s = s + V[(int64_t)i * ldv + k] * c[i];
+  // eight basis entries in flight at a time; the sum runs in i order
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    double vr[8], vi[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const dz v = V[(int64_t)min(i0 + g, nv - 1) * ldv + k];
+      vr[g] = v.re;
+      vi[g] = v.im;
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      if (i0 + g < nv) s = s + mk(vr[g], vi[g]) * c[i0 + g];
+  }
   y[k] = s;
 }
 
@@ -249,7 +261,14 @@ __global__ __launch_bounds__(256) void k_norm2(const dz *__restrict__ w, int64_t
 __global__ void k_norm_reduce(const double *__restrict__ part, int nblk, double *__restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[b];
+  for (int b0 = 0; b0 < nblk; b0 += 16) {   // sixteen loads in flight, summed in order
+    double p[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) p[u] = part[min(b0 + u, nblk - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b0 + u < nblk) s += p[u];
+  }
   *out = sqrt(s);
 }
 
@@ -292,23 +311,41 @@ __global__ void k_arn_begin(const dz *__restrict__ V, int64_t ldv, const int *__
 // partial inner products with V_0 .. V_j (k_dots with nv = j + 1)
 __global__ __launch_bounds__(256) void k_dots_j(const dz *__restrict__ V, int64_t ldv, const int *__restrict__ jd,
                                                 const dz *__restrict__ w, int64_t N, dz *__restrict__ part) {
-  __shared__ dz red[4];
+  // eight basis vectors per pass: their loads are in flight together and one
+  // pair of barriers serves the eight block sums (each sum as for one vector)
+  constexpr int G = 8;
+  __shared__ dz red[G][4];
   const int nv = *jd + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
-  for (int i = 0; i < nv; ++i) {
-    const dz *Vi = V + (int64_t)i * ldv;
-    dz s = mk(0, 0);
+  for (int i0 = 0; i0 < nv; i0 += G) {
+    double sr[G], si[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) sr[g] = si[g] = 0.0;
     for (int64_t k = lo + tid; k < hi; k += 256) {
-      const dz v = Vi[k], ww = w[k];
-      s.re = fma(v.re, ww.re, fma(v.im, ww.im, s.re));
-      s.im = fma(v.re, ww.im, fma(-v.im, ww.re, s.im));
+      const dz ww = w[k];
+      double vr[G], vi[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const dz v = V[(int64_t)min(i0 + g, nv - 1) * ldv + k];
+        vr[g] = v.re;
+        vi[g] = v.im;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        sr[g] = fma(vr[g], ww.re, fma(vi[g], ww.im, sr[g]));
+        si[g] = fma(vr[g], ww.im, fma(-vi[g], ww.re, si[g]));
+      }
     }
-    s = wsum(s);
-    if (lane == 0) red[wave] = s;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const double a = wsum(sr[g]), b = wsum(si[g]);
+      if (lane == 0) red[g][wave] = mk(a, b);
+    }
     __syncthreads();
-    if (tid == 0) part[(int64_t)blockIdx.x * nv + i] = red[0] + red[1] + red[2] + red[3];
+    if (tid < G && i0 + tid < nv)
+      part[(int64_t)blockIdx.x * nv + i0 + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
     __syncthreads();
   }
 }
@@ -320,7 +357,18 @@ __global__ void k_dots_reduce_j(const dz *__restrict__ part, int nblk, const int
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
   dz s = mk(0, 0);
-  for (int b = 0; b < nblk; ++b) s = s + part[(int64_t)b * nv + i];
+  for (int b0 = 0; b0 < nblk; b0 += 16) {   // sixteen loads in flight, summed in order
+    double pr[16], pi[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const dz p = part[(int64_t)min(b0 + u, nblk - 1) * nv + i];
+      pr[u] = p.re;
+      pi[u] = p.im;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b0 + u < nblk) s = s + mk(pr[u], pi[u]);
+  }
   dz *h = H + (int64_t)j * ldh;
   h[i] = pass ? h[i] + s : s;
   y[i] = s;
@@ -333,7 +381,19 @@ __global__ __launch_bounds__(256) void k_update_j(const dz *__restrict__ V, int6
   if (k >= N) return;
   const int nv = *jd + 1;
   dz s = w[k];
-  for (int i = 0; i < nv; ++i) s = s - V[(int64_t)i * ldv + k] * c[i];
+  // eight basis entries in flight at a time; the updates run in i order
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    double vr[8], vi[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const dz v = V[(int64_t)min(i0 + g, nv - 1) * ldv + k];
+      vr[g] = v.re;
+      vi[g] = v.im;
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      if (i0 + g < nv) s = s - mk(vr[g], vi[g]) * c[i0 + g];
+  }
   w[k] = s;
 }
 
