@@ -217,7 +217,7 @@ enum {
                              * may run up to this many steps past convergence (unused).  Needs a
                              * non-null stream: vie_solve returns VIE_EINVAL on the null stream */
   VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
-  VIE_OPT_TRSV_ROWS = 3,    /* triangular-solve update rows per wave: 1, 2, 4 (default) or 8 */
+  VIE_OPT_TRSV_ROWS = 3,    /* triangular-solve update rows per wave: 4 (default) or 8 */
   VIE_OPT_TRSV_COOP = 4,    /* 1: each preconditioner apply runs its triangular-solve steps in one
                              * cooperative launch with grid barriers between steps (not inside
                              * captured graphs); 0 (default): one
@@ -234,7 +234,7 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value);
 
 typedef struct {
   double matvec_ms[3];   /* per product, rows per wave 2, 4, 8 */
-  double apply_ms[4];    /* per preconditioner apply, rows per wave 1, 2, 4, 8 */
+  double apply_ms[4];    /* per preconditioner apply, rows per wave 4 and 8: one vector, then two */
   int matvec_rows, trsv_rows;   /* the picks, now set on the context */
 } vie_tuning;
 

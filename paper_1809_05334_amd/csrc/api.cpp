@@ -73,7 +73,7 @@ struct vie_ctx {
   int packlen = 0;
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
   int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
-  int trsv_rw = 4;                  // triangular-solve update rows per wave (1, 2, 4)
+  int trsv_rw = 4;                  // triangular-solve update rows per wave (4, 8)
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
   int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
   int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
@@ -989,46 +989,30 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
 
 void launch_trsv_step(vie_ctx *ctx, const TrsvStep &st, int nv) {
   const dim3 g(st.total_blocks), b(1024);
-  const int rw = ctx->trsv_rw;
+  const bool r8 = ctx->trsv_rw == 8;
   if (nv == 2) {
     if (fp32_factors(ctx)) {
-      if (rw == 1) hipLaunchKernelGGL(k_trsv_step2_c_r1, g, b, 0, ctx->stream, st);
-      else if (rw == 2) hipLaunchKernelGGL(k_trsv_step2_c_r2, g, b, 0, ctx->stream, st);
-      else if (rw == 8) hipLaunchKernelGGL(k_trsv_step2_c_r8, g, b, 0, ctx->stream, st);
+      if (r8) hipLaunchKernelGGL(k_trsv_step2_c_r8, g, b, 0, ctx->stream, st);
       else hipLaunchKernelGGL(k_trsv_step2_c_r4, g, b, 0, ctx->stream, st);
     } else {
-      if (rw == 1) hipLaunchKernelGGL(k_trsv_step2_z_r1, g, b, 0, ctx->stream, st);
-      else if (rw == 2) hipLaunchKernelGGL(k_trsv_step2_z_r2, g, b, 0, ctx->stream, st);
-      else if (rw == 8) hipLaunchKernelGGL(k_trsv_step2_z_r8, g, b, 0, ctx->stream, st);
+      if (r8) hipLaunchKernelGGL(k_trsv_step2_z_r8, g, b, 0, ctx->stream, st);
       else hipLaunchKernelGGL(k_trsv_step2_z_r4, g, b, 0, ctx->stream, st);
     }
     return;
   }
   if (fp32_factors(ctx)) {
-    if (rw == 1) hipLaunchKernelGGL(k_trsv_step_c_r1, g, b, 0, ctx->stream, st);
-    else if (rw == 2) hipLaunchKernelGGL(k_trsv_step_c_r2, g, b, 0, ctx->stream, st);
-    else if (rw == 8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
+    if (r8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
     else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
   } else {
-    if (rw == 1) hipLaunchKernelGGL(k_trsv_step_z_r1, g, b, 0, ctx->stream, st);
-    else if (rw == 2) hipLaunchKernelGGL(k_trsv_step_z_r2, g, b, 0, ctx->stream, st);
-    else if (rw == 8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
+    if (r8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
     else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
   }
 }
 
 const void *coop_kernel(const vie_ctx *ctx) {
-  const int rw = ctx->trsv_rw;
-  if (fp32_factors(ctx)) {
-    if (rw == 1) return (const void *)k_trsv_coop_c_r1;
-    if (rw == 2) return (const void *)k_trsv_coop_c_r2;
-    if (rw == 8) return (const void *)k_trsv_coop_c_r8;
-    return (const void *)k_trsv_coop_c_r4;
-  }
-  if (rw == 1) return (const void *)k_trsv_coop_z_r1;
-  if (rw == 2) return (const void *)k_trsv_coop_z_r2;
-  if (rw == 8) return (const void *)k_trsv_coop_z_r8;
-  return (const void *)k_trsv_coop_z_r4;
+  const bool r8 = ctx->trsv_rw == 8;
+  if (fp32_factors(ctx)) return r8 ? (const void *)k_trsv_coop_c_r8 : (const void *)k_trsv_coop_c_r4;
+  return r8 ? (const void *)k_trsv_coop_z_r8 : (const void *)k_trsv_coop_z_r4;
 }
 
 // Run the plan as one cooperative launch: the plan is uploaded once per
@@ -1703,8 +1687,7 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       ctx->lu_pivot = value;
       return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
-      if (value != 1 && value != 2 && value != 4 && value != 8)
-        return fail(ctx, VIE_EINVAL, "trsv rows per wave: 1, 2, 4 or 8");
+      if (value != 4 && value != 8) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 4 or 8");
       if (value != ctx->trsv_rw) drop_graphs(ctx);
       ctx->trsv_rw = value;
       return VIE_OK;
@@ -1746,7 +1729,7 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
     *ms_out = ms / reps;
     return VIE_OK;
   };
-  const int mv_opts[3] = {2, 4, 8}, tr_opts[4] = {1, 2, 4, 8};
+  const int mv_opts[3] = {2, 4, 8}, tr_opts[2] = {4, 8};
   double best = 1e300;
   int pick = ctx->mv_rpw;
   for (int i = 0; i < 3; ++i) {
@@ -1758,16 +1741,20 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
     }
   }
   ctx->mv_rpw = pick;
+  // triangular solves for one vector and for two (paired solves): the pick
+  // minimises the sum of the two
   best = 1e300;
   pick = ctx->trsv_rw;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 2; ++i) {
     ctx->trsv_rw = tr_opts[i];
-    if (int rc = time_it([&]() { return apply_minv(ctx, x, ctx->ptr<dz>(L.K[0].vu), ctx->ptr<dz>(L.K[0].vt),
-                                                   ctx->ptr<dz>(L.K[0].vr)); },
-                         &t.apply_ms[i]))
-      return rc;
-    if (t.apply_ms[i] < best) {
-      best = t.apply_ms[i];
+    const Layout::Kry &A = L.K[0], &B = L.K[1];
+    const dz *v2[2] = {x, x};
+    dz *o2[2] = {ctx->ptr<dz>(A.vu), ctx->ptr<dz>(B.vu)}, *t2[2] = {ctx->ptr<dz>(A.vt), ctx->ptr<dz>(B.vt)},
+       *r2[2] = {ctx->ptr<dz>(A.vr), ctx->ptr<dz>(B.vr)};
+    if (int rc = time_it([&]() { return apply_minv(ctx, x, o2[0], t2[0], r2[0]); }, &t.apply_ms[i])) return rc;
+    if (int rc = time_it([&]() { return apply_minv_n(ctx, 2, v2, o2, t2, r2); }, &t.apply_ms[2 + i])) return rc;
+    if (t.apply_ms[i] + t.apply_ms[2 + i] < best) {
+      best = t.apply_ms[i] + t.apply_ms[2 + i];
       pick = tr_opts[i];
     }
   }

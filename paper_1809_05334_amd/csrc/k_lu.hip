@@ -918,6 +918,29 @@ __device__ __forceinline__ dz wave_sum(dz v) {
   return v;
 }
 
+// Sums over a 16-lane row of the wave, in every lane of the row, by DPP
+// moves (no shared-memory traffic): lane pairs, quads, half rows, rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  return __longlong_as_double((long long)dpp64<CTRL>((unsigned long long)__double_as_longlong(v)));
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v = v + dpp_d<0xb1>(v);    // quad_perm [1,0,3,2]
+  v = v + dpp_d<0x4e>(v);    // quad_perm [2,3,0,1]
+  v = v + dpp_d<0x141>(v);   // row_half_mirror
+  return v + dpp_d<0x140>(v);   // row_mirror
+}
+__device__ __forceinline__ dz row16_sum(dz v) { return mk(row16_sum(v.re), row16_sum(v.im)); }
+// the sum over the whole wave (uniform): the four row sums added in row order
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = row16_sum(v);
+  const auto rl = [](double x, int l) {
+    return __longlong_as_double((long long)readlane64((unsigned long long)__double_as_longlong(x), l));
+  };
+  return ((rl(v, 0) + rl(v, 16)) + rl(v, 32)) + rl(v, 48);
+}
+__device__ __forceinline__ dz wave_sum_dpp(dz v) { return mk(wave_sum_dpp(v.re), wave_sum_dpp(v.im)); }
+
 // One step of the blocked triangular solves (L forward or U backward) of
 // every material domain at once, with nb = kTrsvNB diagonal blocks whose
 // transposed inverses DT are precomputed.  Blocks are numbered in the order
@@ -1079,8 +1102,8 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
       for (int c = 0; c < kTrsvCol; ++c) so = so + to_dz(fo[c]) * zo[q][lane + 64 * c];
 #pragma unroll
       for (int c = 0; c < kTrsvCol; ++c) sn = sn + to_dz(fn[c]) * zn[q][lane + 64 * c];
-      so = wave_sum(so);
-      sn = wave_sum(sn);
+      so = wave_sum_dpp(so);
+      sn = wave_sum_dpp(sn);
       if (lane == 0) rg[q][wave] = r < nm ? (cm > 0 ? rv[q] - so : rv[q]) - sn : mk(0, 0);
     }
     __syncthreads();
@@ -1104,7 +1127,11 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
     }
     return;
   }
-  // (a) for the rows past block j
+  // (a) for the rows past block j: each wave takes RW rows as RW / 4 groups
+  // of four, sixteen lanes per row; lane c of a row holds its columns c,
+  // c + 16, .., c + kTrsvNB - 16, and a row's sum is a 16-lane DPP reduction
+  static_assert(RW % 4 == 0, "rows per wave: a multiple of four");
+  constexpr int RG = RW / 4, kPerL = kTrsvNB / 16;
   int rlo, rhi;
   if (st.lower) {
     rlo = nb0 + nm + (blk - kTrsvGroups) * kTrsvBlockRows;
@@ -1115,37 +1142,32 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
   }
   TrsvOld<NV> po;
   po.fetch(D);
-  const int i0 = rlo + RW * wave;
-  C f[RW][kTrsvCol];
+  const int rr = lane >> 4, cl = lane & 15;
+  const int i0 = rlo + RW * wave + rr;   // row of group g: i0 + 4 g
+  C f[RG][kPerL];
 #pragma unroll
-  for (int p = 0; p < RW; ++p)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
-    for (int c = 0; c < kTrsvCol; ++c)
-      f[p][c] = F[(int64_t)clampi(i0 + p, D.n - 1) * ld + cb0 + clampi(lane + 64 * c, cm - 1)];
+    for (int c = 0; c < kPerL; ++c)
+      f[g][c] = F[(int64_t)clampi(i0 + 4 * g, D.n - 1) * ld + cb0 + clampi(cl + 16 * c, cm - 1)];
 #pragma unroll
-  for (int p = 0; p < RW; ++p)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
-    for (int c = 0; c < kTrsvCol; ++c)
-      if (!(i0 + p < rhi && lane + 64 * c < cm)) f[p][c] = cx<C>::make(0, 0);
+    for (int c = 0; c < kPerL; ++c)
+      if (!(i0 + 4 * g < rhi && cl + 16 * c < cm)) f[g][c] = cx<C>::make(0, 0);
   po.store(D, zo);
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    dz s[RW];
+  for (int q = 0; q < NV; ++q)
 #pragma unroll
-    for (int p = 0; p < RW; ++p) {
-      s[p] = mk(0, 0);
+    for (int g = 0; g < RG; ++g) {
+      dz s = mk(0, 0);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) s[p] = s[p] + to_dz(f[p][c]) * zo[q][lane + 64 * c];
+      for (int c = 0; c < kPerL; ++c) s = s + to_dz(f[g][c]) * zo[q][cl + 16 * c];
+      s = row16_sum(s);
+      const int i = i0 + 4 * g;
+      if (cl == 0 && i < rhi) D.rhs[q][i] = D.rhs[q][i] - s;
     }
-#pragma unroll
-    for (int p = 0; p < RW; ++p) s[p] = wave_sum(s[p]);
-    dz v = s[0];
-#pragma unroll
-    for (int p = 1; p < RW; ++p)
-      if (lane == p) v = s[p];
-    if (lane < RW && i0 + lane < rhi) D.rhs[q][i0 + lane] = D.rhs[q][i0 + lane] - v;
-  }
 }
 
 #define VIE_TRSV_STEP(T, C, R)                                                                  \
@@ -1155,12 +1177,8 @@ __device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
   __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_r##R(TrsvStep st) { \
     trsv_step_body<C, R, 2>(st, blockIdx.x);                                                  \
   }
-VIE_TRSV_STEP(z, dz, 1)
-VIE_TRSV_STEP(z, dz, 2)
 VIE_TRSV_STEP(z, dz, 4)
 VIE_TRSV_STEP(z, dz, 8)
-VIE_TRSV_STEP(c, fz, 1)
-VIE_TRSV_STEP(c, fz, 2)
 VIE_TRSV_STEP(c, fz, 4)
 VIE_TRSV_STEP(c, fz, 8)
 
@@ -1187,12 +1205,8 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
   __global__ __launch_bounds__(1024) void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps) { \
     trsv_coop_body<C, R>(plan, nsteps);                                                       \
   }
-VIE_TRSV_COOP(z, dz, 1)
-VIE_TRSV_COOP(z, dz, 2)
 VIE_TRSV_COOP(z, dz, 4)
 VIE_TRSV_COOP(z, dz, 8)
-VIE_TRSV_COOP(c, fz, 1)
-VIE_TRSV_COOP(c, fz, 2)
 VIE_TRSV_COOP(c, fz, 4)
 VIE_TRSV_COOP(c, fz, 8)
 

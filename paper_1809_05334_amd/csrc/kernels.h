@@ -120,7 +120,7 @@ struct TrsvStep {
   int total_blocks;   // thread blocks (work items) of the step over all its domains
 };
 // variants by factor type (_z FP64, _c FP32) and rows per wave of the update
-// blocks (1, 2, 4, 8 -> 16 .. 128 rows per block); vectors and arithmetic FP64.
+// blocks (4, 8 -> 64, 128 rows per block); vectors and arithmetic FP64.
 // k_trsv_step2_*: two right-hand sides per pass over the factors (each
 // vector's sums in the order of the one-vector kernel).
 // k_trsv_coop_*: every step of a plan in one cooperative launch.
@@ -128,12 +128,8 @@ struct TrsvStep {
   __global__ void k_trsv_step_##T##_r##R(TrsvStep st);       \
   __global__ void k_trsv_step2_##T##_r##R(TrsvStep st);      \
   __global__ void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps);
-VIE_DECL_TRSV(z, 1)
-VIE_DECL_TRSV(z, 2)
 VIE_DECL_TRSV(z, 4)
 VIE_DECL_TRSV(z, 8)
-VIE_DECL_TRSV(c, 1)
-VIE_DECL_TRSV(c, 2)
 VIE_DECL_TRSV(c, 4)
 VIE_DECL_TRSV(c, 8)
 #undef VIE_DECL_TRSV
