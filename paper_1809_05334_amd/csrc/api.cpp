@@ -101,6 +101,10 @@ struct vie_ctx {
   int32_t *pin_piv = nullptr;       // pinned: the pivots read back [N], the row permutation [N]
   int64_t pin_piv_n = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  // block LU look-ahead: the next panel's tournament on a stream of its own
+  // (default priority) while the rest of the trailing update runs
+  hipStream_t side = nullptr;
+  hipEvent_t ev_la = nullptr, ev_ts = nullptr;
   vie_fill_stats fstats{};
   double t_fill = 0, t_factor = 0;
 
@@ -367,6 +371,9 @@ int vie_create(vie_ctx **out, int device, void *hip_stream) {
   HIPCK(hipEventCreate(&ctx->ev1));
   HIPCK(hipEventCreate(&ctx->ev2));
   HIPCK(hipEventCreate(&ctx->ev3));
+  HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  HIPCK(hipEventCreateWithFlags(&ctx->ev_la, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&ctx->ev_ts, hipEventDisableTiming));
   *out = ctx;
   return VIE_OK;
 }
@@ -392,6 +399,12 @@ int vie_destroy(vie_ctx *ctx) {
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_la) (void)hipEventDestroy(ctx->ev_la);
+  if (ctx->ev_ts) (void)hipEventDestroy(ctx->ev_ts);
   delete ctx->tab;
   delete ctx;
   return VIE_OK;
@@ -724,45 +737,50 @@ enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_TSEL, LU_TFIN };
 
 // One launch of an LU kernel over every domain with blocks_of(d) > 0 thread
 // blocks (kLuMaxDom domains per launch; more domains take more launches).
+// (GEMM: column tiles gcol0 .. gcol0 + gcols - 1 of the trailing matrix,
+// gcols <= 0 for all from gcol0; stream: the context's unless given.)
 template <typename BlocksOf>
 void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of,
-               int all_cols = 0) {
+               int all_cols = 0, int gcol0 = 0, int gcols = 0, hipStream_t stream = nullptr, bool own = false) {
   LuStep st{};
   st.j = j;
   st.k0 = k0;
   st.all_cols = all_cols;
+  st.gcol0 = gcol0;
+  st.gcols = gcols;
   int total = 0;
+  const hipStream_t sm = own ? stream : ctx->stream;
   auto flush = [&]() {
     if (st.ndom == 0) return;
     const bool f32 = fp32_factors(ctx);
     switch (k) {
       case LU_PIVOT:
-        if (f32) hipLaunchKernelGGL(k_lu_pivot_c, dim3(total), dim3(1024), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_pivot_z, dim3(total), dim3(1024), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_pivot_c, dim3(total), dim3(1024), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_pivot_z, dim3(total), dim3(1024), 0, sm, st);
         break;
       case LU_COL:
-        if (f32) hipLaunchKernelGGL(k_lu_col_c, dim3(total), dim3(256), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_col_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_col_c, dim3(total), dim3(256), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_col_z, dim3(total), dim3(256), 0, sm, st);
         break;
       case LU_SWAP:
-        if (f32) hipLaunchKernelGGL(k_lu_swap_c, dim3(total), dim3(256), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_swap_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_swap_c, dim3(total), dim3(256), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_swap_z, dim3(total), dim3(256), 0, sm, st);
         break;
       case LU_TRSM:
-        if (f32) hipLaunchKernelGGL(k_lu_trsm_c, dim3(total), dim3(256), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_trsm_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_trsm_c, dim3(total), dim3(256), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_trsm_z, dim3(total), dim3(256), 0, sm, st);
         break;
       case LU_GEMM:
-        if (f32) hipLaunchKernelGGL(k_lu_gemm_c, dim3(total), dim3(256), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_gemm_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_gemm_c, dim3(total), dim3(256), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_gemm_z, dim3(total), dim3(256), 0, sm, st);
         break;
       case LU_TSEL:
-        if (f32) hipLaunchKernelGGL(k_lu_tsel_c, dim3(total), dim3(kTsRowsC * kTsLprC), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_tsel_z, dim3(total), dim3(kTsRowsZ * kTsLprZ), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_tsel_c, dim3(total), dim3(kTsRowsC * kTsLprC), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_tsel_z, dim3(total), dim3(kTsRowsZ * kTsLprZ), 0, sm, st);
         break;
       case LU_TFIN:
-        if (f32) hipLaunchKernelGGL(k_lu_tfin_c, dim3(total), dim3(256), 0, ctx->stream, st);
-        else hipLaunchKernelGGL(k_lu_tfin_z, dim3(total), dim3(256), 0, ctx->stream, st);
+        if (f32) hipLaunchKernelGGL(k_lu_tfin_c, dim3(total), dim3(256), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_tfin_z, dim3(total), dim3(256), 0, sm, st);
         break;
     }
     st.ndom = 0;
@@ -827,14 +845,31 @@ int vie_precond_factor(vie_ctx *ctx) {
     LAUNCHCK();
   }
   // right-looking blocked LU of every domain, advanced together panel by panel
+  // With tournament pivoting the next panel's pivot search runs ahead: after
+  // the trailing update of that panel's own columns, its tournament goes to
+  // the side stream while the update of the remaining columns runs, and the
+  // next panel's row swaps wait for it.
+  const bool ahead = ctx->lu_pivot == 0;
+  const int ts_rows = f32 ? kTsRowsC : kTsRowsZ;
+  auto tsel = [&](int kp, hipStream_t stream, bool own) {
+    lu_launch(ctx, LU_TSEL, doms, kp, kp, [&](int d) { return doms[d].n > kp ? (int)nblk(doms[d].n - kp, ts_rows) : 0; },
+              0, 0, 0, stream, own);
+  };
+  // trailing-update tiles of domain d at panel k0: row tiles x column tiles gcol0 .. (gcols <= 0: to the end)
+  auto gemm_blocks = [&](int d, int k0, int gcol0, int gcols) {
+    const int rest = doms[d].n > k0 ? doms[d].n - k0 - std::min(kLuNB, doms[d].n - k0) : 0;
+    const int nt = (int)((rest + 63) / 64);
+    const int nc = gcols > 0 ? std::min(gcols, nt - gcol0) : nt - gcol0;
+    return rest > 0 && nc > 0 ? nt * nc : 0;
+  };
   for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
     auto jb_of = [&](int d) { return std::min(kLuNB, doms[d].n - k0); };
     auto swap_blocks = [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
     if (ctx->lu_pivot == 0) {
       // tournament pivoting: pivot rows by a reduction tree, swap whole rows,
       // then L21 = A21 U11^-1 below the factored top block
-      const int ts_rows = f32 ? kTsRowsC : kTsRowsZ;
-      lu_launch(ctx, LU_TSEL, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n - k0, ts_rows) : 0; });
+      if (k0 == 0) tsel(k0, nullptr, false);
+      else HIPCK(hipStreamWaitEvent(ctx->stream, ctx->ev_ts, 0));   // issued ahead on the side stream
       lu_launch(ctx, LU_SWAP, doms, k0, k0, swap_blocks, 1);
       lu_launch(ctx, LU_TFIN, doms, k0, k0, [&](int d) {
         if (doms[d].n <= k0) return 0;
@@ -854,11 +889,16 @@ int vie_precond_factor(vie_ctx *ctx) {
       const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
       return rest > 0 ? (int)nblk(rest, kColRows) : 0;
     });
-    lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) {
-      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
-      const int nt = (int)nblk(rest, 64);
-      return rest > 0 ? nt * nt : 0;
-    });
+    if (ahead && k0 + kLuNB < maxn) {
+      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
+      HIPCK(hipEventRecord(ctx->ev_la, ctx->stream));
+      HIPCK(hipStreamWaitEvent(ctx->side, ctx->ev_la, 0));
+      tsel(k0 + kLuNB, ctx->side, true);
+      HIPCK(hipEventRecord(ctx->ev_ts, ctx->side));
+      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0); }, 0, 1, 0);
+    } else {
+      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
+    }
     LAUNCHCK();
   }
   for (int d = 0; d < t.ndom; ++d) {

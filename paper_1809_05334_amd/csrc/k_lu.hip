@@ -718,9 +718,10 @@ __device__ __forceinline__ void lu_gemm_body(const LuStep &st) {
   const int64_t ld = D.ld;
   C *__restrict__ A = (C *)D.A;
   const int nt = (n - k0 - jb + 63) / 64;     // tiles per side of A22
+  const int nc = st.gcols > 0 ? min(st.gcols, nt - st.gcol0) : nt - st.gcol0;   // column tiles of this launch
   const int tile = blockIdx.x - D.first_block;
-  const int r0 = k0 + jb + (tile / nt) * 64;  // rows of A22
-  const int c0 = k0 + jb + (tile % nt) * 64;  // cols of A22
+  const int r0 = k0 + jb + (tile / nc) * 64;  // rows of A22
+  const int c0 = k0 + jb + (st.gcol0 + tile % nc) * 64;  // cols of A22
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   Acc cre[2][2], cim[2][2];

@@ -82,6 +82,7 @@ struct LuStep {
   LuDom d[kLuMaxDom];
   int ndom, j, k0;    // current column and panel start
   int all_cols;       // k_lu_swap: swap inside the panel columns too
+  int gcol0, gcols;   // k_lu_gemm: column tiles gcol0 .. gcol0 + gcols - 1 of A22 (gcols <= 0: to the end)
 };
 #define VIE_DECL_LU(T)                       \
   __global__ void k_lu_pivot_##T(LuStep st); \
