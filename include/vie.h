@@ -223,11 +223,18 @@ enum {
                              * captured graphs); 0 (default): one
                              * launch per step.  Use 1 only where no other context's work needs
                              * the device at the same time (a cooperative grid holds every CU). */
-  VIE_OPT_LU_PIVOT = 5      /* row pivoting of the next vie_precond_factor: 0 (default) tournament
+  VIE_OPT_LU_PIVOT = 5,     /* row pivoting of the next vie_precond_factor: 0 (default) tournament
                              * pivoting, the pivot rows of each 64-column panel chosen by a
-                             * reduction tree of partial-pivoting eliminations on 128-row slices;
+                             * reduction tree of partial-pivoting eliminations on 256-row slices;
                              * 1: partial pivoting column by column.  Both give P A = L U; the
                              * factors, and so the rounding of M^{-1} v, differ between them */
+  VIE_OPT_SYM_FILL = 6      /* 1: the workspace bound next also holds a second N x ld copy of Z's
+                             * far part, and every fill at normal incidence (kt = 0, where g_p is
+                             * even in r - r') evaluates each unordered far tetrahedron pair once,
+                             * writing the swapped pair's block there and adding it transposed into
+                             * Z.  Oblique fills do not use it.  Z differs only by rounding.  Set it
+                             * before vie_workspace_bytes / vie_bind_workspace (VIE_ESTATE after);
+                             * 0 (default): no staging */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);
@@ -249,7 +256,8 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out);
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);
 
 /* Timing and work counts of the last vie_fill.  Device times come from HIP
- * events on the context's stream around each kernel family.  far_flops is
+ * events on the context's stream around each kernel family.  far_pairs counts
+ * the tetrahedron pairs the far kernel evaluated; far_flops is
  * the algorithmic work of the far tetrahedron-pair kernel under the cost model
  * stated in the library source (FMA = 2 FLOPs, per-term operation counts of
  * the lattice-sum evaluation with the fitted degrees of this fill). */
@@ -258,6 +266,7 @@ typedef struct {
   int64_t far_pairs, near_pairs, face_pairs, far_launches;
   double point_pair_flops, far_flops;
   int nimg, nmode;
+  int far_symmetric;   /* 1: the far pairs were evaluated once per unordered pair (VIE_OPT_SYM_FILL) */
 } vie_fill_stats;
 int vie_get_fill_stats(const vie_ctx *ctx, vie_fill_stats *out);
 

@@ -35,7 +35,7 @@ struct Region {
 struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
+  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
       plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
@@ -77,6 +77,8 @@ struct vie_ctx {
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
   int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
   int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
+  int sym_fill = 0;                 // the next bind reserves the transposed-block staging of normal-incidence fills
+  bool last_sym = false;            // the last fill used it
   bool capturing = false;           // a graph capture is in progress on the stream
   int coop_grid = 0;                // co-resident thread blocks of the cooperative kernel
   struct CoopPlan {
@@ -141,7 +143,7 @@ int fail(vie_ctx *c, int code, const char *fmt, ...) {
 unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
 Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf, int precision,
-                   int64_t near_nnz) {
+                   int64_t near_nnz, bool sym_fill) {
   Layout L;
   size_t off = 0;
   auto put = [&](Region &r, size_t bytes) {
@@ -176,6 +178,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   L.ld = (N + 7) / 8 * 8;
   const bool mixed = precision == VIE_MIXED_FP32;
   put(L.Z, (mixed ? 8 : 16) * (size_t)N * L.ld);
+  // staging for the transposed far blocks of a normal-incidence fill (VIE_OPT_SYM_FILL)
+  if (sym_fill) put(L.Zt, (mixed ? 8 : 16) * (size_t)N * L.ld);
   put(L.nrow, mixed ? 8 * (size_t)(N + 1) : 0);
   put(L.ncol, mixed ? 4 * (size_t)near_nnz : 0);
   put(L.nval, mixed ? 16 * (size_t)near_nnz : 0);
@@ -455,7 +459,8 @@ size_t vie_workspace_bytes(const vie_ctx *cctx, int precision, int restart) {
     ensure_near_pattern(ctx);
     nnz = (int64_t)ctx->ncol.size();
   }
-  return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf, precision, nnz)
+  return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf, precision, nnz,
+                     ctx->sym_fill != 0)
       .total;
 }
 
@@ -477,7 +482,7 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
     ensure_near_pattern(ctx);
     nnz = (int64_t)ctx->ncol.size();
   }
-  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz);
+  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz, ctx->sym_fill != 0);
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
   if (ctx->pin_piv_n < t.N) {
     HIPCK(hipStreamSynchronize(ctx->stream));   // no upload of the permutation in flight
@@ -633,6 +638,18 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   if (ctx->nface)
     hipLaunchKernelGGL(k_sigma, dim3(nblk(ctx->nface, 256)), dim3(256), 0, ctx->stream, ctx->nface,
                        ctx->ptr<int32_t>(L.ctp), ctx->ptr<int32_t>(L.ctm), (const dz *)kappa, sigma);
+  // At normal incidence (kt = 0) the lattice sum is even in the separation:
+  // with the staging bound (VIE_OPT_SYM_FILL) each unordered far pair is
+  // evaluated once and also yields the swapped pair's block, gathered in Zt
+  // and added transposed after the far launches.
+  const bool sym = L.Zt.bytes > 0 && kx == 0.0 && ky == 0.0;
+  ctx->last_sym = sym;
+  ZOut zt = zout(ctx);
+  if (sym) {
+    if (ctx->precision == VIE_MIXED_FP32) zt.Zs = ctx->ptr<fz>(L.Zt);
+    else zt.Z = ctx->ptr<dz>(L.Zt);
+    hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Zt), (int64_t)(L.Zt.bytes / 16));
+  }
   // clear Z (and the near part): the fill accumulates into it
   hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z), (int64_t)(L.Z.bytes / 16));
   if (L.nval.bytes)
@@ -643,14 +660,28 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   // far tet pairs (all colour pairs), then touching pairs, then face pairs;
   // events between the groups time each kernel family
   HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
+  int far_launches = 0;
   for (int ct = 0; ct < C; ++ct)
     for (int cs = 0; cs < C; ++cs) {
+      if (sym && cs < ct) continue;   // covered by the launch of (cs, ct)
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
+      const int mode = !sym ? 0 : (ct == cs ? 2 : 1);
       hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                          colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
-                         (const dz *)gsrc, (const dz *)kappa, k0sq9, zo);
+                         (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
       LAUNCHCK();
+      ++far_launches;
     }
+  if (sym) {
+    const dim3 tg2(nblk(t.N, 32), nblk(t.N, 32));
+    if (ctx->precision == VIE_MIXED_FP32)
+      hipLaunchKernelGGL(k_transpose_add_c, tg2, dim3(256), 0, ctx->stream, ctx->ptr<fz>(L.Z),
+                         (const fz *)ctx->ptr<fz>(L.Zt), (int64_t)t.N, L.ld);
+    else
+      hipLaunchKernelGGL(k_transpose_add_z, tg2, dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z),
+                         (const dz *)ctx->ptr<dz>(L.Zt), (int64_t)t.N, L.ld);
+    LAUNCHCK();
+  }
   HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
   for (int g = 0; g < C * C; ++g) {
     const int np = ctx->near_off[g + 1] - ctx->near_off[g];
@@ -699,7 +730,8 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   // rsqrt counted as 8, x, t, Clenshaw, scale, accumulate); spectral set-up
   // 212 (four sincos counted as 40 each, phase powers); per mode 13 + 3 deg
   // (twice the Clenshaw for a complex order); final phase 6.  Per tet pair:
-  // 16 point pairs + 1200 for moments and the 16-entry scatter.
+  // 16 point pairs + 1200 for moments and the 16-entry scatter (+ 1200 for
+  // the swapped pair's scatter when one evaluation serves both).
   double pp = 12 + 212 + 6;
   const PgfTable &tb = *ctx->tab;
   for (int i = 0; i < tb.nimg; ++i) pp += 29 + 3 * tb.img[i].deg;
@@ -716,12 +748,14 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   st.t_far_ms = mfar;
   st.t_near_ms = mnear;
   st.t_face_ms = mface;
-  st.far_pairs = t.nt * t.nt - nnear;
+  // pairs evaluated (near-ness is symmetric and includes every self pair)
+  st.far_pairs = sym ? (t.nt * t.nt - nnear) / 2 : t.nt * t.nt - nnear;
   st.near_pairs = nnear;
   st.face_pairs = (int64_t)t.nt * ctx->nface + (int64_t)ctx->nhalf * t.nt + (int64_t)ctx->nhalf * ctx->nface;
-  st.far_launches = C * C;
+  st.far_launches = far_launches;
+  st.far_symmetric = sym ? 1 : 0;
   st.point_pair_flops = pp;
-  st.far_flops = (double)st.far_pairs * (16.0 * pp + 1200.0);
+  st.far_flops = (double)st.far_pairs * (16.0 * pp + (sym ? 2400.0 : 1200.0));
   st.nimg = tb.nimg;
   st.nmode = nmodes;
   ctx->state = S_FILLED;
@@ -1726,6 +1760,11 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "LU pivoting: 0 (tournament) or 1 (partial)");
       ctx->lu_pivot = value;
       return VIE_OK;
+    case VIE_OPT_SYM_FILL:
+      if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "symmetric fill: 0 or 1");
+      if (ctx->state >= S_BOUND) return fail(ctx, VIE_ESTATE, "VIE_OPT_SYM_FILL is set before the workspace is bound");
+      ctx->sym_fill = value;
+      return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
       if (value != 4 && value != 8) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 4 or 8");
       if (value != ctx->trsv_rw) drop_graphs(ctx);
@@ -1743,6 +1782,7 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value) {
     case VIE_OPT_TRSV_ROWS: *value = ctx->trsv_rw; return VIE_OK;
     case VIE_OPT_TRSV_COOP: *value = ctx->trsv_coop; return VIE_OK;
     case VIE_OPT_LU_PIVOT: *value = ctx->lu_pivot; return VIE_OK;
+    case VIE_OPT_SYM_FILL: *value = ctx->sym_fill; return VIE_OK;
   }
   return VIE_EINVAL;
 }

@@ -98,7 +98,9 @@ __device__ __forceinline__ void moments_zero(Moments &M) {
   for (int d = 0; d < 3; ++d) M.mu[d] = M.mv[d] = mk(0, 0);
 }
 
-// Scatter the 16 face-pair contributions of tet pair (T, S) into Z.
+// Scatter the 16 face-pair contributions of tet pair (T, S) into Z (TRANS:
+// entry (m, n) goes to (n, m) of the output).
+template <bool TRANS = false>
 __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, const TetGeom &gs,
                                            const TetFace *__restrict__ t2f, int T, int S,
                                            const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
@@ -126,25 +128,34 @@ __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, 
       for (int d = 0; d < 3; ++d) I = I - qv[l][d] * M.mu[d];
       I = I + dot3(pk, qv[l]) * M.m0;
       const dz v = M.m0 - k0sq9 * I;
-      zput(out, row, col[l], (ak * bl[l]) * v, near);
+      if (TRANS) zput(out, col[l], row, (ak * bl[l]) * v, near);
+      else zput(out, row, col[l], (ak * bl[l]) * v, near);
     }
   }
 }
 
 // Far tet pairs: 4 x 4 product rule.  One wave = one test tet x 64 source tets.
+// At normal incidence the lattice sum is even in the separation (the phases
+// e^{-j kt.rho} are all 1), so the pair's moments also give those of the
+// swapped pair (S, T): sym > 0 writes that block too (see the declaration).
 __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                 const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                 const int32_t *__restrict__ test_list, int ntest,
                                                 const int32_t *__restrict__ src_list, int nsrc,
                                                 const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
-                                                const dz *__restrict__ kappa, double k0sq9, ZOut out) {
+                                                const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
+                                                int sym) {
   extern __shared__ double s_tab[];
+  // one list against itself: a block whose source positions all lie at or
+  // below its test positions has nothing to do (the whole block returns)
+  if (sym == 2 && (int)blockIdx.x * 64 + 63 <= (int)blockIdx.y * 4) return;
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
   const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int si = blockIdx.x * 64 + (threadIdx.x & 63);
   if (ti >= ntest || si >= nsrc) return;
+  if (sym == 2 && si <= ti) return;
   const int T = uniform(test_list[ti]);
   const int S = src_list[si];
   const TetGeom &gt = tg[T];
@@ -201,6 +212,45 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
   asm volatile("" : "+v"(tgs));
   const TetGeom gs = *tgs;
   scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, false);
+  if (sym) {
+    // (S, T): test offsets and source offsets trade places
+    Moments Ms;
+    Ms.m0 = M.m0;
+    Ms.muv = M.muv;
+    for (int d = 0; d < 3; ++d) {
+      Ms.mu[d] = M.mv[d];
+      Ms.mv[d] = M.mu[d];
+    }
+    scatter_tt<true>(Ms, gs, gt, t2f, S, T, alpha, gsrc, kappa, k0sq9, outT, false);
+  }
+}
+
+// Z[i][j] += Zt[j][i]: 32 x 32 tiles through shared memory, both sides read
+// and written along rows.  In FP32 the sum is formed in FP64 and rounded once.
+template <typename C>
+__device__ __forceinline__ void transpose_add_body(C *__restrict__ Z, const C *__restrict__ Zt, int64_t N, int64_t ld) {
+  __shared__ C tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  // tile of Zt rows j0.., columns i0..
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (j < N && i < N) tile[r][tx] = Zt[j * ld + i];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < N && j < N) {
+      const C a = Z[i * ld + j], b = tile[tx][r];
+      Z[i * ld + j] = cx<C>::make((double)a.re + (double)b.re, (double)a.im + (double)b.im);
+    }
+  }
+}
+__global__ __launch_bounds__(256) void k_transpose_add_z(dz *Z, const dz *Zt, int64_t N, int64_t ld) {
+  transpose_add_body(Z, Zt, N, ld);
+}
+__global__ __launch_bounds__(256) void k_transpose_add_c(fz *Z, const fz *Zt, int64_t N, int64_t ld) {
+  transpose_add_body(Z, Zt, N, ld);
 }
 
 // Touching tet pairs: 14-point outer rule on T; per touching image the closed

@@ -24,9 +24,15 @@ __global__ void k_prep(int64_t nt, const TetFace *t2f, const TetGeom *tg, const 
                        double kx, double ky, double a, double b, dz *alpha, dz *gsrc, dz *kappa, dz *inv_eps);
 __global__ void k_sigma(int nc, const int32_t *ctp, const int32_t *ctm, const dz *kappa, dz *sigma);
 __global__ void k_zero(dz *p, int64_t n);
+// sym: 0 every pair of the two lists, writing Z; 1 the same, also writing the
+// transposed pair's block into outT (stored untransposed); 2 (one list twice)
+// only pairs with source position > test position, both blocks as for 1.
 __global__ void k_tt_far(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                          const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc, const dz *alpha,
-                         const dz *gsrc, const dz *kappa, double k0sq9, ZOut out);
+                         const dz *gsrc, const dz *kappa, double k0sq9, ZOut out, ZOut outT, int sym);
+// Z[i][j] += Zt[j][i] for i, j < N (row-major, leading dimension ld)
+__global__ void k_transpose_add_z(dz *Z, const dz *Zt, int64_t N, int64_t ld);
+__global__ void k_transpose_add_c(fz *Z, const fz *Zt, int64_t N, int64_t ld);
 __global__ void k_tt_near(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                           const int32_t *lt, const int32_t *ls, const int32_t *lmask, int npairs, const dz *alpha,
                           const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, ZOut out);

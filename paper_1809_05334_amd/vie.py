@@ -46,7 +46,7 @@ class FillStats(C.Structure):
     _fields_ = [("t_fill_ms", C.c_double), ("t_far_ms", C.c_double), ("t_near_ms", C.c_double),
                 ("t_face_ms", C.c_double), ("far_pairs", C.c_int64), ("near_pairs", C.c_int64),
                 ("face_pairs", C.c_int64), ("far_launches", C.c_int64), ("point_pair_flops", C.c_double),
-                ("far_flops", C.c_double), ("nimg", C.c_int), ("nmode", C.c_int)]
+                ("far_flops", C.c_double), ("nimg", C.c_int), ("nmode", C.c_int), ("far_symmetric", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -55,6 +55,7 @@ class FillStats(C.Structure):
 _LIB = None
 
 VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS, VIE_OPT_TRSV_COOP, VIE_OPT_LU_PIVOT = 1, 2, 3, 4, 5
+VIE_OPT_SYM_FILL = 6
 
 
 class Tuning(C.Structure):

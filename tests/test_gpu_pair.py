@@ -139,3 +139,23 @@ def test_pair_matches_oracle(vie):
         xo, it, hist, ok = OV.gmres_right_block(Zo, OV.rhs(t, wave, p), t.domain_ranges, tol=1e-10, restart=30)
         assert ok and info[p]["converged"] and abs(info[p]["iters"] - it) <= 1
         assert np.linalg.norm(s.read_solution(p) - xo) < 1e-8 * np.linalg.norm(xo)
+
+
+def test_pair_with_more_domains_than_one_launch_carries(vie):
+    """Ten domains (8 x 8 x 4 slab split by x slice and z half): the paired
+    triangular solves and block LU run in two launches per step."""
+    m = W.slab_mesh(nx=8, ny=8, nz=4)
+    c = W.centroids(m.verts, m.tets)
+    xs = np.digitize(c[:, 0], [20.0, 40.0, 60.0, 80.0])
+    m.tet_domain = (2 * xs + (c[:, 2] > 25.0)).astype(np.int32)
+    m.ndom = 10
+    for prec in (vie.VIE_FP64, vie.VIE_MIXED_FP32):
+        s = vie.Solver()
+        s.upload_mesh(m)
+        s.bind(prec, 30)
+        s.fill(600.0, 0.3, 0.2, W.slab_eps(m, 3.0 + 0.2j))
+        s.factor()
+        assert len(s.domain_ranges()) == 10
+        ref = singles(vie, s, 1e-10, 300, 30)
+        assert ref[0][0]["converged"] and ref[1][0]["converged"]
+        check_pair(vie, s, ref, 1e-10, 300, 30)
