@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-iter", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="Arnoldi steps per captured HIP graph (0: plain launches)")
     ap.add_argument("--no-sym-fill", action="store_true",
                     help="evaluate every ordered far pair (no use of the kt = 0 symmetry)")
     ap.add_argument("--solve", choices=["pair", "single"], default="pair",
@@ -139,6 +141,8 @@ def main():
             # normal incidence: one evaluation per unordered far pair (staging bound with the workspace)
             s.set_option(vie.VIE_OPT_SYM_FILL, 1)
         ws_bytes = s.bind(precision, args.restart)
+        if args.graph_steps:
+            s.set_option(vie.VIE_OPT_GRAPH_STEPS, args.graph_steps)
         lat, stages, fills, results = [], [], [], []
         tuning = {}
 
@@ -247,7 +251,7 @@ def main():
         "config": {"workload": "plasmonic OSC cell 200x200 nm, Ag sphere r=20 nm, N=%d, 400-800 nm sweep, "
                                "normal incidence, TE+TM per step" % N,
                    "unknowns": N, "tets": int(mesh.nt), "restart": args.restart, "tol": args.tol,
-                   "solve": args.solve, "sym_fill": not args.no_sym_fill,
+                   "solve": args.solve, "sym_fill": not args.no_sym_fill, "graph_steps": args.graph_steps,
                    "workspace_gb": mixed["ws_bytes"] / 1e9},
         "latency_ms": {"p50": float(np.percentile(mixed["lat"], 50)), "p99": float(np.percentile(mixed["lat"], 99))},
         "fill_gflops": far_tflops * 1e3,

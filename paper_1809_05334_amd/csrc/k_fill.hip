@@ -376,22 +376,24 @@ __device__ dz pair_tet_face(const double *__restrict__ P, const QuadRules *__res
   const double wf = f.area / 3.0;
   dz acc = mk(0, 0);
   if (!mask) {
-#pragma unroll 1
-    for (int i = 0; i < 4; ++i) {
-      double r[3];
+    // one face point against the tet's four points per lattice-sum call
+    double tp[4][3];
+    for (int i = 0; i < 4; ++i)
       for (int d = 0; d < 3; ++d) {
         double s = 0;
         for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
-        r[d] = s;
+        tp[i][d] = s;
       }
-      double sep[3][3];
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+      double sep[4][3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sep[j][d] = r[d] - fp[j][d];
-      dz g[3];
-      pgf_eval_w<false, 3>(P, sep, 0, g);
-      acc = acc + (g[0] + g[1]) + g[2];
+        for (int d = 0; d < 3; ++d) sep[i][d] = tp[i][d] - fp[j][d];
+      dz g[4];
+      pgf_eval_w<false, 4>(P, sep, 0, g);
+      acc = acc + ((g[0] + g[1]) + (g[2] + g[3]));
     }
     return (0.25 * gt.vol * wf) * acc;
   }
