@@ -33,7 +33,8 @@ struct Region {
 };
 
 struct Layout {
-  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, quad, pgf, pack;
+  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, near_tf, near_ft, quad, pgf,
+      pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
   Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
       plans;
@@ -72,6 +73,7 @@ struct vie_ctx {
   std::vector<double> pack;         // packed lattice-sum table of the last fill
   int packlen = 0;
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
+  std::vector<int32_t> tf_off, ft_off;   // offsets (in pairs) of the touching tet-face / face-tet lists per colour
   int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
   int trsv_rw = 4;                  // triangular-solve update rows per wave (4, 8)
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
@@ -142,6 +144,12 @@ int fail(vie_ctx *c, int code, const char *fmt, ...) {
 
 unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
+size_t nested_size(const std::vector<std::vector<int32_t>> &v) {
+  size_t s = 0;
+  for (const auto &x : v) s += x.size();
+  return s;
+}
+
 Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf, int precision,
                    int64_t near_nnz, bool sym_fill) {
   Layout L;
@@ -166,6 +174,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.near_t, 4 * std::max<int64_t>(1, nnear));
   put(L.near_s, 4 * std::max<int64_t>(1, nnear));
   put(L.near_m, 4 * std::max<int64_t>(1, nnear));
+  put(L.near_tf, 4 * std::max<size_t>(1, nested_size(t.near_tf)));
+  put(L.near_ft, 4 * std::max<size_t>(1, nested_size(t.near_ft)));
   put(L.quad, sizeof(QuadRules));
   put(L.pgf, sizeof(PgfTable));
   put(L.pack, 8 * (size_t)kMaxPack);
@@ -577,6 +587,19 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   rc |= up(L.near_t, nt_.data(), 4 * nt_.size());
   rc |= up(L.near_s, ns_.data(), 4 * ns_.size());
   rc |= up(L.near_m, nm_.data(), 4 * nm_.size());
+  std::vector<int32_t> tf_, ft_;
+  ctx->tf_off.assign(C + 1, 0);
+  ctx->ft_off.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    ctx->tf_off[c] = (int32_t)(tf_.size() / 2);
+    ctx->ft_off[c] = (int32_t)(ft_.size() / 2);
+    tf_.insert(tf_.end(), t.near_tf[c].begin(), t.near_tf[c].end());
+    ft_.insert(ft_.end(), t.near_ft[c].begin(), t.near_ft[c].end());
+  }
+  ctx->tf_off[C] = (int32_t)(tf_.size() / 2);
+  ctx->ft_off[C] = (int32_t)(ft_.size() / 2);
+  rc |= up(L.near_tf, tf_.data(), 4 * tf_.size());
+  rc |= up(L.near_ft, ft_.data(), 4 * ft_.size());
   rc |= up(L.quad, &ctx->quad, sizeof(QuadRules));
   if (precision == VIE_MIXED_FP32) {
     rc |= up(L.nrow, ctx->nrow.data(), 8 * ctx->nrow.size());
@@ -697,10 +720,17 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   HIPCK(hipEventRecord(evn, ctx->stream));
   if (ctx->nface) {
     const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
+    // per test colour: the far pairs, then the touching ones from their list
+    // (one lane each, so no wave mixes the two kinds)
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
       hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
                          t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, zo);
+      const int np = ctx->tf_off[ct + 1] - ctx->tf_off[ct];
+      if (np)
+        hipLaunchKernelGGL(k_tet_face_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
+                           (const int32_t *)ctx->ptr<int32_t>(L.near_tf) + 2 * (int64_t)ctx->tf_off[ct], np, fg,
+                           (const dz *)alpha, (const dz *)sigma, zo);
       LAUNCHCK();
     }
     if (ctx->nhalf) {
@@ -709,6 +739,12 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
         hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr,
                            fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
                            (const dz *)gsrc, (const dz *)kappa, zo);
+        const int np = ctx->ft_off[cs + 1] - ctx->ft_off[cs];
+        if (np)
+          hipLaunchKernelGGL(k_face_tet_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, fg,
+                             ctx->ptr<int32_t>(L.half), tg, t2f,
+                             (const int32_t *)ctx->ptr<int32_t>(L.near_ft) + 2 * (int64_t)ctx->ft_off[cs], np,
+                             (const dz *)gsrc, (const dz *)kappa, zo);
         LAUNCHCK();
       }
       hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_,

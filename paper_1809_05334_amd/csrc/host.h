@@ -39,6 +39,12 @@ struct MeshTopology {
   std::vector<std::vector<int32_t>> color_tets;   // per colour, increasing
   // touching tet pairs, grouped by (colour(T), colour(T')): test, source, image mask
   std::vector<std::vector<int32_t>> near_t, near_s, near_mask;
+  // touching (tet T, surface-charge face) pairs grouped by colour(T): T and the
+  // face's position in `charged`, interleaved
+  std::vector<std::vector<int32_t>> near_tf;
+  // touching (half-SWG face, tet S) pairs grouped by colour(S): the face's
+  // position among the half-SWG faces of `charged`, and S, interleaved
+  std::vector<std::vector<int32_t>> near_ft;
 };
 
 // Returns "" on success, else an error message.

@@ -543,7 +543,18 @@ __device__ dz pair_face_face(const double *__restrict__ P, const QuadRules *__re
   return acc;
 }
 
-// test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0
+// test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0.
+// Far pairs only: the touching ones come from the host list (k_tet_face_near).
+__device__ __forceinline__ void tet_face_pair(const double *__restrict__ P, const QuadRules *__restrict__ qr,
+                                              const TetGeom &gt, const TetFace *__restrict__ t2f, int T,
+                                              const FaceGeom &f, int fi, const dz *__restrict__ alpha,
+                                              const dz *__restrict__ sigma, const ZOut &out) {
+  int mask;
+  const dz m0 = pair_tet_face(P, qr, gt, f, mask);
+  const dz sm = sigma[fi] * m0;
+  for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, mask != 0);
+}
+
 __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
@@ -560,13 +571,37 @@ __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ 
   const int T = uniform(test_list[ti]);
   const TetGeom &gt = tg[T];
   const FaceGeom f = fg[fi];
-  int mask;
-  const dz m0 = pair_tet_face(s_tab, qr, gt, f, mask);
-  const dz sm = sigma[fi] * m0;
-  for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, mask != 0);
+  if (touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3)) return;
+  tet_face_pair(s_tab, qr, gt, t2f, T, f, fi, alpha, sigma, out);
 }
 
-// half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0
+// touching (test tet, surface-charge face) pairs of one test colour, one lane each
+__global__ __launch_bounds__(256, 2) void k_tet_face_near(const double *__restrict__ pack, int packlen,
+                                                       const QuadRules *__restrict__ qr, const TetGeom *__restrict__ tg,
+                                                       const TetFace *__restrict__ t2f, const int32_t *__restrict__ pairs,
+                                                       int npairs, const FaceGeom *__restrict__ fg,
+                                                       const dz *__restrict__ alpha, const dz *__restrict__ sigma,
+                                                       ZOut out) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npairs) return;
+  const int T = pairs[2 * i], fi = pairs[2 * i + 1];
+  const FaceGeom f = fg[fi];
+  tet_face_pair(s_tab, qr, tg[T], t2f, T, f, fi, alpha, sigma, out);
+}
+
+// half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0.
+// Far pairs only: the touching ones come from the host list (k_face_tet_near).
+__device__ __forceinline__ void face_tet_pair(const double *__restrict__ P, const QuadRules *__restrict__ qr,
+                                              const FaceGeom &f, const TetGeom &gs, const TetFace *__restrict__ t2f,
+                                              int S, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                              const ZOut &out) {
+  int mask;
+  const dz m0 = pair_face_tet(P, qr, f, gs, mask) * kappa[S];
+  for (int l = 0; l < 4; ++l) zput(out, f.unknown, t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0, mask != 0);
+}
+
 __global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
                                                   int nhalf, const TetGeom *__restrict__ tg,
@@ -583,9 +618,26 @@ __global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ 
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const int S = src_list[si];
   const TetGeom gs = tg[S];
-  int mask;
-  const dz m0 = pair_face_tet(s_tab, qr, f, gs, mask) * kappa[S];
-  for (int l = 0; l < 4; ++l) zput(out, f.unknown, t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0, mask != 0);
+  if (touch_mask(f.canon, f.off, 3, gs.canon, gs.off, 4)) return;
+  face_tet_pair(s_tab, qr, f, gs, t2f, S, gsrc, kappa, out);
+}
+
+// touching (half-SWG test face, source tet) pairs of one source colour, one lane each
+__global__ __launch_bounds__(256, 2) void k_face_tet_near(const double *__restrict__ pack, int packlen,
+                                                       const QuadRules *__restrict__ qr, const FaceGeom *__restrict__ fg,
+                                                       const int32_t *__restrict__ half_list,
+                                                       const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                       const int32_t *__restrict__ pairs, int npairs,
+                                                       const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                       ZOut out) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= npairs) return;
+  const int hi = pairs[2 * i], S = pairs[2 * i + 1];
+  const FaceGeom f = fg[half_list[hi]];
+  const TetGeom gs = tg[S];
+  face_tet_pair(s_tab, qr, f, gs, t2f, S, gsrc, kappa, out);
 }
 
 // half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0

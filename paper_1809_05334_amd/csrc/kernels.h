@@ -42,6 +42,14 @@ __global__ void k_tet_face(const double *pack, int packlen, const QuadRules *qr,
 __global__ void k_face_tet(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                            int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
                            const dz *gsrc, const dz *kappa, ZOut out);
+// touching pairs from the host lists (lane = pair): (tet, surface-charge face
+// index) and (half-SWG face position, tet), interleaved
+__global__ void k_tet_face_near(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg,
+                                const TetFace *t2f, const int32_t *pairs, int npairs, const FaceGeom *fg,
+                                const dz *alpha, const dz *sigma, ZOut out);
+__global__ void k_face_tet_near(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg,
+                                const int32_t *half_list, const TetGeom *tg, const TetFace *t2f, const int32_t *pairs,
+                                int npairs, const dz *gsrc, const dz *kappa, ZOut out);
 __global__ void k_face_face(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                             int nhalf, int nface, const dz *sigma, ZOut out);
 __global__ void k_rhs(int64_t N, const int32_t *utet, const int32_t *uk, const TetGeom *tg, const QuadRules *qr,

@@ -305,6 +305,31 @@ std::string build_topology(MeshTopology &t, const double *verts, int64_t nv, con
       t.near_mask[g].push_back(mask);
     }
   }
+
+  // ---- touching (tet, surface-charge face) and (half-SWG face, tet) pairs:
+  // the tets around the face's vertices (sharing a canonical vertex is
+  // touching under some image)
+  t.near_tf.assign(C, {});
+  t.near_ft.assign(C, {});
+  int32_t hidx = 0;
+  for (size_t fi = 0; fi < t.charged.size(); ++fi) {
+    const int32_t f = t.charged[fi];
+    const bool half = t.tminus[f] < 0;
+    cand.clear();
+    for (int j = 0; j < 3; ++j)
+      for (int32_t e : around[t.canon[t.face_vid[3 * f + j]]]) cand.push_back(e);
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int32_t e : cand) {
+      t.near_tf[t.color[e]].push_back(e);
+      t.near_tf[t.color[e]].push_back((int32_t)fi);
+      if (half) {
+        t.near_ft[t.color[e]].push_back(hidx);
+        t.near_ft[t.color[e]].push_back(e);
+      }
+    }
+    if (half) ++hidx;
+  }
   return "";
 }
 
