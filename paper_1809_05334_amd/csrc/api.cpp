@@ -762,15 +762,17 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   (void)hipEventDestroy(evn);
   ctx->t_fill = ms;
   // algorithmic work of the far tet-pair kernel (cost model, FMA = 2 FLOPs):
-  // per point pair: separation and wrap 12; per image 29 + 3 deg (X, Y, R^2,
-  // rsqrt counted as 8, x, t, Clenshaw, scale, accumulate); spectral set-up
-  // 212 (four sincos counted as 40 each, phase powers); per mode 13 + 3 deg
-  // (twice the Clenshaw for a complex order); final phase 6.  Per tet pair:
+  // per point pair: separation and wrap 12; per image 27 + 3 deg (X, Y, R^2,
+  // rsqrt counted as 8, the fit argument from R, Clenshaw, scale,
+  // accumulate); spectral set-up 212 (four sincos counted as 40 each, phase
+  // powers; 132 at normal incidence, where the two sincos of kt vanish); per
+  // mode 13 + 3 deg (twice the Clenshaw for a complex order); final phase 6.
+  // Per tet pair:
   // 16 point pairs + 1200 for moments and the 16-entry scatter (+ 1200 for
   // the swapped pair's scatter when one evaluation serves both).
-  double pp = 12 + 212 + 6;
+  double pp = 12 + ((kx == 0.0 && ky == 0.0) ? 132 : 212) + 6;
   const PgfTable &tb = *ctx->tab;
-  for (int i = 0; i < tb.nimg; ++i) pp += 29 + 3 * tb.img[i].deg;
+  for (int i = 0; i < tb.nimg; ++i) pp += 27 + 3 * tb.img[i].deg;
   int nmodes = 0;
   for (int i = 0; i < kPgfTerms; ++i)
     if (tb.mode[i].deg >= 0) {

@@ -177,7 +177,7 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
 #pragma unroll 1
   for (int i = 0; i < nimg; ++i) {
     const double *R = P + off;
-    const double xa = R[0], xs = R[1], cre = R[2], cim = R[3];
+    const double ts = R[0], t0 = R[1], cre = R[2], cim = R[3];   // t = ts R + t0
     const int im = pint(R[4]), in = pint(R[5]), K = pint(R[6]);
     off += pint(R[7]);
     double t[W], sc[W];
@@ -191,15 +191,15 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
         const int um = im - im0[w], un = in - in0[w];
         touch[w] = um >= -1 && um <= 1 && un >= -1 && un <= 1 && ((mask >> ((um + 1) * 3 + (un + 1))) & 1);
       }
-      double rinv, x;
+      double rinv, Rw;
       if (TOUCH) {   // a touching image can sit at R = 0 (its H fit is evaluated at x = 0)
         rinv = rsqrt(R2);
-        x = R2 > 0.0 ? R2 * rinv * E : 0.0;
+        Rw = R2 > 0.0 ? R2 * rinv : 0.0;
       } else {       // separations of non-touching elements never vanish
         rinv = rsqrt_pos(R2);
-        x = R2 * rinv * E;
+        Rw = R2 * rinv;
       }
-      t[w] = fma(x - xa, xs, -1.0);
+      t[w] = fma(Rw, ts, t0);
       sc[w] = touch[w] ? E : rinv;
     }
     // W interleaved Clenshaw recurrences on the F coefficients
@@ -248,18 +248,24 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
   // phases e^{-j k_tpq . Delta_t} of each separation by recurrence in p and q
   double tw[W], kre[W], kim[W];
   dz erow[W], bx[W], by[W];   // erow: phase of (p, q = -4); steps in p and in q
+  const bool kt0 = P[pk::KX] == 0.0 && P[pk::KY] == 0.0;   // normal incidence: e^{-j kt.Delta} = 1
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     tw[w] = fma(dz2[w] * E * E, P[pk::WS], -1.0);
     double s0, c0, s1, c1;
     sincos(-P[pk::TPA] * dx[w], &s1, &c1);
     bx[w] = mk(c1, s1);
-    sincos(-P[pk::KX] * dx[w], &s0, &c0);
-    const dz ex = mk(c0, s0) * conjz(bx[w] * bx[w] * bx[w] * bx[w]);  // p = -4
     sincos(-P[pk::TPB] * dy[w], &s1, &c1);
     by[w] = mk(c1, s1);
-    sincos(-P[pk::KY] * dy[w], &s0, &c0);
-    erow[w] = ex * (mk(c0, s0) * conjz(by[w] * by[w] * by[w] * by[w]));  // (p, q) = (-4, -4)
+    const dz bx4 = conjz(bx[w] * bx[w] * bx[w] * bx[w]), by4 = conjz(by[w] * by[w] * by[w] * by[w]);
+    if (kt0) {
+      erow[w] = bx4 * by4;   // (p, q) = (-4, -4)
+    } else {
+      sincos(-P[pk::KX] * dx[w], &s0, &c0);
+      const dz ex = mk(c0, s0) * bx4;   // p = -4
+      sincos(-P[pk::KY] * dy[w], &s0, &c0);
+      erow[w] = ex * (mk(c0, s0) * by4);
+    }
     kre[w] = 0.0;
     kim[w] = 0.0;
   }

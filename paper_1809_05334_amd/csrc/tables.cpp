@@ -490,7 +490,8 @@ void pack_pgf_table(const PgfTable &tab, std::vector<double> &out) {
     const PgfImage &im = tab.img[i];
     const int K = pad4(im.deg), HK = im.hdeg >= 0 ? pad4(im.hdeg) : -1;
     const size_t start = out.size();
-    out.insert(out.end(), {im.xa, im.xs, im.cre, im.cim, ibits(im.m), ibits(im.n), ibits(K), 0.0});
+    // the fit's argument t = (x - xa) xs - 1 with x = E R, stored as t = R (E xs) - (xa xs + 1)
+    out.insert(out.end(), {tab.E * im.xs, -(im.xa * im.xs + 1.0), im.cre, im.cim, ibits(im.m), ibits(im.n), ibits(K), 0.0});
     for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= im.deg ? im.f[k] : 0.0);
     if (HK >= 0) {
       out.insert(out.end(), {ibits(HK), 0.0, 0.0, 0.0});
