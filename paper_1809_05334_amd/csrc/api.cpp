@@ -663,8 +663,9 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
                        ctx->ptr<int32_t>(L.ctp), ctx->ptr<int32_t>(L.ctm), (const dz *)kappa, sigma);
   // At normal incidence (kt = 0) the lattice sum is even in the separation:
   // with the staging bound (VIE_OPT_SYM_FILL) each unordered far pair is
-  // evaluated once and also yields the swapped pair's block, gathered in Zt
-  // and added transposed after the far launches.
+  // evaluated once and also yields the swapped pair's block, gathered in Zt;
+  // likewise each far (tet, half-SWG face) pair yields the (face, tet) entry.
+  // Zt is added transposed after the face kernels.
   const bool sym = L.Zt.bytes > 0 && kx == 0.0 && ky == 0.0;
   ctx->last_sym = sym;
   ZOut zt = zout(ctx);
@@ -695,16 +696,6 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
       LAUNCHCK();
       ++far_launches;
     }
-  if (sym) {
-    const dim3 tg2(nblk(t.N, 32), nblk(t.N, 32));
-    if (ctx->precision == VIE_MIXED_FP32)
-      hipLaunchKernelGGL(k_transpose_add_c, tg2, dim3(256), 0, ctx->stream, ctx->ptr<fz>(L.Z),
-                         (const fz *)ctx->ptr<fz>(L.Zt), (int64_t)t.N, L.ld);
-    else
-      hipLaunchKernelGGL(k_transpose_add_z, tg2, dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z),
-                         (const dz *)ctx->ptr<dz>(L.Zt), (int64_t)t.N, L.ld);
-    LAUNCHCK();
-  }
   HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
   for (int g = 0; g < C * C; ++g) {
     const int np = ctx->near_off[g + 1] - ctx->near_off[g];
@@ -725,7 +716,8 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
       hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
-                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma, zo);
+                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma,
+                         (const dz *)gsrc, (const dz *)kappa, zo, zt, sym ? 1 : 0);
       const int np = ctx->tf_off[ct + 1] - ctx->tf_off[ct];
       if (np)
         hipLaunchKernelGGL(k_tet_face_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
@@ -736,9 +728,10 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     if (ctx->nhalf) {
       for (int cs = 0; cs < C; ++cs) {
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-        hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr,
-                           fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
-                           (const dz *)gsrc, (const dz *)kappa, zo);
+        if (!sym)   // (with sym the far pairs came from k_tet_face)
+          hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
+                             qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
+                             (const dz *)gsrc, (const dz *)kappa, zo);
         const int np = ctx->ft_off[cs + 1] - ctx->ft_off[cs];
         if (np)
           hipLaunchKernelGGL(k_face_tet_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, fg,
@@ -751,6 +744,16 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
                          pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, zo);
       LAUNCHCK();
     }
+  }
+  if (sym) {
+    const dim3 tg2(nblk(t.N, 32), nblk(t.N, 32));
+    if (ctx->precision == VIE_MIXED_FP32)
+      hipLaunchKernelGGL(k_transpose_add_c, tg2, dim3(256), 0, ctx->stream, ctx->ptr<fz>(L.Z),
+                         (const fz *)ctx->ptr<fz>(L.Zt), (int64_t)t.N, L.ld);
+    else
+      hipLaunchKernelGGL(k_transpose_add_z, tg2, dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z),
+                         (const dz *)ctx->ptr<dz>(L.Zt), (int64_t)t.N, L.ld);
+    LAUNCHCK();
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipEventSynchronize(ctx->ev1));

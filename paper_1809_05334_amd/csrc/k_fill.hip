@@ -555,12 +555,21 @@ __device__ __forceinline__ void tet_face_pair(const double *__restrict__ P, cons
   for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, mask != 0);
 }
 
+// At normal incidence the lattice sum is even in the separation, and the far
+// rules of the two face kernels take the same 4 x 3 point pairs with the same
+// weights, so the (tet T, face F) value M0 is also that of (F as a half-SWG
+// test face, T as source).  With swap set, each far pair with a half-SWG face
+// writes that entry too, Z[m_F, n_l(T)] -= gsrc_Tl kappa_T M0, at the
+// transposed position of outT (rows of T's unknowns, columns of faces: the
+// same conflict-free pattern as the tet-face entries); the staging copy is
+// added transposed after the fill's other kernels.
 __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
                                                   const FaceGeom *__restrict__ fg, int nface,
                                                   const dz *__restrict__ alpha, const dz *__restrict__ sigma,
-                                                  ZOut out) {
+                                                  const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                  ZOut out, ZOut outT, int swap) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
@@ -572,7 +581,14 @@ __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ 
   const TetGeom &gt = tg[T];
   const FaceGeom f = fg[fi];
   if (touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3)) return;
-  tet_face_pair(s_tab, qr, gt, t2f, T, f, fi, alpha, sigma, out);
+  int mask;
+  const dz m0 = pair_tet_face(s_tab, qr, gt, f, mask);
+  const dz sm = sigma[fi] * m0;
+  for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, false);
+  if (swap && f.half) {
+    const dz km = m0 * kappa[T];
+    for (int l = 0; l < 4; ++l) zput(outT, t2f[4 * T + l].unknown, f.unknown, mk(0, 0) - gsrc[4 * T + l] * km, false);
+  }
 }
 
 // touching (test tet, surface-charge face) pairs of one test colour, one lane each

@@ -36,9 +36,11 @@ __global__ void k_transpose_add_c(fz *Z, const fz *Zt, int64_t N, int64_t ld);
 __global__ void k_tt_near(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                           const int32_t *lt, const int32_t *ls, const int32_t *lmask, int npairs, const dz *alpha,
                           const dz *gsrc, const dz *kappa, const dz *inv_eps, double k0sq9, ZOut out);
+// swap = 1 (normal incidence, staging bound): a far pair with a half-SWG
+// face also gives the (face, tet) entry, written transposed into outT
 __global__ void k_tet_face(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                            const int32_t *test_list, int ntest, const FaceGeom *fg, int nface, const dz *alpha,
-                           const dz *sigma, ZOut out);
+                           const dz *sigma, const dz *gsrc, const dz *kappa, ZOut out, ZOut outT, int swap);
 __global__ void k_face_tet(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                            int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
                            const dz *gsrc, const dz *kappa, ZOut out);

@@ -6,6 +6,8 @@ tetrahedron pair (T, S) also give those of (S, T).  The symmetric fill must
 give the oracle's Z to the usual tolerance (|dZ| <= 1e-10 max(|Z_ij|, 1e-5
 max|Z|)), the plain fill's Z to rounding (FP64) or to the FP32 rounding of
 far entries (mixed), the same solutions, and evaluate half the far pairs.
+The far (half-SWG face, tet) entries come from the tet-face kernel's
+evaluation of the same pair, written transposed into the staging copy.
 Oblique fills ignore the option and give the plain fill's Z bit for bit."""
 import numpy as np
 import pytest
@@ -51,6 +53,9 @@ def test_symmetric_fill_matches_oracle_and_plain_fill(vie, case):
     t = OT.build(m.verts, m.tets, m.tet_domain, m.ndom, m.a, m.b)
     Zo = OV.assemble(t, OV.make_wave(lam, 0.0, 0.0), eps)
     scale = np.abs(Zo).max()
+    # the structure's top and bottom faces are half-SWGs: their rows take the
+    # swapped (face, tet) entries of the tet-face kernel
+    assert t.is_half.sum() > 0
     for prec in (vie.VIE_FP64, vie.VIE_MIXED_FP32):
         sp = solver(vie, m, prec, False)
         ss = solver(vie, m, prec, True)
