@@ -240,7 +240,7 @@ int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);
 
 typedef struct {
-  double matvec_ms[3];   /* per product, rows per wave 2, 4, 8 */
+  double matvec_ms[6];   /* per product, rows per wave 2, 4, 8: one vector, then two */
   double apply_ms[4];    /* per preconditioner apply, rows per wave 4 and 8: one vector, then two */
   int matvec_rows, trsv_rows;   /* the picks, now set on the context */
 } vie_tuning;

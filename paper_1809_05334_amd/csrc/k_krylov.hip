@@ -308,18 +308,23 @@ __global__ void k_arn_begin(const dz *__restrict__ V, int64_t ldv, const int *__
   if (k < N) vin[k] = V[(int64_t)(*jd) * ldv + k];
 }
 
-// partial inner products with V_0 .. V_j (k_dots with nv = j + 1)
+// partial inner products with V_0 .. V_j (k_dots with nv = j + 1): block
+// (x, y) sums chunk x of N for basis vectors 8 y .. 8 y + 7; the grid's y
+// extent covers the largest j (blocks past V_j return at once), so every
+// group of eight runs at the same time and the launch is the same for every j
 __global__ __launch_bounds__(256) void k_dots_j(const dz *__restrict__ V, int64_t ldv, const int *__restrict__ jd,
                                                 const dz *__restrict__ w, int64_t N, dz *__restrict__ part) {
-  // eight basis vectors per pass: their loads are in flight together and one
-  // pair of barriers serves the eight block sums (each sum as for one vector)
+  // eight basis vectors per block: their loads are in flight together and one
+  // barrier serves the eight block sums (each sum as for one vector)
   constexpr int G = 8;
   __shared__ dz red[G][4];
   const int nv = *jd + 1;
+  const int i0 = blockIdx.y * G;
+  if (i0 >= nv) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk, hi = min<int64_t>(N, lo + chunk);
-  for (int i0 = 0; i0 < nv; i0 += G) {
+  {
     double sr[G], si[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) sr[g] = si[g] = 0.0;
@@ -346,7 +351,6 @@ __global__ __launch_bounds__(256) void k_dots_j(const dz *__restrict__ V, int64_
     __syncthreads();
     if (tid < G && i0 + tid < nv)
       part[(int64_t)blockIdx.x * nv + i0 + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
-    __syncthreads();
   }
 }
 

@@ -59,7 +59,7 @@ VIE_OPT_SYM_FILL = 6
 
 
 class Tuning(C.Structure):
-    _fields_ = [("matvec_ms", C.c_double * 3), ("apply_ms", C.c_double * 4),
+    _fields_ = [("matvec_ms", C.c_double * 6), ("apply_ms", C.c_double * 4),
                 ("matvec_rows", C.c_int), ("trsv_rows", C.c_int)]
 
     def as_dict(self):
