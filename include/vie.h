@@ -208,9 +208,10 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta_host, int64_t n, vie_c128 *ou
 int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z);
 
 /* ---------------------------------------------------------------- tuning
- * Launch shapes, graph capture and the pivoting of the block LU.  Apart from
- * VIE_OPT_LU_PIVOT none of them changes a result: every variant computes the
- * same sums in the same order. */
+ * Launch shapes, graph capture, the pivoting of the block LU and the choice
+ * of preconditioner.  Apart from VIE_OPT_LU_PIVOT and VIE_OPT_PRECOND none of
+ * them changes a result: every variant computes the same sums in the same
+ * order. */
 enum {
   VIE_OPT_GRAPH_STEPS = 1,  /* Arnoldi steps per captured HIP graph, 0 = plain launches (default);
                              * residual estimates are read back once per graph launch, so a solve
@@ -228,13 +229,19 @@ enum {
                              * reduction tree of partial-pivoting eliminations on 256-row slices;
                              * 1: partial pivoting column by column.  Both give P A = L U; the
                              * factors, and so the rounding of M^{-1} v, differ between them */
-  VIE_OPT_SYM_FILL = 6      /* 1: the workspace bound next also holds a second N x ld copy of Z's
+  VIE_OPT_SYM_FILL = 6,     /* 1: the workspace bound next also holds a second N x ld copy of Z's
                              * far part, and every fill at normal incidence (kt = 0, where g_p is
                              * even in r - r') evaluates each unordered far tetrahedron pair once,
                              * writing the swapped pair's block there and adding it transposed into
                              * Z.  Oblique fills do not use it.  Z differs only by rounding.  Set it
                              * before vie_workspace_bytes / vie_bind_workspace (VIE_ESTATE after);
                              * 0 (default): no staging */
+  VIE_OPT_PRECOND = 7       /* preconditioner of the next vie_solve / vie_solve_pair: 0 (default)
+                             * the block-diagonal M of the last vie_precond_factor (Sec. 2.3,
+                             * Eq. 6); 1: none, M = I (GMRES on Z x = b, the reference against
+                             * which Sec. 3 compares the block preconditioner), for which a
+                             * completed fill suffices.  The iterations and the rounding of x
+                             * differ between the two */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);

@@ -79,6 +79,9 @@ struct vie_ctx {
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
   int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
   int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
+  int precond = 0;                  // 0: block-diagonal LU preconditioner, 1: none (M = I)
+  bool factored = false;            // the factors belong to the current fill (a solve with M = I
+                                    // reaches S_SOLVED without them)
   int sym_fill = 0;                 // the next bind reserves the transposed-block staging of normal-incidence fills
   bool last_sym = false;            // the last fill used it
   bool capturing = false;           // a graph capture is in progress on the stream
@@ -436,6 +439,7 @@ int vie_mesh_upload(vie_ctx *ctx, const double *verts_nm, int64_t nv, const int3
     return fail(ctx, VIE_EINVAL, "mesh: %s", e.c_str());
   }
   ctx->state = S_MESH;
+  ctx->factored = false;
   ctx->ws = nullptr;
   return VIE_OK;
 }
@@ -611,6 +615,7 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   HIPCK(hipMemsetAsync(ctx->ws + L.ttcnt.off, 0, L.ttcnt.bytes, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));   // host staging vectors go out of scope
   ctx->state = S_BOUND;
+  ctx->factored = false;
   return VIE_OK;
 }
 
@@ -800,6 +805,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   st.nimg = tb.nimg;
   st.nmode = nmodes;
   ctx->state = S_FILLED;
+  ctx->factored = false;
   return VIE_OK;
 }
 
@@ -1020,6 +1026,7 @@ int vie_precond_factor(vie_ctx *ctx) {
   }
   HIPCK(hipMemcpyAsync(perm, hp, 4 * (size_t)t.N, hipMemcpyHostToDevice, ctx->stream));
   ctx->state = S_FACTORED;
+  ctx->factored = true;
   return VIE_OK;
 }
 
@@ -1271,7 +1278,11 @@ int arnoldi_step(vie_ctx *ctx, int mask) {
     hipLaunchKernelGGL(k_arn_begin, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, (const dz *)ctx->ptr<dz>(K.V),
                        L.ldv, (const int *)ctx->ptr<int>(K.jd), vi, N);
   }
-  if (int rc = apply_minv_n(ctx, np, vin, z, tmp, u)) return rc;
+  if (ctx->precond == 0) {
+    if (int rc = apply_minv_n(ctx, np, vin, z, tmp, u)) return rc;
+  } else {
+    for (int i = 0; i < np; ++i) z[i] = const_cast<dz *>(vin[i]);   // M = I: the product takes V_j itself
+  }
   if (np == 2) {
     const MvVecs v{{z[0], z[1]}, {nullptr, nullptr}, {w[0], w[1]}};
     if (int rc = matvec2(ctx, v)) return rc;
@@ -1464,7 +1475,11 @@ int gmres(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int restart)
       rv.y[nc] = ctx->ptr<dz>(K.vr);
       ++nc;
     }
-    if (int rc = apply_minv_n(ctx, nc, wv, uv, tv, zv)) return rc;
+    if (ctx->precond == 0) {
+      if (int rc = apply_minv_n(ctx, nc, wv, uv, tv, zv)) return rc;
+    } else {
+      for (int q = 0; q < nc; ++q) uv[q] = const_cast<dz *>(wv[q]);   // M = I: x += V y
+    }
     for (int q = 0; q < nc; ++q)
       hipLaunchKernelGGL(k_axpy, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, const_cast<dz *>(rv.x[q]),
                          (const dz *)uv[q], N);
@@ -1535,7 +1550,9 @@ int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int rest
 }  // namespace
 
 int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
-  if (int r = check(ctx, S_FACTORED, "vie_solve")) return r;
+  if (int r = check(ctx, S_FILLED, "vie_solve")) return r;
+  if (!ctx->precond && !ctx->factored)
+    return fail(ctx, VIE_ESTATE, "vie_solve: the block preconditioner needs vie_precond_factor after the fill");
   if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
   if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
   Gmres P[1];
@@ -1545,7 +1562,9 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
 }
 
 int vie_solve_pair(vie_ctx *ctx, double tol, int max_iter, int restart, vie_solve_info *info) {
-  if (int r = check(ctx, S_FACTORED, "vie_solve_pair")) return r;
+  if (int r = check(ctx, S_FILLED, "vie_solve_pair")) return r;
+  if (!ctx->precond && !ctx->factored)
+    return fail(ctx, VIE_ESTATE, "vie_solve_pair: the block preconditioner needs vie_precond_factor after the fill");
   if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
   Gmres P[2];
   P[0].k = 0;
@@ -1768,6 +1787,7 @@ int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec) {
 
 int vie_precond_apply(vie_ctx *ctx, const vie_c128 *v, vie_c128 *z) {
   if (int r = check(ctx, S_FACTORED, "vie_precond_apply")) return r;
+  if (!ctx->factored) return fail(ctx, VIE_ESTATE, "vie_precond_apply needs vie_precond_factor after the fill");
   if (!v || !z) return fail(ctx, VIE_EINVAL, "null vector");
   HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;
@@ -1806,6 +1826,11 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       if (ctx->state >= S_BOUND) return fail(ctx, VIE_ESTATE, "VIE_OPT_SYM_FILL is set before the workspace is bound");
       ctx->sym_fill = value;
       return VIE_OK;
+    case VIE_OPT_PRECOND:
+      if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "preconditioner: 0 (block-diagonal LU) or 1 (none)");
+      if (value != ctx->precond) drop_graphs(ctx);
+      ctx->precond = value;
+      return VIE_OK;
     case VIE_OPT_TRSV_ROWS:
       if (value != 4 && value != 8) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 4 or 8");
       if (value != ctx->trsv_rw) drop_graphs(ctx);
@@ -1824,12 +1849,14 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value) {
     case VIE_OPT_TRSV_COOP: *value = ctx->trsv_coop; return VIE_OK;
     case VIE_OPT_LU_PIVOT: *value = ctx->lu_pivot; return VIE_OK;
     case VIE_OPT_SYM_FILL: *value = ctx->sym_fill; return VIE_OK;
+    case VIE_OPT_PRECOND: *value = ctx->precond; return VIE_OK;
   }
   return VIE_EINVAL;
 }
 
 int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   if (int r = check(ctx, S_FACTORED, "vie_autotune")) return r;
+  if (!ctx->factored) return fail(ctx, VIE_ESTATE, "vie_autotune needs vie_precond_factor after the fill");
   if (reps < 1) return fail(ctx, VIE_EINVAL, "reps must be >= 1");
   HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;

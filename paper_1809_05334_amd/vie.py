@@ -56,6 +56,7 @@ _LIB = None
 
 VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS, VIE_OPT_TRSV_COOP, VIE_OPT_LU_PIVOT = 1, 2, 3, 4, 5
 VIE_OPT_SYM_FILL = 6
+VIE_OPT_PRECOND = 7
 
 
 class Tuning(C.Structure):

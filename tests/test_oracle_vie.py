@@ -158,3 +158,66 @@ def test_three_domain_cell(small_osc):
     # TM (E along x) at normal incidence are mirror images
     assert np.max(np.abs(res[0][0] - res[1][0])) < 1e-11
     assert abs(res[0][1] - res[1][1]) < 1e-11 and abs(res[0][2] - res[1][2]) < 1e-11
+
+
+# ---- GMRES without a preconditioner (blocks = []: M = I), the reference the
+# block preconditioner is compared against in Sec. 3 (Figs. 2-3).  Pins that
+# hold for any correct GMRES, independent of the oracle's own arithmetic:
+# on I + (rank k) the Krylov space closes after k + 1 steps, so GMRES stops
+# there with the exact solution; within one cycle the residual estimate never
+# grows (minimal residual over nested spaces) and equals the true residual.
+
+def _rank_k_plus_identity(n, k, seed):
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))
+    Vh = rng.standard_normal((k, n)) + 1j * rng.standard_normal((k, n))
+    return np.eye(n) + 0.1 * U @ Vh
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_gmres_no_precond_rank_k_closes_in_k_plus_1(k):
+    n = 40
+    A = _rank_k_plus_identity(n, k, seed=10 + k)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it, hist, ok = V.gmres_right_block(A, b, [], tol=1e-12, restart=50)
+    assert ok and it <= k + 1, (it, hist)
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) < 1e-10 * np.linalg.norm(xs)
+
+
+def test_gmres_no_precond_residual_monotone_and_true():
+    n = 30
+    rng = np.random.default_rng(3)
+    A = np.eye(n) * 3 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it, hist, ok = V.gmres_right_block(A, b, [], tol=1e-11, restart=n)
+    assert ok and it <= n
+    h = np.array(hist)
+    assert np.all(np.diff(h) <= 1e-14 * h[0]), h
+    r = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert r <= 1e-11 * 1.01 and abs(r - h[-1]) < 1e-12
+
+
+def test_block_preconditioner_beats_none_on_multidomain_cell():
+    """Sec. 2.3 / Sec. 3: on a three-domain cell with a metal particle the
+    block preconditioner needs fewer GMRES iterations than none, and both
+    reach the same solution (Eq. 8 difference at the solver tolerance)."""
+    xs = np.array([0.0, 12.0, 20.0, 28.0, 40.0])
+    zs = np.array([0.0, 20.0, 30.0, 40.0])
+    verts, tets = W.brick_grid_mesh(xs, xs, zs)
+    c = W.centroids(verts, tets)
+    dom = np.where(c[:, 2] < 20.0, W.DOM_ACTIVE, W.DOM_SPACER).astype(np.int32)
+    dom[np.sum((c - [20.0, 20.0, 30.0]) ** 2, 1) <= 8.0 ** 2] = W.DOM_METAL
+    m = W.Mesh(verts, tets, dom, 3, 40.0, 40.0, (xs, xs, zs))
+    topo = build(m)
+    lam = 400.0
+    wave = V.make_wave(lam, 0.0, 0.0)
+    Z = V.assemble(topo, wave, W.osc_eps(m, lam))
+    b = V.rhs(topo, wave, 0)
+    xp, ip, _, okp = V.gmres_right_block(Z, b, topo.domain_ranges, tol=1e-10, restart=60, maxit=3000)
+    xn, inn, _, okn = V.gmres_right_block(Z, b, [], tol=1e-10, restart=60, maxit=3000)
+    assert okp and okn and ip < inn, (ip, inn)
+    xs_ = V.solve_lu(Z, b)
+    for x in (xp, xn):
+        assert np.linalg.norm(x - xs_) < 1e-7 * np.linalg.norm(xs_)
