@@ -177,6 +177,17 @@ int vie_absorption(vie_ctx *ctx, double *absorptance_per_domain, double *R, doub
  * vie_solve or vie_solve_pair; VIE_ESTATE if that solve did not cover it. */
 int vie_absorption_pol(vie_ctx *ctx, int polarisation, double *absorptance_per_domain, double *R, double *T);
 
+/* Each tetrahedron's share of the absorptance of the last solution of
+ * polarisation `polarisation` (-1: the last solve's), the term of Eq. 7 for
+ * one tetrahedron with the same normalisation, so that the shares of a
+ * domain's tetrahedra add up to its absorptance (up to summation order):
+ *   per_tet[T] = k0 Im(1/eps_T) int_T |D/eps0|^2 dV / (cos th a b).
+ * Divided by the tetrahedron's volume it is the absorption density whose
+ * maps Sec. 3 shows (Fig. 5).  per_tet [number of tetrahedra], host memory,
+ * mesh order.  VIE_ESTATE before a solve or for a polarisation the last solve
+ * did not cover. */
+int vie_absorption_per_tet(vie_ctx *ctx, int polarisation, double *per_tet);
+
 const char *vie_last_error(const vie_ctx *ctx);
 
 /* ---------------------------------------------------------------- diagnostics

@@ -504,6 +504,24 @@ def absorptance(topo, wave, eps_in, x):
     return out * wave.k0 / (np.cos(wave.theta) * topo.a * topo.b)
 
 
+def absorptance_per_tet(topo, wave, eps_in, x):
+    """Each tetrahedron's term of Eq. 7 (Sec. 3) with the normalisation of
+    absorptance(): k0 (-Im eps_T)/|eps_T|^2 I_T |D~|^2 dV / (cos th a b), so the
+    terms of a domain add up to its absorptance.  Divided by V_T it is the
+    absorption density mapped in Sec. 3 (Fig. 5)."""
+    eps = internal_eps(eps_in)
+    c = tet_field_coeffs(topo, wave, x)
+    out = np.zeros(len(topo.tets))
+    for t in range(len(topo.tets)):
+        v4 = topo.verts[topo.tets[t]]
+        s = 0.0 + 0.0j
+        for k in range(4):
+            for l in range(4):
+                s += c[t, k] * np.conj(c[t, l]) * _tet_quad_form(v4, v4[k], v4[l])
+        out[t] = (-eps[t].imag) / abs(eps[t]) ** 2 * s.real
+    return out * wave.k0 / (np.cos(wave.theta) * topo.a * topo.b)
+
+
 def reflect_transmit(topo, wave, eps_in, x, pol, P=4):
     """Floquet-mode reflectance and transmittance (sum over propagating orders)
     of the radiated field of P~ = kappa D~ plus the incident wave."""

@@ -43,7 +43,7 @@ struct Layout {
   struct Kry {
     Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, jd, rhist;
   } K[2];
-  Region apart, kv, idx;
+  Region apart, atet, kv, idx;
   size_t total = 0;
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
@@ -265,6 +265,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     put(k.scal, 64);
   }
   put(L.apart, 8 * (size_t)nblk(nt, 256) * std::max(6 * 2 * 32, t.ndom));
+  put(L.atet, 8 * (size_t)std::max<int64_t>(1, nt));
   put(L.kv, 8 * 3 * 2 * 32);
   put(L.idx, 16 * (size_t)N);
   L.total = off;
@@ -1580,6 +1581,31 @@ int vie_absorption(vie_ctx *ctx, double *absorptance, double *R, double *T) {
   return vie_absorption_pol(ctx, ctx->last_pol, absorptance, R, T);
 }
 
+int vie_absorption_per_tet(vie_ctx *ctx, int pol, double *per_tet) {
+  if (int r = check(ctx, S_SOLVED, "vie_absorption_per_tet")) return r;
+  if (pol < 0) pol = ctx->last_pol;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE, VIE_TM or -1");
+  if (ctx->sol_k[pol] < 0) return fail(ctx, VIE_ESTATE, "the last solve did not cover this polarisation");
+  if (!per_tet) return fail(ctx, VIE_EINVAL, "null output");
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const dz *xsol = ctx->ptr<dz>(L.K[ctx->sol_k[pol]].vx);
+  const unsigned nb = nblk(t.nt, 256);
+  double *dev = ctx->ptr<double>(L.atet);
+  hipLaunchKernelGGL(k_absorb, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, t.ndom, ctx->ptr<TetGeom>(L.tg),
+                     ctx->ptr<TetFace>(L.t2f), ctx->ptr<int32_t>(L.dom), ctx->ptr<QuadRules>(L.quad),
+                     (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), xsol,
+                     ctx->ptr<double>(L.apart), dev);
+  LAUNCHCK();
+  HIPCK(hipMemcpyAsync(per_tet, dev, 8 * (size_t)t.nt, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  const double k0 = 2 * M_PI / ctx->lambda;
+  const double scale = k0 / (std::cos(ctx->theta) * t.a * t.b);
+  for (int64_t i = 0; i < t.nt; ++i) per_tet[i] *= scale;
+  return VIE_OK;
+}
+
 int vie_absorption_pol(vie_ctx *ctx, int pol, double *absorptance, double *R, double *T) {
   if (int r = check(ctx, S_SOLVED, "vie_absorption_pol")) return r;
   if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
@@ -1595,7 +1621,7 @@ int vie_absorption_pol(vie_ctx *ctx, int pol, double *absorptance, double *R, do
   hipLaunchKernelGGL(k_absorb, dim3(nb), dim3(256), 0, ctx->stream, (int64_t)t.nt, t.ndom, ctx->ptr<TetGeom>(L.tg),
                      ctx->ptr<TetFace>(L.t2f), ctx->ptr<int32_t>(L.dom), ctx->ptr<QuadRules>(L.quad),
                      (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), xsol,
-                     part);
+                     part, nullptr);
   hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, ctx->stream, (const double *)part, (int)nb, t.ndom, out);
   LAUNCHCK();
   std::vector<double> h(t.ndom);

@@ -24,12 +24,13 @@ __device__ __forceinline__ double bsum(double v, double *red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// part[blockIdx.x * ndom + d] = sum over this block's tets in domain d
+// part[blockIdx.x * ndom + d] = sum over this block's tets in domain d;
+// per_tet[t] (if given) = tet t's own term
 __global__ __launch_bounds__(256) void k_absorb(int64_t nt, int ndom, const TetGeom *__restrict__ tg,
                                                 const TetFace *__restrict__ t2f, const int32_t *__restrict__ dom,
                                                 const QuadRules *__restrict__ qr, const dz *__restrict__ gsrc,
                                                 const dz *__restrict__ inv_eps, const dz *__restrict__ x,
-                                                double *__restrict__ part) {
+                                                double *__restrict__ part, double *__restrict__ per_tet) {
   __shared__ double red[4];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double val = 0.0;
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(256) void k_absorb(int64_t nt, int ndom, const TetG
     }
     val = s * inv_eps[t].im;   // (-Im eps)/|eps|^2 = Im(1/eps)
     d = dom[t];
+    if (per_tet) per_tet[t] = val;
   }
   for (int dd = 0; dd < ndom; ++dd) {
     const double v = bsum(d == dd ? val : 0.0, red);

@@ -192,8 +192,10 @@ __global__ void k_jset(int *jd, int v);
 __global__ void k_jinc(int *jd);
 
 // outputs (k_absorb.hip)
+// (per_tet, nullable: each tetrahedron's term before the domain sums)
 __global__ void k_absorb(int64_t nt, int ndom, const TetGeom *tg, const TetFace *t2f, const int32_t *dom,
-                         const QuadRules *qr, const dz *gsrc, const dz *inv_eps, const dz *x, double *part);
+                         const QuadRules *qr, const dz *gsrc, const dz *inv_eps, const dz *x, double *part,
+                         double *per_tet);
 __global__ void k_project(int64_t nt, const TetGeom *tg, const TetFace *t2f, const QuadRules *qr, const dz *gsrc,
                           const dz *kappa, const dz *x, int nk, const double *kv, double *part);
 __global__ void k_reduce_cols(const double *part, int nblk, int width, double *out);

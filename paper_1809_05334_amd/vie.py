@@ -84,6 +84,7 @@ _SIGS = {
     "vie_solve_pair": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(SolveInfo)]),
     "vie_absorption": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_absorption_pol": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_absorption_per_tet": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
     "vie_last_error": (C.c_char_p, [C.c_void_p]),
     "vie_export_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_read_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -243,6 +244,14 @@ class Solver:
         else:
             self._ck(self.lib.vie_absorption_pol(self.h, int(pol), _p(A), rp, tp))
         return (A, R.value, T.value) if want_rt else A
+
+    def absorption_per_tet(self, pol=None):
+        """Each tetrahedron's share of the absorptance (mesh order) of the last
+        solution, or of polarisation `pol`; a domain's shares add up to its
+        absorptance."""
+        out = np.zeros(self.nt)
+        self._ck(self.lib.vie_absorption_per_tet(self.h, -1 if pol is None else int(pol), _p(out)))
+        return out
 
     # -------------------------------------------------------------- diagnostics
     def read_Z(self, rows, cols):

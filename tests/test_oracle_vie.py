@@ -221,3 +221,31 @@ def test_block_preconditioner_beats_none_on_multidomain_cell():
     xs_ = V.solve_lu(Z, b)
     for x in (xp, xn):
         assert np.linalg.norm(x - xs_) < 1e-7 * np.linalg.norm(xs_)
+
+
+# ---- per-tetrahedron absorption (Eq. 7 term by term; the maps of Fig. 5).
+# Pins: the terms of each domain add up to absorptance() (itself pinned on the
+# Fresnel slab and the energy balance); a lossless domain absorbs exactly
+# nothing; a passive lossy one nowhere absorbs a negative amount.
+
+def test_absorptance_per_tet_sums_and_signs():
+    xs = np.array([0.0, 12.0, 20.0, 28.0, 40.0])
+    zs = np.array([0.0, 20.0, 30.0, 40.0])
+    verts, tets = W.brick_grid_mesh(xs, xs, zs)
+    c = W.centroids(verts, tets)
+    dom = np.where(c[:, 2] < 20.0, W.DOM_ACTIVE, W.DOM_SPACER).astype(np.int32)
+    dom[np.sum((c - [20.0, 20.0, 30.0]) ** 2, 1) <= 8.0 ** 2] = W.DOM_METAL
+    m = W.Mesh(verts, tets, dom, 3, 40.0, 40.0, (xs, xs, zs))
+    topo = build(m)
+    lam = 450.0
+    eps = np.array(W.osc_eps(m, lam), complex)
+    eps[dom == W.DOM_SPACER] = eps[dom == W.DOM_SPACER].real   # a lossless domain
+    wave = V.make_wave(lam, 0.2, 0.3)
+    Z = V.assemble(topo, wave, eps)
+    x = V.solve_lu(Z, V.rhs(topo, wave, 1))
+    per = V.absorptance_per_tet(topo, wave, eps, x)
+    A = V.absorptance(topo, wave, eps, x)
+    for d in range(m.ndom):
+        assert abs(per[dom == d].sum() - A[d]) <= 1e-13 * max(abs(A).max(), 1e-30), d
+    assert np.all(per[dom == W.DOM_SPACER] == 0.0)
+    assert np.all(per[dom != W.DOM_SPACER] >= 0.0) and per.max() > 0
