@@ -1,4 +1,4 @@
-"""The timed workload at full size: the plasmonic cell (200 x 200 nm,
+"""Full-size cases.  The timed workload: the plasmonic cell (200 x 200 nm,
 18,432 tetrahedra, N = 37,376) filled as the bench fills it (normal incidence,
 one evaluation per unordered far pair), on both precision paths.
 
@@ -80,3 +80,39 @@ def test_full_size_cell_as_benched(vie, cell, precision):
     assert abs(info[0]["iters"] - info[1]["iters"]) <= (0 if precision == "fp64" else 2)
     assert np.max(np.abs(out[0][0] - out[1][0])) < sym * out[0][0].max()
     assert abs(out[0][1] - out[1][1]) < sym and abs(out[0][2] - out[1][2]) < sym
+
+
+def test_precision_form_at_full_size(vie):
+    """The precision form of the cell (3.33 nm over the particle and spacer,
+    38,400 tetrahedra, N = 77,600) at one oblique incidence: the mixed path's
+    sampled Z entries against the oracle, then absorptance per domain, R and T
+    of both polarisations against the FP64 path on the same inputs."""
+    m = W.plasmonic_cell_fine_mesh()
+    t = OT.build(m.verts, m.tets, m.tet_domain, m.ndom, m.a, m.b)
+    assert t.N == 77600
+    lam, th, ph = 550.0, np.deg2rad(40.0), np.deg2rad(45.0)
+    eps = W.osc_eps(m, lam)
+    wave = OV.make_wave(lam, th, ph)
+    rng = np.random.default_rng(11)
+    rows = rng.choice(t.N, 16, replace=False)
+    cols = np.unique(np.concatenate([rows, t.t2f[t.tplus[rows[:6]]].ravel(), rng.choice(t.N, 16, replace=False)]))
+    Zo = OV.assemble(t, wave, eps, rows=rows, cols=cols)
+    out = {}
+    for name, prec in (("mixed", vie.VIE_MIXED_FP32), ("fp64", vie.VIE_FP64)):
+        s = vie.Solver()
+        s.upload_mesh(m)
+        s.bind(prec, 150)
+        s.fill(lam, th, ph, eps)
+        if name == "mixed":
+            r, c = np.meshgrid(rows, cols, indexing="ij")
+            Zg = s.read_Z(r.ravel(), c.ravel()).reshape(len(rows), len(cols))
+            assert np.max(np.abs(Zg - Zo)) < 1e-6 * np.abs(Zo).max()
+        s.factor()
+        info = s.solve_pair(tol=1e-8, max_iter=3000, restart=150)
+        assert all(i["converged"] for i in info), info
+        out[name] = [s.absorption(pol=p) for p in (0, 1)]
+        s.close()   # free this path's workspace before the next
+    for pol in (0, 1):
+        (Am, Rm, Tm), (Af, Rf, Tf) = out["mixed"][pol], out["fp64"][pol]
+        d = max(np.max(np.abs(Am - Af)), abs(Rm - Rf), abs(Tm - Tf))
+        assert d < 1e-6, (pol, d)
