@@ -1031,6 +1031,8 @@ int vie_precond_factor(vie_ctx *ctx) {
   return VIE_OK;
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------- solve
 namespace {
 
@@ -1549,6 +1551,8 @@ int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int rest
 }
 
 }  // namespace
+
+extern "C" {
 
 int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
   if (int r = check(ctx, S_FILLED, "vie_solve")) return r;
