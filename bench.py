@@ -121,7 +121,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the method's units of parallel work "
-              "(sweep points, cells) shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+              "(sweep points, cells) shard across GPUs without communication: run one process per GPU "
+              "on its share of the sweep", file=sys.stderr)
         sys.exit(2)
 
     import torch
