@@ -1,7 +1,7 @@
 """Plain FP64 CPU oracle of the periodic SWG volume-integral-equation method.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports or calls this
-package: only the tests, the graft smoke check and the bench's CPU-baseline leg
+package: only the tests, the smoke check in __graft_entry__.py and the bench's CPU-baseline leg
 do.  It shares no code with the HIP library (no kernels, tables, helpers or
 constant generators); the only common inputs are the seeded meshes and
 permittivities from the input-generator module.
