@@ -67,3 +67,40 @@ def slab_rta_matrix(eps, d, lam, theta, pol):
     R = abs(r) ** 2
     T = abs(t) ** 2
     return R, T, 1.0 - R - T
+
+
+def multilayer_rta(eps_layers, d_layers, lam, theta, pol):
+    """Planar stack in vacuum, layers listed in the order the incident wave
+    meets them.  Characteristic matrix of each layer (as slab_rta_matrix),
+    r and t from their product; the absorbed fraction of each layer is the
+    drop of the normal Poynting flux Re(U V*) across it, with the tangential
+    fields (U, V) carried up from the exit side, (U, V) = (t, Y0 t).
+    Returns R, T and the list of per-layer absorptions (they add up to
+    1 - R - T)."""
+    k0 = 2 * np.pi / lam
+    s2 = np.sin(theta) ** 2
+    kz0 = k0 * np.sqrt(1 - s2 + 0j)
+    Y0 = kz0 / k0 if pol == 0 else k0 / kz0
+    mats = []
+    for eps, d in zip(eps_layers, d_layers):
+        kz = k0 * np.sqrt(complex(eps) - s2)
+        if kz.imag < 0:
+            kz = -kz
+        Y = kz / k0 if pol == 0 else complex(eps) * k0 / kz
+        bb = kz * d
+        mats.append(np.array([[np.cos(bb), -1j * np.sin(bb) / Y], [-1j * Y * np.sin(bb), np.cos(bb)]]))
+    M = np.eye(2, dtype=complex)
+    for Mj in mats:
+        M = M @ Mj
+    den = (M[0, 0] + M[0, 1] * Y0) * Y0 + (M[1, 0] + M[1, 1] * Y0)
+    r = ((M[0, 0] + M[0, 1] * Y0) * Y0 - (M[1, 0] + M[1, 1] * Y0)) / den
+    t = 2 * Y0 / den
+    uv = np.array([t, Y0 * t])
+    flux = [(uv[0] * np.conj(uv[1])).real]          # below the last layer
+    for Mj in reversed(mats):
+        uv = Mj @ uv
+        flux.append((uv[0] * np.conj(uv[1])).real)  # above layer j
+    flux = flux[::-1]                                # above layer 0, ..., below the last
+    s_inc = Y0.real
+    absorbed = [(flux[j] - flux[j + 1]) / s_inc for j in range(len(mats))]
+    return abs(r) ** 2, abs(t) ** 2, absorbed

@@ -249,3 +249,57 @@ def test_absorptance_per_tet_sums_and_signs():
         assert abs(per[dom == d].sum() - A[d]) <= 1e-13 * max(abs(A).max(), 1e-30), d
     assert np.all(per[dom == W.DOM_SPACER] == 0.0)
     assert np.all(per[dom != W.DOM_SPACER] >= 0.0) and per.max() > 0
+
+
+# ---- two-layer stack: the interface between two materials (surface charge
+# sigma = kappa(T+) - kappa(T-) on interior faces) and the absorptance per
+# domain, against the multilayer transfer matrix (closed form).
+
+@pytest.mark.parametrize("th,pol", [(0, 0), (30, 0), (30, 1), (60, 1)])
+def test_multilayer_one_layer_is_the_airy_formula(th, pol):
+    e = 3.6 + 0.6j
+    R, T_, A = F.multilayer_rta([e], [50.0], 600.0, np.deg2rad(th), pol)
+    Rf, Tf, Af = F.slab_rta(e, 50.0, 600.0, np.deg2rad(th), pol)
+    assert abs(R - Rf) < 1e-13 and abs(T_ - Tf) < 1e-13 and abs(A[0] - Af) < 1e-13
+
+
+def test_multilayer_split_layer_and_energy():
+    e1, e2 = 3.6 + 0.6j, 1.8 + 0.3j
+    R, T_, A = F.multilayer_rta([e1], [50.0], 550.0, 0.5, 1)
+    R2, T2, A2 = F.multilayer_rta([e1, e1], [20.0, 30.0], 550.0, 0.5, 1)
+    assert abs(R - R2) < 1e-13 and abs(T_ - T2) < 1e-13 and abs(A[0] - sum(A2)) < 1e-13
+    R3, T3, A3 = F.multilayer_rta([e1, 2.25, e2], [20.0, 15.0, 25.0], 480.0, 0.3, 0)
+    assert abs(R3 + T3 + sum(A3) - 1.0) < 1e-13
+    assert abs(A3[1]) < 1e-13 and A3[0] > 0 and A3[2] > 0   # the lossless middle layer absorbs nothing
+
+
+def two_layer_slab(nxy, nz):
+    m = W.slab_mesh(a=50.0, b=50.0, thickness=50.0, nx=nxy, ny=nxy, nz=nz)
+    c = W.centroids(m.verts, m.tets)
+    dom = np.where(c[:, 2] >= 25.0, 0, 1).astype(np.int32)   # the wave meets domain 0 (top) first
+    return W.Mesh(m.verts, m.tets, dom, 2, 50.0, 50.0, m.grid)
+
+
+def _two_layer_errors(nxy, nz, th, pol):
+    e1, e2 = 3.6 + 0.6j, 1.8 + 0.3j
+    m = two_layer_slab(nxy, nz)
+    topo = build(m)
+    eps = np.where(m.tet_domain == 0, e1, e2).astype(complex)
+    wave = V.make_wave(600.0, np.deg2rad(th), 0.3 if th else 0.0)
+    x = V.solve_lu(V.assemble(topo, wave, eps), V.rhs(topo, wave, pol))
+    A = V.absorptance(topo, wave, eps, x)
+    R, T_ = V.reflect_transmit(topo, wave, eps, x, pol)
+    Rf, Tf, Af = F.multilayer_rta([e1, e2], [25.0, 25.0], 600.0, np.deg2rad(th), pol)
+    return np.abs(np.array([A[0] - Af[0], A[1] - Af[1], R - Rf, T_ - Tf]))
+
+
+@pytest.mark.parametrize("th,pol", [(0, 0), (30, 0), (30, 1)])
+def test_two_layer_stack_vs_multilayer_transfer_matrix(th, pol):
+    err = _two_layer_errors(2, 4, th, pol)   # N = 200
+    assert np.all(err < 1e-3), err
+
+
+def test_two_layer_stack_refinement():
+    coarse, fine = _two_layer_errors(2, 4, 0, 0), _two_layer_errors(3, 6, 0, 0)
+    # second order: h / 1.5 cuts the error about 2.25x
+    assert fine.max() < coarse.max() / 1.7, (coarse, fine)
