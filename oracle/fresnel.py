@@ -13,8 +13,9 @@ exp(-i w t) with eps Im >= 0 lossy; R, T and A are convention-independent.
   t = t01 t12 e^{i d kz1} / (1 + r01 r12 e^{2 i d kz1})
   R = |r|^2, T = |t|^2 (same medium on both sides), A = 1 - R - T.
 
-A second, independent formulation (characteristic 2x2 matrix of the layer)
-is provided for the pins.
+The multilayer form below (characteristic 2x2 matrix per layer) reduces to
+the same slab for one layer; the slab itself is pinned against a numerical
+integration of the one-dimensional wave equation in the tests.
 """
 import numpy as np
 
@@ -45,33 +46,11 @@ def slab_rta(eps, d, lam, theta, pol):
     return R, T, 1.0 - R - T
 
 
-def slab_rta_matrix(eps, d, lam, theta, pol):
-    """Characteristic-matrix form (Born & Wolf): M = [[cos b, -i sin b / Y],
-    [-i Y sin b, cos b]], b = kz1 d, Y = admittance (TE: kz/k0, TM: eps k0/kz)."""
-    k0 = 2 * np.pi / lam
-    s2 = np.sin(theta) ** 2
-    kz0 = k0 * np.sqrt(1 - s2 + 0j)
-    kz1 = k0 * np.sqrt(complex(eps) - s2)
-    if kz1.imag < 0:
-        kz1 = -kz1
-    if pol == 0:
-        Y0, Y1 = kz0 / k0, kz1 / k0
-    else:
-        Y0, Y1 = k0 / kz0, complex(eps) * k0 / kz1
-    bb = kz1 * d
-    m11, m12 = np.cos(bb), -1j * np.sin(bb) / Y1
-    m21, m22 = -1j * Y1 * np.sin(bb), np.cos(bb)
-    den = (m11 + m12 * Y0) * Y0 + (m21 + m22 * Y0)
-    r = ((m11 + m12 * Y0) * Y0 - (m21 + m22 * Y0)) / den
-    t = 2 * Y0 / den
-    R = abs(r) ** 2
-    T = abs(t) ** 2
-    return R, T, 1.0 - R - T
-
-
 def multilayer_rta(eps_layers, d_layers, lam, theta, pol):
     """Planar stack in vacuum, layers listed in the order the incident wave
-    meets them.  Characteristic matrix of each layer (as slab_rta_matrix),
+    meets them.  Characteristic matrix of each layer (Born & Wolf:
+    [[cos b, -i sin b / Y], [-i Y sin b, cos b]], b = kz d, Y the admittance:
+    TE kz/k0, TM eps k0/kz),
     r and t from their product; the absorbed fraction of each layer is the
     drop of the normal Poynting flux Re(U V*) across it, with the tangential
     fields (U, V) carried up from the exit side, (U, V) = (t, Y0 t).

@@ -10,7 +10,6 @@ Pins: exactness on monomials up to the stated degree (tests).
 import functools
 
 import numpy as np
-from scipy.special import roots_legendre
 
 
 def tet_deg2():
@@ -99,13 +98,3 @@ def tri_deg5():
             lam.append(l)
             w.append(wb)
     return np.array(lam), np.array(w)
-
-
-def gauss_legendre_01(n):
-    x, w = roots_legendre(n)
-    return (x + 1.0) / 2.0, w / 2.0
-
-
-def map_points(lam, verts):
-    """Physical points sum_k lam[:, k] * verts[k] (verts [k, 3])."""
-    return lam @ verts
