@@ -267,7 +267,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.apart, 8 * (size_t)nblk(nt, 256) * std::max(6 * 2 * 32, t.ndom));
   put(L.atet, 8 * (size_t)std::max<int64_t>(1, nt));
   put(L.kv, 8 * 3 * 2 * 32);
-  put(L.idx, 16 * (size_t)N);
+  // solver scratch; also the reduction target of the R/T projections (6 doubles per k-vector, <= 64)
+  put(L.idx, std::max<size_t>(16 * (size_t)N, 8 * 6 * 64));
   L.total = off;
   return L;
 }
@@ -1640,13 +1641,18 @@ int vie_absorption_pol(vie_ctx *ctx, int pol, double *absorptance, double *R, do
     std::vector<double> kvh;
     std::vector<double> beta;
     std::vector<int> isz;
-    for (int p = -kPgfM; p <= kPgfM; ++p)
-      for (int q = -kPgfM; q <= kPgfM; ++q) {
+    // every propagating Floquet order (|kt_pq| < k0 needs |2 pi p / a| < k0 + |kx|)
+    const int pmax = (int)std::ceil((k0 + std::fabs(kx)) * t.a / (2 * M_PI));
+    const int qmax = (int)std::ceil((k0 + std::fabs(ky)) * t.b / (2 * M_PI));
+    for (int p = -pmax; p <= pmax; ++p)
+      for (int q = -qmax; q <= qmax; ++q) {
         double tx = kx + 2 * M_PI * p / t.a, ty = ky + 2 * M_PI * q / t.b;
         double kt2 = tx * tx + ty * ty;
         if (kt2 >= k0 * k0) continue;
+        if (std::abs(p) > kPgfM || std::abs(q) > kPgfM || (int)beta.size() >= 32)
+          return fail(ctx, VIE_EINVAL, "propagating Floquet order (%d, %d) beyond the %d orders R/T can sum", p, q,
+                      (int)beta.size());
         double bz = std::sqrt(k0 * k0 - kt2);
-        if ((int)beta.size() >= 32) break;
         for (int s : {+1, -1}) {
           kvh.push_back(tx);
           kvh.push_back(ty);
