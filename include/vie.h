@@ -23,9 +23,11 @@
  *     the last failure is available from vie_last_error().
  *
  * Memory: host inputs are copied before a call returns.  All device memory
- * the library uses lives in ONE caller-owned workspace bound with
- * vie_bind_workspace (the library never allocates device memory itself).
- * The caller keeps the workspace alive until vie_destroy or the next bind.
+ * a context uses lives in ONE workspace: caller-owned memory bound with
+ * vie_bind_workspace (the library never allocates device memory itself), or
+ * the library's fixed per-device workspace bound with
+ * vie_bind_static_workspace.  The caller keeps its workspace alive until
+ * vie_destroy or the next bind.
  * Work is issued on the stream given to vie_create; calls that return
  * results to host buffers synchronise that stream.
  *
@@ -130,6 +132,24 @@ size_t vie_workspace_bytes(const vie_ctx *ctx, int precision, int restart);
 /* Bind caller-owned device memory (>= vie_workspace_bytes, 256-byte aligned)
  * and upload the mesh tables into it.  VIE_ENOMEM if too small. */
 int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bind the
+ * library's own workspace instead of a caller-owned one, then use the context
+ * exactly as after vie_bind_workspace.  The library holds one such workspace
+ * per device, 64 MiB (VIE_STATIC_WORKSPACE_BYTES), from its first vie_create
+ * on that device until the process ends; this call allocates nothing (no
+ * device memory, no pinned host memory).  A mesh whose
+ * vie_workspace_bytes(precision, restart) exceeds it gets VIE_ENOMEM (roughly
+ * N <= 1,400 unknowns in FP64, 2,000 mixed, at restart 100).  Every context
+ * on a device shares the one workspace, which keeps what the last holder
+ * wrote: binding it to a context first waits for the previous holder's
+ * stream, then takes the workspace from it (the previous holder's next call
+ * returns VIE_ESTATE until it binds again).  Calls on two contexts that hold
+ * it in turn must not overlap in time: they race on the same memory.
+ * Errors as vie_bind_workspace, plus VIE_ENOMEM when the mesh does not fit. */
+#define VIE_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int vie_bind_static_workspace(vie_ctx *ctx, int precision, int restart);
 
 /* Fill Z (dense, complex, row-major, domain-major unknowns) for wavelength
  * lambda_nm, incidence (theta, phi) and per-tetrahedron permittivity

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,7 +54,16 @@ struct Layout {
   int64_t ldv = 0;
 };
 
+// The library's own workspace for callers that cannot allocate device memory
+// (vie_bind_static_workspace).  Each device holds its own copy of the array
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (kept in g_static_ptr).
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
 
 struct vie_ctx {
   int device = 0;
@@ -107,7 +117,9 @@ struct vie_ctx {
   double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
   int32_t *pin_piv = nullptr;       // pinned: the pivots read back [N], the row permutation [N]
   int64_t pin_piv_n = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
+  std::vector<int32_t> piv_host;     // pivot read-back staging when no pinned buffer is allocated
+  bool static_ws = false;            // bound to the library's own workspace (vie_bind_static_workspace)
   // block LU look-ahead: the next panel's tournament on a stream of its own
   // (default priority) while the rest of the trailing update runs
   hipStream_t side = nullptr;
@@ -144,6 +156,31 @@ int fail(vie_ctx *c, int code, const char *fmt, ...) {
     hipError_t e_ = hipGetLastError();                                                                    \
     if (e_ != hipSuccess) return fail(ctx, VIE_EDEVICE, "kernel launch (line %d): %s", __LINE__, hipGetErrorString(e_)); \
   } while (0)
+
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};      // device address of `scratch` on each device
+vie_ctx *g_static_owner[kMaxDevices] = {};  // the context bound to it, if any
+
+// Resolve the device address of the static workspace on ctx->device (the
+// device must be current); once per device.
+int resolve_static(vie_ctx *ctx) {
+  if (ctx->device >= kMaxDevices) return VIE_OK;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_ptr[ctx->device]) return VIE_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return fail(ctx, VIE_EDEVICE, "static workspace address: %s", hipGetErrorString(e));
+  g_static_ptr[ctx->device] = p;
+  return VIE_OK;
+}
+
+// ctx gives up the static workspace of its device (if it holds it).
+void release_static(vie_ctx *ctx) {
+  if (!ctx->static_ws || ctx->device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[ctx->device] == ctx) g_static_owner[ctx->device] = nullptr;
+  ctx->static_ws = false;
+}
 
 unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
@@ -390,6 +427,8 @@ int vie_create(vie_ctx **out, int device, void *hip_stream) {
   HIPCK(hipEventCreate(&ctx->ev1));
   HIPCK(hipEventCreate(&ctx->ev2));
   HIPCK(hipEventCreate(&ctx->ev3));
+  HIPCK(hipEventCreate(&ctx->ev4));
+  if (int rc = resolve_static(ctx)) return rc;
   HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
   HIPCK(hipEventCreateWithFlags(&ctx->ev_la, hipEventDisableTiming));
   HIPCK(hipEventCreateWithFlags(&ctx->ev_ts, hipEventDisableTiming));
@@ -412,12 +451,14 @@ int vie_destroy(vie_ctx *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   drop_graphs(ctx);
+  release_static(ctx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->pin_piv) (void)hipHostFree(ctx->pin_piv);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
   if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
+  if (ctx->ev4) (void)hipEventDestroy(ctx->ev4);
   if (ctx->side) {
     (void)hipStreamSynchronize(ctx->side);
     (void)hipStreamDestroy(ctx->side);
@@ -480,8 +521,14 @@ size_t vie_workspace_bytes(const vie_ctx *cctx, int precision, int restart) {
       .total;
 }
 
-int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart) {
-  if (int r = check(ctx, S_MESH, "vie_bind_workspace")) return r;
+}  // extern "C"
+
+namespace {
+
+// Bind `bytes` of device memory at dev_ptr as the workspace and upload the
+// mesh tables.  no_alloc: allocate nothing (no pinned host staging either;
+// the pivot read-back then goes through pageable host memory).
+int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart, bool no_alloc) {
   if (precision != VIE_FP64 && precision != VIE_MIXED_FP32)
     return fail(ctx, VIE_EINVAL, "precision must be VIE_FP64 or VIE_MIXED_FP32");
   if (restart < 1 || restart > 1000) return fail(ctx, VIE_EINVAL, "restart must be in [1, 1000]");
@@ -502,11 +549,15 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
   if (ctx->pin_piv_n < t.N) {
     HIPCK(hipStreamSynchronize(ctx->stream));   // no upload of the permutation in flight
-    if (ctx->pin_piv) HIPCK(hipHostFree(ctx->pin_piv));
-    ctx->pin_piv = nullptr;
-    ctx->pin_piv_n = 0;
-    HIPCK(hipHostMalloc((void **)&ctx->pin_piv, 8 * (size_t)std::max<int64_t>(1, t.N), hipHostMallocDefault));
-    ctx->pin_piv_n = t.N;
+    if (no_alloc) {
+      ctx->piv_host.resize(2 * (size_t)std::max<int64_t>(1, t.N));
+    } else {
+      if (ctx->pin_piv) HIPCK(hipHostFree(ctx->pin_piv));
+      ctx->pin_piv = nullptr;
+      ctx->pin_piv_n = 0;
+      HIPCK(hipHostMalloc((void **)&ctx->pin_piv, 8 * (size_t)std::max<int64_t>(1, t.N), hipHostMallocDefault));
+      ctx->pin_piv_n = t.N;
+    }
   }
   drop_graphs(ctx);   // captured graphs hold pointers into the old workspace
   ctx->L = L;
@@ -621,6 +672,56 @@ int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision,
   return VIE_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int vie_bind_workspace(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart) {
+  if (int r = check(ctx, S_MESH, "vie_bind_workspace")) return r;
+  release_static(ctx);
+  return bind_impl(ctx, dev_ptr, bytes, precision, restart, false);
+}
+
+int vie_bind_static_workspace(vie_ctx *ctx, int precision, int restart) {
+  if (int r = check(ctx, S_MESH, "vie_bind_static_workspace")) return r;
+  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32)
+    return fail(ctx, VIE_EINVAL, "precision must be VIE_FP64 or VIE_MIXED_FP32");
+  if (restart < 1 || restart > 1000) return fail(ctx, VIE_EINVAL, "restart must be in [1, 1000]");
+  if (ctx->device >= kMaxDevices) return fail(ctx, VIE_EINVAL, "no static workspace on device %d", ctx->device);
+  const size_t need = vie_workspace_bytes(ctx, precision, restart);
+  if (need == 0 || need > kStaticWorkspaceBytes)
+    return fail(ctx, VIE_ENOMEM, "workspace of %zu bytes exceeds the library's static workspace (%zu bytes)", need,
+                kStaticWorkspaceBytes);
+  HIPCK(hipSetDevice(ctx->device));
+  void *p = nullptr;
+  vie_ctx *prev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    p = g_static_ptr[ctx->device];
+    prev = g_static_owner[ctx->device];
+    g_static_owner[ctx->device] = ctx;
+  }
+  if (!p) return fail(ctx, VIE_EDEVICE, "static workspace address unresolved on device %d", ctx->device);
+  if (prev && prev != ctx) {
+    // the previous holder loses the workspace: let its issued work finish,
+    // then any further call on it needs a new bind (VIE_ESTATE)
+    if (prev->stream) HIPCK(hipStreamSynchronize(prev->stream));
+    else HIPCK(hipDeviceSynchronize());
+    prev->static_ws = false;
+    prev->ws = nullptr;
+    prev->factored = false;
+    if (prev->state > S_MESH) prev->state = S_MESH;
+  }
+  ctx->static_ws = true;
+  if (int rc = bind_impl(ctx, p, kStaticWorkspaceBytes, precision, restart, true)) {
+    release_static(ctx);
+    ctx->ws = nullptr;
+    ctx->state = S_MESH;
+    return rc;
+  }
+  return VIE_OK;
+}
+
 int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
   if (int r = check(ctx, S_BOUND, "vie_fill")) return r;
   if (precision != ctx->precision) return fail(ctx, VIE_EINVAL, "precision does not match the bound workspace");
@@ -713,8 +814,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
                        (const dz *)kappa, (const dz *)inveps, k0sq9, zo);
     LAUNCHCK();
   }
-  hipEvent_t evn = nullptr;
-  HIPCK(hipEventCreate(&evn));
+  hipEvent_t evn = ctx->ev4;
   HIPCK(hipEventRecord(evn, ctx->stream));
   if (ctx->nface) {
     const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
@@ -769,7 +869,6 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   HIPCK(hipEventElapsedTime(&mfar, ctx->ev2, ctx->ev3));
   HIPCK(hipEventElapsedTime(&mnear, ctx->ev3, evn));
   HIPCK(hipEventElapsedTime(&mface, evn, ctx->ev1));
-  (void)hipEventDestroy(evn);
   ctx->t_fill = ms;
   // algorithmic work of the far tet-pair kernel (cost model, FMA = 2 FLOPs):
   // per point pair: separation and wrap 12; per image 27 + 3 deg (X, Y, R^2,
@@ -1002,7 +1101,9 @@ int vie_precond_factor(vie_ctx *ctx) {
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->pinned, info, 4 * t.ndom, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCK(hipMemcpyAsync(ctx->pin_piv, ipiv, 4 * (size_t)t.N, hipMemcpyDeviceToHost, ctx->stream));
+  // pivots and permutation staged in pinned memory, or pageable memory after a no-allocation bind
+  int32_t *stage = ctx->pin_piv_n >= t.N ? ctx->pin_piv : ctx->piv_host.data();
+  HIPCK(hipMemcpyAsync(stage, ipiv, 4 * (size_t)t.N, hipMemcpyDeviceToHost, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   float ms = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -1013,10 +1114,10 @@ int vie_precond_factor(vie_ctx *ctx) {
     else if (inf[d]) return fail(ctx, VIE_ESINGULAR, "zero pivot in block %d at column %d", d, inf[d] - 1);
   // row permutation of each block from its swaps (sequential by nature: done
   // on the host from the pivots read back, then uploaded for the applies)
-  int32_t *hp = ctx->pin_piv + t.N;
+  int32_t *hp = stage + t.N;
   for (int d = 0; d < t.ndom; ++d) {
     const int64_t o = t.dstart[d], n = t.dend[d] - t.dstart[d];
-    const int32_t *ip = ctx->pin_piv + o;
+    const int32_t *ip = stage + o;
     int32_t *pm = hp + o;
     for (int64_t i = 0; i < n; ++i) pm[i] = (int32_t)i;
     for (int64_t j = 0; j < n; ++j) {

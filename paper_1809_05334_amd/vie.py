@@ -78,6 +78,7 @@ _SIGS = {
     "vie_domain_ranges": (C.c_int, [C.c_void_p, C.c_void_p]),
     "vie_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_int]),
     "vie_bind_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int]),
+    "vie_bind_static_workspace": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "vie_fill": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_int]),
     "vie_precond_factor": (C.c_int, [C.c_void_p]),
     "vie_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(SolveInfo)]),
@@ -203,6 +204,15 @@ class Solver:
         self.precision = precision
         self.restart = restart
         return nbytes
+
+    def bind_static(self, precision=VIE_FP64, restart=100):
+        """Bind the library's own per-device workspace (no allocation); the
+        previous context holding it loses it."""
+        self._ck(self.lib.vie_bind_static_workspace(self.h, precision, restart))
+        self.ws = None
+        self.precision = precision
+        self.restart = restart
+        return self.workspace_bytes(precision, restart)
 
     # -------------------------------------------------------------- method
     def fill(self, lam, theta, phi, eps, precision=None):
