@@ -261,11 +261,14 @@ enum {
                              * 1: partial pivoting column by column.  Both give P A = L U; the
                              * factors, and so the rounding of M^{-1} v, differ between them */
   VIE_OPT_SYM_FILL = 6,     /* 1: the workspace bound next also holds a second N x ld copy of Z's
-                             * far part, and every fill at normal incidence (kt = 0, where g_p is
-                             * even in r - r') evaluates each unordered far tetrahedron pair once,
-                             * writing the swapped pair's block there and adding it transposed into
-                             * Z.  Oblique fills do not use it.  Z differs only by rounding.  Set it
-                             * before vie_workspace_bytes / vie_bind_workspace (VIE_ESTATE after);
+                             * far part, and every fill evaluates each unordered far tetrahedron
+                             * pair once, writing the swapped pair's block there and adding it
+                             * transposed into Z.  At normal incidence (kt = 0) g_p is even in
+                             * r - r'; at oblique incidence g_p(r' - r) is the conjugate of
+                             * g_p(r - r') plus a term of the propagating Floquet orders (Sec. 2.2,
+                             * Eqs. 3-4, real wavenumber), formed in the same lattice-sum
+                             * evaluation.  Z differs only by rounding.  Set it before
+                             * vie_workspace_bytes / vie_bind_workspace (VIE_ESTATE after);
                              * 0 (default): no staging */
   VIE_OPT_PRECOND = 7       /* preconditioner of the next vie_solve / vie_solve_pair: 0 (default)
                              * the block-diagonal M of the last vie_precond_factor (Sec. 2.3,

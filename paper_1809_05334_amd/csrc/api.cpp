@@ -769,12 +769,19 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   if (ctx->nface)
     hipLaunchKernelGGL(k_sigma, dim3(nblk(ctx->nface, 256)), dim3(256), 0, ctx->stream, ctx->nface,
                        ctx->ptr<int32_t>(L.ctp), ctx->ptr<int32_t>(L.ctm), (const dz *)kappa, sigma);
-  // At normal incidence (kt = 0) the lattice sum is even in the separation:
-  // with the staging bound (VIE_OPT_SYM_FILL) each unordered far pair is
-  // evaluated once and also yields the swapped pair's block, gathered in Zt;
-  // likewise each far (tet, half-SWG face) pair yields the (face, tet) entry.
-  // Zt is added transposed after the face kernels.
-  const bool sym = L.Zt.bytes > 0 && kx == 0.0 && ky == 0.0;
+  // With the staging bound (VIE_OPT_SYM_FILL) each unordered far tet pair is
+  // evaluated once and also yields the swapped pair's block, gathered in Zt:
+  // at normal incidence (kt = 0) the lattice sum is even in the separation;
+  // at oblique incidence g_p at the reversed separations follows from the same
+  // evaluation plus the propagating orders' term (rev).  At kt = 0 each far
+  // (tet, half-SWG face) pair likewise yields the (face, tet) entry.  Zt is
+  // added transposed after the face kernels.
+  const bool kt0 = kx == 0.0 && ky == 0.0;
+  // (the oblique form keeps 32 KB per block of the swapped moments in LDS
+  // beside the table; a table too large for both runs the plain fill)
+  const bool sym = L.Zt.bytes > 0 && (kt0 || lds + kFarRevLds <= 65536);
+  const bool sym_face = sym && kt0;
+  const int rev = kt0 ? 0 : 1;
   ctx->last_sym = sym;
   ZOut zt = zout(ctx);
   if (sym) {
@@ -798,9 +805,14 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
       if (sym && cs < ct) continue;   // covered by the launch of (cs, ct)
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
       const int mode = !sym ? 0 : (ct == cs ? 2 : 1);
-      hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
-                         colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
-                         (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
+      if (sym && rev)
+        hipLaunchKernelGGL(k_tt_far_rev, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds + kFarRevLds, ctx->stream,
+                           pk_, pkl, qr, tg, t2f, colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS,
+                           (const dz *)alpha, (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
+      else
+        hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
+                           t2f, colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
+                           (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
       LAUNCHCK();
       ++far_launches;
     }
@@ -824,7 +836,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
       hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
                          t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma,
-                         (const dz *)gsrc, (const dz *)kappa, zo, zt, sym ? 1 : 0);
+                         (const dz *)gsrc, (const dz *)kappa, zo, zt, sym_face ? 1 : 0);
       const int np = ctx->tf_off[ct + 1] - ctx->tf_off[ct];
       if (np)
         hipLaunchKernelGGL(k_tet_face_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
@@ -835,7 +847,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     if (ctx->nhalf) {
       for (int cs = 0; cs < C; ++cs) {
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-        if (!sym)   // (with sym the far pairs came from k_tet_face)
+        if (!sym_face)   // (at kt = 0 with the staging the far pairs came from k_tet_face)
           hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
                              qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
                              (const dz *)gsrc, (const dz *)kappa, zo);
@@ -878,16 +890,21 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   // mode 13 + 3 deg (twice the Clenshaw for a complex order); final phase 6.
   // Per tet pair:
   // 16 point pairs + 1200 for moments and the 16-entry scatter (+ 1200 for
-  // the swapped pair's scatter when one evaluation serves both).
-  double pp = 12 + ((kx == 0.0 && ky == 0.0) ? 132 : 212) + 6;
+  // the swapped pair's scatter when one evaluation serves both).  At oblique
+  // incidence one evaluation serving both also forms g_p at the reversed
+  // separations (per point pair 4 per propagating order + 10) and the swapped
+  // pair's moments (16 x 36 per tet pair).
+  double pp = 12 + (kt0 ? 132 : 212) + 6;
   const PgfTable &tb = *ctx->tab;
   for (int i = 0; i < tb.nimg; ++i) pp += 27 + 3 * tb.img[i].deg;
-  int nmodes = 0;
+  int nmodes = 0, ncplx = 0;
   for (int i = 0; i < kPgfTerms; ++i)
     if (tb.mode[i].deg >= 0) {
       ++nmodes;
+      ncplx += tb.mode[i].cplx ? 1 : 0;
       pp += 13 + 3 * tb.mode[i].deg * (tb.mode[i].cplx ? 2 : 1) + (tb.mode[i].cplx ? 4 : 0);
     }
+  if (sym && rev) pp += 10 + 4 * ncplx;
   int64_t nnear = 0;
   for (auto &v : t.near_t) nnear += (int64_t)v.size();
   vie_fill_stats &st = ctx->fstats;
@@ -902,7 +919,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   st.far_launches = far_launches;
   st.far_symmetric = sym ? 1 : 0;
   st.point_pair_flops = pp;
-  st.far_flops = (double)st.far_pairs * (16.0 * pp + (sym ? 2400.0 : 1200.0));
+  st.far_flops = (double)st.far_pairs * (16.0 * pp + (sym ? 2400.0 : 1200.0) + (sym && rev ? 16.0 * 36 : 0.0));
   st.nimg = tb.nimg;
   st.nmode = nmodes;
   ctx->state = S_FILLED;

@@ -154,9 +154,20 @@ __device__ __forceinline__ void clenshaw_w(const double *__restrict__ c, int K, 
 // 1/(4 pi R) part is integrated in closed form elsewhere; for those images
 // the remainder H(x) E/(4 pi) is used, so the value returned is
 // g_p - sum_touching e^{j kt.rho}/(4 pi R).
-template <bool TOUCH, int W>
+//
+// REV (non-touching separations only): also g_p at -d[w] into rev[w].  For a
+// real wavenumber every spatial image term is a real function of R times the
+// image phase e^{j kt.rho_mn}, and the images (m, n), (-m, -n) share that
+// function, so the spatial sum at -d is the conjugate of the one at d.  A
+// spectral term e^{-j k_tpq.Delta} K_pq(z) has K_pq even in z and real for an
+// evanescent order, so it too conjugates, except for the propagating orders,
+// whose K_pq is complex.  Hence
+//   g_p(-d) = conj(g_p(d)) + conj(ph0) 2j sum_{propagating} conj(e^{-j k_tpq.Delta}) Im K_pq(z),
+// with ph0 the phase of the nearest-image shift (which flips with d).  The
+// reverse value costs two FMAs per propagating order on top of g_p(d).
+template <bool TOUCH, int W, bool REV = false>
 __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const double (&d)[W][3], int mask,
-                                           dz (&out)[W]) {
+                                           dz (&out)[W], dz *rev = nullptr) {
   const double a = P[pk::A], b = P[pk::B], E = P[pk::E];
   double dx[W], dy[W], dz2[W], sre[W], sim[W];
   int im0[W], in0[W];
@@ -246,7 +257,7 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
   // spectral series: the W separations share every mode's coefficient reads
   // and run W interleaved Clenshaw recurrences in w = (z E)^2; the Floquet
   // phases e^{-j k_tpq . Delta_t} of each separation by recurrence in p and q
-  double tw[W], kre[W], kim[W];
+  double tw[W], kre[W], kim[W], cre_[W], cim_[W];
   dz erow[W], bx[W], by[W];   // erow: phase of (p, q = -4); steps in p and in q
   const bool kt0 = P[pk::KX] == 0.0 && P[pk::KY] == 0.0;   // normal incidence: e^{-j kt.Delta} = 1
 #pragma unroll
@@ -268,6 +279,8 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     }
     kre[w] = 0.0;
     kim[w] = 0.0;
+    cre_[w] = 0.0;
+    cim_[w] = 0.0;
   }
 #pragma unroll 1
   for (int p = 0; p < kPgfSide; ++p) {
@@ -289,6 +302,10 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
           for (int w = 0; w < W; ++w) {
             kre[w] += e[w].re * kr[w] - e[w].im * ki[w];
             kim[w] += e[w].re * ki[w] + e[w].im * kr[w];
+            if (REV) {   // conj(e) Im K_pq of a propagating order
+              cre_[w] = fma(e[w].re, ki[w], cre_[w]);
+              cim_[w] = fma(-e[w].im, ki[w], cim_[w]);
+            }
           }
         } else {
 #pragma unroll
@@ -309,6 +326,7 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     const int pi = (im0[w] + 1) * 3 + (in0[w] + 1);
     const dz ph = mk(P[pk::PHRE + pi], P[pk::PHIM + pi]);
     out[w] = ph * mk(sre[w] + kre[w], sim[w] + kim[w]);
+    if (REV) rev[w] = conjz(out[w]) + conjz(ph) * mk(-2.0 * cim_[w], 2.0 * cre_[w]);
   }
 }
 

@@ -135,22 +135,30 @@ __device__ __forceinline__ void scatter_tt(const Moments &M, const TetGeom &gt, 
 }
 
 // Far tet pairs: 4 x 4 product rule.  One wave = one test tet x 64 source tets.
+// sym > 0 writes the swapped pair's block (S, T) too (see the declaration).
 // At normal incidence the lattice sum is even in the separation (the phases
 // e^{-j kt.rho} are all 1), so the pair's moments also give those of the
-// swapped pair (S, T): sym > 0 writes that block too (see the declaration).
-__global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
-                                                const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
-                                                const int32_t *__restrict__ test_list, int ntest,
-                                                const int32_t *__restrict__ src_list, int nsrc,
-                                                const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
-                                                const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
-                                                int sym) {
+// swapped pair.  At oblique incidence (rev) g_p at the reversed separations
+// follows from g_p at the separations plus the propagating orders' term (see
+// pgf_eval_w), and the swapped pair's moments are accumulated from it.
+// REV: the swapped pair's moments are summed per lane in LDS (16 doubles
+// after the table, one column per thread), not in registers, so that the
+// kernel keeps two waves per SIMD without spilling.
+template <bool REV>
+__device__ __forceinline__ void tt_far_body(const double *__restrict__ pack, int packlen,
+                                            const QuadRules *__restrict__ qr, const TetGeom *__restrict__ tg,
+                                            const TetFace *__restrict__ t2f, const int32_t *__restrict__ test_list,
+                                            int ntest, const int32_t *__restrict__ src_list, int nsrc,
+                                            const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                            const dz *__restrict__ kappa, double k0sq9, const ZOut &out,
+                                            const ZOut &outT, int sym) {
   extern __shared__ double s_tab[];
   // one list against itself: a block whose source positions all lie at or
   // below its test positions has nothing to do (the whole block returns)
   if (sym == 2 && (int)blockIdx.x * 64 + 63 <= (int)blockIdx.y * 4) return;
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
+  double *__restrict__ mr = s_tab + ((packlen + 1) & ~1) + threadIdx.x;   // REV: entry e at mr[256 e]
 
   const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int si = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -179,6 +187,8 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
   const double wt = 0.25 * gt.vol;
   Moments M;
   moments_zero(M);
+  if (REV)
+    for (int e = 0; e < 16; ++e) mr[256 * e] = 0.0;
   // one test point against the four source points per lattice-sum call
 #pragma unroll 1
   for (int i = 0; i < 4; ++i) {
@@ -193,8 +203,8 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int d = 0; d < 3; ++d) sep[j][d] = dc[d] + u[d] - up[j][d];
-    dz g[4];
-    pgf_eval_w<false, 4>(P, sep, 0, g);
+    dz g[4], gr[REV ? 4 : 1];
+    pgf_eval_w<false, 4, REV>(P, sep, 0, g, gr);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const dz gw = (wt * wq) * g[j];
@@ -205,6 +215,31 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
       }
       axpy(M.muv, dot3(u, up[j]), gw);
     }
+    if (REV) {
+      // swapped pair (S, T): its test offsets are up_j, its source offsets u
+      Moments R;
+      moments_zero(R);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const dz grw = (wt * wq) * gr[j];
+        R.m0 = R.m0 + grw;
+        for (int d = 0; d < 3; ++d) {
+          axpy(R.mu[d], up[j][d], grw);
+          axpy(R.mv[d], u[d], grw);
+        }
+        axpy(R.muv, dot3(u, up[j]), grw);
+      }
+      mr[0] += R.m0.re;
+      mr[256] += R.m0.im;
+      for (int d = 0; d < 3; ++d) {
+        mr[256 * (2 + 2 * d)] += R.mu[d].re;
+        mr[256 * (3 + 2 * d)] += R.mu[d].im;
+        mr[256 * (8 + 2 * d)] += R.mv[d].re;
+        mr[256 * (9 + 2 * d)] += R.mv[d].im;
+      }
+      mr[256 * 14] += R.muv.re;
+      mr[256 * 15] += R.muv.im;
+    }
   }
   // the source geometry is read again here rather than held in registers
   // through the lattice sums (the empty asm hides the earlier load)
@@ -212,8 +247,17 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
   asm volatile("" : "+v"(tgs));
   const TetGeom gs = *tgs;
   scatter_tt(M, gt, gs, t2f, T, S, alpha, gsrc, kappa, k0sq9, out, false);
-  if (sym) {
-    // (S, T): test offsets and source offsets trade places
+  if (REV && sym) {
+    Moments R;
+    R.m0 = mk(mr[0], mr[256]);
+    for (int d = 0; d < 3; ++d) {
+      R.mu[d] = mk(mr[256 * (2 + 2 * d)], mr[256 * (3 + 2 * d)]);
+      R.mv[d] = mk(mr[256 * (8 + 2 * d)], mr[256 * (9 + 2 * d)]);
+    }
+    R.muv = mk(mr[256 * 14], mr[256 * 15]);
+    scatter_tt<true>(R, gs, gt, t2f, S, T, alpha, gsrc, kappa, k0sq9, outT, false);
+  } else if (sym) {
+    // (S, T) at kt = 0: test offsets and source offsets trade places
     Moments Ms;
     Ms.m0 = M.m0;
     Ms.muv = M.muv;
@@ -223,6 +267,28 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
     }
     scatter_tt<true>(Ms, gs, gt, t2f, S, T, alpha, gsrc, kappa, k0sq9, outT, false);
   }
+}
+
+__global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                const int32_t *__restrict__ test_list, int ntest,
+                                                const int32_t *__restrict__ src_list, int nsrc,
+                                                const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                                const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
+                                                int sym) {
+  tt_far_body<false>(pack, packlen, qr, tg, t2f, test_list, ntest, src_list, nsrc, alpha, gsrc, kappa, k0sq9, out,
+                     outT, sym);
+}
+
+__global__ __launch_bounds__(256, 2) void k_tt_far_rev(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                    const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                    const int32_t *__restrict__ test_list, int ntest,
+                                                    const int32_t *__restrict__ src_list, int nsrc,
+                                                    const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                                    const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
+                                                    int sym) {
+  tt_far_body<true>(pack, packlen, qr, tg, t2f, test_list, ntest, src_list, nsrc, alpha, gsrc, kappa, k0sq9, out,
+                    outT, sym);
 }
 
 // Z[i][j] += Zt[j][i]: 32 x 32 tiles through shared memory, both sides read

@@ -27,9 +27,17 @@ __global__ void k_zero(dz *p, int64_t n);
 // sym: 0 every pair of the two lists, writing Z; 1 the same, also writing the
 // transposed pair's block into outT (stored untransposed); 2 (one list twice)
 // only pairs with source position > test position, both blocks as for 1.
+// k_tt_far: the swapped block from the same moments (kt = 0 only);
+// k_tt_far_rev (any incidence): from g_p at the reversed separations, with
+// 16 doubles per thread of dynamic LDS after the table (kFarRevLds bytes).
 __global__ void k_tt_far(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                          const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc, const dz *alpha,
                          const dz *gsrc, const dz *kappa, double k0sq9, ZOut out, ZOut outT, int sym);
+__global__ void k_tt_far_rev(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg,
+                             const TetFace *t2f, const int32_t *test_list, int ntest, const int32_t *src_list, int nsrc,
+                             const dz *alpha, const dz *gsrc, const dz *kappa, double k0sq9, ZOut out, ZOut outT,
+                             int sym);
+constexpr int kFarRevLds = 16 * 256 * 8 + 8;
 // Z[i][j] += Zt[j][i] for i, j < N (row-major, leading dimension ld)
 __global__ void k_transpose_add_z(dz *Z, const dz *Zt, int64_t N, int64_t ld);
 __global__ void k_transpose_add_c(fz *Z, const fz *Zt, int64_t N, int64_t ld);

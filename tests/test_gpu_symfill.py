@@ -8,7 +8,11 @@ max|Z|)), the plain fill's Z to rounding (FP64) or to the FP32 rounding of
 far entries (mixed), the same solutions, and evaluate half the far pairs.
 The far (half-SWG face, tet) entries come from the tet-face kernel's
 evaluation of the same pair, written transposed into the staging copy.
-Oblique fills ignore the option and give the plain fill's Z bit for bit."""
+At oblique incidence the option also evaluates each unordered far pair once:
+g_p at the reversed separations is the conjugate of g_p at the separations
+plus a term of the propagating Floquet orders, so the swapped pair's
+moments come from the same lattice sums; checked the same way, including a
+cell where a non-specular order propagates."""
 import numpy as np
 import pytest
 
@@ -85,16 +89,55 @@ def test_symmetric_fill_matches_oracle_and_plain_fill(vie, case):
             assert np.linalg.norm(xs - xp) < tol * np.linalg.norm(xp), (prec, p)
 
 
-def test_oblique_fill_ignores_the_option(vie):
-    m = osc_small()
-    lam = 480.0
-    eps = eps_for(m, lam)
-    sp = solver(vie, m, vie.VIE_FP64, False)
-    ss = solver(vie, m, vie.VIE_FP64, True)
-    for s in (sp, ss):
-        s.fill(lam, 0.3, 0.2, eps)
-    assert ss.fill_stats()["far_symmetric"] == 0
-    assert np.array_equal(full_Z(sp), full_Z(ss))
+def grating():
+    """A 300 x 240 nm cell, two layers of 3 x 3 bricks: at 500 nm, 55 deg
+    the (-1, 0) order propagates."""
+    from paper_1809_05334_amd import workloads as W
+    xs, ys, zs = np.linspace(0, 300.0, 4), np.linspace(0, 240.0, 4), np.array([0.0, 30.0, 60.0])
+    verts, tets = W.brick_grid_mesh(xs, ys, zs)
+    c = W.centroids(verts, tets)
+    dom = np.where(c[:, 2] < 30.0, 1, 0).astype(np.int32)
+    dom[(c[:, 2] > 30.0) & (c[:, 0] < 100.0)] = 0
+    return W.Mesh(verts, tets, dom, 2, 300.0, 240.0, (xs, ys, zs), {"kind": "grating"})
+
+
+@pytest.mark.parametrize("case", ["osc_small", "osc_rect", "grating"])
+def test_oblique_symmetric_fill(vie, case):
+    m = {"osc_small": osc_small, "osc_rect": osc_rect, "grating": grating}[case]()
+    lam, th, ph = (500.0, np.deg2rad(55.0), np.deg2rad(20.0)) if case == "grating" else (480.0, 0.5, 0.3)
+    if case == "grating":
+        eps = np.array([4.0 + 0.3j, 2.3 + 0.05j])[m.tet_domain]
+    else:
+        eps = eps_for(m, lam)
+    t = OT.build(m.verts, m.tets, m.tet_domain, m.ndom, m.a, m.b)
+    wave = OV.make_wave(lam, th, ph)
+    Zo = OV.assemble(t, wave, eps)
+    scale = np.abs(Zo).max()
+    for prec in (vie.VIE_FP64, vie.VIE_MIXED_FP32):
+        sp = solver(vie, m, prec, False)
+        ss = solver(vie, m, prec, True)
+        sp.fill(lam, th, ph, eps)
+        ss.fill(lam, th, ph, eps)
+        fp, fs = sp.fill_stats(), ss.fill_stats()
+        assert fp["far_symmetric"] == 0 and fs["far_symmetric"] == 1
+        assert 2 * fs["far_pairs"] == fp["far_pairs"]
+        Zp, Zs = full_Z(sp), full_Z(ss)
+        if prec == vie.VIE_FP64:
+            bad = np.abs(Zs - Zo) > 1e-10 * np.maximum(np.abs(Zo), 1e-5 * scale)
+            assert not bad.any(), np.max(np.abs(Zs - Zo) / np.maximum(np.abs(Zo), 1e-5 * scale))
+            assert np.max(np.abs(Zs - Zp)) < 1e-13 * scale
+        else:
+            assert np.max(np.abs(Zs - Zo)) < 1e-6 * scale
+            assert np.max(np.abs(Zs - Zp)) < 1e-6 * scale
+        for s in (sp, ss):
+            s.factor()
+        ip = sp.solve_pair(tol=1e-10, max_iter=300, restart=40)
+        is_ = ss.solve_pair(tol=1e-10, max_iter=300, restart=40)
+        for p in (0, 1):
+            assert ip[p]["converged"] and is_[p]["converged"]
+            xp, xs = sp.read_solution(p), ss.read_solution(p)
+            tol = 1e-9 if prec == vie.VIE_FP64 else 1e-5
+            assert np.linalg.norm(xs - xp) < tol * np.linalg.norm(xp), (prec, p)
 
 
 def test_option_is_refused_after_bind(vie):
