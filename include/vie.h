@@ -292,6 +292,52 @@ typedef struct {
  * work vectors but not the last solution.  `out` may be NULL. */
 int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out);
 
+/* ---------------------------------------------------------------- batch
+ * Many independent unit cells solved together (the batched form of the
+ * method: one (cell, wavelength, angles, polarisation) solve per cell, as in
+ * Sec. 3's sweeps).  Each cell is an ordinary context (mesh uploaded,
+ * workspace bound, all in the same precision) that keeps its own Z, factors
+ * and Krylov basis; the batch launches each step of the method once for all
+ * of them:
+ *   - fill: the lattice-sum tables of every cell fitted on host threads, then
+ *     one launch per fill kernel and colour pair (or colour) covering every
+ *     cell, each cell's share of the grid described by a segment table;
+ *   - factor: one blocked LU (Sec. 2.3, Eq. 6) advancing every cell's
+ *     domains together, panel by panel;
+ *   - solve: right-preconditioned GMRES (Sec. 3) with the Arnoldi steps of
+ *     all cells in one launch sequence (fused matvec, triangular solves over
+ *     every cell's domains, Gram-Schmidt, norms, Givens), replayed as one
+ *     captured HIP graph per step (VIE_BATCH_GRAPH), each cell stepping until
+ *     its own stopping test; restart updates per cell.
+ * Per cell the results equal those of vie_fill / vie_precond_factor /
+ * vie_solve on that context up to the summation order of the reductions.
+ * After a batch solve each cell answers vie_absorption, vie_absorption_pol,
+ * vie_read_solution as after vie_solve.  A batch issues all work on its own
+ * stream; binding sets every cell's stream to it. */
+typedef struct vie_batch vie_batch;
+enum { VIE_BATCH_GRAPH = 1 };   /* 1 (default): capture the fused Arnoldi step once and replay it */
+int vie_batch_create(vie_batch **out, int device, void *hip_stream);
+int vie_batch_destroy(vie_batch *b);
+const char *vie_batch_last_error(const vie_batch *b);
+/* Device bytes of the batch's own tables (segment tables, descriptors, the
+ * merged triangular-solve plan) for ncells cells. */
+size_t vie_batch_workspace_bytes(int ncells);
+/* cells [ncells]: bound contexts of one device and one precision, each used
+ * by no other thread or batch while bound here; dev_ptr: caller-owned device
+ * memory (>= vie_batch_workspace_bytes, 256-byte aligned). */
+int vie_batch_bind(vie_batch *b, vie_ctx *const *cells, int ncells, void *dev_ptr, size_t bytes);
+int vie_batch_set_option(vie_batch *b, int option, int value);
+/* Per cell c: wavelength lambda_nm[c], incidence theta[c], phi[c] (radians),
+ * permittivities eps_per_tet[c] (that cell's tetrahedra; optics sign). */
+int vie_batch_fill(vie_batch *b, const double *lambda_nm, const double *theta, const double *phi,
+                   const vie_c128 *const *eps_per_tet);
+int vie_batch_factor(vie_batch *b);
+/* polarisation [ncells]; info [ncells] (nullable; t_fill_ms, t_factor_ms,
+ * t_solve_ms are the batch's).  VIE_ENOCONV if a cell stops at max_iter
+ * (every cell's solution and info are still written). */
+int vie_batch_solve(vie_batch *b, const int *polarisation, double tol, int max_iter, int restart,
+                    vie_solve_info *info);
+
 /* Residual history (estimate / ||b||) of the last solve; returns the count
  * written (at most cap). */
 int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);

@@ -12,47 +12,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vie.h"
-#include "device_math.h"
-#include "host.h"
-#include "kernels.h"
+#include "context.h"
 
 using namespace vie;
 
-namespace {
-
-enum State { S_NEW = 0, S_MESH = 1, S_BOUND = 2, S_FILLED = 3, S_FACTORED = 4, S_SOLVED = 5 };
-
-constexpr int kMaxPack = 8192;     // doubles of the packed lattice-sum table (64 KB of LDS)
-constexpr int kRedBlocks = 240;   // blocks of the two-stage reductions
-constexpr int kMaxPlans = 4;      // cached cooperative triangular-solve plans per context
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-struct Region {
-  size_t off = 0, bytes = 0;
-};
-
-struct Layout {
-  Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, near_tf, near_ft, quad, pgf,
-      pack;
-  Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
-      plans;
-  int plan_steps = 0;   // TrsvStep entries of one cooperative plan
-  // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
-  struct Kry {
-    Region V, H, cs, sn, g, y, vb, vx, vw, vz, vu, vr, vt, vin, dpart, npart, scal, jd, rhist;
-  } K[2];
-  Region apart, atet, kv, idx;
-  size_t total = 0;
-  int64_t ld = 0;
-  std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
-  std::vector<int64_t> doff;       // per-domain offset of the diagonal-block inverses (elements)
-  std::vector<int64_t> toff;       // per-domain offset of the tournament tree nodes (nodes)
-  int restart = 0;
-  int64_t ldv = 0;
-};
+namespace vie {
 
 // The library's own workspace for callers that cannot allocate device memory
 // (vie_bind_static_workspace).  Each device holds its own copy of the array
@@ -61,101 +25,11 @@ struct Layout {
 constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 
-}  // namespace
+}  // namespace vie
 
 static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
 
-struct vie_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  State state = S_NEW;
-  std::string err;
-  MeshTopology topo;
-  QuadRules quad;
-  Layout L;
-  char *ws = nullptr;
-  size_t ws_bytes = 0;
-  int precision = VIE_FP64;
-  // fill parameters
-  double lambda = 0, theta = 0, phi = 0;
-  PgfTable *tab = nullptr;          // host copy (heap, large)
-  std::vector<dz> eps_int;
-  std::vector<double> pack;         // packed lattice-sum table of the last fill
-  int packlen = 0;
-  std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
-  std::vector<int32_t> tf_off, ft_off;   // offsets (in pairs) of the touching tet-face / face-tet lists per colour
-  int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
-  int trsv_rw = 4;                  // triangular-solve update rows per wave (4, 8)
-  int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
-  int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
-  int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
-  int precond = 0;                  // 0: block-diagonal LU preconditioner, 1: none (M = I)
-  bool factored = false;            // the factors belong to the current fill (a solve with M = I
-                                    // reaches S_SOLVED without them)
-  int sym_fill = 0;                 // the next bind reserves the transposed-block staging of normal-incidence fills
-  bool last_sym = false;            // the last fill used it
-  bool capturing = false;           // a graph capture is in progress on the stream
-  int coop_grid = 0;                // co-resident thread blocks of the cooperative kernel
-  struct CoopPlan {
-    const void *v, *out, *s1, *s2;
-    int rw, nsteps;
-    size_t off;                     // byte offset of the plan in the workspace
-  };
-  std::vector<CoopPlan> plans;
-  // captured Arnoldi steps per Krylov process set (K[0], K[1], both):
-  // [0] graph_steps steps, [1] one step (tail of a restart cycle)
-  hipGraphExec_t gexec[3][2] = {};
-  int gexec_steps[3] = {};
-  std::vector<int64_t> nrow;        // near-part CSR pattern (mixed precision), built on first use
-  std::vector<int32_t> ncol;
-  bool npat = false;
-  std::vector<int32_t> color_off;
-  int nhalf = 0, nface = 0;
-  int last_pol = 0;                 // polarisation of the last solve (the TM one of a pair)
-  int sol_k[2] = {-1, -1};          // Krylov process holding the last TE / TM solution, -1: none
-  std::vector<double> hist[2];      // residual estimates of each Krylov process's last solve
-  double *pinned = nullptr;         // small pinned host buffer for scalar read-backs
-  int32_t *pin_piv = nullptr;       // pinned: the pivots read back [N], the row permutation [N]
-  int64_t pin_piv_n = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
-  std::vector<int32_t> piv_host;     // pivot read-back staging when no pinned buffer is allocated
-  bool static_ws = false;            // bound to the library's own workspace (vie_bind_static_workspace)
-  // block LU look-ahead: the next panel's tournament on a stream of its own
-  // (default priority) while the rest of the trailing update runs
-  hipStream_t side = nullptr;
-  hipEvent_t ev_la = nullptr, ev_ts = nullptr;
-  vie_fill_stats fstats{};
-  double t_fill = 0, t_factor = 0;
-
-  template <class T>
-  T *ptr(const Region &r) const {
-    return reinterpret_cast<T *>(ws + r.off);
-  }
-};
-
-namespace {
-
-int fail(vie_ctx *c, int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  if (c) c->err = buf;
-  return code;
-}
-
-#define HIPCK(expr)                                                                            \
-  do {                                                                                         \
-    hipError_t e_ = (expr);                                                                    \
-    if (e_ != hipSuccess) return fail(ctx, VIE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define LAUNCHCK()                                                                                        \
-  do {                                                                                                    \
-    hipError_t e_ = hipGetLastError();                                                                    \
-    if (e_ != hipSuccess) return fail(ctx, VIE_EDEVICE, "kernel launch (line %d): %s", __LINE__, hipGetErrorString(e_)); \
-  } while (0)
+namespace vie {
 
 std::mutex g_static_mu;
 void *g_static_ptr[kMaxDevices] = {};      // device address of `scratch` on each device
@@ -182,7 +56,6 @@ void release_static(vie_ctx *ctx) {
   ctx->static_ws = false;
 }
 
-unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
 
 size_t nested_size(const std::vector<std::vector<int32_t>> &v) {
   size_t s = 0;
@@ -406,7 +279,7 @@ int matvec2(vie_ctx *ctx, const MvVecs &v) {
   return VIE_OK;
 }
 
-}  // namespace
+}  // namespace vie
 
 // ================================================================ C-ABI
 extern "C" {
@@ -523,7 +396,7 @@ size_t vie_workspace_bytes(const vie_ctx *cctx, int precision, int restart) {
 
 }  // extern "C"
 
-namespace {
+namespace vie {
 
 // Bind `bytes` of device memory at dev_ptr as the workspace and upload the
 // mesh tables.  no_alloc: allocate nothing (no pinned host staging either;
@@ -672,7 +545,7 @@ int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int rest
   return VIE_OK;
 }
 
-}  // namespace
+}  // namespace vie
 
 extern "C" {
 
@@ -722,13 +595,22 @@ int vie_bind_static_workspace(vie_ctx *ctx, int precision, int restart) {
   return VIE_OK;
 }
 
-int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
+}  // extern "C"
+
+namespace vie {
+
+// Host part of a fill: the lattice-sum tables of (lambda, theta, phi), the
+// permittivities, the per-tetrahedron coefficients, and Z (with its staging
+// copy and near part) cleared; records ev0.  Decides the form of the far fill.
+// Host-only part of a fill (no device work; any thread): the lattice-sum
+// tables of (lambda, theta, phi) packed for the device, and the internal
+// permittivities.  The previous fill's kernels may still read the device
+// copies: fill_upload waits for them.
+int fill_tables(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
   if (int r = check(ctx, S_BOUND, "vie_fill")) return r;
   if (precision != ctx->precision) return fail(ctx, VIE_EINVAL, "precision does not match the bound workspace");
   if (!eps_per_tet || !(lambda_nm > 0) || !(std::fabs(theta) < 1.5533)) return fail(ctx, VIE_EINVAL, "bad fill arguments");
-  HIPCK(hipSetDevice(ctx->device));
   const MeshTopology &t = ctx->topo;
-  const Layout &L = ctx->L;
   double margin = 0;
   std::string e = build_pgf_table(*ctx->tab, t.a, t.b, t.zmax - t.zmin, lambda_nm, theta, phi, &margin);
   if (!e.empty()) return fail(ctx, VIE_EINVAL, "%s", e.c_str());
@@ -738,30 +620,42 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   ctx->phi = phi;
   ctx->eps_int.resize(t.nt);
   for (int64_t i = 0; i < t.nt; ++i) ctx->eps_int[i] = dz{eps_per_tet[i].re, -eps_per_tet[i].im};
-  // the previous fill's kernels may still read the tables: wait before overwriting
-  HIPCK(hipStreamSynchronize(ctx->stream));
-  HIPCK(hipMemcpyAsync(ctx->ws + L.pgf.off, ctx->tab, sizeof(PgfTable), hipMemcpyHostToDevice, ctx->stream));
   pack_pgf_table(*ctx->tab, ctx->pack);
   if ((int)ctx->pack.size() > kMaxPack)
     return fail(ctx, VIE_EINVAL, "lattice-sum table needs %zu doubles (> %d)", ctx->pack.size(), kMaxPack);
   ctx->packlen = (int)ctx->pack.size();
+  return VIE_OK;
+}
+
+int fill_prepare(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
+  if (int rc = fill_tables(ctx, lambda_nm, theta, phi, eps_per_tet, precision)) return rc;
+  return fill_upload(ctx);
+}
+
+// Device part of a fill's preparation (after fill_tables): tables and
+// permittivities uploaded, per-tetrahedron coefficients, Z (with its staging
+// copy and near part) cleared; records ev0.  Decides the form of the far fill.
+int fill_upload(vie_ctx *ctx) {
+  HIPCK(hipSetDevice(ctx->device));
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const double lambda_nm = ctx->lambda, theta = ctx->theta, phi = ctx->phi;
+  // the previous fill's kernels may still read the tables: wait before overwriting
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->ws + L.pgf.off, ctx->tab, sizeof(PgfTable), hipMemcpyHostToDevice, ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->ws + L.pack.off, ctx->pack.data(), 8 * ctx->pack.size(), hipMemcpyHostToDevice,
                        ctx->stream));
   HIPCK(hipMemcpyAsync(ctx->ws + L.eps.off, ctx->eps_int.data(), 16 * t.nt, hipMemcpyHostToDevice, ctx->stream));
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
 
-  const double *pk_ = ctx->ptr<double>(L.pack);
-  const int pkl = ctx->packlen;
-  const size_t lds = 8 * (size_t)pkl;
-  const QuadRules *qr = ctx->ptr<QuadRules>(L.quad);
   const TetGeom *tg = ctx->ptr<TetGeom>(L.tg);
   const TetFace *t2f = ctx->ptr<TetFace>(L.t2f);
   dz *alpha = ctx->ptr<dz>(L.alpha), *gsrc = ctx->ptr<dz>(L.gsrc), *kappa = ctx->ptr<dz>(L.kappa),
      *inveps = ctx->ptr<dz>(L.inveps), *sigma = ctx->ptr<dz>(L.sigma);
-  const ZOut zo = zout(ctx);
   const double k0 = 2 * M_PI / lambda_nm;
-  const double k0sq9 = k0 * k0 / 9.0;
   const double kx = k0 * std::sin(theta) * std::cos(phi), ky = k0 * std::sin(theta) * std::sin(phi);
+  ctx->fill_k0sq9 = k0 * k0 / 9.0;
+  ctx->fill_lds = 8 * (size_t)ctx->packlen;
 
   hipLaunchKernelGGL(k_prep, dim3(nblk(t.nt, 256)), dim3(256), 0, ctx->stream, (int64_t)t.nt, t2f, tg,
                      ctx->ptr<double>(L.area), ctx->ptr<dz>(L.eps), kx, ky, t.a, t.b, alpha, gsrc, kappa, inveps);
@@ -779,25 +673,49 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   const bool kt0 = kx == 0.0 && ky == 0.0;
   // (the oblique form keeps 32 KB per block of the swapped moments in LDS
   // beside the table; a table too large for both runs the plain fill)
-  const bool sym = L.Zt.bytes > 0 && (kt0 || lds + kFarRevLds <= 65536);
-  const bool sym_face = sym && kt0;
-  const int rev = kt0 ? 0 : 1;
-  ctx->last_sym = sym;
-  ZOut zt = zout(ctx);
-  if (sym) {
-    if (ctx->precision == VIE_MIXED_FP32) zt.Zs = ctx->ptr<fz>(L.Zt);
-    else zt.Z = ctx->ptr<dz>(L.Zt);
+  ctx->fill_sym = L.Zt.bytes > 0 && (kt0 || ctx->fill_lds + kFarRevLds <= 65536);
+  ctx->fill_sym_face = ctx->fill_sym && kt0;
+  ctx->fill_rev = kt0 ? 0 : 1;
+  ctx->last_sym = ctx->fill_sym;
+  if (ctx->fill_sym)
     hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Zt), (int64_t)(L.Zt.bytes / 16));
-  }
   // clear Z (and the near part): the fill accumulates into it
   hipLaunchKernelGGL(k_zero, dim3(4096), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.Z), (int64_t)(L.Z.bytes / 16));
   if (L.nval.bytes)
     hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, ctx->stream, ctx->ptr<dz>(L.nval), (int64_t)(L.nval.bytes / 16));
   LAUNCHCK();
+  return VIE_OK;
+}
+
+// The staging copy of Z as a fill destination (the swapped blocks).
+ZOut zout_staging(vie_ctx *ctx) {
+  ZOut zt = zout(ctx);
+  if (ctx->fill_sym) {
+    if (ctx->precision == VIE_MIXED_FP32) zt.Zs = ctx->ptr<fz>(ctx->L.Zt);
+    else zt.Z = ctx->ptr<dz>(ctx->L.Zt);
+  }
+  return zt;
+}
+
+// One context's fill kernels: far tet pairs (all colour pairs), touching
+// pairs, face pairs; events between the groups time each kernel family.
+int fill_kernels(vie_ctx *ctx) {
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const double *pk_ = ctx->ptr<double>(L.pack);
+  const int pkl = ctx->packlen;
+  const size_t lds = ctx->fill_lds;
+  const QuadRules *qr = ctx->ptr<QuadRules>(L.quad);
+  const TetGeom *tg = ctx->ptr<TetGeom>(L.tg);
+  const TetFace *t2f = ctx->ptr<TetFace>(L.t2f);
+  const dz *alpha = ctx->ptr<dz>(L.alpha), *gsrc = ctx->ptr<dz>(L.gsrc), *kappa = ctx->ptr<dz>(L.kappa),
+           *inveps = ctx->ptr<dz>(L.inveps), *sigma = ctx->ptr<dz>(L.sigma);
+  const ZOut zo = zout(ctx), zt = zout_staging(ctx);
+  const double k0sq9 = ctx->fill_k0sq9;
+  const bool sym = ctx->fill_sym, sym_face = ctx->fill_sym_face;
+  const int rev = ctx->fill_rev;
   const int C = t.ncolors;
   const int32_t *colors = ctx->ptr<int32_t>(L.colors);
-  // far tet pairs (all colour pairs), then touching pairs, then face pairs;
-  // events between the groups time each kernel family
   HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
   int far_launches = 0;
   for (int ct = 0; ct < C; ++ct)
@@ -808,26 +726,25 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
       if (sym && rev)
         hipLaunchKernelGGL(k_tt_far_rev, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds + kFarRevLds, ctx->stream,
                            pk_, pkl, qr, tg, t2f, colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS,
-                           (const dz *)alpha, (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
+                           alpha, gsrc, kappa, k0sq9, zo, zt, mode);
       else
         hipLaunchKernelGGL(k_tt_far, dim3(nblk(nS, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
-                           t2f, colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, (const dz *)alpha,
-                           (const dz *)gsrc, (const dz *)kappa, k0sq9, zo, zt, mode);
+                           t2f, colors + ctx->color_off[ct], nT, colors + ctx->color_off[cs], nS, alpha, gsrc, kappa,
+                           k0sq9, zo, zt, mode);
       LAUNCHCK();
       ++far_launches;
     }
+  ctx->fstats.far_launches = far_launches;
   HIPCK(hipEventRecord(ctx->ev3, ctx->stream));
   for (int g = 0; g < C * C; ++g) {
     const int np = ctx->near_off[g + 1] - ctx->near_off[g];
     if (!np) continue;
     hipLaunchKernelGGL(k_tt_near, dim3(nblk(16 * (int64_t)np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                        ctx->ptr<int32_t>(L.near_t) + ctx->near_off[g], ctx->ptr<int32_t>(L.near_s) + ctx->near_off[g],
-                       ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, (const dz *)alpha, (const dz *)gsrc,
-                       (const dz *)kappa, (const dz *)inveps, k0sq9, zo);
+                       ctx->ptr<int32_t>(L.near_m) + ctx->near_off[g], np, alpha, gsrc, kappa, inveps, k0sq9, zo);
     LAUNCHCK();
   }
-  hipEvent_t evn = ctx->ev4;
-  HIPCK(hipEventRecord(evn, ctx->stream));
+  HIPCK(hipEventRecord(ctx->ev4, ctx->stream));
   if (ctx->nface) {
     const FaceGeom *fg = ctx->ptr<FaceGeom>(L.fg);
     // per test colour: the far pairs, then the touching ones from their list
@@ -835,13 +752,13 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
       hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
-                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, (const dz *)alpha, (const dz *)sigma,
-                         (const dz *)gsrc, (const dz *)kappa, zo, zt, sym_face ? 1 : 0);
+                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, alpha, sigma, gsrc, kappa, zo, zt,
+                         sym_face ? 1 : 0);
       const int np = ctx->tf_off[ct + 1] - ctx->tf_off[ct];
       if (np)
         hipLaunchKernelGGL(k_tet_face_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
                            (const int32_t *)ctx->ptr<int32_t>(L.near_tf) + 2 * (int64_t)ctx->tf_off[ct], np, fg,
-                           (const dz *)alpha, (const dz *)sigma, zo);
+                           alpha, sigma, zo);
       LAUNCHCK();
     }
     if (ctx->nhalf) {
@@ -850,20 +767,31 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
         if (!sym_face)   // (at kt = 0 with the staging the far pairs came from k_tet_face)
           hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
                              qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
-                             (const dz *)gsrc, (const dz *)kappa, zo);
+                             gsrc, kappa, zo);
         const int np = ctx->ft_off[cs + 1] - ctx->ft_off[cs];
         if (np)
           hipLaunchKernelGGL(k_face_tet_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, fg,
                              ctx->ptr<int32_t>(L.half), tg, t2f,
-                             (const int32_t *)ctx->ptr<int32_t>(L.near_ft) + 2 * (int64_t)ctx->ft_off[cs], np,
-                             (const dz *)gsrc, (const dz *)kappa, zo);
+                             (const int32_t *)ctx->ptr<int32_t>(L.near_ft) + 2 * (int64_t)ctx->ft_off[cs], np, gsrc,
+                             kappa, zo);
         LAUNCHCK();
       }
       hipLaunchKernelGGL(k_face_face, dim3(nblk(ctx->nface, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_,
-                         pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, (const dz *)sigma, zo);
+                         pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, sigma, zo);
       LAUNCHCK();
     }
   }
+  return VIE_OK;
+}
+
+// End of a fill: the staging copy added transposed, ev1, the work counts
+// (and, when `timed`, each kernel family's time from the events of
+// fill_kernels); the context becomes S_FILLED.
+int fill_finish(vie_ctx *ctx, bool timed) {
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const bool sym = ctx->fill_sym;
+  const int rev = ctx->fill_rev;
   if (sym) {
     const dim3 tg2(nblk(t.N, 32), nblk(t.N, 32));
     if (ctx->precision == VIE_MIXED_FP32)
@@ -876,12 +804,19 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   }
   HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   HIPCK(hipEventSynchronize(ctx->ev1));
-  float ms = 0, mfar = 0, mnear = 0, mface = 0;
-  HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  HIPCK(hipEventElapsedTime(&mfar, ctx->ev2, ctx->ev3));
-  HIPCK(hipEventElapsedTime(&mnear, ctx->ev3, evn));
-  HIPCK(hipEventElapsedTime(&mface, evn, ctx->ev1));
-  ctx->t_fill = ms;
+  vie_fill_stats &st = ctx->fstats;
+  if (timed) {
+    float ms = 0, mfar = 0, mnear = 0, mface = 0;
+    HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    HIPCK(hipEventElapsedTime(&mfar, ctx->ev2, ctx->ev3));
+    HIPCK(hipEventElapsedTime(&mnear, ctx->ev3, ctx->ev4));
+    HIPCK(hipEventElapsedTime(&mface, ctx->ev4, ctx->ev1));
+    ctx->t_fill = ms;
+    st.t_fill_ms = ms;
+    st.t_far_ms = mfar;
+    st.t_near_ms = mnear;
+    st.t_face_ms = mface;
+  }
   // algorithmic work of the far tet-pair kernel (cost model, FMA = 2 FLOPs):
   // per point pair: separation and wrap 12; per image 27 + 3 deg (X, Y, R^2,
   // rsqrt counted as 8, the fit argument from R, Clenshaw, scale,
@@ -894,7 +829,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   // incidence one evaluation serving both also forms g_p at the reversed
   // separations (per point pair 4 per propagating order + 10) and the swapped
   // pair's moments (16 x 36 per tet pair).
-  double pp = 12 + (kt0 ? 132 : 212) + 6;
+  double pp = 12 + (rev ? 212 : 132) + 6;
   const PgfTable &tb = *ctx->tab;
   for (int i = 0; i < tb.nimg; ++i) pp += 27 + 3 * tb.img[i].deg;
   int nmodes = 0, ncplx = 0;
@@ -907,16 +842,10 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   if (sym && rev) pp += 10 + 4 * ncplx;
   int64_t nnear = 0;
   for (auto &v : t.near_t) nnear += (int64_t)v.size();
-  vie_fill_stats &st = ctx->fstats;
-  st.t_fill_ms = ms;
-  st.t_far_ms = mfar;
-  st.t_near_ms = mnear;
-  st.t_face_ms = mface;
   // pairs evaluated (near-ness is symmetric and includes every self pair)
   st.far_pairs = sym ? (t.nt * t.nt - nnear) / 2 : t.nt * t.nt - nnear;
   st.near_pairs = nnear;
   st.face_pairs = (int64_t)t.nt * ctx->nface + (int64_t)ctx->nhalf * t.nt + (int64_t)ctx->nhalf * ctx->nface;
-  st.far_launches = far_launches;
   st.far_symmetric = sym ? 1 : 0;
   st.point_pair_flops = pp;
   st.far_flops = (double)st.far_pairs * (16.0 * pp + (sym ? 2400.0 : 1200.0) + (sym && rev ? 16.0 * 36 : 0.0));
@@ -927,20 +856,30 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
   return VIE_OK;
 }
 
+}  // namespace vie
+
+extern "C" {
+
+int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie_c128 *eps_per_tet, int precision) {
+  if (int rc = fill_prepare(ctx, lambda_nm, theta, phi, eps_per_tet, precision)) return rc;
+  if (int rc = fill_kernels(ctx)) return rc;
+  return fill_finish(ctx, true);
+}
+
 // ---------------------------------------------------------------- factor
 }  // extern "C"
 
-namespace {
+namespace vie {
 
 enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_TSEL, LU_TFIN };
 
-// One launch of an LU kernel over every domain with blocks_of(d) > 0 thread
-// blocks (kLuMaxDom domains per launch; more domains take more launches).
-// (GEMM: column tiles gcol0 .. gcol0 + gcols - 1 of the trailing matrix,
-// gcols <= 0 for all from gcol0; stream: the context's unless given.)
+// One launch of an LU kernel (FP32 factors if f32) on stream sm over every
+// domain with blocks_of(d) > 0 thread blocks (kLuMaxDom domains per launch;
+// more domains take more launches).  (GEMM: column tiles gcol0 .. gcol0 +
+// gcols - 1 of the trailing matrix, gcols <= 0 for all from gcol0.)
 template <typename BlocksOf>
-void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of,
-               int all_cols = 0, int gcol0 = 0, int gcols = 0, hipStream_t stream = nullptr, bool own = false) {
+void lu_launch(bool f32, hipStream_t sm, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of,
+               int all_cols = 0, int gcol0 = 0, int gcols = 0) {
   LuStep st{};
   st.j = j;
   st.k0 = k0;
@@ -948,10 +887,8 @@ void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, 
   st.gcol0 = gcol0;
   st.gcols = gcols;
   int total = 0;
-  const hipStream_t sm = own ? stream : ctx->stream;
   auto flush = [&]() {
     if (st.ndom == 0) return;
-    const bool f32 = fp32_factors(ctx);
     switch (k) {
       case LU_PIVOT:
         if (f32) hipLaunchKernelGGL(k_lu_pivot_c, dim3(total), dim3(1024), 0, sm, st);
@@ -996,27 +933,32 @@ void lu_launch(vie_ctx *ctx, LuKernel k, const std::vector<LuDom> &doms, int j, 
   flush();
 }
 
-}  // namespace
+}  // namespace vie
 
 extern "C" {
 
-int vie_precond_factor(vie_ctx *ctx) {
+}  // extern "C"
+
+namespace vie {
+
+// The domain descriptors of the block factorisation (Sec. 2.3, Eq. 6) and
+// each diagonal block A_dd copied (with the FP64 near part in mixed
+// precision) into the factor storage; records ev0.
+int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
   if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
   HIPCK(hipSetDevice(ctx->device));
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
   const ZOut zo = zout(ctx);
   const bool f32 = fp32_factors(ctx);
-  int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *perm = ctx->ptr<int32_t>(L.perm), *info = ctx->ptr<int32_t>(L.info);
+  int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *info = ctx->ptr<int32_t>(L.info);
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(hipMemsetAsync(info, 0, 4 * t.ndom, ctx->stream));
-  std::vector<LuDom> doms(t.ndom);
+  doms.assign(t.ndom, LuDom{});
   int64_t poff = 0, pvoff = 0;
-  int maxn = 0;
   for (int d = 0; d < t.ndom; ++d) {
     const int n = (int)(t.dend[d] - t.dstart[d]);
     LuDom &D = doms[d];
-    D = LuDom{};
     D.A = factor_ptr(ctx, L.F, L.foff[d]);
     D.ld = L.fld[d];
     D.n = n;
@@ -1031,7 +973,6 @@ int vie_precond_factor(vie_ctx *ctx) {
     D.tblk = factor_ptr(ctx, L.tblk, (int64_t)d * kLuNB * kLuNB);
     poff += n;
     pvoff += nblk(n, kColRows);
-    maxn = std::max(maxn, n);
     if (n == 0) continue;
     const dim3 cg(nblk(n, 256), std::min(n, 32768)), ng(nblk(n, 256)), b256(256);
     if (f32) {
@@ -1043,16 +984,23 @@ int vie_precond_factor(vie_ctx *ctx) {
     }
     LAUNCHCK();
   }
-  // right-looking blocked LU of every domain, advanced together panel by panel
-  // With tournament pivoting the next panel's pivot search runs ahead: after
-  // the trailing update of that panel's own columns, its tournament goes to
-  // the side stream while the update of the remaining columns runs, and the
-  // next panel's row swaps wait for it.
-  const bool ahead = ctx->lu_pivot == 0;
+  return VIE_OK;
+}
+
+// Right-looking blocked LU of every domain in `doms` (any number of
+// contexts' domains, all FP32 or all FP64 factors), advanced together panel
+// by panel on `stream`.  With tournament pivoting the next panel's pivot
+// search runs ahead: after the trailing update of that panel's own columns,
+// its tournament goes to the side stream while the update of the remaining
+// columns runs, and the next panel's row swaps wait for it.
+int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot, hipStream_t stream,
+                  hipStream_t side, hipEvent_t ev_la, hipEvent_t ev_ts) {
+  int maxn = 0;
+  for (const LuDom &D : doms) maxn = std::max(maxn, D.n);
+  const bool ahead = lu_pivot == 0;
   const int ts_rows = f32 ? kTsRowsC : kTsRowsZ;
-  auto tsel = [&](int kp, hipStream_t stream, bool own) {
-    lu_launch(ctx, LU_TSEL, doms, kp, kp, [&](int d) { return doms[d].n > kp ? (int)nblk(doms[d].n - kp, ts_rows) : 0; },
-              0, 0, 0, stream, own);
+  auto tsel = [&](int kp, hipStream_t sm) {
+    lu_launch(f32, sm, LU_TSEL, doms, kp, kp, [&](int d) { return doms[d].n > kp ? (int)nblk(doms[d].n - kp, ts_rows) : 0; });
   };
   // trailing-update tiles of domain d at panel k0: row tiles x column tiles gcol0 .. (gcols <= 0: to the end)
   auto gemm_blocks = [&](int d, int k0, int gcol0, int gcols) {
@@ -1064,42 +1012,53 @@ int vie_precond_factor(vie_ctx *ctx) {
   for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
     auto jb_of = [&](int d) { return std::min(kLuNB, doms[d].n - k0); };
     auto swap_blocks = [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
-    if (ctx->lu_pivot == 0) {
+    if (lu_pivot == 0) {
       // tournament pivoting: pivot rows by a reduction tree, swap whole rows,
       // then L21 = A21 U11^-1 below the factored top block
-      if (k0 == 0) tsel(k0, nullptr, false);
-      else HIPCK(hipStreamWaitEvent(ctx->stream, ctx->ev_ts, 0));   // issued ahead on the side stream
-      lu_launch(ctx, LU_SWAP, doms, k0, k0, swap_blocks, 1);
-      lu_launch(ctx, LU_TFIN, doms, k0, k0, [&](int d) {
+      if (k0 == 0) tsel(k0, stream);
+      else HIPCK(hipStreamWaitEvent(stream, ev_ts, 0));   // issued ahead on the side stream
+      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks, 1);
+      lu_launch(f32, stream, LU_TFIN, doms, k0, k0, [&](int d) {
         if (doms[d].n <= k0) return 0;
         const int rest = doms[d].n - k0 - jb_of(d);
         return rest > 0 ? (int)nblk(rest, kColRows) : 1;
       });
     } else {
-      lu_launch(ctx, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
+      lu_launch(f32, stream, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
       for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
-        lu_launch(ctx, LU_COL, doms, j, k0, [&](int d) {
+        lu_launch(f32, stream, LU_COL, doms, j, k0, [&](int d) {
           const int n = doms[d].n;
           return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
         });
-      lu_launch(ctx, LU_SWAP, doms, k0, k0, swap_blocks);
+      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks);
     }
-    lu_launch(ctx, LU_TRSM, doms, k0, k0, [&](int d) {
+    lu_launch(f32, stream, LU_TRSM, doms, k0, k0, [&](int d) {
       const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
       return rest > 0 ? (int)nblk(rest, kColRows) : 0;
     });
     if (ahead && k0 + kLuNB < maxn) {
-      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
-      HIPCK(hipEventRecord(ctx->ev_la, ctx->stream));
-      HIPCK(hipStreamWaitEvent(ctx->side, ctx->ev_la, 0));
-      tsel(k0 + kLuNB, ctx->side, true);
-      HIPCK(hipEventRecord(ctx->ev_ts, ctx->side));
-      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0); }, 0, 1, 0);
+      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
+      HIPCK(hipEventRecord(ev_la, stream));
+      HIPCK(hipStreamWaitEvent(side, ev_la, 0));
+      tsel(k0 + kLuNB, side);
+      HIPCK(hipEventRecord(ev_ts, side));
+      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0); }, 0, 1, 0);
     } else {
-      lu_launch(ctx, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
+      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
     }
     LAUNCHCK();
   }
+  return VIE_OK;
+}
+
+// After the panels: the transposed inverses of the 256-row diagonal blocks of
+// L and U, the pivots read back (zero pivot: VIE_ESINGULAR), each block's row
+// permutation built on the host and uploaded; the context becomes S_FACTORED.
+int factor_finish(vie_ctx *ctx, const std::vector<LuDom> &doms) {
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  const bool f32 = fp32_factors(ctx);
+  int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *perm = ctx->ptr<int32_t>(L.perm), *info = ctx->ptr<int32_t>(L.info);
   for (int d = 0; d < t.ndom; ++d) {
     const int n = doms[d].n;
     if (n == 0) continue;
@@ -1150,10 +1109,23 @@ int vie_precond_factor(vie_ctx *ctx) {
   return VIE_OK;
 }
 
+}  // namespace vie
+
+extern "C" {
+
+int vie_precond_factor(vie_ctx *ctx) {
+  std::vector<LuDom> doms;
+  if (int rc = factor_prepare(ctx, doms)) return rc;
+  if (int rc = factor_panels(ctx, doms, fp32_factors(ctx), ctx->lu_pivot, ctx->stream, ctx->side, ctx->ev_la,
+                             ctx->ev_ts))
+    return rc;
+  return factor_finish(ctx, doms);
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- solve
-namespace {
+namespace vie {
 
 // The step list of the blocked triangular solves (L sweep, then U sweep) for
 // nv (1 or 2) right-hand sides; step k advances every domain (kTrsvMaxDom per
@@ -1669,7 +1641,7 @@ int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int rest
   return VIE_OK;
 }
 
-}  // namespace
+}  // namespace vie
 
 extern "C" {
 

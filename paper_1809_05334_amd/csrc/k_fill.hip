@@ -151,17 +151,17 @@ __device__ __forceinline__ void tt_far_body(const double *__restrict__ pack, int
                                             int ntest, const int32_t *__restrict__ src_list, int nsrc,
                                             const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
                                             const dz *__restrict__ kappa, double k0sq9, const ZOut &out,
-                                            const ZOut &outT, int sym) {
+                                            const ZOut &outT, int sym, int bx_, int by_) {
   extern __shared__ double s_tab[];
   // one list against itself: a block whose source positions all lie at or
   // below its test positions has nothing to do (the whole block returns)
-  if (sym == 2 && (int)blockIdx.x * 64 + 63 <= (int)blockIdx.y * 4) return;
+  if (sym == 2 && bx_ * 64 + 63 <= by_ * 4) return;
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
   double *__restrict__ mr = s_tab + ((packlen + 1) & ~1) + threadIdx.x;   // REV: entry e at mr[256 e]
 
-  const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int si = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int ti = uniform(by_ * 4 + (threadIdx.x >> 6));
+  const int si = bx_ * 64 + (threadIdx.x & 63);
   if (ti >= ntest || si >= nsrc) return;
   if (sym == 2 && si <= ti) return;
   const int T = uniform(test_list[ti]);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256, 2) void k_tt_far(const double *__restrict__ pa
                                                 const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
                                                 int sym) {
   tt_far_body<false>(pack, packlen, qr, tg, t2f, test_list, ntest, src_list, nsrc, alpha, gsrc, kappa, k0sq9, out,
-                     outT, sym);
+                     outT, sym, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(256, 2) void k_tt_far_rev(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void k_tt_far_rev(const double *__restrict_
                                                     const dz *__restrict__ kappa, double k0sq9, ZOut out, ZOut outT,
                                                     int sym) {
   tt_far_body<true>(pack, packlen, qr, tg, t2f, test_list, ntest, src_list, nsrc, alpha, gsrc, kappa, k0sq9, out,
-                    outT, sym);
+                    outT, sym, blockIdx.x, blockIdx.y);
 }
 
 // Z[i][j] += Zt[j][i]: 32 x 32 tiles through shared memory, both sides read
@@ -326,18 +326,18 @@ __global__ __launch_bounds__(256) void k_transpose_add_c(fz *Z, const fz *Zt, in
 // across the 16 lanes by shuffles, and the pair's first lane scatters.
 __device__ __forceinline__ dz shfl_xor_dz(dz v, int o) { return mk(__shfl_xor(v.re, o), __shfl_xor(v.im, o)); }
 
-__global__ __launch_bounds__(256) void k_tt_near(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__device__ __forceinline__ void k_tt_near_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                  const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                  const int32_t *__restrict__ lt, const int32_t *__restrict__ ls,
                                                  const int32_t *__restrict__ lmask, int npairs,
                                                  const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
                                                  const dz *__restrict__ kappa, const dz *__restrict__ inv_eps,
-                                                 double k0sq9, ZOut out) {
+                                                 double k0sq9, ZOut out, int bx_, int by_) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = bx_ * blockDim.x + threadIdx.x;
   const int i = gid >> 4, q = gid & 15;
   const bool act = i < npairs;
   // lanes past the last pair stay in the shuffles below with zero moments
@@ -427,6 +427,16 @@ __global__ __launch_bounds__(256) void k_tt_near(const double *__restrict__ pack
       }
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_tt_near(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                 const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                 const int32_t *__restrict__ lt, const int32_t *__restrict__ ls,
+                                                 const int32_t *__restrict__ lmask, int npairs,
+                                                 const dz *__restrict__ alpha, const dz *__restrict__ gsrc,
+                                                 const dz *__restrict__ kappa, const dz *__restrict__ inv_eps,
+                                                 double k0sq9, ZOut out) {
+  k_tt_near_body(pack, packlen, qr, tg, t2f, lt, ls, lmask, npairs, alpha, gsrc, kappa, inv_eps, k0sq9, out, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------ pairs with faces
@@ -629,19 +639,19 @@ __device__ __forceinline__ void tet_face_pair(const double *__restrict__ P, cons
 // transposed position of outT (rows of T's unknowns, columns of faces: the
 // same conflict-free pattern as the tet-face entries); the staging copy is
 // added transposed after the fill's other kernels.
-__global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__device__ __forceinline__ void k_tet_face_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
                                                   const FaceGeom *__restrict__ fg, int nface,
                                                   const dz *__restrict__ alpha, const dz *__restrict__ sigma,
                                                   const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
-                                                  ZOut out, ZOut outT, int swap) {
+                                                  ZOut out, ZOut outT, int swap, int bx_, int by_) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
-  const int ti = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int fi = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int ti = uniform(by_ * 4 + (threadIdx.x >> 6));
+  const int fi = bx_ * 64 + (threadIdx.x & 63);
   if (ti >= ntest || fi >= nface) return;
   const int T = uniform(test_list[ti]);
   const TetGeom &gt = tg[T];
@@ -657,20 +667,39 @@ __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ 
   }
 }
 
+__global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                  const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                  const int32_t *__restrict__ test_list, int ntest,
+                                                  const FaceGeom *__restrict__ fg, int nface,
+                                                  const dz *__restrict__ alpha, const dz *__restrict__ sigma,
+                                                  const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                  ZOut out, ZOut outT, int swap) {
+  k_tet_face_body(pack, packlen, qr, tg, t2f, test_list, ntest, fg, nface, alpha, sigma, gsrc, kappa, out, outT, swap, blockIdx.x, blockIdx.y);
+}
+
 // touching (test tet, surface-charge face) pairs of one test colour, one lane each
+__device__ __forceinline__ void k_tet_face_near_body(const double *__restrict__ pack, int packlen,
+                                                       const QuadRules *__restrict__ qr, const TetGeom *__restrict__ tg,
+                                                       const TetFace *__restrict__ t2f, const int32_t *__restrict__ pairs,
+                                                       int npairs, const FaceGeom *__restrict__ fg,
+                                                       const dz *__restrict__ alpha, const dz *__restrict__ sigma,
+                                                       ZOut out, int bx_, int by_) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const int i = bx_ * 256 + threadIdx.x;
+  if (i >= npairs) return;
+  const int T = pairs[2 * i], fi = pairs[2 * i + 1];
+  const FaceGeom f = fg[fi];
+  tet_face_pair(s_tab, qr, tg[T], t2f, T, f, fi, alpha, sigma, out);
+}
+
 __global__ __launch_bounds__(256, 2) void k_tet_face_near(const double *__restrict__ pack, int packlen,
                                                        const QuadRules *__restrict__ qr, const TetGeom *__restrict__ tg,
                                                        const TetFace *__restrict__ t2f, const int32_t *__restrict__ pairs,
                                                        int npairs, const FaceGeom *__restrict__ fg,
                                                        const dz *__restrict__ alpha, const dz *__restrict__ sigma,
                                                        ZOut out) {
-  extern __shared__ double s_tab[];
-  stage_table(pack, packlen, s_tab);
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= npairs) return;
-  const int T = pairs[2 * i], fi = pairs[2 * i + 1];
-  const FaceGeom f = fg[fi];
-  tet_face_pair(s_tab, qr, tg[T], t2f, T, f, fi, alpha, sigma, out);
+  k_tet_face_near_body(pack, packlen, qr, tg, t2f, pairs, npairs, fg, alpha, sigma, out, blockIdx.x, blockIdx.y);
 }
 
 // half-SWG test face x source tet (colour class list): Z[m_F, n_l(S)] -= gsrc_Sl kappa_S M0.
@@ -684,18 +713,18 @@ __device__ __forceinline__ void face_tet_pair(const double *__restrict__ P, cons
   for (int l = 0; l < 4; ++l) zput(out, f.unknown, t2f[4 * S + l].unknown, mk(0, 0) - gsrc[4 * S + l] * m0, mask != 0);
 }
 
-__global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__device__ __forceinline__ void k_face_tet_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
                                                   int nhalf, const TetGeom *__restrict__ tg,
                                                   const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
                                                   int nsrc, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
-                                                  ZOut out) {
+                                                  ZOut out, int bx_, int by_) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
-  const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int si = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int hi = uniform(by_ * 4 + (threadIdx.x >> 6));
+  const int si = bx_ * 64 + (threadIdx.x & 63);
   if (hi >= nhalf || si >= nsrc) return;
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const int S = src_list[si];
@@ -704,17 +733,26 @@ __global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ 
   face_tet_pair(s_tab, qr, f, gs, t2f, S, gsrc, kappa, out);
 }
 
+__global__ __launch_bounds__(256, 2) void k_face_tet(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                  const FaceGeom *__restrict__ fg, const int32_t *__restrict__ half_list,
+                                                  int nhalf, const TetGeom *__restrict__ tg,
+                                                  const TetFace *__restrict__ t2f, const int32_t *__restrict__ src_list,
+                                                  int nsrc, const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                  ZOut out) {
+  k_face_tet_body(pack, packlen, qr, fg, half_list, nhalf, tg, t2f, src_list, nsrc, gsrc, kappa, out, blockIdx.x, blockIdx.y);
+}
+
 // touching (half-SWG test face, source tet) pairs of one source colour, one lane each
-__global__ __launch_bounds__(256, 2) void k_face_tet_near(const double *__restrict__ pack, int packlen,
+__device__ __forceinline__ void k_face_tet_near_body(const double *__restrict__ pack, int packlen,
                                                        const QuadRules *__restrict__ qr, const FaceGeom *__restrict__ fg,
                                                        const int32_t *__restrict__ half_list,
                                                        const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                        const int32_t *__restrict__ pairs, int npairs,
                                                        const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
-                                                       ZOut out) {
+                                                       ZOut out, int bx_, int by_) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = bx_ * 256 + threadIdx.x;
   if (i >= npairs) return;
   const int hi = pairs[2 * i], S = pairs[2 * i + 1];
   const FaceGeom f = fg[half_list[hi]];
@@ -722,17 +760,27 @@ __global__ __launch_bounds__(256, 2) void k_face_tet_near(const double *__restri
   face_tet_pair(s_tab, qr, f, gs, t2f, S, gsrc, kappa, out);
 }
 
+__global__ __launch_bounds__(256, 2) void k_face_tet_near(const double *__restrict__ pack, int packlen,
+                                                       const QuadRules *__restrict__ qr, const FaceGeom *__restrict__ fg,
+                                                       const int32_t *__restrict__ half_list,
+                                                       const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
+                                                       const int32_t *__restrict__ pairs, int npairs,
+                                                       const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                       ZOut out) {
+  k_face_tet_near_body(pack, packlen, qr, fg, half_list, tg, t2f, pairs, npairs, gsrc, kappa, out, blockIdx.x, blockIdx.y);
+}
+
 // half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
-__global__ __launch_bounds__(256, 2) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+__device__ __forceinline__ void k_face_face_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                    const FaceGeom *__restrict__ fg,
                                                    const int32_t *__restrict__ half_list, int nhalf, int nface,
-                                                   const dz *__restrict__ sigma, ZOut out) {
+                                                   const dz *__restrict__ sigma, ZOut out, int bx_, int by_) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const double *__restrict__ P = s_tab;
 
-  const int hi = uniform(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int hi = uniform(by_ * 4 + (threadIdx.x >> 6));
+  const int gi = bx_ * 64 + (threadIdx.x & 63);
   if (hi >= nhalf || gi >= nface) return;
   const FaceGeom &f = fg[uniform(half_list[hi])];
   const FaceGeom g = fg[gi];
@@ -740,6 +788,72 @@ __global__ __launch_bounds__(256, 2) void k_face_face(const double *__restrict__
   const dz m0 = pair_face_face(s_tab, qr, f, g, mask);
   zput(out, f.unknown, g.unknown, sigma[gi] * m0, mask != 0);
 }
+
+__global__ __launch_bounds__(256, 2) void k_face_face(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
+                                                   const FaceGeom *__restrict__ fg,
+                                                   const int32_t *__restrict__ half_list, int nhalf, int nface,
+                                                   const dz *__restrict__ sigma, ZOut out) {
+  k_face_face_body(pack, packlen, qr, fg, half_list, nhalf, nface, sigma, out, blockIdx.x, blockIdx.y);
+}
+
+// ------------------------------------------------------------ fused multi-cell fill
+// The segment of fused-grid block b (segments ordered by their first block).
+template <class S>
+__device__ __forceinline__ int seg_of(const S *__restrict__ segs, int nseg, int b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return uniform(lo);
+}
+
+#define VIE_SEG_BEGIN(S)                                  \
+  const int s_ = seg_of(segs, nseg, (int)blockIdx.x);     \
+  const S &A = segs[s_];                                  \
+  const int lb_ = (int)blockIdx.x - A.first;              \
+  const int bx = lb_ % A.gx, by = lb_ / A.gx;
+
+__global__ __launch_bounds__(256, 2) void k_tt_far_seg(const FarSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(FarSeg)
+  tt_far_body<false>(A.pack, A.packlen, A.qr, A.tg, A.t2f, A.test_list, A.ntest, A.src_list, A.nsrc, A.alpha, A.gsrc,
+                     A.kappa, A.k0sq9, A.out, A.outT, A.sym, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_tt_far_rev_seg(const FarSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(FarSeg)
+  tt_far_body<true>(A.pack, A.packlen, A.qr, A.tg, A.t2f, A.test_list, A.ntest, A.src_list, A.nsrc, A.alpha, A.gsrc,
+                    A.kappa, A.k0sq9, A.out, A.outT, A.sym, bx, by);
+}
+__global__ __launch_bounds__(256) void k_tt_near_seg(const NearSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(NearSeg)
+  k_tt_near_body(A.pack, A.packlen, A.qr, A.tg, A.t2f, A.lt, A.ls, A.lmask, A.npairs, A.alpha, A.gsrc, A.kappa,
+                 A.inv_eps, A.k0sq9, A.out, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_tet_face_seg(const TetFaceSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(TetFaceSeg)
+  k_tet_face_body(A.pack, A.packlen, A.qr, A.tg, A.t2f, A.test_list, A.ntest, A.fg, A.nface, A.alpha, A.sigma, A.gsrc,
+                  A.kappa, A.out, A.outT, A.swap, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_tet_face_near_seg(const TetFaceNearSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(TetFaceNearSeg)
+  k_tet_face_near_body(A.pack, A.packlen, A.qr, A.tg, A.t2f, A.pairs, A.npairs, A.fg, A.alpha, A.sigma, A.out, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_face_tet_seg(const FaceTetSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(FaceTetSeg)
+  k_face_tet_body(A.pack, A.packlen, A.qr, A.fg, A.half_list, A.nhalf, A.tg, A.t2f, A.src_list, A.nsrc, A.gsrc,
+                  A.kappa, A.out, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_face_tet_near_seg(const FaceTetNearSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(FaceTetNearSeg)
+  k_face_tet_near_body(A.pack, A.packlen, A.qr, A.fg, A.half_list, A.tg, A.t2f, A.pairs, A.npairs, A.gsrc, A.kappa,
+                       A.out, bx, by);
+}
+__global__ __launch_bounds__(256, 2) void k_face_face_seg(const FaceFaceSeg *__restrict__ segs, int nseg) {
+  VIE_SEG_BEGIN(FaceFaceSeg)
+  k_face_face_body(A.pack, A.packlen, A.qr, A.fg, A.half_list, A.nhalf, A.nface, A.sigma, A.out, bx, by);
+}
+#undef VIE_SEG_BEGIN
 
 // ------------------------------------------------------------ right-hand side
 // b_m = sum_{T in m} chi s a_m/(3 V_T) int_T (r - p).E^i dV, 14-point rule;

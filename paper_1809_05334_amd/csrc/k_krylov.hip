@@ -68,9 +68,9 @@ __device__ __forceinline__ void stage_x(const MvVecs &v, int64_t c0, int len, dz
 
 template <int RPW, int NV>
 __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld, int64_t N, const MvVecs &v,
-                                            dz *xs) {
+                                            dz *xs, int blk) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
+  const int64_t row0 = ((int64_t)blk * 4 + wave) * RPW;
   double are[NV][RPW], aim[NV][RPW];
 #pragma unroll
   for (int q = 0; q < NV; ++q)
@@ -119,12 +119,12 @@ __device__ __forceinline__ void matvec_body(const dz *__restrict__ Z, int64_t ld
                                                        dz *__restrict__ y) {                                    \
     __shared__ dz xs[kMvChunk];                                                                                 \
     const MvVecs v{{x, nullptr}, {b, nullptr}, {y, nullptr}};                                                   \
-    matvec_body<R, 1>(Z, ld, N, v, xs);                                                                         \
+    matvec_body<R, 1>(Z, ld, N, v, xs, blockIdx.x);                                                                         \
   }                                                                                                             \
   __global__ __launch_bounds__(256) void k_matvec2_r##R(const dz *__restrict__ Z, int64_t ld, int64_t N,        \
                                                         MvVecs v) {                                             \
     __shared__ dz xs[2 * kMvChunk];                                                                             \
-    matvec_body<R, 2>(Z, ld, N, v, xs);                                                                         \
+    matvec_body<R, 2>(Z, ld, N, v, xs, blockIdx.x);                                                                         \
   }
 VIE_MATVEC(2)
 VIE_MATVEC(4)
@@ -141,9 +141,9 @@ template <int RPW, int NV>
 __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int64_t ld, int64_t N,
                                                   const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ cols, const dz *__restrict__ vals,
-                                                  const MvVecs &v, dz *xs) {
+                                                  const MvVecs &v, dz *xs, int blk) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RPW;
+  const int64_t row0 = ((int64_t)blk * 4 + wave) * RPW;
   double are[NV][RPW], aim[NV][RPW];
 #pragma unroll
   for (int q = 0; q < NV; ++q)
@@ -209,13 +209,13 @@ __device__ __forceinline__ void matvec_mixed_body(const fz *__restrict__ Zs, int
       const dz *__restrict__ b, dz *__restrict__ y) {                                                           \
     __shared__ dz xs[kMvChunk];                                                                                 \
     const MvVecs v{{x, nullptr}, {b, nullptr}, {y, nullptr}};                                                   \
-    matvec_mixed_body<R, 1>(Zs, ld, N, rowptr, cols, vals, v, xs);                                              \
+    matvec_mixed_body<R, 1>(Zs, ld, N, rowptr, cols, vals, v, xs, blockIdx.x);                                              \
   }                                                                                                             \
   __global__ __launch_bounds__(256) void k_matvec2_mixed_r##R(                                                  \
       const fz *__restrict__ Zs, int64_t ld, int64_t N, const int64_t *__restrict__ rowptr,                     \
       const int32_t *__restrict__ cols, const dz *__restrict__ vals, MvVecs v) {                                \
     __shared__ dz xs[2 * kMvChunk];                                                                             \
-    matvec_mixed_body<R, 2>(Zs, ld, N, rowptr, cols, vals, v, xs);                                              \
+    matvec_mixed_body<R, 2>(Zs, ld, N, rowptr, cols, vals, v, xs, blockIdx.x);                                              \
   }
 VIE_MATVEC_MIXED(2)
 VIE_MATVEC_MIXED(4)
@@ -482,5 +482,207 @@ __global__ void k_ginit(dz *__restrict__ g, int m1, const double *__restrict__ b
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m1) g[i] = i == 0 ? mk(*beta, 0.0) : mk(0.0, 0.0);
 }
+
+// ------------------------------------------------------------ fused batch
+// The Arnoldi step of many cells at once (one GMRES process per cell): each
+// kernel's grid is the concatenation of the cells' grids (pre[c] .. pre[c+1]
+// are cell c's blocks), and a cell whose flag act[c] is 0 skips the step.
+// Per cell the arithmetic is that of the single-cell kernels, with the
+// two-stage reductions over nred blocks of the cell.
+
+__device__ __forceinline__ int cell_of(const int *__restrict__ pre, int nc, int b) {
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+#define VIE_CELL_BEGIN                                \
+  const int c_ = cell_of(pre, nc, (int)blockIdx.x);   \
+  if (!act[c_]) return;                               \
+  const KryCell &K = cells[c_];                       \
+  const int lb = (int)blockIdx.x - pre[c_];
+
+// vin = V_j
+__global__ void k_b_arn_begin(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                              const int *__restrict__ act) {
+  VIE_CELL_BEGIN
+  const int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (k < K.N) K.vin[k] = K.V[(int64_t)(*K.jd) * K.ldv + k];
+}
+
+// rhs of the triangular solves: tmp[off + i] = vin[off + perm[off + i]] per domain
+__global__ void k_b_permute(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                            const int *__restrict__ act) {
+  VIE_CELL_BEGIN
+  const int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (k >= K.N) return;
+  int64_t off = 0;
+  for (int d = 1; d < K.ndom; ++d)
+    if (k >= K.dstart[d]) off = K.dstart[d];
+  K.tmp[k] = K.vin[off + K.perm[k]];
+}
+
+// w = Z z (the operator of the cell's precision); z = vin when unpreconditioned
+__global__ __launch_bounds__(256) void k_b_matvec(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                                                  const int *__restrict__ act) {
+  __shared__ dz xs[kMvChunk];
+  VIE_CELL_BEGIN
+  const MvVecs v{{K.precond ? K.vin : K.z, nullptr}, {nullptr, nullptr}, {K.w, nullptr}};
+  if (K.Z) matvec_body<4, 1>(K.Z, K.ld, K.N, v, xs, lb);
+  else matvec_mixed_body<4, 1>(K.Zs, K.ld, K.N, K.rowptr, K.cols, K.vals, v, xs, lb);
+}
+
+// partial inner products with V_0 .. V_j: local block (x, y) = chunk x of the
+// cell's nred, basis vectors 8 y .. 8 y + 7
+__global__ __launch_bounds__(256) void k_b_dots_j(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                                                  const int *__restrict__ act) {
+  constexpr int G = 8;
+  __shared__ dz red[G][4];
+  VIE_CELL_BEGIN
+  const int nv = *K.jd + 1;
+  const int bx = lb % K.nred, by = lb / K.nred;
+  const int i0 = by * G;
+  if (i0 >= nv) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t N = K.N, ldv = K.ldv;
+  const int64_t chunk = (N + K.nred - 1) / K.nred;
+  const int64_t lo = bx * chunk, hi = min<int64_t>(N, lo + chunk);
+  double sr[G], si[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) sr[g] = si[g] = 0.0;
+  for (int64_t k = lo + tid; k < hi; k += 256) {
+    const dz ww = K.w[k];
+    double vr[G], vi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const dz v = K.V[(int64_t)min(i0 + g, nv - 1) * ldv + k];
+      vr[g] = v.re;
+      vi[g] = v.im;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sr[g] = fma(vr[g], ww.re, fma(vi[g], ww.im, sr[g]));
+      si[g] = fma(vr[g], ww.im, fma(-vi[g], ww.re, si[g]));
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const double a = wsum(sr[g]), b = wsum(si[g]);
+    if (lane == 0) red[g][wave] = mk(a, b);
+  }
+  __syncthreads();
+  if (tid < G && i0 + tid < nv)
+    K.dpart[(int64_t)bx * nv + i0 + tid] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
+// s_i = sum_b part[b][i]; y_i = s_i; H[i][j] = s_i (pass 0) or += s_i (pass 1)
+__global__ void k_b_dots_reduce_j(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                                  const int *__restrict__ act, int pass) {
+  VIE_CELL_BEGIN
+  const int j = *K.jd, nv = j + 1;
+  const int i = lb * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  dz s = mk(0, 0);
+  for (int b0 = 0; b0 < K.nred; b0 += 16) {
+    double pr[16], pi[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const dz p = K.dpart[(int64_t)min(b0 + u, K.nred - 1) * nv + i];
+      pr[u] = p.re;
+      pi[u] = p.im;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b0 + u < K.nred) s = s + mk(pr[u], pi[u]);
+  }
+  dz *h = K.H + (int64_t)j * K.ldh;
+  h[i] = pass ? h[i] + s : s;
+  K.y[i] = s;
+}
+
+// w -= sum_{i<=j} V_i y_i
+__global__ __launch_bounds__(256) void k_b_update_j(const KryCell *__restrict__ cells, const int *__restrict__ pre,
+                                                    int nc, const int *__restrict__ act) {
+  VIE_CELL_BEGIN
+  const int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (k >= K.N) return;
+  const int nv = *K.jd + 1;
+  dz s = K.w[k];
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    double vr[8], vi[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const dz v = K.V[(int64_t)min(i0 + g, nv - 1) * K.ldv + k];
+      vr[g] = v.re;
+      vi[g] = v.im;
+    }
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      if (i0 + g < nv) s = s - mk(vr[g], vi[g]) * K.y[i0 + g];
+  }
+  K.w[k] = s;
+}
+
+// partial squared norms of w over the cell's nred chunks
+__global__ __launch_bounds__(256) void k_b_norm2(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                                                 const int *__restrict__ act) {
+  __shared__ double red[4];
+  VIE_CELL_BEGIN
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = (K.N + K.nred - 1) / K.nred;
+  const int64_t lo = lb * chunk, hi = min<int64_t>(K.N, lo + chunk);
+  double s = 0;
+  for (int64_t k = lo + tid; k < hi; k += 256) s = fma(K.w[k].re, K.w[k].re, fma(K.w[k].im, K.w[k].im, s));
+  s = wsum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (tid == 0) K.npart[lb] = red[0] + red[1] + red[2] + red[3];
+}
+
+// per cell (one thread each): h_{j+1,j} = ||w|| from the partials, then the
+// Givens update of column j (|g_{j+1}| into rhist[j])
+__global__ void k_b_norm_givens(const KryCell *__restrict__ cells, int nc, const int *__restrict__ act) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc || !act[c]) return;
+  const KryCell &K = cells[c];
+  double s = 0;
+  for (int b0 = 0; b0 < K.nred; b0 += 16) {
+    double p[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) p[u] = K.npart[min(b0 + u, K.nred - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b0 + u < K.nred) s += p[u];
+  }
+  const double hn = sqrt(s);
+  K.scal[2] = hn;
+  givens_step(K.H, K.ldh, *K.jd, hn, K.cs, K.sn, K.g, K.rhist + *K.jd);
+}
+
+// V_{j+1} = w / h_{j+1,j}
+__global__ void k_b_scale_j(const KryCell *__restrict__ cells, const int *__restrict__ pre, int nc,
+                            const int *__restrict__ act) {
+  VIE_CELL_BEGIN
+  const int64_t k = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (k >= K.N) return;
+  const double s = 1.0 / K.scal[2];
+  K.V[(int64_t)(*K.jd + 1) * K.ldv + k] = s * K.w[k];
+}
+
+// per cell: the step's residual estimate |g_{j+1}| into res[c], then j += 1
+__global__ void k_b_jinc(const KryCell *__restrict__ cells, int nc, const int *__restrict__ act,
+                         double *__restrict__ res) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc || !act[c]) return;
+  const KryCell &K = cells[c];
+  const int j = *K.jd;
+  res[c] = K.rhist[j];
+  *K.jd = j + 1;
+}
+#undef VIE_CELL_BEGIN
 
 }  // namespace vie

@@ -1038,17 +1038,27 @@ struct TrsvNew {
 // RW rows per wave in the update blocks (16 RW rows per thread block); the
 // autotuner picks RW per context.  NV right-hand sides (1 or 2) share each
 // read of the factors; vector q's sums run in the same order for any NV.
-template <typename C, int RW, int NV>
-__device__ __forceinline__ void trsv_step_body(const TrsvStep &st, int vb) {
+template <typename C, int RW, int NV, typename ST = TrsvStep>
+__device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   __shared__ dz zo[NV][kTrsvNB];
   __shared__ dz zn[NV][kTrsvNB];
   __shared__ dz rg[NV][16];
   __shared__ dz red[NV][kTrsvHS][kTrsvNB];
   constexpr int kTrsvBlockRows = 16 * RW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the work item's domain: the last with first_block <= vb
   int d = 0;
-  while (d + 1 < st.ndom && vb >= st.d[d + 1].first_block) ++d;
+  for (int lo = 0, hi = st.ndom - 1; lo <= hi;) {
+    const int mid = (lo + hi) >> 1;
+    if (st.d[mid].first_block <= vb) {
+      d = mid;
+      lo = mid + 1;
+    } else {
+      hi = mid - 1;
+    }
+  }
   const TrsvDom &D = st.d[d];
+  if (D.active && !*D.active) return;   // (fused batch) a cell whose Arnoldi steps are paused
   const int blk = vb - D.first_block;
   const int cb0 = D.cb0, cm = D.cm, pb0 = D.pb0, pm = D.pm, nb0 = D.nb0, nm = D.nm;
   const int64_t ld = D.ld;
@@ -1201,6 +1211,20 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
     grid.sync();
   }
 }
+
+// One step of a batch's fused triangular solves (one vector per cell): the
+// step's domains of every cell, read from device memory.
+struct TrsvStepDev {
+  const TrsvDom *d;
+  int ndom, lower;
+};
+#define VIE_TRSV_STEPD(T, C)                                                                      \
+  __global__ __launch_bounds__(1024) void k_trsv_stepd_##T(const TrsvDom *doms, int ndom, int lower) { \
+    const TrsvStepDev st{doms, ndom, lower};                                                      \
+    trsv_step_body<C, 4, 1, TrsvStepDev>(st, blockIdx.x);                                        \
+  }
+VIE_TRSV_STEPD(z, dz)
+VIE_TRSV_STEPD(c, fz)
 
 #define VIE_TRSV_COOP(T, C, R)                                                                  \
   __global__ __launch_bounds__(1024) void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps) { \

@@ -38,6 +38,53 @@ __global__ void k_tt_far_rev(const double *pack, int packlen, const QuadRules *q
                              const dz *alpha, const dz *gsrc, const dz *kappa, double k0sq9, ZOut out, ZOut outT,
                              int sym);
 constexpr int kFarRevLds = 16 * 256 * 8 + 8;
+// Fused fill of many cells (the batch): one launch runs one fill kernel for
+// every cell that has work for it.  Each segment holds the arguments of one
+// cell's launch; it covers the fused grid's blocks [first, first + gx * gy)
+// and its local block (bx, by) = ((b - first) % gx, (b - first) / gx).
+// Segments are ordered by `first`.  The dynamic LDS of the launch is the
+// largest of its cells' lattice-sum tables.
+struct FarSeg {
+  const double *pack; int packlen; const QuadRules *qr; const TetGeom *tg; const TetFace *t2f;
+  const int32_t *test_list; int ntest; const int32_t *src_list; int nsrc;
+  const dz *alpha, *gsrc, *kappa; double k0sq9; ZOut out, outT; int sym, gx, first;
+};
+struct NearSeg {
+  const double *pack; int packlen; const QuadRules *qr; const TetGeom *tg; const TetFace *t2f;
+  const int32_t *lt, *ls, *lmask; int npairs; const dz *alpha, *gsrc, *kappa, *inv_eps; double k0sq9; ZOut out;
+  int gx, first;
+};
+struct TetFaceSeg {
+  const double *pack; int packlen; const QuadRules *qr; const TetGeom *tg; const TetFace *t2f;
+  const int32_t *test_list; int ntest; const FaceGeom *fg; int nface; const dz *alpha, *sigma, *gsrc, *kappa;
+  ZOut out, outT; int swap, gx, first;
+};
+struct TetFaceNearSeg {
+  const double *pack; int packlen; const QuadRules *qr; const TetGeom *tg; const TetFace *t2f;
+  const int32_t *pairs; int npairs; const FaceGeom *fg; const dz *alpha, *sigma; ZOut out; int gx, first;
+};
+struct FaceTetSeg {
+  const double *pack; int packlen; const QuadRules *qr; const FaceGeom *fg; const int32_t *half_list; int nhalf;
+  const TetGeom *tg; const TetFace *t2f; const int32_t *src_list; int nsrc; const dz *gsrc, *kappa; ZOut out;
+  int gx, first;
+};
+struct FaceTetNearSeg {
+  const double *pack; int packlen; const QuadRules *qr; const FaceGeom *fg; const int32_t *half_list;
+  const TetGeom *tg; const TetFace *t2f; const int32_t *pairs; int npairs; const dz *gsrc, *kappa; ZOut out;
+  int gx, first;
+};
+struct FaceFaceSeg {
+  const double *pack; int packlen; const QuadRules *qr; const FaceGeom *fg; const int32_t *half_list; int nhalf;
+  int nface; const dz *sigma; ZOut out; int gx, first;
+};
+__global__ void k_tt_far_seg(const FarSeg *segs, int nseg);
+__global__ void k_tt_far_rev_seg(const FarSeg *segs, int nseg);
+__global__ void k_tt_near_seg(const NearSeg *segs, int nseg);
+__global__ void k_tet_face_seg(const TetFaceSeg *segs, int nseg);
+__global__ void k_tet_face_near_seg(const TetFaceNearSeg *segs, int nseg);
+__global__ void k_face_tet_seg(const FaceTetSeg *segs, int nseg);
+__global__ void k_face_tet_near_seg(const FaceTetNearSeg *segs, int nseg);
+__global__ void k_face_face_seg(const FaceFaceSeg *segs, int nseg);
 // Z[i][j] += Zt[j][i] for i, j < N (row-major, leading dimension ld)
 __global__ void k_transpose_add_z(dz *Z, const dz *Zt, int64_t N, int64_t ld);
 __global__ void k_transpose_add_c(fz *Z, const fz *Zt, int64_t N, int64_t ld);
@@ -138,6 +185,7 @@ struct TrsvDom {
   // blocks of the step: [cb0, cb0+cm) two back (solution in sol), [pb0, pb0+pm) the previous one
   // (solution in part_in), [nb0, nb0+nm) the one solved; nm = 0: only store the previous block's solution
   int n, cb0, cm, pb0, pm, nb0, nm, first_block;
+  const int *active;  // (fused batch) the cell's flag: 0 skips the domain; nullptr always runs
 };
 struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
@@ -153,6 +201,10 @@ struct TrsvStep {
   __global__ void k_trsv_step_##T##_r##R(TrsvStep st);       \
   __global__ void k_trsv_step2_##T##_r##R(TrsvStep st);      \
   __global__ void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps);
+// k_trsv_stepd_*: one step of a batch's fused solves, one vector per cell,
+// the step's domains (any number) read from device memory
+__global__ void k_trsv_stepd_z(const TrsvDom *doms, int ndom, int lower);
+__global__ void k_trsv_stepd_c(const TrsvDom *doms, int ndom, int lower);
 VIE_DECL_TRSV(z, 4)
 VIE_DECL_TRSV(z, 8)
 VIE_DECL_TRSV(c, 4)
@@ -164,6 +216,31 @@ VIE_DECL_TRSV(c, 8)
 // k_matvec2_* variants take two vectors through one pass over Z: y_q = Z x_q
 // (or b_q - Z x_q when b_q is given), each sum in the order of the one-vector
 // kernel.
+// One cell's GMRES process in a batch's fused Arnoldi step (k_b_*): its
+// operator, Krylov basis and work vectors, the reduction partials over nred
+// blocks, and the row permutation of its block preconditioner.
+constexpr int kCellMaxDom = 8;
+struct KryCell {
+  const dz *Z;                 // FP64 operator, or nullptr: the mixed operator below
+  const fz *Zs; const int64_t *rowptr; const int32_t *cols; const dz *vals;
+  int64_t ld, N, ldv;
+  dz *V; int *jd; dz *vin, *z, *w, *tmp;
+  dz *H; int ldh; double *cs; dz *sn, *g, *y; double *rhist, *scal;
+  dz *dpart; double *npart; int nred;
+  const int32_t *perm; int ndom; int64_t dstart[kCellMaxDom];
+  int precond;                 // 1: no preconditioner (the product takes V_j itself)
+};
+__global__ void k_b_arn_begin(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_permute(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_matvec(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_dots_j(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_dots_reduce_j(const KryCell *cells, const int *pre, int nc, const int *act, int pass);
+__global__ void k_b_update_j(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_norm2(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_norm_givens(const KryCell *cells, int nc, const int *act);
+__global__ void k_b_scale_j(const KryCell *cells, const int *pre, int nc, const int *act);
+__global__ void k_b_jinc(const KryCell *cells, int nc, const int *act, double *res);
+
 struct MvVecs {
   const dz *x[2];
   const dz *b[2];

@@ -100,7 +100,17 @@ _SIGS = {
     "vie_set_option": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "vie_get_option": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
     "vie_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "vie_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "vie_batch_destroy": (C.c_int, [C.c_void_p]),
+    "vie_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "vie_batch_workspace_bytes": (C.c_size_t, [C.c_int]),
+    "vie_batch_bind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
+    "vie_batch_set_option": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "vie_batch_fill": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "vie_batch_factor": (C.c_int, [C.c_void_p]),
+    "vie_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_void_p]),
 }
+VIE_BATCH_GRAPH = 1
 
 
 def load():
@@ -330,3 +340,77 @@ class Solver:
         ms = C.c_double()
         self._ck(self.lib.vie_bench_matvec(self.h, int(reps), C.byref(ms)))
         return ms.value
+
+
+class Batch:
+    """Fused solves of several cells (Solver objects with a mesh uploaded and
+    a workspace bound, one precision): one fill launch per kernel family for
+    all of them, one block factorisation over all their domains, and GMRES
+    with every cell's Arnoldi step in one launch sequence.  Each cell then
+    answers absorption() / read_solution() as after its own solve."""
+
+    def __init__(self, solvers, device=0, stream=None, graph=True):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.cells = list(solvers)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = C.c_void_p()
+        rc = self.lib.vie_batch_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream))
+        if rc != VIE_OK:
+            raise VieError(rc, "vie_batch_create failed")
+        self.h = h
+        n = len(self.cells)
+        nbytes = int(self.lib.vie_batch_workspace_bytes(n))
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        ptr = self.ws.data_ptr()
+        off = (-ptr) % 256
+        arr = (C.c_void_p * n)(*[s.h.value for s in self.cells])
+        self._ck(self.lib.vie_batch_bind(self.h, arr, n, C.c_void_p(ptr + off), self.ws.numel() - off))
+        for s in self.cells:
+            s.stream = self.stream
+        self._ck(self.lib.vie_batch_set_option(self.h, VIE_BATCH_GRAPH, 1 if graph else 0))
+
+    def _ck(self, rc, allow=()):
+        if rc != VIE_OK and rc not in allow:
+            raise VieError(rc, self.lib.vie_batch_last_error(self.h).decode())
+        return rc
+
+    def fill(self, lams, thetas, phis, eps_list):
+        n = len(self.cells)
+        lam = np.ascontiguousarray(lams, np.float64)
+        th = np.ascontiguousarray(thetas, np.float64)
+        ph = np.ascontiguousarray(phis, np.float64)
+        eps = [np.ascontiguousarray(np.asarray(e, np.complex128)) for e in eps_list]
+        for s, e in zip(self.cells, eps):
+            if len(e) != s.nt:
+                raise ValueError("eps must have one value per tetrahedron of its cell")
+        ptrs = (C.c_void_p * n)(*[e.ctypes.data for e in eps])
+        self._ck(self.lib.vie_batch_fill(self.h, _p(lam), _p(th), _p(ph), ptrs))
+
+    def factor(self):
+        self._ck(self.lib.vie_batch_factor(self.h))
+
+    def solve(self, pols, tol=1e-10, max_iter=2000, restart=100, allow_noconv=False):
+        n = len(self.cells)
+        pp = np.ascontiguousarray(pols, np.int32)
+        info = (SolveInfo * n)()
+        rc = self.lib.vie_batch_solve(self.h, _p(pp), float(tol), int(max_iter), int(restart), info)
+        self._ck(rc, allow=(VIE_ENOCONV,) if allow_noconv else ())
+        out = [info[i].as_dict() for i in range(n)]
+        for d in out:
+            d["converged"] = bool(d["converged"])
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vie_batch_destroy(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
