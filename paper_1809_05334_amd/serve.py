@@ -230,7 +230,9 @@ class VieBackend:
         return self.torch.cuda.Stream(device=self.device)
 
     def prepare(self, req):
-        mesh = self.W.cell_mesh(req["cell"])
+        # a request names a cell of the workload generator, or brings its own
+        # mesh (and then may bring its own per-tetrahedron permittivities)
+        mesh = req["mesh"] if "mesh" in req else self.W.cell_mesh(req["cell"])
         s = self.vie.Solver(self.device)
         s.upload_mesh(mesh)
         fp = s.workspace_bytes(self.precision, self.restart)
@@ -240,7 +242,8 @@ class VieBackend:
         s, mesh, req = prep["solver"], prep["mesh"], prep["req"]
         s.set_stream(stream)
         s.bind(self.precision, self.restart)
-        s.fill(req["lambda"], req["theta"], req["phi"], self.W.osc_eps(mesh, req["lambda"]))
+        eps = req["eps"] if "eps" in req else self.W.osc_eps(mesh, req["lambda"])
+        s.fill(req["lambda"], req["theta"], req["phi"], eps)
         s.factor()
         info = s.solve(req["pol"], tol=self.tol, max_iter=self.max_iter, restart=self.restart)
         A, R, T = s.absorption()

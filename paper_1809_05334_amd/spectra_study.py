@@ -6,8 +6,14 @@ r = 20 nm centred in the spacer) at lattice constants a = b from `--periods`,
 meshed at 5 nm over the sphere's span and the spacer, 20 nm elsewhere.
 Absorption counts the active layer only (Fig. 4).  Enhancement = A_active with
 the particle / A_active on the same mesh with the particle's tetrahedra given
-the spacer's permittivity (no particle).  TE and TM are solved together and
-averaged (unpolarised light).
+the spacer's permittivity (no particle).  TE and TM are solved and averaged
+(unpolarised light).
+
+Every solve of a study is one request of the batched (default) or served path
+(`--path`): a study builds its requests (cell, wavelength, angle,
+polarisation, with or without the particle), the batch driver or the serving
+loop runs them on the device, and the reductions below turn their absorptances
+into enhancement factors and normalised absorbed power.
 
 Spectra (normal incidence): one JSON line per (a, lambda).  Angular response
 (azimuth 0) at lattice constant `--angle-period`: one JSON line per
@@ -23,12 +29,73 @@ import sys
 
 import numpy as np
 
+from . import workloads as W
+
+TE, TM = 0, 1
+
 
 def axis(spec):
     if ":" in spec:
         lo, hi, st = (float(v) for v in spec.split(":"))
         return list(np.arange(lo, hi + 0.5 * st, st))
     return [float(v) for v in spec.split(",")]
+
+
+def eps_variants(mesh, lam):
+    """Per-tetrahedron permittivities with the particle, and with the particle's
+    tetrahedra given the spacer's permittivity (the reference cell)."""
+    e = W.osc_eps(mesh, lam)
+    ref = e.copy()
+    ref[mesh.tet_domain == W.DOM_METAL] = W.EPS_SPACER
+    return {"particle": e, "none": ref}
+
+
+def study_requests(mesh, cases, rid0=0):
+    """One request per (case, variant, polarisation); cases are
+    (lambda nm, theta deg).  Each request carries its tag (case index,
+    variant, polarisation)."""
+    reqs = []
+    for ci, (lam, th) in enumerate(cases):
+        for var, eps in eps_variants(mesh, lam).items():
+            for pol in (TE, TM):
+                reqs.append({"rid": rid0 + len(reqs), "arrival": 0.0, "mesh": mesh, "eps": eps, "lambda": lam,
+                             "theta": float(np.deg2rad(th)), "phi": 0.0, "pol": pol, "tag": (ci, var, pol)})
+    return reqs
+
+
+def reduce_active(reqs, results, dom=W.DOM_ACTIVE):
+    """Unpolarised absorptance of domain `dom` per (case index, variant):
+    the mean over TE and TM."""
+    acc = {}
+    for rq, rs in zip(reqs, results):
+        if not rs.ok:
+            raise RuntimeError(f"request {rs.rid} failed: {rs.error}")
+        ci, var, _ = rq["tag"]
+        acc.setdefault((ci, var), []).append(rs.A[dom])
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def enhancement(active, ci):
+    """Enhancement of case ci: A_active with the particle / without."""
+    return active[(ci, "particle")] / active[(ci, "none")]
+
+
+def angular_response(active, cases, ci, ci0):
+    """Absorbed power at case ci normalised to the normal-incidence case ci0,
+    A(theta) cos(theta) / A(0) (with the particle)."""
+    return active[(ci, "particle")] * float(np.cos(np.deg2rad(cases[ci][1]))) / active[(ci0, "particle")]
+
+
+def run_requests(reqs, precision, path="batch", slots=4, tol=1e-8, restart=200):
+    """Solve the requests on the batched or the served path; results in
+    request order."""
+    if path == "batch":
+        from . import batch as B
+        res, _, _ = B.run_batch(reqs, precision, slots=slots, tol=tol, restart=restart)
+        return res
+    from . import serve as S
+    srv = S.Server(S.VieBackend(precision=precision, tol=tol, restart=restart), slots=slots, hbm_budget=200e9)
+    return srv.run_trace(reqs)
 
 
 def main():
@@ -39,64 +106,44 @@ def main():
     ap.add_argument("--angle-lambdas", default="500,600,750")
     ap.add_argument("--thetas", default="0,20,40,60,80")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--path", choices=["batch", "serve"], default="batch")
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=200)
     args = ap.parse_args()
 
     from . import vie
-    from . import workloads as W
 
     prec = vie.VIE_MIXED_FP32 if args.precision == "mixed" else vie.VIE_FP64
-
-    def solver(mesh):
-        s = vie.Solver(0)
-        s.upload_mesh(mesh)
-        s.set_option(vie.VIE_OPT_SYM_FILL, 1)   # normal-incidence fills evaluate each far pair once
-        s.bind(prec, args.restart)
-        return s
-
-    def active(s, mesh, lam, th, eps):
-        s.fill(lam, np.deg2rad(th), 0.0, eps)
-        s.factor()
-        info = s.solve_pair(tol=args.tol, max_iter=4000, restart=args.restart)
-        A = [s.absorption(pol=p)[0] for p in (vie.VIE_TE, vie.VIE_TM)]
-        return 0.5 * (A[0][W.DOM_ACTIVE] + A[1][W.DOM_ACTIVE]), 0.5 * (A[0][W.DOM_METAL] + A[1][W.DOM_METAL]), \
-            [i["iters"] for i in info]
-
-    def eps_pair(mesh, lam):
-        e = W.osc_eps(mesh, lam)
-        ref = e.copy()
-        ref[mesh.tet_domain == W.DOM_METAL] = W.EPS_SPACER
-        return e, ref
 
     def cell(a):
         return W.osc_cell_mesh(a, 80.0, 40.0, 20.0, 5.0, 20.0)
 
     for a in axis(args.periods):
         mesh = cell(a)
-        s = solver(mesh)
-        print(f"a = {a} nm: N = {s.num_unknowns()}", file=sys.stderr, flush=True)
-        for lam in axis(args.lambdas):
-            e, ref = eps_pair(mesh, lam)
-            A_np, A_m, it = active(s, mesh, lam, 0.0, e)
-            A_ref, _, it_ref = active(s, mesh, lam, 0.0, ref)
-            print(json.dumps({"study": "spectrum", "a_nm": a, "lambda_nm": lam, "N": s.num_unknowns(),
-                              "A_active": A_np, "A_active_no_particle": A_ref, "enhancement": A_np / A_ref,
-                              "A_metal": A_m, "iters": it, "iters_no_particle": it_ref}), flush=True)
-        del s
+        cases = [(lam, 0.0) for lam in axis(args.lambdas)]
+        reqs = study_requests(mesh, cases)
+        res = run_requests(reqs, prec, args.path, args.slots, args.tol, args.restart)
+        act = reduce_active(reqs, res)
+        metal = reduce_active(reqs, res, W.DOM_METAL)
+        for ci, (lam, _) in enumerate(cases):
+            print(json.dumps({"study": "spectrum", "a_nm": a, "lambda_nm": lam, "N": res[0].N,
+                              "A_active": act[(ci, "particle")], "A_active_no_particle": act[(ci, "none")],
+                              "enhancement": enhancement(act, ci), "A_metal": metal[(ci, "particle")]}), flush=True)
     mesh = cell(args.angle_period)
-    s = solver(mesh)
+    thetas = axis(args.thetas)
     for lam in axis(args.angle_lambdas):
-        A0 = None
-        for th in axis(args.thetas):
-            e, ref = eps_pair(mesh, lam)
-            A_np, _, it = active(s, mesh, lam, th, e)
-            A_ref, _, _ = active(s, mesh, lam, th, ref)
-            A0 = A_np if A0 is None else A0
-            c = float(np.cos(np.deg2rad(th)))
+        cases = [(lam, th) for th in thetas]
+        reqs = study_requests(mesh, cases)
+        res = run_requests(reqs, prec, args.path, args.slots, args.tol, args.restart)
+        act = reduce_active(reqs, res)
+        ci0 = thetas.index(0.0) if 0.0 in thetas else 0
+        for ci, (_, th) in enumerate(cases):
             print(json.dumps({"study": "angle", "a_nm": args.angle_period, "lambda_nm": lam, "theta_deg": th,
-                              "A_active": A_np, "enhancement": A_np / A_ref,
-                              "normalised_absorbed_power": A_np * c / A0, "lambertian": c, "iters": it}), flush=True)
+                              "A_active": act[(ci, "particle")], "enhancement": enhancement(act, ci),
+                              "normalised_absorbed_power": angular_response(act, cases, ci, ci0),
+                              "lambertian": float(np.cos(np.deg2rad(th)))}), flush=True)
+        print(f"lambda {lam:.0f} nm done", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":
