@@ -84,7 +84,10 @@ enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1 };
 typedef struct {
   int iters;                 /* total GMRES iterations (all restarts, all refinement steps) */
   int restarts;              /* GMRES restarts */
-  int refine_steps;          /* restart cycles, each closed by an FP64 true residual b - Z x */
+  int refine_steps;          /* restart cycles (restarts + 1), each closed by an FP64 true residual
+                              * b - Z x of the stored operator.  In VIE_MIXED_FP32 that operator holds
+                              * the far entries rounded to FP32: the cycles converge on it and do not
+                              * refine toward the FP64 operator (the two differ by that rounding) */
   double true_rel_residual;  /* ||b - Z x|| / ||b|| recomputed in FP64 at the end */
   double t_fill_ms;          /* device time of the last vie_fill */
   double t_factor_ms;        /* device time of the last vie_precond_factor */

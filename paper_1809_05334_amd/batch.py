@@ -5,7 +5,9 @@ Fused mode (default): cells are grouped into waves (in request order, up to
 budget).  A wave is one `vie.Batch`: the library fills every cell of the
 wave with one launch per fill kernel and colour pair, factors all their
 diagonal blocks in one panel loop, and runs GMRES with every cell's Arnoldi
-step in one launch sequence replayed as a captured HIP graph.  `slots`
+step in one launch sequence replayed as a captured HIP graph; the fused
+matvec's rows per wave come from the autotuner, run once per N bucket
+(< 4k, 4-8k, > 8k unknowns) on a cell of that bucket.  `slots`
 workers run waves concurrently, each on its own stream, so one wave's host
 work (mesh topology, lattice-sum table fits) overlaps another's device work;
 a host thread prepares the next cells' meshes ahead of the workers.
@@ -37,10 +39,12 @@ def cell_requests(n_cells=256, seed=0, n_lo=2000, n_hi=15000):
              "pol": c["pol"]} for i, c in enumerate(cells)]
 
 
-def _prepare(req, vie, W, device, precision, restart):
+def _prepare(req, vie, W, device, precision, restart, sym):
     mesh = req["mesh"] if "mesh" in req else W.cell_mesh(req["cell"])
     s = vie.Solver(device, stream=_DummyStream.get(device))
     s.upload_mesh(mesh)
+    if sym:   # one lattice sum per unordered far pair (a staging copy of Z's far part)
+        s.set_option(vie.VIE_OPT_SYM_FILL, 1)
     eps = req["eps"] if "eps" in req else W.osc_eps(mesh, req["lambda"])
     return {"req": req, "solver": s, "mesh": mesh, "eps": eps, "bytes": s.workspace_bytes(precision, restart)}
 
@@ -59,7 +63,7 @@ class _DummyStream:
 
 
 def run_fused(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=100, max_cells=32, graph=True,
-              device=0, max_iter=3000):
+              device=0, max_iter=3000, sym=True):
     """Fused batch: returns (results in request order, seconds, stats)."""
     import torch
 
@@ -69,18 +73,23 @@ def run_fused(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=1
     share = budget_gb * 1e9 / max(1, slots)
     prepq = queue.Queue(maxsize=4 * max_cells)
     results = {}
-    stats = {"waves": 0, "cells_per_wave": [], "peak_gb": 0.0}
+    stats = {"waves": 0, "cells_per_wave": [], "peak_gb": 0.0, "fill_s": 0.0, "factor_s": 0.0, "solve_s": 0.0,
+             "fill_wall_s": 0.0}
     lock = threading.Lock()
     used = [0.0]
 
     def producer():
         for r in requests:
-            prepq.put(_prepare(r, vie, W, device, precision, restart))
+            prepq.put(_prepare(r, vie, W, device, precision, restart, sym))
         for _ in range(slots):
             prepq.put(None)
 
     wave_lock = threading.Lock()
     pending = []
+    tuned = {}   # N bucket -> matvec rows per wave picked by the autotuner
+
+    def bucket(n):
+        return 0 if n < 4000 else (1 if n < 8000 else 2)
 
     def next_wave():
         """Take the next wave from the prepared cells (request order)."""
@@ -117,12 +126,31 @@ def run_fused(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=1
                     p["solver"].set_stream(stream)
                     p["solver"].bind(precision, restart)
                 b = vie.Batch([p["solver"] for p in wave], device=device, stream=stream, graph=graph)
+                tf = time.perf_counter()
                 b.fill([p["req"]["lambda"] for p in wave], [p["req"]["theta"] for p in wave],
                        [p["req"]["phi"] for p in wave], [p["eps"] for p in wave])
+                tf = time.perf_counter() - tf
                 b.factor()
+                # launch shapes per N bucket: the autotuner times the matvec
+                # variants on one cell of the bucket (first wave holding it)
+                for p in wave:
+                    k = bucket(p["solver"].num_unknowns())
+                    with lock:
+                        pick = tuned.get(k)
+                    if pick is None:
+                        pick = p["solver"].autotune(reps=2)["matvec_rows"]
+                        with lock:
+                            tuned[k] = pick
+                            stats.setdefault("matvec_rows_by_bucket", {})[str(k)] = pick
+                    p["solver"].set_option(vie.VIE_OPT_MATVEC_ROWS, pick)
                 infos = b.solve([p["req"]["pol"] for p in wave], tol=tol, max_iter=max_iter, restart=restart,
                                 allow_noconv=True)
                 t_done = time.perf_counter()
+                with lock:   # device time of the wave's stages (HIP events), and the fill's wall time
+                    stats["fill_s"] += infos[0]["t_fill_ms"] / 1e3
+                    stats["factor_s"] += infos[0]["t_factor_ms"] / 1e3
+                    stats["solve_s"] += infos[0]["t_solve_ms"] / 1e3
+                    stats["fill_wall_s"] += tf
                 for p, inf in zip(wave, infos):
                     s = p["solver"]
                     A, R, T = s.absorption()
@@ -158,13 +186,13 @@ def run_fused(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=1
 
 
 def run_batch(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=100, mode="fused", max_cells=32,
-              graph=True):
+              graph=True, sym=True):
     """Solve the requests as one batch; returns (results in request order,
     seconds, stats).  mode: 'fused' (vie.Batch waves) or 'streams' (one
     context and stream per running cell)."""
     if mode == "fused":
         return run_fused(requests, precision, slots=slots, budget_gb=budget_gb, tol=tol, restart=restart,
-                         max_cells=max_cells, graph=graph)
+                         max_cells=max_cells, graph=graph, sym=sym)
     be = VieBackend(precision=precision, tol=tol, restart=restart)
     srv = Server(be, slots=slots, hbm_budget=budget_gb * 1e9, max_skip_s=1e9)
     t0 = time.perf_counter()
@@ -182,6 +210,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--mode", choices=["fused", "streams"], default="fused")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-sym-fill", action="store_true")
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
     args = ap.parse_args()
     from . import vie
@@ -192,7 +221,7 @@ def main():
     results = {}
     for name in sel:
         res, dt, st = run_batch(reqs, runs[name], args.slots, args.budget_gb, args.tol, mode=args.mode,
-                                max_cells=args.max_cells, graph=not args.no_graph)
+                                max_cells=args.max_cells, graph=not args.no_graph, sym=not args.no_sym_fill)
         results[name] = res
         s = summarize(res, dt)
         ok = [r for r in res if r.ok]

@@ -504,10 +504,11 @@ int build_step_plan(vie_batch *b, StepPlan &sp) {
     k.ndom = x->topo.ndom;
     for (int d = 0; d < x->topo.ndom; ++d) k.dstart[d] = x->topo.dstart[d];
     k.precond = x->precond;
+    k.rpw = x->mv_rpw;
     sp.precond = sp.precond || x->precond == 0;
     const int ngrp = (int)nblk(L.restart + 1, 8);
     pe[c + 1] = pe[c] + (int)nblk(N, 256);
-    pm[c + 1] = pm[c] + (int)nblk(N, 16);
+    pm[c + 1] = pm[c] + (int)nblk(N, 4 * k.rpw);
     pd[c + 1] = pd[c] + k.nred * ngrp;
     pr[c + 1] = pr[c] + (int)nblk(L.restart + 1, 128);
     pn[c + 1] = pn[c] + k.nred;

@@ -532,8 +532,16 @@ __global__ __launch_bounds__(256) void k_b_matvec(const KryCell *__restrict__ ce
   __shared__ dz xs[kMvChunk];
   VIE_CELL_BEGIN
   const MvVecs v{{K.precond ? K.vin : K.z, nullptr}, {nullptr, nullptr}, {K.w, nullptr}};
-  if (K.Z) matvec_body<4, 1>(K.Z, K.ld, K.N, v, xs, lb);
-  else matvec_mixed_body<4, 1>(K.Zs, K.ld, K.N, K.rowptr, K.cols, K.vals, v, xs, lb);
+  // rows per wave: the cell's autotuned shape
+  if (K.Z) {
+    if (K.rpw == 2) matvec_body<2, 1>(K.Z, K.ld, K.N, v, xs, lb);
+    else if (K.rpw == 8) matvec_body<8, 1>(K.Z, K.ld, K.N, v, xs, lb);
+    else matvec_body<4, 1>(K.Z, K.ld, K.N, v, xs, lb);
+  } else {
+    if (K.rpw == 2) matvec_mixed_body<2, 1>(K.Zs, K.ld, K.N, K.rowptr, K.cols, K.vals, v, xs, lb);
+    else if (K.rpw == 8) matvec_mixed_body<8, 1>(K.Zs, K.ld, K.N, K.rowptr, K.cols, K.vals, v, xs, lb);
+    else matvec_mixed_body<4, 1>(K.Zs, K.ld, K.N, K.rowptr, K.cols, K.vals, v, xs, lb);
+  }
 }
 
 // partial inner products with V_0 .. V_j: local block (x, y) = chunk x of the

@@ -231,6 +231,7 @@ struct KryCell {
   int precond;                 // 1: no preconditioner (the product takes V_j itself)
 };
 __global__ void k_b_arn_begin(const KryCell *cells, const int *pre, int nc, const int *act);
+  int rpw;                     // matvec rows per wave (2, 4, 8): 4 RPW rows per thread block
 __global__ void k_b_permute(const KryCell *cells, const int *pre, int nc, const int *act);
 __global__ void k_b_matvec(const KryCell *cells, const int *pre, int nc, const int *act);
 __global__ void k_b_dots_j(const KryCell *cells, const int *pre, int nc, const int *act);

@@ -176,16 +176,23 @@ class Server:
             self._pending.append(job)
             self._admit_locked(self.clock())
 
-    def run_trace(self, requests, time_scale=1.0):
+    def run_trace(self, requests, time_scale=1.0, progress_s=0.0):
         """Replay requests at their `arrival` times (s, scaled); returns the
-        results in request order once all have finished."""
+        results in request order once all have finished.  progress_s > 0:
+        a line on stderr every progress_s seconds."""
+        import sys
         reqs = sorted(requests, key=lambda r: r["arrival"])
         self.start()
         t0 = self.clock()
+        t_prog = t0
         k = 0
         try:
             while True:
                 now = self.clock()
+                if progress_s > 0 and now - t_prog >= progress_s:
+                    t_prog = now
+                    print(f"serve: {len(self.done)}/{len(reqs)} done, {self._running} running, "
+                          f"{len(self._pending)} waiting at {now - t0:.0f} s", file=sys.stderr, flush=True)
                 while k < len(reqs) and t0 + reqs[k]["arrival"] * time_scale <= now:
                     self._enqueue(reqs[k], t0 + reqs[k]["arrival"] * time_scale)
                     k += 1
@@ -216,7 +223,7 @@ def summarize(results, t_span):
 class VieBackend:
     """Runs each request through libvie on its own context."""
 
-    def __init__(self, device=0, precision=None, restart=100, tol=1e-8, max_iter=3000):
+    def __init__(self, device=0, precision=None, restart=100, tol=1e-8, max_iter=3000, sym=False):
         import torch
 
         from . import vie
@@ -225,6 +232,7 @@ class VieBackend:
         self.device = device
         self.precision = vie.VIE_MIXED_FP32 if precision is None else precision
         self.restart, self.tol, self.max_iter = restart, tol, max_iter
+        self.sym = sym   # one lattice sum per unordered far pair (admission counts its staging copy)
 
     def make_worker(self, wid):
         return self.torch.cuda.Stream(device=self.device)
@@ -235,6 +243,8 @@ class VieBackend:
         mesh = req["mesh"] if "mesh" in req else self.W.cell_mesh(req["cell"])
         s = self.vie.Solver(self.device)
         s.upload_mesh(mesh)
+        if self.sym:
+            s.set_option(self.vie.VIE_OPT_SYM_FILL, 1)
         fp = s.workspace_bytes(self.precision, self.restart)
         return {"solver": s, "mesh": mesh, "req": req}, fp
 
@@ -265,20 +275,28 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--sym-fill", action="store_true", help="one lattice sum per unordered far pair")
+    ap.add_argument("--out", default="", help="write each request's result to this JSON file (per rate)")
     args = ap.parse_args()
     from . import vie
     from . import workloads as W
     prec = vie.VIE_MIXED_FP32 if args.precision == "mixed" else vie.VIE_FP64
+    per = {}
     for rate in [float(r) for r in args.rates.split(",")]:
         trace = W.serve_trace(rate, args.requests, seed=args.seed)
-        be = VieBackend(precision=prec, tol=args.tol)
+        be = VieBackend(precision=prec, tol=args.tol, sym=args.sym_fill)
         srv = Server(be, slots=args.slots, hbm_budget=args.budget_gb * 1e9)
-        res = srv.run_trace(trace)
+        res = srv.run_trace(trace, progress_s=30.0)
         out = summarize(res, srv.t_end - srv.t_start)
         out.update({"rate_req_s": rate, "precision": args.precision, "slots": args.slots,
                     "budget_gb": args.budget_gb, "peak_gb": srv.peak_used / 1e9, "peak_running": srv.peak_running,
-                    "failed": [r.error for r in res if not r.ok][:3]})
+                    "sym_fill": args.sym_fill, "failed": [r.error for r in res if not r.ok][:3]})
         print(json.dumps(out), flush=True)
+        per[str(rate)] = [{"rid": r.rid, "ok": r.ok, "N": r.N, "A": r.A, "R": r.R, "T": r.T, "iters": r.iters,
+                           "latency_s": r.latency} for r in res]
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(per, f)
 
 
 if __name__ == "__main__":
