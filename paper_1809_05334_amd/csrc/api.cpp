@@ -871,7 +871,7 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta, double phi, const vie
 
 namespace vie {
 
-enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_TSEL, LU_TFIN };
+enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_GEMM2, LU_TSEL, LU_TFIN };
 
 // One launch of an LU kernel (FP32 factors if f32) on stream sm over every
 // domain with blocks_of(d) > 0 thread blocks (kLuMaxDom domains per launch;
@@ -909,6 +909,10 @@ void lu_launch(bool f32, hipStream_t sm, LuKernel k, const std::vector<LuDom> &d
       case LU_GEMM:
         if (f32) hipLaunchKernelGGL(k_lu_gemm_c, dim3(total), dim3(256), 0, sm, st);
         else hipLaunchKernelGGL(k_lu_gemm_z, dim3(total), dim3(256), 0, sm, st);
+        break;
+      case LU_GEMM2:
+        if (f32) hipLaunchKernelGGL(k_lu_gemm2_c, dim3(total), dim3(kGemm2Threads), 0, sm, st);
+        else hipLaunchKernelGGL(k_lu_gemm2_z, dim3(total), dim3(kGemm2Threads), 0, sm, st);
         break;
       case LU_TSEL:
         if (f32) hipLaunchKernelGGL(k_lu_tsel_c, dim3(total), dim3(kTsRowsC * kTsLprC), 0, sm, st);
@@ -988,64 +992,105 @@ int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
 }
 
 // Right-looking blocked LU of every domain in `doms` (any number of
-// contexts' domains, all FP32 or all FP64 factors), advanced together panel
-// by panel on `stream`.  With tournament pivoting the next panel's pivot
-// search runs ahead: after the trailing update of that panel's own columns,
-// its tournament goes to the side stream while the update of the remaining
-// columns runs, and the next panel's row swaps wait for it.
+// contexts' domains, all FP32 or all FP64 factors), advanced together on
+// `stream`.
+//
+// Tournament pivoting (lu_pivot 0) takes the panels two at a time, so that
+// the bulk trailing update has K = 128 (k_lu_gemm2): at k0 the panel a
+// (columns k0 .. k0+63) is pivoted, swapped, and its L21 and U12 formed; its
+// update of panel b's columns (k0+64 .. k0+127) lets b be pivoted and
+// swapped; the rows of b then take a's update of the columns right of the
+// pair (a 64-row strip) before b's U12 is solved; finally every row and
+// column right of the pair takes both panels' update at once.  The next
+// pair's pivot search runs ahead: after the update of the first column tile
+// right of the pair, its tournament goes to the side stream while the
+// update of the remaining columns runs, and the next pair's row swaps wait
+// for it.  Column-by-column partial pivoting (lu_pivot 1) advances one
+// panel at a time with the K = 64 update.
 int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot, hipStream_t stream,
                   hipStream_t side, hipEvent_t ev_la, hipEvent_t ev_ts) {
   int maxn = 0;
   for (const LuDom &D : doms) maxn = std::max(maxn, D.n);
-  const bool ahead = lu_pivot == 0;
   const int ts_rows = f32 ? kTsRowsC : kTsRowsZ;
   auto tsel = [&](int kp, hipStream_t sm) {
     lu_launch(f32, sm, LU_TSEL, doms, kp, kp, [&](int d) { return doms[d].n > kp ? (int)nblk(doms[d].n - kp, ts_rows) : 0; });
   };
-  // trailing-update tiles of domain d at panel k0: row tiles x column tiles gcol0 .. (gcols <= 0: to the end)
-  auto gemm_blocks = [&](int d, int k0, int gcol0, int gcols) {
+  auto jb_of = [&](int d, int k0) { return std::min(kLuNB, doms[d].n - k0); };
+  // single-panel update tiles of domain d at panel k0: row tiles (all, or grows)
+  // x column tiles gcol0 .. (gcols <= 0: to the end)
+  auto gemm_blocks = [&](int d, int k0, int gcol0, int gcols, int grows = 0) {
     const int rest = doms[d].n > k0 ? doms[d].n - k0 - std::min(kLuNB, doms[d].n - k0) : 0;
     const int nt = (int)((rest + 63) / 64);
     const int nc = gcols > 0 ? std::min(gcols, nt - gcol0) : nt - gcol0;
-    return rest > 0 && nc > 0 ? nt * nc : 0;
+    const int nr = grows > 0 ? std::min(grows, nt) : nt;
+    return rest > 0 && nc > 0 ? nr * nc : 0;
   };
-  for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
-    auto jb_of = [&](int d) { return std::min(kLuNB, doms[d].n - k0); };
-    auto swap_blocks = [&](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
-    if (lu_pivot == 0) {
-      // tournament pivoting: pivot rows by a reduction tree, swap whole rows,
-      // then L21 = A21 U11^-1 below the factored top block
-      if (k0 == 0) tsel(k0, stream);
-      else HIPCK(hipStreamWaitEvent(stream, ev_ts, 0));   // issued ahead on the side stream
-      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks, 1);
-      lu_launch(f32, stream, LU_TFIN, doms, k0, k0, [&](int d) {
-        if (doms[d].n <= k0) return 0;
-        const int rest = doms[d].n - k0 - jb_of(d);
-        return rest > 0 ? (int)nblk(rest, kColRows) : 1;
-      });
-    } else {
-      lu_launch(f32, stream, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
-      for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
-        lu_launch(f32, stream, LU_COL, doms, j, k0, [&](int d) {
-          const int n = doms[d].n;
-          return (n > k0 && j < k0 + jb_of(d) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
-        });
-      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks);
-    }
-    lu_launch(f32, stream, LU_TRSM, doms, k0, k0, [&](int d) {
-      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d) : 0;
+  auto swap_blocks = [&](int k0) {
+    return [&, k0](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
+  };
+  auto tfin_blocks = [&](int k0) {
+    return [&, k0](int d) {
+      if (doms[d].n <= k0) return 0;
+      const int rest = doms[d].n - k0 - jb_of(d, k0);
+      return rest > 0 ? (int)nblk(rest, kColRows) : 1;
+    };
+  };
+  auto trsm_blocks = [&](int k0) {
+    return [&, k0](int d) {
+      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d, k0) : 0;
       return rest > 0 ? (int)nblk(rest, kColRows) : 0;
-    });
-    if (ahead && k0 + kLuNB < maxn) {
-      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
-      HIPCK(hipEventRecord(ev_la, stream));
-      HIPCK(hipStreamWaitEvent(side, ev_la, 0));
-      tsel(k0 + kLuNB, side);
-      HIPCK(hipEventRecord(ev_ts, side));
-      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0); }, 0, 1, 0);
-    } else {
-      lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
+    };
+  };
+  if (lu_pivot == 0) {
+    const int tm = 128, tn = f32 ? 128 : 64;   // k_lu_gemm2 tile
+    // pair-update tiles of domain d at k0 (column tiles gcol0 .., gcols <= 0: to the end), padded to 8
+    auto gemm2_blocks = [&](int d, int k0, int gcol0, int gcols) {
+      const int rest = doms[d].n - k0 - 2 * kLuNB;
+      if (rest <= 0) return 0;
+      const int nr = (rest + tm - 1) / tm, ntc = (rest + tn - 1) / tn;
+      const int nc = gcols > 0 ? std::min(gcols, ntc - gcol0) : ntc - gcol0;
+      return nc > 0 ? 8 * (int)nblk(nr * nc, 8) : 0;
+    };
+    tsel(0, stream);
+    for (int k0 = 0; k0 < maxn; k0 += 2 * kLuNB) {
+      const int kb = k0 + kLuNB, next = k0 + 2 * kLuNB;
+      if (k0 > 0) HIPCK(hipStreamWaitEvent(stream, ev_ts, 0));   // issued ahead on the side stream
+      // panel a: whole-row swaps, L21 = A21 U11^-1, U12 = L11^-1 A12 (every column right of a)
+      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0), 1);
+      lu_launch(f32, stream, LU_TFIN, doms, k0, k0, tfin_blocks(k0));
+      lu_launch(f32, stream, LU_TRSM, doms, k0, k0, trsm_blocks(k0));
+      if (kb < maxn) {
+        // panel b's columns take a's update; b is pivoted, swapped and its L21 formed
+        lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
+        tsel(kb, stream);
+        lu_launch(f32, stream, LU_SWAP, doms, kb, kb, swap_blocks(kb), 1);
+        lu_launch(f32, stream, LU_TFIN, doms, kb, kb, tfin_blocks(kb));
+        // b's rows take a's update right of the pair, then b's U12
+        lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0, 1); }, 0, 1, 0);
+        lu_launch(f32, stream, LU_TRSM, doms, kb, kb, trsm_blocks(kb));
+      }
+      if (next < maxn) {
+        lu_launch(f32, stream, LU_GEMM2, doms, k0, k0, [&](int d) { return gemm2_blocks(d, k0, 0, 1); }, 0, 0, 1);
+        HIPCK(hipEventRecord(ev_la, stream));
+        HIPCK(hipStreamWaitEvent(side, ev_la, 0));
+        tsel(next, side);
+        HIPCK(hipEventRecord(ev_ts, side));
+        lu_launch(f32, stream, LU_GEMM2, doms, k0, k0, [&](int d) { return gemm2_blocks(d, k0, 1, 0); }, 0, 1, 0);
+      }
+      LAUNCHCK();
     }
+    return VIE_OK;
+  }
+  for (int k0 = 0; k0 < maxn; k0 += kLuNB) {
+    lu_launch(f32, stream, LU_PIVOT, doms, k0, k0, [&](int d) { return doms[d].n > k0 ? 1 : 0; });
+    for (int j = k0; j < k0 + kLuNB && j < maxn; ++j)
+      lu_launch(f32, stream, LU_COL, doms, j, k0, [&](int d) {
+        const int n = doms[d].n;
+        return (n > k0 && j < k0 + jb_of(d, k0) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
+      });
+    lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0));
+    lu_launch(f32, stream, LU_TRSM, doms, k0, k0, trsm_blocks(k0));
+    lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
     LAUNCHCK();
   }
   return VIE_OK;

@@ -816,6 +816,164 @@ __device__ __forceinline__ void lu_gemm_body(const LuStep &st) {
 __global__ __launch_bounds__(256) void k_lu_gemm_z(LuStep st) { lu_gemm_body<dz>(st); }
 __global__ __launch_bounds__(256) void k_lu_gemm_c(LuStep st) { lu_gemm_body<fz>(st); }
 
+// Trailing update after a pair of panels: A22 -= [L21_a L21_b] [U12_a; U12_b]
+// with K = 2 kLuNB = 128 (the panels at k0 and k0 + 64 both factored and
+// their U rows solved), rows and columns from k0 + 128.  Twice the K of the
+// single-panel update halves the read-modify-write of A22 per flop.  Tiles
+// of TM x TN (FP32: 128 x 128, FP64: 128 x 64) per block of 8 waves (WR x WC),
+// each wave MB x NB MFMA tiles of 16 x 16; K staged through LDS in chunks of
+// 16 with the next chunk's loads in flight.
+//
+// Tile order: each domain's blocks are padded to a multiple of 8 and its
+// first block is a multiple of 8, so block b runs on XCD b % 8 (workgroups
+// go to the XCDs in turn); XCD x takes the tiles [x q, (x + 1) q) of the
+// domain's sequence (q = tiles / 8, rounded up), and the sequence walks
+// groups of 8 column tiles row by row, so the 64 or so blocks an XCD holds at
+// once share 8 row panels of L21 and 8 column panels of U12 in its L2.
+template <typename C> struct Gemm2Cfg;
+template <> struct Gemm2Cfg<fz> { static constexpr int TM = 128, TN = 128, WR = 2, WC = 4; };
+template <> struct Gemm2Cfg<dz> { static constexpr int TM = 128, TN = 64, WR = 4, WC = 2; };
+constexpr int kGemm2K = 2 * kLuNB, kGemm2Group = 8;
+
+template <typename C>
+__device__ __forceinline__ void lu_gemm2_body(const LuStep &st) {
+  typedef typename Mfma<C>::R R;
+  typedef typename Mfma<C>::Acc Acc;
+  constexpr int TM = Gemm2Cfg<C>::TM, TN = Gemm2Cfg<C>::TN, WR = Gemm2Cfg<C>::WR, WC = Gemm2Cfg<C>::WC;
+  constexpr int WM = TM / WR, WN = TN / WC, MB = WM / 16, NB = WN / 16, NT = kGemm2Threads;
+  static_assert(WR * WC * 64 == NT, "one wave per wave tile");
+  constexpr int kPerA = TM * kGemmKC / NT, kPerB = kGemmKC * TN / NT;
+  __shared__ R As[2][TM][kGemmKC + 1];   // [0]: real, [1]: imaginary parts
+  __shared__ R Bs[2][kGemmKC][TN + 1];
+  const LuDom &D = st.d[lu_domain(st)];
+  const int k0 = st.k0, n = D.n, base = k0 + kGemm2K;
+  const int64_t ld = D.ld;
+  C *__restrict__ A = (C *)D.A;
+  const int nr = (n - base + TM - 1) / TM, ntc = (n - base + TN - 1) / TN;
+  const int nc = st.gcols > 0 ? min(st.gcols, ntc - st.gcol0) : ntc - st.gcol0;
+  const int total = nr * nc, q = (total + 7) / 8;
+  const int b = blockIdx.x - D.first_block;
+  const int t = (b & 7) * q + (b >> 3);
+  if (t >= total) return;
+  const int g = t / (kGemm2Group * nr), rem = t - g * kGemm2Group * nr;
+  const int gw = min(kGemm2Group, nc - g * kGemm2Group);
+  const int r0 = base + (rem / gw) * TM;
+  const int c0 = base + (st.gcol0 + g * kGemm2Group + rem % gw) * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  Acc cre[MB][NB], cim[MB][NB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      cre[a][c] = Acc{0, 0, 0, 0};
+      cim[a][c] = Acc{0, 0, 0, 0};
+    }
+  // L21[r0.., k0+kc..] (TM x KC) and U12[k0+kc.., c0..] (KC x TN); K = 128 <= n - k0.
+  // Thread tid loads A rows ar + u (NT / KC), column ak, and B rows bk + u (NT / TN),
+  // column bj: uniform bases with 32-bit offsets (a tile spans < 2^31 / ld rows),
+  // fixed per thread except for uniform steps, and LDS slots at constant
+  // distances from one address per operand.
+  constexpr int kRowStepA = NT / kGemmKC, kRowStepB = NT / TN;
+  const uint32_t ld32 = (uint32_t)ld, rmax = (uint32_t)(n - 1 - r0), cmax = (uint32_t)(n - 1 - c0);
+  const int ar = tid / kGemmKC, ak = tid % kGemmKC, bk = tid / TN, bj = tid % TN;
+  const C *__restrict__ Ab = A + (int64_t)r0 * ld + k0;
+  const C *__restrict__ Bb = A + (int64_t)k0 * ld + c0;
+  uint32_t aoff[kPerA];
+#pragma unroll
+  for (int u = 0; u < kPerA; ++u) aoff[u] = min((uint32_t)(ar + u * kRowStepA), rmax) * ld32 + ak;
+  const uint32_t boff = bk * ld32 + min((uint32_t)bj, cmax);
+  bool aok[kPerA];
+#pragma unroll
+  for (int u = 0; u < kPerA; ++u) aok[u] = (uint32_t)(ar + u * kRowStepA) <= rmax;
+  const bool bok = (uint32_t)bj <= cmax;
+  R *const sa = &As[0][ar][ak];
+  R *const sb = &Bs[0][bk][bj];
+  constexpr int kAim = TM * (kGemmKC + 1), kBim = kGemmKC * (TN + 1);   // imaginary - real part
+  C va[kPerA], vb[kPerB];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kPerA; ++u) va[u] = Ab[aoff[u] + kc];
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) vb[u] = Bb[boff + (uint32_t)(kc + u * kRowStepB) * ld32];
+  };
+  const R *const la = &As[0][wr * WM + (lane & 15)][lane >> 4];
+  const R *const lb = &Bs[0][lane >> 4][wc * WN + (lane & 15)];
+  fetch(0);
+  for (int kc = 0; kc < kGemm2K; kc += kGemmKC) {
+    __syncthreads();   // the previous chunk's shared reads are done
+#pragma unroll
+    for (int u = 0; u < kPerA; ++u) {
+      sa[u * kRowStepA * (kGemmKC + 1)] = aok[u] ? va[u].re : R(0);
+      sa[u * kRowStepA * (kGemmKC + 1) + kAim] = aok[u] ? va[u].im : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPerB; ++u) {
+      sb[u * kRowStepB * (TN + 1)] = bok ? vb[u].re : R(0);
+      sb[u * kRowStepB * (TN + 1) + kBim] = bok ? vb[u].im : R(0);
+    }
+    __syncthreads();
+    fetch(min(kc + kGemmKC, kGemm2K - kGemmKC));   // the next chunk (the last one again at the end, unused)
+    __builtin_amdgcn_sched_barrier(0);  // keep its loads ahead of the products
+#pragma unroll
+    for (int kk = 0; kk < kGemmKC; kk += 4) {
+      R are[MB], aim[MB], bre[NB], bim[NB];
+#pragma unroll
+      for (int a = 0; a < MB; ++a) {
+        are[a] = la[a * 16 * (kGemmKC + 1) + kk];
+        aim[a] = la[a * 16 * (kGemmKC + 1) + kk + kAim];
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        bre[c] = lb[kk * (TN + 1) + c * 16];
+        bim[c] = lb[kk * (TN + 1) + c * 16 + kBim];
+      }
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) cre[a][c] = Mfma<C>::mma(are[a], bre[c], cre[a][c]);
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) cim[a][c] = Mfma<C>::mma(are[a], bim[c], cim[a][c]);
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) cre[a][c] = Mfma<C>::mma(-aim[a], bim[c], cre[a][c]);
+#pragma unroll
+      for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) cim[a][c] = Mfma<C>::mma(aim[a], bre[c], cim[a][c]);
+    }
+  }
+  // A22 -= C, one MFMA row of the wave tile at a time: its loads first, then
+  // the stores of the in-range entries
+  C *__restrict__ Cb = A + (int64_t)r0 * ld + c0;
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    C old[NB][4];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = wr * WM + a * 16 + Mfma<C>::row(r, lane), j = wc * WN + c * 16 + (lane & 15);
+        old[c][r] = Cb[min(i, rmax) * ld32 + min(j, cmax)];
+      }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = wr * WM + a * 16 + Mfma<C>::row(r, lane), j = wc * WN + c * 16 + (lane & 15);
+        if (i <= rmax && j <= cmax)
+          Cb[i * ld32 + j] = cx<C>::make(old[c][r].re - cre[a][c][r], old[c][r].im - cim[a][c][r]);
+      }
+  }
+}
+
+__global__ __launch_bounds__(kGemm2Threads, 4) void k_lu_gemm2_z(LuStep st) { lu_gemm2_body<dz>(st); }
+__global__ __launch_bounds__(kGemm2Threads, 4) void k_lu_gemm2_c(LuStep st) { lu_gemm2_body<fz>(st); }
+
 __global__ __launch_bounds__(1024) void k_lu_pivot_z(LuStep st) { lu_pivot_body<dz>(st); }
 __global__ __launch_bounds__(1024) void k_lu_pivot_c(LuStep st) { lu_pivot_body<fz>(st); }
 __global__ __launch_bounds__(256) void k_lu_col_z(LuStep st) { lu_col_body<dz>(st); }

@@ -128,6 +128,7 @@ constexpr int kLuNB = 64;
 constexpr int kColT = 4;        // lanes per row in the panel column kernel
 constexpr int kColRows = 64;    // rows per thread block of the panel column kernel (256 / kColT)
 constexpr int kLuMaxDom = 8;
+constexpr int kGemm2Threads = 512;   // threads per block of the two-panel trailing update (k_lu_gemm2)
 // Tournament nodes: 256 rows and four children per node; a row takes two
 // lanes for FP64 factors (512 threads), one lane for FP32 (256 threads).
 constexpr int kTsFanZ = 4, kTsFanC = 4;
@@ -161,6 +162,7 @@ struct LuStep {
   __global__ void k_lu_swap_##T(LuStep st);  \
   __global__ void k_lu_trsm_##T(LuStep st);  \
   __global__ void k_lu_gemm_##T(LuStep st);  \
+  __global__ void k_lu_gemm2_##T(LuStep st); \
   __global__ void k_lu_tsel_##T(LuStep st);  \
   __global__ void k_lu_tfin_##T(LuStep st);
 VIE_DECL_LU(z)
@@ -229,9 +231,9 @@ struct KryCell {
   dz *dpart; double *npart; int nred;
   const int32_t *perm; int ndom; int64_t dstart[kCellMaxDom];
   int precond;                 // 1: no preconditioner (the product takes V_j itself)
+  int rpw;                     // matvec rows per wave (2, 4, 8): 4 RPW rows per thread block
 };
 __global__ void k_b_arn_begin(const KryCell *cells, const int *pre, int nc, const int *act);
-  int rpw;                     // matvec rows per wave (2, 4, 8): 4 RPW rows per thread block
 __global__ void k_b_permute(const KryCell *cells, const int *pre, int nc, const int *act);
 __global__ void k_b_matvec(const KryCell *cells, const int *pre, int nc, const int *act);
 __global__ void k_b_dots_j(const KryCell *cells, const int *pre, int nc, const int *act);
