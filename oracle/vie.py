@@ -504,6 +504,41 @@ def absorptance(topo, wave, eps_in, x):
     return out * wave.k0 / (np.cos(wave.theta) * topo.a * topo.b)
 
 
+def locate_points(topo, points, tol=1e-12):
+    """Tetrahedron holding each point (-1 if none): the lowest index among the
+    tetrahedra whose barycentric coordinates of the point are all >= -tol."""
+    V = topo.verts[topo.tets]                                   # [nt, 4, 3]
+    M = np.transpose(V[:, 1:, :] - V[:, :1, :], (0, 2, 1))      # columns v_k - v_0
+    Minv = np.linalg.inv(M)
+    out = np.full(len(points), -1, np.int64)
+    for i, p in enumerate(np.asarray(points, float)):
+        lam = np.einsum("tij,tj->ti", Minv, p[None, :] - V[:, 0, :])
+        inside = np.flatnonzero(np.all(lam >= -tol, axis=1) & (lam.sum(axis=1) <= 1.0 + tol))
+        if len(inside):
+            out[i] = inside[0]
+    return out
+
+
+def field_at(topo, wave, eps_in, x, points):
+    """The field of the solution inside the structure (Sec. 3, the field maps
+    behind Fig. 5): at each point, E~ = D~ / eps_T with D~ = sum_k c_k (r - v_k)
+    on the tetrahedron T holding it (internal convention, |E0| = 1).  Returns
+    (E [npts, 3] complex, tet [npts]); points outside every tetrahedron get
+    tet -1 and E = 0."""
+    eps = internal_eps(eps_in)
+    c = tet_field_coeffs(topo, wave, x)
+    pts = np.asarray(points, float)
+    tet = locate_points(topo, pts)
+    E = np.zeros((len(pts), 3), complex)
+    for i, t in enumerate(tet):
+        if t < 0:
+            continue
+        v4 = topo.verts[topo.tets[t]]
+        D = sum(c[t, k] * (pts[i] - v4[k]) for k in range(4))
+        E[i] = D / eps[t]
+    return E, tet
+
+
 def absorptance_per_tet(topo, wave, eps_in, x):
     """Each tetrahedron's term of Eq. 7 (Sec. 3) with the normalisation of
     absorptance(): k0 (-Im eps_T)/|eps_T|^2 I_T |D~|^2 dV / (cos th a b), so the
