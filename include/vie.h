@@ -211,6 +211,23 @@ int vie_absorption_pol(vie_ctx *ctx, int polarisation, double *absorptance_per_d
  * did not cover. */
 int vie_absorption_per_tet(vie_ctx *ctx, int polarisation, double *per_tet);
 
+/* The field of the last solution of polarisation `polarisation` (-1: the last
+ * solve's) at points inside the structure, for field maps on a plane (Sec. 3,
+ * the profiles behind Fig. 5): on the tetrahedron T holding a point, the SWG
+ * expansion gives D/eps0 (Sec. 2.1) and
+ *   e[3i + d] = (D/eps0)_d / eps_T,  the field E/E0 of a unit incident wave,
+ * in the library's exp(+j w t) convention (conjugate for exp(-j w t)).
+ * points [3 npts] (x, y, z in nm), host memory.  e [3 npts], host memory.
+ * tet [npts] (nullable), host memory: the tetrahedron holding each point, the
+ * lowest index when a point lies on a face shared by several, -1 when it lies
+ * in none (e = 0 there).  Points are located on the host (a bin grid over
+ * the mesh); the field is evaluated on the device, with the points staged
+ * through the Krylov-basis region of the workspace, which this call
+ * overwrites (a later solve starts its own basis).  VIE_ESTATE before a solve
+ * or for a polarisation the last solve did not cover. */
+int vie_sample_field(vie_ctx *ctx, int polarisation, const double *points, int64_t npts, vie_c128 *e,
+                     int32_t *tet);
+
 const char *vie_last_error(const vie_ctx *ctx);
 
 /* ---------------------------------------------------------------- diagnostics

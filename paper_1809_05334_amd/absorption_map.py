@@ -9,7 +9,11 @@ sphere r = 20 nm), N = 37,376, normal incidence, TE, FP64.  For each
 wavelength one JSON line gives the absorptance per domain, the density map
 (tetrahedra whose centroid lies within `--slab` nm of the plane y = b/2,
 averaged per (x, z) bin; null where no centroid falls) and, per domain, the
-mean density and the largest one with its position.
+mean density and the largest one with its position.  It also samples the
+field itself on that plane (vie_sample_field, at the centres of the same
+bins, 0.37 nm off y = b/2 so that no point lies on a mesh plane): |E|/E0 and
+the point absorption density k0 Im(eps) |E/E0|^2 / (cos th a b) (null outside
+the structure).
 
     python -m paper_1809_05334_amd.absorption_map --lambdas 400,450,650
 """
@@ -43,6 +47,10 @@ def main():
     near = np.abs(cen[:, 1] - mesh.b / 2) <= args.slab
     ix = np.clip((cen[:, 0] / mesh.a * args.nx).astype(int), 0, args.nx - 1)
     iz = np.clip(((cen[:, 2] - zlo) / (zhi - zlo) * args.nz).astype(int), 0, args.nz - 1)
+    gx = (np.arange(args.nx) + 0.5) / args.nx * mesh.a
+    gz = zlo + (np.arange(args.nz) + 0.5) / args.nz * (zhi - zlo)
+    X, Zg = np.meshgrid(gx, gz, indexing="ij")
+    plane = np.stack([X.ravel(), np.full(X.size, mesh.b / 2 + 0.37), Zg.ravel()], axis=1)
     print(f"N = {N}, {int(near.sum())} tetrahedra on the plane", file=sys.stderr, flush=True)
     for lam in [float(x) for x in args.lambdas.split(",")]:
         s.fill(lam, 0.0, 0.0, W.osc_eps(mesh, lam))
@@ -61,9 +69,18 @@ def main():
             k = int(np.argmax(np.where(sel, dens, -np.inf)))
             doms[str(d)] = {"mean_density": float(np.sum(dens[sel] * vol[sel]) / np.sum(vol[sel])),
                             "max_density": float(dens[k]), "max_at_nm": [float(c) for c in cen[k]]}
+        e, tet = s.sample_field(plane)
+        eps = W.osc_eps(mesh, lam)
+        emag = np.sqrt(np.sum(np.abs(e) ** 2, axis=1))
+        pden = np.where(tet >= 0, 2 * np.pi / lam * eps[np.maximum(tet, 0)].imag * emag ** 2 / (mesh.a * mesh.b), np.nan)
+        emap = np.where(tet >= 0, emag, np.nan).reshape(args.nx, args.nz).T
+        pmap = pden.reshape(args.nx, args.nz).T
+        as_list = lambda g: [[None if np.isnan(v) else float(v) for v in row] for row in g]
         print(json.dumps({"lambda_nm": lam, "iters": info["iters"], "absorptance": [float(a) for a in A],
                           "R": R, "T": T, "domains": doms, "map_x_nm": [0.0, mesh.a], "map_z_nm": [float(zlo), float(zhi)],
-                          "map": [[None if np.isnan(g) else float(g) for g in row] for row in grid]}), flush=True)
+                          "map": as_list(grid), "field_max_E": float(np.nanmax(emap)),
+                          "field_max_at_nm": [float(c) for c in plane[int(np.nanargmax(np.where(tet >= 0, emag, np.nan)))]],
+                          "field_map_E": as_list(emap), "field_map_density": as_list(pmap)}), flush=True)
 
 
 if __name__ == "__main__":

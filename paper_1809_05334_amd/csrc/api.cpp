@@ -1746,6 +1746,41 @@ int vie_absorption_per_tet(vie_ctx *ctx, int pol, double *per_tet) {
   return VIE_OK;
 }
 
+int vie_sample_field(vie_ctx *ctx, int pol, const double *points, int64_t npts, vie_c128 *e, int32_t *tet) {
+  if (int r = check(ctx, S_SOLVED, "vie_sample_field")) return r;
+  if (pol < 0) pol = ctx->last_pol;
+  if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE, VIE_TM or -1");
+  if (ctx->sol_k[pol] < 0) return fail(ctx, VIE_ESTATE, "the last solve did not cover this polarisation");
+  if (npts < 0 || (npts > 0 && (!points || !e))) return fail(ctx, VIE_EINVAL, "bad arguments");
+  if (npts == 0) return VIE_OK;
+  const MeshTopology &t = ctx->topo;
+  const Layout &L = ctx->L;
+  std::vector<int32_t> hostTet(npts);
+  locate_points(t, points, npts, hostTet.data());
+  if (tet) std::copy(hostTet.begin(), hostTet.end(), tet);
+  // points, their tetrahedra and the field staged in the Krylov-basis region (clobbers it), in chunks
+  const int64_t cap = (int64_t)((L.K[0].V.bytes - 1024) / 80);
+  if (cap < 1) return fail(ctx, VIE_ENOMEM, "no staging space");
+  HIPCK(hipSetDevice(ctx->device));
+  const dz *xsol = ctx->ptr<dz>(L.K[ctx->sol_k[pol]].vx);
+  for (int64_t s0 = 0; s0 < npts; s0 += cap) {
+    const int64_t m = std::min(cap, npts - s0);
+    char *base = ctx->ws + L.K[0].V.off;
+    double *dp = reinterpret_cast<double *>(base);
+    int32_t *dt = reinterpret_cast<int32_t *>(base + align256(24 * (size_t)m));
+    dz *de = reinterpret_cast<dz *>(base + align256(24 * (size_t)m) + align256(4 * (size_t)m));
+    HIPCK(hipMemcpyAsync(dp, points + 3 * s0, 24 * m, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(hipMemcpyAsync(dt, hostTet.data() + s0, 4 * m, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_field, dim3(nblk(m, 256)), dim3(256), 0, ctx->stream, m, (const double *)dp,
+                       (const int32_t *)dt, ctx->ptr<TetGeom>(L.tg), ctx->ptr<TetFace>(L.t2f),
+                       (const dz *)ctx->ptr<dz>(L.gsrc), (const dz *)ctx->ptr<dz>(L.inveps), xsol, de);
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(e + 3 * s0, de, 48 * m, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+  }
+  return VIE_OK;
+}
+
 int vie_absorption_pol(vie_ctx *ctx, int pol, double *absorptance, double *R, double *T) {
   if (int r = check(ctx, S_SOLVED, "vie_absorption_pol")) return r;
   if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");

@@ -55,6 +55,10 @@ std::string build_topology(MeshTopology &t, const double *verts, int64_t nv, con
 // rows (rowptr [N+1], cols [nnz]).
 void build_near_pattern(const MeshTopology &t, std::vector<int64_t> &rowptr, std::vector<int32_t> &cols);
 
+// Tetrahedron holding each of n points (3n doubles): the lowest index among
+// those whose barycentric coordinates are all >= -1e-12, -1 if none.
+void locate_points(const MeshTopology &t, const double *pts, int64_t n, int32_t *tet);
+
 // Touching-image mask (bit (m+1)*3 + (n+1)) of two vertex sets given by canonical
 // ids and packed offsets ((ox+2) | (oy+2) << 4).
 inline int touching_mask(const int32_t *ct, const int32_t *ot, int nt_, const int32_t *cs, const int32_t *os,

@@ -122,4 +122,29 @@ __global__ void k_reduce_cols(const double *__restrict__ part, int nblk, int wid
   out[j] = s;
 }
 
+// The field at sample points inside the structure (the field maps of
+// Sec. 3): on the tetrahedron T holding point i (tet[i], -1 if none),
+// D/eps0 = sum_k c_k (r - v_k) as in k_absorb, and e[3i + d] = (D/eps0)_d / eps_T
+// (zero outside).  One lane per point.
+__global__ __launch_bounds__(256) void k_field(int64_t np, const double *__restrict__ pts,
+                                               const int32_t *__restrict__ tet, const TetGeom *__restrict__ tg,
+                                               const TetFace *__restrict__ t2f, const dz *__restrict__ gsrc,
+                                               const dz *__restrict__ inv_eps, const dz *__restrict__ x,
+                                               dz *__restrict__ e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int32_t t = tet[i];
+  dz D[3] = {mk(0, 0), mk(0, 0), mk(0, 0)};
+  if (t >= 0) {
+    const TetGeom &g = tg[t];
+    for (int k = 0; k < 4; ++k) {
+      const dz c = (1.0 / 3.0) * (x[t2f[4 * t + k].unknown] * gsrc[4 * t + k]);
+      for (int d = 0; d < 3; ++d) axpy(D[d], pts[3 * i + d] - g.v[k][d], c);
+    }
+    const dz ie = inv_eps[t];
+    for (int d = 0; d < 3; ++d) D[d] = D[d] * ie;
+  }
+  for (int d = 0; d < 3; ++d) e[3 * i + d] = D[d];
+}
+
 }  // namespace vie

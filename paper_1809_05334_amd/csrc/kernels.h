@@ -287,5 +287,7 @@ __global__ void k_absorb(int64_t nt, int ndom, const TetGeom *tg, const TetFace 
 __global__ void k_project(int64_t nt, const TetGeom *tg, const TetFace *t2f, const QuadRules *qr, const dz *gsrc,
                           const dz *kappa, const dz *x, int nk, const double *kv, double *part);
 __global__ void k_reduce_cols(const double *part, int nblk, int width, double *out);
+__global__ void k_field(int64_t np, const double *pts, const int32_t *tet, const TetGeom *tg, const TetFace *t2f,
+                        const dz *gsrc, const dz *inv_eps, const dz *x, dz *e);
 
 }  // namespace vie

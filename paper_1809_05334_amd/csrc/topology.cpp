@@ -378,4 +378,83 @@ void build_near_pattern(const MeshTopology &t, std::vector<int64_t> &rowptr, std
   for (int64_t m = 0; m < N; ++m) std::copy(raw.begin() + cnt[m], raw.begin() + cnt[m] + uniq[m], cols.begin() + rowptr[m]);
 }
 
+// Tetrahedron holding each point: the lowest index among the tetrahedra
+// whose barycentric coordinates of the point are all >= -1e-12, -1 if none.
+// Candidates come from a uniform bin grid over the mesh's bounding box (bin
+// edge about twice the mean tetrahedron edge); each tetrahedron is listed,
+// in increasing order, in every bin its slightly padded bounding box meets.
+void locate_points(const MeshTopology &t, const double *pts, int64_t n, int32_t *tet) {
+  if (t.nt == 0) {
+    std::fill(tet, tet + n, -1);
+    return;
+  }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < t.nv; ++v)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], t.verts[3 * v + d]);
+      hi[d] = std::max(hi[d], t.verts[3 * v + d]);
+    }
+  double vol = 0;
+  for (int64_t i = 0; i < t.nt; ++i) vol += t.vol[i];
+  const double h = std::max(2.0 * std::cbrt(6.0 * vol / (double)t.nt), 1e-9);
+  int nb[3];
+  for (int d = 0; d < 3; ++d) nb[d] = (int)std::min<double>(512.0, std::floor((hi[d] - lo[d]) / h) + 1);
+  auto bin_of = [&](int d, double x) { return std::max(0, std::min(nb[d] - 1, (int)std::floor((x - lo[d]) / h))); };
+  const int64_t nbins = (int64_t)nb[0] * nb[1] * nb[2];
+  std::vector<std::vector<int32_t>> bins(nbins);
+  for (int64_t i = 0; i < t.nt; ++i) {
+    double bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < 4; ++k)
+      for (int d = 0; d < 3; ++d) {
+        const double x = t.verts[3 * (int64_t)t.tets[4 * i + k] + d];
+        bl[d] = std::min(bl[d], x);
+        bh[d] = std::max(bh[d], x);
+      }
+    int b0[3], b1[3];
+    for (int d = 0; d < 3; ++d) {
+      const double pad = 1e-9 * (bh[d] - bl[d] + h);
+      b0[d] = bin_of(d, bl[d] - pad);
+      b1[d] = bin_of(d, bh[d] + pad);
+    }
+    for (int x = b0[0]; x <= b1[0]; ++x)
+      for (int y = b0[1]; y <= b1[1]; ++y)
+        for (int z = b0[2]; z <= b1[2]; ++z) bins[((int64_t)x * nb[1] + y) * nb[2] + z].push_back((int32_t)i);
+  }
+  for (int64_t p = 0; p < n; ++p) {
+    const double *q = pts + 3 * p;
+    tet[p] = -1;
+    bool outside = false;
+    for (int d = 0; d < 3; ++d) outside |= !(q[d] >= lo[d] - 1e-9 * h && q[d] <= hi[d] + 1e-9 * h);
+    if (outside) continue;
+    const auto &cand = bins[((int64_t)bin_of(0, q[0]) * nb[1] + bin_of(1, q[1])) * nb[2] + bin_of(2, q[2])];
+    for (int32_t i : cand) {
+      // barycentric coordinates: solve [v1-v0 v2-v0 v3-v0] l = q - v0 by Cramer's rule
+      const double *v0 = &t.verts[3 * (int64_t)t.tets[4 * i]];
+      double e[3][3], r[3];
+      for (int k = 0; k < 3; ++k) {
+        const double *vk = &t.verts[3 * (int64_t)t.tets[4 * i + k + 1]];
+        for (int d = 0; d < 3; ++d) e[d][k] = vk[d] - v0[d];
+      }
+      for (int d = 0; d < 3; ++d) r[d] = q[d] - v0[d];
+      auto det3 = [](const double m[3][3]) {
+        return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+               m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+      };
+      const double det = det3(e);
+      double l[3], sum = 0;
+      for (int k = 0; k < 3; ++k) {
+        double m[3][3];
+        for (int d = 0; d < 3; ++d)
+          for (int c = 0; c < 3; ++c) m[d][c] = c == k ? r[d] : e[d][c];
+        l[k] = det3(m) / det;
+        sum += l[k];
+      }
+      if (l[0] >= -1e-12 && l[1] >= -1e-12 && l[2] >= -1e-12 && 1.0 - sum >= -1e-12) {
+        tet[p] = i;
+        break;
+      }
+    }
+  }
+}
+
 }  // namespace vie

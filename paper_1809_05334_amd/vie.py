@@ -86,6 +86,7 @@ _SIGS = {
     "vie_absorption": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_absorption_pol": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_absorption_per_tet": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "vie_sample_field": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "vie_last_error": (C.c_char_p, [C.c_void_p]),
     "vie_export_faces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_read_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -272,6 +273,16 @@ class Solver:
         out = np.zeros(self.nt)
         self._ck(self.lib.vie_absorption_per_tet(self.h, -1 if pol is None else int(pol), _p(out)))
         return out
+
+    def sample_field(self, points, pol=None):
+        """E/E0 at points [n, 3] (nm) inside the structure for the last solution
+        (or polarisation `pol`): (e [n, 3] complex, tet [n]; -1 and e = 0
+        outside every tetrahedron)."""
+        p = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+        e = np.zeros((len(p), 3), np.complex128)
+        tet = np.zeros(len(p), np.int32)
+        self._ck(self.lib.vie_sample_field(self.h, -1 if pol is None else int(pol), _p(p), len(p), _p(e), _p(tet)))
+        return e, tet
 
     # -------------------------------------------------------------- diagnostics
     def read_Z(self, rows, cols):
