@@ -159,7 +159,7 @@ int vie_bind_static_workspace(vie_ctx *ctx, int precision, int restart);
  * eps_per_tet [nt] (Sec. 2.1, Eq. 2 with the periodic Green's function of
  * Sec. 2.2, Eqs. 3-4).  precision: VIE_FP64 or VIE_MIXED_FP32 (must match the
  * bound workspace).  VIE_EWOOD if a non-specular Floquet order has
- * |gamma_pq| / k0 < 0.02. */
+ * |gamma_pq| / k0 < 0.02; VIE_EINVAL if a permittivity is zero or not finite. */
 int vie_fill(vie_ctx *ctx, double lambda_nm, double theta_rad, double phi_rad, const vie_c128 *eps_per_tet,
              int precision);
 

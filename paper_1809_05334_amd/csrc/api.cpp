@@ -599,9 +599,6 @@ int vie_bind_static_workspace(vie_ctx *ctx, int precision, int restart) {
 
 namespace vie {
 
-// Host part of a fill: the lattice-sum tables of (lambda, theta, phi), the
-// permittivities, the per-tetrahedron coefficients, and Z (with its staging
-// copy and near part) cleared; records ev0.  Decides the form of the far fill.
 // Host-only part of a fill (no device work; any thread): the lattice-sum
 // tables of (lambda, theta, phi) packed for the device, and the internal
 // permittivities.  The previous fill's kernels may still read the device
@@ -618,6 +615,11 @@ int fill_tables(vie_ctx *ctx, double lambda_nm, double theta, double phi, const 
   ctx->lambda = lambda_nm;
   ctx->theta = theta;
   ctx->phi = phi;
+  for (int64_t i = 0; i < t.nt; ++i) {
+    const vie_c128 e = eps_per_tet[i];
+    if (!std::isfinite(e.re) || !std::isfinite(e.im) || (e.re == 0 && e.im == 0))
+      return fail(ctx, VIE_EINVAL, "permittivity of tetrahedron %lld is zero or not finite", (long long)i);
+  }
   ctx->eps_int.resize(t.nt);
   for (int64_t i = 0; i < t.nt; ++i) ctx->eps_int[i] = dz{eps_per_tet[i].re, -eps_per_tet[i].im};
   pack_pgf_table(*ctx->tab, ctx->pack);

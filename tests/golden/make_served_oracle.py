@@ -1,5 +1,5 @@
 """Writes served_oracle.json: oracle absorptance per domain, R and T for a few
-cells of the batched/served workload (config-4 generator: Drude-Ag sphere in
+cells of the batched/served workload (the batch-cell generator: Drude-Ag sphere in
 a spacer layer over an active layer, uneven N, oblique incidence, random
 polarisation), one of them at an incidence where a non-specular Floquet
 order propagates (a (1 + sin theta) > lambda).

@@ -8,7 +8,7 @@ def slab_small():
     return W.slab_mesh(a=50.0, b=50.0, thickness=50.0, nx=2, ny=2, nz=2)
 
 
-def slab_cfg1():
+def slab_100nm():
     return W.slab_mesh()
 
 
@@ -34,9 +34,25 @@ def osc_rect():
     return W.Mesh(verts, tets, dom, 3, 60.0, 45.0, (xs, ys, zs), {"kind": "rect"})
 
 
+def osc_jitter():
+    """osc_small's grid with every vertex off the cell walls and the top and
+    bottom planes moved by up to 1.5 nm (seeded): tetrahedra that are no
+    longer Kuhn-congruent; lossless permittivities (eps_for)."""
+    m = osc_small()
+    v = m.verts.copy()
+    rng = np.random.default_rng(21)
+    inner = ((v[:, 0] > 0) & (v[:, 0] < m.a) & (v[:, 1] > 0) & (v[:, 1] < m.b)
+             & (v[:, 2] > v[:, 2].min()) & (v[:, 2] < v[:, 2].max()))
+    v[inner] += rng.uniform(-1.5, 1.5, size=(int(inner.sum()), 3))
+    return W.Mesh(v, m.tets, m.tet_domain, m.ndom, m.a, m.b, m.grid, {"kind": "lossless"})
+
+
 def eps_for(mesh, lam):
     if mesh.ndom == 1:
         return W.slab_eps(mesh)
+    if mesh.info.get("kind") == "lossless":
+        table = np.array([2.3 + 0j, 3.6 + 0j, 2.1 + 0j])
+        return table[mesh.tet_domain]
     if mesh.info.get("kind") == "rect":
         table = np.array([W.EPS_SPACER, W.EPS_ACTIVE, W.drude_eps(lam)])
         return table[mesh.tet_domain]

@@ -17,7 +17,7 @@ from oracle import topology as OT
 from oracle import vie as OV
 from paper_1809_05334_amd import workloads as W
 
-from gpu_cases import eps_for, osc_rect, osc_small, slab_cfg1
+from gpu_cases import eps_for, osc_rect, osc_small, slab_100nm
 
 pytestmark = pytest.mark.gpu
 
@@ -31,8 +31,8 @@ def vie():
     return V
 
 
-CASES = {"slab_cfg1": slab_cfg1, "osc_small": osc_small, "osc_rect": osc_rect}
-ILLUM = {"slab_cfg1": (600.0, 0.5, 0.3), "osc_small": (520.0, 0.35, 0.6), "osc_rect": (450.0, 0.6, 1.1)}
+CASES = {"slab_100nm": slab_100nm, "osc_small": osc_small, "osc_rect": osc_rect}
+ILLUM = {"slab_100nm": (600.0, 0.5, 0.3), "osc_small": (520.0, 0.35, 0.6), "osc_rect": (450.0, 0.6, 1.1)}
 
 
 def solver(vie, m, precision, restart=60):

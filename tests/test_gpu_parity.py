@@ -13,7 +13,7 @@ from oracle import topology as OT
 from oracle import vie as OV
 from paper_1809_05334_amd import workloads as W
 
-from gpu_cases import eps_for, osc_rect, osc_small, slab_cfg1, slab_small
+from gpu_cases import eps_for, osc_jitter, osc_rect, osc_small, slab_100nm, slab_small
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,10 @@ def make_solver(vie, m, restart=60):
     return s
 
 
-CASES = {"slab_small": slab_small, "slab_cfg1": slab_cfg1, "osc_small": osc_small, "osc_rect": osc_rect}
-ILLUM = {"slab_small": (600.0, 0.0, 0.0), "slab_cfg1": (600.0, 0.5, 0.3),
-         "osc_small": (520.0, 0.35, 0.6), "osc_rect": (450.0, 0.6, 1.1)}
+CASES = {"slab_small": slab_small, "slab_100nm": slab_100nm, "osc_small": osc_small, "osc_rect": osc_rect,
+         "osc_jitter": osc_jitter}
+ILLUM = {"slab_small": (600.0, 0.0, 0.0), "slab_100nm": (600.0, 0.5, 0.3),
+         "osc_small": (520.0, 0.35, 0.6), "osc_rect": (450.0, 0.6, 1.1), "osc_jitter": (540.0, 1.15, 0.25)}
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -176,6 +177,13 @@ def test_error_paths(vie):
     with pytest.raises(vie.VieError) as e:
         s.fill(50.0 * (1 + np.sin(th)), th, 0.0, W.slab_eps(m))
     assert e.value.code == vie.VIE_EWOOD
+    # a permittivity that is zero or not finite
+    for bad_eps in (np.nan, np.inf, 0.0):
+        e_bad = W.slab_eps(m).copy()
+        e_bad[3] = bad_eps
+        with pytest.raises(vie.VieError) as e:
+            s.fill(600.0, 0.0, 0.0, e_bad)
+        assert e.value.code == vie.VIE_EINVAL
     s.fill(600.0, 0.0, 0.0, W.slab_eps(m))
     s.factor()
     # two-domain split of the slab so that GMRES needs more than one iteration

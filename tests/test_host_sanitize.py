@@ -1,0 +1,69 @@
+"""The library's host C++ under AddressSanitizer and UndefinedBehaviorSanitizer.
+
+tests/host_check.cpp drives mesh topology and validation, the near-pair
+pattern, point location, the quadrature rules and the lattice-sum tables on
+seeded meshes; g++ builds it with the host sources and -fsanitize=address,
+undefined (no device code).  The run must end cleanly, and the unknown count
+must equal the oracle's topology for the same mesh."""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import topology as OT
+from paper_1809_05334_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_1809_05334_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    out = str(tmp_path_factory.mktemp("asan") / "host_check")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-I", CSRC, "-I", os.path.join(os.path.dirname(HERE), "include"),
+           os.path.join(HERE, "host_check.cpp"), os.path.join(CSRC, "topology.cpp"), os.path.join(CSRC, "tables.cpp"),
+           "-o", out, "-lpthread"]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    assert p.returncode == 0, p.stderr[-3000:]
+    return out
+
+
+def write_mesh(path, m):
+    with open(path, "wb") as f:
+        f.write(struct.pack("<qqidd", len(m.verts), len(m.tets), int(m.ndom), float(m.a), float(m.b)))
+        f.write(np.ascontiguousarray(m.verts, "<f8").tobytes())
+        f.write(np.ascontiguousarray(m.tets, "<i4").tobytes())
+        f.write(np.ascontiguousarray(m.tet_domain, "<i4").tobytes())
+
+
+def meshes():
+    xs = np.array([0.0, 12.0, 20.0, 28.0, 40.0])
+    zs = np.array([0.0, 20.0, 30.0, 40.0])
+    verts, tets = W.brick_grid_mesh(xs, xs, zs)
+    c = W.centroids(verts, tets)
+    dom = np.where(c[:, 2] < 20.0, 1, 0).astype(np.int32)
+    dom[np.sum((c - [20.0, 20.0, 30.0]) ** 2, 1) <= 8.0 ** 2] = 2
+    yield "three-domain", W.Mesh(verts, tets, dom, 3, 40.0, 40.0, (xs, xs, zs))
+    yield "slab", W.slab_mesh()
+    yield "batch cell", W.cell_mesh(W.batch_cells(1, seed=3, n_lo=2000, n_hi=3000)[0])
+
+
+@pytest.mark.parametrize("name,mesh", list(meshes()), ids=lambda v: v if isinstance(v, str) else "")
+def test_host_code_is_clean_under_sanitizers(driver, tmp_path, name, mesh):
+    path = str(tmp_path / "mesh.bin")
+    write_mesh(path, mesh)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    p = subprocess.run([driver, path], capture_output=True, text=True, env=env, timeout=600)
+    assert p.returncode == 0, (p.stdout[-2000:], p.stderr[-4000:])
+    assert "runtime error" not in p.stderr and "ERROR: AddressSanitizer" not in p.stderr, p.stderr[-4000:]
+    topo = OT.build(mesh.verts, mesh.tets, mesh.tet_domain, mesh.ndom, mesh.a, mesh.b)
+    first = p.stdout.splitlines()[0].split()
+    assert int(first[1]) == topo.N
+    assert p.stdout.count("table lambda") == 3
