@@ -169,6 +169,7 @@ def run_fused(requests, precision, slots=2, budget_gb=200.0, tol=1e-8, restart=1
             finally:
                 for p in wave:
                     p["solver"].close()
+                torch.cuda.empty_cache()   # the wave's workspaces back to the device (see serve.VieBackend.release)
                 with lock:
                     used[0] -= nbytes
 

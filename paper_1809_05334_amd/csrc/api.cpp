@@ -284,6 +284,33 @@ int matvec2(vie_ctx *ctx, const MvVecs &v) {
 // ================================================================ C-ABI
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// Events, pinned staging and the static workspace's address of a new context.
+int init_ctx(vie_ctx *ctx) {
+  ctx->tab = new PgfTable();
+  build_quadrature(ctx->quad);
+  HIPCK(hipSetDevice(ctx->device));
+  HIPCK(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
+  HIPCK(hipEventCreate(&ctx->ev0));
+  HIPCK(hipEventCreate(&ctx->ev1));
+  HIPCK(hipEventCreate(&ctx->ev2));
+  HIPCK(hipEventCreate(&ctx->ev3));
+  HIPCK(hipEventCreate(&ctx->ev4));
+  if (int rc = resolve_static(ctx)) return rc;
+  // the factorisation's side stream is created at its first use, so contexts
+  // that only wait (a serving queue) hold no stream of their own
+  HIPCK(hipEventCreateWithFlags(&ctx->ev_la, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&ctx->ev_ts, hipEventDisableTiming));
+  return VIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int vie_create(vie_ctx **out, int device, void *hip_stream) {
   if (!out) return VIE_EINVAL;
   *out = nullptr;
@@ -292,19 +319,10 @@ int vie_create(vie_ctx **out, int device, void *hip_stream) {
   vie_ctx *ctx = new vie_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
-  ctx->tab = new PgfTable();
-  build_quadrature(ctx->quad);
-  HIPCK(hipSetDevice(device));
-  HIPCK(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
-  HIPCK(hipEventCreate(&ctx->ev0));
-  HIPCK(hipEventCreate(&ctx->ev1));
-  HIPCK(hipEventCreate(&ctx->ev2));
-  HIPCK(hipEventCreate(&ctx->ev3));
-  HIPCK(hipEventCreate(&ctx->ev4));
-  if (int rc = resolve_static(ctx)) return rc;
-  HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-  HIPCK(hipEventCreateWithFlags(&ctx->ev_la, hipEventDisableTiming));
-  HIPCK(hipEventCreateWithFlags(&ctx->ev_ts, hipEventDisableTiming));
+  if (int rc = init_ctx(ctx)) {
+    vie_destroy(ctx);
+    return rc;
+  }
   *out = ctx;
   return VIE_OK;
 }
@@ -1163,6 +1181,7 @@ extern "C" {
 int vie_precond_factor(vie_ctx *ctx) {
   std::vector<LuDom> doms;
   if (int rc = factor_prepare(ctx, doms)) return rc;
+  if (!ctx->side) HIPCK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
   if (int rc = factor_panels(ctx, doms, fp32_factors(ctx), ctx->lu_pivot, ctx->stream, ctx->side, ctx->ev_la,
                              ctx->ev_ts))
     return rc;

@@ -233,6 +233,9 @@ class VieBackend:
         self.precision = vie.VIE_MIXED_FP32 if precision is None else precision
         self.restart, self.tol, self.max_iter = restart, tol, max_iter
         self.sym = sym   # one lattice sum per unordered far pair (admission counts its staging copy)
+        # prepared contexts wait on one shared stream (they issue no device
+        # work before `run` moves them to a worker's stream)
+        self.prep_stream = torch.cuda.Stream(device=device)
 
     def make_worker(self, wid):
         return self.torch.cuda.Stream(device=self.device)
@@ -241,7 +244,7 @@ class VieBackend:
         # a request names a cell of the workload generator, or brings its own
         # mesh (and then may bring its own per-tetrahedron permittivities)
         mesh = req["mesh"] if "mesh" in req else self.W.cell_mesh(req["cell"])
-        s = self.vie.Solver(self.device)
+        s = self.vie.Solver(self.device, stream=self.prep_stream)
         s.upload_mesh(mesh)
         if self.sym:
             s.set_option(self.vie.VIE_OPT_SYM_FILL, 1)
@@ -262,8 +265,15 @@ class VieBackend:
     def release(self, prep):
         s = prep.get("solver")
         if s is not None:
-            s.close()
+            big = s.ws is not None and s.ws.numel() >= (1 << 30)
+            s.close()   # waits for the context's stream, then drops the workspace
             prep["solver"] = None
+            if big:
+                # hand a large workspace back to the device at once: kept in
+                # torch's cache it would hold memory that neither the next
+                # request (of another size) nor the HIP runtime (queues,
+                # scratch) could use
+                self.torch.cuda.empty_cache()
 
 
 def main():
