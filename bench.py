@@ -65,26 +65,29 @@ def case_of_step(i, all_cases):
     return all_cases[(STRIDE * i) % len(all_cases)]
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_tt_far_traffic_osc_cell_N77600.md")
+FP32_MFMA_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak
+FAR_PROFILE = os.path.join(ROOT, "profiles", "k_tt_far_rev_counters_osc_cell_N77600.md")
 FAR_SOURCES = ["k_fill.hip", "device_math.h", "common.h", "tables.cpp"]   # kernel code and the tables that set its work
+LU_PROFILE = os.path.join(ROOT, "profiles", "k_lu_gemm2_counters_osc_cell_N77600.md")
+LU_SOURCES = ["k_lu.hip"]
 
 
-def far_counters():
-    """HBM bytes and hardware FP64 FLOPs per far-kernel launch from the
-    committed counter summary, or None when the kernel's sources changed after
-    the counters were read."""
+def profile_counters(path, sources):
+    """Per-launch figures from a committed counter summary (HBM bytes, and
+    hardware FLOPs when recorded), or None when the kernel's sources changed
+    after the counters were read."""
     import hashlib
     import re
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in FAR_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_1809_05334_amd", "csrc", f), "rb").read())
     m_hash = re.search(r"kernel_source_sha256_16: ([0-9a-f]+)", txt)
     m_val = re.search(r"traffic_bytes_per_launch: ([0-9.e+]+)", txt)
-    m_hw = re.search(r"hw_fp64_flops_per_launch: ([0-9.e+]+)", txt)
+    m_hw = re.search(r"hw_flops_per_launch: ([0-9.e+]+)", txt)
     if not m_hash or not m_val or m_hash.group(1) != h.hexdigest()[:16]:
         return None
     return {"traffic": float(m_val.group(1)), "hw_flops": float(m_hw.group(1)) if m_hw else None}
@@ -186,14 +189,15 @@ def main():
         ws_bytes = s.bind(precision, args.restart)
         if args.graph_steps:
             s.set_option(vie.VIE_OPT_GRAPH_STEPS, args.graph_steps)
-        lat, stages, fills, results, step_s = [], [], [], [], []
+        lat, stages, fills, facs, results, step_s = [], [], [], [], [], []
 
         def step(i, case):
             lam, th, ph = case
             t0 = time.perf_counter()
             s.fill(lam, np.deg2rad(th), np.deg2rad(ph), eps_of[lam])
-            fills.append(s.fill_stats())
+            fills.append({**s.fill_stats(), "oblique": th != 0})
             s.factor()
+            facs.append(s.factor_stats())
             infos = s.solve_pair(tol=args.tol, max_iter=args.max_iter, restart=args.restart, allow_noconv=True)
             out = {}
             for pol in (vie.VIE_TE, vie.VIE_TM):
@@ -219,7 +223,7 @@ def main():
         print(f"autotune: {json.dumps(tuning)}", file=sys.stderr, flush=True)
         for i, c in enumerate(warm_cases):
             step(i, c)
-        lat.clear(); stages.clear(); fills.clear(); results.clear(); step_s.clear()
+        lat.clear(); stages.clear(); fills.clear(); facs.clear(); results.clear(); step_s.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, c in enumerate(timed_cases):
@@ -230,7 +234,7 @@ def main():
         s.close()
         del s
         torch.cuda.empty_cache()
-        return {"N": N, "ws_bytes": ws_bytes, "dt": dt, "lat": lat, "stages": stages, "fills": fills,
+        return {"N": N, "ws_bytes": ws_bytes, "dt": dt, "lat": lat, "stages": stages, "fills": fills, "facs": facs,
                 "results": results, "mv_ms": mv_ms, "tuning": tuning, "step_s": step_s, "sym": sym}
 
     mixed = run_path(vie.VIE_MIXED_FP32, warm, timed)
@@ -254,23 +258,43 @@ def main():
         launches = sum(f["far_launches"] for f in fills)
         return flops, ms, launches
 
-    # dominant kernel of the headline (mixed) path: the far tet-pair fill kernel
-    far_flops, far_ms, far_launches = far_rate(mixed["fills"])
+    # the far tet-pair fill kernel of the oblique cases (with the symmetric
+    # fill: k_tt_far_rev, one lattice sum per unordered pair; normal-incidence
+    # cases run k_tt_far and are left out)
+    obl = [f for f in mixed["fills"] if f["oblique"]] or mixed["fills"]
+    far_kernel = "k_tt_far_rev" if mixed["sym"] and obl[0]["oblique"] else "k_tt_far"
+    far_flops, far_ms, far_launches = far_rate(obl)
     far_tflops = far_flops / (far_ms * 1e-3) / 1e12
     mv32_bytes = 8.0 * N * N + 32.0 * N
     mv64_bytes = 16.0 * N * N + 32.0 * N
     mv32_gbs = mv32_bytes / (mixed["mv_ms"] * 1e-3) / 1e9
-    counters = far_counters()
+    counters = profile_counters(FAR_PROFILE, FAR_SOURCES) if far_kernel == "k_tt_far_rev" else None
     avg_ms = far_ms / far_launches
-    roofline = {"bound": "alu", "kernel": "k_tt_far", "achieved": far_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": far_tflops / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": counters["traffic"] if counters else None,
-                "traffic_unit": "bytes per launch", "launches": far_launches,
-                "flops_per_launch": far_flops / far_launches, "avg_launch_ms": avg_ms}
+    far_roofline = {"bound": "alu", "kernel": far_kernel, "achieved": far_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": far_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                    "traffic": counters["traffic"] if counters else None,
+                    "traffic_unit": "bytes per launch", "launches": far_launches,
+                    "flops_per_launch": far_flops / far_launches, "avg_launch_ms": avg_ms}
     if counters and counters["hw_flops"]:
         # hardware-counted FP64 FLOPs (rocprofv3 VALU counters) over the same launch time
-        roofline["achieved_hw"] = counters["hw_flops"] / (avg_ms * 1e-3) / 1e12
-        roofline["frac_hw"] = roofline["achieved_hw"] / FP64_VECTOR_PEAK_TFLOPS
+        far_roofline["achieved_hw"] = counters["hw_flops"] / (avg_ms * 1e-3) / 1e12
+        far_roofline["frac_hw"] = far_roofline["achieved_hw"] / FP64_VECTOR_PEAK_TFLOPS
+    # dominant kernel of a step (largest device time): the block factor's
+    # K = 128 trailing update on the FP32 matrix cores, timed live by the
+    # library (HIP events around each launch on the context's stream)
+    upd_flops = sum(f["update_flops"] for f in mixed["facs"])
+    upd_ms = sum(f["t_update_ms"] for f in mixed["facs"])
+    upd_n = sum(f["update_launches"] for f in mixed["facs"])
+    upd_tflops = upd_flops / (upd_ms * 1e-3) / 1e12
+    lu_counters = profile_counters(LU_PROFILE, LU_SOURCES)
+    roofline = {"bound": "mfma", "kernel": "k_lu_gemm2_c", "achieved": upd_tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": upd_tflops / FP32_MFMA_PEAK_TFLOPS,
+                "traffic": lu_counters["traffic"] if lu_counters else None,
+                "traffic_unit": "bytes per launch", "launches": upd_n, "flops_per_launch": upd_flops / upd_n,
+                "avg_launch_ms": upd_ms / upd_n,
+                "step_share": upd_ms / sum(st["fill_ms"] + st["factor_ms"] + st["pair_solve_ms"]
+                                           for st in mixed["stages"]),
+                "factor_ms": [f["t_factor_ms"] for f in mixed["facs"]]}
     res = {
         "metric": "solves/s (mixed FP32/FP64 path) vs FP64 path at dA<=1e-4; p50/p99 latency; fill GFLOP/s; "
                   "matvec GB/s",
@@ -300,6 +324,7 @@ def main():
         "tuning": {"mixed": mixed["tuning"]},
         "fill_stats": mixed["fills"][-1],
         "roofline": roofline,
+        "far_fill_roofline": far_roofline,
     }
     if fp64:
         ff, fms, _ = far_rate(fp64["fills"])
@@ -311,6 +336,11 @@ def main():
                        "workspace_gb": fp64["ws_bytes"] / 1e9, "sym_fill": fp64["sym"], "dtype": "f64",
                        "stages": fp64["stages"]}
         res["fp64"]["matvec_frac_hbm"] = res["fp64"]["matvec_gbs"] / HBM_PEAK_GBS
+        u_fl = sum(f["update_flops"] for f in fp64["facs"])
+        u_ms = sum(f["t_update_ms"] for f in fp64["facs"])
+        if u_ms > 0:   # k_lu_gemm2_z on the FP64 matrix cores (peak 78.6 TFLOP/s)
+            res["fp64"]["lu_update_tflops"] = u_fl / (u_ms * 1e-3) / 1e12
+            res["fp64"]["lu_update_frac_mfma"] = res["fp64"]["lu_update_tflops"] / 78.6
         res["tuning"]["fp64"] = fp64["tuning"]
         res["dA_per_case"] = dA_cases
         res["dA_mixed_vs_fp64"] = max(d["dA"] for d in dA_cases)

@@ -377,6 +377,21 @@ typedef struct {
 } vie_fill_stats;
 int vie_get_fill_stats(const vie_ctx *ctx, vie_fill_stats *out);
 
+/* Timing and work counts of the last vie_precond_factor (Sec. 2.3, Eq. 6).
+ * t_update_ms sums the device times (HIP events on the context's stream around
+ * each launch) of the bulk trailing updates that follow each pair of 64-column
+ * panels (K = 128, tournament pivoting only; zero with VIE_OPT_LU_PIVOT = 1);
+ * update_flops is their algorithmic work, 8 rows cols 128 real FLOPs per
+ * domain and pair (four real products and four sums per complex multiply-add);
+ * factor_flops = (8/3) sum_d n_d^3, the whole factorisation's.  VIE_ESTATE
+ * before a factorisation. */
+typedef struct {
+  double t_factor_ms, t_update_ms;
+  double update_flops, factor_flops;
+  int64_t update_launches;
+} vie_factor_stats;
+int vie_get_factor_stats(const vie_ctx *ctx, vie_factor_stats *out);
+
 /* Time `reps` back-to-back products y = Z x on the context's stream (HIP
  * events); *ms_per_matvec = average.  Needs a completed fill; uses the
  * solver's work vectors. */

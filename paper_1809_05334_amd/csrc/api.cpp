@@ -356,6 +356,7 @@ int vie_destroy(vie_ctx *ctx) {
   }
   if (ctx->ev_la) (void)hipEventDestroy(ctx->ev_la);
   if (ctx->ev_ts) (void)hipEventDestroy(ctx->ev_ts);
+  for (hipEvent_t e : ctx->upd_ev) (void)hipEventDestroy(e);
   delete ctx->tab;
   delete ctx;
   return VIE_OK;
@@ -978,6 +979,7 @@ int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
   int32_t *ipiv = ctx->ptr<int32_t>(L.ipiv), *info = ctx->ptr<int32_t>(L.info);
   HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(hipMemsetAsync(info, 0, 4 * t.ndom, ctx->stream));
+  ctx->upd_n = 0;
   doms.assign(t.ndom, LuDom{});
   int64_t poff = 0, pvoff = 0;
   for (int d = 0; d < t.ndom; ++d) {
@@ -1071,6 +1073,22 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
       const int nc = gcols > 0 ? std::min(gcols, ntc - gcol0) : ntc - gcol0;
       return nc > 0 ? 8 * (int)nblk(nr * nc, 8) : 0;
     };
+    // each bulk update between an event pair of ctx's pool (its device time)
+    auto timed_gemm2 = [&](int k0, int gcol0, int gcols) -> int {
+      if ((int)ctx->upd_ev.size() < 2 * (ctx->upd_n + 1)) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCK(hipEventCreate(&e0));
+        HIPCK(hipEventCreate(&e1));
+        ctx->upd_ev.push_back(e0);
+        ctx->upd_ev.push_back(e1);
+      }
+      HIPCK(hipEventRecord(ctx->upd_ev[2 * ctx->upd_n], stream));
+      lu_launch(f32, stream, LU_GEMM2, doms, k0, k0, [&](int d) { return gemm2_blocks(d, k0, gcol0, gcols); }, 0, gcol0,
+                gcols);
+      HIPCK(hipEventRecord(ctx->upd_ev[2 * ctx->upd_n + 1], stream));
+      ++ctx->upd_n;
+      return VIE_OK;
+    };
     tsel(0, stream);
     for (int k0 = 0; k0 < maxn; k0 += 2 * kLuNB) {
       const int kb = k0 + kLuNB, next = k0 + 2 * kLuNB;
@@ -1090,12 +1108,12 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
         lu_launch(f32, stream, LU_TRSM, doms, kb, kb, trsm_blocks(kb));
       }
       if (next < maxn) {
-        lu_launch(f32, stream, LU_GEMM2, doms, k0, k0, [&](int d) { return gemm2_blocks(d, k0, 0, 1); }, 0, 0, 1);
+        if (int rc = timed_gemm2(k0, 0, 1)) return rc;
         HIPCK(hipEventRecord(ev_la, stream));
         HIPCK(hipStreamWaitEvent(side, ev_la, 0));
         tsel(next, side);
         HIPCK(hipEventRecord(ev_ts, side));
-        lu_launch(f32, stream, LU_GEMM2, doms, k0, k0, [&](int d) { return gemm2_blocks(d, k0, 1, 0); }, 0, 1, 0);
+        if (int rc = timed_gemm2(k0, 1, 0)) return rc;
       }
       LAUNCHCK();
     }
@@ -1149,6 +1167,26 @@ int factor_finish(vie_ctx *ctx, const std::vector<LuDom> &doms) {
   float ms = 0;
   HIPCK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->t_factor = ms;
+  {
+    vie_factor_stats &fs = ctx->facstats;
+    fs = vie_factor_stats{};
+    fs.t_factor_ms = ms;
+    for (int i = 0; i < ctx->upd_n; ++i) {
+      float e = 0;
+      HIPCK(hipEventElapsedTime(&e, ctx->upd_ev[2 * i], ctx->upd_ev[2 * i + 1]));
+      fs.t_update_ms += e;
+    }
+    fs.update_launches = ctx->upd_n;
+    for (const LuDom &D : doms) {
+      const double n = D.n;
+      fs.factor_flops += 8.0 / 3.0 * n * n * n;
+      if (ctx->upd_n)
+        for (int64_t k0 = 0; k0 + 2 * kLuNB < D.n; k0 += 2 * kLuNB) {
+          const double m = (double)(D.n - k0 - 2 * kLuNB);
+          fs.update_flops += 8.0 * m * m * (2 * kLuNB);
+        }
+    }
+  }
   const int32_t *inf = reinterpret_cast<const int32_t *>(ctx->pinned);
   for (int d = 0; d < t.ndom; ++d)
     if (inf[d] < 0) return fail(ctx, VIE_EDEVICE, "tournament pivoting of block %d chose a row outside the panel", d);
@@ -1982,6 +2020,13 @@ int vie_pgf_eval(vie_ctx *ctx, const double *delta, int64_t n, vie_c128 *out) {
     HIPCK(hipMemcpyAsync(out + s, o, 16 * m, hipMemcpyDeviceToHost, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
   }
+  return VIE_OK;
+}
+
+int vie_get_factor_stats(const vie_ctx *ctx, vie_factor_stats *out) {
+  if (!ctx || !out) return VIE_EINVAL;
+  if (!ctx->factored) return VIE_ESTATE;
+  *out = ctx->facstats;
   return VIE_OK;
 }
 

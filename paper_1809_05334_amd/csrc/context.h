@@ -115,6 +115,11 @@ struct vie_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_la = nullptr, ev_ts = nullptr;
   vie_fill_stats fstats{};
+  // timing of the factorisation's K = 128 trailing updates: one event pair per
+  // launch (pool grown on demand), pairs used by the last factorisation
+  std::vector<hipEvent_t> upd_ev;
+  int upd_n = 0;
+  vie_factor_stats facstats{};
   // the fill in progress (set by fill_prepare): one evaluation per unordered
   // far pair, the (face, tet) entries from the tet-face kernel, the
   // reversed-separation form, the table's LDS bytes, k0^2 / 9

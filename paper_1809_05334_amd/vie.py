@@ -52,6 +52,14 @@ class FillStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FactorStats(C.Structure):
+    _fields_ = [("t_factor_ms", C.c_double), ("t_update_ms", C.c_double), ("update_flops", C.c_double),
+                ("factor_flops", C.c_double), ("update_launches", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _LIB = None
 
 VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS, VIE_OPT_TRSV_COOP, VIE_OPT_LU_PIVOT = 1, 2, 3, 4, 5
@@ -96,6 +104,7 @@ _SIGS = {
     "vie_pgf_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "vie_residual_history": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
+    "vie_get_factor_stats": (C.c_int, [C.c_void_p, C.POINTER(FactorStats)]),
     "vie_bench_matvec": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
     "vie_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_set_option": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
@@ -324,6 +333,11 @@ class Solver:
     def fill_stats(self):
         st = FillStats()
         self._ck(self.lib.vie_get_fill_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def factor_stats(self):
+        st = FactorStats()
+        self._ck(self.lib.vie_get_factor_stats(self.h, C.byref(st)))
         return st.as_dict()
 
     def precond_apply(self, v):
