@@ -900,13 +900,15 @@ enum LuKernel { LU_PIVOT, LU_COL, LU_SWAP, LU_TRSM, LU_GEMM, LU_GEMM2, LU_TSEL, 
 // gcols - 1 of the trailing matrix, gcols <= 0 for all from gcol0.)
 template <typename BlocksOf>
 void lu_launch(bool f32, hipStream_t sm, LuKernel k, const std::vector<LuDom> &doms, int j, int k0, BlocksOf blocks_of,
-               int all_cols = 0, int gcol0 = 0, int gcols = 0) {
+               int all_cols = 0, int gcol0 = 0, int gcols = 0, int c_lo = 0, int c_hi = 0) {
   LuStep st{};
   st.j = j;
   st.k0 = k0;
   st.all_cols = all_cols;
   st.gcol0 = gcol0;
   st.gcols = gcols;
+  st.c_lo = c_lo;
+  st.c_hi = c_hi;
   int total = 0;
   auto flush = [&]() {
     if (st.ndom == 0) return;
@@ -1018,17 +1020,20 @@ int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
 // `stream`.
 //
 // Tournament pivoting (lu_pivot 0) takes the panels two at a time, so that
-// the bulk trailing update has K = 128 (k_lu_gemm2): at k0 the panel a
-// (columns k0 .. k0+63) is pivoted, swapped, and its L21 and U12 formed; its
-// update of panel b's columns (k0+64 .. k0+127) lets b be pivoted and
-// swapped; the rows of b then take a's update of the columns right of the
-// pair (a 64-row strip) before b's U12 is solved; finally every row and
-// column right of the pair takes both panels' update at once.  The next
-// pair's pivot search runs ahead: after the update of the first column tile
-// right of the pair, its tournament goes to the side stream while the
-// update of the remaining columns runs, and the next pair's row swaps wait
-// for it.  Column-by-column partial pivoting (lu_pivot 1) advances one
-// panel at a time with the K = 64 update.
+// the bulk trailing update has K = 128 (k_lu_gemm2).  A pair at k0 (panels
+// a = [k0, k0+64), b = [k0+64, k0+128)) is done in two phases:
+//   * panels: a's tournament, its row swaps on the pair's columns, L21 and
+//     the U12 rows of a over b's columns; a's update of b's columns; b's
+//     tournament, its swaps on the pair's columns, L21;
+//   * rest: both panels' swaps on every other column (a's, then b's), a's
+//     U12 right of the pair, a's update of b's rows right of the pair (a
+//     64-row strip), b's U12; then every row and column right of the pair
+//     takes both panels' update at once.
+// The panel phase of the next pair touches only the next pair's columns, so
+// it runs on the side stream while the bulk update of the current pair runs
+// (after that update's first 128 columns, the next pair's, are done); the
+// rest phase waits for it.  Column-by-column partial pivoting (lu_pivot 1)
+// advances one panel at a time with the K = 64 update.
 int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot, hipStream_t stream,
                   hipStream_t side, hipEvent_t ev_la, hipEvent_t ev_ts) {
   int maxn = 0;
@@ -1047,8 +1052,14 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
     const int nr = grows > 0 ? std::min(grows, nt) : nt;
     return rest > 0 && nc > 0 ? nr * nc : 0;
   };
-  auto swap_blocks = [&](int k0) {
-    return [&, k0](int d) { return doms[d].n > k0 ? (int)nblk(doms[d].n, 256) : 0; };
+  // row swaps of panel k0 on the columns that mode (k_lu_swap) selects
+  auto swap_blocks = [&](int k0, int mode, int c_lo, int c_hi) {
+    return [&, k0, mode, c_lo, c_hi](int d) {
+      const int n = doms[d].n;
+      if (n <= k0) return 0;
+      if (mode == 2) return (int)nblk(std::max(0, std::min(c_hi, n) - c_lo), 256);
+      return (int)nblk(n, 256);
+    };
   };
   auto tfin_blocks = [&](int k0) {
     return [&, k0](int d) {
@@ -1057,10 +1068,14 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
       return rest > 0 ? (int)nblk(rest, kColRows) : 1;
     };
   };
-  auto trsm_blocks = [&](int k0) {
-    return [&, k0](int d) {
-      const int rest = doms[d].n > k0 ? doms[d].n - k0 - jb_of(d, k0) : 0;
-      return rest > 0 ? (int)nblk(rest, kColRows) : 0;
+  // U12 of panel k0 on the columns [c_lo, c_hi) right of it (c_hi <= 0: all of them)
+  auto trsm_blocks = [&](int k0, int c_lo = 0, int c_hi = 0) {
+    return [&, k0, c_lo, c_hi](int d) {
+      const int n = doms[d].n;
+      if (n <= k0) return 0;
+      const int beg = c_hi > 0 ? std::max(c_lo, k0 + jb_of(d, k0)) : k0 + jb_of(d, k0);
+      const int end = c_hi > 0 ? std::min(c_hi, n) : n;
+      return end > beg ? (int)nblk(end - beg, kColRows) : 0;
     };
   };
   if (lu_pivot == 0) {
@@ -1089,31 +1104,42 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
       ++ctx->upd_n;
       return VIE_OK;
     };
-    tsel(0, stream);
-    for (int k0 = 0; k0 < maxn; k0 += 2 * kLuNB) {
-      const int kb = k0 + kLuNB, next = k0 + 2 * kLuNB;
-      if (k0 > 0) HIPCK(hipStreamWaitEvent(stream, ev_ts, 0));   // issued ahead on the side stream
-      // panel a: whole-row swaps, L21 = A21 U11^-1, U12 = L11^-1 A12 (every column right of a)
-      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0), 1);
-      lu_launch(f32, stream, LU_TFIN, doms, k0, k0, tfin_blocks(k0));
-      lu_launch(f32, stream, LU_TRSM, doms, k0, k0, trsm_blocks(k0));
+    constexpr int kBig = 1 << 30;
+    auto panels = [&](int k0, hipStream_t sm) {
+      const int kb = k0 + kLuNB, pe = k0 + 2 * kLuNB;
+      tsel(k0, sm);
+      lu_launch(f32, sm, LU_SWAP, doms, k0, k0, swap_blocks(k0, 2, k0, pe), 2, 0, 0, k0, pe);
+      lu_launch(f32, sm, LU_TFIN, doms, k0, k0, tfin_blocks(k0));
       if (kb < maxn) {
-        // panel b's columns take a's update; b is pivoted, swapped and its L21 formed
-        lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
-        tsel(kb, stream);
-        lu_launch(f32, stream, LU_SWAP, doms, kb, kb, swap_blocks(kb), 1);
-        lu_launch(f32, stream, LU_TFIN, doms, kb, kb, tfin_blocks(kb));
-        // b's rows take a's update right of the pair, then b's U12
-        lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0, 1); }, 0, 1, 0);
-        lu_launch(f32, stream, LU_TRSM, doms, kb, kb, trsm_blocks(kb));
+        lu_launch(f32, sm, LU_TRSM, doms, k0, k0, trsm_blocks(k0, kb, pe), 0, 0, 0, kb, pe);
+        lu_launch(f32, sm, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 1); }, 0, 0, 1);
+        tsel(kb, sm);
+        lu_launch(f32, sm, LU_SWAP, doms, kb, kb, swap_blocks(kb, 2, k0, pe), 2, 0, 0, k0, pe);
+        lu_launch(f32, sm, LU_TFIN, doms, kb, kb, tfin_blocks(kb));
       }
+    };
+    auto rest = [&](int k0) {
+      const int kb = k0 + kLuNB, pe = k0 + 2 * kLuNB;
+      lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0, 3, k0, pe), 3, 0, 0, k0, pe);
+      if (kb < maxn) lu_launch(f32, stream, LU_SWAP, doms, kb, kb, swap_blocks(kb, 3, k0, pe), 3, 0, 0, k0, pe);
+      lu_launch(f32, stream, LU_TRSM, doms, k0, k0, trsm_blocks(k0, pe, kBig), 0, 0, 0, pe, kBig);
+      if (kb < maxn) {
+        lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 1, 0, 1); }, 0, 1, 0);
+        lu_launch(f32, stream, LU_TRSM, doms, kb, kb, trsm_blocks(kb, pe, kBig), 0, 0, 0, pe, kBig);
+      }
+    };
+    panels(0, stream);
+    for (int k0 = 0; k0 < maxn; k0 += 2 * kLuNB) {
+      const int next = k0 + 2 * kLuNB;
+      if (k0 > 0) HIPCK(hipStreamWaitEvent(stream, ev_ts, 0));   // this pair's panels, factored on the side stream
+      rest(k0);
       if (next < maxn) {
-        if (int rc = timed_gemm2(k0, 0, 1)) return rc;
+        if (int rc = timed_gemm2(k0, 0, 2 * kLuNB / tn)) return rc;   // the next pair's columns first
         HIPCK(hipEventRecord(ev_la, stream));
         HIPCK(hipStreamWaitEvent(side, ev_la, 0));
-        tsel(next, side);
+        panels(next, side);
         HIPCK(hipEventRecord(ev_ts, side));
-        if (int rc = timed_gemm2(k0, 1, 0)) return rc;
+        if (int rc = timed_gemm2(k0, 2 * kLuNB / tn, 0)) return rc;
       }
       LAUNCHCK();
     }
@@ -1126,7 +1152,7 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
         const int n = doms[d].n;
         return (n > k0 && j < k0 + jb_of(d, k0) && n - j - 1 > 0) ? (int)nblk(n - j - 1, kColRows) : 0;
       });
-    lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0));
+    lu_launch(f32, stream, LU_SWAP, doms, k0, k0, swap_blocks(k0, 0, 0, 0));
     lu_launch(f32, stream, LU_TRSM, doms, k0, k0, trsm_blocks(k0));
     lu_launch(f32, stream, LU_GEMM, doms, k0, k0, [&](int d) { return gemm_blocks(d, k0, 0, 0); });
     LAUNCHCK();

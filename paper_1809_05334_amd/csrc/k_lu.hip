@@ -209,15 +209,22 @@ __device__ __forceinline__ void lu_col_body(const LuStep &st) {
   if (tid == 0) __hip_atomic_store(D.counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Apply the panel's row swaps to the columns outside the panel (to every
-// column with st.all_cols, after tournament pivoting).
+// Apply the panel's row swaps to a set of columns (st.all_cols): those
+// outside the panel (column pivoting), all of them (tournament pivoting), only
+// [c_lo, c_hi) (mode 2: the blocks start at c_lo), or all but [c_lo, c_hi)
+// (mode 3).  A pair's swaps can so be applied to its own panels first and to
+// the other columns later, in the same order.
 template <typename C>
 __device__ __forceinline__ void lu_swap_body(const LuStep &st) {
   const LuDom &D = st.d[lu_domain(st)];
   C *A = (C *)D.A;
   const int k0 = st.k0, n = D.n, jb = min(kLuNB, n - k0);
-  const int c = (blockIdx.x - D.first_block) * 256 + threadIdx.x;
-  if (c >= n || (!st.all_cols && c >= k0 && c < k0 + jb)) return;
+  const int m = st.all_cols;
+  const int c = (m == 2 ? st.c_lo : 0) + (blockIdx.x - D.first_block) * 256 + threadIdx.x;
+  if (c >= n) return;
+  if (m == 0 && c >= k0 && c < k0 + jb) return;
+  if (m == 2 && c >= st.c_hi) return;
+  if (m == 3 && c >= st.c_lo && c < st.c_hi) return;
   for (int j = k0; j < k0 + jb; ++j) {
     const int p = D.ipiv[j];
     if (p != j) {
@@ -228,9 +235,10 @@ __device__ __forceinline__ void lu_swap_body(const LuStep &st) {
   }
 }
 
-// U12 = L11^{-1} A12 (L11 unit lower, jb <= 64), kColRows columns per
-// thread block: L11 staged in LDS, kColT lanes per column (lane t owns the
-// rows i = t (mod kColT) of its column), the dot products of the forward
+// U12 = L11^{-1} A12 (L11 unit lower, jb <= 64) for the columns right of the
+// panel (or those of them in [c_lo, c_hi)), kColRows columns per thread
+// block: L11 staged in LDS, kColT lanes per column (lane t owns the rows
+// i = t (mod kColT) of its column), the dot products of the forward
 // substitution split over the lanes and combined by shuffles.
 template <typename C>
 __device__ __forceinline__ void lu_trsm_body(const LuStep &st) {
@@ -247,8 +255,9 @@ __device__ __forceinline__ void lu_trsm_body(const LuStep &st) {
   __syncthreads();
   constexpr int kPer = kLuNB / kColT;
   const int t = tid % kColT;
-  const int c = k0 + jb + (blockIdx.x - D.first_block) * kColRows + tid / kColT;
-  const bool ok = c < n;
+  const int cbeg = st.c_hi > 0 ? max(st.c_lo, k0 + jb) : k0 + jb, cend = st.c_hi > 0 ? min(st.c_hi, n) : n;
+  const int c = cbeg + (blockIdx.x - D.first_block) * kColRows + tid / kColT;
+  const bool ok = c < cend;
   C x[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u)

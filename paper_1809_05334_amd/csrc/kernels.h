@@ -153,8 +153,9 @@ struct LuDom {
 struct LuStep {
   LuDom d[kLuMaxDom];
   int ndom, j, k0;    // current column and panel start
-  int all_cols;       // k_lu_swap: swap inside the panel columns too
+  int all_cols;       // k_lu_swap columns: 0 all but the panel's, 1 all, 2 only [c_lo, c_hi), 3 all but [c_lo, c_hi)
   int gcol0, gcols;   // k_lu_gemm: column tiles gcol0 .. gcol0 + gcols - 1 of A22 (gcols <= 0: to the end)
+  int c_lo, c_hi;     // k_lu_swap column range (modes 2, 3); k_lu_trsm: columns [c_lo, c_hi) if c_hi > 0
 };
 #define VIE_DECL_LU(T)                       \
   __global__ void k_lu_pivot_##T(LuStep st); \
