@@ -688,14 +688,14 @@ int fill_upload(vie_ctx *ctx) {
   // evaluated once and also yields the swapped pair's block, gathered in Zt:
   // at normal incidence (kt = 0) the lattice sum is even in the separation;
   // at oblique incidence g_p at the reversed separations follows from the same
-  // evaluation plus the propagating orders' term (rev).  At kt = 0 each far
-  // (tet, half-SWG face) pair likewise yields the (face, tet) entry.  Zt is
-  // added transposed after the face kernels.
+  // evaluation plus the propagating orders' term (rev).  Each far (tet,
+  // half-SWG face) pair likewise yields the (face, tet) entry, by the same
+  // two forms.  Zt is added transposed after the face kernels.
   const bool kt0 = kx == 0.0 && ky == 0.0;
   // (the oblique form keeps 32 KB per block of the swapped moments in LDS
   // beside the table; a table too large for both runs the plain fill)
   ctx->fill_sym = L.Zt.bytes > 0 && (kt0 || ctx->fill_lds + kFarRevLds <= 65536);
-  ctx->fill_sym_face = ctx->fill_sym && kt0;
+  ctx->fill_sym_face = ctx->fill_sym;
   ctx->fill_rev = kt0 ? 0 : 1;
   ctx->last_sym = ctx->fill_sym;
   if (ctx->fill_sym)
@@ -772,9 +772,13 @@ int fill_kernels(vie_ctx *ctx) {
     // (one lane each, so no wave mixes the two kinds)
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
-      hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg,
-                         t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, alpha, sigma, gsrc, kappa, zo, zt,
-                         sym_face ? 1 : 0);
+      if (sym_face && rev)
+        hipLaunchKernelGGL(k_tet_face_rev, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
+                           qr, tg, t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, alpha, sigma, gsrc, kappa, zo, zt);
+      else
+        hipLaunchKernelGGL(k_tet_face, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl, qr,
+                           tg, t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, alpha, sigma, gsrc, kappa, zo, zt,
+                           sym_face ? 1 : 0);
       const int np = ctx->tf_off[ct + 1] - ctx->tf_off[ct];
       if (np)
         hipLaunchKernelGGL(k_tet_face_near, dim3(nblk(np, 256)), dim3(256), lds, ctx->stream, pk_, pkl, qr, tg, t2f,
@@ -785,7 +789,7 @@ int fill_kernels(vie_ctx *ctx) {
     if (ctx->nhalf) {
       for (int cs = 0; cs < C; ++cs) {
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-        if (!sym_face)   // (at kt = 0 with the staging the far pairs came from k_tet_face)
+        if (!sym_face)   // (with the staging the far pairs came from k_tet_face)
           hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
                              qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
                              gsrc, kappa, zo);

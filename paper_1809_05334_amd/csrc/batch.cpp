@@ -327,7 +327,7 @@ int vie_batch_fill(vie_batch *b, const double *lambda_nm, const double *theta, c
       const auto c = P(x);
       const int nT = x->color_off[ct + 1] - x->color_off[ct];
       TetFaceSeg s{c.pk, c.pkl, c.qr, c.tg, c.t2f, c.colors + x->color_off[ct], nT, c.fg, x->nface, c.alpha,
-                   c.sigma, c.gsrc, c.kappa, c.zo, c.zt, x->fill_sym_face ? 1 : 0, 0, 0};
+                   c.sigma, c.gsrc, c.kappa, c.zo, c.zt, x->fill_sym_face ? (x->fill_rev ? 2 : 1) : 0, 0, 0};
       tf.add(s, (int)nblk(x->nface, 64), (int)nblk(nT, 4), x->fill_lds);
       const int np = x->tf_off[ct + 1] - x->tf_off[ct];
       if (np) {

@@ -619,6 +619,39 @@ __device__ dz pair_face_face(const double *__restrict__ P, const QuadRules *__re
   return acc;
 }
 
+// Far rule of pair_tet_face with both separations from one lattice-sum
+// evaluation: m0 = II g_p(r - r') (test tet, source face) and m0r the same
+// with r - r' reversed (test face, source tet), by the reversed-separation
+// form of pgf_eval_w (oblique incidence, non-touching pairs).
+__device__ void pair_tet_face_far_rev(const double *__restrict__ P, const QuadRules *__restrict__ qr,
+                                      const TetGeom &gt, const FaceGeom &f, dz &m0, dz &m0r) {
+  double fp[3][3], tp[4][3];
+  for (int j = 0; j < 3; ++j)
+    for (int d = 0; d < 3; ++d) fp[j][d] = qr->tri3[j][0] * f.v[0][d] + qr->tri3[j][1] * f.v[1][d] + qr->tri3[j][2] * f.v[2][d];
+  for (int i = 0; i < 4; ++i)
+    for (int d = 0; d < 3; ++d) {
+      double s = 0;
+      for (int k = 0; k < 4; ++k) s = fma(qr->tet4[i][k], gt.v[k][d], s);
+      tp[i][d] = s;
+    }
+  dz acc = mk(0, 0), accr = mk(0, 0);
+#pragma unroll 1
+  for (int j = 0; j < 3; ++j) {
+    double sep[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sep[i][d] = tp[i][d] - fp[j][d];
+    dz g[4], gr[4];
+    pgf_eval_w<false, 4, true>(P, sep, 0, g, gr);
+    acc = acc + ((g[0] + g[1]) + (g[2] + g[3]));
+    accr = accr + ((gr[0] + gr[1]) + (gr[2] + gr[3]));
+  }
+  const double w = 0.25 * gt.vol * (f.area / 3.0);
+  m0 = w * acc;
+  m0r = w * accr;
+}
+
 // test tet (colour class list) x surface-charge face: Z[m_k(T), n_F] -= alpha_Tk sigma_F M0.
 // Far pairs only: the touching ones come from the host list (k_tet_face_near).
 __device__ __forceinline__ void tet_face_pair(const double *__restrict__ P, const QuadRules *__restrict__ qr,
@@ -631,14 +664,17 @@ __device__ __forceinline__ void tet_face_pair(const double *__restrict__ P, cons
   for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, mask != 0);
 }
 
-// At normal incidence the lattice sum is even in the separation, and the far
-// rules of the two face kernels take the same 4 x 3 point pairs with the same
-// weights, so the (tet T, face F) value M0 is also that of (F as a half-SWG
-// test face, T as source).  With swap set, each far pair with a half-SWG face
-// writes that entry too, Z[m_F, n_l(T)] -= gsrc_Tl kappa_T M0, at the
-// transposed position of outT (rows of T's unknowns, columns of faces: the
-// same conflict-free pattern as the tet-face entries); the staging copy is
-// added transposed after the fill's other kernels.
+// The far rules of the two face kernels take the same 4 x 3 point pairs with
+// the same weights, so the (tet T, face F) evaluation also gives the value
+// M0' of (F as a half-SWG test face, T as source): at normal incidence
+// (swap 1) the lattice sum is even and M0' = M0; at oblique incidence
+// (swap 2) M0' comes from the reversed-separation form of the same lattice
+// sum.  With swap set, each far pair with a half-SWG face writes that entry
+// too, Z[m_F, n_l(T)] -= gsrc_Tl kappa_T M0', at the transposed position of
+// outT (rows of T's unknowns, columns of faces: the same conflict-free
+// pattern as the tet-face entries); the staging copy is added transposed
+// after the fill's other kernels.
+template <bool REV_ONLY = false>
 __device__ __forceinline__ void k_tet_face_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                   const TetGeom *__restrict__ tg, const TetFace *__restrict__ t2f,
                                                   const int32_t *__restrict__ test_list, int ntest,
@@ -658,11 +694,17 @@ __device__ __forceinline__ void k_tet_face_body(const double *__restrict__ pack,
   const FaceGeom f = fg[fi];
   if (touch_mask(gt.canon, gt.off, 4, f.canon, f.off, 3)) return;
   int mask;
-  const dz m0 = pair_tet_face(s_tab, qr, gt, f, mask);
+  dz m0, m0r;
+  if (REV_ONLY || swap == 2) {
+    pair_tet_face_far_rev(s_tab, qr, gt, f, m0, m0r);
+  } else {
+    m0 = pair_tet_face(s_tab, qr, gt, f, mask);
+    m0r = m0;
+  }
   const dz sm = sigma[fi] * m0;
   for (int k = 0; k < 4; ++k) zput(out, t2f[4 * T + k].unknown, f.unknown, mk(0, 0) - alpha[4 * T + k] * sm, false);
   if (swap && f.half) {
-    const dz km = m0 * kappa[T];
+    const dz km = m0r * kappa[T];
     for (int l = 0; l < 4; ++l) zput(outT, t2f[4 * T + l].unknown, f.unknown, mk(0, 0) - gsrc[4 * T + l] * km, false);
   }
 }
@@ -674,7 +716,22 @@ __global__ __launch_bounds__(256, 2) void k_tet_face(const double *__restrict__ 
                                                   const dz *__restrict__ alpha, const dz *__restrict__ sigma,
                                                   const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
                                                   ZOut out, ZOut outT, int swap) {
-  k_tet_face_body(pack, packlen, qr, tg, t2f, test_list, ntest, fg, nface, alpha, sigma, gsrc, kappa, out, outT, swap, blockIdx.x, blockIdx.y);
+  k_tet_face_body<false>(pack, packlen, qr, tg, t2f, test_list, ntest, fg, nface, alpha, sigma, gsrc, kappa, out, outT,
+                         swap == 2 ? 0 : swap, blockIdx.x, blockIdx.y);
+}
+// oblique incidence with the staging copy: the (face, tet) entries from the
+// reversed separation (swap 2); a kernel of its own, whose registers the
+// two-separation form does not take from k_tet_face
+__global__ __launch_bounds__(256, 2) void k_tet_face_rev(const double *__restrict__ pack, int packlen,
+                                                      const QuadRules *__restrict__ qr, const TetGeom *__restrict__ tg,
+                                                      const TetFace *__restrict__ t2f,
+                                                      const int32_t *__restrict__ test_list, int ntest,
+                                                      const FaceGeom *__restrict__ fg, int nface,
+                                                      const dz *__restrict__ alpha, const dz *__restrict__ sigma,
+                                                      const dz *__restrict__ gsrc, const dz *__restrict__ kappa,
+                                                      ZOut out, ZOut outT) {
+  k_tet_face_body<true>(pack, packlen, qr, tg, t2f, test_list, ntest, fg, nface, alpha, sigma, gsrc, kappa, out, outT, 2,
+                        blockIdx.x, blockIdx.y);
 }
 
 // touching (test tet, surface-charge face) pairs of one test colour, one lane each

@@ -96,6 +96,9 @@ __global__ void k_tt_near(const double *pack, int packlen, const QuadRules *qr, 
 __global__ void k_tet_face(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg, const TetFace *t2f,
                            const int32_t *test_list, int ntest, const FaceGeom *fg, int nface, const dz *alpha,
                            const dz *sigma, const dz *gsrc, const dz *kappa, ZOut out, ZOut outT, int swap);
+__global__ void k_tet_face_rev(const double *pack, int packlen, const QuadRules *qr, const TetGeom *tg,
+                               const TetFace *t2f, const int32_t *test_list, int ntest, const FaceGeom *fg, int nface,
+                               const dz *alpha, const dz *sigma, const dz *gsrc, const dz *kappa, ZOut out, ZOut outT);
 __global__ void k_face_tet(const double *pack, int packlen, const QuadRules *qr, const FaceGeom *fg, const int32_t *half_list,
                            int nhalf, const TetGeom *tg, const TetFace *t2f, const int32_t *src_list, int nsrc,
                            const dz *gsrc, const dz *kappa, ZOut out);
