@@ -124,10 +124,16 @@ def test_tournament_and_partial_pivoting_agree(vie, prec):
     assert s.get_option(vie.VIE_OPT_LU_PIVOT) == 0
     s.factor()
     z_t = s.precond_apply(v)
+    # the timed K = 128 updates: their algorithmic work is 8 rows cols 128 per panel pair
+    st = s.factor_stats()
+    exp = sum(8.0 * (N - k0 - 128) ** 2 * 128 for k0 in range(0, N, 128) if N - k0 - 128 > 0)
+    assert st["update_flops"] == exp and abs(st["factor_flops"] - 8.0 / 3.0 * N ** 3) < 1e-6 * N ** 3
+    assert 0 < st["t_update_ms"] < st["t_factor_ms"] and st["update_launches"] == 2 * (len(range(0, N, 128)) - 1)
     s.set_option(vie.VIE_OPT_LU_PIVOT, 1)
     assert s.get_option(vie.VIE_OPT_LU_PIVOT) == 1
     s.factor()
     z_p = s.precond_apply(v)
+    assert s.factor_stats()["update_flops"] == 0 and s.factor_stats()["update_launches"] == 0
     with pytest.raises(vie.VieError):
         s.set_option(vie.VIE_OPT_LU_PIVOT, 2)
     A = read_block(s, 0, N)
