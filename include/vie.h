@@ -166,7 +166,8 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta_rad, double phi_rad, c
 /* LU factorisation P A_dd = L U of every diagonal block A_dd (Sec. 2.3,
  * Eq. 6), with tournament pivoting per 64-column panel by default or partial
  * pivoting column by column (VIE_OPT_LU_PIVOT).  VIE_ESINGULAR on a zero
- * pivot. */
+ * pivot; VIE_EINVAL if a domain has more than 131,072 unknowns (the bound
+ * of the triangular solves' row sums). */
 int vie_precond_factor(vie_ctx *ctx);
 
 /* Right-preconditioned restarted GMRES(restart) on Z M^-1 y = b, x = M^-1 y,
@@ -269,7 +270,7 @@ enum {
                              * may run up to this many steps past convergence (unused).  Needs a
                              * non-null stream: vie_solve returns VIE_EINVAL on the null stream */
   VIE_OPT_MATVEC_ROWS = 2,  /* matvec rows per wave: 2, 4 (default) or 8 */
-  VIE_OPT_TRSV_ROWS = 3,    /* triangular-solve update rows per wave: 4 (default) or 8 */
+  VIE_OPT_TRSV_CHUNK = 3,   /* triangular-solve columns per update work item: 1024 or 2048 (default) */
   VIE_OPT_TRSV_COOP = 4,    /* 1: each preconditioner apply runs its triangular-solve steps in one
                              * cooperative launch with grid barriers between steps (not inside
                              * captured graphs); 0 (default): one
@@ -302,8 +303,9 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value);
 
 typedef struct {
   double matvec_ms[6];   /* per product, rows per wave 2, 4, 8: one vector, then two */
-  double apply_ms[4];    /* per preconditioner apply, rows per wave 4 and 8: one vector, then two */
-  int matvec_rows, trsv_rows;   /* the picks, now set on the context */
+  double apply_ms[4];    /* per preconditioner apply, work items of 1024 and 2048 columns: one
+                          * vector, then two */
+  int matvec_rows, trsv_chunk;   /* the picks, now set on the context */
 } vie_tuning;
 
 /* Autotuner: time each matvec and triangular-solve variant on this context's

@@ -127,6 +127,14 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
   put(L.tpart, 16 * 4 * (size_t)kTrsvPart * std::max(1, t.ndom));   // two buffers of two right-hand sides per domain
+  // chunk sums: per domain two buffers (steps alternate) of two vectors, kTrsvNB rows each
+  L.boff.resize(t.ndom);
+  int64_t bel = 0;
+  for (int d = 0; d < t.ndom; ++d) {
+    L.boff[d] = bel;
+    bel += 4 * (int64_t)kTrsvNB * trsv_bsum_stride(t.dend[d] - t.dstart[d]);
+  }
+  put(L.tbsum, 16 * (size_t)std::max<int64_t>(1, bel));
   {
     int maxnbk = 1;
     for (int d = 0; d < t.ndom; ++d) maxnbk = std::max<int>(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
@@ -977,8 +985,12 @@ namespace vie {
 // precision) into the factor storage; records ev0.
 int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
   if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
-  HIPCK(hipSetDevice(ctx->device));
   const MeshTopology &t = ctx->topo;
+  for (int d = 0; d < t.ndom; ++d)
+    if (t.dend[d] - t.dstart[d] > (int64_t)kTrsvChunksMax * kTrsvSumCols)
+      return fail(ctx, VIE_EINVAL, "domain %d has %lld unknowns; the block preconditioner takes at most %d", d,
+                  (long long)(t.dend[d] - t.dstart[d]), kTrsvChunksMax * kTrsvSumCols);
+  HIPCK(hipSetDevice(ctx->device));
   const Layout &L = ctx->L;
   const ZOut zo = zout(ctx);
   const bool f32 = fp32_factors(ctx);
@@ -1264,16 +1276,26 @@ namespace vie {
 // The step list of the blocked triangular solves (L sweep, then U sweep) for
 // nv (1 or 2) right-hand sides; step k advances every domain (kTrsvMaxDom per
 // entry) by one diagonal block, so the step count follows the largest domain.
+// Step k of a domain with nbk blocks (numbered in the sweep's order) solves
+// block k and forms the chunk sums of block k + 1 over the blocks <= k - 2,
+// in work items of ctx->trsv_kc columns.
 std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const *s1, dz *const *s2) {
   const MeshTopology &t = ctx->topo;
   const Layout &L = ctx->L;
+  const int kc = ctx->trsv_kc;
   int maxnbk = 0;
   for (int d = 0; d < t.ndom; ++d) maxnbk = std::max(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
   // partial products: per domain two buffers (steps alternate) of two vectors
   dz *part = ctx->ptr<dz>(L.tpart);
   auto buf = [&](int d, int k) { return part + ((int64_t)d * 4 + 2 * (k & 1)) * kTrsvPart; };
+  // chunk sums: the same alternation, in the domain's region of L.tbsum
+  dz *bsum = ctx->ptr<dz>(L.tbsum);
+  auto bbuf = [&](int d, int k) {
+    const int64_t n = t.dend[d] - t.dstart[d];
+    return bsum + L.boff[d] + (int64_t)(k & 1) * 2 * kTrsvNB * trsv_bsum_stride(n);
+  };
   std::vector<TrsvStep> plan;
-  // L sweep: rhs s1 (updated in place), solution s2; U sweep: rhs s2, solution out.
+  // L sweep: rhs s1, solution s2; U sweep: rhs s2, solution out.
   for (int lower = 1; lower >= 0; --lower) {
     // steps 0 .. maxnbk-1 advance the solves; step maxnbk stores each
     // domain's last diagonal block
@@ -1282,6 +1304,7 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
       st.lower = lower;
       auto push = [&]() {
         if (st.ndom == 0) return;
+        st.chain_blocks = trsv_number_items(st.d, st.ndom, &st.total_blocks);
         plan.push_back(st);
         st = TrsvStep{};
         st.lower = lower;
@@ -1296,11 +1319,11 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
         D.F = factor_ptr(ctx, L.F, L.foff[d]);
         D.ld = L.fld[d];
         D.n = n;
-        D.first_block = st.total_blocks;
         for (int q = 0; q < nv; ++q) {
           D.rhs[q] = (lower ? s1[q] : s2[q]) + off;
           D.sol[q] = (lower ? s2[q] : out[q]) + off;
         }
+        D.bst = trsv_bsum_stride(n);
         if (k == maxnbk) {
           // the partials of the domain's last step: one thread block stores them
           const int bk = lower ? nbk - 1 : 0;
@@ -1310,7 +1333,7 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
           D.part_in = buf(d, nbk - 1);
           D.part_out = nullptr;
           D.DT = nullptr;
-          st.total_blocks += 1;
+          D.bsum_in = D.bsum_out = bbuf(d, 0);
           if (++st.ndom == kTrsvMaxDom) push();
           continue;
         }
@@ -1326,9 +1349,21 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
         D.cb0 = k >= 2 ? (bk + 2 * dir) * kTrsvNB : 0;
         D.cm = k >= 2 ? std::min(kTrsvNB, n - D.cb0) : 0;
         D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(lower ? bk : nbk + bk) * kTrsvNB * kTrsvNB);
-        // rows past block bk take the update of block bk -+ 2
-        const int rest = D.cm > 0 ? (lower ? n - D.nb0 - D.nm : D.nb0) : 0;
-        st.total_blocks += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * ctx->trsv_rw) : 0);
+        // block k's chunk sums over the blocks <= k - 3, from step k - 1
+        D.bsum_in = bbuf(d, k - 1);
+        const int kin = k >= 3 ? (lower ? (k - 2) * kTrsvNB : n - (nbk + 2 - k) * kTrsvNB) : 0;
+        D.nci = (kin + kTrsvSumCols - 1) / kTrsvSumCols;
+        // block k + 1's chunk sums over the blocks <= k - 2 (columns [bc0, bc0 + bk))
+        D.bsum_out = bbuf(d, k);
+        if (k >= 2 && k + 1 < nbk) {
+          const int tb = lower ? k + 1 : nbk - 2 - k;
+          D.br0 = tb * kTrsvNB;
+          D.brm = std::min(kTrsvNB, n - D.br0);
+          D.bc0 = lower ? 0 : (nbk + 1 - k) * kTrsvNB;
+          D.bk = lower ? (k - 1) * kTrsvNB : n - D.bc0;
+          D.nrg = (D.brm + 15) / 16;
+          D.nco = (D.bk + kc - 1) / kc;
+        }
         if (++st.ndom == kTrsvMaxDom) push();
       }
       push();
@@ -1339,30 +1374,30 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
 
 void launch_trsv_step(vie_ctx *ctx, const TrsvStep &st, int nv) {
   const dim3 g(st.total_blocks), b(1024);
-  const bool r8 = ctx->trsv_rw == 8;
+  const bool w = ctx->trsv_kc == 2048;
   if (nv == 2) {
     if (fp32_factors(ctx)) {
-      if (r8) hipLaunchKernelGGL(k_trsv_step2_c_r8, g, b, 0, ctx->stream, st);
-      else hipLaunchKernelGGL(k_trsv_step2_c_r4, g, b, 0, ctx->stream, st);
+      if (w) hipLaunchKernelGGL(k_trsv_step2_c_k2048, g, b, 0, ctx->stream, st);
+      else hipLaunchKernelGGL(k_trsv_step2_c_k1024, g, b, 0, ctx->stream, st);
     } else {
-      if (r8) hipLaunchKernelGGL(k_trsv_step2_z_r8, g, b, 0, ctx->stream, st);
-      else hipLaunchKernelGGL(k_trsv_step2_z_r4, g, b, 0, ctx->stream, st);
+      if (w) hipLaunchKernelGGL(k_trsv_step2_z_k2048, g, b, 0, ctx->stream, st);
+      else hipLaunchKernelGGL(k_trsv_step2_z_k1024, g, b, 0, ctx->stream, st);
     }
     return;
   }
   if (fp32_factors(ctx)) {
-    if (r8) hipLaunchKernelGGL(k_trsv_step_c_r8, g, b, 0, ctx->stream, st);
-    else hipLaunchKernelGGL(k_trsv_step_c_r4, g, b, 0, ctx->stream, st);
+    if (w) hipLaunchKernelGGL(k_trsv_step_c_k2048, g, b, 0, ctx->stream, st);
+    else hipLaunchKernelGGL(k_trsv_step_c_k1024, g, b, 0, ctx->stream, st);
   } else {
-    if (r8) hipLaunchKernelGGL(k_trsv_step_z_r8, g, b, 0, ctx->stream, st);
-    else hipLaunchKernelGGL(k_trsv_step_z_r4, g, b, 0, ctx->stream, st);
+    if (w) hipLaunchKernelGGL(k_trsv_step_z_k2048, g, b, 0, ctx->stream, st);
+    else hipLaunchKernelGGL(k_trsv_step_z_k1024, g, b, 0, ctx->stream, st);
   }
 }
 
 const void *coop_kernel(const vie_ctx *ctx) {
-  const bool r8 = ctx->trsv_rw == 8;
-  if (fp32_factors(ctx)) return r8 ? (const void *)k_trsv_coop_c_r8 : (const void *)k_trsv_coop_c_r4;
-  return r8 ? (const void *)k_trsv_coop_z_r8 : (const void *)k_trsv_coop_z_r4;
+  const bool w = ctx->trsv_kc == 2048;
+  if (fp32_factors(ctx)) return w ? (const void *)k_trsv_coop_c_k2048 : (const void *)k_trsv_coop_c_k1024;
+  return w ? (const void *)k_trsv_coop_z_k2048 : (const void *)k_trsv_coop_z_k1024;
 }
 
 // Run the plan as one cooperative launch: the plan is uploaded once per
@@ -1382,10 +1417,10 @@ int launch_trsv_coop(vie_ctx *ctx, const std::vector<TrsvStep> &plan, const dz *
   if ((int)plan.size() > L.plan_steps) return fail(ctx, VIE_EINVAL, "triangular-solve plan too long");
   const vie_ctx::CoopPlan *cp = nullptr;
   for (const auto &p : ctx->plans)
-    if (p.v == v && p.out == out && p.s1 == s1 && p.s2 == s2 && p.rw == ctx->trsv_rw) cp = &p;
+    if (p.v == v && p.out == out && p.s1 == s1 && p.s2 == s2 && p.kc == ctx->trsv_kc) cp = &p;
   if (!cp) {
     if ((int)ctx->plans.size() == kMaxPlans) ctx->plans.clear();
-    vie_ctx::CoopPlan p{v, out, s1, s2, ctx->trsv_rw, (int)plan.size(),
+    vie_ctx::CoopPlan p{v, out, s1, s2, ctx->trsv_kc, (int)plan.size(),
                         L.plans.off + ctx->plans.size() * sizeof(TrsvStep) * (size_t)L.plan_steps};
     HIPCK(hipMemcpyAsync(ctx->ws + p.off, plan.data(), sizeof(TrsvStep) * plan.size(), hipMemcpyHostToDevice,
                          ctx->stream));
@@ -2133,10 +2168,10 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       if (value != ctx->precond) drop_graphs(ctx);
       ctx->precond = value;
       return VIE_OK;
-    case VIE_OPT_TRSV_ROWS:
-      if (value != 4 && value != 8) return fail(ctx, VIE_EINVAL, "trsv rows per wave: 4 or 8");
-      if (value != ctx->trsv_rw) drop_graphs(ctx);
-      ctx->trsv_rw = value;
+    case VIE_OPT_TRSV_CHUNK:
+      if (value != 1024 && value != 2048) return fail(ctx, VIE_EINVAL, "trsv chunk width: 1024 or 2048 columns");
+      if (value != ctx->trsv_kc) drop_graphs(ctx);
+      ctx->trsv_kc = value;
       return VIE_OK;
   }
   return fail(ctx, VIE_EINVAL, "unknown option %d", option);
@@ -2147,7 +2182,7 @@ int vie_get_option(const vie_ctx *ctx, int option, int *value) {
   switch (option) {
     case VIE_OPT_GRAPH_STEPS: *value = ctx->graph_steps; return VIE_OK;
     case VIE_OPT_MATVEC_ROWS: *value = ctx->mv_rpw; return VIE_OK;
-    case VIE_OPT_TRSV_ROWS: *value = ctx->trsv_rw; return VIE_OK;
+    case VIE_OPT_TRSV_CHUNK: *value = ctx->trsv_kc; return VIE_OK;
     case VIE_OPT_TRSV_COOP: *value = ctx->trsv_coop; return VIE_OK;
     case VIE_OPT_LU_PIVOT: *value = ctx->lu_pivot; return VIE_OK;
     case VIE_OPT_SYM_FILL: *value = ctx->sym_fill; return VIE_OK;
@@ -2181,7 +2216,7 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   };
   // products for one vector and for two (paired solves): the pick
   // minimises the sum of the two
-  const int mv_opts[3] = {2, 4, 8}, tr_opts[2] = {4, 8};
+  const int mv_opts[3] = {2, 4, 8}, tr_opts[2] = {1024, 2048};
   double best = 1e300;
   int pick = ctx->mv_rpw;
   MvVecs v2{};
@@ -2201,9 +2236,9 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
   // triangular solves for one vector and for two (paired solves): the pick
   // minimises the sum of the two
   best = 1e300;
-  pick = ctx->trsv_rw;
+  pick = ctx->trsv_kc;
   for (int i = 0; i < 2; ++i) {
-    ctx->trsv_rw = tr_opts[i];
+    ctx->trsv_kc = tr_opts[i];
     const Layout::Kry &A = L.K[0], &B = L.K[1];
     const dz *v2[2] = {x, x};
     dz *o2[2] = {ctx->ptr<dz>(A.vu), ctx->ptr<dz>(B.vu)}, *t2[2] = {ctx->ptr<dz>(A.vt), ctx->ptr<dz>(B.vt)},
@@ -2215,10 +2250,10 @@ int vie_autotune(vie_ctx *ctx, int reps, vie_tuning *out) {
       pick = tr_opts[i];
     }
   }
-  ctx->trsv_rw = pick;
+  ctx->trsv_kc = pick;
   drop_graphs(ctx);
   t.matvec_rows = ctx->mv_rpw;
-  t.trsv_rows = ctx->trsv_rw;
+  t.trsv_chunk = ctx->trsv_kc;
   if (out) *out = t;
   return VIE_OK;
 }

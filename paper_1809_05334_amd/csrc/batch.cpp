@@ -455,7 +455,7 @@ struct StepPlan {
   int tot_elem, tot_mv, tot_dots, tot_red, tot_norm;
   struct TStep {
     size_t off;
-    int ndom, lower, blocks;
+    int ndom, lower, blocks, chain;   // chain: the step's chain items, numbered first
   };
   std::vector<TStep> tsteps;
   bool precond = true;
@@ -539,10 +539,10 @@ int build_step_plan(vie_batch *b, StepPlan &sp) {
       if (x->precond) continue;
       const Layout::Kry &K = x->L.K[0];
       dz *out = x->ptr<dz>(K.vz), *s1 = x->ptr<dz>(K.vt), *s2 = x->ptr<dz>(K.vu);
-      const int save_rw = x->trsv_rw;
-      x->trsv_rw = 4;   // the fused kernel's update rows per wave
+      const int save_kc = x->trsv_kc;
+      x->trsv_kc = kTrsvSumCols;   // the fused kernel's work-item width
       const std::vector<TrsvStep> plan = trsv_plan(x, 1, &out, &s1, &s2);
-      x->trsv_rw = save_rw;
+      x->trsv_kc = save_kc;
       // each entry to its step in the merged plan: a regular entry of block bk
       // at the sweep's step for bk, a domain's closing entry right after its
       // own last step (its partial products are not touched in between)
@@ -562,16 +562,8 @@ int build_step_plan(vie_batch *b, StepPlan &sp) {
       for (auto &v : steps[sw]) {
         if (v.empty()) continue;
         int total = 0;
-        for (TrsvDom &D : v) {
-          D.first_block = total;
-          if (D.nm == 0) {
-            total += 1;
-          } else {
-            const int rest = D.cm > 0 ? (sw == 0 ? D.n - D.nb0 - D.nm : D.nb0) : 0;
-            total += kTrsvGroupsH + (rest > 0 ? (int)nblk(rest, 16 * 4) : 0);
-          }
-        }
-        sp.tsteps.push_back({st.add(v.data(), sizeof(TrsvDom) * v.size()), (int)v.size(), sw == 0 ? 1 : 0, total});
+        const int chain = trsv_number_items(v.data(), (int)v.size(), &total);
+        sp.tsteps.push_back({st.add(v.data(), sizeof(TrsvDom) * v.size()), (int)v.size(), sw == 0 ? 1 : 0, total, chain});
       }
   }
   return upload(b, st);
@@ -591,8 +583,10 @@ int issue_step(vie_batch *b, const StepPlan &sp) {
     const bool f32 = b->precision == VIE_MIXED_FP32;
     for (const auto &s : sp.tsteps) {
       const TrsvDom *d = (const TrsvDom *)(b->ws + s.off);
-      if (f32) hipLaunchKernelGGL(k_trsv_stepd_c, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower);
-      else hipLaunchKernelGGL(k_trsv_stepd_z, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower);
+      if (f32)
+        hipLaunchKernelGGL(k_trsv_stepd_c, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain);
+      else
+        hipLaunchKernelGGL(k_trsv_stepd_z, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain);
     }
   }
   hipLaunchKernelGGL(k_b_matvec, dim3(sp.tot_mv), t256, 0, b->stream, kc, pre(sp.pre_mv), nc, act);

@@ -34,7 +34,7 @@ struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, near_tf, near_ft, quad, pgf,
       pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart,
+  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart, tbsum,
       plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
@@ -46,6 +46,7 @@ struct Layout {
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
   std::vector<int64_t> doff;       // per-domain offset of the diagonal-block inverses (elements)
+  std::vector<int64_t> boff;       // per-domain offset of the triangular solves' chunk sums (elements)
   std::vector<int64_t> toff;       // per-domain offset of the tournament tree nodes (nodes)
   int restart = 0;
   int64_t ldv = 0;
@@ -75,7 +76,7 @@ struct vie_ctx {
   std::vector<int32_t> near_off;    // offsets of the near lists per colour pair
   std::vector<int32_t> tf_off, ft_off;   // offsets (in pairs) of the touching tet-face / face-tet lists per colour
   int mv_rpw = 4;                   // matvec rows per wave (2, 4, 8)
-  int trsv_rw = 4;                  // triangular-solve update rows per wave (4, 8)
+  int trsv_kc = 2048;               // triangular-solve chunk width in columns (1024, 2048)
   int graph_steps = 0;              // Arnoldi steps per captured graph (0: plain launches)
   int trsv_coop = 0;                // triangular solves as one cooperative launch per apply
   int lu_pivot = 0;                 // 0: tournament pivoting per panel, 1: partial pivoting column by column
@@ -88,7 +89,7 @@ struct vie_ctx {
   int coop_grid = 0;                // co-resident thread blocks of the cooperative kernel
   struct CoopPlan {
     const void *v, *out, *s1, *s2;
-    int rw, nsteps;
+    int kc, nsteps;
     size_t off;                     // byte offset of the plan in the workspace
   };
   std::vector<CoopPlan> plans;

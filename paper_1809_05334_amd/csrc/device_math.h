@@ -30,6 +30,14 @@ __device__ __forceinline__ void axpy(dz &acc, double s, dz a) {
   acc.re = fma(s, a.re, acc.re);
   acc.im = fma(s, a.im, acc.im);
 }
+// acc += a * b with each real product fused into the accumulator (four FMAs,
+// no separate product to keep live)
+__device__ __forceinline__ void cmac(dz &acc, dz a, dz b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
 
 __device__ __forceinline__ fz operator+(fz a, fz b) { return fz{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ fz operator-(fz a, fz b) { return fz{a.re - b.re, a.im - b.im}; }

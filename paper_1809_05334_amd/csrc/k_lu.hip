@@ -1117,20 +1117,25 @@ __device__ __forceinline__ dz wave_sum_dpp(dz v) { return mk(wave_sum_dpp(v.re),
 //   - the solution of block j-2, [cb0, cb0+cm), is in sol (cm = 0 if j < 2);
 //   - the solution of block j-1, [pb0, pb0+pm), is known only as
 //     kTrsvGroupsH partial products in part_in (pm = 0 if j < 1);
-//   - every row still to be solved has received the updates of blocks < j-2.
+//   - for every row of block j, the sum of T[i, k] z_k over the blocks k < j-2
+//     is in bsum_in as nci chunk sums (nci = 0 if j < 3).
 // The launch
-//   (a) subtracts T[i, block j-2] z_{j-2} from every row i past block j
-//       (below it for L, above it for U);
+//   (a) for every row i of block j+1 (if any), sums T[i, k] z_k over the
+//       blocks k <= j-2, whose solutions are in sol: columns [bc0, bc0+bk)
+//       in chunks of kc, one chunk sum per (row, chunk) into bsum_out;
 //   (b) sums z_{j-1} from its partials (thread block 0 also stores it in sol),
-//       and solves block j: r = rhs_j - T[j, j-2] z_{j-2} - T[j, j-1] z_{j-1},
-//       z_j = inv(T_jj) r, left as partial products: the first kTrsvGroupsH
-//       thread blocks own 16 rows each; after updating them they form
-//       inv(T_jj)[:, 16g:16g+16] r_g into part_out[g][:].
+//       and solves block j: r = rhs_j - (its chunk sums) - T[j, j-2] z_{j-2}
+//       - T[j, j-1] z_{j-1}, z_j = inv(T_jj) r, left as partial products: the
+//       first kTrsvGroupsH thread blocks own 16 rows each; after forming them
+//       they write inv(T_jj)[:, 16g:16g+16] r_g into part_out[g][:].
 // The next launch (the same-stream kernel boundary orders the two) sums them.
-// Each row receives its updates one block at a time in the sweep's order, as
-// in a plain blocked substitution.  An entry with nm = 0 only stores z_{j-1}
-// (one thread block; the end of a sweep).  No thread block waits on another.
-// The domain's further thread blocks do (a), 16 RW rows per block.
+// Row i of block j thus receives rhs_i minus the sum over k < j of T[i, k]
+// z_k, the terms grouped as (chunks of the blocks < j-2), block j-2, block
+// j-1.  The update reads of (a) run along factor rows, kc contiguous entries
+// per wave, so each launch streams whole row segments rather than a strip of
+// one block column.  An entry with nm = 0 only stores z_{j-1} (one thread
+// block; the end of a sweep).  No thread block waits on another; the right-
+// hand sides are only read.
 constexpr int kTrsvGroups = kTrsvGroupsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
 constexpr int kTrsvHS = 1024 / kTrsvNB;  // thread groups sharing a group's 16 columns of inv(T_nn)
@@ -1202,22 +1207,29 @@ struct TrsvNew {
   }
 };
 
-// RW rows per wave in the update blocks (16 RW rows per thread block); the
-// autotuner picks RW per context.  NV right-hand sides (1 or 2) share each
-// read of the factors; vector q's sums run in the same order for any NV.
-template <typename C, int RW, int NV, typename ST = TrsvStep>
+// Shared memory of a step's thread block: the chain items use zo, zn, rg and
+// red, the chunk items the chunk's solutions; one array serves both.
+template <int NV, int KC>
+struct TrsvLds {
+  static constexpr int kChain = NV * (2 * kTrsvNB + 16 + kTrsvHS * kTrsvNB);
+  static constexpr int kChunk = NV * KC;
+  static constexpr int kSize = kChain > kChunk ? kChain : kChunk;
+};
+
+// KC columns per chunk sum (the autotuner picks 1024 or 2048 per context).
+// NV right-hand sides (1 or 2) share each read of the factors; vector q's
+// sums run in the same order for any NV.
+template <typename C, int KC, int NV, typename ST = TrsvStep>
 __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
-  __shared__ dz zo[NV][kTrsvNB];
-  __shared__ dz zn[NV][kTrsvNB];
-  __shared__ dz rg[NV][16];
-  __shared__ dz red[NV][kTrsvHS][kTrsvNB];
-  constexpr int kTrsvBlockRows = 16 * RW;
+  static_assert(KC % 1024 == 0, "chunk staging: whole passes of 1024 threads");
+  __shared__ dz sm[TrsvLds<NV, KC>::kSize];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // the work item's domain: the last with first_block <= vb
+  // the work item's domain: the last whose first chain (or chunk-sum) item is <= vb
+  const bool chain = vb < st.chain_blocks;
   int d = 0;
   for (int lo = 0, hi = st.ndom - 1; lo <= hi;) {
     const int mid = (lo + hi) >> 1;
-    if (st.d[mid].first_block <= vb) {
+    if ((chain ? st.d[mid].first_block : st.d[mid].first_bulk) <= vb) {
       d = mid;
       lo = mid + 1;
     } else {
@@ -1226,22 +1238,26 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   }
   const TrsvDom &D = st.d[d];
   if (D.active && !*D.active) return;   // (fused batch) a cell whose Arnoldi steps are paused
-  const int blk = vb - D.first_block;
-  const int cb0 = D.cb0, cm = D.cm, pb0 = D.pb0, pm = D.pm, nb0 = D.nb0, nm = D.nm;
+  const int blk = chain ? vb - D.first_block : kTrsvGroups + (vb - D.first_bulk);
   const int64_t ld = D.ld;
   const C *__restrict__ F = (const C *)D.F;
-  if (nm == 0) {   // end of a sweep: only the last block's solution
+  dz(*zo)[kTrsvNB] = reinterpret_cast<dz(*)[kTrsvNB]>(sm);
+  dz(*zn)[kTrsvNB] = reinterpret_cast<dz(*)[kTrsvNB]>(sm + NV * kTrsvNB);
+  dz(*rg)[16] = reinterpret_cast<dz(*)[16]>(sm + 2 * NV * kTrsvNB);
+  dz(*red)[kTrsvHS][kTrsvNB] = reinterpret_cast<dz(*)[kTrsvHS][kTrsvNB]>(sm + 2 * NV * kTrsvNB + 16 * NV);
+  if (D.nm == 0) {   // end of a sweep: only the last block's solution
     TrsvNew<NV> pn;
     pn.fetch(D);
     pn.store(D, blk, zn, red);
     return;
   }
   if (blk < kTrsvGroups) {
+    const int cb0 = D.cb0, cm = D.cm, pb0 = D.pb0, pm = D.pm, nb0 = D.nb0, nm = D.nm;
     const int g = blk;
     // every load is issued before the first wait: z_{j-2}, the partials of
     // z_{j-1} (into shared memory once they arrive), the row of group g this
-    // wave updates (its entries in blocks j-2 and j-1), its rhs, and this
-    // thread's four entries of the DT slice
+    // wave solves (its entries in blocks j-2 and j-1), its rhs, this thread's
+    // four entries of the DT slice and the row's chunk sums
     TrsvOld<NV> po;
     TrsvNew<NV> pn;
     po.fetch(D);
@@ -1268,11 +1284,23 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
     C dt[kTrsvCPH];
 #pragma unroll
     for (int l = 0; l < kTrsvCPH; ++l) dt[l] = col[(int64_t)l * kTrsvNB];
+    // chunk sums of row r: lane l takes chunks l and l + 64 (bst <= 128)
+    dz bs[NV];
+    {
+      const int bst = D.bst, nci = D.nci;
+      const dz *bp = D.bsum_in + (int64_t)clampi(r, kTrsvNB - 1) * bst;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const dz b0 = bp[(int64_t)q * kTrsvNB * bst + clampi(lane, bst - 1)];
+        const dz b1 = bp[(int64_t)q * kTrsvNB * bst + clampi(lane + 64, bst - 1)];
+        bs[q] = (lane < nci ? b0 : mk(0, 0)) + (lane + 64 < nci ? b1 : mk(0, 0));
+      }
+    }
     po.store(D, zo);
     pn.store(D, blk, zn, red);
     __syncthreads();
-    // (b) for the 16 rows of group g, one row per wave: the updates of
-    // blocks j-2 and j-1, in that order
+    // (b) for the 16 rows of group g, one row per wave: the chunk sums, then
+    // the updates of blocks j-2 and j-1, in that order
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       dz so = mk(0, 0), sn = mk(0, 0);
@@ -1280,9 +1308,10 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
       for (int c = 0; c < kTrsvCol; ++c) so = so + to_dz(fo[c]) * zo[q][lane + 64 * c];
 #pragma unroll
       for (int c = 0; c < kTrsvCol; ++c) sn = sn + to_dz(fn[c]) * zn[q][lane + 64 * c];
+      const dz sb = wave_sum_dpp(bs[q]);
       so = wave_sum_dpp(so);
       sn = wave_sum_dpp(sn);
-      if (lane == 0) rg[q][wave] = r < nm ? (cm > 0 ? rv[q] - so : rv[q]) - sn : mk(0, 0);
+      if (lane == 0) rg[q][wave] = r < nm ? ((rv[q] - sb) - so) - sn : mk(0, 0);
     }
     __syncthreads();
     // partial product with columns 16 g .. 16 g + 15 of inv(T_jj)
@@ -1305,67 +1334,103 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
     }
     return;
   }
-  // (a) for the rows past block j: each wave takes RW rows as RW / 4 groups
-  // of four, sixteen lanes per row; lane c of a row holds its columns c,
-  // c + 16, .., c + kTrsvNB - 16, and a row's sum is a 16-lane DPP reduction
-  static_assert(RW % 4 == 0, "rows per wave: a multiple of four");
-  constexpr int RG = RW / 4, kPerL = kTrsvNB / 16;
-  int rlo, rhi;
-  if (st.lower) {
-    rlo = nb0 + nm + (blk - kTrsvGroups) * kTrsvBlockRows;
-    rhi = min(D.n, rlo + kTrsvBlockRows);
-  } else {
-    rlo = (blk - kTrsvGroups) * kTrsvBlockRows;
-    rhi = min(nb0, rlo + kTrsvBlockRows);
-  }
-  TrsvOld<NV> po;
-  po.fetch(D);
-  const int rr = lane >> 4, cl = lane & 15;
-  const int i0 = rlo + RW * wave + rr;   // row of group g: i0 + 4 g
-  C f[RG][kPerL];
-#pragma unroll
-  for (int g = 0; g < RG; ++g)
-#pragma unroll
-    for (int c = 0; c < kPerL; ++c)
-      f[g][c] = F[(int64_t)clampi(i0 + 4 * g, D.n - 1) * ld + cb0 + clampi(cl + 16 * c, cm - 1)];
-#pragma unroll
-  for (int g = 0; g < RG; ++g)
-#pragma unroll
-    for (int c = 0; c < kPerL; ++c)
-      if (!(i0 + 4 * g < rhi && cl + 16 * c < cm)) f[g][c] = cx<C>::make(0, 0);
-  po.store(D, zo);
-  __syncthreads();
+  // (a) work item ch of the next block's row group rgp: one row per wave,
+  // lane l holding columns l + 64 t of the item's KC columns; the item's
+  // solutions are staged in shared memory (zero past the item's end, so
+  // clamped factor reads add 0).  Each kTrsvSumCols columns give one chunk
+  // sum: lane sums in column order, then the wave sum.
+  static_assert(KC % kTrsvSumCols == 0 && kTrsvSumCols == 1024, "chunks of one pass of 1024 threads");
+  const int b = blk - kTrsvGroups;
+  const int ch = b / D.nrg, rgp = b - ch * D.nrg;
+  const int cs = D.bc0 + ch * KC;
+  const int cn = min(KC, D.bc0 + D.bk - cs);
+  const int sc0 = ch * (KC / kTrsvSumCols);   // the item's first chunk
+  const int r = 16 * rgp + wave;
+  const int i = D.br0 + clampi(r, D.brm - 1);
+  constexpr int kPer = KC / 1024;
+  dz zv[NV][kPer];
 #pragma unroll
   for (int q = 0; q < NV; ++q)
 #pragma unroll
-    for (int g = 0; g < RG; ++g) {
-      dz s = mk(0, 0);
+    for (int u = 0; u < kPer; ++u) zv[q][u] = D.sol[q][cs + clampi(tid + 1024 * u, cn - 1)];
+  constexpr int T = KC / 64;                                 // factor entries per lane
+  constexpr int LB = sizeof(C) == 8 && NV == 1 ? 16 : 8;     // entries per batch of loads
+  constexpr int NB = T / LB;
+  constexpr int kBatchesPerSum = kTrsvSumCols / 64 / LB;
+  static_assert(T % LB == 0 && (kTrsvSumCols / 64) % LB == 0, "whole batches per chunk");
+  const C *__restrict__ row = F + (int64_t)i * ld + cs;
+  C fa[LB];
 #pragma unroll
-      for (int c = 0; c < kPerL; ++c) s = s + to_dz(f[g][c]) * zo[q][cl + 16 * c];
-      s = row16_sum(s);
-      const int i = i0 + 4 * g;
-      if (cl == 0 && i < rhi) D.rhs[q][i] = D.rhs[q][i] - s;
+  for (int u = 0; u < LB; ++u) fa[u] = row[clampi(lane + 64 * u, cn - 1)];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int t = tid + 1024 * u;
+      sm[q * KC + t] = t < cn ? zv[q][u] : mk(0, 0);
     }
+  __syncthreads();
+  dz s[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) s[q] = mk(0, 0);
+  const auto use = [&](const C(&f)[LB], int bt) {
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int t = lane + 64 * (bt * LB + u);
+      const dz fu = to_dz(f[u]);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) cmac(s[q], fu, sm[q * KC + t]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // no hoisting of one batch's work into another's
+  };
+  // chunk h of the item done: every vector's wave sum, then lane 0's stores
+  // (no vector's arithmetic moves past another's store branch)
+  const auto flush = [&](int h) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = wave_sum_dpp(s[q]);
+    if (lane == 0 && r < D.brm && h * kTrsvSumCols < cn) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+        D.bsum_out[(int64_t)q * kTrsvNB * D.bst + (int64_t)r * D.bst + sc0 + h] = s[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = mk(0, 0);
+  };
+  // batch bt + 1 loads while batch bt is used (a rolled loop, so that the
+  // compiler keeps two batches in registers rather than hoisting them all);
+  // the last batch is used after the loop
+#pragma unroll 1
+  for (int bt = 0; bt < NB - 1; ++bt) {
+    C fb[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) fb[u] = row[clampi(lane + 64 * ((bt + 1) * LB + u), cn - 1)];
+    use(fa, bt);
+    if ((bt + 1) % kBatchesPerSum == 0) flush(bt / kBatchesPerSum);
+#pragma unroll
+    for (int u = 0; u < LB; ++u) fa[u] = fb[u];
+  }
+  use(fa, NB - 1);
+  flush(KC / kTrsvSumCols - 1);
 }
 
-#define VIE_TRSV_STEP(T, C, R)                                                                  \
-  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_r##R(TrsvStep st) { \
-    trsv_step_body<C, R, 1>(st, blockIdx.x);                                                  \
+#define VIE_TRSV_STEP(T, C, K)                                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_k##K(TrsvStep st) {                \
+    trsv_step_body<C, K, 1>(st, blockIdx.x);                                                  \
   }                                                                                           \
-  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_r##R(TrsvStep st) { \
-    trsv_step_body<C, R, 2>(st, blockIdx.x);                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_k##K(TrsvStep st) {               \
+    trsv_step_body<C, K, 2>(st, blockIdx.x);                                                  \
   }
-VIE_TRSV_STEP(z, dz, 4)
-VIE_TRSV_STEP(z, dz, 8)
-VIE_TRSV_STEP(c, fz, 4)
-VIE_TRSV_STEP(c, fz, 8)
+VIE_TRSV_STEP(z, dz, 1024)
+VIE_TRSV_STEP(z, dz, 2048)
+VIE_TRSV_STEP(c, fz, 1024)
+VIE_TRSV_STEP(c, fz, 2048)
 
 // Every step of the triangular solves in one cooperative launch: the thread
 // blocks share each step's work items (the same items the per-step launches
 // give to their thread blocks) and meet at a grid barrier between steps,
 // which orders one step's partial products before the next step's sums.
 // All blocks run the same loops and reach every barrier.
-template <typename C, int RW>
+template <typename C, int KC>
 __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan, int nsteps) {
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int s = 0; s < nsteps; ++s) {
@@ -1373,7 +1438,7 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
     const int total = st.total_blocks;
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
       __syncthreads();   // the previous item's shared memory is free
-      trsv_step_body<C, RW, 1>(st, vb);
+      trsv_step_body<C, KC, 1>(st, vb);
     }
     grid.sync();
   }
@@ -1383,23 +1448,24 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
 // step's domains of every cell, read from device memory.
 struct TrsvStepDev {
   const TrsvDom *d;
-  int ndom, lower;
+  int ndom, lower, chain_blocks;
 };
 #define VIE_TRSV_STEPD(T, C)                                                                      \
-  __global__ __launch_bounds__(1024) void k_trsv_stepd_##T(const TrsvDom *doms, int ndom, int lower) { \
-    const TrsvStepDev st{doms, ndom, lower};                                                      \
-    trsv_step_body<C, 4, 1, TrsvStepDev>(st, blockIdx.x);                                        \
+  __global__ __launch_bounds__(1024) void k_trsv_stepd_##T(const TrsvDom *doms, int ndom, int lower,   \
+                                                            int chain_blocks) {                        \
+    const TrsvStepDev st{doms, ndom, lower, chain_blocks};                                            \
+    trsv_step_body<C, kTrsvSumCols, 1, TrsvStepDev>(st, blockIdx.x);                             \
   }
 VIE_TRSV_STEPD(z, dz)
 VIE_TRSV_STEPD(c, fz)
 
-#define VIE_TRSV_COOP(T, C, R)                                                                  \
-  __global__ __launch_bounds__(1024) void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps) { \
-    trsv_coop_body<C, R>(plan, nsteps);                                                       \
+#define VIE_TRSV_COOP(T, C, K)                                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_coop_##T##_k##K(const TrsvStep *plan, int nsteps) { \
+    trsv_coop_body<C, K>(plan, nsteps);                                                       \
   }
-VIE_TRSV_COOP(z, dz, 4)
-VIE_TRSV_COOP(z, dz, 8)
-VIE_TRSV_COOP(c, fz, 4)
-VIE_TRSV_COOP(c, fz, 8)
+VIE_TRSV_COOP(z, dz, 1024)
+VIE_TRSV_COOP(z, dz, 2048)
+VIE_TRSV_COOP(c, fz, 1024)
+VIE_TRSV_COOP(c, fz, 2048)
 
 }  // namespace vie

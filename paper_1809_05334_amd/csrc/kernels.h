@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_math.h"
 
 namespace vie {
@@ -180,41 +182,83 @@ __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, 
 constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
 constexpr int kTrsvPart = kTrsvGroupsH * kTrsvNB;   // partial products of one vector
 constexpr int kTrsvMaxDom = 8;
+// Row sums over the solved columns come in chunks of kTrsvSumCols columns
+// (a work item covers kc = 1024 or 2048 columns, one or two chunks, with the
+// same sums either way); a row's chunk sums are read by 64 lanes, two each,
+// which bounds a domain at kTrsvChunksMax * kTrsvSumCols unknowns.
+constexpr int kTrsvSumCols = 1024;
+constexpr int kTrsvChunksMax = 128;
 struct TrsvDom {
   const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
   const void *DT;     // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB, same type)
-  dz *rhs[2], *sol[2];  // right-hand sides (updated in place) and solutions, domain-local, per vector
+  const dz *rhs[2];   // right-hand sides, domain-local, per vector (read only)
+  dz *sol[2];         // solutions, domain-local, per vector
   const dz *part_in;  // partial products of the previous block's solution (kTrsvGroupsH x kTrsvNB
                       // per vector, vector q at q * kTrsvPart), written by the previous step
   dz *part_out;       // the same for this step's diagonal block, read by the next step
+  // chunk sums over the solved columns: for row i of a block, chunk c of vector q at
+  // q * kTrsvNB * bst + i * bst + c.  bsum_in holds nci chunks for this step's block
+  // (written by the previous step); bsum_out receives those of the next block
+  const dz *bsum_in;
+  dz *bsum_out;
   int64_t ld;
   // blocks of the step: [cb0, cb0+cm) two back (solution in sol), [pb0, pb0+pm) the previous one
   // (solution in part_in), [nb0, nb0+nm) the one solved; nm = 0: only store the previous block's solution
-  int n, cb0, cm, pb0, pm, nb0, nm, first_block;
+  int n, cb0, cm, pb0, pm, nb0, nm;
+  // the entry's work items: its chain items (the diagonal block) from first_block,
+  // its chunk-sum items from first_bulk; every chain item of a step precedes
+  // every chunk-sum item, so the chain starts with the launch
+  int first_block, first_bulk;
+  // the next block's rows [br0, br0+brm) against the solved columns [bc0, bc0+bk):
+  // nrg groups of 16 rows times nco work items of kc columns (brm = 0: none)
+  int bst, nci, br0, brm, bc0, bk, nrg, nco;
   const int *active;  // (fused batch) the cell's flag: 0 skips the domain; nullptr always runs
 };
+// chunk sums per row of a domain of n unknowns (the row stride bst)
+inline int trsv_bsum_stride(int64_t n) { return (int)std::max<int64_t>(1, (n + kTrsvSumCols - 1) / kTrsvSumCols); }
+// work items of one domain's entry in a step: chain items, chunk-sum items
+inline int trsv_chain_items(const TrsvDom &D) { return D.nm == 0 ? 1 : kTrsvGroupsH; }
+inline int trsv_bulk_items(const TrsvDom &D) { return D.nm == 0 ? 0 : D.nrg * D.nco; }
+// first_block / first_bulk of entries d[0 .. nd), chain items first; returns
+// the chain items, *total the work items of the step
+inline int trsv_number_items(TrsvDom *d, int nd, int *total) {
+  int c = 0;
+  for (int i = 0; i < nd; ++i) {
+    d[i].first_block = c;
+    c += trsv_chain_items(d[i]);
+  }
+  int b = c;
+  for (int i = 0; i < nd; ++i) {
+    d[i].first_bulk = b;
+    b += trsv_bulk_items(d[i]);
+  }
+  *total = b;
+  return c;
+}
 struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
   int ndom, lower;
+  int chain_blocks;   // work items of the diagonal blocks, numbered first
   int total_blocks;   // thread blocks (work items) of the step over all its domains
 };
-// variants by factor type (_z FP64, _c FP32) and rows per wave of the update
-// blocks (4, 8 -> 64, 128 rows per block); vectors and arithmetic FP64.
+// variants by factor type (_z FP64, _c FP32) and columns per work item
+// (1024 or 2048, the same sums); vectors and arithmetic FP64.
 // k_trsv_step2_*: two right-hand sides per pass over the factors (each
 // vector's sums in the order of the one-vector kernel).
 // k_trsv_coop_*: every step of a plan in one cooperative launch.
-#define VIE_DECL_TRSV(T, R)                                  \
-  __global__ void k_trsv_step_##T##_r##R(TrsvStep st);       \
-  __global__ void k_trsv_step2_##T##_r##R(TrsvStep st);      \
-  __global__ void k_trsv_coop_##T##_r##R(const TrsvStep *plan, int nsteps);
+#define VIE_DECL_TRSV(T, K)                                  \
+  __global__ void k_trsv_step_##T##_k##K(TrsvStep st);       \
+  __global__ void k_trsv_step2_##T##_k##K(TrsvStep st);      \
+  __global__ void k_trsv_coop_##T##_k##K(const TrsvStep *plan, int nsteps);
 // k_trsv_stepd_*: one step of a batch's fused solves, one vector per cell,
-// the step's domains (any number) read from device memory
-__global__ void k_trsv_stepd_z(const TrsvDom *doms, int ndom, int lower);
-__global__ void k_trsv_stepd_c(const TrsvDom *doms, int ndom, int lower);
-VIE_DECL_TRSV(z, 4)
-VIE_DECL_TRSV(z, 8)
-VIE_DECL_TRSV(c, 4)
-VIE_DECL_TRSV(c, 8)
+// the step's domains (any number) read from device memory; work items of
+// kTrsvSumCols columns
+__global__ void k_trsv_stepd_z(const TrsvDom *doms, int ndom, int lower, int chain_blocks);
+__global__ void k_trsv_stepd_c(const TrsvDom *doms, int ndom, int lower, int chain_blocks);
+VIE_DECL_TRSV(z, 1024)
+VIE_DECL_TRSV(z, 2048)
+VIE_DECL_TRSV(c, 1024)
+VIE_DECL_TRSV(c, 2048)
 #undef VIE_DECL_TRSV
 
 // Krylov (k_krylov.hip).  Matvec variants by rows per wave (2, 4, 8): a block

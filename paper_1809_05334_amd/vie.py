@@ -62,18 +62,18 @@ class FactorStats(C.Structure):
 
 _LIB = None
 
-VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_ROWS, VIE_OPT_TRSV_COOP, VIE_OPT_LU_PIVOT = 1, 2, 3, 4, 5
+VIE_OPT_GRAPH_STEPS, VIE_OPT_MATVEC_ROWS, VIE_OPT_TRSV_CHUNK, VIE_OPT_TRSV_COOP, VIE_OPT_LU_PIVOT = 1, 2, 3, 4, 5
 VIE_OPT_SYM_FILL = 6
 VIE_OPT_PRECOND = 7
 
 
 class Tuning(C.Structure):
     _fields_ = [("matvec_ms", C.c_double * 6), ("apply_ms", C.c_double * 4),
-                ("matvec_rows", C.c_int), ("trsv_rows", C.c_int)]
+                ("matvec_rows", C.c_int), ("trsv_chunk", C.c_int)]
 
     def as_dict(self):
         return {"matvec_ms": list(self.matvec_ms), "apply_ms": list(self.apply_ms),
-                "matvec_rows": self.matvec_rows, "trsv_rows": self.trsv_rows}
+                "matvec_rows": self.matvec_rows, "trsv_chunk": self.trsv_chunk}
 
 
 _SIGS = {

@@ -112,12 +112,12 @@ def test_autotune_picks_a_variant_without_changing_results(vie, precision):
     s.factor()
     base = solved(vie, s, 0, 40)
     tun = s.autotune(reps=3)
-    assert tun["matvec_rows"] in (2, 4, 8) and tun["trsv_rows"] in (4, 8)
+    assert tun["matvec_rows"] in (2, 4, 8) and tun["trsv_chunk"] in (1024, 2048)
     assert all(t > 0 for t in tun["matvec_ms"] + tun["apply_ms"])
     assert s.get_option(vie.VIE_OPT_MATVEC_ROWS) == tun["matvec_rows"]
     for mv in (2, 4, 8):
-        for tr in (4, 8):
+        for tr in (1024, 2048):
             s.set_option(vie.VIE_OPT_MATVEC_ROWS, mv)
-            s.set_option(vie.VIE_OPT_TRSV_ROWS, tr)
+            s.set_option(vie.VIE_OPT_TRSV_CHUNK, tr)
             info, x, h = solved(vie, s, 0, 40)
             assert info["iters"] == base[0]["iters"] and np.array_equal(x, base[1]), (mv, tr)
