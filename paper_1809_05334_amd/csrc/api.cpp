@@ -126,7 +126,8 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
-  put(L.tpart, 16 * 4 * (size_t)kTrsvPart * std::max(1, t.ndom));   // two buffers of two right-hand sides per domain
+  put(L.gcpl, fes * (size_t)std::max<int64_t>(1, del));   // coupling blocks, laid out as the inverses
+  put(L.trr, 16 * 4 * (size_t)kTrsvNB * std::max(1, t.ndom));   // r of a block: two buffers of two vectors per domain
   // chunk sums: per domain two buffers (steps alternate) of two vectors, kTrsvNB rows each
   L.boff.resize(t.ndom);
   int64_t bel = 0;
@@ -1176,8 +1177,8 @@ int factor_panels(vie_ctx *ctx, std::vector<LuDom> &doms, bool f32, int lu_pivot
   return VIE_OK;
 }
 
-// After the panels: the transposed inverses of the 256-row diagonal blocks of
-// L and U, the pivots read back (zero pivot: VIE_ESINGULAR), each block's row
+// After the panels: the inverses of the 256-row diagonal blocks of L and U and
+// the coupling blocks of the triangular solves, the pivots read back (zero pivot: VIE_ESINGULAR), each block's row
 // permutation built on the host and uploaded; the context becomes S_FACTORED.
 int factor_finish(vie_ctx *ctx, const std::vector<LuDom> &doms) {
   const MeshTopology &t = ctx->topo;
@@ -1190,13 +1191,26 @@ int factor_finish(vie_ctx *ctx, const std::vector<LuDom> &doms) {
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
     void *DL = factor_ptr(ctx, L.dinv, L.doff[d]);
     void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
+    void *GL = factor_ptr(ctx, L.gcpl, L.doff[d]);
+    void *GU = factor_ptr(ctx, L.gcpl, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
     const dim3 ig(nbk, kTrsvNB / kInvColsH), ib(4 * kInvColsH);   // kInvColsH columns of one inverse per block
+    const dim3 cg(nbk - 1, (kTrsvNB / 64) * (kTrsvNB / 64)), cb(256);   // 64 x 64 tiles of each coupling block
     if (f32) {
-      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, (fz *)DL);
-      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, (const fz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, (fz *)DU);
+      const fz *A = (const fz *)doms[d].A;
+      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, A, doms[d].ld, n, kTrsvNB, 1, (fz *)DL);
+      hipLaunchKernelGGL(k_diag_inv_c, ig, ib, 0, ctx->stream, A, doms[d].ld, n, kTrsvNB, 0, (fz *)DU);
+      if (nbk > 1) {
+        hipLaunchKernelGGL(k_trsv_coupling_c, cg, cb, 0, ctx->stream, A, doms[d].ld, n, 1, (const fz *)DL, (fz *)GL);
+        hipLaunchKernelGGL(k_trsv_coupling_c, cg, cb, 0, ctx->stream, A, doms[d].ld, n, 0, (const fz *)DU, (fz *)GU);
+      }
     } else {
-      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 1, (dz *)DL);
-      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, (const dz *)doms[d].A, doms[d].ld, n, kTrsvNB, 0, (dz *)DU);
+      const dz *A = (const dz *)doms[d].A;
+      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, A, doms[d].ld, n, kTrsvNB, 1, (dz *)DL);
+      hipLaunchKernelGGL(k_diag_inv_z, ig, ib, 0, ctx->stream, A, doms[d].ld, n, kTrsvNB, 0, (dz *)DU);
+      if (nbk > 1) {
+        hipLaunchKernelGGL(k_trsv_coupling_z, cg, cb, 0, ctx->stream, A, doms[d].ld, n, 1, (const dz *)DL, (dz *)GL);
+        hipLaunchKernelGGL(k_trsv_coupling_z, cg, cb, 0, ctx->stream, A, doms[d].ld, n, 0, (const dz *)DU, (dz *)GU);
+      }
     }
     LAUNCHCK();
   }
@@ -1285,9 +1299,9 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
   const int kc = ctx->trsv_kc;
   int maxnbk = 0;
   for (int d = 0; d < t.ndom; ++d) maxnbk = std::max(maxnbk, (int)((t.dend[d] - t.dstart[d] + kTrsvNB - 1) / kTrsvNB));
-  // partial products: per domain two buffers (steps alternate) of two vectors
-  dz *part = ctx->ptr<dz>(L.tpart);
-  auto buf = [&](int d, int k) { return part + ((int64_t)d * 4 + 2 * (k & 1)) * kTrsvPart; };
+  // r of a block: per domain two buffers (steps alternate) of two vectors
+  dz *rr = ctx->ptr<dz>(L.trr);
+  auto rbuf = [&](int d, int k) { return rr + ((int64_t)d * 4 + 2 * (k & 1)) * kTrsvNB; };
   // chunk sums: the same alternation, in the domain's region of L.tbsum
   dz *bsum = ctx->ptr<dz>(L.tbsum);
   auto bbuf = [&](int d, int k) {
@@ -1304,7 +1318,7 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
       st.lower = lower;
       auto push = [&]() {
         if (st.ndom == 0) return;
-        st.chain_blocks = trsv_number_items(st.d, st.ndom, &st.total_blocks);
+        st.chain_blocks = trsv_number_items(st.d, st.ndom, &st.z_end, &st.total_blocks);
         plan.push_back(st);
         st = TrsvStep{};
         st.lower = lower;
@@ -1324,22 +1338,27 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
           D.sol[q] = (lower ? s2[q] : out[q]) + off;
         }
         D.bst = trsv_bsum_stride(n);
+        // inverse and coupling block of matrix block b of this sweep
+        auto blockof = [&](Region R, int b) {
+          return factor_ptr(ctx, R, dl + (int64_t)(lower ? b : nbk + b) * kTrsvNB * kTrsvNB);
+        };
         if (k == maxnbk) {
-          // the partials of the domain's last step: one thread block stores them
+          // the end of the domain's sweep: the solution of its last block
           const int bk = lower ? nbk - 1 : 0;
           D.pb0 = bk * kTrsvNB;
           D.pm = std::min(kTrsvNB, n - D.pb0);
           D.cb0 = D.cm = D.nb0 = D.nm = 0;
-          D.part_in = buf(d, nbk - 1);
-          D.part_out = nullptr;
-          D.DT = nullptr;
+          D.rin = rbuf(d, nbk - 1);
+          D.rout = nullptr;
+          D.INV = blockof(L.dinv, bk);
+          D.G = D.INV;
           D.bsum_in = D.bsum_out = bbuf(d, 0);
           if (++st.ndom == kTrsvMaxDom) push();
           continue;
         }
-        // step k solves block bk; blocks bk -+ 1 and bk -+ 2 (in the sweep's order) come before it
-        D.part_in = buf(d, k - 1);
-        D.part_out = buf(d, k);
+        // step k reduces block bk; blocks bk -+ 1 and bk -+ 2 (in the sweep's order) come before it
+        D.rin = rbuf(d, k - 1);
+        D.rout = rbuf(d, k);
         const int bk = lower ? k : nbk - 1 - k;
         const int dir = lower ? -1 : 1;
         D.nb0 = bk * kTrsvNB;
@@ -1348,7 +1367,9 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
         D.pm = k >= 1 ? std::min(kTrsvNB, n - D.pb0) : 0;
         D.cb0 = k >= 2 ? (bk + 2 * dir) * kTrsvNB : 0;
         D.cm = k >= 2 ? std::min(kTrsvNB, n - D.cb0) : 0;
-        D.DT = factor_ptr(ctx, L.dinv, dl + (int64_t)(lower ? bk : nbk + bk) * kTrsvNB * kTrsvNB);
+        // (k = 0: no previous block; the pointers stay valid, their entries masked)
+        D.G = blockof(L.gcpl, bk);
+        D.INV = blockof(L.dinv, k >= 1 ? bk + dir : bk);
         // block k's chunk sums over the blocks <= k - 3, from step k - 1
         D.bsum_in = bbuf(d, k - 1);
         const int kin = k >= 3 ? (lower ? (k - 2) * kTrsvNB : n - (nbk + 2 - k) * kTrsvNB) : 0;

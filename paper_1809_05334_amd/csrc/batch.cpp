@@ -455,7 +455,7 @@ struct StepPlan {
   int tot_elem, tot_mv, tot_dots, tot_red, tot_norm;
   struct TStep {
     size_t off;
-    int ndom, lower, blocks, chain;   // chain: the step's chain items, numbered first
+    int ndom, lower, blocks, chain, zend;   // reduction items first, solution items up to zend
   };
   std::vector<TStep> tsteps;
   bool precond = true;
@@ -561,9 +561,10 @@ int build_step_plan(vie_batch *b, StepPlan &sp) {
     for (int sw = 0; sw < 2; ++sw)
       for (auto &v : steps[sw]) {
         if (v.empty()) continue;
-        int total = 0;
-        const int chain = trsv_number_items(v.data(), (int)v.size(), &total);
-        sp.tsteps.push_back({st.add(v.data(), sizeof(TrsvDom) * v.size()), (int)v.size(), sw == 0 ? 1 : 0, total, chain});
+        int total = 0, zend = 0;
+        const int chain = trsv_number_items(v.data(), (int)v.size(), &zend, &total);
+        sp.tsteps.push_back(
+            {st.add(v.data(), sizeof(TrsvDom) * v.size()), (int)v.size(), sw == 0 ? 1 : 0, total, chain, zend});
       }
   }
   return upload(b, st);
@@ -584,9 +585,11 @@ int issue_step(vie_batch *b, const StepPlan &sp) {
     for (const auto &s : sp.tsteps) {
       const TrsvDom *d = (const TrsvDom *)(b->ws + s.off);
       if (f32)
-        hipLaunchKernelGGL(k_trsv_stepd_c, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain);
+        hipLaunchKernelGGL(k_trsv_stepd_c, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain,
+                           s.zend);
       else
-        hipLaunchKernelGGL(k_trsv_stepd_z, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain);
+        hipLaunchKernelGGL(k_trsv_stepd_z, dim3(s.blocks), dim3(1024), 0, b->stream, d, s.ndom, s.lower, s.chain,
+                           s.zend);
     }
   }
   hipLaunchKernelGGL(k_b_matvec, dim3(sp.tot_mv), t256, 0, b->stream, kc, pre(sp.pre_mv), nc, act);

@@ -34,7 +34,7 @@ struct Layout {
   Region tg, t2f, area, dom, fg, half, ctp, ctm, utet, uk, colors, near_t, near_s, near_m, near_tf, near_ft, quad, pgf,
       pack;
   Region eps, alpha, gsrc, kappa, inveps, sigma;
-  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, tpart, tbsum,
+  Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, gcpl, trr, tbsum,
       plans;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)

@@ -1005,8 +1005,8 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
 }
 
 // Inverses of the kTrsvNB x kTrsvNB diagonal blocks of L (unit lower) and U
-// (upper), computed once per factorisation and stored TRANSPOSED: block b of
-// DT holds inv(T_bb)^T row-major, T_bb the diagonal block at row b*nb.  A
+// (upper), computed once per factorisation: block b of INV holds inv(T_bb)
+// row-major, T_bb the diagonal block at row b*nb, zero past its size.  A
 // thread block forms 32 columns of one inverse by substitution; the columns
 // live in LDS, and each column's dot products are split over 4 lanes
 // (residues of the summation index mod 4, combined by shuffles).  A lane only
@@ -1016,7 +1016,7 @@ constexpr int kInvCols = kInvColsH;
 
 template <typename C>
 __device__ __forceinline__ void diag_inv_body(const C *__restrict__ F, int64_t ld, int n, int nb, int lower,
-                                              C *__restrict__ DT) {
+                                              C *__restrict__ INV) {
   __shared__ dz X[kInvCols][kTrsvNB];
   const int b = blockIdx.x;
   const int b0 = b * nb;
@@ -1066,16 +1066,82 @@ __device__ __forceinline__ void diag_inv_body(const C *__restrict__ F, int64_t l
   }
   __syncthreads();
   if (j < nb) {
-    C *row = DT + ((int64_t)b * nb + j) * nb;   // row j of DT = column j of the inverse
-    for (int i = t; i < nb; i += 4) row[i] = cx<C>::of(X[cl][i]);
+    C *inv_b = INV + (int64_t)b * nb * nb;   // the inverse of block b, row-major: its column j
+    for (int i = t; i < nb; i += 4) inv_b[(int64_t)i * nb + j] = cx<C>::of(X[cl][i]);
   }
 }
 
-__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *DT) {
-  diag_inv_body(F, ld, n, nb, lower, DT);
+__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *INV) {
+  diag_inv_body(F, ld, n, nb, lower, INV);
 }
-__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *DT) {
-  diag_inv_body(F, ld, n, nb, lower, DT);
+__global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *INV) {
+  diag_inv_body(F, ld, n, nb, lower, INV);
+}
+
+// Coupling blocks of one domain's sweep: for the matrix blocks b that follow
+// another in the sweep's order (b >= 1 for L, b <= nbk - 2 for U), with p =
+// b - 1 (L) or b + 1 (U), G_b = T[b, p] inv(T_pp), a kTrsvNB x kTrsvNB
+// product in FP64 (rounded to the factor type), written at G + b nb^2.  A
+// thread block forms a 64 x 64 tile, 4 x 4 entries per thread, through
+// 16-deep slices of both operands in shared memory; entries past the blocks'
+// sizes are zero.
+template <typename C>
+__device__ __forceinline__ void coupling_body(const C *__restrict__ F, int64_t ld, int n, int lower,
+                                              const C *__restrict__ INV, C *__restrict__ G) {
+  constexpr int nb = kTrsvNB, TS = 64, KS = 16;
+  __shared__ dz As[TS][KS + 1], Bs[KS][TS + 1];
+  const int b = lower ? blockIdx.x + 1 : blockIdx.x;
+  const int p = lower ? b - 1 : b + 1;
+  const int b0 = b * nb, p0 = p * nb;
+  const int mr = min(nb, n - b0), mc = min(nb, n - p0);
+  const int tr = blockIdx.y / (nb / TS), tc = blockIdx.y % (nb / TS);
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const C *__restrict__ Ip = INV + (int64_t)p * nb * nb;
+  dz acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = mk(0, 0);
+  for (int k0 = 0; k0 < nb; k0 += KS) {
+    // A slice: rows tr*TS .. +TS of T[b, p], columns k0 .. k0+KS; B slice: rows k0 .. of inv(T_pp)
+#pragma unroll
+    for (int e = tid; e < TS * KS; e += 256) {
+      const int rr = e / KS, kk = e % KS;
+      const int gr = tr * TS + rr, gk = k0 + kk;
+      As[rr][kk] = gr < mr && gk < mc ? to_dz(F[(int64_t)(b0 + gr) * ld + p0 + gk]) : mk(0, 0);
+    }
+#pragma unroll
+    for (int e = tid; e < KS * TS; e += 256) {
+      const int kk = e / TS, cc = e % TS;
+      Bs[kk][cc] = to_dz(Ip[(int64_t)(k0 + kk) * nb + tc * TS + cc]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      dz a[4], bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = As[ty * 4 + u][kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bb[v] = Bs[kk][tx * 4 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cmac(acc[u][v], a[u], bb[v]);
+    }
+    __syncthreads();
+  }
+  C *__restrict__ Gb = G + (int64_t)b * nb * nb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      Gb[(int64_t)(tr * TS + ty * 4 + u) * nb + tc * TS + tx * 4 + v] = cx<C>::of(acc[u][v]);
+}
+__global__ __launch_bounds__(256) void k_trsv_coupling_z(const dz *F, int64_t ld, int n, int lower, const dz *INV, dz *G) {
+  coupling_body(F, ld, n, lower, INV, G);
+}
+__global__ __launch_bounds__(256) void k_trsv_coupling_c(const fz *F, int64_t ld, int n, int lower, const fz *INV, fz *G) {
+  coupling_body(F, ld, n, lower, INV, G);
 }
 
 __device__ __forceinline__ dz wave_sum(dz v) {
@@ -1110,126 +1176,83 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 __device__ __forceinline__ dz wave_sum_dpp(dz v) { return mk(wave_sum_dpp(v.re), wave_sum_dpp(v.im)); }
 
 // One step of the blocked triangular solves (L forward or U backward) of
-// every material domain at once, with nb = kTrsvNB diagonal blocks whose
-// transposed inverses DT are precomputed.  Blocks are numbered in the order
-// of the sweep; step j of domain d solves its diagonal block j, [nb0, nb0+nm).
-// On entry
-//   - the solution of block j-2, [cb0, cb0+cm), is in sol (cm = 0 if j < 2);
-//   - the solution of block j-1, [pb0, pb0+pm), is known only as
-//     kTrsvGroupsH partial products in part_in (pm = 0 if j < 1);
+// every material domain at once, with nb = kTrsvNB diagonal blocks.  Blocks
+// are numbered in the order of the sweep; step j of domain d reduces block j.
+// Write r_k = rhs_k - sum over i < k of T[k, i] z_i, so that z_k =
+// inv(T_kk) r_k, and precompute per block the coupling G_k = T[k, k-1]
+// inv(T_{k-1,k-1}), for which T[k, k-1] z_{k-1} = G_k r_{k-1}.  On entry
+//   - z_{j-2}, block [cb0, cb0+cm), is in sol (cm = 0 if j < 2);
+//   - r_{j-1} of block [pb0, pb0+pm) is in rin (pm = 0 if j < 1);
 //   - for every row of block j, the sum of T[i, k] z_k over the blocks k < j-2
 //     is in bsum_in as nci chunk sums (nci = 0 if j < 3).
-// The launch
-//   (a) for every row i of block j+1 (if any), sums T[i, k] z_k over the
-//       blocks k <= j-2, whose solutions are in sol: columns [bc0, bc0+bk)
-//       in chunks of kc, one chunk sum per (row, chunk) into bsum_out;
-//   (b) sums z_{j-1} from its partials (thread block 0 also stores it in sol),
-//       and solves block j: r = rhs_j - (its chunk sums) - T[j, j-2] z_{j-2}
-//       - T[j, j-1] z_{j-1}, z_j = inv(T_jj) r, left as partial products: the
-//       first kTrsvGroupsH thread blocks own 16 rows each; after forming them
-//       they write inv(T_jj)[:, 16g:16g+16] r_g into part_out[g][:].
-// The next launch (the same-stream kernel boundary orders the two) sums them.
-// Row i of block j thus receives rhs_i minus the sum over k < j of T[i, k]
-// z_k, the terms grouped as (chunks of the blocks < j-2), block j-2, block
-// j-1.  The update reads of (a) run along factor rows, kc contiguous entries
-// per wave, so each launch streams whole row segments rather than a strip of
-// one block column.  An entry with nm = 0 only stores z_{j-1} (one thread
-// block; the end of a sweep).  No thread block waits on another; the right-
-// hand sides are only read.
+// The launch has three kinds of work items, numbered in this order:
+//   (1) reduction items, 16 rows of block j each:
+//       r_j = rhs_j - (its chunk sums) - T[j, j-2] z_{j-2} - G_j r_{j-1},
+//       written to rout (the next step's rin);
+//   (2) solution items, 16 rows of block j-1 each: z_{j-1} = inv(T_{j-1,j-1})
+//       r_{j-1}, written to sol;
+//   (3) chunk-sum items: for the rows of block j+1 (if any), the sums of
+//       T[i, k] z_k over the blocks k <= j-2 (solutions in sol), columns
+//       [bc0, bc0+bk) in chunks of kTrsvSumCols, into bsum_out.
+// Only (1) is on the step-to-step chain: one stage of loads, one barrier and
+// one dot product per row.  The update reads of (3) run along factor rows,
+// so each launch streams whole row segments rather than a strip of one block
+// column.  An entry with nm = 0 (the end of a sweep) has only solution items.
+// No thread block waits on another; the right-hand sides are only read.
 constexpr int kTrsvGroups = kTrsvGroupsH;
 constexpr int kTrsvCol = kTrsvNB / 64;   // column chunks of 64 per row
-constexpr int kTrsvHS = 1024 / kTrsvNB;  // thread groups sharing a group's 16 columns of inv(T_nn)
-constexpr int kTrsvCPH = 16 / kTrsvHS;   // columns per thread group
 
 // Loads in these kernels are unconditional, from addresses clamped into the
 // domain's arrays, with out-of-range values zeroed afterwards: a load under a
 // branch is waited for inside the branch, which would serialise the loads.
 __device__ __forceinline__ int clampi(int v, int hi) { return max(0, min(v, hi)); }
 
-// z_{j-2} of vector q at t = tid mod kTrsvNB, from sol (zero past cm).  All
-// threads load (the same addresses four times over), so that no branch waits
-// for the load before the factor loads that follow are issued.
+// A block-length vector (m entries at src_q, zero past m) of each of NV
+// vectors into shared memory.  All threads load (the same addresses
+// 1024 / kTrsvNB times over) so that no branch waits for the load before
+// the loads that follow are issued; threads below kTrsvNB store.
 template <int NV>
-struct TrsvOld {
+struct TrsvVec {
   dz v[NV];
-  __device__ __forceinline__ void fetch(const TrsvDom &D) {
+  template <class Src>
+  __device__ __forceinline__ void fetch(Src src, int m) {
     const int t = threadIdx.x & (kTrsvNB - 1);
-    const int c = D.cb0 + clampi(t, D.cm - 1);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = D.sol[q][c];
+    for (int q = 0; q < NV; ++q) v[q] = src(q)[clampi(t, m - 1)];
   }
-  __device__ __forceinline__ void store(const TrsvDom &D, dz (*zo)[kTrsvNB]) const {
+  __device__ __forceinline__ void store(dz *dst, int m) const {   // dst[q * kTrsvNB + t]
     const int t = threadIdx.x;
     if (t >= kTrsvNB) return;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) zo[q][t] = t < D.cm ? v[q] : mk(0, 0);
+    for (int q = 0; q < NV; ++q) dst[q * kTrsvNB + t] = t < m ? v[q] : mk(0, 0);
   }
 };
 
-// z_{j-1} of vector q at t = tid mod kTrsvNB from its kTrsvGroups partials:
-// thread group h = tid / kTrsvNB sums partials kTrsvHS h .. kTrsvHS h + 3 in
-// order, the four group sums are added in group order through shared memory
-// (zero past pm), and thread block 0 of the domain stores z_{j-1} in sol.
-static_assert(kTrsvGroups == 4 * kTrsvHS, "four thread groups of kTrsvHS partials each");
-template <int NV>
-struct TrsvNew {
-  dz p[NV][kTrsvHS];
-  __device__ __forceinline__ void fetch(const TrsvDom &D) {
-    const int t = threadIdx.x & (kTrsvNB - 1), h = threadIdx.x / kTrsvNB;
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-#pragma unroll
-      for (int k = 0; k < kTrsvHS; ++k) p[q][k] = D.part_in[q * kTrsvPart + (kTrsvHS * h + k) * kTrsvNB + t];
-  }
-  // red: kTrsvHS x kTrsvNB scratch per vector; a barrier follows before zn is read
-  __device__ __forceinline__ void store(const TrsvDom &D, int blk, dz (*zn)[kTrsvNB],
-                                        dz (*red)[kTrsvHS][kTrsvNB]) const {
-    const int t = threadIdx.x & (kTrsvNB - 1), h = threadIdx.x / kTrsvNB;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      dz z = p[q][0];
-#pragma unroll
-      for (int k = 1; k < kTrsvHS; ++k) z = z + p[q][k];
-      red[q][h][t] = z;
-    }
-    __syncthreads();
-    if (threadIdx.x >= kTrsvNB) return;
-    const bool ok = t < D.pm;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      dz z = red[q][0][t];
-#pragma unroll
-      for (int k = 1; k < 4; ++k) z = z + red[q][k][t];
-      if (!ok) z = mk(0, 0);
-      if (ok && blk == 0) D.sol[q][D.pb0 + t] = z;
-      zn[q][t] = z;
-    }
-  }
-};
-
-// Shared memory of a step's thread block: the chain items use zo, zn, rg and
-// red, the chunk items the chunk's solutions; one array serves both.
+// Shared memory of a step's thread block: reduction and solution items use
+// two block-length vectors per right-hand side, chunk-sum items the chunk's
+// solutions; one array serves all.
 template <int NV, int KC>
 struct TrsvLds {
-  static constexpr int kChain = NV * (2 * kTrsvNB + 16 + kTrsvHS * kTrsvNB);
+  static constexpr int kChain = 2 * NV * kTrsvNB;
   static constexpr int kChunk = NV * KC;
   static constexpr int kSize = kChain > kChunk ? kChain : kChunk;
 };
 
-// KC columns per chunk sum (the autotuner picks 1024 or 2048 per context).
-// NV right-hand sides (1 or 2) share each read of the factors; vector q's
-// sums run in the same order for any NV.
+// KC columns per chunk-sum item (the autotuner picks 1024 or 2048 per
+// context; the sums are the same).  NV right-hand sides (1 or 2) share each
+// read of the factors; vector q's sums run in the same order for any NV.
 template <typename C, int KC, int NV, typename ST = TrsvStep>
 __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   static_assert(KC % 1024 == 0, "chunk staging: whole passes of 1024 threads");
   __shared__ dz sm[TrsvLds<NV, KC>::kSize];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // the work item's domain: the last whose first chain (or chunk-sum) item is <= vb
-  const bool chain = vb < st.chain_blocks;
+  // the item's kind and domain: the last entry whose first item of that kind is <= vb
+  const int kind = vb < st.chain_blocks ? 0 : (vb < st.z_end ? 1 : 2);
   int d = 0;
   for (int lo = 0, hi = st.ndom - 1; lo <= hi;) {
     const int mid = (lo + hi) >> 1;
-    if ((chain ? st.d[mid].first_block : st.d[mid].first_bulk) <= vb) {
+    const TrsvDom &M = st.d[mid];
+    if ((kind == 0 ? M.first_block : kind == 1 ? M.first_z : M.first_bulk) <= vb) {
       d = mid;
       lo = mid + 1;
     } else {
@@ -1238,99 +1261,103 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   }
   const TrsvDom &D = st.d[d];
   if (D.active && !*D.active) return;   // (fused batch) a cell whose Arnoldi steps are paused
-  const int blk = chain ? vb - D.first_block : kTrsvGroups + (vb - D.first_bulk);
+  const int blk = vb - (kind == 0 ? D.first_block : kind == 1 ? D.first_z : D.first_bulk);
   const int64_t ld = D.ld;
   const C *__restrict__ F = (const C *)D.F;
-  dz(*zo)[kTrsvNB] = reinterpret_cast<dz(*)[kTrsvNB]>(sm);
-  dz(*zn)[kTrsvNB] = reinterpret_cast<dz(*)[kTrsvNB]>(sm + NV * kTrsvNB);
-  dz(*rg)[16] = reinterpret_cast<dz(*)[16]>(sm + 2 * NV * kTrsvNB);
-  dz(*red)[kTrsvHS][kTrsvNB] = reinterpret_cast<dz(*)[kTrsvHS][kTrsvNB]>(sm + 2 * NV * kTrsvNB + 16 * NV);
-  if (D.nm == 0) {   // end of a sweep: only the last block's solution
-    TrsvNew<NV> pn;
-    pn.fetch(D);
-    pn.store(D, blk, zn, red);
-    return;
-  }
-  if (blk < kTrsvGroups) {
-    const int cb0 = D.cb0, cm = D.cm, pb0 = D.pb0, pm = D.pm, nb0 = D.nb0, nm = D.nm;
-    const int g = blk;
-    // every load is issued before the first wait: z_{j-2}, the partials of
-    // z_{j-1} (into shared memory once they arrive), the row of group g this
-    // wave solves (its entries in blocks j-2 and j-1), its rhs, this thread's
-    // four entries of the DT slice and the row's chunk sums
-    TrsvOld<NV> po;
-    TrsvNew<NV> pn;
-    po.fetch(D);
-    pn.fetch(D);
-    const int r = 16 * g + wave;
-    // (kept in the factor type until used: registers bound the occupancy)
+  if (kind == 0) {
+    // (1) row r of block j, one per wave: every load is issued before the
+    // barrier (the row's rhs, its entries in block j-2, row r of G_j, its
+    // chunk sums, z_{j-2} and r_{j-1} for shared memory)
+    const int cb0 = D.cb0, cm = D.cm, pm = D.pm, nb0 = D.nb0, nm = D.nm;
+    const int r = 16 * blk + wave;
     const int ic = nb0 + clampi(r, nm - 1);
-    C fo[kTrsvCol], fn[kTrsvCol];
+    dz *zo = sm, *zn = sm + NV * kTrsvNB;
+    TrsvVec<NV> po, pn;
+    po.fetch([&](int q) { return D.sol[q] + cb0; }, cm);
+    pn.fetch([&](int q) { return D.rin + q * kTrsvNB; }, pm);
     dz rv[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) rv[q] = D.rhs[q][ic];
+    // (kept in the factor type until used: registers bound the occupancy)
+    const C *__restrict__ G = (const C *)D.G + (int64_t)clampi(r, kTrsvNB - 1) * kTrsvNB;
+    C fo[kTrsvCol], fg[kTrsvCol];
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c) {
       fo[c] = F[(int64_t)ic * ld + cb0 + clampi(lane + 64 * c, cm - 1)];
-      fn[c] = F[(int64_t)ic * ld + pb0 + clampi(lane + 64 * c, pm - 1)];
+      fg[c] = G[lane + 64 * c];
     }
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c) {
       if (!(lane + 64 * c < cm)) fo[c] = cx<C>::make(0, 0);
-      if (!(lane + 64 * c < pm)) fn[c] = cx<C>::make(0, 0);
+      if (!(lane + 64 * c < pm)) fg[c] = cx<C>::make(0, 0);
     }
-    const int oi = tid & (kTrsvNB - 1), h = tid / kTrsvNB;   // group h takes columns 16 g + kTrsvCPH h ..
-    const C *col = (const C *)D.DT + (int64_t)(16 * g + kTrsvCPH * h) * kTrsvNB + oi;
-    C dt[kTrsvCPH];
-#pragma unroll
-    for (int l = 0; l < kTrsvCPH; ++l) dt[l] = col[(int64_t)l * kTrsvNB];
-    // chunk sums of row r: lane l takes chunks l and l + 64 (bst <= 128)
+    // chunk sums of row r: lane l takes chunks l and l + 64 (bst <= 128; the
+    // second only for domains of more than 64 chunks, under a uniform branch)
     dz bs[NV];
-    {
-      const int bst = D.bst, nci = D.nci;
-      const dz *bp = D.bsum_in + (int64_t)clampi(r, kTrsvNB - 1) * bst;
+    const int bst = D.bst, nci = D.nci;
+    const dz *bp = D.bsum_in + (int64_t)clampi(r, kTrsvNB - 1) * bst;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const dz b0 = bp[(int64_t)q * kTrsvNB * bst + clampi(lane, bst - 1)];
+      bs[q] = lane < nci ? b0 : mk(0, 0);
+    }
+    if (nci > 64) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
-        const dz b0 = bp[(int64_t)q * kTrsvNB * bst + clampi(lane, bst - 1)];
         const dz b1 = bp[(int64_t)q * kTrsvNB * bst + clampi(lane + 64, bst - 1)];
-        bs[q] = (lane < nci ? b0 : mk(0, 0)) + (lane + 64 < nci ? b1 : mk(0, 0));
+        bs[q] = bs[q] + (lane + 64 < nci ? b1 : mk(0, 0));
       }
     }
-    po.store(D, zo);
-    pn.store(D, blk, zn, red);
+    po.store(zo, cm);
+    pn.store(zn, pm);
     __syncthreads();
-    // (b) for the 16 rows of group g, one row per wave: the chunk sums, then
-    // the updates of blocks j-2 and j-1, in that order
+    // the chunk sums, then the updates of blocks j-2 and j-1, in that order
+    dz rg[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       dz so = mk(0, 0), sn = mk(0, 0);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) so = so + to_dz(fo[c]) * zo[q][lane + 64 * c];
+      for (int c = 0; c < kTrsvCol; ++c) cmac(so, to_dz(fo[c]), zo[q * kTrsvNB + lane + 64 * c]);
 #pragma unroll
-      for (int c = 0; c < kTrsvCol; ++c) sn = sn + to_dz(fn[c]) * zn[q][lane + 64 * c];
+      for (int c = 0; c < kTrsvCol; ++c) cmac(sn, to_dz(fg[c]), zn[q * kTrsvNB + lane + 64 * c]);
       const dz sb = wave_sum_dpp(bs[q]);
       so = wave_sum_dpp(so);
       sn = wave_sum_dpp(sn);
-      if (lane == 0) rg[q][wave] = r < nm ? ((rv[q] - sb) - so) - sn : mk(0, 0);
+      rg[q] = ((rv[q] - sb) - so) - sn;
     }
+    if (lane == 0 && r < nm) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) D.rout[q * kTrsvNB + r] = rg[q];
+    }
+    return;
+  }
+  if (kind == 1) {
+    // (2) row o of inv(T_{j-1,j-1}), one per wave, against r_{j-1}
+    const int pb0 = D.pb0, pm = D.pm;
+    const int o = 16 * blk + wave;
+    dz *zn = sm;
+    TrsvVec<NV> pn;
+    pn.fetch([&](int q) { return D.rin + q * kTrsvNB; }, pm);
+    const C *__restrict__ IV = (const C *)D.INV + (int64_t)clampi(o, kTrsvNB - 1) * kTrsvNB;
+    C fi[kTrsvCol];
+#pragma unroll
+    for (int c = 0; c < kTrsvCol; ++c) fi[c] = IV[lane + 64 * c];
+#pragma unroll
+    for (int c = 0; c < kTrsvCol; ++c)
+      if (!(lane + 64 * c < pm)) fi[c] = cx<C>::make(0, 0);
+    pn.store(zn, pm);
     __syncthreads();
-    // partial product with columns 16 g .. 16 g + 15 of inv(T_jj)
+    dz zq[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      dz acc = to_dz(dt[0]) * rg[q][kTrsvCPH * h];
+      dz a = mk(0, 0);
 #pragma unroll
-      for (int l = 1; l < kTrsvCPH; ++l) acc = acc + to_dz(dt[l]) * rg[q][kTrsvCPH * h + l];
-      red[q][h][oi] = acc;
+      for (int c = 0; c < kTrsvCol; ++c) cmac(a, to_dz(fi[c]), zn[q * kTrsvNB + lane + 64 * c]);
+      zq[q] = wave_sum_dpp(a);
     }
-    __syncthreads();
-    if (tid < kTrsvNB) {
+    if (lane == 0 && o < pm) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        dz z = red[q][0][tid];
-#pragma unroll
-        for (int p = 1; p < kTrsvHS; ++p) z = z + red[q][p][tid];
-        D.part_out[q * kTrsvPart + g * kTrsvNB + tid] = z;
-      }
+      for (int q = 0; q < NV; ++q) D.sol[q][pb0 + o] = zq[q];
     }
     return;
   }
@@ -1340,7 +1367,7 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   // clamped factor reads add 0).  Each kTrsvSumCols columns give one chunk
   // sum: lane sums in column order, then the wave sum.
   static_assert(KC % kTrsvSumCols == 0 && kTrsvSumCols == 1024, "chunks of one pass of 1024 threads");
-  const int b = blk - kTrsvGroups;
+  const int b = blk;
   const int ch = b / D.nrg, rgp = b - ch * D.nrg;
   const int cs = D.bc0 + ch * KC;
   const int cn = min(KC, D.bc0 + D.bk - cs);
@@ -1413,17 +1440,19 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   flush(KC / kTrsvSumCols - 1);
 }
 
-#define VIE_TRSV_STEP(T, C, K)                                                                  \
-  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_k##K(TrsvStep st) {                \
+// W: waves per SIMD the compiler keeps room for (8: two thread blocks of 1024
+// per CU; the FP32-factor kernels with 1024-column items fit it)
+#define VIE_TRSV_STEP(T, C, K, W)                                                                \
+  __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(W))) void k_trsv_step_##T##_k##K(TrsvStep st) { \
     trsv_step_body<C, K, 1>(st, blockIdx.x);                                                  \
   }                                                                                           \
-  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_k##K(TrsvStep st) {               \
+  __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(W))) void k_trsv_step2_##T##_k##K(TrsvStep st) { \
     trsv_step_body<C, K, 2>(st, blockIdx.x);                                                  \
   }
-VIE_TRSV_STEP(z, dz, 1024)
-VIE_TRSV_STEP(z, dz, 2048)
-VIE_TRSV_STEP(c, fz, 1024)
-VIE_TRSV_STEP(c, fz, 2048)
+VIE_TRSV_STEP(z, dz, 1024, 4)
+VIE_TRSV_STEP(z, dz, 2048, 4)
+VIE_TRSV_STEP(c, fz, 1024, 8)
+VIE_TRSV_STEP(c, fz, 2048, 4)
 
 // Every step of the triangular solves in one cooperative launch: the thread
 // blocks share each step's work items (the same items the per-step launches
@@ -1448,12 +1477,12 @@ __device__ __forceinline__ void trsv_coop_body(const TrsvStep *__restrict__ plan
 // step's domains of every cell, read from device memory.
 struct TrsvStepDev {
   const TrsvDom *d;
-  int ndom, lower, chain_blocks;
+  int ndom, lower, chain_blocks, z_end;
 };
 #define VIE_TRSV_STEPD(T, C)                                                                      \
   __global__ __launch_bounds__(1024) void k_trsv_stepd_##T(const TrsvDom *doms, int ndom, int lower,   \
-                                                            int chain_blocks) {                        \
-    const TrsvStepDev st{doms, ndom, lower, chain_blocks};                                            \
+                                                            int chain_blocks, int z_end) {             \
+    const TrsvStepDev st{doms, ndom, lower, chain_blocks, z_end};                                     \
     trsv_step_body<C, kTrsvSumCols, 1, TrsvStepDev>(st, blockIdx.x);                             \
   }
 VIE_TRSV_STEPD(z, dz)

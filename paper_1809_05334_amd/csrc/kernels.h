@@ -177,10 +177,13 @@ VIE_DECL_LU(c)
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
 __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *Dinv);
+// coupling blocks G_b = T[b, b-dir] inv(T_{b-dir,b-dir}) of one domain's L (dir 1) or
+// U (dir -1) sweep, b = blocks 1 .. nb-1 of the sweep (k_lu.hip)
+__global__ void k_trsv_coupling_z(const dz *F, int64_t ld, int n, int lower, const dz *INV, dz *G);
+__global__ void k_trsv_coupling_c(const fz *F, int64_t ld, int n, int lower, const fz *INV, fz *G);
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
 // domains by one diagonal block each (k_lu.hip).
-constexpr int kTrsvGroupsH = kTrsvNB / 16;   // thread blocks that solve a domain's next diagonal block
-constexpr int kTrsvPart = kTrsvGroupsH * kTrsvNB;   // partial products of one vector
+constexpr int kTrsvGroupsH = kTrsvNB / 16;   // work items of 16 rows per diagonal block
 constexpr int kTrsvMaxDom = 8;
 // Row sums over the solved columns come in chunks of kTrsvSumCols columns
 // (a work item covers kc = 1024 or 2048 columns, one or two chunks, with the
@@ -190,12 +193,12 @@ constexpr int kTrsvSumCols = 1024;
 constexpr int kTrsvChunksMax = 128;
 struct TrsvDom {
   const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
-  const void *DT;     // transposed inverse of the next diagonal block (kTrsvNB x kTrsvNB, same type)
+  const void *G;      // coupling block of block j: T[j, j-1] inv(T_{j-1,j-1}) (kTrsvNB x kTrsvNB, row-major)
+  const void *INV;    // inv(T_{j-1,j-1}) (kTrsvNB x kTrsvNB, row-major, zero past its size)
   const dz *rhs[2];   // right-hand sides, domain-local, per vector (read only)
   dz *sol[2];         // solutions, domain-local, per vector
-  const dz *part_in;  // partial products of the previous block's solution (kTrsvGroupsH x kTrsvNB
-                      // per vector, vector q at q * kTrsvPart), written by the previous step
-  dz *part_out;       // the same for this step's diagonal block, read by the next step
+  const dz *rin;      // r_{j-1}, the previous block's reduced right-hand side (vector q at q * kTrsvNB)
+  dz *rout;           // r_j, written by this step
   // chunk sums over the solved columns: for row i of a block, chunk c of vector q at
   // q * kTrsvNB * bst + i * bst + c.  bsum_in holds nci chunks for this step's block
   // (written by the previous step); bsum_out receives those of the next block
@@ -203,42 +206,50 @@ struct TrsvDom {
   dz *bsum_out;
   int64_t ld;
   // blocks of the step: [cb0, cb0+cm) two back (solution in sol), [pb0, pb0+pm) the previous one
-  // (solution in part_in), [nb0, nb0+nm) the one solved; nm = 0: only store the previous block's solution
+  // (its r in rin), [nb0, nb0+nm) the one reduced; nm = 0: only solve the previous block
   int n, cb0, cm, pb0, pm, nb0, nm;
-  // the entry's work items: its chain items (the diagonal block) from first_block,
-  // its chunk-sum items from first_bulk; every chain item of a step precedes
-  // every chunk-sum item, so the chain starts with the launch
-  int first_block, first_bulk;
   // the next block's rows [br0, br0+brm) against the solved columns [bc0, bc0+bk):
   // nrg groups of 16 rows times nco work items of kc columns (brm = 0: none)
   int bst, nci, br0, brm, bc0, bk, nrg, nco;
+  // the entry's work items: reduction items (block j) from first_block, solution
+  // items (block j-1) from first_z, chunk-sum items from first_bulk; a step numbers
+  // every entry's reduction items first, then the solution items, then the chunk sums
+  int first_block, first_z, first_bulk;
   const int *active;  // (fused batch) the cell's flag: 0 skips the domain; nullptr always runs
 };
 // chunk sums per row of a domain of n unknowns (the row stride bst)
 inline int trsv_bsum_stride(int64_t n) { return (int)std::max<int64_t>(1, (n + kTrsvSumCols - 1) / kTrsvSumCols); }
-// work items of one domain's entry in a step: chain items, chunk-sum items
-inline int trsv_chain_items(const TrsvDom &D) { return D.nm == 0 ? 1 : kTrsvGroupsH; }
-inline int trsv_bulk_items(const TrsvDom &D) { return D.nm == 0 ? 0 : D.nrg * D.nco; }
-// first_block / first_bulk of entries d[0 .. nd), chain items first; returns
-// the chain items, *total the work items of the step
-inline int trsv_number_items(TrsvDom *d, int nd, int *total) {
+// work items of one domain's entry in a step
+inline int trsv_chain_items(const TrsvDom &D) { return D.nm > 0 ? kTrsvGroupsH : 0; }
+inline int trsv_z_items(const TrsvDom &D) { return D.pm > 0 ? kTrsvGroupsH : 0; }
+inline int trsv_bulk_items(const TrsvDom &D) { return D.nm > 0 ? D.nrg * D.nco : 0; }
+// first_block / first_z / first_bulk of entries d[0 .. nd) in that order; returns
+// the reduction items, *zend the end of the solution items, *total every item
+inline int trsv_number_items(TrsvDom *d, int nd, int *zend, int *total) {
   int c = 0;
   for (int i = 0; i < nd; ++i) {
     d[i].first_block = c;
     c += trsv_chain_items(d[i]);
   }
-  int b = c;
+  int z = c;
+  for (int i = 0; i < nd; ++i) {
+    d[i].first_z = z;
+    z += trsv_z_items(d[i]);
+  }
+  int b = z;
   for (int i = 0; i < nd; ++i) {
     d[i].first_bulk = b;
     b += trsv_bulk_items(d[i]);
   }
+  *zend = z;
   *total = b;
   return c;
 }
 struct TrsvStep {
   TrsvDom d[kTrsvMaxDom];
   int ndom, lower;
-  int chain_blocks;   // work items of the diagonal blocks, numbered first
+  int chain_blocks;   // reduction items, numbered first
+  int z_end;          // end of the solution items
   int total_blocks;   // thread blocks (work items) of the step over all its domains
 };
 // variants by factor type (_z FP64, _c FP32) and columns per work item
@@ -253,8 +264,8 @@ struct TrsvStep {
 // k_trsv_stepd_*: one step of a batch's fused solves, one vector per cell,
 // the step's domains (any number) read from device memory; work items of
 // kTrsvSumCols columns
-__global__ void k_trsv_stepd_z(const TrsvDom *doms, int ndom, int lower, int chain_blocks);
-__global__ void k_trsv_stepd_c(const TrsvDom *doms, int ndom, int lower, int chain_blocks);
+__global__ void k_trsv_stepd_z(const TrsvDom *doms, int ndom, int lower, int chain_blocks, int z_end);
+__global__ void k_trsv_stepd_c(const TrsvDom *doms, int ndom, int lower, int chain_blocks, int z_end);
 VIE_DECL_TRSV(z, 1024)
 VIE_DECL_TRSV(z, 2048)
 VIE_DECL_TRSV(c, 1024)
