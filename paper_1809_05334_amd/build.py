@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvie.so")
 ROOT = os.path.dirname(HERE)
 
-HIP_SOURCES = ["k_fill.hip", "k_lu.hip", "k_krylov.hip", "k_absorb.hip", "api.cpp", "batch.cpp"]
+HIP_SOURCES = ["k_fill.hip", "k_lu.hip", "k_trsv.hip", "k_krylov.hip", "k_absorb.hip", "api.cpp", "batch.cpp"]
 HOST_SOURCES = ["topology.cpp", "tables.cpp"]
 ARCH = os.environ.get("VIE_OFFLOAD_ARCH", "gfx950")
 

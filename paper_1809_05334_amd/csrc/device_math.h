@@ -30,6 +30,19 @@ __device__ __forceinline__ void axpy(dz &acc, double s, dz a) {
   acc.re = fma(s, a.re, acc.re);
   acc.im = fma(s, a.im, acc.im);
 }
+// 64-bit DPP lane move (CTRL: a row-local permutation) and lane read, as two
+// 32-bit halves
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)v, (int)(unsigned)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(v >> 32), (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
 // acc += a * b with each real product fused into the accumulator (four FMAs,
 // no separate product to keep live)
 __device__ __forceinline__ void cmac(dz &acc, dz a, dz b) {

@@ -119,7 +119,7 @@ __global__ void k_rhs(int64_t N, const int32_t *utet, const int32_t *uk, const T
 __global__ void k_pgf_probe(const double *pack, int packlen, const double *d, int64_t n, dz *out);
 __global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
-// block LU and its application (k_lu.hip)
+// block LU (k_lu.hip) and its application (k_trsv.hip)
 constexpr int kTrsvNB = 256;                   // diagonal-block size of the triangular solves
 constexpr int kInvColsH = 8192 / kTrsvNB;      // columns of one inverse per k_diag_inv block (128 KB of LDS)
 // FP64 (_z) and FP32 (_c) factor storage
@@ -174,15 +174,16 @@ struct LuStep {
 VIE_DECL_LU(z)
 VIE_DECL_LU(c)
 #undef VIE_DECL_LU
+// (k_trsv.hip)
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
 __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *Dinv);
 // coupling blocks G_b = T[b, b-dir] inv(T_{b-dir,b-dir}) of one domain's L (dir 1) or
-// U (dir -1) sweep, b = blocks 1 .. nb-1 of the sweep (k_lu.hip)
+// U (dir -1) sweep, b = blocks 1 .. nb-1 of the sweep (k_trsv.hip)
 __global__ void k_trsv_coupling_z(const dz *F, int64_t ld, int n, int lower, const dz *INV, dz *G);
 __global__ void k_trsv_coupling_c(const fz *F, int64_t ld, int n, int lower, const fz *INV, fz *G);
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
-// domains by one diagonal block each (k_lu.hip).
+// domains by one diagonal block each (k_trsv.hip).
 constexpr int kTrsvGroupsH = kTrsvNB / 16;   // work items of 16 rows per diagonal block
 constexpr int kTrsvMaxDom = 8;
 // Row sums over the solved columns come in chunks of kTrsvSumCols columns
