@@ -118,15 +118,23 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   }
   const size_t fes = mixed ? 8 : 16;   // factor element: complex FP32 in mixed precision
   put(L.F, fes * (size_t)std::max<int64_t>(1, fel));
+  // per domain: the L then the U inverses of its diagonal blocks (block b at b nb^2, the
+  // last one m x m), and the L then the U coupling blocks (nbk - 1 per sweep, nb^2 each)
   L.doff.resize(t.ndom);
-  int64_t del = 0;
+  L.goff.resize(t.ndom);
+  int64_t del = 0, gel = 0;
   for (int d = 0; d < t.ndom; ++d) {
-    int64_t n = t.dend[d] - t.dstart[d];
+    const int64_t n = t.dend[d] - t.dstart[d];
+    const int64_t nbk = (n + kTrsvNB - 1) / kTrsvNB;
     L.doff[d] = del;
-    del += 2 * ((n + kTrsvNB - 1) / kTrsvNB) * kTrsvNB * kTrsvNB;   // L then U inverses
+    L.goff[d] = gel;
+    if (nbk == 0) continue;
+    const int64_t mlast = n - (nbk - 1) * kTrsvNB;
+    del += 2 * ((nbk - 1) * kTrsvNB * kTrsvNB + mlast * mlast);
+    gel += 2 * (nbk - 1) * kTrsvNB * kTrsvNB;
   }
   put(L.dinv, fes * (size_t)std::max<int64_t>(1, del));
-  put(L.gcpl, fes * (size_t)std::max<int64_t>(1, del));   // coupling blocks, laid out as the inverses
+  put(L.gcpl, fes * (size_t)std::max<int64_t>(1, gel));
   put(L.trr, 16 * 4 * (size_t)kTrsvNB * std::max(1, t.ndom));   // r of a block: two buffers of two vectors per domain
   // chunk sums: per domain two buffers (steps alternate) of two vectors, kTrsvNB rows each
   L.boff.resize(t.ndom);
@@ -1189,10 +1197,11 @@ int factor_finish(vie_ctx *ctx, const std::vector<LuDom> &doms) {
     const int n = doms[d].n;
     if (n == 0) continue;
     const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
+    const int64_t mlast = n - (int64_t)(nbk - 1) * kTrsvNB;
     void *DL = factor_ptr(ctx, L.dinv, L.doff[d]);
-    void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
-    void *GL = factor_ptr(ctx, L.gcpl, L.doff[d]);
-    void *GU = factor_ptr(ctx, L.gcpl, L.doff[d] + (int64_t)nbk * kTrsvNB * kTrsvNB);
+    void *DU = factor_ptr(ctx, L.dinv, L.doff[d] + (int64_t)(nbk - 1) * kTrsvNB * kTrsvNB + mlast * mlast);
+    void *GL = factor_ptr(ctx, L.gcpl, L.goff[d]);
+    void *GU = factor_ptr(ctx, L.gcpl, L.goff[d] + (int64_t)(nbk - 1) * kTrsvNB * kTrsvNB);
     const dim3 ig(nbk, kTrsvNB / kInvColsH), ib(4 * kInvColsH);   // kInvColsH columns of one inverse per block
     const dim3 cg(nbk - 1, (kTrsvNB / 64) * (kTrsvNB / 64)), cb(256);   // 64 x 64 tiles of each coupling block
     if (f32) {
@@ -1328,7 +1337,8 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
         const int nbk = (n + kTrsvNB - 1) / kTrsvNB;
         if (nbk == 0 || (k >= nbk && k < maxnbk)) continue;
         const int64_t off = t.dstart[d];
-        const int64_t dl = L.doff[d];
+        const int64_t mlast = n - (int64_t)(nbk - 1) * kTrsvNB;
+        const int64_t isz = (int64_t)(nbk - 1) * kTrsvNB * kTrsvNB + mlast * mlast;   // inverses of one sweep
         TrsvDom &D = st.d[st.ndom];
         D.F = factor_ptr(ctx, L.F, L.foff[d]);
         D.ld = L.fld[d];
@@ -1338,9 +1348,13 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
           D.sol[q] = (lower ? s2[q] : out[q]) + off;
         }
         D.bst = trsv_bsum_stride(n);
-        // inverse and coupling block of matrix block b of this sweep
-        auto blockof = [&](Region R, int b) {
-          return factor_ptr(ctx, R, dl + (int64_t)(lower ? b : nbk + b) * kTrsvNB * kTrsvNB);
+        // inverse of matrix block b of this sweep, and its coupling block (L: b >= 1, U: b <= nbk - 2)
+        auto invof = [&](int b) {
+          return factor_ptr(ctx, L.dinv, L.doff[d] + (lower ? 0 : isz) + (int64_t)b * kTrsvNB * kTrsvNB);
+        };
+        auto cplof = [&](int b) {
+          const int64_t slot = lower ? b - 1 : (nbk - 1) + b;
+          return factor_ptr(ctx, L.gcpl, L.goff[d] + slot * kTrsvNB * kTrsvNB);
         };
         if (k == maxnbk) {
           // the end of the domain's sweep: the solution of its last block
@@ -1350,8 +1364,9 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
           D.cb0 = D.cm = D.nb0 = D.nm = 0;
           D.rin = rbuf(d, nbk - 1);
           D.rout = nullptr;
-          D.INV = blockof(L.dinv, bk);
-          D.G = D.INV;
+          D.INV = invof(bk);
+          D.G = D.F;   // (unused: no reduction items)
+          D.gld = 0;
           D.bsum_in = D.bsum_out = bbuf(d, 0);
           if (++st.ndom == kTrsvMaxDom) push();
           continue;
@@ -1367,9 +1382,10 @@ std::vector<TrsvStep> trsv_plan(vie_ctx *ctx, int nv, dz *const *out, dz *const 
         D.pm = k >= 1 ? std::min(kTrsvNB, n - D.pb0) : 0;
         D.cb0 = k >= 2 ? (bk + 2 * dir) * kTrsvNB : 0;
         D.cm = k >= 2 ? std::min(kTrsvNB, n - D.cb0) : 0;
-        // (k = 0: no previous block; the pointers stay valid, their entries masked)
-        D.G = blockof(L.gcpl, bk);
-        D.INV = blockof(L.dinv, k >= 1 ? bk + dir : bk);
+        // (k = 0: no previous block; G then reads one valid entry, masked)
+        D.G = k >= 1 ? cplof(bk) : D.F;
+        D.gld = k >= 1 ? kTrsvNB : 0;
+        D.INV = invof(k >= 1 ? bk + dir : bk);
         // block k's chunk sums over the blocks <= k - 3, from step k - 1
         D.bsum_in = bbuf(d, k - 1);
         const int kin = k >= 3 ? (lower ? (k - 2) * kTrsvNB : n - (nbk + 2 - k) * kTrsvNB) : 0;

@@ -46,6 +46,7 @@ struct Layout {
   int64_t ld = 0;
   std::vector<int64_t> fld, foff;  // per-domain factor leading dim and offset (elements)
   std::vector<int64_t> doff;       // per-domain offset of the diagonal-block inverses (elements)
+  std::vector<int64_t> goff;       // per-domain offset of the coupling blocks (elements)
   std::vector<int64_t> boff;       // per-domain offset of the triangular solves' chunk sums (elements)
   std::vector<int64_t> toff;       // per-domain offset of the tournament tree nodes (nodes)
   int restart = 0;

@@ -1,7 +1,7 @@
 // Application of the block-diagonal preconditioner of Sec. 2.3 (Eq. 6)
 // inside GMRES: z = A_dd^{-1} v for every material domain d, from the LU
 // factors of k_lu.hip, by a permutation and blocked forward (L, unit lower)
-// and backward (U) substitutions over 256-row diagonal blocks; the inverses
+// and backward (U) substitutions over 512-row diagonal blocks; the inverses
 // of the diagonal blocks and the coupling blocks the substitutions use are
 // formed once per factorisation.
 #include <hip/hip_cooperative_groups.h>
@@ -20,8 +20,9 @@ __global__ void k_permute(int n, int64_t off, const int32_t *__restrict__ perm, 
 }
 
 // Inverses of the kTrsvNB x kTrsvNB diagonal blocks of L (unit lower) and U
-// (upper), computed once per factorisation: block b of INV holds inv(T_bb)
-// row-major, T_bb the diagonal block at row b*nb, zero past its size.  A
+// (upper), computed once per factorisation: block b of INV, at b nb^2,
+// holds inv(T_bb) row-major with its own size m (nb but for a domain's last
+// block) as leading dimension, T_bb the diagonal block at row b*nb.  A
 // thread block forms 32 columns of one inverse by substitution; the columns
 // live in LDS, and each column's dot products are split over 4 lanes
 // (residues of the summation index mod 4, combined by shuffles).  A lane only
@@ -80,9 +81,9 @@ __device__ __forceinline__ void diag_inv_body(const C *__restrict__ F, int64_t l
     }
   }
   __syncthreads();
-  if (j < nb) {
-    C *inv_b = INV + (int64_t)b * nb * nb;   // the inverse of block b, row-major: its column j
-    for (int i = t; i < nb; i += 4) inv_b[(int64_t)i * nb + j] = cx<C>::of(X[cl][i]);
+  if (j < m) {
+    C *inv_b = INV + (int64_t)b * nb * nb;   // the inverse of block b, m x m row-major: its column j
+    for (int i = t; i < m; i += 4) inv_b[(int64_t)i * m + j] = cx<C>::of(X[cl][i]);
   }
 }
 
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(4 * kInvCols) void k_diag_inv_c(const fz *F, int64_
 // Coupling blocks of one domain's sweep: for the matrix blocks b that follow
 // another in the sweep's order (b >= 1 for L, b <= nbk - 2 for U), with p =
 // b - 1 (L) or b + 1 (U), G_b = T[b, p] inv(T_pp), a kTrsvNB x kTrsvNB
-// product in FP64 (rounded to the factor type), written at G + b nb^2.  A
+// product in FP64 (rounded to the factor type), written to slot b - 1 (L) or
+// b (U) of nb^2 entries, leading dimension nb.  A
 // thread block forms a 64 x 64 tile, 4 x 4 entries per thread, through
 // 16-deep slices of both operands in shared memory; entries past the blocks'
 // sizes are zero.
@@ -111,7 +113,7 @@ __device__ __forceinline__ void coupling_body(const C *__restrict__ F, int64_t l
   const int mr = min(nb, n - b0), mc = min(nb, n - p0);
   const int tr = blockIdx.y / (nb / TS), tc = blockIdx.y % (nb / TS);
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const C *__restrict__ Ip = INV + (int64_t)p * nb * nb;
+  const C *__restrict__ Ip = INV + (int64_t)p * nb * nb;   // mc x mc, leading dimension mc
   dz acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -128,7 +130,8 @@ __device__ __forceinline__ void coupling_body(const C *__restrict__ F, int64_t l
 #pragma unroll
     for (int e = tid; e < KS * TS; e += 256) {
       const int kk = e / TS, cc = e % TS;
-      Bs[kk][cc] = to_dz(Ip[(int64_t)(k0 + kk) * nb + tc * TS + cc]);
+      const int gk = k0 + kk, gc = tc * TS + cc;
+      Bs[kk][cc] = gk < mc && gc < mc ? to_dz(Ip[(int64_t)gk * mc + gc]) : mk(0, 0);
     }
     __syncthreads();
 #pragma unroll
@@ -145,7 +148,7 @@ __device__ __forceinline__ void coupling_body(const C *__restrict__ F, int64_t l
     }
     __syncthreads();
   }
-  C *__restrict__ Gb = G + (int64_t)b * nb * nb;
+  C *__restrict__ Gb = G + (int64_t)(lower ? b - 1 : b) * nb * nb;   // slots of the sweep's nbk - 1 blocks
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -294,12 +297,13 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) rv[q] = D.rhs[q][ic];
     // (kept in the factor type until used: registers bound the occupancy)
-    const C *__restrict__ G = (const C *)D.G + (int64_t)clampi(r, kTrsvNB - 1) * kTrsvNB;
+    const int gld = D.gld;
+    const C *__restrict__ G = (const C *)D.G + (int64_t)clampi(r, kTrsvNB - 1) * gld;
     C fo[kTrsvCol], fg[kTrsvCol];
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c) {
       fo[c] = F[(int64_t)ic * ld + cb0 + clampi(lane + 64 * c, cm - 1)];
-      fg[c] = G[lane + 64 * c];
+      fg[c] = G[gld > 0 ? lane + 64 * c : 0];
     }
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c) {
@@ -353,10 +357,10 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
     dz *zn = sm;
     TrsvVec<NV> pn;
     pn.fetch([&](int q) { return D.rin + q * kTrsvNB; }, pm);
-    const C *__restrict__ IV = (const C *)D.INV + (int64_t)clampi(o, kTrsvNB - 1) * kTrsvNB;
+    const C *__restrict__ IV = (const C *)D.INV + (int64_t)clampi(o, pm - 1) * pm;
     C fi[kTrsvCol];
 #pragma unroll
-    for (int c = 0; c < kTrsvCol; ++c) fi[c] = IV[lane + 64 * c];
+    for (int c = 0; c < kTrsvCol; ++c) fi[c] = IV[clampi(lane + 64 * c, pm - 1)];
 #pragma unroll
     for (int c = 0; c < kTrsvCol; ++c)
       if (!(lane + 64 * c < pm)) fi[c] = cx<C>::make(0, 0);
@@ -455,19 +459,17 @@ __device__ __forceinline__ void trsv_step_body(const ST &st, int vb) {
   flush(KC / kTrsvSumCols - 1);
 }
 
-// W: waves per SIMD the compiler keeps room for (8: two thread blocks of 1024
-// per CU; the FP32-factor kernels with 1024-column items fit it)
-#define VIE_TRSV_STEP(T, C, K, W)                                                                \
-  __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(W))) void k_trsv_step_##T##_k##K(TrsvStep st) { \
+#define VIE_TRSV_STEP(T, C, K)                                                                  \
+  __global__ __launch_bounds__(1024) void k_trsv_step_##T##_k##K(TrsvStep st) {                \
     trsv_step_body<C, K, 1>(st, blockIdx.x);                                                  \
   }                                                                                           \
-  __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(W))) void k_trsv_step2_##T##_k##K(TrsvStep st) { \
+  __global__ __launch_bounds__(1024) void k_trsv_step2_##T##_k##K(TrsvStep st) {               \
     trsv_step_body<C, K, 2>(st, blockIdx.x);                                                  \
   }
-VIE_TRSV_STEP(z, dz, 1024, 4)
-VIE_TRSV_STEP(z, dz, 2048, 4)
-VIE_TRSV_STEP(c, fz, 1024, 8)
-VIE_TRSV_STEP(c, fz, 2048, 4)
+VIE_TRSV_STEP(z, dz, 1024)
+VIE_TRSV_STEP(z, dz, 2048)
+VIE_TRSV_STEP(c, fz, 1024)
+VIE_TRSV_STEP(c, fz, 2048)
 
 // Every step of the triangular solves in one cooperative launch: the thread
 // blocks share each step's work items (the same items the per-step launches

@@ -120,7 +120,7 @@ __global__ void k_pgf_probe(const double *pack, int packlen, const double *d, in
 __global__ void k_gather(ZOut Z, const int64_t *rows, const int64_t *cols, int64_t k, dz *out);
 
 // block LU (k_lu.hip) and its application (k_trsv.hip)
-constexpr int kTrsvNB = 256;                   // diagonal-block size of the triangular solves
+constexpr int kTrsvNB = 512;                   // diagonal-block size of the triangular solves
 constexpr int kInvColsH = 8192 / kTrsvNB;      // columns of one inverse per k_diag_inv block (128 KB of LDS)
 // FP64 (_z) and FP32 (_c) factor storage
 __global__ void k_copy_block_z(ZOut Z, int64_t start, int n, dz *A, int64_t lda);
@@ -178,8 +178,8 @@ VIE_DECL_LU(c)
 __global__ void k_permute(int n, int64_t off, const int32_t *perm, const dz *v, dz *z);
 __global__ void k_diag_inv_z(const dz *F, int64_t ld, int n, int nb, int lower, dz *Dinv);
 __global__ void k_diag_inv_c(const fz *F, int64_t ld, int n, int nb, int lower, fz *Dinv);
-// coupling blocks G_b = T[b, b-dir] inv(T_{b-dir,b-dir}) of one domain's L (dir 1) or
-// U (dir -1) sweep, b = blocks 1 .. nb-1 of the sweep (k_trsv.hip)
+// coupling blocks G_b = T[b, p] inv(T_pp) of one domain's L (p = b - 1, b >= 1) or U
+// (p = b + 1, b <= nbk - 2) sweep, each kTrsvNB x kTrsvNB (k_trsv.hip)
 __global__ void k_trsv_coupling_z(const dz *F, int64_t ld, int n, int lower, const dz *INV, dz *G);
 __global__ void k_trsv_coupling_c(const fz *F, int64_t ld, int n, int lower, const fz *INV, fz *G);
 // One launch advances the blocked triangular solves of up to kTrsvMaxDom
@@ -194,8 +194,9 @@ constexpr int kTrsvSumCols = 1024;
 constexpr int kTrsvChunksMax = 128;
 struct TrsvDom {
   const void *F;      // the domain's LU factors (dz or fz, row-major, leading dimension ld)
-  const void *G;      // coupling block of block j: T[j, j-1] inv(T_{j-1,j-1}) (kTrsvNB x kTrsvNB, row-major)
-  const void *INV;    // inv(T_{j-1,j-1}) (kTrsvNB x kTrsvNB, row-major, zero past its size)
+  const void *G;      // coupling block of block j: T[j, j-1] inv(T_{j-1,j-1}) (row-major, leading
+                      // dimension gld = kTrsvNB, zero past its sizes; gld = 0 when j has no predecessor)
+  const void *INV;    // inv(T_{j-1,j-1}) (pm x pm, row-major)
   const dz *rhs[2];   // right-hand sides, domain-local, per vector (read only)
   dz *sol[2];         // solutions, domain-local, per vector
   const dz *rin;      // r_{j-1}, the previous block's reduced right-hand side (vector q at q * kTrsvNB)
@@ -208,7 +209,7 @@ struct TrsvDom {
   int64_t ld;
   // blocks of the step: [cb0, cb0+cm) two back (solution in sol), [pb0, pb0+pm) the previous one
   // (its r in rin), [nb0, nb0+nm) the one reduced; nm = 0: only solve the previous block
-  int n, cb0, cm, pb0, pm, nb0, nm;
+  int n, cb0, cm, pb0, pm, nb0, nm, gld;
   // the next block's rows [br0, br0+brm) against the solved columns [bc0, bc0+bk):
   // nrg groups of 16 rows times nco work items of kc columns (brm = 0: none)
   int bst, nci, br0, brm, bc0, bk, nrg, nco;
