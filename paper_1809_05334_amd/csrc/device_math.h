@@ -153,9 +153,9 @@ __device__ __forceinline__ void clenshaw_w(const double *__restrict__ c, int K, 
     b1[w] = b2[w] = 0.0;
     t2[w] = t[w] + t[w];
   }
-#pragma unroll 1
-  for (int k = K; k >= 2; k -= 2) {
-    const double ck = c[k], ck1 = c[k - 1];
+  // four coefficients per pass, all read before the first is used, so one
+  // read's latency is exposed per four coefficients rather than per two
+  const auto pair = [&](double ck, double ck1) {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       const double bk = fma(t2[w], b1[w], ck - b2[w]);
@@ -163,7 +163,19 @@ __device__ __forceinline__ void clenshaw_w(const double *__restrict__ c, int K, 
       b2[w] = bk;
       b1[w] = bk1;
     }
+  };
+  int k = K;
+#pragma unroll 1
+  for (; k >= 8; k -= 8) {
+    const double c0 = c[k], c1 = c[k - 1], c2 = c[k - 2], c3 = c[k - 3];
+    const double c4 = c[k - 4], c5 = c[k - 5], c6 = c[k - 6], c7 = c[k - 7];
+    pair(c0, c1);
+    pair(c2, c3);
+    pair(c4, c5);
+    pair(c6, c7);
   }
+#pragma unroll 1
+  for (; k >= 2; k -= 2) pair(c[k], c[k - 1]);
 #pragma unroll
   for (int w = 0; w < W; ++w) f[w] = fma(t[w], b1[w], c[0] - b2[w]);
 }
@@ -239,18 +251,31 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
 #pragma unroll
     for (int w = 0; w < W; ++w) b1[w] = b2[w] = 0.0;
     const double *c = R + 8;
-#pragma unroll 1
-    for (int k = K; k >= 2; k -= 2) {
-      const double ck = c[k], ck1 = c[k - 1];
+    // four coefficients per pass, read before the first is used (as in clenshaw_w)
+    double t2[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) t2[w] = t[w] + t[w];
+    const auto pair = [&](double ck, double ck1) {
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const double t2 = t[w] + t[w];
-        const double bk = fma(t2, b1[w], ck - b2[w]);
-        const double bk1 = fma(t2, bk, ck1 - b1[w]);
+        const double bk = fma(t2[w], b1[w], ck - b2[w]);
+        const double bk1 = fma(t2[w], bk, ck1 - b1[w]);
         b2[w] = bk;
         b1[w] = bk1;
       }
+    };
+    int k = K;
+#pragma unroll 1
+    for (; k >= 8; k -= 8) {
+      const double c0 = c[k], c1 = c[k - 1], c2 = c[k - 2], c3 = c[k - 3];
+      const double c4 = c[k - 4], c5 = c[k - 5], c6 = c[k - 6], c7 = c[k - 7];
+      pair(c0, c1);
+      pair(c2, c3);
+      pair(c4, c5);
+      pair(c6, c7);
     }
+#pragma unroll 1
+    for (; k >= 2; k -= 2) pair(c[k], c[k - 1]);
     double f[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) f[w] = fma(t[w], b1[w], c[0] - b2[w]);
