@@ -120,7 +120,7 @@ __device__ __forceinline__ double clenshaw4(const double *__restrict__ c, int K,
 // offsets, image records, mode records; see host.h).
 namespace pk {
 constexpr int E = 0, A = 1, B = 2, IA = 3, IB = 4, KX = 5, KY = 6, TPA = 7, TPB = 8, WS = 9, PHRE = 10, PHIM = 19,
-              NIMG = 28, MODES = 32, IMAGES = 116;
+              NIMG = 28, MODES = 32, ROWS = 116, IMAGES = 128;
 }
 
 // Stage the packed table into LDS (all threads of the block participate).
@@ -173,6 +173,12 @@ __device__ __forceinline__ void clenshaw_w(const double *__restrict__ c, int K, 
     pair(c2, c3);
     pair(c4, c5);
     pair(c6, c7);
+  }
+  if (k >= 4) {   // (K is a multiple of 4: what remains is 4 or 0)
+    const double c0 = c[k], c1 = c[k - 1], c2 = c[k - 2], c3 = c[k - 3];
+    pair(c0, c1);
+    pair(c2, c3);
+    k -= 4;
   }
 #pragma unroll 1
   for (; k >= 2; k -= 2) pair(c[k], c[k - 1]);
@@ -274,6 +280,12 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
       pair(c4, c5);
       pair(c6, c7);
     }
+    if (k >= 4) {   // (K is a multiple of 4: what remains is 4 or 0)
+      const double c0 = c[k], c1 = c[k - 1], c2 = c[k - 2], c3 = c[k - 3];
+      pair(c0, c1);
+      pair(c2, c3);
+      k -= 4;
+    }
 #pragma unroll 1
     for (; k >= 2; k -= 2) pair(c[k], c[k - 1]);
     double f[W];
@@ -328,20 +340,31 @@ __device__ __forceinline__ void pgf_eval_w(const double *__restrict__ P, const d
     cre_[w] = 0.0;
     cim_[w] = 0.0;
   }
+  // rows of the grid: only the slots from the row's first to its last mode
+  // (the phases of the slots below reached by the same products as before)
 #pragma unroll 1
   for (int p = 0; p < kPgfSide; ++p) {
+    const int rr = pint(P[pk::ROWS + p]);
+    const int qlo = rr & 0xff, qend = rr >> 8;
     dz e[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) e[w] = erow[w];
 #pragma unroll 1
-    for (int q = 0; q < kPgfSide; ++q) {
-      const int moff = pint(P[pk::MODES + p * kPgfSide + q]);
+    for (int q = 0; q < qlo; ++q) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) e[w] = e[w] * by[w];
+    }
+#pragma unroll 1
+    for (int q = qlo; q < qend; ++q) {
+      const double slot = P[pk::MODES + p * kPgfSide + q];
+      const int moff = pint(slot);
       if (moff > 0) {
         const double *M = P + moff;
-        const int K = pint(M[0]);
+        const int kc = ufirst(__double2hiint(slot));   // K | cplx << 16
+        const int K = kc & 0xffff;
         double kr[W];
         clenshaw_w<W>(M + 4, K, tw, kr);
-        if (pint(M[1]) != 0) {
+        if ((kc >> 16) != 0) {
           double ki[W];
           clenshaw_w<W>(M + 4 + K + 4, K, tw, ki);
 #pragma unroll

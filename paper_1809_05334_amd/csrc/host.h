@@ -91,7 +91,10 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
 // fitted coefficients of the significant terms, in doubles.  Layout:
 //   [0..10)  E, a, b, 1/a, 1/b, kx, ky, 2pi/a, 2pi/b, ws
 //   [10..19) Re phase0[9], [19..28) Im phase0[9], [28] nimg
-//   [32..113) per mode (p,q) grid index: offset of its record or 0
+//   [32..113) per mode (p,q) grid index: offset of its record or 0 (low
+//             word), K | cplx << 16 (high word)
+//   [116..125) per row p of the mode grid: q_lo | (q_hi + 1) << 8, the
+//             first and last q with a mode (0 | 0 << 8: none)
 //   image records from kPackImages on, each
 //     [xa, xs, cre, cim, m, n, K, len] f[0..K] (pad to 4) [HK, 0, 0, 0] h[0..HK] (pad to 4)
 //     (the H block only for touching classes; len = record length)
@@ -99,7 +102,8 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
 // Integer fields (nimg, mode offsets, m, n, K, len, HK, cplx) hold the value in
 // the low 32 bits of the double slot.
 // K, HK are the degrees rounded up to a multiple of 4 (zero coefficients).
-constexpr int kPackImages = 116;
+constexpr int kPackRows = 116;
+constexpr int kPackImages = 128;
 void pack_pgf_table(const PgfTable &tab, std::vector<double> &out);
 
 }  // namespace vie

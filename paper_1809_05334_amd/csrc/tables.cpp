@@ -469,8 +469,8 @@ std::string build_pgf_table(PgfTable &tab, double a, double b, double zspan, dou
 // ---------------------------------------------------------------- packing
 // An integer field of the packed table: its value in the low 32 bits of the
 // double slot (the device reads the register half, no conversion).
-static double ibits(int v) {
-  const uint64_t u = (uint32_t)v;
+static double ibits(int v, int hi = 0) {
+  const uint64_t u = (uint64_t)(uint32_t)hi << 32 | (uint32_t)v;
   double d;
   std::memcpy(&d, &u, sizeof d);
   return d;
@@ -503,11 +503,21 @@ void pack_pgf_table(const PgfTable &tab, std::vector<double> &out) {
     const PgfMode &md = tab.mode[idx];
     if (md.deg < 0) continue;
     const int K = pad4(md.deg);
-    out[32 + idx] = ibits((int)out.size());
+    out[32 + idx] = ibits((int)out.size(), K | (md.cplx ? 1 << 16 : 0));
     out.insert(out.end(), {ibits(K), ibits(md.cplx), 0.0, 0.0});
     for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kre[k] : 0.0);
     if (md.cplx)
       for (int k = 0; k < pad4(K + 1); ++k) out.push_back(k <= md.deg ? md.kim[k] : 0.0);
+  }
+  // each row's range of q with a mode, so that a pass over the grid skips the rest
+  for (int p = 0; p < kPgfSide; ++p) {
+    int lo = kPgfSide, hi = -1;
+    for (int q = 0; q < kPgfSide; ++q)
+      if (tab.mode[p * kPgfSide + q].deg >= 0) {
+        lo = std::min(lo, q);
+        hi = std::max(hi, q);
+      }
+    out[kPackRows + p] = ibits(hi < 0 ? 0 : lo | (hi + 1) << 8);
   }
 }
 
