@@ -21,10 +21,17 @@ Spectra (normal incidence): one JSON line per (a, lambda).  Angular response
 normalised to normal incidence, A(theta) cos(theta) / A(0), next to the ideal
 Lambertian cos(theta) (Fig. 6).
 
+Checkpoint / resume (`--out study.jsonl`): every solve appends one JSON
+record, keyed by (a, lambda, theta, phi, polarisation, variant), as soon as its
+study group returns; on restart the records already in the file are read back
+and only the missing solves run.  A partial last line (a run killed while
+writing) is ignored and its solve redone.
+
     python -m paper_1809_05334_amd.spectra_study --periods 60,80,120,200 --lambdas 400:800:50
 """
 import argparse
 import json
+import os
 import sys
 
 import numpy as np
@@ -98,6 +105,67 @@ def run_requests(reqs, precision, path="batch", slots=4, tol=1e-8, restart=200):
     return srv.run_trace(reqs)
 
 
+def solve_key(a_nm, rq):
+    """Checkpoint key of one solve: lattice constant, wavelength, angles,
+    polarisation and variant, rounded so a key read back from JSON compares
+    equal to the one rebuilt from the request."""
+    _, var, pol = rq["tag"]
+    return (round(float(a_nm), 9), round(float(rq["lambda"]), 9), round(float(np.rad2deg(rq["theta"])), 9),
+            round(float(np.rad2deg(rq["phi"])), 9), int(pol), str(var))
+
+
+class Checkpoint:
+    """Append-only JSONL record of finished solves (one line per solve)."""
+
+    def __init__(self, path):
+        self.path = path
+        self.done = {}
+        if path and os.path.exists(path):
+            with open(path, "rb+") as f:
+                data = f.read()
+                keep = data.rfind(b"\n") + 1
+                if keep < len(data):      # partial last line of an interrupted write: cut it off,
+                    f.truncate(keep)      # so the next record starts on a line of its own
+            for line in data[:keep].decode().splitlines():
+                try:
+                    r = json.loads(line)
+                except json.JSONDecodeError:
+                    continue
+                self.done[tuple(r["key"])] = r
+
+    def append(self, key, res):
+        rec = {"key": list(key), "N": int(res.N), "A": [float(v) for v in res.A], "R": float(res.R),
+               "T": float(res.T), "iters": int(res.iters)}
+        self.done[key] = rec
+        if self.path:
+            with open(self.path, "a") as f:
+                f.write(json.dumps(rec) + "\n")
+                f.flush()
+                os.fsync(f.fileno())
+
+
+def run_with_checkpoint(a_nm, reqs, ckpt, run, **kw):
+    """Results of `reqs` in request order: the ones `ckpt` holds are read
+    back, the rest are solved by `run(pending, **kw)` and appended to it.
+    A failed solve is not recorded (it raises in the reduction and runs again
+    on restart)."""
+    from .serve import Result
+    keys = [solve_key(a_nm, rq) for rq in reqs]
+    pending = [i for i, k in enumerate(keys) if k not in ckpt.done]
+    out = [None] * len(reqs)
+    if pending:
+        res = run([reqs[i] for i in pending], **kw)
+        for i, rs in zip(pending, res):
+            out[i] = rs
+            if rs.ok:
+                ckpt.append(keys[i], rs)
+    for i, k in enumerate(keys):
+        if out[i] is None:
+            r = ckpt.done[k]
+            out[i] = Result(rid=reqs[i]["rid"], N=r["N"], A=list(r["A"]), R=r["R"], T=r["T"], iters=r["iters"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--periods", default="60,80,120,200")
@@ -110,6 +178,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--out", default="", help="JSONL checkpoint: append each solve, skip those already there")
     args = ap.parse_args()
 
     from . import vie
@@ -119,11 +188,16 @@ def main():
     def cell(a):
         return W.osc_cell_mesh(a, 80.0, 40.0, 20.0, 5.0, 20.0)
 
+    ckpt = Checkpoint(args.out)
+    if ckpt.done:
+        print(f"resuming: {len(ckpt.done)} solves read from {args.out}", file=sys.stderr, flush=True)
+    kw = dict(precision=prec, path=args.path, slots=args.slots, tol=args.tol, restart=args.restart)
+
     for a in axis(args.periods):
         mesh = cell(a)
         cases = [(lam, 0.0) for lam in axis(args.lambdas)]
         reqs = study_requests(mesh, cases)
-        res = run_requests(reqs, prec, args.path, args.slots, args.tol, args.restart)
+        res = run_with_checkpoint(a, reqs, ckpt, run_requests, **kw)
         act = reduce_active(reqs, res)
         metal = reduce_active(reqs, res, W.DOM_METAL)
         for ci, (lam, _) in enumerate(cases):
@@ -135,7 +209,7 @@ def main():
     for lam in axis(args.angle_lambdas):
         cases = [(lam, th) for th in thetas]
         reqs = study_requests(mesh, cases)
-        res = run_requests(reqs, prec, args.path, args.slots, args.tol, args.restart)
+        res = run_with_checkpoint(args.angle_period, reqs, ckpt, run_requests, **kw)
         act = reduce_active(reqs, res)
         ci0 = thetas.index(0.0) if 0.0 in thetas else 0
         for ci, (_, th) in enumerate(cases):
