@@ -166,8 +166,12 @@ int vie_fill(vie_ctx *ctx, double lambda_nm, double theta_rad, double phi_rad, c
 /* LU factorisation P A_dd = L U of every diagonal block A_dd (Sec. 2.3,
  * Eq. 6), with tournament pivoting per 64-column panel by default or partial
  * pivoting column by column (VIE_OPT_LU_PIVOT).  VIE_ESINGULAR on a zero
- * pivot; VIE_EINVAL if a domain has more than 131,072 unknowns (the bound
- * of the triangular solves' row sums). */
+ * pivot (the message names the domain and the column); VIE_EINVAL if a
+ * domain has more than 131,072 unknowns (the bound of the triangular solves'
+ * row sums).  Any factors of an earlier call are void from the start of the
+ * call: after a failure, vie_solve, vie_solve_pair and vie_precond_apply
+ * return VIE_ESTATE until a factorisation succeeds (the no-preconditioner
+ * option aside). */
 int vie_precond_factor(vie_ctx *ctx);
 
 /* Right-preconditioned restarted GMRES(restart) on Z M^-1 y = b, x = M^-1 y,

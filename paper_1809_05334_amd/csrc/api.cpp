@@ -994,6 +994,9 @@ namespace vie {
 // precision) into the factor storage; records ev0.
 int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
   if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
+  // the factors of an earlier factorisation of this fill are overwritten from
+  // here on: until this one succeeds, no solve or apply may use them
+  ctx->factored = false;
   const MeshTopology &t = ctx->topo;
   for (int d = 0; d < t.ndom; ++d)
     if (t.dend[d] - t.dstart[d] > (int64_t)kTrsvChunksMax * kTrsvSumCols)
