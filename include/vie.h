@@ -78,8 +78,23 @@ enum { VIE_TE = 0, VIE_TM = 1 };
  *   Krylov basis, Hessenberg/Givens updates and the true residual that closes
  *   every restart cycle run in FP64 on the mixed operator, so the solve
  *   converges to the tolerance of that operator; its difference from the FP64
- *   Z is the FP32 rounding of far entries. */
-enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1 };
+ *   Z is the FP32 rounding of far entries.
+ * VIE_GRID_FP64: structured-grid operator for a uniform Kuhn brick grid
+ *   (every brick split along its (0,0,0)-(1,1,1) diagonal, at least two
+ *   bricks per lattice period; vie_bind_workspace returns VIE_EINVAL for any
+ *   other mesh).  Z is never stored: the near part is the FP64 sparse part
+ *   above; the far part is applied by FFT.  Each far product-rule term is a
+ *   lattice sum between quadrature points, and on such a grid the points fall
+ *   on 60 sublattices whose kernels depend only on the brick offset
+ *   (circulant in x and y after a Bloch modulation, Toeplitz in z).  The fill
+ *   tabulates those kernels (60^2 x nx ny 2(nz+1) complex values) instead of
+ *   the N^2 far entries; a product with Z costs two batched 3D FFTs of 132
+ *   fields plus a per-frequency contraction.  Same Z as VIE_FP64 to
+ *   rounding.  There is no block preconditioner (vie_precond_factor returns
+ *   VIE_EINVAL; solve with VIE_OPT_PRECOND 1), no vie_read_Z (vie_apply_Z
+ *   gives Z x), no graph-captured steps, no batch and no static workspace.
+ *   hipFFT allocates its plans' work areas at bind. */
+enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1, VIE_GRID_FP64 = 2 };
 
 typedef struct {
   int iters;                 /* total GMRES iterations (all restarts, all refinement steps) */
@@ -402,6 +417,11 @@ int vie_get_factor_stats(const vie_ctx *ctx, vie_factor_stats *out);
  * events); *ms_per_matvec = average.  Needs a completed fill; uses the
  * solver's work vectors. */
 int vie_bench_matvec(vie_ctx *ctx, int reps, double *ms_per_matvec);
+
+/* y = Z x with the bound operator (any precision; Eq. 2's Z of the last
+ * fill), x and y host arrays of N values.  Needs a completed fill; uses the
+ * solver's work vectors (the stored solutions are kept). */
+int vie_apply_Z(vie_ctx *ctx, const vie_c128 *x, vie_c128 *y);
 
 #ifdef __cplusplus
 }

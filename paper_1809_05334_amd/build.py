@@ -15,8 +15,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvie.so")
 ROOT = os.path.dirname(HERE)
 
-HIP_SOURCES = ["k_fill.hip", "k_lu.hip", "k_trsv.hip", "k_krylov.hip", "k_absorb.hip", "api.cpp", "batch.cpp"]
-HOST_SOURCES = ["topology.cpp", "tables.cpp"]
+HIP_SOURCES = ["k_fill.hip", "k_lu.hip", "k_trsv.hip", "k_krylov.hip", "k_absorb.hip", "k_grid.hip", "api.cpp",
+               "batch.cpp"]
+HOST_SOURCES = ["topology.cpp", "tables.cpp", "grid.cpp"]
 ARCH = os.environ.get("VIE_OFFLOAD_ARCH", "gfx950")
 
 
@@ -55,7 +56,8 @@ def build(verbose=False, jobs=None):
             if verbose and err.strip():
                 sys.stderr.write(err)
     tmp = LIB + ".tmp"
-    _run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs])
+    _run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lhipfft",
+          "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -64,7 +64,7 @@ size_t nested_size(const std::vector<std::vector<int32_t>> &v) {
 }
 
 Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface, int nhalf, int precision,
-                   int64_t near_nnz, bool sym_fill) {
+                   int64_t near_nnz, bool sym_fill, int64_t grid_nf) {
   Layout L;
   size_t off = 0;
   auto put = [&](Region &r, size_t bytes) {
@@ -99,18 +99,29 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   put(L.inveps, 16 * nt);
   put(L.sigma, 16 * std::max(1, nface));
   L.ld = (N + 7) / 8 * 8;
-  const bool mixed = precision == VIE_MIXED_FP32;
-  put(L.Z, (mixed ? 8 : 16) * (size_t)N * L.ld);
+  const bool mixed = precision == VIE_MIXED_FP32, grid = precision == VIE_GRID_FP64;
+  // the grid operator keeps no dense Z (far part by FFT, near part in the CSR)
+  put(L.Z, grid ? 0 : (mixed ? 8 : 16) * (size_t)N * L.ld);
   // staging for the transposed far blocks of a normal-incidence fill (VIE_OPT_SYM_FILL)
-  if (sym_fill) put(L.Zt, (mixed ? 8 : 16) * (size_t)N * L.ld);
-  put(L.nrow, mixed ? 8 * (size_t)(N + 1) : 0);
-  put(L.ncol, mixed ? 4 * (size_t)near_nnz : 0);
-  put(L.nval, mixed ? 16 * (size_t)near_nnz : 0);
+  if (sym_fill && !grid) put(L.Zt, (mixed ? 8 : 16) * (size_t)N * L.ld);
+  const bool csr = mixed || grid;
+  put(L.nrow, csr ? 8 * (size_t)(N + 1) : 0);
+  put(L.ncol, csr ? 4 * (size_t)near_nnz : 0);
+  put(L.nval, csr ? 16 * (size_t)near_nnz : 0);
+  if (grid) {
+    put(L.ggeo, sizeof(GridGeom));
+    put(L.gtet, 8 * (size_t)nt);
+    put(L.gface, 16 * (size_t)std::max(1, nface));
+    put(L.ghalf, 4 * (size_t)std::max<int64_t>(1, N));
+    put(L.gtab, 16 * (size_t)kGridSub * kGridSub * grid_nf);
+    put(L.gin, 16 * (size_t)kGridFields * grid_nf);
+    put(L.gout, 16 * (size_t)kGridFields * grid_nf);
+  }
   L.fld.resize(t.ndom);
   L.foff.resize(t.ndom);
   int64_t fel = 0, npiv = 0;
   for (int d = 0; d < t.ndom; ++d) {
-    int64_t n = t.dend[d] - t.dstart[d];
+    int64_t n = grid ? 0 : t.dend[d] - t.dstart[d];   // (no block preconditioner with the grid operator)
     L.fld[d] = (n + 7) / 8 * 8;
     L.foff[d] = fel;
     fel += n * L.fld[d];
@@ -124,7 +135,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   L.goff.resize(t.ndom);
   int64_t del = 0, gel = 0;
   for (int d = 0; d < t.ndom; ++d) {
-    const int64_t n = t.dend[d] - t.dstart[d];
+    const int64_t n = grid ? 0 : t.dend[d] - t.dstart[d];
     const int64_t nbk = (n + kTrsvNB - 1) / kTrsvNB;
     L.doff[d] = del;
     L.goff[d] = gel;
@@ -141,7 +152,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   int64_t bel = 0;
   for (int d = 0; d < t.ndom; ++d) {
     L.boff[d] = bel;
-    bel += 4 * (int64_t)kTrsvNB * trsv_bsum_stride(t.dend[d] - t.dstart[d]);
+    if (!grid) bel += 4 * (int64_t)kTrsvNB * trsv_bsum_stride(t.dend[d] - t.dstart[d]);
   }
   put(L.tbsum, 16 * (size_t)std::max<int64_t>(1, bel));
   {
@@ -166,7 +177,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
   L.toff.assign(t.ndom, 0);
   for (int d = 0; d < t.ndom; ++d) {
     L.toff[d] = nodes;
-    for (int64_t c = nblk(t.dend[d] - t.dstart[d], mixed ? kTsRowsC : kTsRowsZ);;
+    for (int64_t c = nblk(grid ? 1 : t.dend[d] - t.dstart[d], mixed ? kTsRowsC : kTsRowsZ);;
          c = (c + (mixed ? kTsFanC : kTsFanZ) - 1) / (mixed ? kTsFanC : kTsFanZ)) {
       nodes += c;
       if (c == 1) break;
@@ -230,12 +241,36 @@ void ensure_near_pattern(vie_ctx *ctx) {
   ctx->npat = true;
 }
 
+// Grid analysis of the uploaded mesh (once per mesh): "" if it is a uniform
+// Kuhn grid the structured-grid operator can take, else the reason.
+const std::string &ensure_grid(vie_ctx *ctx) {
+  if (!ctx->grid) {
+    ctx->grid = new GridHost();
+    ctx->grid_err = analyse_grid(ctx->topo, ctx->quad, *ctx->grid);
+  }
+  return ctx->grid_err;
+}
+
+void release_fft(vie_ctx *ctx) {
+  if (ctx->fft_tab) (void)hipfftDestroy(ctx->fft_tab);
+  if (ctx->fft_fld) (void)hipfftDestroy(ctx->fft_fld);
+  ctx->fft_tab = ctx->fft_fld = 0;
+}
+
+void release_grid(vie_ctx *ctx) {
+  release_fft(ctx);
+  delete ctx->grid;
+  ctx->grid = nullptr;
+  ctx->grid_err.clear();
+}
+
 ZOut zout(vie_ctx *ctx) {
   const Layout &L = ctx->L;
   ZOut o{};
   o.ld = L.ld;
-  if (ctx->precision == VIE_MIXED_FP32) {
-    o.Zs = ctx->ptr<fz>(L.Z);
+  if (ctx->precision == VIE_MIXED_FP32 || ctx->precision == VIE_GRID_FP64) {
+    // (the grid operator has no dense part: far entries written by a fill kernel are dropped)
+    if (ctx->precision == VIE_MIXED_FP32) o.Zs = ctx->ptr<fz>(L.Z);
     o.rowptr = ctx->ptr<int64_t>(L.nrow);
     o.cols = ctx->ptr<int32_t>(L.ncol);
     o.vals = ctx->ptr<dz>(L.nval);
@@ -245,8 +280,52 @@ ZOut zout(vie_ctx *ctx) {
   return o;
 }
 
+// Structured-grid operator: y = Z x (or b - Z x): source fields, forward
+// FFTs, per-frequency products with the kernel tables, inverse FFTs, then the
+// far potentials and the near part per unknown.
+int grid_matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
+  const Layout &L = ctx->L;
+  const MeshTopology &t = ctx->topo;
+  const int64_t nf = ctx->grid->g.nf;
+  const GridGeom *gg = ctx->ptr<GridGeom>(L.ggeo);
+  dz *fin = ctx->ptr<dz>(L.gin), *fout = ctx->ptr<dz>(L.gout);
+  const double kx = ctx->fill_kx, ky = ctx->fill_ky;
+  hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, ctx->stream, fin, (int64_t)kGridFields * nf);
+  hipLaunchKernelGGL(k_grid_gather_tet, dim3(nblk(t.nt, 256)), dim3(256), 0, ctx->stream, (int64_t)t.nt, gg,
+                     (const int32_t *)ctx->ptr<int32_t>(L.gtet), (const TetGeom *)ctx->ptr<TetGeom>(L.tg),
+                     (const TetFace *)ctx->ptr<TetFace>(L.t2f), (const dz *)ctx->ptr<dz>(L.gsrc),
+                     (const dz *)ctx->ptr<dz>(L.kappa), x, kx, ky, fin);
+  if (ctx->nface)
+    hipLaunchKernelGGL(k_grid_gather_face, dim3(nblk(ctx->nface, 256)), dim3(256), 0, ctx->stream, ctx->nface, gg,
+                       (const int32_t *)ctx->ptr<int32_t>(L.gface), (const FaceGeom *)ctx->ptr<FaceGeom>(L.fg),
+                       (const dz *)ctx->ptr<dz>(L.sigma), x, kx, ky, fin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "grid matvec: %s", hipGetErrorString(e));
+  if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fin, (hipfftDoubleComplex *)fin, HIPFFT_FORWARD) !=
+      HIPFFT_SUCCESS)
+    return fail(ctx, VIE_EDEVICE, "grid matvec: forward FFT failed");
+  hipLaunchKernelGGL(k_grid_mul, dim3(nblk(nf, 256), kGridSub), dim3(256), 0, ctx->stream, nf,
+                     (const dz *)ctx->ptr<dz>(L.gtab), (const dz *)fin, fout);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "grid matvec: %s", hipGetErrorString(e));
+  if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fout, (hipfftDoubleComplex *)fout, HIPFFT_BACKWARD) !=
+      HIPFFT_SUCCESS)
+    return fail(ctx, VIE_EDEVICE, "grid matvec: inverse FFT failed");
+  hipLaunchKernelGGL(k_grid_apply, dim3(nblk(t.N, 256)), dim3(256), 0, ctx->stream, (int64_t)t.N, gg,
+                     (const int32_t *)ctx->ptr<int32_t>(L.gtet), (const int32_t *)ctx->ptr<int32_t>(L.gface),
+                     (const int32_t *)ctx->ptr<int32_t>(L.ghalf), (const int32_t *)ctx->ptr<int32_t>(L.utet),
+                     (const int32_t *)ctx->ptr<int32_t>(L.uk), (const TetGeom *)ctx->ptr<TetGeom>(L.tg),
+                     (const FaceGeom *)ctx->ptr<FaceGeom>(L.fg), (const dz *)ctx->ptr<dz>(L.alpha), (const dz *)fout,
+                     ctx->fill_k0sq9, kx, ky, (const int64_t *)ctx->ptr<int64_t>(L.nrow),
+                     (const int32_t *)ctx->ptr<int32_t>(L.ncol), (const dz *)ctx->ptr<dz>(L.nval), x, b, y);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "grid matvec: %s", hipGetErrorString(e));
+  return VIE_OK;
+}
+
 // y = Z x, or y = b - Z x when b is given, with the bound precision's operator
 int matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
+  if (ctx->precision == VIE_GRID_FP64) return grid_matvec(ctx, x, b, y);
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
   const int R = ctx->mv_rpw;
@@ -273,6 +352,11 @@ int matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
 // y_q = Z x_q (or b_q - Z x_q) for two vectors in one pass over Z; each y_q
 // is bitwise the single-vector result.
 int matvec2(vie_ctx *ctx, const MvVecs &v) {
+  if (ctx->precision == VIE_GRID_FP64) {
+    for (int q = 0; q < 2; ++q)
+      if (int rc = grid_matvec(ctx, v.x[q], v.b[q], v.y[q])) return rc;
+    return VIE_OK;
+  }
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
   const int R = ctx->mv_rpw;
@@ -350,6 +434,8 @@ int vie_set_stream(vie_ctx *ctx, void *hip_stream) {
   // before the workspace is bound the context has issued no device work
   if (ctx->state >= S_BOUND) HIPCK(hipStreamSynchronize(ctx->stream));
   ctx->stream = (hipStream_t)hip_stream;
+  for (hipfftHandle h : {ctx->fft_tab, ctx->fft_fld})
+    if (h && hipfftSetStream(h, ctx->stream) != HIPFFT_SUCCESS) return fail(ctx, VIE_EDEVICE, "hipfftSetStream failed");
   return VIE_OK;
 }
 
@@ -374,6 +460,7 @@ int vie_destroy(vie_ctx *ctx) {
   if (ctx->ev_la) (void)hipEventDestroy(ctx->ev_la);
   if (ctx->ev_ts) (void)hipEventDestroy(ctx->ev_ts);
   for (hipEvent_t e : ctx->upd_ev) (void)hipEventDestroy(e);
+  release_grid(ctx);
   delete ctx->tab;
   delete ctx;
   return VIE_OK;
@@ -393,6 +480,11 @@ int vie_mesh_upload(vie_ctx *ctx, const double *verts_nm, int64_t nv, const int3
   ctx->state = S_MESH;
   ctx->factored = false;
   ctx->ws = nullptr;
+  // per-mesh host state of the previous mesh: the near-part pattern and the grid analysis
+  ctx->npat = false;
+  ctx->nrow.clear();
+  ctx->ncol.clear();
+  release_grid(ctx);
   return VIE_OK;
 }
 
@@ -415,18 +507,22 @@ static int64_t total_near(const MeshTopology &t) {
 
 size_t vie_workspace_bytes(const vie_ctx *cctx, int precision, int restart) {
   if (!cctx || cctx->state < S_MESH || restart < 1) return 0;
-  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32) return 0;
+  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32 && precision != VIE_GRID_FP64) return 0;
   vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
   int nhalf = 0;
   for (int32_t f : ctx->topo.charged)
     if (ctx->topo.tminus[f] < 0) ++nhalf;
-  int64_t nnz = 0;
-  if (precision == VIE_MIXED_FP32) {
+  int64_t nnz = 0, gnf = 0;
+  if (precision == VIE_GRID_FP64) {
+    if (!ensure_grid(ctx).empty()) return 0;
+    gnf = ctx->grid->g.nf;
+  }
+  if (precision == VIE_MIXED_FP32 || precision == VIE_GRID_FP64) {
     ensure_near_pattern(ctx);
     nnz = (int64_t)ctx->ncol.size();
   }
   return make_layout(ctx->topo, restart, total_near(ctx->topo), (int)ctx->topo.charged.size(), nhalf, precision, nnz,
-                     ctx->sym_fill != 0)
+                     ctx->sym_fill != 0, gnf)
       .total;
 }
 
@@ -438,8 +534,9 @@ namespace vie {
 // mesh tables.  no_alloc: allocate nothing (no pinned host staging either;
 // the pivot read-back then goes through pageable host memory).
 int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int restart, bool no_alloc) {
-  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32)
-    return fail(ctx, VIE_EINVAL, "precision must be VIE_FP64 or VIE_MIXED_FP32");
+  if (precision != VIE_FP64 && precision != VIE_MIXED_FP32 && (precision != VIE_GRID_FP64 || no_alloc))
+    return fail(ctx, VIE_EINVAL, no_alloc ? "precision must be VIE_FP64 or VIE_MIXED_FP32"
+                                          : "precision must be VIE_FP64, VIE_MIXED_FP32 or VIE_GRID_FP64");
   if (restart < 1 || restart > 1000) return fail(ctx, VIE_EINVAL, "restart must be in [1, 1000]");
   if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(ctx, VIE_EINVAL, "workspace must be 256-byte aligned");
   HIPCK(hipSetDevice(ctx->device));
@@ -449,12 +546,17 @@ int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int rest
     if (t.tminus[t.charged[i]] < 0) half.push_back((int32_t)i);
   ctx->nhalf = (int)half.size();
   ctx->nface = (int)t.charged.size();
-  int64_t nnz = 0;
-  if (precision == VIE_MIXED_FP32) {
+  int64_t nnz = 0, gnf = 0;
+  if (precision == VIE_GRID_FP64) {
+    const std::string &ge = ensure_grid(ctx);
+    if (!ge.empty()) return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 needs a uniform Kuhn brick grid: %s", ge.c_str());
+    gnf = ctx->grid->g.nf;
+  }
+  if (precision == VIE_MIXED_FP32 || precision == VIE_GRID_FP64) {
     ensure_near_pattern(ctx);
     nnz = (int64_t)ctx->ncol.size();
   }
-  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz, ctx->sym_fill != 0);
+  Layout L = make_layout(t, restart, total_near(t), ctx->nface, ctx->nhalf, precision, nnz, ctx->sym_fill != 0, gnf);
   if (bytes < L.total) return fail(ctx, VIE_ENOMEM, "workspace %zu bytes < required %zu", bytes, L.total);
   if (ctx->pin_piv_n < t.N) {
     HIPCK(hipStreamSynchronize(ctx->stream));   // no upload of the permutation in flight
@@ -567,9 +669,30 @@ int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int rest
   rc |= up(L.near_tf, tf_.data(), 4 * tf_.size());
   rc |= up(L.near_ft, ft_.data(), 4 * ft_.size());
   rc |= up(L.quad, &ctx->quad, sizeof(QuadRules));
-  if (precision == VIE_MIXED_FP32) {
+  if (precision == VIE_MIXED_FP32 || precision == VIE_GRID_FP64) {
     rc |= up(L.nrow, ctx->nrow.data(), 8 * ctx->nrow.size());
     rc |= up(L.ncol, ctx->ncol.data(), 4 * ctx->ncol.size());
+  }
+  release_fft(ctx);
+  if (precision == VIE_GRID_FP64) {
+    const GridHost &G = *ctx->grid;
+    rc |= up(L.ggeo, &G.g, sizeof(GridGeom));
+    rc |= up(L.gtet, G.tet.data(), 4 * G.tet.size());
+    rc |= up(L.gface, G.face.data(), 4 * G.face.size());
+    rc |= up(L.ghalf, G.half.data(), 4 * G.half.size());
+    // batched 3D transforms over (z, y, x): the kernel tables and the fields
+    // of one product (hipFFT allocates their work areas)
+    int n3[3] = {G.g.pz, G.g.ny, G.g.nx};
+    const int nf = (int)G.g.nf;
+    if (hipfftPlanMany(&ctx->fft_tab, 3, n3, nullptr, 1, nf, nullptr, 1, nf, HIPFFT_Z2Z, kGridSub * kGridSub) !=
+            HIPFFT_SUCCESS ||
+        hipfftPlanMany(&ctx->fft_fld, 3, n3, nullptr, 1, nf, nullptr, 1, nf, HIPFFT_Z2Z, kGridFields) !=
+            HIPFFT_SUCCESS ||
+        hipfftSetStream(ctx->fft_tab, ctx->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(ctx->fft_fld, ctx->stream) != HIPFFT_SUCCESS) {
+      release_fft(ctx);
+      return fail(ctx, VIE_EDEVICE, "hipFFT plans for the grid operator could not be made");
+    }
   }
   if (rc) return rc;
   // the panel and tournament counters start (and always end) at zero
@@ -693,6 +816,8 @@ int fill_upload(vie_ctx *ctx) {
   const double k0 = 2 * M_PI / lambda_nm;
   const double kx = k0 * std::sin(theta) * std::cos(phi), ky = k0 * std::sin(theta) * std::sin(phi);
   ctx->fill_k0sq9 = k0 * k0 / 9.0;
+  ctx->fill_kx = kx;
+  ctx->fill_ky = ky;
   ctx->fill_lds = 8 * (size_t)ctx->packlen;
 
   hipLaunchKernelGGL(k_prep, dim3(nblk(t.nt, 256)), dim3(256), 0, ctx->stream, (int64_t)t.nt, t2f, tg,
@@ -754,9 +879,11 @@ int fill_kernels(vie_ctx *ctx) {
   const int rev = ctx->fill_rev;
   const int C = t.ncolors;
   const int32_t *colors = ctx->ptr<int32_t>(L.colors);
+  // the grid operator takes every far pair from its FFT tables (built below)
+  const bool grid = ctx->precision == VIE_GRID_FP64;
   HIPCK(hipEventRecord(ctx->ev2, ctx->stream));
   int far_launches = 0;
-  for (int ct = 0; ct < C; ++ct)
+  for (int ct = 0; ct < (grid ? 0 : C); ++ct)
     for (int cs = 0; cs < C; ++cs) {
       if (sym && cs < ct) continue;   // covered by the launch of (cs, ct)
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct], nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
@@ -789,7 +916,9 @@ int fill_kernels(vie_ctx *ctx) {
     // (one lane each, so no wave mixes the two kinds)
     for (int ct = 0; ct < C; ++ct) {
       const int nT = ctx->color_off[ct + 1] - ctx->color_off[ct];
-      if (sym_face && rev)
+      if (grid)
+        ;
+      else if (sym_face && rev)
         hipLaunchKernelGGL(k_tet_face_rev, dim3(nblk(ctx->nface, 64), nblk(nT, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
                            qr, tg, t2f, colors + ctx->color_off[ct], nT, fg, ctx->nface, alpha, sigma, gsrc, kappa, zo, zt);
       else
@@ -806,7 +935,7 @@ int fill_kernels(vie_ctx *ctx) {
     if (ctx->nhalf) {
       for (int cs = 0; cs < C; ++cs) {
         const int nS = ctx->color_off[cs + 1] - ctx->color_off[cs];
-        if (!sym_face)   // (with the staging the far pairs came from k_tet_face)
+        if (!sym_face && !grid)   // (with the staging the far pairs came from k_tet_face)
           hipLaunchKernelGGL(k_face_tet, dim3(nblk(nS, 64), nblk(ctx->nhalf, 4)), dim3(256), lds, ctx->stream, pk_, pkl,
                              qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, tg, t2f, colors + ctx->color_off[cs], nS,
                              gsrc, kappa, zo);
@@ -822,6 +951,19 @@ int fill_kernels(vie_ctx *ctx) {
                          pkl, qr, fg, ctx->ptr<int32_t>(L.half), ctx->nhalf, ctx->nface, sigma, zo);
       LAUNCHCK();
     }
+  }
+  if (grid) {
+    // kernel tables of every sublattice pair, scaled by 1/nf for the
+    // unnormalised inverse transform, then transformed in place
+    const int64_t nf = ctx->grid->g.nf;
+    dz *tab = ctx->ptr<dz>(L.gtab);
+    hipLaunchKernelGGL(k_grid_table, dim3(nblk(nf, 256), kGridSub * kGridSub), dim3(256), lds, ctx->stream, pk_, pkl,
+                       (const GridGeom *)ctx->ptr<GridGeom>(L.ggeo), ctx->fill_kx, ctx->fill_ky, 1.0 / (double)nf,
+                       tab);
+    LAUNCHCK();
+    if (hipfftExecZ2Z(ctx->fft_tab, (hipfftDoubleComplex *)tab, (hipfftDoubleComplex *)tab, HIPFFT_FORWARD) !=
+        HIPFFT_SUCCESS)
+      return fail(ctx, VIE_EDEVICE, "grid operator: FFT of the kernel tables failed");
   }
   return VIE_OK;
 }
@@ -994,6 +1136,8 @@ namespace vie {
 // precision) into the factor storage; records ev0.
 int factor_prepare(vie_ctx *ctx, std::vector<LuDom> &doms) {
   if (int r = check(ctx, S_FILLED, "vie_precond_factor")) return r;
+  if (ctx->precision == VIE_GRID_FP64)
+    return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 stores no diagonal blocks to factor (solve with VIE_OPT_PRECOND 1)");
   // the factors of an earlier factorisation of this fill are overwritten from
   // here on: until this one succeeds, no solve or apply may use them
   ctx->factored = false;
@@ -1852,10 +1996,21 @@ int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int rest
 
 }  // namespace vie
 
+// The grid operator solves with M = I and plain launches (its FFTs are not
+// captured into the Arnoldi-step graphs).
+static int grid_solve_args(vie_ctx *ctx) {
+  if (ctx->precision != VIE_GRID_FP64) return VIE_OK;
+  if (ctx->precond == 0)
+    return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 has no block preconditioner: set VIE_OPT_PRECOND to 1");
+  if (ctx->graph_steps > 0) return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 runs without graph-captured steps");
+  return VIE_OK;
+}
+
 extern "C" {
 
 int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
   if (int r = check(ctx, S_FILLED, "vie_solve")) return r;
+  if (int r = grid_solve_args(ctx)) return r;
   if (!ctx->precond && !ctx->factored)
     return fail(ctx, VIE_ESTATE, "vie_solve: the block preconditioner needs vie_precond_factor after the fill");
   if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
@@ -1868,6 +2023,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
 
 int vie_solve_pair(vie_ctx *ctx, double tol, int max_iter, int restart, vie_solve_info *info) {
   if (int r = check(ctx, S_FILLED, "vie_solve_pair")) return r;
+  if (int r = grid_solve_args(ctx)) return r;
   if (!ctx->precond && !ctx->factored)
     return fail(ctx, VIE_ESTATE, "vie_solve_pair: the block preconditioner needs vie_precond_factor after the fill");
   if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
@@ -2056,6 +2212,7 @@ int vie_export_faces(const vie_ctx *c, int32_t *face_vid, int32_t *tplus, int32_
 int vie_read_Z(const vie_ctx *cctx, const int64_t *rows, const int64_t *cols, int64_t k, vie_c128 *out) {
   vie_ctx *ctx = const_cast<vie_ctx *>(cctx);
   if (int r = check(ctx, S_FILLED, "vie_read_Z")) return r;
+  if (ctx->precision == VIE_GRID_FP64) return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 stores no Z (vie_apply_Z gives Z x)");
   if (!rows || !cols || !out || k < 0) return fail(ctx, VIE_EINVAL, "bad arguments");
   const Layout &L = ctx->L;
   const int64_t N = ctx->topo.N;
@@ -2139,6 +2296,20 @@ int vie_get_fill_stats(const vie_ctx *ctx, vie_fill_stats *out) {
   if (!ctx || !out) return VIE_EINVAL;
   if (ctx->state < S_FILLED) return VIE_ESTATE;
   *out = ctx->fstats;
+  return VIE_OK;
+}
+
+int vie_apply_Z(vie_ctx *ctx, const vie_c128 *x, vie_c128 *y) {
+  if (int r = check(ctx, S_FILLED, "vie_apply_Z")) return r;
+  if (!x || !y) return fail(ctx, VIE_EINVAL, "null vector");
+  HIPCK(hipSetDevice(ctx->device));
+  const Layout &L = ctx->L;
+  const int64_t N = ctx->topo.N;
+  dz *xd = ctx->ptr<dz>(L.K[0].vz), *yd = ctx->ptr<dz>(L.K[0].vw);   // Krylov scratch (clobbered)
+  HIPCK(hipMemcpyAsync(xd, x, 16 * (size_t)N, hipMemcpyHostToDevice, ctx->stream));
+  if (int rc = matvec(ctx, xd, nullptr, yd)) return rc;
+  HIPCK(hipMemcpyAsync(y, yd, 16 * (size_t)N, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
   return VIE_OK;
 }
 

@@ -165,6 +165,7 @@ int vie_batch_bind(vie_batch *b, vie_ctx *const *cells, int ncells, void *dev_pt
     if (!x || x->state < S_BOUND) return bfail(b, VIE_ESTATE, "cell %d has no bound workspace", c);
     if (x->device != b->device) return bfail(b, VIE_EINVAL, "cell %d is on another device", c);
     if (x->precision != cells[0]->precision) return bfail(b, VIE_EINVAL, "cells of mixed precisions");
+    if (x->precision == VIE_GRID_FP64) return bfail(b, VIE_EINVAL, "cell %d uses the grid operator (not batched)", c);
     if (x->topo.ndom > kCellMaxDom) return bfail(b, VIE_EINVAL, "cell %d has more than %d domains", c, kCellMaxDom);
     for (int k = 0; k < c; ++k)
       if (cells[k] == x) return bfail(b, VIE_EINVAL, "cell %d repeats cell %d", c, k);

@@ -3,6 +3,7 @@
 // and the fused multi-cell batch (batch.cpp).  Not part of the C-ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -13,6 +14,7 @@
 
 #include "../../include/vie.h"
 #include "device_math.h"
+#include "grid.h"
 #include "host.h"
 #include "kernels.h"
 
@@ -36,6 +38,9 @@ struct Layout {
   Region eps, alpha, gsrc, kappa, inveps, sigma;
   Region Z, Zt, nrow, ncol, nval, F, ipiv, perm, rpiv, info, lupv, lupi, lucnt, tcand, ttcnt, tblk, dinv, gcpl, trr, tbsum,
       plans;
+  // structured-grid operator (VIE_GRID_FP64): geometry, element maps, kernel
+  // tables (kGridSub^2 x nf), source and potential fields (kGridFields x nf)
+  Region ggeo, gtet, gface, ghalf, gtab, gin, gout;
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
   struct Kry {
@@ -129,6 +134,13 @@ struct vie_ctx {
   int fill_rev = 0;
   size_t fill_lds = 0;
   double fill_k0sq9 = 0;
+  double fill_kx = 0, fill_ky = 0;  // transverse wavevector of the fill
+  // structured-grid operator: the mesh's grid analysis (built on first use,
+  // per mesh; grid_err holds why the mesh is not a uniform Kuhn grid) and the
+  // hipFFT plans of the bound workspace
+  GridHost *grid = nullptr;
+  std::string grid_err;
+  hipfftHandle fft_tab = 0, fft_fld = 0;
   double t_fill = 0, t_factor = 0;
 
   template <class T>

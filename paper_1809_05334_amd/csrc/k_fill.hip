@@ -29,7 +29,8 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // Z[m][n] += v into the destination of this fill (see ZOut).  In mixed
 // precision a far contribution is added to the FP32 entry in FP64 and rounded
-// once; a near one goes to its slot of the sorted CSR row.
+// once; a near one goes to its slot of the sorted CSR row.  With no dense part
+// (the structured-grid operator) a far contribution is dropped.
 __device__ __forceinline__ void zput(const ZOut &o, int64_t m, int64_t n, dz v, bool near) {
   if (o.Z) {
     dz *p = o.Z + m * o.ld + n;
@@ -42,7 +43,7 @@ __device__ __forceinline__ void zput(const ZOut &o, int64_t m, int64_t n, dz v, 
       else hi = mid;
     }
     if (lo < o.rowptr[m + 1] && o.cols[lo] == n) o.vals[lo] = o.vals[lo] + v;
-  } else {
+  } else if (o.Zs) {
     fz *p = o.Zs + m * o.ld + n;
     const fz z = *p;
     *p = fz{(float)((double)z.re + v.re), (float)((double)z.im + v.im)};

@@ -1,0 +1,187 @@
+// Structured-grid far operator (see grid.h): kernel tables from the lattice
+// sums, the source fields of a vector, the per-frequency products and the
+// far potentials tested against every unknown, plus the near part.
+//
+// Field layout: field c, point x + nx (y + ny z) at c nf + that index, z over
+// the padded length pz; charge fields c = s (s < kGridSub), current fields
+// c = kGridSub + kGridTetSub d + s (component d, tetrahedron sublattice s).
+// Table: sublattice pair (s, s') at (s kGridSub + s') nf.
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "grid.h"
+#include "kernels.h"
+
+namespace vie {
+
+__device__ __forceinline__ dz cexpj(double t) {
+  double s, c;
+  sincos(t, &s, &c);
+  return mk(c, s);
+}
+
+// Kernel table of one sublattice pair (blockIdx.y = s kGridSub + s') over the
+// brick offsets: offset (dx, dy) taken in (-n/2, n/2] (the circulant kernel
+// is periodic in it), dz = z for z < lz and z - pz above (z = lz unused).
+//   K(s, s', d) = scale e^{+j kt.(dx hx, dy hy)} g_p(pos_s - pos_s' + d h),
+// zero for corner-sharing pairs (any image) and for separations beyond the
+// mesh's height (no element pair has them; the fits do not cover them).
+__global__ __launch_bounds__(256) void k_grid_table(const double *__restrict__ pack, int packlen,
+                                                    const GridGeom *__restrict__ gg, double kx, double ky,
+                                                    double scale, dz *__restrict__ tab) {
+  extern __shared__ double s_tab[];
+  stage_table(pack, packlen, s_tab);
+  const GridGeom &G = *gg;
+  const int64_t nf = G.nf;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nf) return;
+  const int sp = blockIdx.y;
+  const int s = sp / kGridSub, s2 = sp % kGridSub;
+  const int nx = G.nx, ny = G.ny;
+  const int x = (int)(id % nx), y = (int)((id / nx) % ny), z = (int)(id / ((int64_t)nx * ny));
+  dz out = mk(0.0, 0.0);
+  if (z != G.lz) {
+    const int dz_ = z < G.lz ? z : z - G.pz;
+    const int dx = x <= nx / 2 ? x : x - nx, dy = y <= ny / 2 ? y : y - ny;
+    bool touch = false;
+    if (dz_ >= -1 && dz_ <= 1) {
+      const int e = G.ent[s], e2 = G.ent[s2];
+      for (int ox = -1; ox <= 1; ++ox) {
+        if (((ox - x) % nx + nx) % nx) continue;
+        for (int oy = -1; oy <= 1; ++oy) {
+          if (((oy - y) % ny + ny) % ny) continue;
+          touch = touch || G.touch[e][e2][(ox + 1) + 3 * (oy + 1) + 9 * (dz_ + 1)];
+        }
+      }
+    }
+    const double sx = G.pos[s][0] - G.pos[s2][0] + dx * G.h[0];
+    const double sy = G.pos[s][1] - G.pos[s2][1] + dy * G.h[1];
+    const double sz = G.pos[s][2] - G.pos[s2][2] + dz_ * G.h[2];
+    if (!touch && fabs(sz) <= G.zspan * (1.0 + 1e-12)) {
+      const dz g = pgf_eval<false>(s_tab, sx, sy, sz, 0);
+      out = (scale * cexpj(kx * dx * G.h[0] + ky * dy * G.h[1])) * g;
+    }
+  }
+  tab[(int64_t)sp * nf + id] = out;
+}
+
+// Source fields of the tetrahedra: per tetrahedron S (one thread) its charge
+// w rho_S and current w (rho_S r'_j - sum_l b_l x_l v_l) at its four points,
+// positions relative to its brick, modulated by e^{+j kt.o} (o: brick origin).
+// Every (brick, type) holds at most one tetrahedron: no two threads write one
+// slot.  The fields start cleared.
+__global__ __launch_bounds__(256) void k_grid_gather_tet(int64_t nt, const GridGeom *__restrict__ gg,
+                                                         const int32_t *__restrict__ gtet,
+                                                         const TetGeom *__restrict__ tg,
+                                                         const TetFace *__restrict__ t2f, const dz *__restrict__ gsrc,
+                                                         const dz *__restrict__ kappa, const dz *__restrict__ x,
+                                                         double kx, double ky, dz *__restrict__ fld) {
+  const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (T >= nt) return;
+  const GridGeom &G = *gg;
+  const int64_t nf = G.nf;
+  const int slot = gtet[2 * T], type = gtet[2 * T + 1];
+  const int bx = slot % G.nx, by = (slot / G.nx) % G.ny, bz = slot / (G.nx * G.ny);
+  const double o[3] = {G.org[0] + bx * G.h[0], G.org[1] + by * G.h[1], G.org[2] + bz * G.h[2]};
+  const dz ks = kappa[T];
+  dz rho = mk(0.0, 0.0), c[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+  for (int l = 0; l < 4; ++l) {
+    const dz bxl = (gsrc[4 * T + l] * ks) * x[t2f[4 * T + l].unknown];
+    rho = rho + bxl;
+    for (int d = 0; d < 3; ++d) c[d] = c[d] + (tg[T].v[l][d] - o[d]) * bxl;
+  }
+  const dz ph = cexpj(kx * bx * G.h[0] + ky * by * G.h[1]);
+  const double w = 0.25 * tg[T].vol;
+  const dz wr = (w * ph) * rho;
+  for (int q = 0; q < 4; ++q) {
+    const int s = 4 * type + q;
+    fld[(int64_t)s * nf + slot] = wr;
+    for (int d = 0; d < 3; ++d)
+      fld[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + slot] = (w * ph) * (G.pos[s][d] * rho - c[d]);
+  }
+}
+
+// Source fields of the surface-charge faces: charge -(A/3) sigma x at each of
+// the face's three points (one thread per face).
+__global__ __launch_bounds__(256) void k_grid_gather_face(int nface, const GridGeom *__restrict__ gg,
+                                                          const int32_t *__restrict__ gface,
+                                                          const FaceGeom *__restrict__ fg,
+                                                          const dz *__restrict__ sigma, const dz *__restrict__ x,
+                                                          double kx, double ky, dz *__restrict__ fld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nface) return;
+  const GridGeom &G = *gg;
+  const int bx = gface[4 * i], by = gface[4 * i + 1], bz = gface[4 * i + 2], type = gface[4 * i + 3];
+  const int64_t slot = bx % G.nx + (int64_t)G.nx * (by % G.ny + (int64_t)G.ny * bz);
+  const dz q = (-fg[i].area / 3.0 * cexpj(kx * bx * G.h[0] + ky * by * G.h[1])) * (sigma[i] * x[fg[i].unknown]);
+  for (int p = 0; p < 3; ++p) fld[(int64_t)(kGridTetSub + 3 * type + p) * G.nf + slot] = q;
+}
+
+// Per frequency f (x) and test sublattice s (blockIdx.y): the scalar
+// potential from every charge field and, for tetrahedron sublattices, the
+// vector potential from the current fields.
+__global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restrict__ tab, const dz *__restrict__ fin,
+                                                  dz *__restrict__ fout) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int s = blockIdx.y;
+  const dz *K = tab + (int64_t)s * kGridSub * nf + f;
+  dz acc = mk(0.0, 0.0);
+  for (int s2 = 0; s2 < kGridSub; ++s2) acc = acc + K[(int64_t)s2 * nf] * fin[(int64_t)s2 * nf + f];
+  fout[(int64_t)s * nf + f] = acc;
+  if (s < kGridTetSub) {
+    for (int d = 0; d < 3; ++d) {
+      const dz *J = fin + (int64_t)(kGridSub + kGridTetSub * d) * nf + f;
+      dz a = mk(0.0, 0.0);
+      for (int s2 = 0; s2 < kGridTetSub; ++s2) a = a + K[(int64_t)s2 * nf] * J[(int64_t)s2 * nf];
+      fout[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + f] = a;
+    }
+  }
+}
+
+// y = Z x (or b - Z x): per unknown m (one thread) the far potentials at the
+// points of its tetrahedra (demodulated by e^{-j kt.o}) and, for a half-SWG
+// face, at its own points, plus its row of the near part (CSR, FP64).
+__global__ __launch_bounds__(256) void k_grid_apply(
+    int64_t N, const GridGeom *__restrict__ gg, const int32_t *__restrict__ gtet, const int32_t *__restrict__ gface,
+    const int32_t *__restrict__ ghalf, const int32_t *__restrict__ utet, const int32_t *__restrict__ uk,
+    const TetGeom *__restrict__ tg, const FaceGeom *__restrict__ fg, const dz *__restrict__ alpha,
+    const dz *__restrict__ fout, double k0sq9, double kx, double ky, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ cols, const dz *__restrict__ vals, const dz *__restrict__ x, const dz *__restrict__ b,
+    dz *__restrict__ y) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const GridGeom &G = *gg;
+  const int64_t nf = G.nf;
+  dz acc = mk(0.0, 0.0);
+  for (int h = 0; h < 2; ++h) {
+    const int T = utet[2 * m + h];
+    if (T < 0) continue;
+    const int k = uk[2 * m + h];
+    const int slot = gtet[2 * T], type = gtet[2 * T + 1];
+    const int bx = slot % G.nx, by = (slot / G.nx) % G.ny, bz = slot / (G.nx * G.ny);
+    const double vk[3] = {tg[T].v[k][0] - (G.org[0] + bx * G.h[0]), tg[T].v[k][1] - (G.org[1] + by * G.h[1]),
+                          tg[T].v[k][2] - (G.org[2] + bz * G.h[2])};
+    dz phi = mk(0.0, 0.0), ra = mk(0.0, 0.0);
+    for (int q = 0; q < 4; ++q) {
+      const int s = 4 * type + q;
+      phi = phi + fout[(int64_t)s * nf + slot];
+      for (int d = 0; d < 3; ++d)
+        ra = ra + (G.pos[s][d] - vk[d]) * fout[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + slot];
+    }
+    const dz ph = cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]));
+    acc = acc + ((0.25 * tg[T].vol) * alpha[4 * T + k]) * (ph * (phi - k0sq9 * ra));
+  }
+  const int i = ghalf[m];
+  if (i >= 0) {
+    const int bx = gface[4 * i], by = gface[4 * i + 1], bz = gface[4 * i + 2], type = gface[4 * i + 3];
+    const int64_t slot = bx % G.nx + (int64_t)G.nx * (by % G.ny + (int64_t)G.ny * bz);
+    dz phi = mk(0.0, 0.0);
+    for (int p = 0; p < 3; ++p) phi = phi + fout[(int64_t)(kGridTetSub + 3 * type + p) * nf + slot];
+    acc = acc - (fg[i].area / 3.0 * cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]))) * phi;
+  }
+  for (int64_t e = rowptr[m]; e < rowptr[m + 1]; ++e) acc = acc + vals[e] * x[cols[e]];
+  y[m] = b ? b[m] - acc : acc;
+}
+
+}  // namespace vie

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libvie.so")
 
 VIE_OK, VIE_EINVAL, VIE_ESTATE, VIE_ENOMEM, VIE_ENOCONV, VIE_EWOOD, VIE_ESINGULAR, VIE_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 VIE_TE, VIE_TM = 0, 1
-VIE_FP64, VIE_MIXED_FP32 = 0, 1
+VIE_FP64, VIE_MIXED_FP32, VIE_GRID_FP64 = 0, 1, 2
 
 _STATUS = {0: "VIE_OK", -1: "VIE_EINVAL", -2: "VIE_ESTATE", -3: "VIE_ENOMEM", -4: "VIE_ENOCONV",
            -5: "VIE_EWOOD", -6: "VIE_ESINGULAR", -7: "VIE_EDEVICE"}
@@ -106,6 +106,7 @@ _SIGS = {
     "vie_get_fill_stats": (C.c_int, [C.c_void_p, C.POINTER(FillStats)]),
     "vie_get_factor_stats": (C.c_int, [C.c_void_p, C.POINTER(FactorStats)]),
     "vie_bench_matvec": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double)]),
+    "vie_apply_Z": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "vie_set_option": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "vie_get_option": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
@@ -360,6 +361,15 @@ class Solver:
         t = Tuning()
         self._ck(self.lib.vie_autotune(self.h, int(reps), C.byref(t)))
         return t.as_dict()
+
+    def apply_Z(self, x):
+        """y = Z x with the bound operator of the last fill."""
+        xin = np.ascontiguousarray(x, np.complex128)
+        if len(xin) != self.num_unknowns():
+            raise ValueError("x must have one value per unknown")
+        out = np.zeros(len(xin), np.complex128)
+        self._ck(self.lib.vie_apply_Z(self.h, _p(xin), _p(out)))
+        return out
 
     def bench_matvec(self, reps=10):
         ms = C.c_double()
