@@ -304,14 +304,14 @@ int grid_matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
   if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fin, (hipfftDoubleComplex *)fin, HIPFFT_FORWARD) !=
       HIPFFT_SUCCESS)
     return fail(ctx, VIE_EDEVICE, "grid matvec: forward FFT failed");
-  hipLaunchKernelGGL(k_grid_mul, dim3(nblk(nf, 256), kGridSub), dim3(256), 0, ctx->stream, nf,
+  hipLaunchKernelGGL(k_grid_mul, dim3(nblk(nf, 32)), dim3(256), 0, ctx->stream, nf,
                      (const dz *)ctx->ptr<dz>(L.gtab), (const dz *)fin, fout);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "grid matvec: %s", hipGetErrorString(e));
   if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fout, (hipfftDoubleComplex *)fout, HIPFFT_BACKWARD) !=
       HIPFFT_SUCCESS)
     return fail(ctx, VIE_EDEVICE, "grid matvec: inverse FFT failed");
-  hipLaunchKernelGGL(k_grid_apply, dim3(nblk(t.N, 256)), dim3(256), 0, ctx->stream, (int64_t)t.N, gg,
+  hipLaunchKernelGGL(k_grid_apply, dim3(nblk(t.N, 4)), dim3(256), 0, ctx->stream, (int64_t)t.N, gg,
                      (const int32_t *)ctx->ptr<int32_t>(L.gtet), (const int32_t *)ctx->ptr<int32_t>(L.gface),
                      (const int32_t *)ctx->ptr<int32_t>(L.ghalf), (const int32_t *)ctx->ptr<int32_t>(L.utet),
                      (const int32_t *)ctx->ptr<int32_t>(L.uk), (const TetGeom *)ctx->ptr<TetGeom>(L.tg),

@@ -117,31 +117,54 @@ __global__ __launch_bounds__(256) void k_grid_gather_face(int nface, const GridG
   for (int p = 0; p < 3; ++p) fld[(int64_t)(kGridTetSub + 3 * type + p) * G.nf + slot] = q;
 }
 
-// Per frequency f (x) and test sublattice s (blockIdx.y): the scalar
-// potential from every charge field and, for tetrahedron sublattices, the
-// vector potential from the current fields.
+// Per-frequency products.  A block takes kGridTile frequencies and every
+// test sublattice: the 132 source fields of the tile are staged in LDS once,
+// and each table entry is read once from HBM (the 32 lanes of an s-group
+// read kGridTile consecutive frequencies of one table row).  Thread t owns
+// frequency t % kGridTile of the tile and the sublattices s = t / kGridTile
+// + 8 i: the scalar potential from every charge field and, for tetrahedron
+// sublattices, the vector potential from the current fields.
+constexpr int kGridTile = 32;
 __global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restrict__ tab, const dz *__restrict__ fin,
                                                   dz *__restrict__ fout) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  const int s = blockIdx.y;
-  const dz *K = tab + (int64_t)s * kGridSub * nf + f;
-  dz acc = mk(0.0, 0.0);
-  for (int s2 = 0; s2 < kGridSub; ++s2) acc = acc + K[(int64_t)s2 * nf] * fin[(int64_t)s2 * nf + f];
-  fout[(int64_t)s * nf + f] = acc;
-  if (s < kGridTetSub) {
-    for (int d = 0; d < 3; ++d) {
-      const dz *J = fin + (int64_t)(kGridSub + kGridTetSub * d) * nf + f;
-      dz a = mk(0.0, 0.0);
-      for (int s2 = 0; s2 < kGridTetSub; ++s2) a = a + K[(int64_t)s2 * nf] * J[(int64_t)s2 * nf];
-      fout[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + f] = a;
+  __shared__ dz sf[kGridFields][kGridTile];
+  const int64_t f0 = (int64_t)blockIdx.x * kGridTile;
+  const int nt = (int)min<int64_t>(kGridTile, nf - f0);
+  for (int e = threadIdx.x; e < kGridFields * kGridTile; e += 256) {
+    const int c = e / kGridTile, fi = e % kGridTile;
+    sf[c][fi] = fi < nt ? fin[(int64_t)c * nf + f0 + fi] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int fi = threadIdx.x % kGridTile, sg = threadIdx.x / kGridTile;
+  if (fi >= nt) return;
+  const int64_t f = f0 + fi;
+  for (int s = sg; s < kGridSub; s += 256 / kGridTile) {
+    const dz *K = tab + (int64_t)s * kGridSub * nf + f;
+    dz acc = mk(0.0, 0.0);
+#pragma unroll 4
+    for (int s2 = 0; s2 < kGridSub; ++s2) acc = acc + K[(int64_t)s2 * nf] * sf[s2][fi];
+    fout[(int64_t)s * nf + f] = acc;
+    if (s < kGridTetSub) {
+      dz a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0), a2 = mk(0.0, 0.0);
+#pragma unroll 4
+      for (int s2 = 0; s2 < kGridTetSub; ++s2) {
+        const dz k = K[(int64_t)s2 * nf];
+        a0 = a0 + k * sf[kGridSub + s2][fi];
+        a1 = a1 + k * sf[kGridSub + kGridTetSub + s2][fi];
+        a2 = a2 + k * sf[kGridSub + 2 * kGridTetSub + s2][fi];
+      }
+      fout[(int64_t)(kGridSub + s) * nf + f] = a0;
+      fout[(int64_t)(kGridSub + kGridTetSub + s) * nf + f] = a1;
+      fout[(int64_t)(kGridSub + 2 * kGridTetSub + s) * nf + f] = a2;
     }
   }
 }
 
-// y = Z x (or b - Z x): per unknown m (one thread) the far potentials at the
-// points of its tetrahedra (demodulated by e^{-j kt.o}) and, for a half-SWG
-// face, at its own points, plus its row of the near part (CSR, FP64).
+// y = Z x (or b - Z x), one wave per unknown m: lanes 0-7 the far
+// potentials at the four points of each of m's tetrahedra (demodulated by
+// e^{-j kt.o}), lanes 8-10 those at the three points of m's face when it is a
+// half-SWG face, and all lanes m's row of the near part (CSR, FP64); the wave
+// sum is written by lane 0.
 __global__ __launch_bounds__(256) void k_grid_apply(
     int64_t N, const GridGeom *__restrict__ gg, const int32_t *__restrict__ gtet, const int32_t *__restrict__ gface,
     const int32_t *__restrict__ ghalf, const int32_t *__restrict__ utet, const int32_t *__restrict__ uk,
@@ -149,39 +172,43 @@ __global__ __launch_bounds__(256) void k_grid_apply(
     const dz *__restrict__ fout, double k0sq9, double kx, double ky, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ cols, const dz *__restrict__ vals, const dz *__restrict__ x, const dz *__restrict__ b,
     dz *__restrict__ y) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= N) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= N) return;   // the whole wave
   const GridGeom &G = *gg;
   const int64_t nf = G.nf;
   dz acc = mk(0.0, 0.0);
-  for (int h = 0; h < 2; ++h) {
+  if (lane < 8) {
+    const int h = lane >> 2, q = lane & 3;
     const int T = utet[2 * m + h];
-    if (T < 0) continue;
-    const int k = uk[2 * m + h];
-    const int slot = gtet[2 * T], type = gtet[2 * T + 1];
-    const int bx = slot % G.nx, by = (slot / G.nx) % G.ny, bz = slot / (G.nx * G.ny);
-    const double vk[3] = {tg[T].v[k][0] - (G.org[0] + bx * G.h[0]), tg[T].v[k][1] - (G.org[1] + by * G.h[1]),
-                          tg[T].v[k][2] - (G.org[2] + bz * G.h[2])};
-    dz phi = mk(0.0, 0.0), ra = mk(0.0, 0.0);
-    for (int q = 0; q < 4; ++q) {
+    if (T >= 0) {
+      const int k = uk[2 * m + h];
+      const int slot = gtet[2 * T], type = gtet[2 * T + 1];
+      const int bx = slot % G.nx, by = (slot / G.nx) % G.ny, bz = slot / (G.nx * G.ny);
       const int s = 4 * type + q;
-      phi = phi + fout[(int64_t)s * nf + slot];
-      for (int d = 0; d < 3; ++d)
-        ra = ra + (G.pos[s][d] - vk[d]) * fout[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + slot];
+      dz ra = mk(0.0, 0.0);
+      for (int d = 0; d < 3; ++d) {
+        const double vk = tg[T].v[k][d] - (G.org[d] + (d == 0 ? bx : d == 1 ? by : bz) * G.h[d]);
+        ra = ra + (G.pos[s][d] - vk) * fout[(int64_t)(kGridSub + kGridTetSub * d + s) * nf + slot];
+      }
+      const dz ph = cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]));
+      acc = ((0.25 * tg[T].vol) * alpha[4 * T + k]) * (ph * (fout[(int64_t)s * nf + slot] - k0sq9 * ra));
     }
-    const dz ph = cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]));
-    acc = acc + ((0.25 * tg[T].vol) * alpha[4 * T + k]) * (ph * (phi - k0sq9 * ra));
+  } else if (lane < 11) {
+    const int i = ghalf[m];
+    if (i >= 0) {
+      const int bx = gface[4 * i], by = gface[4 * i + 1], bz = gface[4 * i + 2], type = gface[4 * i + 3];
+      const int64_t slot = bx % G.nx + (int64_t)G.nx * (by % G.ny + (int64_t)G.ny * bz);
+      acc = (-fg[i].area / 3.0 * cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]))) *
+            fout[(int64_t)(kGridTetSub + 3 * type + (lane - 8)) * nf + slot];
+    }
   }
-  const int i = ghalf[m];
-  if (i >= 0) {
-    const int bx = gface[4 * i], by = gface[4 * i + 1], bz = gface[4 * i + 2], type = gface[4 * i + 3];
-    const int64_t slot = bx % G.nx + (int64_t)G.nx * (by % G.ny + (int64_t)G.ny * bz);
-    dz phi = mk(0.0, 0.0);
-    for (int p = 0; p < 3; ++p) phi = phi + fout[(int64_t)(kGridTetSub + 3 * type + p) * nf + slot];
-    acc = acc - (fg[i].area / 3.0 * cexpj(-(kx * bx * G.h[0] + ky * by * G.h[1]))) * phi;
+  for (int64_t e = rowptr[m] + lane; e < rowptr[m + 1]; e += 64) acc = acc + vals[e] * x[cols[e]];
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.re += __shfl_xor(acc.re, o);
+    acc.im += __shfl_xor(acc.im, o);
   }
-  for (int64_t e = rowptr[m]; e < rowptr[m + 1]; ++e) acc = acc + vals[e] * x[cols[e]];
-  y[m] = b ? b[m] - acc : acc;
+  if (lane == 0) y[m] = b ? b[m] - acc : acc;
 }
 
 }  // namespace vie

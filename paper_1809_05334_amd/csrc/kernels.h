@@ -353,7 +353,8 @@ __global__ void k_field(int64_t np, const double *pts, const int32_t *tet, const
                         const dz *gsrc, const dz *inv_eps, const dz *x, dz *e);
 
 // structured-grid far operator (k_grid.hip); grid (ceil(nf / 256), kGridSub^2) for the
-// table, (ceil(nf / 256), kGridSub) for the products
+// table, ceil(nf / 32) blocks for the products, ceil(N / 4) blocks (a wave per unknown)
+// for the apply; 256 threads
 __global__ void k_grid_table(const double *pack, int packlen, const GridGeom *gg, double kx, double ky, double scale,
                              dz *tab);
 __global__ void k_grid_gather_tet(int64_t nt, const GridGeom *gg, const int32_t *gtet, const TetGeom *tg,
