@@ -269,7 +269,8 @@ ZOut zout(vie_ctx *ctx) {
   ZOut o{};
   o.ld = L.ld;
   if (ctx->precision == VIE_MIXED_FP32 || ctx->precision == VIE_GRID_FP64) {
-    // (the grid operator has no dense part: far entries written by a fill kernel are dropped)
+    // (the grid operator has no dense part; its fill launches no far-pair writer but k_face_face,
+    // which then writes only the touching pairs)
     if (ctx->precision == VIE_MIXED_FP32) o.Zs = ctx->ptr<fz>(L.Z);
     o.rowptr = ctx->ptr<int64_t>(L.nrow);
     o.cols = ctx->ptr<int32_t>(L.ncol);

@@ -29,8 +29,7 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // Z[m][n] += v into the destination of this fill (see ZOut).  In mixed
 // precision a far contribution is added to the FP32 entry in FP64 and rounded
-// once; a near one goes to its slot of the sorted CSR row.  With no dense part
-// (the structured-grid operator) a far contribution is dropped.
+// once; a near one goes to its slot of the sorted CSR row.
 __device__ __forceinline__ void zput(const ZOut &o, int64_t m, int64_t n, dz v, bool near) {
   if (o.Z) {
     dz *p = o.Z + m * o.ld + n;
@@ -43,7 +42,7 @@ __device__ __forceinline__ void zput(const ZOut &o, int64_t m, int64_t n, dz v, 
       else hi = mid;
     }
     if (lo < o.rowptr[m + 1] && o.cols[lo] == n) o.vals[lo] = o.vals[lo] + v;
-  } else if (o.Zs) {
+  } else {
     fz *p = o.Zs + m * o.ld + n;
     const fz z = *p;
     *p = fz{(float)((double)z.re + v.re), (float)((double)z.im + v.im)};
@@ -828,7 +827,9 @@ __global__ __launch_bounds__(256, 2) void k_face_tet_near(const double *__restri
   k_face_tet_near_body(pack, packlen, qr, fg, half_list, tg, t2f, pairs, npairs, gsrc, kappa, out, blockIdx.x, blockIdx.y);
 }
 
-// half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0
+// half-SWG test face x surface-charge face: Z[m_F, n_G] += sigma_G M0.  With
+// no dense part in the destination (the structured-grid operator, whose far
+// pairs come from its FFT tables) only the touching pairs are written.
 __device__ __forceinline__ void k_face_face_body(const double *__restrict__ pack, int packlen, const QuadRules *__restrict__ qr,
                                                    const FaceGeom *__restrict__ fg,
                                                    const int32_t *__restrict__ half_list, int nhalf, int nface,
@@ -844,6 +845,7 @@ __device__ __forceinline__ void k_face_face_body(const double *__restrict__ pack
   const FaceGeom g = fg[gi];
   int mask;
   const dz m0 = pair_face_face(s_tab, qr, f, g, mask);
+  if (mask == 0 && !out.Z && !out.Zs) return;
   zput(out, f.unknown, g.unknown, sigma[gi] * m0, mask != 0);
 }
 
