@@ -91,7 +91,7 @@ enum { VIE_TE = 0, VIE_TM = 1 };
  *   the N^2 far entries; a product with Z costs two batched 3D FFTs of 132
  *   fields plus a per-frequency contraction.  Same Z as VIE_FP64 to
  *   rounding.  There is no block preconditioner (vie_precond_factor returns
- *   VIE_EINVAL; solve with VIE_OPT_PRECOND 1), no vie_read_Z (vie_apply_Z
+ *   VIE_EINVAL; solve with VIE_OPT_PRECOND 2, point Jacobi, or 1), no vie_read_Z (vie_apply_Z
  *   gives Z x), no graph-captured steps, no batch and no static workspace.
  *   hipFFT allocates its plans' work areas at bind. */
 enum { VIE_FP64 = 0, VIE_MIXED_FP32 = 1, VIE_GRID_FP64 = 2 };
@@ -314,8 +314,9 @@ enum {
                              * the block-diagonal M of the last vie_precond_factor (Sec. 2.3,
                              * Eq. 6); 1: none, M = I (GMRES on Z x = b, the reference against
                              * which Sec. 3 compares the block preconditioner), for which a
-                             * completed fill suffices.  The iterations and the rounding of x
-                             * differ between the two */
+                             * completed fill suffices; 2: point Jacobi, M = diag(Z) of the last
+                             * fill (also needs only the fill; not in the batch).  The iterations
+                             * and the rounding of x differ between them */
 };
 int vie_set_option(vie_ctx *ctx, int option, int value);
 int vie_get_option(const vie_ctx *ctx, int option, int *value);

@@ -202,6 +202,7 @@ Layout make_layout(const MeshTopology &t, int restart, int64_t nnear, int nface,
     put(k.npart, 8 * kRedBlocks);
     put(k.scal, 64);
   }
+  put(L.jdiag, 16 * (size_t)std::max<int64_t>(1, N));
   put(L.apart, 8 * (size_t)nblk(nt, 256) * std::max(6 * 2 * 32, t.ndom));
   put(L.atet, 8 * (size_t)std::max<int64_t>(1, nt));
   put(L.kv, 8 * 3 * 2 * 32);
@@ -819,6 +820,7 @@ int fill_upload(vie_ctx *ctx) {
   ctx->fill_k0sq9 = k0 * k0 / 9.0;
   ctx->fill_kx = kx;
   ctx->fill_ky = ky;
+  ctx->jdiag_ok = false;
   ctx->fill_lds = 8 * (size_t)ctx->packlen;
 
   hipLaunchKernelGGL(k_prep, dim3(nblk(t.nt, 256)), dim3(256), 0, ctx->stream, (int64_t)t.nt, t2f, tg,
@@ -1728,6 +1730,10 @@ int arnoldi_step(vie_ctx *ctx, int mask) {
   }
   if (ctx->precond == 0) {
     if (int rc = apply_minv_n(ctx, np, vin, z, tmp, u)) return rc;
+  } else if (ctx->precond == 2) {
+    for (int i = 0; i < np; ++i)
+      hipLaunchKernelGGL(k_jacobi_apply, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, N,
+                         (const dz *)ctx->ptr<dz>(L.jdiag), vin[i], z[i]);
   } else {
     for (int i = 0; i < np; ++i) z[i] = const_cast<dz *>(vin[i]);   // M = I: the product takes V_j itself
   }
@@ -1925,6 +1931,10 @@ int gmres(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int restart)
     }
     if (ctx->precond == 0) {
       if (int rc = apply_minv_n(ctx, nc, wv, uv, tv, zv)) return rc;
+    } else if (ctx->precond == 2) {
+      for (int q = 0; q < nc; ++q)
+        hipLaunchKernelGGL(k_jacobi_apply, dim3(nblk(N, 256)), dim3(256), 0, ctx->stream, N,
+                           (const dz *)ctx->ptr<dz>(L.jdiag), wv[q], uv[q]);
     } else {
       for (int q = 0; q < nc; ++q) uv[q] = const_cast<dz *>(wv[q]);   // M = I: x += V y
     }
@@ -1997,12 +2007,21 @@ int run_solve(vie_ctx *ctx, int np, Gmres *P, double tol, int max_iter, int rest
 
 }  // namespace vie
 
-// The grid operator solves with M = I and plain launches (its FFTs are not
-// captured into the Arnoldi-step graphs).
-static int grid_solve_args(vie_ctx *ctx) {
+// Before a solve: the point-Jacobi scaling of this fill (once) when that
+// preconditioner is chosen; the grid operator solves with M = diag(Z) or
+// M = I and plain launches (its FFTs are not captured into the Arnoldi-step
+// graphs).
+static int solve_setup(vie_ctx *ctx) {
+  if (ctx->precond == 2 && !ctx->jdiag_ok) {
+    HIPCK(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_jacobi_diag, dim3(nblk(ctx->topo.N, 256)), dim3(256), 0, ctx->stream, (int64_t)ctx->topo.N,
+                       zout(ctx), ctx->ptr<dz>(ctx->L.jdiag));
+    LAUNCHCK();
+    ctx->jdiag_ok = true;
+  }
   if (ctx->precision != VIE_GRID_FP64) return VIE_OK;
   if (ctx->precond == 0)
-    return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 has no block preconditioner: set VIE_OPT_PRECOND to 1");
+    return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 has no block preconditioner: set VIE_OPT_PRECOND to 2 or 1");
   if (ctx->graph_steps > 0) return fail(ctx, VIE_EINVAL, "VIE_GRID_FP64 runs without graph-captured steps");
   return VIE_OK;
 }
@@ -2011,7 +2030,7 @@ extern "C" {
 
 int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_solve_info *info) {
   if (int r = check(ctx, S_FILLED, "vie_solve")) return r;
-  if (int r = grid_solve_args(ctx)) return r;
+  if (int r = solve_setup(ctx)) return r;
   if (!ctx->precond && !ctx->factored)
     return fail(ctx, VIE_ESTATE, "vie_solve: the block preconditioner needs vie_precond_factor after the fill");
   if (pol != VIE_TE && pol != VIE_TM) return fail(ctx, VIE_EINVAL, "polarisation must be VIE_TE or VIE_TM");
@@ -2024,7 +2043,7 @@ int vie_solve(vie_ctx *ctx, int pol, double tol, int max_iter, int restart, vie_
 
 int vie_solve_pair(vie_ctx *ctx, double tol, int max_iter, int restart, vie_solve_info *info) {
   if (int r = check(ctx, S_FILLED, "vie_solve_pair")) return r;
-  if (int r = grid_solve_args(ctx)) return r;
+  if (int r = solve_setup(ctx)) return r;
   if (!ctx->precond && !ctx->factored)
     return fail(ctx, VIE_ESTATE, "vie_solve_pair: the block preconditioner needs vie_precond_factor after the fill");
   if (int r = solve_args(ctx, tol, max_iter, restart)) return r;
@@ -2376,7 +2395,8 @@ int vie_set_option(vie_ctx *ctx, int option, int value) {
       ctx->sym_fill = value;
       return VIE_OK;
     case VIE_OPT_PRECOND:
-      if (value != 0 && value != 1) return fail(ctx, VIE_EINVAL, "preconditioner: 0 (block-diagonal LU) or 1 (none)");
+      if (value < 0 || value > 2)
+        return fail(ctx, VIE_EINVAL, "preconditioner: 0 (block-diagonal LU), 1 (none) or 2 (point Jacobi)");
       if (value != ctx->precond) drop_graphs(ctx);
       ctx->precond = value;
       return VIE_OK;

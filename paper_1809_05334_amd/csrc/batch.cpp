@@ -628,6 +628,7 @@ int vie_batch_solve(vie_batch *b, const int *polarisation, double tol, int max_i
   for (int c = 0; c < nc; ++c) {
     vie_ctx *x = b->cells[c];
     if (polarisation[c] != VIE_TE && polarisation[c] != VIE_TM) return bfail(b, VIE_EINVAL, "bad polarisation");
+    if (x->precond == 2) return bfail(b, VIE_EINVAL, "cell %d: the point-Jacobi preconditioner is not batched", c);
     if (restart < 1 || restart > x->L.restart) return bfail(b, VIE_EINVAL, "restart exceeds cell %d's workspace", c);
   }
   BCK(hipStreamSynchronize(b->stream));   // the previous solve's tables are no longer read

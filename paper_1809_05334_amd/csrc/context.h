@@ -41,6 +41,7 @@ struct Layout {
   // structured-grid operator (VIE_GRID_FP64): geometry, element maps, kernel
   // tables (kGridSub^2 x nf), source and potential fields (kGridFields x nf)
   Region ggeo, gtet, gface, ghalf, gtab, gin, gout;
+  Region jdiag;   // 1 / Z_mm of the last fill (point-Jacobi preconditioner)
   int plan_steps = 0;   // TrsvStep entries of one cooperative plan
   // one GMRES process per polarisation of a paired solve (K[0] alone otherwise)
   struct Kry {
@@ -141,6 +142,7 @@ struct vie_ctx {
   GridHost *grid = nullptr;
   std::string grid_err;
   hipfftHandle fft_tab = 0, fft_fld = 0;
+  bool jdiag_ok = false;            // jdiag holds the last fill's 1 / Z_mm
   double t_fill = 0, t_factor = 0;
 
   template <class T>

@@ -285,6 +285,33 @@ __global__ void k_axpy(dz *__restrict__ x, const dz *__restrict__ u, int64_t N) 
   if (k < N) x[k] = x[k] + u[k];
 }
 
+// 1 / Z_mm (one thread per row).  Z_mm sums the dense entry (FP64, or the
+// FP32 far part) and the row's CSR slot for column m when there is a near
+// part; a zero diagonal (no physical operator has one) leaves the row unscaled.
+__global__ void k_jacobi_diag(int64_t N, ZOut Z, dz *__restrict__ dinv) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  dz d = mk(0.0, 0.0);
+  if (Z.Z) d = Z.Z[m * Z.ld + m];
+  if (Z.Zs) d = mk((double)Z.Zs[m * Z.ld + m].re, (double)Z.Zs[m * Z.ld + m].im);
+  if (Z.rowptr) {
+    int64_t lo = Z.rowptr[m], hi = Z.rowptr[m + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (Z.cols[mid] < m) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < Z.rowptr[m + 1] && Z.cols[lo] == m) d = d + Z.vals[lo];
+  }
+  const double den = d.re * d.re + d.im * d.im;
+  dinv[m] = den > 0.0 ? mk(d.re / den, -d.im / den) : mk(1.0, 0.0);
+}
+
+__global__ void k_jacobi_apply(int64_t N, const dz *__restrict__ dinv, const dz *__restrict__ v, dz *__restrict__ z) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < N) z[m] = dinv[m] * v[m];
+}
+
 __global__ void k_fill_const(dz *__restrict__ x, int64_t N, double re, double im) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < N) x[k] = mk(re, im);

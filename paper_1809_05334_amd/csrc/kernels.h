@@ -327,6 +327,11 @@ __global__ void k_norm2(const dz *w, int64_t N, double *part);
 __global__ void k_norm_reduce(const double *part, int nblk, double *out);
 __global__ void k_scale(const dz *w, const double *nrm, dz *v, int64_t N);
 __global__ void k_axpy(dz *x, const dz *u, int64_t N);
+// point-Jacobi preconditioner: dinv = 1 / Z_mm from the stored operator (dense
+// entry, or the FP32 dense part plus the CSR near part, or the CSR alone),
+// and z = dinv v
+__global__ void k_jacobi_diag(int64_t N, ZOut Z, dz *dinv);
+__global__ void k_jacobi_apply(int64_t N, const dz *dinv, const dz *v, dz *z);
 __global__ void k_copy(dz *d, const dz *s, int64_t N);
 __global__ void k_fill_const(dz *x, int64_t N, double re, double im);
 __global__ void k_backsolve(const dz *H, int ldh, int k, const dz *g, dz *y);

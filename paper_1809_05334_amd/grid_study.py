@@ -6,9 +6,11 @@ r = 20 nm centred in the spacer), a = b = `--a`, every brick `--h` on a side
 (16 x 16 x 24 bricks, N = 74,240 at a = 80 nm, h = 5 nm).  Per operator: the
 fill time, the time of one product Z x (`--reps` back to back), the
 workspace, and a paired TE + TM solve (GMRES(`--restart`), tol `--tol`): the
-grid operator with M = I (it stores no diagonal blocks), the dense ones with
-the block-diagonal preconditioner (Sec. 2.3) and, with `--dense-identity`,
-with M = I too.  Absorptances are compared with the FP64 dense solve.
+grid operator with the forms in `--grid-precond` (identity, M = I, and/or
+jacobi, M = diag(Z); it stores no diagonal blocks), the dense ones with the
+block-diagonal preconditioner (Sec. 2.3) and the forms in `--dense-extra`.
+Absorptances are compared with the FP64 dense solve; the summary line takes
+the first grid form.
 
 One JSON line per operator, then one with the grid operator's speedups.
 
@@ -29,7 +31,7 @@ def run(vie, mesh, prec, precond, args, eps):
     s = vie.Solver()
     N = s.upload_mesh(mesh)
     ws = s.bind(prec, args.restart)
-    s.set_option(vie.VIE_OPT_PRECOND, 0 if precond == "block" else 1)
+    s.set_option(vie.VIE_OPT_PRECOND, {"block": 0, "identity": 1, "jacobi": 2}[precond])
     t0 = time.perf_counter()
     s.fill(args.lam, args.theta, args.phi, eps)
     torch.cuda.synchronize()
@@ -69,7 +71,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=4000)
     ap.add_argument("--operators", default="grid,mixed,fp64")
     ap.add_argument("--solve", action="store_true")
-    ap.add_argument("--dense-identity", action="store_true")
+    ap.add_argument("--grid-precond", default="identity", help="comma list of identity, jacobi")
+    ap.add_argument("--dense-extra", default="", help="comma list of jacobi, identity (besides block)")
     args = ap.parse_args()
 
     from . import vie
@@ -80,13 +83,14 @@ def main():
     rows = []
     for name in args.operators.split(","):
         prec = code[name]
-        runs = ["identity"] if prec == vie.VIE_GRID_FP64 else (["block", "identity"] if args.dense_identity else ["block"])
+        extra = [e for e in args.dense_extra.split(",") if e]
+        runs = args.grid_precond.split(",") if prec == vie.VIE_GRID_FP64 else ["block"] + extra
         for pc in runs:
             r = run(vie, mesh, prec, pc, args, eps)
             rows.append(r)
             print(json.dumps(r), flush=True)
     ref = next((r for r in rows if r["operator"] == "fp64" and r["precond"] == "block"), None)
-    grid = next((r for r in rows if r["operator"] == "grid"), None)
+    grid = next((r for r in rows if r["operator"] == "grid"), None)   # the first grid form
     if grid and ref:
         summary = {"summary": "grid vs fp64", "N": grid["N"], "fill_speedup": ref["fill_ms"] / grid["fill_ms"],
                    "matvec_speedup": ref["matvec_ms"] / grid["matvec_ms"],

@@ -9,7 +9,8 @@ with the lattice sums of Sec. 2.2, Eqs. 3-4), so:
     oblique incidence, with one domain and with interface surface charges
     (several domains) and half-SWG boundary faces; the bar 1e-10 relative in
     the 2-norm (FFT and rounding-order differences only);
-  * a solve with M = I gives the dense path's absorptance, R and T;
+  * a solve with M = I or M = diag(Z) gives the dense path's iterations,
+    absorptance, R and T;
   * meshes that are not uniform Kuhn grids, and the calls the operator does
     not offer, are refused with VIE_EINVAL.
 """
@@ -107,19 +108,24 @@ def test_grid_matches_dense_with_interfaces(vie, lam, th, ph):
         assert rel(g.apply_Z(e), Zd[:, j]) < 1e-10
 
 
-def test_grid_solve_matches_dense(vie):
+@pytest.mark.parametrize("precond", [1, 2])
+def test_grid_solve_matches_dense(vie, precond):
+    """With M = I (1) or M = diag(Z) (2) the grid and dense operators run the
+    same method on the same Z: same iterations, same absorptance, R, T."""
     m = layered_grid()
     eps = eps_of(m)
     lam, th, ph = 520.0, 0.4, 0.7
-    out = {}
+    out, its = {}, {}
     for prec in (vie.VIE_GRID_FP64, vie.VIE_FP64):
         s, N = solver(vie, m, prec, restart=120)
-        s.set_option(vie.VIE_OPT_PRECOND, 1)
+        s.set_option(vie.VIE_OPT_PRECOND, precond)
         s.fill(lam, th, ph, eps)
         infos = s.solve_pair(tol=1e-11, max_iter=3000)
         assert all(i["converged"] for i in infos)
         out[prec] = [s.absorption(pol=p) for p in (0, 1)]
-        print(f"  precision {prec}: iterations {[i['iters'] for i in infos]}", flush=True)
+        its[prec] = [i["iters"] for i in infos]
+        print(f"  precision {prec}, preconditioner {precond}: iterations {its[prec]}", flush=True)
+    assert all(abs(a - b) <= 1 for a, b in zip(its[vie.VIE_GRID_FP64], its[vie.VIE_FP64]))
     for p in (0, 1):
         (Ag, Rg, Tg), (Ad, Rd, Td) = out[vie.VIE_GRID_FP64][p], out[vie.VIE_FP64][p]
         assert np.max(np.abs(np.asarray(Ag) - np.asarray(Ad))) < 1e-8

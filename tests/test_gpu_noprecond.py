@@ -1,5 +1,7 @@
 """GMRES without a preconditioner (VIE_OPT_PRECOND = 1, M = I): the reference
-against which Sec. 3 (Figs. 2-3) measures the block-diagonal preconditioner.
+against which Sec. 3 (Figs. 2-3) measures the block-diagonal preconditioner;
+and with the point-Jacobi scaling M = diag(Z) (VIE_OPT_PRECOND = 2) against
+the oracle's GMRES with 1 x 1 diagonal blocks.
 
 The library's unpreconditioned solve is compared with the oracle's GMRES on
 the same Z with no blocks (M = I): iteration count, the residual history's
@@ -113,6 +115,37 @@ def test_no_precond_graph_replays_match_plain(vie, case):
 def test_precond_option_checks(vie):
     s = vie.Solver()
     assert s.get_option(vie.VIE_OPT_PRECOND) == 0
-    with pytest.raises(vie.VieError) as e:
-        s.set_option(vie.VIE_OPT_PRECOND, 2)
-    assert e.value.code == vie.VIE_EINVAL
+    for bad in (3, -1):
+        with pytest.raises(vie.VieError) as e:
+            s.set_option(vie.VIE_OPT_PRECOND, bad)
+        assert e.value.code == vie.VIE_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_jacobi_matches_oracle(vie, case, prec):
+    """VIE_OPT_PRECOND = 2, M = diag(Z): the oracle's right-preconditioned
+    GMRES with 1 x 1 diagonal blocks is the same method on the same Z."""
+    m, lam, eps, t, wave, Zo = case
+    tol, restart = 1e-8, 60
+    ones = [(i, i + 1) for i in range(t.N)]
+    s = vie.Solver()
+    s.upload_mesh(m)
+    s.bind(vie.VIE_FP64 if prec == "fp64" else vie.VIE_MIXED_FP32, restart)
+    s.set_option(vie.VIE_OPT_PRECOND, 2)
+    s.fill(lam, 0.0, 0.0, eps)   # no factorisation: M = diag(Z) needs none
+    for pol in (0, 1):
+        xo, it, hist, ok = OV.gmres_right_block(Zo, OV.rhs(t, wave, pol), ones, tol=tol, restart=restart, maxit=2000)
+        assert ok
+        _, it_none, _, _ = OV.gmres_right_block(Zo, OV.rhs(t, wave, pol), [], tol=tol, restart=restart, maxit=2000)
+        info = s.solve(pol, tol=tol, max_iter=2000, restart=restart)
+        print(f"  {prec} pol {pol}: jacobi {info['iters']} iterations (oracle {it}, oracle with M = I {it_none})",
+              flush=True)
+        assert info["converged"] and abs(info["iters"] - it) <= 2, (pol, info["iters"], it)
+        assert it < it_none
+        x = s.read_solution()
+        bar = 1e-5 if prec == "fp64" else 1e-4
+        assert np.linalg.norm(x - xo) < bar * np.linalg.norm(xo), pol
+        if prec == "fp64":
+            h = s.residual_history()
+            n = min(40, len(h), len(hist))
+            assert np.allclose(h[:n], hist[:n], rtol=1e-6, atol=0)
