@@ -1,6 +1,7 @@
 // Host-side driver for the sanitizer test (tests/test_host_sanitize.py): runs
 // the library's host C++ (mesh topology and validation, near-pair pattern,
-// point location, quadrature rules, lattice-sum tables and their packing) on
+// point location, quadrature rules, lattice-sum tables and their packing, the
+// structured-grid analysis) on
 // one mesh read from a binary file, built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by g++ (no device code is involved).
 //
@@ -14,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "grid.h"
 #include "host.h"
 
 using namespace vie;
@@ -80,5 +82,29 @@ int main(int argc, char **argv) {
                 pack.size(), margin);
     delete tab;
   }
+
+  // structured-grid analysis: a uniform Kuhn grid or the reason it is not;
+  // on a grid, the corner-sharing table is symmetric under swapping the two
+  // elements and negating the offset, every element shares a corner with
+  // itself, and every sublattice point lies in its brick
+  GridHost G;
+  err = analyse_grid(t, q, G);
+  if (!err.empty()) {
+    std::printf("grid none: %s\n", err.c_str());
+    return 0;
+  }
+  for (int e = 0; e < kGridEnt; ++e) {
+    if (!G.g.touch[e][e][13]) return 5;
+    for (int e2 = 0; e2 < kGridEnt; ++e2)
+      for (int o = 0; o < 27; ++o)
+        if (G.g.touch[e][e2][o] != G.g.touch[e2][e][26 - o]) return 6;
+  }
+  for (int s = 0; s < kGridSub; ++s)
+    for (int d = 0; d < 3; ++d)
+      if (G.g.pos[s][d] < 0 || G.g.pos[s][d] > G.g.h[d]) return 7;
+  int sharing = 0;
+  for (int o = 0; o < 27; ++o) sharing += G.g.touch[0][0][o];
+  std::printf("grid %d %d %d nf %lld faces %zu sharing %d\n", G.g.nx, G.g.ny, G.g.nz, (long long)G.g.nf,
+              G.face.size() / 4, sharing);
   return 0;
 }

@@ -1,10 +1,12 @@
 """The library's host C++ under AddressSanitizer and UndefinedBehaviorSanitizer.
 
 tests/host_check.cpp drives mesh topology and validation, the near-pair
-pattern, point location, the quadrature rules and the lattice-sum tables on
-seeded meshes; g++ builds it with the host sources and -fsanitize=address,
-undefined (no device code).  The run must end cleanly, and the unknown count
-must equal the oracle's topology for the same mesh."""
+pattern, point location, the quadrature rules, the lattice-sum tables and the
+structured-grid analysis on seeded meshes; g++ builds it with the host
+sources and -fsanitize=address,undefined (no device code).  The run must end
+cleanly, the unknown count must equal the oracle's topology for the same
+mesh, graded meshes must be refused by the grid analysis and uniform Kuhn
+grids accepted with their brick counts and surface-charge faces."""
 import os
 import shutil
 import struct
@@ -28,6 +30,7 @@ def driver(tmp_path_factory):
     cmd = ["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-I", CSRC, "-I", os.path.join(os.path.dirname(HERE), "include"),
            os.path.join(HERE, "host_check.cpp"), os.path.join(CSRC, "topology.cpp"), os.path.join(CSRC, "tables.cpp"),
+           os.path.join(CSRC, "grid.cpp"),
            "-o", out, "-lpthread"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     assert p.returncode == 0, p.stderr[-3000:]
@@ -51,6 +54,13 @@ def meshes():
     dom[np.sum((c - [20.0, 20.0, 30.0]) ** 2, 1) <= 8.0 ** 2] = 2
     yield "three-domain", W.Mesh(verts, tets, dom, 3, 40.0, 40.0, (xs, xs, zs))
     yield "slab", W.slab_mesh()
+    xs = np.linspace(0.0, 20.0, 6)                          # uniform 4 nm grid, three domains
+    zs = np.linspace(0.0, 24.0, 7)
+    verts, tets = W.brick_grid_mesh(xs, xs, zs)
+    c = W.centroids(verts, tets)
+    dom = np.where(c[:, 2] < 12.0, 2, 1).astype(np.int32)
+    dom[np.sum((c - [10.0, 10.0, 18.0]) ** 2, 1) <= 5.0 ** 2] = 0
+    yield "uniform three-domain", W.Mesh(verts, tets, dom, 3, 20.0, 20.0, (xs, xs, zs))
     yield "batch cell", W.cell_mesh(W.batch_cells(1, seed=3, n_lo=2000, n_hi=3000)[0])
 
 
@@ -67,3 +77,15 @@ def test_host_code_is_clean_under_sanitizers(driver, tmp_path, name, mesh):
     first = p.stdout.splitlines()[0].split()
     assert int(first[1]) == topo.N
     assert p.stdout.count("table lambda") == 3
+    last = p.stdout.splitlines()[-1].split()
+    if name == "three-domain":
+        assert last[:2] == ["grid", "none:"]
+    elif name in ("slab", "uniform three-domain"):
+        nx, ny, nz = (len(v) - 1 for v in mesh.grid)
+        assert last[0] == "grid" and [int(v) for v in last[1:4]] == [nx, ny, nz]
+        assert int(last[5]) == nx * ny * 2 * (nz + 1)
+        # surface-charge faces: interfaces between domains and the structure's top and bottom
+        assert int(last[7]) == sum(1 for f in range(topo.N)
+                                   if topo.tminus[f] < 0 or topo.fdom[f] != mesh.tet_domain[topo.tminus[f]]
+                                   or mesh.tet_domain[topo.tplus[f]] != mesh.tet_domain[topo.tminus[f]])
+        assert int(last[9]) > 1
