@@ -7,8 +7,10 @@ with the lattice sums of Sec. 2.2, Eqs. 3-4), so:
   * Z x through the grid operator equals the oracle's Z x (oracle Z assembled
     here) and the dense FP64 path's Z x on the same seeded x, at normal and
     oblique incidence, with one domain and with interface surface charges
-    (several domains) and half-SWG boundary faces; the bar 1e-10 relative in
-    the 2-norm (FFT and rounding-order differences only);
+    (several domains) and half-SWG boundary faces, on the smallest grid (two
+    bricks per period, one layer), on a diffracting cell and on unequal x and
+    y; the bar 1e-10 relative in the 2-norm (FFT and rounding-order
+    differences only);
   * a solve with M = I or M = diag(Z) gives the dense path's iterations,
     absorptance, R and T;
   * meshes that are not uniform Kuhn grids, and the calls the operator does
@@ -106,6 +108,36 @@ def test_grid_matches_dense_with_interfaces(vie, lam, th, ph):
     for j in (0, N // 2, N - 1):
         e = np.zeros(N, complex); e[j] = 1.0
         assert rel(g.apply_Z(e), Zd[:, j]) < 1e-10
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def uniform_grid(nx, ny, nz, a, b, c, split=True):
+    xs = np.linspace(0.0, a, nx + 1); ys = np.linspace(0.0, b, ny + 1); zs = np.linspace(0.0, c, nz + 1)
+    verts, tets = W.brick_grid_mesh(xs, ys, zs)
+    cen = W.centroids(verts, tets)
+    dom = (cen[:, 0] > a / 2).astype(np.int32) if split else np.zeros(len(tets), np.int32)
+    return W.Mesh(verts, tets, dom, 2 if split else 1, a, b, (xs, ys, zs))
+
+
+@pytest.mark.parametrize("name,mesh,lam,th,ph", [
+    # two bricks per period and one layer: offsets +1 and -1 are the same ring offset
+    ("2x2x1", lambda: uniform_grid(2, 2, 1, 40.0, 40.0, 20.0), 500.0, 0.5, 0.2),
+    # a = b = 300 nm at 400 nm, theta 0.7: non-specular Floquet orders propagate
+    ("diffracting", lambda: uniform_grid(3, 3, 2, 300.0, 300.0, 100.0), 400.0, 0.7, 0.3),
+    # unequal bricks and counts in x and y, one domain
+    ("5x2x3", lambda: uniform_grid(5, 2, 3, 70.0, 30.0, 45.0, split=False), 650.0, 0.9, 1.2),
+])
+def test_grid_edge_cases_match_dense(vie, name, mesh, lam, th, ph):
+    m = mesh()
+    eps = np.array([2.4 + 0.2j, 3.3 + 0.05j])[m.tet_domain]
+    g, N = solver(vie, m, vie.VIE_GRID_FP64)
+    d, _ = solver(vie, m, vie.VIE_FP64)
+    g.fill(lam, th, ph, eps)
+    d.fill(lam, th, ph, eps)
+    x = seeded_x(N, 9)
+    err = rel(g.apply_Z(x), d.apply_Z(x))
+    print(f"grid {name} N={N}: |Zx_grid - Zx_dense| / |Zx_dense| = {err:.3e}", flush=True)
+    assert err < 1e-10
 
 
 @pytest.mark.parametrize("precond", [1, 2])
