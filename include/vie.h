@@ -386,7 +386,9 @@ int vie_residual_history(const vie_ctx *ctx, double *hist, int cap);
 
 /* Timing and work counts of the last vie_fill.  Device times come from HIP
  * events on the context's stream around each kernel family.  far_pairs counts
- * the tetrahedron pairs the far kernel evaluated; far_flops is
+ * the tetrahedron pairs the far kernel evaluated (0 with VIE_GRID_FP64, whose
+ * far part is tabulated per sublattice pair: the table build counts in
+ * t_face_ms); far_flops is
  * the algorithmic work of the far tetrahedron-pair kernel under the cost model
  * stated in the library source (FMA = 2 FLOPs, per-term operation counts of
  * the lattice-sum evaluation with the fitted degrees of this fill). */

@@ -1036,6 +1036,13 @@ int fill_finish(vie_ctx *ctx, bool timed) {
   st.far_symmetric = sym ? 1 : 0;
   st.point_pair_flops = pp;
   st.far_flops = (double)st.far_pairs * (16.0 * pp + (sym ? 2400.0 : 1200.0) + (sym && rev ? 16.0 * 36 : 0.0));
+  if (ctx->precision == VIE_GRID_FP64) {
+    // no far pair is evaluated: the far part lives in the FFT tables; only the
+    // touching face pairs of the face-face kernel write anything
+    st.far_pairs = 0;
+    st.far_flops = 0;
+    st.face_pairs = (int64_t)ctx->nhalf * ctx->nface;
+  }
   st.nimg = tb.nimg;
   st.nmode = nmodes;
   ctx->state = S_FILLED;
