@@ -84,6 +84,7 @@ def test_grid_matches_oracle_on_slab(vie, lam, th, ph):
     Zo = OV.assemble(t, OV.make_wave(lam, th, ph), eps)
     err = rel(y, Zo @ x)
     print(f"  |Zx - Zo x| / |Zo x| = {err:.3e}", flush=True)
+    s.close()
     assert err < 1e-10
 
 
@@ -108,6 +109,7 @@ def test_grid_matches_dense_with_interfaces(vie, lam, th, ph):
     for j in (0, N // 2, N - 1):
         e = np.zeros(N, complex); e[j] = 1.0
         assert rel(g.apply_Z(e), Zd[:, j]) < 1e-10
+    g.close(); d.close()
 
 
 @pytest.mark.parametrize("precond", [1, 2])
@@ -136,6 +138,7 @@ def test_grid_edge_cases_match_dense(vie, name, mesh, lam, th, ph):
     d.fill(lam, th, ph, eps)
     x = seeded_x(N, 9)
     err = rel(g.apply_Z(x), d.apply_Z(x))
+    g.close(); d.close()
     print(f"grid {name} N={N}: |Zx_grid - Zx_dense| / |Zx_dense| = {err:.3e}", flush=True)
     assert err < 1e-10
 
@@ -156,6 +159,7 @@ def test_grid_solve_matches_dense(vie, precond):
         assert all(i["converged"] for i in infos)
         out[prec] = [s.absorption(pol=p) for p in (0, 1)]
         its[prec] = [i["iters"] for i in infos]
+        s.close()
         print(f"  precision {prec}, preconditioner {precond}: iterations {its[prec]}", flush=True)
     assert all(abs(a - b) <= 1 for a, b in zip(its[vie.VIE_GRID_FP64], its[vie.VIE_FP64]))
     for p in (0, 1):
@@ -185,6 +189,7 @@ def test_grid_refusals(vie):
     with pytest.raises(vie.VieError) as e:
         g.solve(0, tol=1e-8)
     assert e.value.code == vie.VIE_EINVAL
+    g.close(); s.close()
 
 
 def test_new_mesh_on_a_context_rebuilds_the_near_pattern(vie):
@@ -200,4 +205,6 @@ def test_new_mesh_on_a_context_rebuilds_the_near_pattern(vie):
     for c in (s, f):
         c.fill(600.0, 0.3, 0.2, eps_of(m2))
     x = seeded_x(N, 5)
-    assert np.array_equal(s.apply_Z(x), f.apply_Z(x))
+    same = np.array_equal(s.apply_Z(x), f.apply_Z(x))
+    s.close(); f.close()
+    assert same
