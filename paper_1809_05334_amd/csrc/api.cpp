@@ -254,8 +254,9 @@ const std::string &ensure_grid(vie_ctx *ctx) {
 
 void release_fft(vie_ctx *ctx) {
   if (ctx->fft_tab) (void)hipfftDestroy(ctx->fft_tab);
+  if (ctx->fft_tab_sym) (void)hipfftDestroy(ctx->fft_tab_sym);
   if (ctx->fft_fld) (void)hipfftDestroy(ctx->fft_fld);
-  ctx->fft_tab = ctx->fft_fld = 0;
+  ctx->fft_tab = ctx->fft_tab_sym = ctx->fft_fld = 0;
 }
 
 void release_grid(vie_ctx *ctx) {
@@ -306,8 +307,13 @@ int grid_matvec(vie_ctx *ctx, const dz *x, const dz *b, dz *y) {
   if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fin, (hipfftDoubleComplex *)fin, HIPFFT_FORWARD) !=
       HIPFFT_SUCCESS)
     return fail(ctx, VIE_EDEVICE, "grid matvec: forward FFT failed");
-  hipLaunchKernelGGL(k_grid_mul, dim3(nblk(nf, 32)), dim3(256), 0, ctx->stream, nf,
-                     (const dz *)ctx->ptr<dz>(L.gtab), (const dz *)fin, fout);
+  const GridGeom &G = ctx->grid->g;
+  if (ctx->grid_sym)
+    hipLaunchKernelGGL(k_grid_mul_sym, dim3(nblk(nf, 32)), dim3(256), 0, ctx->stream, nf, G.nx, G.ny, G.pz,
+                       (const dz *)ctx->ptr<dz>(L.gtab), (const dz *)fin, fout);
+  else
+    hipLaunchKernelGGL(k_grid_mul, dim3(nblk(nf, 32)), dim3(256), 0, ctx->stream, nf,
+                       (const dz *)ctx->ptr<dz>(L.gtab), (const dz *)fin, fout);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, VIE_EDEVICE, "grid matvec: %s", hipGetErrorString(e));
   if (hipfftExecZ2Z(ctx->fft_fld, (hipfftDoubleComplex *)fout, (hipfftDoubleComplex *)fout, HIPFFT_BACKWARD) !=
@@ -436,7 +442,7 @@ int vie_set_stream(vie_ctx *ctx, void *hip_stream) {
   // before the workspace is bound the context has issued no device work
   if (ctx->state >= S_BOUND) HIPCK(hipStreamSynchronize(ctx->stream));
   ctx->stream = (hipStream_t)hip_stream;
-  for (hipfftHandle h : {ctx->fft_tab, ctx->fft_fld})
+  for (hipfftHandle h : {ctx->fft_tab, ctx->fft_tab_sym, ctx->fft_fld})
     if (h && hipfftSetStream(h, ctx->stream) != HIPFFT_SUCCESS) return fail(ctx, VIE_EDEVICE, "hipfftSetStream failed");
   return VIE_OK;
 }
@@ -688,9 +694,12 @@ int bind_impl(vie_ctx *ctx, void *dev_ptr, size_t bytes, int precision, int rest
     const int nf = (int)G.g.nf;
     if (hipfftPlanMany(&ctx->fft_tab, 3, n3, nullptr, 1, nf, nullptr, 1, nf, HIPFFT_Z2Z, kGridSub * kGridSub) !=
             HIPFFT_SUCCESS ||
+        hipfftPlanMany(&ctx->fft_tab_sym, 3, n3, nullptr, 1, nf, nullptr, 1, nf, HIPFFT_Z2Z, kGridSymPairs) !=
+            HIPFFT_SUCCESS ||
         hipfftPlanMany(&ctx->fft_fld, 3, n3, nullptr, 1, nf, nullptr, 1, nf, HIPFFT_Z2Z, kGridFields) !=
             HIPFFT_SUCCESS ||
         hipfftSetStream(ctx->fft_tab, ctx->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(ctx->fft_tab_sym, ctx->stream) != HIPFFT_SUCCESS ||
         hipfftSetStream(ctx->fft_fld, ctx->stream) != HIPFFT_SUCCESS) {
       release_fft(ctx);
       return fail(ctx, VIE_EDEVICE, "hipFFT plans for the grid operator could not be made");
@@ -956,16 +965,19 @@ int fill_kernels(vie_ctx *ctx) {
     }
   }
   if (grid) {
-    // kernel tables of every sublattice pair, scaled by 1/nf for the
+    // kernel tables of every sublattice pair (at normal incidence, where g_p
+    // is even, of the pairs s <= s' only), scaled by 1/nf for the
     // unnormalised inverse transform, then transformed in place
     const int64_t nf = ctx->grid->g.nf;
+    const bool sym = ctx->fill_kx == 0.0 && ctx->fill_ky == 0.0;
+    ctx->grid_sym = sym;
     dz *tab = ctx->ptr<dz>(L.gtab);
-    hipLaunchKernelGGL(k_grid_table, dim3(nblk(nf, 256), kGridSub * kGridSub), dim3(256), lds, ctx->stream, pk_, pkl,
-                       (const GridGeom *)ctx->ptr<GridGeom>(L.ggeo), ctx->fill_kx, ctx->fill_ky, 1.0 / (double)nf,
-                       tab);
+    hipLaunchKernelGGL(k_grid_table, dim3(nblk(nf, 256), sym ? kGridSymPairs : kGridSub * kGridSub), dim3(256), lds,
+                       ctx->stream, pk_, pkl, (const GridGeom *)ctx->ptr<GridGeom>(L.ggeo), ctx->fill_kx, ctx->fill_ky,
+                       1.0 / (double)nf, sym ? 1 : 0, tab);
     LAUNCHCK();
-    if (hipfftExecZ2Z(ctx->fft_tab, (hipfftDoubleComplex *)tab, (hipfftDoubleComplex *)tab, HIPFFT_FORWARD) !=
-        HIPFFT_SUCCESS)
+    if (hipfftExecZ2Z(sym ? ctx->fft_tab_sym : ctx->fft_tab, (hipfftDoubleComplex *)tab, (hipfftDoubleComplex *)tab,
+                      HIPFFT_FORWARD) != HIPFFT_SUCCESS)
       return fail(ctx, VIE_EDEVICE, "grid operator: FFT of the kernel tables failed");
   }
   return VIE_OK;

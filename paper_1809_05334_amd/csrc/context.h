@@ -141,7 +141,8 @@ struct vie_ctx {
   // hipFFT plans of the bound workspace
   GridHost *grid = nullptr;
   std::string grid_err;
-  hipfftHandle fft_tab = 0, fft_fld = 0;
+  hipfftHandle fft_tab = 0, fft_fld = 0, fft_tab_sym = 0;
+  bool grid_sym = false;            // the tables hold the pairs s <= s' only (normal incidence)
   bool jdiag_ok = false;            // jdiag holds the last fill's 1 / Z_mm
   double t_fill = 0, t_factor = 0;
 

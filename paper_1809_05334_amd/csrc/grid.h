@@ -30,6 +30,13 @@
 #include <string>
 #include <vector>
 
+#ifndef __HIPCC__
+#ifndef __host__
+#define __host__
+#define __device__
+#endif
+#endif
+
 namespace vie {
 
 constexpr int kGridTetTypes = 6;                        // Kuhn tetrahedra of a brick
@@ -38,6 +45,10 @@ constexpr int kGridEnt = kGridTetTypes + kGridFaceTypes;
 constexpr int kGridTetSub = 4 * kGridTetTypes;          // tetrahedron point sublattices
 constexpr int kGridSub = kGridTetSub + 3 * kGridFaceTypes;   // all point sublattices (60)
 constexpr int kGridFields = kGridSub + 3 * kGridTetSub;  // charge fields + current fields (132)
+constexpr int kGridSymPairs = kGridSub * (kGridSub + 1) / 2;   // pairs s <= s' (1,830)
+
+// Slot of the pair (s, s'), s <= s', in a table stored for s <= s' only.
+__host__ __device__ inline int grid_sym_pair(int s, int s2) { return s * kGridSub - s * (s - 1) / 2 + (s2 - s); }
 
 // Geometry of the grid and its sublattices (device copy in the workspace).
 struct GridGeom {

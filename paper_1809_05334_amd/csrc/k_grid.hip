@@ -20,15 +20,18 @@ __device__ __forceinline__ dz cexpj(double t) {
   return mk(c, s);
 }
 
-// Kernel table of one sublattice pair (blockIdx.y = s kGridSub + s') over the
-// brick offsets: offset (dx, dy) taken in (-n/2, n/2] (the circulant kernel
-// is periodic in it), dz = z for z < lz and z - pz above (z = lz unused).
+// Kernel table of one sublattice pair over the brick offsets (blockIdx.y =
+// s kGridSub + s', or with `sym` the slot of a pair s <= s'): offset (dx, dy)
+// taken in (-n/2, n/2] (the circulant kernel is periodic in it), dz = z for
+// z < lz and z - pz above (z = lz unused).  At normal incidence (sym) g_p is
+// even, so K(s', s, -d) = K(s, s', d): only the pairs s <= s' are stored, and
+// the product reads K(s', s) at the reversed frequency.
 //   K(s, s', d) = scale e^{+j kt.(dx hx, dy hy)} g_p(pos_s - pos_s' + d h),
 // zero for corner-sharing pairs (any image) and for separations beyond the
 // mesh's height (no element pair has them; the fits do not cover them).
 __global__ __launch_bounds__(256) void k_grid_table(const double *__restrict__ pack, int packlen,
                                                     const GridGeom *__restrict__ gg, double kx, double ky,
-                                                    double scale, dz *__restrict__ tab) {
+                                                    double scale, int sym, dz *__restrict__ tab) {
   extern __shared__ double s_tab[];
   stage_table(pack, packlen, s_tab);
   const GridGeom &G = *gg;
@@ -36,7 +39,12 @@ __global__ __launch_bounds__(256) void k_grid_table(const double *__restrict__ p
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nf) return;
   const int sp = blockIdx.y;
-  const int s = sp / kGridSub, s2 = sp % kGridSub;
+  int s = sp / kGridSub, s2 = sp % kGridSub;
+  if (sym) {   // slot sp of the pairs s <= s2, row by row
+    s = 0;
+    while (sp >= grid_sym_pair(s + 1, s + 1)) ++s;
+    s2 = s + (sp - grid_sym_pair(s, s));
+  }
   const int nx = G.nx, ny = G.ny;
   const int x = (int)(id % nx), y = (int)((id / nx) % ny), z = (int)(id / ((int64_t)nx * ny));
   dz out = mk(0.0, 0.0);
@@ -125,8 +133,9 @@ __global__ __launch_bounds__(256) void k_grid_gather_face(int nface, const GridG
 // + 8 i: the scalar potential from every charge field and, for tetrahedron
 // sublattices, the vector potential from the current fields.
 constexpr int kGridTile = 32;
-__global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restrict__ tab, const dz *__restrict__ fin,
-                                                  dz *__restrict__ fout) {
+template <bool SYM>
+__device__ __forceinline__ void grid_mul_body(int64_t nf, int nx, int ny, int pz, const dz *__restrict__ tab,
+                                              const dz *__restrict__ fin, dz *__restrict__ fout) {
   __shared__ dz sf[kGridFields][kGridTile];
   const int64_t f0 = (int64_t)blockIdx.x * kGridTile;
   const int nt = (int)min<int64_t>(kGridTile, nf - f0);
@@ -138,17 +147,43 @@ __global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restri
   const int fi = threadIdx.x % kGridTile, sg = threadIdx.x / kGridTile;
   if (fi >= nt) return;
   const int64_t f = f0 + fi;
+  // (SYM) the reversed frequency -f: each coordinate negated modulo its length
+  int64_t fr = f;
+  if (SYM) {
+    const int x = (int)(f % nx), y = (int)((f / nx) % ny), z = (int)(f / ((int64_t)nx * ny));
+    fr = (nx - x) % nx + (int64_t)nx * ((ny - y) % ny + (int64_t)ny * ((pz - z) % pz));
+  }
+  // Table row of output s: without SYM the 60 pairs (s, s2) at f, one table
+  // stride apart.  With SYM, for s2 < s the stored pair (s2, s) at -f (its
+  // slot advances by kGridSub - s2 - 1 from s2 to s2 + 1), and for
+  // s2 >= s the pairs (s, s2) at f, in consecutive slots.
+  auto entry = [&](int s, int s2) -> const dz * {
+    if (!SYM) return tab + ((int64_t)s * kGridSub + s2) * nf + f;
+    return s2 < s ? tab + (int64_t)grid_sym_pair(s2, s) * nf + fr : tab + (int64_t)grid_sym_pair(s, s2) * nf + f;
+  };
   for (int s = sg; s < kGridSub; s += 256 / kGridTile) {
-    const dz *K = tab + (int64_t)s * kGridSub * nf + f;
     dz acc = mk(0.0, 0.0);
+    if (SYM) {
+      const dz *K = tab + (int64_t)s * nf + fr;   // slot of (0, s)
 #pragma unroll 4
-    for (int s2 = 0; s2 < kGridSub; ++s2) acc = acc + K[(int64_t)s2 * nf] * sf[s2][fi];
+      for (int s2 = 0; s2 < s; ++s2) {
+        acc = acc + *K * sf[s2][fi];
+        K += (int64_t)(kGridSub - s2 - 1) * nf;   // (s2, s) -> (s2 + 1, s)
+      }
+      K = tab + (int64_t)grid_sym_pair(s, s) * nf + f;
+#pragma unroll 4
+      for (int s2 = s; s2 < kGridSub; ++s2, K += nf) acc = acc + *K * sf[s2][fi];
+    } else {
+      const dz *K = tab + (int64_t)s * kGridSub * nf + f;
+#pragma unroll 4
+      for (int s2 = 0; s2 < kGridSub; ++s2) acc = acc + K[(int64_t)s2 * nf] * sf[s2][fi];
+    }
     fout[(int64_t)s * nf + f] = acc;
     if (s < kGridTetSub) {
       dz a0 = mk(0.0, 0.0), a1 = mk(0.0, 0.0), a2 = mk(0.0, 0.0);
 #pragma unroll 4
       for (int s2 = 0; s2 < kGridTetSub; ++s2) {
-        const dz k = K[(int64_t)s2 * nf];
+        const dz k = *entry(s, s2);
         a0 = a0 + k * sf[kGridSub + s2][fi];
         a1 = a1 + k * sf[kGridSub + kGridTetSub + s2][fi];
         a2 = a2 + k * sf[kGridSub + 2 * kGridTetSub + s2][fi];
@@ -158,6 +193,15 @@ __global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restri
       fout[(int64_t)(kGridSub + 2 * kGridTetSub + s) * nf + f] = a2;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_grid_mul(int64_t nf, const dz *__restrict__ tab, const dz *__restrict__ fin,
+                                                  dz *__restrict__ fout) {
+  grid_mul_body<false>(nf, 1, 1, 1, tab, fin, fout);
+}
+__global__ __launch_bounds__(256) void k_grid_mul_sym(int64_t nf, int nx, int ny, int pz, const dz *__restrict__ tab,
+                                                      const dz *__restrict__ fin, dz *__restrict__ fout) {
+  grid_mul_body<true>(nf, nx, ny, pz, tab, fin, fout);
 }
 
 // y = Z x (or b - Z x), one wave per unknown m: lanes 0-7 the far

@@ -357,17 +357,19 @@ __global__ void k_reduce_cols(const double *part, int nblk, int width, double *o
 __global__ void k_field(int64_t np, const double *pts, const int32_t *tet, const TetGeom *tg, const TetFace *t2f,
                         const dz *gsrc, const dz *inv_eps, const dz *x, dz *e);
 
-// structured-grid far operator (k_grid.hip); grid (ceil(nf / 256), kGridSub^2) for the
-// table, ceil(nf / 32) blocks for the products, ceil(N / 4) blocks (a wave per unknown)
+// structured-grid far operator (k_grid.hip); grid (ceil(nf / 256), kGridSub^2, or
+// kGridSymPairs with sym) for the table, ceil(nf / 32) blocks for the products (the _sym
+// form reads tables of the pairs s <= s' only), ceil(N / 4) blocks (a wave per unknown)
 // for the apply; 256 threads
 __global__ void k_grid_table(const double *pack, int packlen, const GridGeom *gg, double kx, double ky, double scale,
-                             dz *tab);
+                             int sym, dz *tab);
 __global__ void k_grid_gather_tet(int64_t nt, const GridGeom *gg, const int32_t *gtet, const TetGeom *tg,
                                   const TetFace *t2f, const dz *gsrc, const dz *kappa, const dz *x, double kx,
                                   double ky, dz *fld);
 __global__ void k_grid_gather_face(int nface, const GridGeom *gg, const int32_t *gface, const FaceGeom *fg,
                                    const dz *sigma, const dz *x, double kx, double ky, dz *fld);
 __global__ void k_grid_mul(int64_t nf, const dz *tab, const dz *fin, dz *fout);
+__global__ void k_grid_mul_sym(int64_t nf, int nx, int ny, int pz, const dz *tab, const dz *fin, dz *fout);
 __global__ void k_grid_apply(int64_t N, const GridGeom *gg, const int32_t *gtet, const int32_t *gface,
                              const int32_t *ghalf, const int32_t *utet, const int32_t *uk, const TetGeom *tg,
                              const FaceGeom *fg, const dz *alpha, const dz *fout, double k0sq9, double kx, double ky,
