@@ -208,3 +208,31 @@ def test_new_mesh_on_a_context_rebuilds_the_near_pattern(vie):
     same = np.array_equal(s.apply_Z(x), f.apply_Z(x))
     s.close(); f.close()
     assert same
+
+
+def test_grid_and_jacobi_are_refused_where_not_offered(vie):
+    """The grid operator is neither batched nor bound to the library's static
+    workspace (its FFT plans allocate), and the batch does not take the
+    point-Jacobi preconditioner: each is refused with VIE_EINVAL."""
+    m = layered_grid()
+    eps = eps_of(m)
+    g, _ = solver(vie, m, vie.VIE_GRID_FP64)
+    with pytest.raises(vie.VieError) as e:
+        vie.Batch([g])
+    assert e.value.code == vie.VIE_EINVAL and "grid operator" in str(e.value)
+    g.close()
+    s = vie.Solver()
+    s.upload_mesh(m)
+    with pytest.raises(vie.VieError) as e:
+        s.bind_static(vie.VIE_GRID_FP64, 20)
+    assert e.value.code == vie.VIE_EINVAL
+    s.close()
+    d, _ = solver(vie, m, vie.VIE_FP64, restart=40)
+    d.set_option(vie.VIE_OPT_PRECOND, 2)
+    b = vie.Batch([d])
+    b.fill([600.0], [0.0], [0.0], [eps])
+    b.factor()
+    with pytest.raises(vie.VieError) as e:
+        b.solve([0], restart=40)
+    assert e.value.code == vie.VIE_EINVAL and "Jacobi" in str(e.value)
+    d.close()
